@@ -1,0 +1,235 @@
+"""FP64 CPU oracle for the FFT-based Core-AFD maximal-selection loop.
+
+TEST INFRASTRUCTURE ONLY.  This module is the plain, slow, obviously-correct
+reference that the GPU path is checked against.  Only the test-suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+product path (the HIP library and its Python binding) never does, and the two
+share no code.
+
+Paper: Gao, Ku, Qian, "Fast algorithm of adaptive Fourier series"
+(arXiv 1711.08604).  Equations are cited by section and by the label the
+paper's source gives them (the compiled number in brackets):
+
+* Sec. 2, eq. (1) [1]      inner product on the circle
+* Sec. 2, eq. (2) [2]      Takenaka-Malmquist system B_k
+* Sec. 2, eqs. (3)-(4)     one-step Core-AFD decomposition, e_a
+* Sec. 2, eq. ak [8]       maximal selection principle
+* Sec. 2, eq. (7) [7]      remainder recursion (Blaschke / Moebius division)
+* Sec. 2, eq. (9) [9]      energy identity
+* Sec. 3.1, eq. term81 [14] rectangle-rule grid value <G, e_{a_j}>~
+* Sec. 3.1, eqs. ku12 [15], term4 [16], rcl [17]  aliased geometric series,
+  forward DFT of the samples, per-radius inverse DFT
+* Sec. 3.2, Steps 1 and 2  all grid values, then the maximum
+* Sec. 4, eq. er [24]      relative error delta
+
+Readings adopted where the paper is silent or inconsistent (each is also
+listed with its reason in the design notes):
+
+* The circle measure is dt/2pi (so e_a has unit continuous norm and the
+  discrete inner product is (1/N) * sum); the stray 1/sqrt(2pi) of eq. (2)
+  and the 2pi constants of eqs. ku12/rcl are replaced by this normalisation
+  and by N = 2^K respectively.
+* Grid order is radius-major: flat index f = m*N + j, a_{m,j} = r_m e^{2 pi i j/N}.
+  Ties in the maximal selection go to the lowest flat index (the first
+  maximum of a linear scan, Sec. 3.2 Step 2).
+* 0^0 = 1 for the radius r = 0.
+* Optional first_a_zero forces a_1 = 0 (the convention the paper's Sec. 4
+  tables follow: their first row is exactly 1.0000 on zero-mean signals).
+
+Parity status: every function here is pinned by tests against closed forms,
+brute force or the paper's printed tables (see tests/test_oracle_pins.py);
+none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "circle_points",
+    "szego",
+    "grid_direct",
+    "grid_fft",
+    "select",
+    "update",
+    "energy",
+    "decompose",
+    "tm_basis",
+    "partial_sum",
+    "Decomposition",
+]
+
+
+def circle_points(n: int) -> np.ndarray:
+    """Uniform samples z_n = e^{2 pi i n / N}, n = 0..N-1 (Sec. 3.1, t_m = 2 pi m / 2^K)."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    return np.exp(1j * t)
+
+
+def szego(a: complex, z: np.ndarray) -> np.ndarray:
+    """Normalised Szego kernel e_a(z) = sqrt(1-|a|^2) / (1 - conj(a) z) (Sec. 2, after eq. (3))."""
+    a = complex(a)
+    return np.sqrt(1.0 - abs(a) ** 2) / (1.0 - np.conj(a) * z)
+
+
+def _radius_power(r: float, n: int) -> np.ndarray:
+    """r^l for l = 0..n-1 with 0^0 = 1."""
+    w = np.empty(n, dtype=np.float64)
+    w[0] = 1.0
+    if n > 1:
+        w[1:] = float(r) ** np.arange(1, n, dtype=np.float64)
+    return w
+
+
+def grid_direct(G: np.ndarray, radii: np.ndarray) -> np.ndarray:
+    """Grid values by the rectangle rule, Sec. 3.1 eq. term81.
+
+    V[m, j] = (sqrt(1 - r_m^2) / N) * sum_n G[n] / (1 - a_{m,j} e^{-2 pi i n/N}),
+    with a_{m,j} = r_m e^{2 pi i j/N}.  Cost O(M N^2): the direct form the paper
+    compares against (Sec. 3.3 remark), used here as the brute-force reference.
+    """
+    G = np.asarray(G, dtype=np.complex128)
+    N = G.shape[0]
+    z = circle_points(N)
+    V = np.empty((len(radii), N), dtype=np.complex128)
+    for m, r in enumerate(radii):
+        a = r * z  # a_{m,j}, j = 0..N-1
+        # denominator[j, n] = 1 - a_j * conj(z_n)
+        den = 1.0 - np.outer(a, np.conj(z))
+        V[m] = np.sqrt(1.0 - r * r) / N * (den ** -1 @ G)
+    return V
+
+
+def grid_fft(G: np.ndarray, radii: np.ndarray) -> np.ndarray:
+    """Grid values by the FFT form, Sec. 3.1 eqs. term4 and rcl.
+
+    c = DFT(G) (eq. term4, unnormalised, e^{-2 pi i l m/N}); for each radius the
+    inverse DFT of f(l) = r^l c_l, scaled by sqrt(1-r^2) / (N (1 - r^N))
+    (eq. rcl with the constant N, see the module notes).  numpy's ifft carries
+    the 1/N.
+    """
+    G = np.asarray(G, dtype=np.complex128)
+    N = G.shape[0]
+    c = np.fft.fft(G)
+    V = np.empty((len(radii), N), dtype=np.complex128)
+    for m, r in enumerate(radii):
+        w = _radius_power(r, N)
+        V[m] = np.sqrt(1.0 - r * r) / (1.0 - float(r) ** N) * np.fft.ifft(c * w)
+    return V
+
+
+def select(V: np.ndarray, forced: tuple[int, int] | None = None):
+    """Maximal selection on the grid, Sec. 2 eq. ak and Sec. 3.2 Step 2.
+
+    Returns ((m, j), margin) where (m, j) is the first maximiser of |V|^2 in
+    radius-major order (lowest flat index) and margin = (P1 - P2) / P1 with
+    P1 >= P2 the two largest values of |V|^2 over the grid (0 when P1 = 0).
+    With `forced`, that index is taken instead and the margin is NaN.
+    """
+    M, N = V.shape
+    if forced is not None:
+        return (int(forced[0]), int(forced[1])), float("nan")
+    P = (V.real ** 2 + V.imag ** 2).ravel()
+    f = int(np.argmax(P))
+    p1 = P[f]
+    if P.size > 1:
+        p2 = np.partition(P, P.size - 2)[P.size - 2]
+    else:
+        p2 = 0.0
+    margin = float((p1 - p2) / p1) if p1 > 0 else 0.0
+    return (f // N, f % N), margin
+
+
+def update(G: np.ndarray, a: complex, coef: complex) -> np.ndarray:
+    """Remainder recursion, Sec. 2 eq. (7).
+
+    G_{k+1}(z) = (G_k(z) - coef * e_a(z)) * (1 - conj(a) z) / (z - a) on the samples.
+    """
+    z = circle_points(G.shape[0])
+    return (G - coef * szego(a, z)) * (1.0 - np.conj(a) * z) / (z - a)
+
+
+def energy(G: np.ndarray) -> float:
+    """Discrete squared norm (1/N) sum |G[n]|^2 (the dt/2pi measure of eq. (1), rectangle rule)."""
+    G = np.asarray(G)
+    return float(np.mean(G.real ** 2 + G.imag ** 2))
+
+
+class Decomposition:
+    """Per-step record: indices (m_k, j_k), parameters a_k, coefficients
+    <G_k, e_{a_k}>~, energies E_0..E_S (E_k = ||G_{k+1}||^2_N), margins and the
+    final remainder G_{S+1}."""
+
+    def __init__(self, index, a, coef, energy, margin, remainder):
+        self.index = np.asarray(index, dtype=np.int64).reshape(-1, 2)
+        self.a = np.asarray(a, dtype=np.complex128)
+        self.coef = np.asarray(coef, dtype=np.complex128)
+        self.energy = np.asarray(energy, dtype=np.float64)
+        self.margin = np.asarray(margin, dtype=np.float64)
+        self.remainder = np.asarray(remainder, dtype=np.complex128)
+
+    @property
+    def delta(self) -> np.ndarray:
+        """Relative error after n = 1..S steps, Sec. 4 eq. er: ||G - S_n||^2 / ||G||^2.
+
+        Equal to E_n / E_0 because the Blaschke factor is unimodular on the
+        circle, so ||G - S_n||_N = ||G_{n+1}||_N at every sample (expansion (Sn)).
+        """
+        return self.energy[1:] / self.energy[0]
+
+
+def decompose(G, radii, steps: int, first_a_zero: bool = False, forced=None,
+              form: str = "fft") -> Decomposition:
+    """Run `steps` steps of Core-AFD on the samples G (Sec. 2 and Sec. 3.2).
+
+    Per step k: grid values (Step 1; `form` = "fft" for eqs. term4/rcl, "direct"
+    for eq. term81), maximal selection (Step 2, eq. ak), coefficient
+    c_k = <G_k, e_{a_k}>~ (eq. (3)), remainder update (eq. (7)) and energy.
+    `forced` (steps x 2 indices) replaces the selection at every step (replay);
+    `first_a_zero` replaces it at step 1 by the r = 0 grid point.
+    """
+    G = np.asarray(G, dtype=np.complex128).copy()
+    radii = np.asarray(radii, dtype=np.float64)
+    N = G.shape[0]
+    grid = grid_fft if form == "fft" else grid_direct
+    zero_idx = None
+    if first_a_zero:
+        hits = np.nonzero(radii == 0.0)[0]
+        if hits.size == 0:
+            raise ValueError("first_a_zero needs a radius equal to 0")
+        zero_idx = int(hits[0])
+    idx, a_list, c_list, e_list, mg = [], [], [], [energy(G)], []
+    for k in range(steps):
+        V = grid(G, radii)
+        f = None
+        if forced is not None:
+            f = tuple(forced[k])
+        elif first_a_zero and k == 0:
+            f = (zero_idx, 0)
+        (m, j), margin = select(V, f)
+        a = radii[m] * np.exp(2j * np.pi * j / N)
+        coef = V[m, j]
+        G = update(G, a, coef)
+        idx.append((m, j))
+        a_list.append(a)
+        c_list.append(coef)
+        e_list.append(energy(G))
+        mg.append(margin)
+    return Decomposition(idx, a_list, c_list, e_list, mg, G)
+
+
+def tm_basis(a_list, z: np.ndarray) -> np.ndarray:
+    """Takenaka-Malmquist system on the samples, Sec. 2 eq. (2) with the dt/2pi
+    normalisation: B_k(z) = e_{a_k}(z) * prod_{l<k} (z - a_l) / (1 - conj(a_l) z).
+    Returns an array of shape (len(a_list), len(z))."""
+    out = np.empty((len(a_list), len(z)), dtype=np.complex128)
+    blaschke = np.ones_like(z, dtype=np.complex128)
+    for k, a in enumerate(a_list):
+        out[k] = szego(a, z) * blaschke
+        blaschke = blaschke * (z - a) / (1.0 - np.conj(a) * z)
+    return out
+
+
+def partial_sum(coefs, a_list, z: np.ndarray) -> np.ndarray:
+    """S_n = sum_k <G_k, e_{a_k}> B_k on the samples (Sec. 2 expansion (Sn))."""
+    B = tm_basis(a_list, z)
+    return np.asarray(coefs) @ B

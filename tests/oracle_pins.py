@@ -1,0 +1,295 @@
+"""Pins for the FP64 oracle: each check compares the oracle with something other
+than itself (a closed form, brute force, an invariant, or a value the paper
+prints).  Every pin takes the oracle namespace as an argument so that the
+planted-mistake test can run the same battery on a deliberately broken copy.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def load_golden(name):
+    vals = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                vals.append(float(line))
+    return np.array(vals)
+
+
+# ------------------------------------------------------------------ P0 brute force
+def _term81_loops(G, radii):
+    """Sec. 3.1 eq. term81 written out with plain Python loops (tiny inputs only)."""
+    import cmath
+    import math
+    N = len(G)
+    out = []
+    for r in radii:
+        row = []
+        for j in range(N):
+            a = r * cmath.exp(2j * math.pi * j / N)
+            s = 0j
+            for n in range(N):
+                s += complex(G[n]) / (1 - a * cmath.exp(-2j * math.pi * n / N))
+            row.append(math.sqrt(1 - r * r) / N * s)
+        out.append(row)
+    return np.array(out)
+
+
+def pin_bruteforce_loops(O):
+    """Oracle grid values (both forms) and one full decomposition step against
+    pure-Python loops of eq. term81 and an exhaustive scan."""
+    rng = _rng(1)
+    N = 8
+    G = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    radii = np.array([0.0, 0.3, 0.75, 0.95])
+    ref = _term81_loops(G, radii)
+    assert _rel(O.grid_direct(G, radii), ref) < 1e-13
+    assert _rel(O.grid_fft(G, radii), ref) < 1e-13
+    # exhaustive scan for the maximum, first occurrence in radius-major order
+    best, bi = -1.0, None
+    for m in range(len(radii)):
+        for j in range(N):
+            p = abs(ref[m, j]) ** 2
+            if p > best:
+                best, bi = p, (m, j)
+    d = O.decompose(G, radii, 1)
+    assert tuple(d.index[0]) == bi
+    assert abs(d.coef[0] - ref[bi]) < 1e-13 * abs(ref[bi])
+    assert abs(d.a[0] - radii[bi[0]] * np.exp(2j * np.pi * bi[1] / N)) < 1e-15
+
+
+# ------------------------------------------------------------------ P1
+def pin_fft_equals_direct(O):
+    """The aliased geometric series (eqs. ku12/term1) is exact: FFT form = direct form."""
+    rng = _rng(2)
+    for N in (16, 64, 256):
+        G = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        radii = np.array([0.0, 0.1, 0.5, 0.9, 0.99, 0.999])
+        assert _rel(O.grid_fft(G, radii), O.grid_direct(G, radii)) < 1e-12
+
+
+# ------------------------------------------------------------------ P2
+def pin_kernel_spectrum(O):
+    """DFT of the sampled normalised Szego kernel has the closed form
+    N sqrt(1-|b|^2) conj(b)^l / (1 - conj(b)^N) (geometric series)."""
+    for N in (8, 64, 1024):
+        z = O.circle_points(N)
+        for b in (0.0, 0.37, 0.9 * np.exp(0.7j), 0.999 * np.exp(-2.1j)):
+            l = np.arange(N)
+            closed = N * np.sqrt(1 - abs(b) ** 2) * np.conj(b) ** l / (1 - np.conj(b) ** N)
+            if b == 0.0:
+                closed = np.zeros(N, complex)
+                closed[0] = N
+            assert _rel(np.fft.fft(O.szego(b, z)), closed) < 1e-12
+    # sample points: angles 2 pi n / N, starting at 1
+    z = O.circle_points(12)
+    assert abs(z[0] - 1) < 1e-15 and abs(z[3] - 1j) < 1e-15 and abs(z[6] + 1) < 1e-15
+
+
+# ------------------------------------------------------------------ P3
+def pin_reproducing(O):
+    """For a polynomial G of degree < N the grid value is
+    sqrt(1-r^2) G(a) / (1 - r^N) (reproducing property; G(a) by Horner)."""
+    rng = _rng(3)
+    N = 32
+    coeffs = rng.standard_normal(N - 3) + 1j * rng.standard_normal(N - 3)  # degree N-4
+    z = O.circle_points(N)
+    G = np.polyval(coeffs[::-1], z)
+    radii = np.array([0.0, 0.2, 0.6, 0.97])
+    V = O.grid_fft(G, radii)
+    Vd = O.grid_direct(G, radii)
+    for m, r in enumerate(radii):
+        a = r * z
+        ref = np.sqrt(1 - r * r) * np.polyval(coeffs[::-1], a) / (1 - r ** N)
+        assert _rel(V[m], ref) < 1e-12
+        assert _rel(Vd[m], ref) < 1e-12
+
+
+# ------------------------------------------------------------------ P4
+def pin_kernel_kernel(O):
+    """<e_b, e_a>~ = sqrt((1-|a|^2)(1-|b|^2)) (1-(a conj b)^N) / ((1-a conj b)(1-a^N)(1-conj(b)^N))."""
+    N = 64
+    z = O.circle_points(N)
+    b = 0.8 * np.exp(1.3j)
+    G = O.szego(b, z)
+    radii = np.array([0.0, 0.4, 0.8, 0.95])
+    V = O.grid_fft(G, radii)
+    for m, r in enumerate(radii):
+        a = r * z
+        ab = a * np.conj(b)
+        ref = (np.sqrt((1 - abs(a) ** 2) * (1 - abs(b) ** 2)) * (1 - ab ** N)
+               / ((1 - ab) * (1 - a ** N) * (1 - np.conj(b) ** N)))
+        assert _rel(V[m], ref) < 1e-12
+
+
+# ------------------------------------------------------------------ P5
+def pin_single_kernel(O):
+    """G = w e_b with b on the grid: one step selects b (when rho = |b|^N is
+    negligible), with coefficient w (1+rho)/(1-rho) and remainder energy
+    |w|^2 (2 rho/(1-rho))^2 (1+rho)/(1-rho); the two formulas are exact for
+    any rho once a_1 = b (checked with the index forced at rho = 0.9^64)."""
+    radii = np.round(np.arange(0, 100) / 100.0, 12)
+    w = 0.7 - 1.1j
+    for N, rb, jb, free in ((64, 0.9, 11, False), (64, 0.5, 40, True),
+                            (256, 0.5, 200, True), (1024, 0.5, 3, True)):
+        mb = int(round(rb * 100))
+        b = radii[mb] * np.exp(2j * np.pi * jb / N)
+        z = O.circle_points(N)
+        G = w * O.szego(b, z)
+        d = O.decompose(G, radii, 1, forced=None if free else [(mb, jb)])
+        assert tuple(d.index[0]) == (mb, jb)
+        rho = abs(b) ** N
+        assert abs(d.coef[0] - w * (1 + rho) / (1 - rho)) < 1e-13 * abs(w)
+        e1 = abs(w) ** 2 * (2 * rho / (1 - rho)) ** 2 * (1 + rho) / (1 - rho)
+        assert abs(d.energy[1] - e1) < 1e-14 * abs(w) ** 2
+        assert abs(d.energy[0] - abs(w) ** 2 * (1 + rho) / (1 - rho)) < 1e-13
+        if free:
+            # margin to the nearest grid neighbour: pseudo-hyperbolic distance squared
+            cand = [radii[mb] * np.exp(2j * np.pi * (jb + 1) / N),
+                    radii[mb + 1] * np.exp(2j * np.pi * jb / N),
+                    radii[mb - 1] * np.exp(2j * np.pi * jb / N)]
+            rho2 = min(abs(a - b) ** 2 / abs(1 - np.conj(b) * a) ** 2 for a in cand)
+            assert abs(d.margin[0] - rho2) < 1e-6 * rho2
+
+
+# ------------------------------------------------------------------ P6
+def pin_zero_radius_is_dft(O):
+    """With radii = {0} every grid value ties, index j = 0 is taken, and the
+    decomposition peels off the DFT coefficients: c_k = DFT(G)[k-1]/N,
+    E_k = sum_{l >= k} |DFT(G)_l|^2 / N^2 (Parseval)."""
+    rng = _rng(6)
+    N = 32
+    G = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    C = np.fft.fft(G)
+    d = O.decompose(G, np.array([0.0]), 6)
+    assert np.all(d.index == 0)
+    assert _rel(d.coef, C[:6] / N) < 1e-13
+    ref_e = np.array([np.sum(np.abs(C[k:]) ** 2) / N ** 2 for k in range(7)])
+    assert _rel(d.energy, ref_e) < 1e-13
+
+
+# ------------------------------------------------------------------ P7
+def pin_energy_with_aliasing(O):
+    """Discrete energy bookkeeping: E_k = E_{k-1} - |c_k|^2 (1 - 3 rho)/(1 - rho),
+    rho = |a_k|^N (the discrete norm of e_a is (1+rho)/(1-rho), not 1)."""
+    rng = _rng(7)
+    N = 64
+    G = W.kernel_sum(N, 0.9 * np.exp(2j * np.pi * rng.random(4)), rng.standard_normal(4) + 0j)
+    radii = np.array([0.0, 0.3, 0.6, 0.8, 0.9, 0.95])
+    d = O.decompose(G, radii, 6)
+    for k in range(6):
+        rho = abs(d.a[k]) ** N
+        pred = d.energy[k] - abs(d.coef[k]) ** 2 * (1 - 3 * rho) / (1 - rho)
+        assert abs(pred - d.energy[k + 1]) < 1e-13 * d.energy[0]
+
+
+# ------------------------------------------------------------------ P8
+def pin_expansion(O):
+    """Expansion (Sn): G = sum_k c_k B_k + G_{n+1} prod_k (z - a_k)/(1 - conj(a_k) z)
+    at every sample, so ||G - S_n||_N = ||G_{n+1}||_N and delta = E_n/E_0."""
+    g, radii, _ = W.config1()
+    g = g[::8]  # N = 128
+    N = g.shape[0]
+    z = O.circle_points(N)
+    d = O.decompose(g, radii[::5], 5)
+    blaschke = np.ones(N, complex)
+    for a in d.a:
+        blaschke *= (z - a) / (1 - np.conj(a) * z)
+    S = O.partial_sum(d.coef, d.a, z)
+    assert _rel(S + d.remainder * blaschke, g) < 1e-12
+    assert abs(np.mean(np.abs(g - S) ** 2) - d.energy[-1]) < 1e-12 * d.energy[0]
+    # orthonormality of the TM system in the continuous sense, checked by a fine rule
+    zf = O.circle_points(1 << 14)
+    B = O.tm_basis(d.a, zf)
+    gram = (B @ np.conj(B).T) / zf.shape[0]
+    assert np.max(np.abs(gram - np.eye(len(d.a)))) < 1e-9
+
+
+# ------------------------------------------------------------------ P9
+def pin_invariances(O):
+    """Cyclic shift of the samples by s shifts every selected angle index by s;
+    scaling G by lambda scales every coefficient by lambda."""
+    g, radii, _ = W.config1()
+    g = g[::4]  # N = 256
+    N = g.shape[0]
+    radii = radii[::4]
+    d0 = O.decompose(g, radii, 4)
+    assert np.all(d0.margin > 1e-6)
+    s = 37
+    d1 = O.decompose(np.roll(g, s), radii, 4)
+    assert np.all(d1.index[:, 0] == d0.index[:, 0])
+    assert np.all(d1.index[:, 1] == (d0.index[:, 1] + s) % N)
+    rot = np.exp(2j * np.pi * s / N)  # a_k rotates with the shift; coefficients keep their modulus
+    assert _rel(d1.a, d0.a * rot) < 1e-12
+    assert _rel(np.abs(d1.coef), np.abs(d0.coef)) < 1e-10
+    assert _rel(d1.energy, d0.energy) < 1e-10
+    lam = 2.5 - 0.5j
+    d2 = O.decompose(lam * g, radii, 4)
+    assert np.all(d2.index == d0.index)
+    assert _rel(d2.coef, lam * d0.coef) < 1e-12
+
+
+# ------------------------------------------------------------------ P10
+def pin_paper_tables(O):
+    """Tables 4 and 8 of the paper (delta after n steps, 4 decimals) with a_1 = 0,
+    N = 1024, radii 0..0.8.  Weak pin: the printed digits agree to about 1e-3."""
+    radii = W.paper_radii()
+    d1 = O.decompose(W.paper_f1(1024), radii, 10, first_a_zero=True)
+    assert np.max(np.abs(d1.delta - load_golden("paper_table4_f1_delta.txt"))) < 1.5e-3
+    d2 = O.decompose(W.paper_f2(1024), radii, 10, first_a_zero=True)
+    assert np.max(np.abs(d2.delta - load_golden("paper_table8_f2_delta.txt"))) < 1.5e-3
+
+
+# ------------------------------------------------------------------ selection rules
+def pin_selection_rules(O):
+    """Ties go to the lowest flat index; margin = (P1 - P2)/P1; forced indices replay."""
+    V = np.zeros((3, 4), complex)
+    V[1, 2] = 2.0
+    V[2, 1] = -2.0  # same |.|^2, later in radius-major order
+    V[0, 3] = 1.0j
+    (m, j), margin = O.select(V)
+    assert (m, j) == (1, 2) and margin == 0.0
+    V[2, 1] = 1.9
+    (m, j), margin = O.select(V)
+    assert (m, j) == (1, 2) and abs(margin - (4 - 1.9 ** 2) / 4) < 1e-15
+    g, radii, _ = W.config1()
+    g = g[::4]
+    radii = radii[::4]
+    d = O.decompose(g, radii, 3)
+    r = O.decompose(g, radii, 3, forced=d.index)
+    assert np.all(r.index == d.index)
+    assert _rel(r.coef, d.coef) < 1e-15 and _rel(r.energy, d.energy) < 1e-15
+
+
+ALL_PINS = [
+    pin_bruteforce_loops,
+    pin_fft_equals_direct,
+    pin_kernel_spectrum,
+    pin_reproducing,
+    pin_kernel_kernel,
+    pin_single_kernel,
+    pin_zero_radius_is_dft,
+    pin_energy_with_aliasing,
+    pin_expansion,
+    pin_invariances,
+    pin_paper_tables,
+    pin_selection_rules,
+]

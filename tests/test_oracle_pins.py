@@ -1,0 +1,138 @@
+"""The FP64 oracle against closed forms, brute force, invariants and the paper's tables.
+
+Also: every planted mistake (a dropped term, a wrong sign, a swapped index, a
+conjugate lost) must make at least one pin fail, so the battery is shown to be
+able to catch the kinds of slips that could hide in the oracle.
+"""
+import types
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import afd_oracle as OA
+from tests import oracle_pins as P
+
+
+@pytest.mark.parametrize("pin", P.ALL_PINS, ids=lambda f: f.__name__)
+def test_pin(pin):
+    pin(O)
+
+
+def test_first_a_zero_requires_zero_radius():
+    with pytest.raises(ValueError):
+        O.decompose(np.ones(8, complex), np.array([0.1, 0.2]), 1, first_a_zero=True)
+
+
+# ---------------------------------------------------------------- planted mistakes
+def _mutant(**overrides):
+    ns = types.SimpleNamespace(**{name: getattr(OA, name) for name in OA.__all__})
+    for k, v in overrides.items():
+        setattr(ns, k, v)
+
+    # decompose must route through the mutated helpers
+    def decompose(G, radii, steps, first_a_zero=False, forced=None, form="fft"):
+        G = np.asarray(G, dtype=np.complex128).copy()
+        radii = np.asarray(radii, dtype=np.float64)
+        N = G.shape[0]
+        grid = ns.grid_fft if form == "fft" else ns.grid_direct
+        idx, a_l, c_l, e_l, mg = [], [], [], [ns.energy(G)], []
+        zero = int(np.nonzero(radii == 0.0)[0][0]) if first_a_zero else None
+        for k in range(steps):
+            V = grid(G, radii)
+            f = tuple(forced[k]) if forced is not None else ((zero, 0) if first_a_zero and k == 0 else None)
+            (m, j), margin = ns.select(V, f)
+            a = radii[m] * np.exp(2j * np.pi * j / N)
+            G = ns.update(G, a, V[m, j])
+            idx.append((m, j)); a_l.append(a); c_l.append(V[m, j]); e_l.append(ns.energy(G)); mg.append(margin)
+        return OA.Decomposition(idx, a_l, c_l, e_l, mg, G)
+
+    if "decompose" not in overrides:
+        ns.decompose = decompose
+    return ns
+
+
+def _grid_fft_forward_sign(G, radii):
+    N = len(G)
+    c = np.fft.fft(G)
+    return np.array([np.sqrt(1 - r * r) / (1 - r ** N) * np.fft.fft(c * OA._radius_power(r, N)) / N
+                     for r in radii])
+
+
+def _grid_fft_no_alias(G, radii):
+    c = np.fft.fft(G)
+    return np.array([np.sqrt(1 - r * r) * np.fft.ifft(c * OA._radius_power(r, len(G))) for r in radii])
+
+
+def _grid_fft_no_sqrt(G, radii):
+    N = len(G)
+    c = np.fft.fft(G)
+    return np.array([1 / (1 - r ** N) * np.fft.ifft(c * OA._radius_power(r, N)) for r in radii])
+
+
+def _grid_fft_shifted_weight(G, radii):
+    N = len(G)
+    c = np.fft.fft(G)
+    return np.array([np.sqrt(1 - r * r) / (1 - r ** N) * np.fft.ifft(c * r ** np.arange(1, N + 1)) for r in radii])
+
+
+def _szego_no_conj(a, z):
+    return np.sqrt(1 - abs(a) ** 2) / (1 - a * z)
+
+
+def _update_wrong_factor(G, a, coef):
+    z = OA.circle_points(len(G))
+    return (G - coef * OA.szego(a, z)) * (1 - a * z) / (z - a)
+
+
+def _update_no_subtract(G, a, coef):
+    z = OA.circle_points(len(G))
+    return G * (1 - np.conj(a) * z) / (z - a)
+
+
+def _select_last_max(V, forced=None):
+    if forced is not None:
+        return tuple(forced), float("nan")
+    M, N = V.shape
+    P = np.abs(V.ravel()) ** 2
+    f = len(P) - 1 - int(np.argmax(P[::-1]))
+    return (f // N, f % N), 0.0
+
+
+def _select_transposed(V, forced=None):
+    if forced is not None:
+        return tuple(forced), float("nan")
+    M, N = V.shape
+    P = np.abs(V.ravel()) ** 2
+    f = int(np.argmax(P))
+    return (f % M, f // M), 0.0
+
+
+def _energy_sum(G):
+    return float(np.sum(np.abs(G) ** 2))
+
+
+MUTANTS = {
+    "forward-sign inverse DFT": dict(grid_fft=_grid_fft_forward_sign),
+    "aliasing factor 1/(1-r^N) dropped": dict(grid_fft=_grid_fft_no_alias),
+    "sqrt(1-r^2) dropped": dict(grid_fft=_grid_fft_no_sqrt),
+    "weights r^(l+1)": dict(grid_fft=_grid_fft_shifted_weight),
+    "szego kernel without conjugate": dict(szego=_szego_no_conj),
+    "Moebius factor without conjugate": dict(update=_update_wrong_factor),
+    "projection not subtracted": dict(update=_update_no_subtract),
+    "ties to the last maximum": dict(select=_select_last_max),
+    "flat index transposed": dict(select=_select_transposed),
+    "energy without 1/N": dict(energy=_energy_sum),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name):
+    ns = _mutant(**MUTANTS[name])
+    failures = 0
+    for pin in P.ALL_PINS:
+        try:
+            pin(ns)
+        except (AssertionError, ValueError, IndexError, FloatingPointError):
+            failures += 1
+    assert failures > 0, f"no pin caught the planted mistake: {name}"
