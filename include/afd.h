@@ -1,0 +1,153 @@
+/*
+ * afd.h -- C ABI of libafd: the FFT-based Core-AFD maximal-selection loop on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gao, Ku, Qian, "Fast algorithm of adaptive Fourier series"
+ * (arXiv 1711.08604).  Given the boundary samples G(z_n), z_n = e^{2 pi i n/N},
+ * n = 0..N-1, N = 2^K, of a function in the Hardy space of the unit disc, each
+ * step k of Core-AFD (Sec. 2, eqs. (3), (7) and ak; Sec. 3.2, Steps 1-2)
+ *
+ *   1. evaluates the rectangle-rule inner products <G_k, e_a>~ (Sec. 3.1,
+ *      eq. term81) on the polar grid a_{m,j} = r_m e^{2 pi i j/N}, m = 0..M-1,
+ *      j = 0..N-1, through one forward DFT of the samples (eq. term4) and one
+ *      inverse DFT per radius of the weighted spectrum r_m^l c_l (eq. rcl,
+ *      with the constant N = 2^K; the circle measure is dt/2pi);
+ *   2. selects the grid point with the largest |<G_k, e_a>~|^2 (ties: lowest
+ *      flat index m*N + j);
+ *   3. records a_k and the coefficient c_k = <G_k, e_{a_k}>~ and replaces the
+ *      remainder by G_{k+1} = (G_k - c_k e_{a_k}) (1 - conj(a_k) z)/(z - a_k)
+ *      (eq. (7)), with e_a(z) = sqrt(1-|a|^2)/(1 - conj(a) z);
+ *   4. records the remainder energy E_k = (1/N) sum_n |G_{k+1}(z_n)|^2.
+ *
+ * Every step runs in hand-written HIP kernels on the plan's stream.  All
+ * functions are extern "C"; no C++ exception crosses this boundary.
+ */
+#ifndef AFD_H_
+#define AFD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct afd_plan_s* afd_plan; /* opaque; owns its device workspace and tables */
+
+typedef enum {
+  AFD_OK = 0,
+  AFD_E_INVALID = 1,     /* bad argument (see each function)                        */
+  AFD_E_NONFINITE = 2,   /* NaN or Inf in the input samples                          */
+  AFD_E_NOMEM = 3,       /* device or host allocation failed                         */
+  AFD_E_HIP = 4,         /* a HIP runtime error; afd_last_error() holds its text     */
+  AFD_E_UNSUPPORTED = 5  /* valid but outside what this build supports (N > 2^20)    */
+} afd_status;
+
+typedef enum {
+  /* Every step in IEEE double: forward DFT, per-radius inverse DFTs, |.|^2,
+     selection, coefficient (the grid value itself), update and energy.        */
+  AFD_FP64 = 0,
+  /* Forward and inverse DFTs, |.|^2 and a candidate short-list in IEEE single
+     (complex64 data, FP32 accumulation); the short-list (at least recheck_k
+     points, plus every point within a relative band of the FP32 maximum) is
+     re-evaluated in double by the direct rule of eq. term81 against the double
+     remainder, and the winner, coefficient, update and energy are double.    */
+  AFD_FP32_RECHECK = 1
+} afd_precision;
+
+typedef struct {
+  int64_t n;              /* N = 2^K samples, 2 <= N <= 2^20                                  */
+  int32_t m;              /* M >= 1 radii; M * N must be < 2^31                                */
+  const double* radii;    /* host pointer, length M, each in [0, 1); any order; copied at
+                             create.  Grid index m refers to position m of this array.        */
+  afd_precision precision;
+  int32_t recheck_k;      /* FP32 mode: minimum short-list length, 1..256 (0 -> 8)             */
+  int32_t first_a_zero;   /* 1: step 1 takes a_1 = 0 (the grid point (m0, 0) of the first
+                             radius equal to 0) instead of the maximum; requires such a radius */
+  double recheck_band;    /* FP32 mode: relative band below the FP32 maximum whose points are
+                             all re-checked in double, in [0, 1e-4] (0 -> 4e-6, about eight
+                             times the FP32 error of |.|^2 at N = 2^14); the short-list holds
+                             at most 256 points (flags bit 0 reports a cut)                   */
+} afd_plan_desc;
+
+/* Per-decomposition outputs.  Caller-owned; each pointer may be host memory
+   or device memory of the plan's device (detected per pointer).  Layouts:   */
+typedef struct {
+  int32_t* index;         /* 2*steps: (m_k, j_k) per step                          [required] */
+  double* a;              /* 2*steps: a_k as interleaved (re, im)                  [required] */
+  double* coef;           /* 2*steps: c_k = <G_k, e_{a_k}>~, interleaved (re, im)  [required] */
+  double* energy;         /* steps+1: E_0 = ||G||_N^2, E_k = ||G_{k+1}||_N^2       [required] */
+  double* margin;         /* steps: (P1 - P2)/P1, P1 >= P2 the two largest |.|^2 seen by the
+                             selection (FP64: the whole grid; FP32: the re-checked short-list);
+                             NaN for forced steps                                   [nullable] */
+  double* remainder;      /* 2*N: final remainder G_{steps+1}, interleaved          [nullable] */
+  int32_t* recheck_count; /* steps: short-list length re-checked in double (FP64: 0) [nullable] */
+  int32_t* flags;         /* steps: bit 0 = the band held more points than could be
+                             re-checked; bit 1 = some radius held more band points than
+                             its per-radius list; bit 2 = an exact fallback path of the
+                             selection ran (flat or exactly tied values, e.g. r = 0) [nullable] */
+} afd_result;
+
+/* Validate `desc`, copy the radii, build the per-radius double-precision
+   tables and allocate the device workspace on the current HIP device.
+   `hip_stream` is a hipStream_t (NULL = the default stream) on which every
+   later call of this plan runs.  On success *out receives the plan.
+   Errors: AFD_E_INVALID (null pointer, N not a power of two or < 2, M < 1,
+   M*N >= 2^31, a radius outside [0,1) or non-finite, recheck_k or
+   recheck_band out of range, first_a_zero without a zero radius),
+   AFD_E_UNSUPPORTED (N > 2^20), AFD_E_NOMEM, AFD_E_HIP.  On error *out is
+   set to NULL and nothing is left allocated. */
+afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan* out);
+
+/* Run `steps` >= 0 steps of the maximal-selection loop on `signal` (2*N
+   doubles, interleaved complex128, host or device) and write `out`.
+   Synchronous: returns after the results are in `out`.  The plan's device
+   state is overwritten; `signal` is only read.  Errors: AFD_E_INVALID (null
+   plan/signal/out or a required out field, steps < 0), AFD_E_NONFINITE,
+   AFD_E_HIP.  Validation happens before any device work; on error `out` is
+   untouched.  An all-zero remainder selects flat index 0 with c_k = 0 and
+   the loop continues. */
+afd_status afd_decompose(afd_plan plan, const double* signal, int32_t steps, afd_result* out);
+
+/* As afd_decompose, but step k takes the grid point forced_index[2k],
+   forced_index[2k+1] (host or device, 2*steps int32) instead of selecting;
+   c_k is then the grid value at that point evaluated in double by the direct
+   rule (eq. term81).  Used to compare every step with a reference trajectory
+   past near-ties.  Errors as afd_decompose, plus AFD_E_INVALID for an index
+   outside [0,M) x [0,N). */
+afd_status afd_replay(afd_plan plan, const double* signal, int32_t steps,
+                      const int32_t* forced_index, afd_result* out);
+
+/* Device bytes a plan with this description allocates (tables + workspace);
+   0 if `desc` is invalid.  For admission control. */
+size_t afd_workspace_bytes(const afd_plan_desc* desc);
+
+/* Release the plan and its device memory.  NULL-safe. */
+void afd_plan_destroy(afd_plan plan);
+
+/* Static text for a status code. */
+const char* afd_status_string(afd_status status);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char* afd_last_error(void);
+
+/* Per-kernel timing with HIP events recorded on the plan's stream around
+   every launch of the kernel class `kernel` ("radius": the fused weighted
+   inverse-DFT / |.|^2 / selection kernel; "fft": the forward DFT; "update":
+   the remainder update).  enable = 1 starts accumulating (and clears the
+   totals), 0 stops.  Errors: AFD_E_INVALID for an unknown class. */
+afd_status afd_plan_set_timing(afd_plan plan, const char* kernel, int32_t enable);
+
+/* Accumulated milliseconds and launch count of the timed kernel class since
+   timing was enabled.  Errors: AFD_E_INVALID. */
+afd_status afd_plan_kernel_time(afd_plan plan, double* ms, int64_t* launches);
+
+/* Launch geometry of the radius kernel of this plan: grid blocks, threads
+   per block, dynamic LDS bytes per block.  Errors: AFD_E_INVALID. */
+afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threads, int32_t* lds_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFD_H_ */

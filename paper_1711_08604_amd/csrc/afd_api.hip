@@ -1,0 +1,573 @@
+// Host side of libafd: plan validation, double-precision tables, device
+// workspace, and the stream-ordered step driver behind the C ABI of afd.h.
+#include "../../include/afd.h"
+#include "afd_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace afd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+afd_status fail(afd_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+afd_status hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return AFD_E_HIP;
+}
+
+int ilog2_exact(int64_t n) {
+  if (n < 2 || (n & (n - 1)) != 0) return -1;
+  int r = 0;
+  while ((int64_t(1) << r) < n) ++r;
+  return r;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3 };
+
+// Device arena layout for one plan.
+struct Layout {
+  size_t radii, omega, tw, pw, pv, scale, g64, g32, c, blocks, cand, partials, winner, epart, nonfinite, forced0;
+  size_t total;
+};
+
+struct Config {
+  int logn;
+  int64_t N;
+  int M;
+  bool fp64;
+  FftGeom geom;
+  int rpb;
+  int nblocks;
+  int nch;
+  int nparts;
+};
+
+afd_status validate(const afd_plan_desc* d, Config* cfg) {
+  if (!d) return fail(AFD_E_INVALID, "desc is NULL");
+  if (d->n > (int64_t(1) << kMaxLogN) && ilog2_exact(d->n) > 0)
+    return fail(AFD_E_UNSUPPORTED, "N > 2^20 is not supported");
+  const int logn = ilog2_exact(d->n);
+  if (logn < 1) return fail(AFD_E_INVALID, "N must be a power of two >= 2");
+  if (d->m < 1) return fail(AFD_E_INVALID, "M must be >= 1");
+  if (!d->radii) return fail(AFD_E_INVALID, "radii is NULL");
+  if (int64_t(d->m) * d->n >= (int64_t(1) << 31)) return fail(AFD_E_INVALID, "M*N must be < 2^31");
+  if (d->precision != AFD_FP64 && d->precision != AFD_FP32_RECHECK) return fail(AFD_E_INVALID, "bad precision");
+  if (d->recheck_k < 0 || d->recheck_k > kKMax) return fail(AFD_E_INVALID, "recheck_k must be in 0..256");
+  if (!(d->recheck_band >= 0.0) || d->recheck_band > 1e-4)
+    return fail(AFD_E_INVALID, "recheck_band must be in [0, 1e-4]");
+  bool has_zero = false;
+  for (int i = 0; i < d->m; ++i) {
+    const double r = d->radii[i];
+    if (!std::isfinite(r) || r < 0.0 || r >= 1.0) return fail(AFD_E_INVALID, "radius outside [0, 1)");
+    if (r == 0.0) has_zero = true;
+  }
+  if (d->first_a_zero && !has_zero) return fail(AFD_E_INVALID, "first_a_zero needs a radius equal to 0");
+  if (logn > kMaxLdsLogN) return fail(AFD_E_UNSUPPORTED, "N > 2^14 is not supported by this build yet");
+  if (cfg) {
+    cfg->logn = logn;
+    cfg->N = d->n;
+    cfg->M = d->m;
+    cfg->fp64 = d->precision == AFD_FP64;
+    cfg->geom = fft_geom(logn, cfg->fp64);
+    const int tpr = cfg->geom.tpr;
+    cfg->rpb = tpr >= 64 ? 1 : 64 / tpr;
+    cfg->nblocks = (d->m + cfg->rpb - 1) / cfg->rpb;
+    cfg->nch = int(d->n >= 2048 ? d->n / 2048 : 1);
+    cfg->nparts = update_blocks(int(d->n));
+  }
+  return AFD_OK;
+}
+
+Layout layout_of(const Config& c) {
+  Layout L{};
+  size_t o = 0;
+  const size_t real = c.fp64 ? 8 : 4;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.radii = take(8 * size_t(c.M));
+  L.omega = take(16 * size_t(c.N));
+  L.tw = take(2 * real * size_t(c.geom.twsize + 1));
+  L.pw = take(real * size_t(c.M) * c.geom.tpr);
+  L.pv = take(real * size_t(c.M) * c.geom.E);
+  L.scale = take(real * size_t(c.M));
+  L.g64 = take(16 * size_t(c.N));
+  L.g32 = take(c.fp64 ? 0 : 8 * size_t(c.N));
+  L.c = take(2 * real * size_t(c.N));
+  L.blocks = take((c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.nblocks));
+  L.cand = take(sizeof(CandList) + 4 * size_t(c.nblocks));
+  L.partials = take(16 * size_t(kKMax) * c.nch);
+  L.winner = take(sizeof(Winner));
+  L.epart = take(8 * size_t(c.nparts));
+  L.nonfinite = take(4);
+  L.forced0 = take(8);
+  L.total = o;
+  return L;
+}
+
+bool is_device_pointer(const void* p) {
+  hipPointerAttribute_t attr;
+  const hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct afd_plan_s {
+  Config cfg{};
+  Layout L{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int recheck_k = 8;
+  float tau_band = 1e-5f;
+  bool first_a_zero = false;
+  int zero_m = -1;
+  unsigned char* arena = nullptr;
+  // per-call result staging on the device
+  unsigned char* res = nullptr;
+  int res_steps = -1;
+  int32_t* forced = nullptr;
+  int forced_steps = -1;
+  // timing
+  int time_kind = kTimeNone;
+  double time_ms = 0.0;
+  int64_t time_launches = 0;
+  std::vector<hipEvent_t> events;
+
+  template <typename P>
+  P* at(size_t off) const {
+    return reinterpret_cast<P*>(arena + off);
+  }
+};
+
+namespace {
+
+afd_status build_tables(afd_plan_s* p, const double* radii) {
+  const Config& c = p->cfg;
+  const int64_t N = c.N;
+  const int M = c.M, tpr = c.geom.tpr, E = c.geom.E;
+  std::vector<double> omega(2 * size_t(N));
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int64_t n = 0; n < N; ++n) {
+    const long double ang = two_pi * (long double)n / (long double)N;
+    omega[2 * n] = (double)cosl(ang);
+    omega[2 * n + 1] = (double)sinl(ang);
+  }
+  std::vector<double> tw(2 * size_t(c.geom.twsize + 1), 0.0);
+  fft_twiddles(c.logn, c.fp64, tw.data());
+  std::vector<double> pw(size_t(M) * tpr), pv(size_t(M) * E), sc(M);
+  for (int m = 0; m < M; ++m) {
+    const long double r = radii[m];
+    for (int t = 0; t < tpr; ++t) pw[size_t(m) * tpr + t] = t == 0 ? 1.0 : (double)powl(r, (long double)t);
+    for (int v = 0; v < E; ++v)
+      pv[size_t(m) * E + v] = v == 0 ? 1.0 : (double)powl(r, (long double)tpr * (long double)v);
+    const long double rN = powl(r, (long double)N);
+    sc[m] = (double)(sqrtl((1.0L - r) * (1.0L + r)) / ((long double)N * (1.0L - rN)));
+  }
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    return hipMemcpy(p->arena + off, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e = up(p->L.radii, radii, 8 * size_t(M));
+  if (e == hipSuccess) e = up(p->L.omega, omega.data(), omega.size() * 8);
+  if (c.fp64) {
+    if (e == hipSuccess) e = up(p->L.tw, tw.data(), tw.size() * 8);
+    if (e == hipSuccess) e = up(p->L.pw, pw.data(), pw.size() * 8);
+    if (e == hipSuccess) e = up(p->L.pv, pv.data(), pv.size() * 8);
+    if (e == hipSuccess) e = up(p->L.scale, sc.data(), sc.size() * 8);
+  } else {
+    auto f32 = [](const std::vector<double>& v) {
+      std::vector<float> o(v.size());
+      for (size_t i = 0; i < v.size(); ++i) o[i] = float(v[i]);
+      return o;
+    };
+    const std::vector<float> tw32 = f32(tw), pw32 = f32(pw), pv32 = f32(pv), sc32 = f32(sc);
+    if (e == hipSuccess) e = up(p->L.tw, tw32.data(), tw32.size() * 4);
+    if (e == hipSuccess) e = up(p->L.pw, pw32.data(), pw32.size() * 4);
+    if (e == hipSuccess) e = up(p->L.pv, pv32.data(), pv32.size() * 4);
+    if (e == hipSuccess) e = up(p->L.scale, sc32.data(), sc32.size() * 4);
+  }
+  const int32_t f0[2] = {p->zero_m < 0 ? 0 : p->zero_m, 0};
+  if (e == hipSuccess) e = up(p->L.forced0, f0, sizeof(f0));
+  if (e == hipSuccess) e = hipMemset(p->arena + p->L.nonfinite, 0, 4);
+  if (e != hipSuccess) return hip_fail(e, "uploading plan tables");
+  return AFD_OK;
+}
+
+// Result staging: idx(2s i32) a(2s) coef(2s) energy(s+1) margin(s) kcount(s i32) flags(s i32)
+struct ResPtrs {
+  int32_t* idx;
+  double* a;
+  double* coef;
+  double* energy;
+  double* margin;
+  int32_t* kcount;
+  int32_t* flags;
+  size_t total;
+};
+
+ResPtrs res_layout(unsigned char* base, int steps) {
+  ResPtrs r{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, 256);
+    return base + at;
+  };
+  const size_t s = size_t(steps < 1 ? 1 : steps);
+  r.idx = reinterpret_cast<int32_t*>(take(8 * s));
+  r.a = reinterpret_cast<double*>(take(16 * s));
+  r.coef = reinterpret_cast<double*>(take(16 * s));
+  r.energy = reinterpret_cast<double*>(take(8 * (s + 1)));
+  r.margin = reinterpret_cast<double*>(take(8 * s));
+  r.kcount = reinterpret_cast<int32_t*>(take(4 * s));
+  r.flags = reinterpret_cast<int32_t*>(take(4 * s));
+  r.total = o;
+  return r;
+}
+
+afd_status ensure_res(afd_plan_s* p, int steps) {
+  if (p->res && p->res_steps >= steps) return AFD_OK;
+  if (p->res) {
+    (void)hipFree(p->res);
+    p->res = nullptr;
+  }
+  const size_t bytes = res_layout(nullptr, steps).total;
+  hipError_t e = hipMalloc(&p->res, bytes);
+  if (e != hipSuccess) {
+    p->res = nullptr;
+    return fail(AFD_E_NOMEM, std::string("result staging: ") + hipGetErrorString(e));
+  }
+  p->res_steps = steps;
+  return AFD_OK;
+}
+
+afd_status ensure_forced(afd_plan_s* p, int steps) {
+  if (p->forced && p->forced_steps >= steps) return AFD_OK;
+  if (p->forced) {
+    (void)hipFree(p->forced);
+    p->forced = nullptr;
+  }
+  hipError_t e = hipMalloc(&p->forced, 8 * size_t(steps < 1 ? 1 : steps));
+  if (e != hipSuccess) {
+    p->forced = nullptr;
+    return fail(AFD_E_NOMEM, std::string("forced indices: ") + hipGetErrorString(e));
+  }
+  p->forced_steps = steps;
+  return AFD_OK;
+}
+
+struct Timer {
+  afd_plan_s* p;
+  int kind;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pairs;
+  size_t next = 0;
+  hipError_t begin(int k) {
+    if (p->time_kind != k) return hipSuccess;
+    if (next >= p->events.size() / 2) {
+      hipEvent_t a, b;
+      hipError_t e = hipEventCreate(&a);
+      if (e != hipSuccess) return e;
+      e = hipEventCreate(&b);
+      if (e != hipSuccess) return e;
+      p->events.push_back(a);
+      p->events.push_back(b);
+    }
+    return hipEventRecord(p->events[2 * next], p->stream);
+  }
+  hipError_t end(int k) {
+    if (p->time_kind != k) return hipSuccess;
+    const hipError_t e = hipEventRecord(p->events[2 * next + 1], p->stream);
+    ++next;
+    return e;
+  }
+  hipError_t collect() {
+    for (size_t i = 0; i < next; ++i) {
+      float ms = 0.f;
+      const hipError_t e = hipEventElapsedTime(&ms, p->events[2 * i], p->events[2 * i + 1]);
+      if (e != hipSuccess) return e;
+      p->time_ms += ms;
+      p->time_launches += 1;
+    }
+    return hipSuccess;
+  }
+};
+
+#define HIPCHK(expr, where)                     \
+  do {                                          \
+    const hipError_t _e = (expr);               \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* forced_user, afd_result* out) {
+  if (!p) return fail(AFD_E_INVALID, "plan is NULL");
+  if (!signal) return fail(AFD_E_INVALID, "signal is NULL");
+  if (!out) return fail(AFD_E_INVALID, "out is NULL");
+  if (steps < 0) return fail(AFD_E_INVALID, "steps must be >= 0");
+  if (!out->energy || (steps > 0 && (!out->index || !out->a || !out->coef)))
+    return fail(AFD_E_INVALID, "out.energy (and out.index, out.a, out.coef when steps > 0) are required");
+  const Config& c = p->cfg;
+  const int N = int(c.N);
+  HIPCHK(hipSetDevice(p->device), "hipSetDevice");
+
+  const bool sig_dev = is_device_pointer(signal);
+  if (!sig_dev) {
+    for (int64_t i = 0; i < 2 * c.N; ++i)
+      if (!std::isfinite(signal[i])) return fail(AFD_E_NONFINITE, "signal holds NaN or Inf");
+  }
+  std::vector<int32_t> forced_host;
+  if (forced_user) {
+    forced_host.resize(2 * size_t(steps));
+    if (steps > 0)
+      HIPCHK(hipMemcpy(forced_host.data(), forced_user, 8 * size_t(steps), hipMemcpyDefault), "reading forced indices");
+    for (int k = 0; k < steps; ++k) {
+      if (forced_host[2 * k] < 0 || forced_host[2 * k] >= c.M || forced_host[2 * k + 1] < 0 ||
+          forced_host[2 * k + 1] >= N)
+        return fail(AFD_E_INVALID, "forced index outside [0,M) x [0,N)");
+    }
+    afd_status st = ensure_forced(p, steps);
+    if (st != AFD_OK) return st;
+    if (steps > 0)
+      HIPCHK(hipMemcpyAsync(p->forced, forced_host.data(), 8 * size_t(steps), hipMemcpyHostToDevice, p->stream),
+             "uploading forced indices");
+  }
+  afd_status st = ensure_res(p, steps);
+  if (st != AFD_OK) return st;
+  const ResPtrs R = res_layout(p->res, steps);
+
+  hipStream_t s = p->stream;
+  double* g64 = p->at<double>(p->L.g64);
+  float* g32 = c.fp64 ? nullptr : p->at<float>(p->L.g32);
+  void* cspec = p->at<void>(p->L.c);
+  const double* radii = p->at<double>(p->L.radii);
+  const double* omega = p->at<double>(p->L.omega);
+  Winner* win = p->at<Winner>(p->L.winner);
+  CandList* cand = p->at<CandList>(p->L.cand);
+  double* partials = p->at<double>(p->L.partials);
+  double* epart = p->at<double>(p->L.epart);
+  int* nonfinite = p->at<int>(p->L.nonfinite);
+  const int32_t* forced0 = p->at<int32_t>(p->L.forced0);
+
+  HIPCHK(hipMemsetAsync(nonfinite, 0, 4, s), "clearing flag");
+  HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N), sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
+         "copying signal");
+  HIPCHK(launch_prepare(nullptr, g64, g32, N, epart, nonfinite, s), "k_prepare");
+  HIPCHK(launch_record(win, radii, omega, epart, c.nparts, N, c.M, -1, R.idx, R.a, R.coef, R.energy, R.margin, R.kcount,
+                       R.flags, s),
+         "k_record");
+
+  RadiusParams rp{};
+  rp.c = cspec;
+  rp.pw = p->at<void>(p->L.pw);
+  rp.pv = p->at<void>(p->L.pv);
+  rp.scale = p->at<void>(p->L.scale);
+  rp.tw = p->at<void>(p->L.tw);
+  rp.M = c.M;
+  rp.rpb = c.rpb;
+  rp.tau_list = kTauList > p->tau_band ? kTauList : p->tau_band;
+  rp.tau_band = p->tau_band;
+  rp.out = p->at<void>(p->L.blocks);
+
+  Timer tm{p, p->time_kind};
+  for (int k = 0; k < steps; ++k) {
+    const int32_t* fsrc = nullptr;
+    int fstep = k;
+    if (forced_user) {
+      fsrc = p->forced;
+    } else if (p->first_a_zero && k == 0) {
+      fsrc = forced0;
+      fstep = 0;
+    }
+    if (fsrc) {
+      HIPCHK(launch_force(fsrc, fstep, N, cand, s), "k_force");
+      HIPCHK(launch_recheck(cand, g64, omega, radii, N, c.nch, partials, s), "k_recheck");
+      HIPCHK(launch_finalize(cand, partials, radii, omega, N, c.nch, win, s), "k_finalize");
+    } else {
+      HIPCHK(tm.begin(kTimeFft), "event");
+      HIPCHK(launch_fft_fwd(c.logn, c.fp64, c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32),
+                            rp.tw, cspec, s),
+             "k_fft_fwd");
+      HIPCHK(tm.end(kTimeFft), "event");
+      HIPCHK(tm.begin(kTimeRadius), "event");
+      HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, s), "k_radius");
+      HIPCHK(tm.end(kTimeRadius), "event");
+      if (c.fp64) {
+        HIPCHK(launch_merge64(p->at<BlockBest64>(p->L.blocks), c.nblocks, N, win, s), "k_merge64");
+      } else {
+        HIPCHK(launch_select32(p->at<BlockList32>(p->L.blocks), c.nblocks, p->recheck_k, p->tau_band, rp.tau_list,
+                               cand, s),
+               "k_select32");
+        HIPCHK(launch_recheck(cand, g64, omega, radii, N, c.nch, partials, s), "k_recheck");
+        HIPCHK(launch_finalize(cand, partials, radii, omega, N, c.nch, win, s), "k_finalize");
+      }
+    }
+    HIPCHK(tm.begin(kTimeUpdate), "event");
+    HIPCHK(launch_update(win, radii, omega, g64, g32, N, c.M, epart, s), "k_update");
+    HIPCHK(tm.end(kTimeUpdate), "event");
+    HIPCHK(launch_record(win, radii, omega, epart, c.nparts, N, c.M, k, R.idx, R.a, R.coef, R.energy, R.margin, R.kcount,
+                         R.flags, s),
+           "k_record");
+  }
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, nonfinite, 4, hipMemcpyDeviceToHost, s), "reading flag");
+  HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
+  HIPCHK(tm.collect(), "hipEventElapsedTime");
+  if (bad) return fail(AFD_E_NONFINITE, "signal holds NaN or Inf");
+
+  const size_t S = size_t(steps);
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s) : hipSuccess;
+  };
+  HIPCHK(cp(out->index, R.idx, 8 * S), "copy index");
+  HIPCHK(cp(out->a, R.a, 16 * S), "copy a");
+  HIPCHK(cp(out->coef, R.coef, 16 * S), "copy coef");
+  HIPCHK(cp(out->energy, R.energy, 8 * (S + 1)), "copy energy");
+  if (out->margin) HIPCHK(cp(out->margin, R.margin, 8 * S), "copy margin");
+  if (out->recheck_count) HIPCHK(cp(out->recheck_count, R.kcount, 4 * S), "copy recheck_count");
+  if (out->flags) HIPCHK(cp(out->flags, R.flags, 4 * S), "copy flags");
+  if (out->remainder) HIPCHK(cp(out->remainder, g64, 16 * size_t(N)), "copy remainder");
+  HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
+  g_last_error.clear();
+  return AFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan* out) {
+  if (!out) return fail(AFD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  Config cfg;
+  afd_status st = validate(desc, &cfg);
+  if (st != AFD_OK) return st;
+  afd_plan_s* p = new (std::nothrow) afd_plan_s();
+  if (!p) return fail(AFD_E_NOMEM, "host allocation failed");
+  p->cfg = cfg;
+  p->L = layout_of(cfg);
+  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  p->recheck_k = desc->recheck_k == 0 ? 8 : desc->recheck_k;
+  p->tau_band = desc->recheck_band == 0.0 ? kTauBandDefault : float(desc->recheck_band);
+  p->first_a_zero = desc->first_a_zero != 0;
+  for (int i = 0; i < desc->m; ++i)
+    if (desc->radii[i] == 0.0) {
+      p->zero_m = i;
+      break;
+    }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) {
+    static bool attrs_done = false;
+    if (!attrs_done) {
+      e = setup_kernel_attributes();
+      if (e == hipSuccess) attrs_done = true;
+    }
+  }
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "device setup");
+  }
+  e = hipMalloc(&p->arena, p->L.total);
+  if (e != hipSuccess) {
+    p->arena = nullptr;
+    delete p;
+    return fail(AFD_E_NOMEM, std::string("workspace: ") + hipGetErrorString(e));
+  }
+  st = build_tables(p, desc->radii);
+  if (st != AFD_OK) {
+    afd_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  g_last_error.clear();
+  return AFD_OK;
+}
+
+afd_status afd_decompose(afd_plan plan, const double* signal, int32_t steps, afd_result* out) {
+  return run(plan, signal, steps, nullptr, out);
+}
+
+afd_status afd_replay(afd_plan plan, const double* signal, int32_t steps, const int32_t* forced_index,
+                      afd_result* out) {
+  if (!forced_index && steps > 0) return fail(AFD_E_INVALID, "forced_index is NULL");
+  static const int32_t none[2] = {0, 0};
+  return run(plan, signal, steps, forced_index ? forced_index : none, out);
+}
+
+size_t afd_workspace_bytes(const afd_plan_desc* desc) {
+  Config cfg;
+  if (validate(desc, &cfg) != AFD_OK) return 0;
+  return layout_of(cfg).total;
+}
+
+void afd_plan_destroy(afd_plan plan) {
+  if (!plan) return;
+  for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
+  if (plan->arena) (void)hipFree(plan->arena);
+  if (plan->res) (void)hipFree(plan->res);
+  if (plan->forced) (void)hipFree(plan->forced);
+  delete plan;
+}
+
+const char* afd_status_string(afd_status status) {
+  switch (status) {
+    case AFD_OK: return "AFD_OK";
+    case AFD_E_INVALID: return "AFD_E_INVALID: invalid argument";
+    case AFD_E_NONFINITE: return "AFD_E_NONFINITE: non-finite input";
+    case AFD_E_NOMEM: return "AFD_E_NOMEM: allocation failed";
+    case AFD_E_HIP: return "AFD_E_HIP: HIP runtime error";
+    case AFD_E_UNSUPPORTED: return "AFD_E_UNSUPPORTED: unsupported size";
+  }
+  return "unknown afd_status";
+}
+
+const char* afd_last_error(void) { return g_last_error.c_str(); }
+
+afd_status afd_plan_set_timing(afd_plan plan, const char* kernel, int32_t enable) {
+  if (!plan || !kernel) return fail(AFD_E_INVALID, "plan or kernel is NULL");
+  int kind = kTimeNone;
+  if (std::strcmp(kernel, "radius") == 0) kind = kTimeRadius;
+  else if (std::strcmp(kernel, "fft") == 0) kind = kTimeFft;
+  else if (std::strcmp(kernel, "update") == 0) kind = kTimeUpdate;
+  else return fail(AFD_E_INVALID, "unknown kernel class");
+  plan->time_kind = enable ? kind : kTimeNone;
+  plan->time_ms = 0.0;
+  plan->time_launches = 0;
+  return AFD_OK;
+}
+
+afd_status afd_plan_kernel_time(afd_plan plan, double* ms, int64_t* launches) {
+  if (!plan || !ms || !launches) return fail(AFD_E_INVALID, "NULL argument");
+  *ms = plan->time_ms;
+  *launches = plan->time_launches;
+  return AFD_OK;
+}
+
+afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threads, int32_t* lds_bytes) {
+  if (!plan || !blocks || !threads || !lds_bytes) return fail(AFD_E_INVALID, "NULL argument");
+  *blocks = plan->cfg.nblocks;
+  *threads = plan->cfg.geom.tpr * plan->cfg.rpb;
+  *lds_bytes = radius_lds_bytes(plan->cfg.logn, plan->cfg.fp64, plan->cfg.rpb, !plan->cfg.fp64);
+  return AFD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,341 @@
+// Device building blocks for the Core-AFD kernels on gfx950 (wave64).
+//
+// * Cx<T>: interleaved complex in registers (T = float or double).
+// * Dif<R>: an R-point DFT (R <= 32) held in registers, radix-2 decimation in
+//   frequency with compile-time twiddles; output position p holds bin
+//   bitrev_R(p).
+// * Stockham passes: a length-N transform is spread over TPR = N/E threads
+//   holding E values each.  Before pass p a thread holds x[t + TPR*v],
+//   v = 0..E-1; the pass runs E/R independent radix-R butterfly jobs
+//   (job = t + u*TPR, its inputs x[job + r*N/R] = regs[u + (E/R)*r]), applies
+//   the twiddle e^{+-2 pi i k r/(Ns R)} (k = job mod Ns) and the R-point DFT,
+//   and its output q belongs at y[(job/Ns)*Ns*R + k + q*Ns] of the
+//   self-sorting (Stockham) order.  The exchange between passes goes
+//   through LDS with one pad element every 16 so that the strided writes of
+//   the early passes stay free of bank conflicts.  After the last pass
+//   (radix E, Ns = TPR) the thread holds output bins t + TPR*bitrev_E(p).
+// The forward DFT of the samples (Sec. 3.1, eqs. term4/term3) and the
+// per-radius inverse DFT (Sec. 3.1, eq. rcl and Theorem 2.1, eq. term8) are
+// both this transform with SIGN = -1 and +1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <utility>
+
+namespace afd {
+
+template <typename T>
+struct Cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> csqr(Cx<T> a) {
+  return {fma(a.x, a.x, -a.y * a.y), T(2) * a.x * a.y};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cscale(Cx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// ---------------------------------------------------------------- shape
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+
+// Pass structure of a length 2^LOGN transform with E values per thread: an
+// optional first pass of radix 2^(LOGN mod log2 E), then passes of radix E.
+template <int LOGN, int E>
+struct Shape {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int LE = ilog2c(E);
+  static constexpr int Q0 = LOGN % LE;
+  static constexpr int NP = LOGN / LE + (Q0 ? 1 : 0);
+  static constexpr int TPR = N / E;
+  static_assert(E >= 2 && (E & (E - 1)) == 0 && E <= N, "bad E");
+  __host__ __device__ static constexpr int radix(int p) { return (p == 0 && Q0) ? (1 << Q0) : E; }
+  __host__ __device__ static constexpr int ns(int p) {
+    int s = 1;
+    for (int i = 0; i < p; ++i) s *= radix(i);
+    return s;
+  }
+  // twiddle table: pass p >= 1 owns ns(p) entries e^{+2 pi i k/(ns(p) radix(p))}
+  __host__ __device__ static constexpr int twoff(int p) {
+    int o = 0;
+    for (int i = 1; i < p; ++i) o += ns(i);
+    return o;
+  }
+  __host__ __device__ static constexpr int twsize() { return twoff(NP); }
+  // LDS elements for one transform (one pad element every 16)
+  static constexpr int LDS_ELEMS = N + (N >> 4) + 1;
+};
+
+__host__ __device__ constexpr int bitrev(int v, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+// ---------------------------------------------------------------- constant twiddles
+// cos(2 pi q / 64), q = 0..16 (correctly rounded); the rest by symmetry.
+__host__ __device__ constexpr double kCosQ[17] = {
+    1.0,                  0.9951847266721969,  0.9807852804032304,  0.9569403357322088,
+    0.9238795325112867,   0.881921264348355,   0.8314696123025452,  0.773010453362737,
+    0.7071067811865476,   0.6343932841636455,  0.5555702330196022,  0.47139673682599764,
+    0.3826834323650898,   0.2902846772544624,  0.19509032201612828, 0.0980171403295606,
+    0.0};
+
+__host__ __device__ constexpr double cos64(int q) {
+  q = ((q % 64) + 64) % 64;
+  return q <= 16 ? kCosQ[q] : q <= 32 ? -kCosQ[32 - q] : q <= 48 ? -kCosQ[q - 32] : kCosQ[64 - q];
+}
+__host__ __device__ constexpr double sin64(int q) { return cos64(q - 16); }
+
+// v * e^{SIGN * 2 pi i Q / R}, R | 64
+template <int R, int Q, int SIGN, typename T>
+__device__ __forceinline__ Cx<T> twc(Cx<T> v) {
+  constexpr int q = ((Q % R) + R) % R;
+  if constexpr (q == 0) {
+    return v;
+  } else if constexpr (2 * q == R) {
+    return {-v.x, -v.y};
+  } else if constexpr (4 * q == R) {
+    return {T(-SIGN) * v.y, T(SIGN) * v.x};
+  } else if constexpr (4 * q == 3 * R) {
+    return {T(SIGN) * v.y, T(-SIGN) * v.x};
+  } else if constexpr (8 * q == R) {
+    constexpr T h = T(0.7071067811865476);
+    return {h * (v.x - T(SIGN) * v.y), h * (T(SIGN) * v.x + v.y)};
+  } else if constexpr (8 * q == 3 * R) {
+    constexpr T h = T(0.7071067811865476);
+    return {h * (-v.x - T(SIGN) * v.y), h * (T(SIGN) * v.x - v.y)};
+  } else if constexpr (8 * q == 5 * R) {
+    constexpr T h = T(0.7071067811865476);
+    return {h * (-v.x + T(SIGN) * v.y), h * (-T(SIGN) * v.x - v.y)};
+  } else if constexpr (8 * q == 7 * R) {
+    constexpr T h = T(0.7071067811865476);
+    return {h * (v.x + T(SIGN) * v.y), h * (-T(SIGN) * v.x + v.y)};
+  } else {
+    constexpr int q64 = q * (64 / R);
+    constexpr T c = T(cos64(q64));
+    constexpr T s = T(SIGN * sin64(q64));
+    return {fma(v.x, c, -v.y * s), fma(v.x, s, v.y * c)};
+  }
+}
+
+// R-point DFT on a[OFF + p*STR], p = 0..R-1, in place; output position p
+// holds bin bitrev_R(p).  X[q] = sum_r x[r] e^{SIGN 2 pi i r q / R}.
+template <int R, int SIGN, int OFF, int STR, typename T>
+struct Dif {
+  template <int I>
+  static __device__ __forceinline__ void bfly(Cx<T>* a) {
+    constexpr int i0 = OFF + I * STR, i1 = OFF + (I + R / 2) * STR;
+    const Cx<T> x = a[i0], y = a[i1];
+    a[i0] = cadd(x, y);
+    a[i1] = twc<R, I, SIGN>(csub(x, y));
+  }
+  template <int... I>
+  static __device__ __forceinline__ void stage(Cx<T>* a, std::integer_sequence<int, I...>) {
+    (bfly<I>(a), ...);
+  }
+  static __device__ __forceinline__ void run(Cx<T>* a) {
+    if constexpr (R > 1) {
+      stage(a, std::make_integer_sequence<int, R / 2>{});
+      Dif<R / 2, SIGN, OFF, STR, T>::run(a);
+      Dif<R / 2, SIGN, OFF + (R / 2) * STR, STR, T>::run(a);
+    }
+  }
+};
+
+// a[OFF + r*STR] *= w^r for r = 1..R-1.  Powers come from w, w^2, w^3 and
+// steps of w^4, so no power is more than about six rounded products deep and
+// only five complex values stay live.
+template <int R, int OFF, int STR, typename T>
+__device__ __forceinline__ void apply_twiddles(Cx<T>* a, Cx<T> w) {
+  if constexpr (R == 2) {
+    a[OFF + STR] = cmul(a[OFF + STR], w);
+  } else {
+    const Cx<T> w2 = csqr(w);
+    const Cx<T> w3 = cmul(w2, w);
+    const Cx<T> w4 = csqr(w2);
+    a[OFF + STR] = cmul(a[OFF + STR], w);
+    a[OFF + 2 * STR] = cmul(a[OFF + 2 * STR], w2);
+    a[OFF + 3 * STR] = cmul(a[OFF + 3 * STR], w3);
+    Cx<T> base = w4;
+#pragma unroll
+    for (int q = 1; q < R / 4; ++q) {
+      a[OFF + 4 * q * STR] = cmul(a[OFF + 4 * q * STR], base);
+      a[OFF + (4 * q + 1) * STR] = cmul(a[OFF + (4 * q + 1) * STR], cmul(base, w));
+      a[OFF + (4 * q + 2) * STR] = cmul(a[OFF + (4 * q + 2) * STR], cmul(base, w2));
+      a[OFF + (4 * q + 3) * STR] = cmul(a[OFF + (4 * q + 3) * STR], cmul(base, w3));
+      if (q + 1 < R / 4) base = cmul(base, w4);
+    }
+  }
+}
+
+// One butterfly job u of Stockham pass P, in place on the registers.
+template <typename T, int LOGN, int E, int P, int SIGN, int U>
+__device__ __forceinline__ void pass_job(Cx<T> (&v)[E], int t, const Cx<T>* __restrict__ tw) {
+  using S = Shape<LOGN, E>;
+  constexpr int R = S::radix(P);
+  constexpr int NS = S::ns(P);
+  constexpr int J = E / R;
+  if constexpr (NS > 1) {
+    const int job = t + U * S::TPR;
+    const int k = job & (NS - 1);
+    Cx<T> w = tw[S::twoff(P) + k];
+    if constexpr (SIGN < 0) w.y = -w.y;
+    apply_twiddles<R, U, J>(v, w);
+  }
+  Dif<R, SIGN, U, J, T>::run(v);
+}
+
+template <typename T, int LOGN, int E, int P, int SIGN, int... U>
+__device__ __forceinline__ void pass_jobs(Cx<T> (&v)[E], int t, const Cx<T>* __restrict__ tw,
+                                          std::integer_sequence<int, U...>) {
+  (pass_job<T, LOGN, E, P, SIGN, U>(v, t, tw), ...);
+}
+
+// One Stockham pass P on the registers v (see the file comment).
+template <typename T, int LOGN, int E, int P, int SIGN>
+__device__ __forceinline__ void pass_compute(Cx<T> (&v)[E], int t, const Cx<T>* __restrict__ tw) {
+  using S = Shape<LOGN, E>;
+  pass_jobs<T, LOGN, E, P, SIGN>(v, t, tw, std::make_integer_sequence<int, E / S::radix(P)>{});
+}
+
+// Destination index (in the Stockham order) of output bin q of job u after pass P.
+template <int LOGN, int E, int P>
+__device__ __forceinline__ int pass_dest(int t, int u, int q) {
+  using S = Shape<LOGN, E>;
+  constexpr int R = S::radix(P);
+  constexpr int NS = S::ns(P);
+  const int job = t + u * S::TPR;
+  const int k = job & (NS - 1);
+  return (job / NS) * NS * R + k + q * NS;
+}
+
+// Write the outputs of pass P to LDS (complex elements).
+template <typename T, int LOGN, int E, int P>
+__device__ __forceinline__ void lds_write(const Cx<T> (&v)[E], int t, Cx<T>* lds) {
+  using S = Shape<LOGN, E>;
+  constexpr int R = S::radix(P);
+  constexpr int J = E / R;
+  constexpr int LR = ilog2c(R);
+#pragma unroll
+  for (int u = 0; u < J; ++u) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) lds[lds_pad(pass_dest<LOGN, E, P>(t, u, q))] = v[u + J * bitrev(q, LR)];
+  }
+}
+
+template <typename T, int LOGN, int E, int P, int PART>
+__device__ __forceinline__ void lds_write_part(const Cx<T> (&v)[E], int t, T* lds) {
+  using S = Shape<LOGN, E>;
+  constexpr int R = S::radix(P);
+  constexpr int J = E / R;
+  constexpr int LR = ilog2c(R);
+#pragma unroll
+  for (int u = 0; u < J; ++u) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const Cx<T> val = v[u + J * bitrev(q, LR)];
+      lds[lds_pad(pass_dest<LOGN, E, P>(t, u, q))] = PART == 0 ? val.x : val.y;
+    }
+  }
+}
+
+template <typename T, int LOGN, int E>
+__device__ __forceinline__ void lds_read(Cx<T> (&v)[E], int t, const Cx<T>* lds) {
+  using S = Shape<LOGN, E>;
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] = lds[lds_pad(t + S::TPR * i)];
+}
+
+template <typename T, int LOGN, int E, int PART>
+__device__ __forceinline__ void lds_read_part(Cx<T> (&v)[E], int t, const T* lds) {
+  using S = Shape<LOGN, E>;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const T val = lds[lds_pad(t + S::TPR * i)];
+    if constexpr (PART == 0) v[i].x = val; else v[i].y = val;
+  }
+}
+
+// Full transform on registers: passes 0..NP-1 with LDS exchanges between
+// them.  `lds` points at this transform's LDS region (Shape::LDS_ELEMS
+// complex elements, or that many reals when SPLIT, which exchanges the real
+// parts and then the imaginary parts through half the space).  Every thread
+// of the block must call this (block-wide barriers).
+template <typename T, int LOGN, int E, int SIGN, bool SPLIT, int P = 0>
+__device__ __forceinline__ void fft_regs(Cx<T> (&v)[E], int t, void* lds, const Cx<T>* __restrict__ tw) {
+  using S = Shape<LOGN, E>;
+  if constexpr (P > 0) {
+    if constexpr (SPLIT) {
+      T* l = reinterpret_cast<T*>(lds);
+      lds_write_part<T, LOGN, E, P - 1, 0>(v, t, l);
+      __syncthreads();
+      lds_read_part<T, LOGN, E, 0>(v, t, l);
+      __syncthreads();
+      lds_write_part<T, LOGN, E, P - 1, 1>(v, t, l);
+      __syncthreads();
+      lds_read_part<T, LOGN, E, 1>(v, t, l);
+      __syncthreads();
+    } else {
+      Cx<T>* l = reinterpret_cast<Cx<T>*>(lds);
+      lds_write<T, LOGN, E, P - 1>(v, t, l);
+      __syncthreads();
+      lds_read<T, LOGN, E>(v, t, l);
+      __syncthreads();
+    }
+  }
+  pass_compute<T, LOGN, E, P, SIGN>(v, t, tw);
+  if constexpr (P + 1 < S::NP) fft_regs<T, LOGN, E, SIGN, SPLIT, P + 1>(v, t, lds, tw);
+}
+
+// Output bin held by register p after fft_regs.
+template <int LOGN, int E>
+__device__ __forceinline__ int out_bin(int t, int p) {
+  return t + Shape<LOGN, E>::TPR * bitrev(p, ilog2c(E));
+}
+
+// ---------------------------------------------------------------- selection keys
+// Key order: larger |.|^2 first, then lower flat index.
+__device__ __forceinline__ bool better64(double pa, uint32_t fa, double pb, uint32_t fb) {
+  return pa > pb || (pa == pb && fa < fb);
+}
+
+// FP32 key: (float bits of P >= 0) << 32 | ~f  -- larger key = better.
+__device__ __forceinline__ uint64_t key32(float p, uint32_t f) {
+  return (uint64_t(__float_as_uint(p)) << 32) | uint64_t(~f);
+}
+__device__ __forceinline__ float key_p(uint64_t k) { return __uint_as_float(uint32_t(k >> 32)); }
+__device__ __forceinline__ uint32_t key_f(uint64_t k) { return ~uint32_t(k & 0xffffffffu); }
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor(uint32_t(v), m);
+  const uint32_t hi = __shfl_xor(uint32_t(v >> 32), m);
+  return (uint64_t(hi) << 32) | lo;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const uint64_t o = shfl_xor_u64(v, m);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ float wave_max_f32(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m));
+  return v;
+}
+
+}  // namespace afd

@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/afd.h declares, and rejects invalid arguments before
+any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "afd.h")
+
+
+def _lib():
+    from paper_1711_08604_amd import afd
+    if not os.path.exists(afd.LIB_PATH):
+        from paper_1711_08604_amd import build
+        build.build()
+    return afd, afd.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(afd_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    afd, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(afd.EXPORTS)
+
+
+def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=0, band=0.0):
+    r = np.ascontiguousarray(np.asarray(radii, dtype=np.float64))
+    d = afd.PlanDesc()
+    d.n = n
+    d.m = r.shape[0]
+    d.radii = r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.precision = precision
+    d.recheck_k = recheck_k
+    d.first_a_zero = first_a_zero
+    d.recheck_band = band
+    return d, r
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=1000), 1), (dict(n=1), 1), (dict(n=0), 1), (dict(n=-4), 1),
+    (dict(n=1 << 21), 5), (dict(radii=()), 1), (dict(radii=(0.2, 1.0)), 1), (dict(radii=(-0.1,)), 1),
+    (dict(radii=(np.nan,)), 1), (dict(radii=(np.inf,)), 1), (dict(precision=7), 1),
+    (dict(recheck_k=-1), 1), (dict(recheck_k=257), 1), (dict(band=-1e-3), 1), (dict(band=0.5), 1),
+    (dict(first_a_zero=1, radii=(0.1, 0.2)), 1), (dict(n=1 << 16, radii=np.zeros(1 << 15)), 1),
+])
+def test_plan_create_rejects(kw, status):
+    afd, lib = _lib()
+    d, keep = _desc(afd, **kw)
+    h = ctypes.c_void_p(123)
+    st = lib.afd_plan_create(ctypes.byref(d), None, ctypes.byref(h))
+    assert st == status, (kw, st, lib.afd_last_error())
+    assert h.value is None
+    assert lib.afd_last_error().decode() != ""
+    assert lib.afd_workspace_bytes(ctypes.byref(d)) == 0
+
+
+def test_null_arguments():
+    afd, lib = _lib()
+    assert lib.afd_plan_create(None, None, None) == 1
+    h = ctypes.c_void_p()
+    assert lib.afd_plan_create(None, None, ctypes.byref(h)) == 1
+    rd = afd.ResultDesc()
+    assert lib.afd_decompose(None, None, 1, ctypes.byref(rd)) == 1
+    assert lib.afd_replay(None, None, 1, None, ctypes.byref(rd)) == 1
+    lib.afd_plan_destroy(None)
+    assert lib.afd_plan_set_timing(None, b"radius", 1) == 1
+    assert lib.afd_workspace_bytes(None) == 0
+
+
+def test_workspace_bytes_scales():
+    afd, lib = _lib()
+    d1, k1 = _desc(afd, n=1024, radii=np.linspace(0, 0.99, 100))
+    d2, k2 = _desc(afd, n=16384, radii=np.linspace(0, 0.999, 1000), precision=1)
+    b1 = lib.afd_workspace_bytes(ctypes.byref(d1))
+    b2 = lib.afd_workspace_bytes(ctypes.byref(d2))
+    assert 0 < b1 < b2
+    # tables dominate: 16 B per sample of omega + the per-radius power tables
+    assert b2 >= 16 * 16384 + 4 * 1000 * (1024 + 16)
+
+
+def test_status_strings():
+    afd, lib = _lib()
+    for s in range(6):
+        assert lib.afd_status_string(s).decode().startswith("AFD_")
