@@ -61,7 +61,7 @@ typedef struct {
   const double* radii;    /* host pointer, length M, each in [0, 1); any order; copied at
                              create.  Grid index m refers to position m of this array.        */
   afd_precision precision;
-  int32_t recheck_k;      /* FP32 mode: minimum short-list length, 1..256 (0 -> 8)             */
+  int32_t recheck_k;      /* FP32 mode: minimum short-list length, 1..64 (0 -> 8)              */
   int32_t first_a_zero;   /* 1: step 1 takes a_1 = 0 (the grid point (m0, 0) of the first
                              radius equal to 0) instead of the maximum; requires such a radius */
   double recheck_band;    /* FP32 mode: relative band below the FP32 maximum whose points are

@@ -67,7 +67,7 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
   if (!d->radii) return fail(AFD_E_INVALID, "radii is NULL");
   if (int64_t(d->m) * d->n >= (int64_t(1) << 31)) return fail(AFD_E_INVALID, "M*N must be < 2^31");
   if (d->precision != AFD_FP64 && d->precision != AFD_FP32_RECHECK) return fail(AFD_E_INVALID, "bad precision");
-  if (d->recheck_k < 0 || d->recheck_k > kKMax) return fail(AFD_E_INVALID, "recheck_k must be in 0..256");
+  if (d->recheck_k < 0 || d->recheck_k > kListC) return fail(AFD_E_INVALID, "recheck_k must be in 0..64");
   if (!(d->recheck_band >= 0.0) || d->recheck_band > 1e-4)
     return fail(AFD_E_INVALID, "recheck_band must be in [0, 1e-4]");
   bool has_zero = false;
@@ -384,7 +384,6 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.tw = p->at<void>(p->L.tw);
   rp.M = c.M;
   rp.rpb = c.rpb;
-  rp.tau_list = kTauList > p->tau_band ? kTauList : p->tau_band;
   rp.tau_band = p->tau_band;
   rp.out = p->at<void>(p->L.blocks);
 
@@ -414,8 +413,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       if (c.fp64) {
         HIPCHK(launch_merge64(p->at<BlockBest64>(p->L.blocks), c.nblocks, N, win, s), "k_merge64");
       } else {
-        HIPCHK(launch_select32(p->at<BlockList32>(p->L.blocks), c.nblocks, p->recheck_k, p->tau_band, rp.tau_list,
-                               cand, s),
+        HIPCHK(launch_select32(p->at<BlockList32>(p->L.blocks), c.nblocks, p->recheck_k, p->tau_band, cand, s),
                "k_select32");
         HIPCHK(launch_recheck(cand, g64, omega, radii, N, c.nch, partials, s), "k_recheck");
         HIPCHK(launch_finalize(cand, partials, radii, omega, N, c.nch, win, s), "k_finalize");

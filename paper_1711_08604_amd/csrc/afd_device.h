@@ -86,7 +86,7 @@ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 
 // ---------------------------------------------------------------- constant twiddles
 // cos(2 pi q / 64), q = 0..16 (correctly rounded); the rest by symmetry.
-__host__ __device__ constexpr double kCosQ[17] = {
+constexpr double kCosQ[17] = {
     1.0,                  0.9951847266721969,  0.9807852804032304,  0.9569403357322088,
     0.9238795325112867,   0.881921264348355,   0.8314696123025452,  0.773010453362737,
     0.7071067811865476,   0.6343932841636455,  0.5555702330196022,  0.47139673682599764,

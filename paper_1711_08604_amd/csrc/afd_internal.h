@@ -12,11 +12,10 @@ namespace afd {
 constexpr int kMaxLogN = 20;       // N <= 2^20
 constexpr int kMaxLdsLogN = 14;    // single-workgroup (LDS-resident) transforms up to 2^14
 constexpr int kListC = 64;         // per-block candidate list length (FP32 mode)
-constexpr int kListCap = 256;      // per-block LDS gather capacity before the exact fallback
+constexpr int kListCap = 1024;     // per-block LDS gather capacity before the exact fallback
 constexpr int kKMax = 256;         // longest short-list re-checked in double
 constexpr int kSelCap = 1024;      // global gather capacity of the short-list selection
 constexpr float kTauBandDefault = 4e-6f;  // default re-check band (relative to the FP32 maximum)
-constexpr float kTauList = 2e-4f;  // first per-block list band (relative to the block maximum)
 
 // flags (per step)
 constexpr int kFlagBandTruncated = 1;
@@ -65,8 +64,7 @@ struct RadiusParams {
   const void* tw;     // Stockham twiddles of the inverse transform
   int M;
   int rpb;            // radii per block
-  float tau_list;
-  float tau_band;
+  float tau_band;     // FP32 lists: relative band below the block maximum
   void* out;          // BlockBest64[blocks] or BlockList32[blocks]
 };
 
@@ -89,8 +87,8 @@ hipError_t setup_kernel_attributes();
 hipError_t launch_fft_fwd(int logn, bool fp64, const void* g, const void* tw, void* c, hipStream_t s);
 hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, hipStream_t s);
 hipError_t launch_merge64(const BlockBest64* blocks, int nblocks, int N, Winner* w, hipStream_t s);
-hipError_t launch_select32(const BlockList32* lists, int nblocks, int recheck_k, float tau_band, float tau_list,
-                           CandList* cand, hipStream_t s);
+hipError_t launch_select32(const BlockList32* lists, int nblocks, int recheck_k, float tau_band, CandList* cand,
+                           hipStream_t s);
 hipError_t launch_force(const int32_t* forced, int step, int N, CandList* cand, hipStream_t s);
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii,
                           int N, int nch, double* partials, hipStream_t s);

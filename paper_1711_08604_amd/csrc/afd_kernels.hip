@@ -35,7 +35,7 @@ __host__ __device__ constexpr size_t fft_region_bytes() {
   return align16(size_t(S::LDS_ELEMS) * (pickSplit<LOGN>() ? sizeof(T) : sizeof(Cx<T>)));
 }
 
-constexpr size_t kScratchBytes = 256 + sizeof(uint64_t) * kListCap;
+constexpr size_t kScratchBytes = 512 + sizeof(uint64_t) * kListCap;
 
 // ---------------------------------------------------------------- forward DFT (one workgroup)
 template <int LOGN>
@@ -135,76 +135,139 @@ __device__ __forceinline__ void select_best(const Cx<T> (&v)[pickE<LOGN>()], boo
   }
 }
 
+// Descending bitonic sort of buf[0..n) in LDS (n <= p2 <= kListCap, padded with 0).
+__device__ __forceinline__ void lds_sort_desc(uint64_t* buf, uint32_t n) {
+  uint32_t p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  for (uint32_t i = n + threadIdx.x; i < p2; i += blockDim.x) buf[i] = 0;
+  __syncthreads();
+  for (uint32_t k = 2; k <= p2; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = buf[i], c = buf[ixj];
+          if ((i & k) == 0 ? (a < c) : (a > c)) {
+            buf[i] = c;
+            buf[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Append key k of every lane with q set to buf (wave-aggregated: one LDS
+// atomic per wave); entries past cap are counted but dropped.
+__device__ __forceinline__ void wave_append(bool q, uint64_t k, uint32_t* cnt, uint64_t* buf, uint32_t cap) {
+  const uint64_t mask = __ballot(q);
+  if (mask == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(cnt, uint32_t(__popcll(mask)));
+  base = __shfl(base, leader);
+  if (q) {
+    const uint32_t pos = base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
+    if (pos < cap) buf[pos] = k;
+  }
+}
+
+// FP32 block list: the block's points within tau_band of the block maximum,
+// best first, at most kListC of them (exact top by key).
 template <int LOGN>
 __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<LOGN>()], bool active, float sc,
-                                            uint32_t fbase, int t, unsigned char* scratch, float tau_list,
-                                            float tau_band, BlockList32* out) {
+                                            uint32_t fbase, int t, unsigned char* scratch, float tau_band,
+                                            uint32_t fstart, uint32_t nactive, BlockList32* out) {
   constexpr int E = pickE<LOGN>();
   float P[E];
-  float pm = -1.f;
+  float pm = -1.f, pn = 3.4e38f;
 #pragma unroll
   for (int p = 0; p < E; ++p) {
     const float vx = v[p].x * sc, vy = v[p].y * sc;
     P[p] = active ? fmaf(vx, vx, vy * vy) : -1.f;
     pm = fmaxf(pm, P[p]);
+    if (active) pn = fminf(pn, P[p]);
   }
-  pm = wave_max_f32(pm);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    pm = fmaxf(pm, __shfl_xor(pm, m));
+    pn = fminf(pn, __shfl_xor(pn, m));
+  }
   float* wmax = reinterpret_cast<float*>(scratch);                 // [16]
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(scratch + 64);       // [1]
-  uint64_t* wbest = reinterpret_cast<uint64_t*>(scratch + 128);    // [16]
-  uint64_t* keys = reinterpret_cast<uint64_t*>(scratch + 256);     // [kListCap]
+  float* wmin = reinterpret_cast<float*>(scratch + 64);            // [16]
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(scratch + 128);      // [1]
+  uint64_t* wbest = reinterpret_cast<uint64_t*>(scratch + 256);    // [16]
+  uint64_t* keys = reinterpret_cast<uint64_t*>(scratch + 512);     // [kListCap]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = (blockDim.x + 63) >> 6;
-  if (lane == 0) wmax[wave] = pm;
+  if (lane == 0) {
+    wmax[wave] = pm;
+    wmin[wave] = pn;
+  }
   if (tid == 0) *cnt = 0;
   __syncthreads();
-  float pb = wmax[0];
-  for (int w = 1; w < nw; ++w) pb = fmaxf(pb, wmax[w]);
-
-  float tau = tau_list;
-  uint32_t n = 0;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    const float theta = pb - pb * tau;
-#pragma unroll
-    for (int p = 0; p < E; ++p) {
-      if (P[p] >= theta && P[p] >= 0.f) {
-        const uint32_t pos = atomicAdd(cnt, 1u);
-        if (pos < uint32_t(kListCap)) keys[pos] = key32(P[p], fbase + uint32_t(out_bin<LOGN, E>(t, p)));
-      }
-    }
-    __syncthreads();
-    n = *cnt;
-    if (n <= uint32_t(kListCap) || attempt == 1 || tau <= tau_band) break;
-    __syncthreads();
-    if (tid == 0) *cnt = 0;
-    __syncthreads();
-    tau = tau_band;
+  float pb = wmax[0], pbn = wmin[0];
+  for (int w = 1; w < nw; ++w) {
+    pb = fmaxf(pb, wmax[w]);
+    pbn = fminf(pbn, wmin[w]);
   }
+  BlockList32* o = out + blockIdx.x;
 
-  if (n <= uint32_t(kListCap)) {
-    for (uint32_t i = tid; i < n; i += blockDim.x) {
-      const uint64_t ki = keys[i];
-      uint32_t rank = 0;
-      for (uint32_t j = 0; j < n; ++j) rank += keys[j] > ki ? 1u : 0u;
-      if (rank < uint32_t(kListC)) out[blockIdx.x].keys[rank] = ki;
-    }
+  if (pb == pbn) {
+    // every value of the block is exactly equal (e.g. the r = 0 ring): the
+    // best keys are the lowest flat indices
+    const uint32_t c = nactive < uint32_t(kListC) ? nactive : uint32_t(kListC);
+    for (uint32_t i = tid; i < c; i += blockDim.x) o->keys[i] = key32(pb, fstart + i);
     if (tid == 0) {
-      out[blockIdx.x].pmax = pb;
-      out[blockIdx.x].count = n < uint32_t(kListC) ? n : uint32_t(kListC);
-      out[blockIdx.x].total = n;
-      out[blockIdx.x].flags = 0;
+      o->pmax = pb;
+      o->count = c;
+      o->total = nactive;
+      o->flags = uint32_t(kFlagFallback);
     }
     return;
   }
 
-  // Exact fallback (flat or all-zero block): kListC rounds of block argmax.
+  const float theta = pb - pb * tau_band;
+#pragma unroll
+  for (int p = 0; p < E; ++p) {
+    const bool q = P[p] >= theta && P[p] >= 0.f;
+    wave_append(q, key32(P[p], fbase + uint32_t(out_bin<LOGN, E>(t, p))), cnt, keys, uint32_t(kListCap));
+  }
+  __syncthreads();
+  const uint32_t n = *cnt;
+
+  if (n <= uint32_t(kListCap)) {
+    if (n <= 64) {
+      for (uint32_t i = tid; i < n; i += blockDim.x) {
+        const uint64_t ki = keys[i];
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < n; ++j) rank += keys[j] > ki ? 1u : 0u;
+        o->keys[rank] = ki;  // rank < n <= 64 = kListC
+      }
+    } else {
+      lds_sort_desc(keys, n);
+      for (uint32_t i = tid; i < uint32_t(kListC); i += blockDim.x) o->keys[i] = keys[i];
+    }
+    if (tid == 0) {
+      o->pmax = pb;
+      o->count = n < uint32_t(kListC) ? n : uint32_t(kListC);
+      o->total = n;
+      o->flags = 0;
+    }
+    return;
+  }
+
+  // Exact fallback (more than kListCap points in the band, not all equal):
+  // kListC rounds of block argmax.
   uint32_t taken = 0;
   uint32_t rounds = 0;
   for (; rounds < uint32_t(kListC); ++rounds) {
     uint64_t tb = 0;
 #pragma unroll
     for (int p = 0; p < E; ++p) {
-      if (!((taken >> p) & 1u) && P[p] >= 0.f) {
+      if (!((taken >> p) & 1u) && P[p] >= theta) {
         const uint64_t k = key32(P[p], fbase + uint32_t(out_bin<LOGN, E>(t, p)));
         tb = k > tb ? k : tb;
       }
@@ -216,17 +279,17 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<LOGN>()],
     for (int w = 1; w < nw; ++w) b = wbest[w] > b ? wbest[w] : b;
     __syncthreads();
     if (b == 0) break;
-    if (tid == 0) out[blockIdx.x].keys[rounds] = b;
+    if (tid == 0) o->keys[rounds] = b;
 #pragma unroll
     for (int p = 0; p < E; ++p) {
-      if (P[p] >= 0.f && key32(P[p], fbase + uint32_t(out_bin<LOGN, E>(t, p))) == b) taken |= 1u << p;
+      if (P[p] >= theta && key32(P[p], fbase + uint32_t(out_bin<LOGN, E>(t, p))) == b) taken |= 1u << p;
     }
   }
   if (tid == 0) {
-    out[blockIdx.x].pmax = pb;
-    out[blockIdx.x].count = rounds;
-    out[blockIdx.x].total = n;
-    out[blockIdx.x].flags = uint32_t(kFlagFallback);
+    o->pmax = pb;
+    o->count = rounds;
+    o->total = n;
+    o->flags = uint32_t(kFlagFallback);
   }
 }
 
@@ -265,7 +328,9 @@ __global__ __launch_bounds__(radius_threads<LOGN>()) void k_radius(RadiusParams 
   const T sc = scale[mm];
   const uint32_t fbase = uint32_t(mm) * uint32_t(N);
   if constexpr (LIST) {
-    select_list<LOGN>(v, active, sc, fbase, t, scratch, prm.tau_list, prm.tau_band,
+    const uint32_t r0 = uint32_t(blockIdx.x) * uint32_t(prm.rpb);
+    const uint32_t ract = uint32_t(prm.M) - r0 < uint32_t(prm.rpb) ? uint32_t(prm.M) - r0 : uint32_t(prm.rpb);
+    select_list<LOGN>(v, active, sc, fbase, t, scratch, prm.tau_band, r0 * uint32_t(N), ract * uint32_t(N),
                       reinterpret_cast<BlockList32*>(prm.out));
   } else {
     select_best<LOGN, T>(v, active, sc, fbase, t, scratch, reinterpret_cast<BlockBest64*>(prm.out));
@@ -333,12 +398,12 @@ __global__ __launch_bounds__(1024) void k_merge64(const BlockBest64* __restrict_
 }
 
 // ---------------------------------------------------------------- FP32 short-list
-// Global short-list from the per-block lists: every listed point within
-// tau_band of the FP32 maximum (the re-check band), and at least recheck_k
-// points (the band is widened by 8x steps up to tau_list to find them),
-// sorted by key and cut at kKMax.  A gather that overflows kSelCap (a flat
-// grid: all-zero or exactly tied values) falls back to an exact pop-merge of
-// the sorted per-block lists.
+// Global short-list from the per-block lists (each: its points within the
+// re-check band of the block maximum, best first): every listed point within
+// tau_band of the FP32 maximum, sorted by key and cut at kKMax; if that is
+// fewer than recheck_k points, the best points of the next-best blocks are
+// appended until it is not.  A gather that overflows kSelCap (a flat grid:
+// all-zero or exactly tied values) falls back to an exact pop-merge.
 __device__ __forceinline__ float block_max_f32(float v, float* wf) {
   v = wave_max_f32(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -352,75 +417,94 @@ __device__ __forceinline__ float block_max_f32(float v, float* wf) {
 }
 
 __global__ __launch_bounds__(1024) void k_select32(const BlockList32* __restrict__ lists, int nb, int recheck_k,
-                                                   float tau_band, float tau_list, uint32_t* __restrict__ heads,
+                                                   float tau_band, uint32_t* __restrict__ heads,
                                                    CandList* __restrict__ cand) {
   __shared__ uint64_t buf[kSelCap];
+  __shared__ uint32_t cblk[kSelCap];
   __shared__ uint64_t wb[16];
   __shared__ float wf[16];
-  __shared__ uint32_t scount, sflags;
-  const int tid = threadIdx.x;
+  __shared__ uint32_t scount, sblocks, sflags;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
   float pm = -1.f;
   uint32_t fl = 0;
   for (int b = tid; b < nb; b += blockDim.x) {
     fl |= lists[b].flags;
-    if (lists[b].count > 0) pm = fmaxf(pm, key_p(lists[b].keys[0]));
+    if (lists[b].count > 0) pm = fmaxf(pm, lists[b].pmax);
   }
-  if (tid == 0) sflags = 0;
-  const float pg = block_max_f32(pm, wf);  // contains a barrier after sflags = 0
+  if (tid == 0) {
+    sflags = 0;
+    scount = 0;
+    sblocks = 0;
+  }
+  const float pg = block_max_f32(pm, wf);  // its barriers order the initialisation above
   if (fl) atomicOr(&sflags, fl & uint32_t(kFlagFallback));
-
-  float tau = tau_band;
-  uint32_t n = 0, band = 0;
-  for (int attempt = 0;; ++attempt) {
-    if (tid == 0) scount = 0;
-    __syncthreads();
-    const float theta = pg - pg * tau;
-    for (int b = tid; b < nb; b += blockDim.x) {
-      const uint32_t cnt = lists[b].count;
-      for (uint32_t q = 0; q < cnt; ++q) {
-        const uint64_t k = lists[b].keys[q];
-        if (key_p(k) < theta) break;
-        const uint32_t pos = atomicAdd(&scount, 1u);
-        if (pos < uint32_t(kSelCap)) buf[pos] = k;
+  const float theta = pg - pg * tau_band;
+  // blocks whose maximum reaches the band
+  for (int b0 = 0; b0 < nb; b0 += blockDim.x) {
+    const int b = b0 + tid;
+    const bool q = b < nb && lists[b].count > 0 && lists[b].pmax >= theta;
+    const uint64_t mask = __ballot(q);
+    if (mask) {
+      const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&sblocks, uint32_t(__popcll(mask)));
+      base = __shfl(base, leader);
+      if (q) {
+        const uint32_t pos = base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
+        if (pos < uint32_t(kSelCap)) cblk[pos] = uint32_t(b);
       }
-      if (attempt == 0 && cnt > 0 && lists[b].total > cnt && key_p(lists[b].keys[cnt - 1]) >= theta)
-        atomicOr(&sflags, uint32_t(kFlagListTruncated));
     }
-    __syncthreads();
-    n = scount;
-    if (attempt == 0) band = n;
-    if (n >= uint32_t(recheck_k) || n >= uint32_t(kSelCap) || tau >= tau_list) break;
-    tau = fminf(tau * 8.f, tau_list);
-    __syncthreads();
   }
+  __syncthreads();
+  const uint32_t ncb = sblocks < uint32_t(kSelCap) ? sblocks : uint32_t(kSelCap);
+  // one wave per candidate block: its band prefix, one coalesced load of 64 keys
+  for (uint32_t i = wave; i < ncb; i += nw) {
+    const BlockList32* L = lists + cblk[i];
+    const uint32_t cnt = L->count;
+    const uint64_t k = lane < int(cnt) ? L->keys[lane] : 0;
+    const bool q = lane < int(cnt) && key_p(k) >= theta;
+    wave_append(q, k, &scount, buf, uint32_t(kSelCap));
+    if (lane == 0 && cnt > 0 && L->total > cnt && key_p(L->keys[cnt - 1]) >= theta)
+      atomicOr(&sflags, uint32_t(kFlagListTruncated));
+  }
+  __syncthreads();
+  const uint32_t band = scount;
 
-  if (n <= uint32_t(kSelCap)) {
-    uint32_t p2 = 1;
-    while (p2 < n) p2 <<= 1;
-    for (uint32_t i = n + tid; i < p2; i += blockDim.x) buf[i] = 0;
-    __syncthreads();
-    // bitonic sort, descending
-    for (uint32_t k = 2; k <= p2; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = tid; i < p2; i += blockDim.x) {
-          const uint32_t ixj = i ^ j;
-          if (ixj > i) {
-            const uint64_t a = buf[i], c = buf[ixj];
-            const bool swap = (i & k) == 0 ? (a < c) : (a > c);
-            if (swap) {
-              buf[i] = c;
-              buf[ixj] = a;
+  if (band <= uint32_t(kSelCap) && sblocks <= uint32_t(kSelCap)) {
+    lds_sort_desc(buf, band);
+    uint32_t keff = band < uint32_t(kKMax) ? band : uint32_t(kKMax);
+    if (band > uint32_t(kKMax) && tid == 0) atomicOr(&sflags, uint32_t(kFlagBandTruncated));
+    for (uint32_t i = tid; i < keff; i += blockDim.x) cand->keys[i] = buf[i];
+    if (keff < uint32_t(recheck_k)) {
+      // top up with the best points of the next-best blocks (maxima below the band)
+      uint64_t tb = 0;
+      int tbb = -1;
+      for (int b = tid; b < nb; b += blockDim.x) {
+        heads[b] = 0;
+        if (lists[b].count > 0 && lists[b].pmax < theta && lists[b].keys[0] > tb) {
+          tb = lists[b].keys[0];
+          tbb = b;
+        }
+      }
+      while (keff < uint32_t(recheck_k)) {
+        const uint64_t g = block_max_u64(tb, wb);
+        if (g == 0) break;
+        if (tid == 0) cand->keys[keff] = g;
+        ++keff;
+        if (tbb >= 0 && tb == g) {
+          heads[tbb] = 1;
+          tb = 0;
+          tbb = -1;
+          for (int b = tid; b < nb; b += blockDim.x) {
+            if (heads[b] == 0 && lists[b].count > 0 && lists[b].pmax < theta && lists[b].keys[0] > tb) {
+              tb = lists[b].keys[0];
+              tbb = b;
             }
           }
         }
-        __syncthreads();
       }
     }
-    uint32_t keff = band > uint32_t(recheck_k) ? band : uint32_t(recheck_k);
-    keff = keff < n ? keff : n;
-    keff = keff < uint32_t(kKMax) ? keff : uint32_t(kKMax);
-    if (band > uint32_t(kKMax) && tid == 0) atomicOr(&sflags, uint32_t(kFlagBandTruncated));
-    for (uint32_t i = tid; i < keff; i += blockDim.x) cand->keys[i] = buf[i];
     __syncthreads();
     if (tid == 0) {
       cand->count = int32_t(keff);
@@ -430,7 +514,8 @@ __global__ __launch_bounds__(1024) void k_select32(const BlockList32* __restrict
     return;
   }
 
-  // Exact fallback: pop-merge of the sorted per-block lists.
+  // Exact fallback (a flat grid: more band points or band blocks than the
+  // gather holds): pop-merge of the sorted per-block lists.
   uint64_t tb = 0;
   int tbb = -1;
   for (int b = tid; b < nb; b += blockDim.x) {
@@ -462,7 +547,7 @@ __global__ __launch_bounds__(1024) void k_select32(const BlockList32* __restrict
   }
   __syncthreads();
   if (tid == 0) {
-    atomicOr(&sflags, uint32_t(kFlagFallback) | (band > uint32_t(kKMax) ? uint32_t(kFlagBandTruncated) : 0u));
+    atomicOr(&sflags, uint32_t(kFlagFallback) | uint32_t(kFlagBandTruncated));
     cand->count = r;
     cand->flags = int32_t(sflags);
     cand->pmax32 = pg;
@@ -816,12 +901,11 @@ hipError_t launch_merge64(const BlockBest64* blocks, int nblocks, int N, Winner*
   return hipGetLastError();
 }
 
-hipError_t launch_select32(const BlockList32* lists, int nblocks, int recheck_k, float tau_band, float tau_list,
-                           CandList* cand, hipStream_t s) {
+hipError_t launch_select32(const BlockList32* lists, int nblocks, int recheck_k, float tau_band, CandList* cand,
+                           hipStream_t s) {
   // the per-block heads live right after the candidate list record
   uint32_t* heads = reinterpret_cast<uint32_t*>(cand + 1);
-  hipLaunchKernelGGL(k_select32, dim3(1), dim3(1024), 0, s, lists, nblocks, recheck_k, tau_band, tau_list, heads,
-                     cand);
+  hipLaunchKernelGGL(k_select32, dim3(1), dim3(1024), 0, s, lists, nblocks, recheck_k, tau_band, heads, cand);
   return hipGetLastError();
 }
 

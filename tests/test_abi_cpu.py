@@ -52,7 +52,7 @@ def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=
     (dict(n=1000), 1), (dict(n=1), 1), (dict(n=0), 1), (dict(n=-4), 1),
     (dict(n=1 << 21), 5), (dict(radii=()), 1), (dict(radii=(0.2, 1.0)), 1), (dict(radii=(-0.1,)), 1),
     (dict(radii=(np.nan,)), 1), (dict(radii=(np.inf,)), 1), (dict(precision=7), 1),
-    (dict(recheck_k=-1), 1), (dict(recheck_k=257), 1), (dict(band=-1e-3), 1), (dict(band=0.5), 1),
+    (dict(recheck_k=-1), 1), (dict(recheck_k=65), 1), (dict(band=-1e-3), 1), (dict(band=0.5), 1),
     (dict(first_a_zero=1, radii=(0.1, 0.2)), 1), (dict(n=1 << 16, radii=np.zeros(1 << 15)), 1),
 ])
 def test_plan_create_rejects(kw, status):
