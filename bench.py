@@ -90,6 +90,9 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
                      "flop_per_launch": flop_launch, "grid": [blocks, threads, lds]},
         "index_last": [int(x) for x in res.index[-1].tolist()],
     }
+    if prec == "fp32":
+        out["fp32_error_max"] = float(res.fp32_error.max().item())
+        out["recheck_count_mean"] = float(res.recheck_count.double().mean().item())
     return out
 
 
@@ -161,6 +164,9 @@ def main():
         "p99_ms": prim["p99_ms"],
         "roofline": prim["roofline"],
     }
+    if "fp32_error_max" in prim:
+        line["fp32_error_max"] = prim["fp32_error_max"]
+        line["recheck_count_mean"] = prim["recheck_count_mean"]
     if "fp32" in res and "fp64" in res:
         line["fp64"] = {k: res["fp64"][k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
     if not args.no_cpu:

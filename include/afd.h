@@ -86,6 +86,9 @@ typedef struct {
                              re-checked; bit 1 = some radius held more band points than
                              its per-radius list; bit 2 = an exact fallback path of the
                              selection ran (flat or exactly tied values, e.g. r = 0) [nullable] */
+  double* fp32_error;     /* steps: FP32 mode, max |P32 - P64| / P64max over the re-checked
+                             points (P = |<G_k, e_a>~|^2; P64 by the double direct rule); the
+                             measured error of the FP32 bulk against double.  FP64: 0 [nullable] */
 } afd_result;
 
 /* Validate `desc`, copy the radii, build the per-radius double-precision

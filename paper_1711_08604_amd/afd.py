@@ -51,6 +51,7 @@ class ResultDesc(ctypes.Structure):
         ("remainder", ctypes.c_void_p),
         ("recheck_count", ctypes.c_void_p),
         ("flags", ctypes.c_void_p),
+        ("fp32_error", ctypes.c_void_p),
     ]
 
 
@@ -132,6 +133,7 @@ class Result:
     remainder: object  # (N,) complex128
     recheck_count: object
     flags: object
+    fp32_error: object  # (steps,) float64: FP32-vs-FP64 error of |.|^2 on the re-checked points
 
     @property
     def delta(self):
@@ -189,6 +191,7 @@ class Plan:
                 remainder=torch.empty((self.n,), dtype=torch.complex128, device=dev),
                 recheck_count=torch.empty((steps,), dtype=torch.int32, device=dev),
                 flags=torch.empty((steps,), dtype=torch.int32, device=dev),
+                fp32_error=torch.empty((steps,), dtype=torch.float64, device=dev),
             )
             ptr = lambda t: t.data_ptr()  # noqa: E731
         else:
@@ -201,10 +204,11 @@ class Plan:
                 remainder=np.empty(self.n, dtype=np.complex128),
                 recheck_count=np.empty(steps, dtype=np.int32),
                 flags=np.empty(steps, dtype=np.int32),
+                fp32_error=np.empty(steps, dtype=np.float64),
             )
             ptr = lambda a: a.ctypes.data  # noqa: E731
         rd = ResultDesc()
-        for name in ("index", "a", "coef", "energy", "margin", "remainder", "recheck_count", "flags"):
+        for name in ("index", "a", "coef", "energy", "margin", "remainder", "recheck_count", "flags", "fp32_error"):
             setattr(rd, name, ptr(getattr(out, name)))
         return out, rd
 

@@ -41,7 +41,8 @@ enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3 }
 
 // Device arena layout for one plan.
 struct Layout {
-  size_t radii, omega, tw, pw, pv, scale, g64, g32, c, blocks, cand, partials, winner, epart, nonfinite, forced0;
+  size_t radii, omega, tw, twf1, twf2, pw, pv, scale, g64, g32, c, xt, blocks, cand, partials, winner, epart,
+      nonfinite, forced0, counters;
   size_t total;
 };
 
@@ -51,11 +52,14 @@ struct Config {
   int M;
   bool fp64;
   FftGeom geom;
+  FwdPlan fwd;
   int rpb;
   int nblocks;
   int nch;
   int nparts;
 };
+
+constexpr int kNumCounters = 4;  // radius, recheck, update, prepare
 
 afd_status validate(const afd_plan_desc* d, Config* cfg) {
   if (!d) return fail(AFD_E_INVALID, "desc is NULL");
@@ -84,10 +88,11 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     cfg->M = d->m;
     cfg->fp64 = d->precision == AFD_FP64;
     cfg->geom = fft_geom(logn, cfg->fp64);
+    cfg->fwd = fwd_plan(logn, cfg->fp64);
     const int tpr = cfg->geom.tpr;
     cfg->rpb = tpr >= 64 ? 1 : 64 / tpr;
     cfg->nblocks = (d->m + cfg->rpb - 1) / cfg->rpb;
-    cfg->nch = int(d->n >= 2048 ? d->n / 2048 : 1);
+    cfg->nch = recheck_chunks(int(d->n));
     cfg->nparts = update_blocks(int(d->n));
   }
   return AFD_OK;
@@ -105,19 +110,23 @@ Layout layout_of(const Config& c) {
   L.radii = take(8 * size_t(c.M));
   L.omega = take(16 * size_t(c.N));
   L.tw = take(2 * real * size_t(c.geom.twsize + 1));
+  L.twf1 = take(2 * real * size_t(c.fwd.tw1_size + 1));
+  L.twf2 = take(2 * real * size_t(c.fwd.tw2_size + 1));
   L.pw = take(real * size_t(c.M) * c.geom.tpr);
   L.pv = take(real * size_t(c.M) * c.geom.E);
   L.scale = take(real * size_t(c.M));
   L.g64 = take(16 * size_t(c.N));
   L.g32 = take(c.fp64 ? 0 : 8 * size_t(c.N));
   L.c = take(2 * real * size_t(c.N));
+  L.xt = take(c.fwd.two_pass ? 2 * real * size_t(c.N) : 0);
   L.blocks = take((c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.nblocks));
-  L.cand = take(sizeof(CandList) + 4 * size_t(c.nblocks));
+  L.cand = take(sizeof(CandList));
   L.partials = take(16 * size_t(kKMax) * c.nch);
   L.winner = take(sizeof(Winner));
   L.epart = take(8 * size_t(c.nparts));
   L.nonfinite = take(4);
   L.forced0 = take(8);
+  L.counters = take(4 * kNumCounters);
   L.total = o;
   return L;
 }
@@ -176,6 +185,9 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   }
   std::vector<double> tw(2 * size_t(c.geom.twsize + 1), 0.0);
   fft_twiddles(c.logn, c.fp64, tw.data());
+  std::vector<double> twf1(2 * size_t(c.fwd.tw1_size + 1), 0.0), twf2(2 * size_t(c.fwd.tw2_size + 1), 0.0);
+  fft_twiddles(c.fwd.two_pass ? c.fwd.l1 : c.logn, c.fp64, twf1.data());
+  if (c.fwd.two_pass) fft_twiddles(c.fwd.l2, c.fp64, twf2.data());
   std::vector<double> pw(size_t(M) * tpr), pv(size_t(M) * E), sc(M);
   for (int m = 0; m < M; ++m) {
     const long double r = radii[m];
@@ -192,6 +204,8 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   if (e == hipSuccess) e = up(p->L.omega, omega.data(), omega.size() * 8);
   if (c.fp64) {
     if (e == hipSuccess) e = up(p->L.tw, tw.data(), tw.size() * 8);
+    if (e == hipSuccess) e = up(p->L.twf1, twf1.data(), twf1.size() * 8);
+    if (e == hipSuccess) e = up(p->L.twf2, twf2.data(), twf2.size() * 8);
     if (e == hipSuccess) e = up(p->L.pw, pw.data(), pw.size() * 8);
     if (e == hipSuccess) e = up(p->L.pv, pv.data(), pv.size() * 8);
     if (e == hipSuccess) e = up(p->L.scale, sc.data(), sc.size() * 8);
@@ -202,7 +216,10 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
       return o;
     };
     const std::vector<float> tw32 = f32(tw), pw32 = f32(pw), pv32 = f32(pv), sc32 = f32(sc);
+    const std::vector<float> twf1_32 = f32(twf1), twf2_32 = f32(twf2);
     if (e == hipSuccess) e = up(p->L.tw, tw32.data(), tw32.size() * 4);
+    if (e == hipSuccess) e = up(p->L.twf1, twf1_32.data(), twf1_32.size() * 4);
+    if (e == hipSuccess) e = up(p->L.twf2, twf2_32.data(), twf2_32.size() * 4);
     if (e == hipSuccess) e = up(p->L.pw, pw32.data(), pw32.size() * 4);
     if (e == hipSuccess) e = up(p->L.pv, pv32.data(), pv32.size() * 4);
     if (e == hipSuccess) e = up(p->L.scale, sc32.data(), sc32.size() * 4);
@@ -210,6 +227,7 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   const int32_t f0[2] = {p->zero_m < 0 ? 0 : p->zero_m, 0};
   if (e == hipSuccess) e = up(p->L.forced0, f0, sizeof(f0));
   if (e == hipSuccess) e = hipMemset(p->arena + p->L.nonfinite, 0, 4);
+  if (e == hipSuccess) e = hipMemset(p->arena + p->L.counters, 0, 4 * kNumCounters);
   if (e != hipSuccess) return hip_fail(e, "uploading plan tables");
   return AFD_OK;
 }
@@ -223,6 +241,7 @@ struct ResPtrs {
   double* margin;
   int32_t* kcount;
   int32_t* flags;
+  double* fp32err;
   size_t total;
 };
 
@@ -242,6 +261,7 @@ ResPtrs res_layout(unsigned char* base, int steps) {
   r.margin = reinterpret_cast<double*>(take(8 * s));
   r.kcount = reinterpret_cast<int32_t*>(take(4 * s));
   r.flags = reinterpret_cast<int32_t*>(take(4 * s));
+  r.fp32err = reinterpret_cast<double*>(take(8 * s));
   r.total = o;
   return r;
 }
@@ -280,7 +300,6 @@ afd_status ensure_forced(afd_plan_s* p, int steps) {
 struct Timer {
   afd_plan_s* p;
   int kind;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pairs;
   size_t next = 0;
   hipError_t begin(int k) {
     if (p->time_kind != k) return hipSuccess;
@@ -367,14 +386,29 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   double* epart = p->at<double>(p->L.epart);
   int* nonfinite = p->at<int>(p->L.nonfinite);
   const int32_t* forced0 = p->at<int32_t>(p->L.forced0);
+  unsigned int* counters = p->at<unsigned int>(p->L.counters);
 
+  RecordArgs rec{};
+  rec.w = win;
+  rec.radii = radii;
+  rec.omega = omega;
+  rec.N = N;
+  rec.M = c.M;
+  rec.idx = R.idx;
+  rec.a = R.a;
+  rec.coef = R.coef;
+  rec.energy = R.energy;
+  rec.margin = R.margin;
+  rec.kcount = R.kcount;
+  rec.flags = R.flags;
+  rec.fp32err = R.fp32err;
+
+  // flags and last-workgroup counters start at zero (also after an aborted call)
   HIPCHK(hipMemsetAsync(nonfinite, 0, 4, s), "clearing flag");
+  HIPCHK(hipMemsetAsync(counters, 0, 4 * kNumCounters, s), "clearing counters");
   HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N), sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
          "copying signal");
-  HIPCHK(launch_prepare(nullptr, g64, g32, N, epart, nonfinite, s), "k_prepare");
-  HIPCHK(launch_record(win, radii, omega, epart, c.nparts, N, c.M, -1, R.idx, R.a, R.coef, R.energy, R.margin, R.kcount,
-                       R.flags, s),
-         "k_record");
+  HIPCHK(launch_prepare(g64, g32, N, epart, nonfinite, counters + 3, rec, s), "k_prepare");
 
   RadiusParams rp{};
   rp.c = cspec;
@@ -385,7 +419,11 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.M = c.M;
   rp.rpb = c.rpb;
   rp.tau_band = p->tau_band;
+  rp.recheck_k = p->recheck_k;
   rp.out = p->at<void>(p->L.blocks);
+  rp.counter = counters + 0;
+  rp.cand = cand;
+  rp.winner = win;
 
   Timer tm{p, p->time_kind};
   for (int k = 0; k < steps; ++k) {
@@ -399,32 +437,22 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     }
     if (fsrc) {
       HIPCHK(launch_force(fsrc, fstep, N, cand, s), "k_force");
-      HIPCHK(launch_recheck(cand, g64, omega, radii, N, c.nch, partials, s), "k_recheck");
-      HIPCHK(launch_finalize(cand, partials, radii, omega, N, c.nch, win, s), "k_finalize");
+      HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1, win, s), "k_recheck");
     } else {
       HIPCHK(tm.begin(kTimeFft), "event");
-      HIPCHK(launch_fft_fwd(c.logn, c.fp64, c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32),
-                            rp.tw, cspec, s),
-             "k_fft_fwd");
+      HIPCHK(launch_fwd(c.logn, c.fp64, c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32),
+                        p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega, p->at<void>(p->L.xt), cspec, s),
+             "forward DFT");
       HIPCHK(tm.end(kTimeFft), "event");
       HIPCHK(tm.begin(kTimeRadius), "event");
       HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, s), "k_radius");
       HIPCHK(tm.end(kTimeRadius), "event");
-      if (c.fp64) {
-        HIPCHK(launch_merge64(p->at<BlockBest64>(p->L.blocks), c.nblocks, N, win, s), "k_merge64");
-      } else {
-        HIPCHK(launch_select32(p->at<BlockList32>(p->L.blocks), c.nblocks, p->recheck_k, p->tau_band, cand, s),
-               "k_select32");
-        HIPCHK(launch_recheck(cand, g64, omega, radii, N, c.nch, partials, s), "k_recheck");
-        HIPCHK(launch_finalize(cand, partials, radii, omega, N, c.nch, win, s), "k_finalize");
-      }
+      if (!c.fp64)
+        HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1, win, s), "k_recheck");
     }
     HIPCHK(tm.begin(kTimeUpdate), "event");
-    HIPCHK(launch_update(win, radii, omega, g64, g32, N, c.M, epart, s), "k_update");
+    HIPCHK(launch_update(radii, omega, g64, g32, N, c.M, epart, counters + 2, rec, k, s), "k_update");
     HIPCHK(tm.end(kTimeUpdate), "event");
-    HIPCHK(launch_record(win, radii, omega, epart, c.nparts, N, c.M, k, R.idx, R.a, R.coef, R.energy, R.margin, R.kcount,
-                         R.flags, s),
-           "k_record");
   }
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, nonfinite, 4, hipMemcpyDeviceToHost, s), "reading flag");
@@ -443,6 +471,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   if (out->margin) HIPCHK(cp(out->margin, R.margin, 8 * S), "copy margin");
   if (out->recheck_count) HIPCHK(cp(out->recheck_count, R.kcount, 4 * S), "copy recheck_count");
   if (out->flags) HIPCHK(cp(out->flags, R.flags, 4 * S), "copy flags");
+  if (out->fp32_error) HIPCHK(cp(out->fp32_error, R.fp32err, 8 * S), "copy fp32_error");
   if (out->remainder) HIPCHK(cp(out->remainder, g64, 16 * size_t(N)), "copy remainder");
   HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
   g_last_error.clear();
@@ -476,7 +505,8 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
   if (e == hipSuccess) {
     static bool attrs_done = false;
     if (!attrs_done) {
-      e = setup_kernel_attributes();
+      e = setup_radius_attributes();
+      if (e == hipSuccess) e = setup_fwd_attributes();
       if (e == hipSuccess) attrs_done = true;
     }
   }
@@ -563,8 +593,8 @@ afd_status afd_plan_kernel_time(afd_plan plan, double* ms, int64_t* launches) {
 afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threads, int32_t* lds_bytes) {
   if (!plan || !blocks || !threads || !lds_bytes) return fail(AFD_E_INVALID, "NULL argument");
   *blocks = plan->cfg.nblocks;
-  *threads = plan->cfg.geom.tpr * plan->cfg.rpb;
-  *lds_bytes = radius_lds_bytes(plan->cfg.logn, plan->cfg.fp64, plan->cfg.rpb, !plan->cfg.fp64);
+  *threads = radius_threads_of(plan->cfg.logn, plan->cfg.fp64);
+  *lds_bytes = radius_lds_bytes(plan->cfg.logn, plan->cfg.fp64, plan->cfg.rpb);
   return AFD_OK;
 }
 

@@ -155,28 +155,31 @@ struct Dif {
   }
 };
 
-// a[OFF + r*STR] *= w^r for r = 1..R-1.  Powers come from w, w^2, w^3 and
-// steps of w^4, so no power is more than about six rounded products deep and
-// only five complex values stay live.
+// a[OFF + r*STR] *= w^r for r = 1..R-1.  Powers come from w^0..w^(G-1)
+// (squarings and one product per odd power) and steps of w^G, G = 4 for
+// R <= 16 and 8 for R = 32, so no power is more than about six rounded
+// products deep while few complex values stay live.
 template <int R, int OFF, int STR, typename T>
 __device__ __forceinline__ void apply_twiddles(Cx<T>* a, Cx<T> w) {
   if constexpr (R == 2) {
     a[OFF + STR] = cmul(a[OFF + STR], w);
   } else {
-    const Cx<T> w2 = csqr(w);
-    const Cx<T> w3 = cmul(w2, w);
-    const Cx<T> w4 = csqr(w2);
-    a[OFF + STR] = cmul(a[OFF + STR], w);
-    a[OFF + 2 * STR] = cmul(a[OFF + 2 * STR], w2);
-    a[OFF + 3 * STR] = cmul(a[OFF + 3 * STR], w3);
-    Cx<T> base = w4;
+    constexpr int G = R >= 32 ? 8 : 4;
+    Cx<T> p[G];
+    p[0] = {T(1), T(0)};
+    p[1] = w;
 #pragma unroll
-    for (int q = 1; q < R / 4; ++q) {
-      a[OFF + 4 * q * STR] = cmul(a[OFF + 4 * q * STR], base);
-      a[OFF + (4 * q + 1) * STR] = cmul(a[OFF + (4 * q + 1) * STR], cmul(base, w));
-      a[OFF + (4 * q + 2) * STR] = cmul(a[OFF + (4 * q + 2) * STR], cmul(base, w2));
-      a[OFF + (4 * q + 3) * STR] = cmul(a[OFF + (4 * q + 3) * STR], cmul(base, w3));
-      if (q + 1 < R / 4) base = cmul(base, w4);
+    for (int k = 2; k < G; ++k) p[k] = (k & 1) ? cmul(p[k - 1], w) : csqr(p[k / 2]);
+    const Cx<T> wg = csqr(p[G / 2]);
+#pragma unroll
+    for (int k = 1; k < G; ++k) a[OFF + k * STR] = cmul(a[OFF + k * STR], p[k]);
+    Cx<T> base = wg;
+#pragma unroll
+    for (int q = 1; q < R / G; ++q) {
+      a[OFF + q * G * STR] = cmul(a[OFF + q * G * STR], base);
+#pragma unroll
+      for (int k = 1; k < G; ++k) a[OFF + (q * G + k) * STR] = cmul(a[OFF + (q * G + k) * STR], cmul(base, p[k]));
+      if (q + 1 < R / G) base = cmul(base, wg);
     }
   }
 }
@@ -304,6 +307,29 @@ __device__ __forceinline__ void fft_regs(Cx<T> (&v)[E], int t, void* lds, const 
 template <int LOGN, int E>
 __device__ __forceinline__ int out_bin(int t, int p) {
   return t + Shape<LOGN, E>::TPR * bitrev(p, ilog2c(E));
+}
+
+// ---------------------------------------------------------------- geometry choices
+// Values per thread: 32 for single precision from 2^12 points (fewer LDS
+// exchanges, two workgroups per CU at 2^14), 16 otherwise; the exchange runs
+// real and imaginary parts through half the LDS from 2^14 points so that a
+// single-precision workgroup leaves room for a second one and a
+// double-precision one fits at all.
+template <typename T, int LOGN>
+__host__ __device__ constexpr int pickE() {
+  return (1 << LOGN) < 16 ? (1 << LOGN) : (sizeof(T) == 4 && LOGN >= 12) ? 32 : 16;
+}
+template <typename T, int LOGN>
+__host__ __device__ constexpr bool pickSplit() {
+  return LOGN >= 14;
+}
+__host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+
+// LDS bytes of one transform's exchange region
+template <typename T, int LOGN, bool SPLIT>
+__host__ __device__ constexpr size_t fft_region_bytes() {
+  using S = Shape<LOGN, pickE<T, LOGN>()>;
+  return align16(size_t(S::LDS_ELEMS) * (SPLIT ? sizeof(T) : sizeof(Cx<T>)));
 }
 
 // ---------------------------------------------------------------- selection keys

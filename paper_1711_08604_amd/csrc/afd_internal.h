@@ -1,5 +1,6 @@
 // Internal interface between the host plan (afd_api.hip) and the kernels
-// (afd_kernels.hip): device record layouts and launchers.
+// (afd_fwd.hip, afd_radius.hip, afd_step.hip): device record layouts and
+// launchers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,26 +12,27 @@ namespace afd {
 
 constexpr int kMaxLogN = 20;       // N <= 2^20
 constexpr int kMaxLdsLogN = 14;    // single-workgroup (LDS-resident) transforms up to 2^14
-constexpr int kListC = 64;         // per-block candidate list length (FP32 mode)
-constexpr int kListCap = 1024;     // per-block LDS gather capacity before the exact fallback
+constexpr int kListC = 64;         // per-workgroup candidate list length (FP32 mode)
+constexpr int kListCap = 1024;     // per-workgroup LDS gather capacity before the exact fallback
 constexpr int kKMax = 256;         // longest short-list re-checked in double
 constexpr int kSelCap = 1024;      // global gather capacity of the short-list selection
 constexpr float kTauBandDefault = 4e-6f;  // default re-check band (relative to the FP32 maximum)
 
-// flags (per step)
+// flags (per step; bits 0-2 are reported)
 constexpr int kFlagBandTruncated = 1;
 constexpr int kFlagListTruncated = 2;
 constexpr int kFlagFallback = 4;
+constexpr int kFlagForced = 8;
 
-// FP64 mode: best and runner-up of one radius block
+// FP64 mode: best and runner-up of one radius workgroup
 struct BlockBest64 {
   double p1, p2, vx, vy;
   uint32_t f;
   uint32_t pad;
 };
 
-// FP32 mode: exact top entries (key order) among the block's points within
-// the list band of the block maximum
+// FP32 mode: exact top entries (key order) among the workgroup's points within
+// the re-check band of the workgroup maximum
 struct BlockList32 {
   float pmax;
   uint32_t count;   // entries written (<= kListC)
@@ -53,7 +55,7 @@ struct Winner {
   double ax, ay;
   double cx, cy;
   double margin;
-  double pad;
+  double fp32err;  // FP32 mode: max |P32 - P64| / P64max over the re-checked points
 };
 
 struct RadiusParams {
@@ -63,9 +65,29 @@ struct RadiusParams {
   const void* scale;  // [M]       sqrt(1-r^2) / (N (1 - r^N))
   const void* tw;     // Stockham twiddles of the inverse transform
   int M;
-  int rpb;            // radii per block
-  float tau_band;     // FP32 lists: relative band below the block maximum
+  int rpb;            // radii per workgroup
+  float tau_band;     // FP32 lists: relative band below the workgroup maximum
+  int recheck_k;      // FP32: minimum short-list length
   void* out;          // BlockBest64[blocks] or BlockList32[blocks]
+  unsigned int* counter;  // last-workgroup counter (zero between launches)
+  CandList* cand;     // FP32 short-list (written by the last workgroup)
+  Winner* winner;     // FP64 winner (written by the last workgroup)
+};
+
+// Step outputs written by the last workgroup of k_update / k_prepare.
+struct RecordArgs {
+  const Winner* w;
+  const double* radii;
+  const double* omega;
+  int N, M;
+  int32_t* idx;
+  double* a;
+  double* coef;
+  double* energy;
+  double* margin;
+  int32_t* kcount;
+  int32_t* flags;
+  double* fp32err;
 };
 
 // Geometry of the LDS-resident transform for 2^logn points.
@@ -80,27 +102,40 @@ FftGeom fft_geom(int logn, bool fp64);
 // Fill the Stockham twiddle table (e^{+2 pi i k/(Ns R)} per pass) in double.
 void fft_twiddles(int logn, bool fp64, double* out_interleaved);
 
-int radius_lds_bytes(int logn, bool fp64, int rpb, bool list);
+// Forward DFT: one workgroup below 2^12 points (table tw1 of size 2^logn),
+// else two passes of sizes 2^l2 (columns, table tw2) and 2^l1 (rows, tw1).
+struct FwdPlan {
+  bool two_pass;
+  int l1, l2;
+  int tw1_size, tw2_size;
+};
+FwdPlan fwd_plan(int logn, bool fp64);
 
-hipError_t setup_kernel_attributes();
-
-hipError_t launch_fft_fwd(int logn, bool fp64, const void* g, const void* tw, void* c, hipStream_t s);
-hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, hipStream_t s);
-hipError_t launch_merge64(const BlockBest64* blocks, int nblocks, int N, Winner* w, hipStream_t s);
-hipError_t launch_select32(const BlockList32* lists, int nblocks, int recheck_k, float tau_band, CandList* cand,
-                           hipStream_t s);
-hipError_t launch_force(const int32_t* forced, int step, int N, CandList* cand, hipStream_t s);
-hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii,
-                          int N, int nch, double* partials, hipStream_t s);
-hipError_t launch_finalize(const CandList* cand, const double* partials, const double* radii,
-                           const double* omega, int N, int nch, Winner* w, hipStream_t s);
-hipError_t launch_prepare(const double* g, double* g64, float* g32, int N, double* epart, int* nonfinite,
-                          hipStream_t s);
-hipError_t launch_update(const Winner* w, const double* radii, const double* omega, double* g64, float* g32,
-                         int N, int M, double* epart, hipStream_t s);
-hipError_t launch_record(const Winner* w, const double* radii, const double* omega, const double* epart, int nparts,
-                         int N, int M, int step, int32_t* idx, double* a, double* coef, double* energy,
-                         double* margin, int32_t* kcount, int32_t* flags, hipStream_t s);
+int radius_lds_bytes(int logn, bool fp64, int rpb);
+int radius_threads_of(int logn, bool fp64);
 int update_blocks(int N);
+int recheck_chunks(int N);
+
+// Allow a kernel the whole 160 KB of LDS less its static LDS.
+inline hipError_t set_max_dynamic_lds(const void* fn) {
+  hipFuncAttributes a;
+  hipError_t e = hipFuncGetAttributes(&a, fn);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(160 * 1024 - a.sharedSizeBytes));
+}
+
+hipError_t setup_radius_attributes();
+hipError_t setup_fwd_attributes();
+
+hipError_t launch_fwd(int logn, bool fp64, const void* g, const void* tw1, const void* tw2, const double* omega,
+                      void* xt, void* c, hipStream_t s);
+hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, hipStream_t s);
+hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* nonfinite, unsigned int* counter,
+                          const RecordArgs& R, hipStream_t s);
+hipError_t launch_force(const int32_t* forced, int step, int N, CandList* cand, hipStream_t s);
+hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
+                          double* partials, unsigned int* counter, Winner* w, hipStream_t s);
+hipError_t launch_update(const double* radii, const double* omega, double* g64, float* g32, int N, int M,
+                         double* epart, unsigned int* counter, const RecordArgs& R, int step, hipStream_t s);
 
 }  // namespace afd

@@ -1,0 +1,253 @@
+// Per-step kernels around the radius kernel:
+//   k_prepare   copy-in checks, complex64 copy of the samples, E_0
+//   k_force     forced grid point (first_a_zero, replay) as a one-entry short-list
+//   k_recheck   the direct rule of Sec. 3.1, eq. term81, in double for each
+//               short-listed point, in partial sums over chunks of samples; the
+//               last workgroup picks the winner (largest |.|^2, lowest flat
+//               index) and its coefficient c_k = <G_k, e_{a_k}>~ (eq. (3))
+//   k_update    G_{k+1} = (G_k - c_k e_{a_k}) (1 - conj(a_k) z)/(z - a_k) (eq. (7))
+//               in double; the last workgroup sums E_k = (1/N) sum |G_{k+1}|^2
+//               and records the step's outputs
+#include "afd_select.h"
+
+namespace afd {
+
+constexpr int kUpdThreads = 256;
+constexpr int kUpdPerThread = 4;
+constexpr int kRecheckBlocksX = 16;
+
+int update_blocks(int N) { return (N + kUpdThreads * kUpdPerThread - 1) / (kUpdThreads * kUpdPerThread); }
+int recheck_chunks(int N) { return N >= 2048 ? N / 2048 : 1; }
+
+__device__ __forceinline__ void write_record(const RecordArgs& R, int step, double E) {
+  if (step < 0) {
+    R.energy[0] = E;
+    return;
+  }
+  Winner W = *R.w;
+  W.m = min(max(W.m, 0), R.M - 1);
+  W.j = W.j & (R.N - 1);
+  const double r = R.radii[W.m];
+  R.idx[2 * step] = W.m;
+  R.idx[2 * step + 1] = W.j;
+  R.a[2 * step] = r * R.omega[2 * W.j];
+  R.a[2 * step + 1] = r * R.omega[2 * W.j + 1];
+  R.coef[2 * step] = W.cx;
+  R.coef[2 * step + 1] = W.cy;
+  R.energy[step + 1] = E;
+  R.margin[step] = W.margin;
+  R.kcount[step] = W.kcount;
+  R.flags[step] = W.flags;
+  R.fp32err[step] = W.fp32err;
+}
+
+// energy of the samples from the per-workgroup partial sums, in index order
+__device__ __forceinline__ double energy_from_parts(const double* __restrict__ epart, int nparts, int N,
+                                                    double* wd) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += ld_agent(epart + i);
+  return block_sum_f64(acc, wd) / double(N);
+}
+
+__global__ __launch_bounds__(256) void k_prepare(double* __restrict__ g64, float* __restrict__ g32, int N,
+                                                 double* __restrict__ epart, int* __restrict__ nonfinite,
+                                                 unsigned int* __restrict__ counter, RecordArgs R) {
+  __shared__ double wd[16];
+  __shared__ int s_last;
+  double acc = 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int s = 0; s < kUpdPerThread; ++s) {
+    const int n = blockIdx.x * (kUpdThreads * kUpdPerThread) + s * kUpdThreads + threadIdx.x;
+    if (n < N) {
+      const double x = g64[2 * n], y = g64[2 * n + 1];
+      if (!isfinite(x) || !isfinite(y)) bad = 1;
+      if (g32) {
+        g32[2 * n] = float(x);
+        g32[2 * n + 1] = float(y);
+      }
+      acc += fma(x, x, y * y);
+    }
+  }
+  if (bad) atomicOr(nonfinite, 1);
+  const double tot = block_sum_f64(acc, wd);
+  if (threadIdx.x == 0) st_agent(epart + blockIdx.x, tot);
+  if (!last_workgroup(counter, &s_last)) return;
+  const double E = energy_from_parts(epart, int(gridDim.x), N, wd);
+  if (threadIdx.x == 0) write_record(R, -1, E);
+}
+
+__global__ void k_force(const int32_t* __restrict__ forced, int step, int N, CandList* __restrict__ cand) {
+  if (threadIdx.x == 0) {
+    const uint32_t m = uint32_t(forced[2 * step]), j = uint32_t(forced[2 * step + 1]);
+    cand->count = 1;
+    cand->flags = kFlagForced;
+    cand->pmax32 = 0.f;
+    cand->keys[0] = uint64_t(~(m * uint32_t(N) + j));  // P = 0: the re-check supplies the value
+  }
+}
+
+// Winner among the short-list from the chunk partial sums (last workgroup).
+__device__ __forceinline__ void finalize_tail(const CandList* __restrict__ cand, const double* __restrict__ partials,
+                                              const double* __restrict__ radii, int N, int logn, int nch,
+                                              Winner* __restrict__ w, Best* bb, double* wd) {
+  const int count = cand->count;
+  const bool forced = (cand->flags & kFlagForced) != 0;
+  Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
+  double err = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    const uint32_t f = key_f(cand->keys[i]);
+    const double r = radii[f >> logn];
+    double ax = 0.0, ay = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      ax += ld_agent(partials + 2 * (size_t(i) * nch + ch));
+      ay += ld_agent(partials + 2 * (size_t(i) * nch + ch) + 1);
+    }
+    const double s = sqrt((1.0 - r) * (1.0 + r)) / double(N);
+    const Best x{(ax * s) * (ax * s) + (ay * s) * (ay * s), -1.0, ax * s, ay * s, f};
+    err = fmax(err, fabs(double(key_p(cand->keys[i])) - x.p1));
+    best_merge(b, x);
+  }
+  const Best r = block_best(b, bb);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) err = fmax(err, __shfl_xor(err, m));
+  if ((threadIdx.x & 63) == 0) wd[threadIdx.x >> 6] = err;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = wd[0];
+    for (int i = 1; i < nwaves(); ++i) e = fmax(e, wd[i]);
+    Winner o;
+    const bool valid = count > 0 && r.f != 0xffffffffu;
+    o.m = valid ? int32_t(r.f >> logn) : 0;
+    o.j = valid ? int32_t(r.f & uint32_t(N - 1)) : 0;
+    o.cx = valid ? r.vx : 0.0;
+    o.cy = valid ? r.vy : 0.0;
+    if (forced || count < 2 || !valid) o.margin = __builtin_nan("");
+    else o.margin = r.p1 > 0.0 ? (r.p1 - r.p2) / r.p1 : 0.0;
+    o.kcount = forced ? 1 : count;
+    o.flags = cand->flags & 7;
+    o.ax = o.ay = 0.0;
+    o.fp32err = (forced || !valid || !(r.p1 > 0.0)) ? 0.0 : e / r.p1;
+    *w = o;
+  }
+}
+
+// partial sums over a chunk of samples of G[n] / (1 - r_m e^{2 pi i (j - n)/N})
+__global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ cand, const double* __restrict__ g,
+                                                 const double* __restrict__ omega, const double* __restrict__ radii,
+                                                 int N, int logn, int nch, double* __restrict__ partials,
+                                                 unsigned int* __restrict__ counter, Winner* __restrict__ w) {
+  __shared__ double wd[16];
+  __shared__ Best bb[16];
+  __shared__ int s_last;
+  const int chunk = blockIdx.y;
+  const int cl = N / nch;
+  const int count = cand->count;
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
+    const uint32_t f = key_f(cand->keys[i]);
+    const int m = int(f >> logn), j = int(f & uint32_t(N - 1));
+    const double r = radii[m];
+    double ax = 0.0, ay = 0.0;
+    for (int n = chunk * cl + threadIdx.x; n < (chunk + 1) * cl; n += blockDim.x) {
+      const int d = (j - n) & (N - 1);
+      const double ox = omega[2 * d], oy = omega[2 * d + 1];
+      const double dx = fma(-r, ox, 1.0), dy = -r * oy;
+      const double inv = 1.0 / fma(dx, dx, dy * dy);
+      const double gx = g[2 * n], gy = g[2 * n + 1];
+      ax += fma(gx, dx, gy * dy) * inv;
+      ay += fma(gy, dx, -gx * dy) * inv;
+    }
+    const double sx = block_sum_f64(ax, wd);
+    const double sy = block_sum_f64(ay, wd);
+    if (threadIdx.x == 0) {
+      st_agent(partials + 2 * (size_t(i) * nch + chunk), sx);
+      st_agent(partials + 2 * (size_t(i) * nch + chunk) + 1, sy);
+    }
+  }
+  if (!last_workgroup(counter, &s_last)) return;
+  finalize_tail(cand, partials, radii, N, logn, nch, w, bb, wd);
+}
+
+__global__ __launch_bounds__(256) void k_update(const double* __restrict__ radii, const double* __restrict__ omega,
+                                                double* __restrict__ g64, float* __restrict__ g32, int N, int M,
+                                                double* __restrict__ epart, unsigned int* __restrict__ counter,
+                                                RecordArgs R, int step) {
+  __shared__ double wd[16];
+  __shared__ int s_last;
+  Winner W = *R.w;
+  W.m = min(max(W.m, 0), M - 1);
+  W.j = W.j & (N - 1);
+  const double r = radii[W.m];
+  const double s = sqrt((1.0 - r) * (1.0 + r));
+  const double wjx = omega[2 * W.j], wjy = -omega[2 * W.j + 1];  // e^{-2 pi i j/N}
+  const double csx = W.cx * s, csy = W.cy * s;
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < kUpdPerThread; ++q) {
+    const int n = blockIdx.x * (kUpdThreads * kUpdPerThread) + q * kUpdThreads + threadIdx.x;
+    if (n < N) {
+      // with a = r e^{2 pi i j/N}, z_n = e^{2 pi i n/N}, d = n - j:
+      // G' = (G (1 - r w^d) - c s) e^{-2 pi i j/N} / (w^d - r)
+      const int d = (n - W.j) & (N - 1);
+      const double ox = omega[2 * d], oy = omega[2 * d + 1];
+      const double gx = g64[2 * n], gy = g64[2 * n + 1];
+      const double ux = fma(-r, ox, 1.0), uy = -r * oy;
+      const double nx = fma(gx, ux, -gy * uy) - csx;
+      const double ny = fma(gx, uy, gy * ux) - csy;
+      const double dx = ox - r, dy = oy;
+      const double inv = 1.0 / fma(dx, dx, dy * dy);
+      const double qx = fma(nx, dx, ny * dy) * inv;
+      const double qy = fma(ny, dx, -nx * dy) * inv;
+      const double hx = fma(qx, wjx, -qy * wjy);
+      const double hy = fma(qx, wjy, qy * wjx);
+      g64[2 * n] = hx;
+      g64[2 * n + 1] = hy;
+      if (g32) {
+        g32[2 * n] = float(hx);
+        g32[2 * n + 1] = float(hy);
+      }
+      acc += fma(hx, hx, hy * hy);
+    }
+  }
+  const double tot = block_sum_f64(acc, wd);
+  if (threadIdx.x == 0) st_agent(epart + blockIdx.x, tot);
+  if (!last_workgroup(counter, &s_last)) return;
+  const double E = energy_from_parts(epart, int(gridDim.x), N, wd);
+  if (threadIdx.x == 0) write_record(R, step, E);
+}
+
+// ---------------------------------------------------------------- launchers
+static int ilog2i(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* nonfinite, unsigned int* counter,
+                          const RecordArgs& R, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare, dim3(update_blocks(N)), dim3(kUpdThreads), 0, s, g64, g32, N, epart, nonfinite,
+                     counter, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_force(const int32_t* forced, int step, int N, CandList* cand, hipStream_t s) {
+  hipLaunchKernelGGL(k_force, dim3(1), dim3(64), 0, s, forced, step, N, cand);
+  return hipGetLastError();
+}
+
+hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
+                          double* partials, unsigned int* counter, Winner* w, hipStream_t s) {
+  const int nch = recheck_chunks(N);
+  hipLaunchKernelGGL(k_recheck, dim3(kRecheckBlocksX, nch), dim3(256), 0, s, cand, g, omega, radii, N, ilog2i(N),
+                     nch, partials, counter, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const double* radii, const double* omega, double* g64, float* g32, int N, int M,
+                         double* epart, unsigned int* counter, const RecordArgs& R, int step, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(update_blocks(N)), dim3(kUpdThreads), 0, s, radii, omega, g64, g32, N, M,
+                     epart, counter, R, step);
+  return hipGetLastError();
+}
+
+}  // namespace afd

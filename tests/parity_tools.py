@@ -24,7 +24,7 @@ MARGIN_MIN = 1e-6
 
 def to_numpy(res):
     out = {}
-    for name in ("index", "a", "coef", "energy", "margin", "remainder", "recheck_count", "flags"):
+    for name in ("index", "a", "coef", "energy", "margin", "remainder", "recheck_count", "flags", "fp32_error"):
         v = getattr(res, name)
         if hasattr(v, "detach"):
             v = v.detach().cpu().numpy()

@@ -87,7 +87,7 @@ def test_workspace_bytes_scales():
     b2 = lib.afd_workspace_bytes(ctypes.byref(d2))
     assert 0 < b1 < b2
     # tables dominate: 16 B per sample of omega + the per-radius power tables
-    assert b2 >= 16 * 16384 + 4 * 1000 * (1024 + 16)
+    assert b2 >= 16 * 16384 + 4 * 1000 * (512 + 32)
 
 
 def test_status_strings():

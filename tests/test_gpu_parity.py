@@ -107,6 +107,9 @@ def test_config2_full_size(prec):
         if prec == "fp32":
             assert np.all((r["flags"] & 3) == 0), r["flags"]
             assert np.all(r["recheck_count"] >= 8)
+            # the re-check band (4e-6 by default) must cover twice the measured FP32 error
+            print("max FP32 error of |.|^2:", float(np.max(r["fp32_error"])), flush=True)
+            assert np.max(r["fp32_error"]) * 2 < 4e-6
 
 
 def test_paper_case1_first_a_zero():
