@@ -118,6 +118,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=5, help="AFD steps of the oracle sample")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a known-size kernel for "
+                         "scaling HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -135,6 +138,14 @@ def main():
     log(f"bench: N={n} M={m} afd_steps={afd_steps} solves={args.steps} warmup={args.warmup}")
     sig = torch.from_numpy(g).to("cuda:0")
     torch.cuda.synchronize()
+    if args.copy_calibration_mib:
+        n_el = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration {args.copy_calibration_mib} MiB read + {args.copy_calibration_mib} MiB written")
+        del src, dst
     res = {}
     for prec in ("fp32", "fp64"):
         if args.only and prec != args.only:

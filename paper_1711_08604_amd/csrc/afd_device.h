@@ -65,10 +65,11 @@ struct Shape {
     for (int i = 0; i < p; ++i) s *= radix(i);
     return s;
   }
-  // twiddle table: pass p >= 1 owns ns(p) entries e^{+2 pi i k/(ns(p) radix(p))}
+  // twiddle table: pass p >= 1 owns (radix(p) - 1) * ns(p) entries, entry
+  // (r - 1) * ns(p) + k = e^{+2 pi i k r/(ns(p) radix(p))}, r = 1..radix-1
   __host__ __device__ static constexpr int twoff(int p) {
     int o = 0;
-    for (int i = 1; i < p; ++i) o += ns(i);
+    for (int i = 1; i < p; ++i) o += (radix(i) - 1) * ns(i);
     return o;
   }
   __host__ __device__ static constexpr int twsize() { return twoff(NP); }
@@ -155,36 +156,68 @@ struct Dif {
   }
 };
 
-// a[OFF + r*STR] *= w^r for r = 1..R-1.  Powers come from w^0..w^(G-1)
-// (squarings and one product per odd power) and steps of w^G, G = 4 for
-// R <= 16 and 8 for R = 32, so no power is more than about six rounded
-// products deep while few complex values stay live.
-template <int R, int OFF, int STR, typename T>
-__device__ __forceinline__ void apply_twiddles(Cx<T>* a, Cx<T> w) {
-  if constexpr (R == 2) {
-    a[OFF + STR] = cmul(a[OFF + STR], w);
+// Radix-2 decimation-in-time butterfly on (e, o) with the compile-time twiddle
+// W = e^{SIGN 2 pi i Q/R}: e <- e + W o, o <- e - W o, the second formed as
+// 2e - (e + W o) so that a general twiddle costs six FMA-class operations.
+template <int R, int Q, int SIGN, typename T>
+__device__ __forceinline__ void dit_bfly(Cx<T>& e, Cx<T>& o) {
+  constexpr int q = ((Q % R) + R) % R;
+  if constexpr (q == 0) {
+    const Cx<T> x = cadd(e, o), y = csub(e, o);
+    e = x;
+    o = y;
+  } else if constexpr (4 * q == R) {
+    // W o = SIGN i o
+    const Cx<T> t{T(-SIGN) * o.y, T(SIGN) * o.x};
+    const Cx<T> x = cadd(e, t), y = csub(e, t);
+    e = x;
+    o = y;
+  } else if constexpr (8 * q == R || 8 * q == 3 * R) {
+    // W = (cs + SIGN i)/sqrt2 with cs = +1 (q = R/8) or -1 (q = 3R/8)
+    constexpr T h = T(0.7071067811865476);
+    constexpr T cs = (8 * q == R) ? T(1) : T(-1);
+    const T ur = fma(cs, o.x, -T(SIGN) * o.y);  // Re(sqrt2 W o)
+    const T ui = fma(cs, o.y, T(SIGN) * o.x);   // Im(sqrt2 W o)
+    const Cx<T> x{fma(h, ur, e.x), fma(h, ui, e.y)};
+    o = {fma(T(2), e.x, -x.x), fma(T(2), e.y, -x.y)};
+    e = x;
   } else {
-    constexpr int G = R >= 32 ? 8 : 4;
-    Cx<T> p[G];
-    p[0] = {T(1), T(0)};
-    p[1] = w;
-#pragma unroll
-    for (int k = 2; k < G; ++k) p[k] = (k & 1) ? cmul(p[k - 1], w) : csqr(p[k / 2]);
-    const Cx<T> wg = csqr(p[G / 2]);
-#pragma unroll
-    for (int k = 1; k < G; ++k) a[OFF + k * STR] = cmul(a[OFF + k * STR], p[k]);
-    Cx<T> base = wg;
-#pragma unroll
-    for (int q = 1; q < R / G; ++q) {
-      a[OFF + q * G * STR] = cmul(a[OFF + q * G * STR], base);
-#pragma unroll
-      for (int k = 1; k < G; ++k) a[OFF + (q * G + k) * STR] = cmul(a[OFF + (q * G + k) * STR], cmul(base, p[k]));
-      if (q + 1 < R / G) base = cmul(base, wg);
-    }
+    constexpr int q64 = q * (64 / R);
+    constexpr T c = T(cos64(q64));
+    constexpr T sn = T(SIGN * sin64(q64));
+    const Cx<T> x{fma(c, o.x, fma(-sn, o.y, e.x)), fma(c, o.y, fma(sn, o.x, e.y))};
+    o = {fma(T(2), e.x, -x.x), fma(T(2), e.y, -x.y)};
+    e = x;
   }
 }
 
-// One butterfly job u of Stockham pass P, in place on the registers.
+// R-point DFT on a[OFF + p*STR], p = 0..R-1, in place, radix-2 decimation in
+// time (even and odd halves first, then the combining butterflies); output
+// position p holds bin bitrev_R(p), the same layout as Dif.
+template <int R, int SIGN, int OFF, int STR, typename T>
+struct Dit {
+  template <int I>
+  static __device__ __forceinline__ void bfly(Cx<T>* a) {
+    // E[I] sits at position 2*bitrev_{R/2}(I), O[I] right after it
+    constexpr int p = bitrev(I, ilog2c(R / 2));
+    dit_bfly<R, I, SIGN>(a[OFF + (2 * p) * STR], a[OFF + (2 * p + 1) * STR]);
+  }
+  template <int... I>
+  static __device__ __forceinline__ void stage(Cx<T>* a, std::integer_sequence<int, I...>) {
+    (bfly<I>(a), ...);
+  }
+  static __device__ __forceinline__ void run(Cx<T>* a) {
+    if constexpr (R > 1) {
+      Dit<R / 2, SIGN, OFF, 2 * STR, T>::run(a);
+      Dit<R / 2, SIGN, OFF + STR, 2 * STR, T>::run(a);
+      stage(a, std::make_integer_sequence<int, R / 2>{});
+    }
+  }
+};
+
+// One butterfly job u of Stockham pass P, in place on the registers: the
+// twiddles e^{+-2 pi i k r/(Ns R)} come from the pass's table (exactly
+// rounded), then the R-point DFT.
 template <typename T, int LOGN, int E, int P, int SIGN, int U>
 __device__ __forceinline__ void pass_job(Cx<T> (&v)[E], int t, const Cx<T>* __restrict__ tw) {
   using S = Shape<LOGN, E>;
@@ -194,11 +227,18 @@ __device__ __forceinline__ void pass_job(Cx<T> (&v)[E], int t, const Cx<T>* __re
   if constexpr (NS > 1) {
     const int job = t + U * S::TPR;
     const int k = job & (NS - 1);
-    Cx<T> w = tw[S::twoff(P) + k];
-    if constexpr (SIGN < 0) w.y = -w.y;
-    apply_twiddles<R, U, J>(v, w);
+    const Cx<T>* __restrict__ row = tw + S::twoff(P) + k;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      Cx<T> w = row[(r - 1) * NS];
+      if constexpr (SIGN < 0) w.y = -w.y;
+      v[U + r * J] = cmul(v[U + r * J], w);
+      // double precision: keep at most four twiddles in flight so the
+      // 1024-thread transforms stay inside their 128-register budget
+      if (sizeof(T) == 8 && (r % 4) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
   }
-  Dif<R, SIGN, U, J, T>::run(v);
+  Dit<R, SIGN, U, J, T>::run(v);
 }
 
 template <typename T, int LOGN, int E, int P, int SIGN, int... U>
@@ -214,15 +254,23 @@ __device__ __forceinline__ void pass_compute(Cx<T> (&v)[E], int t, const Cx<T>* 
   pass_jobs<T, LOGN, E, P, SIGN>(v, t, tw, std::make_integer_sequence<int, E / S::radix(P)>{});
 }
 
-// Destination index (in the Stockham order) of output bin q of job u after pass P.
+// LDS addressing.  Element i lives at lds_pad(i) = i + (i >> 4).  For every
+// access pattern below the index is base + c with c a compile-time constant
+// and (base mod 16) + (c mod 16) < 16, so lds_pad(base + c) = lds_pad(base) +
+// c + (c >> 4): the padded base is computed once per job and the rest are
+// immediate offsets.
+__host__ __device__ constexpr int pad_off(int c) { return c + (c >> 4); }
+
+// Padded LDS index of the first output (q = 0) of job u after pass P; output
+// q of the job sits pad_off(q * Ns) further on.  (Stockham destination
+// (job / Ns) * Ns * R + (job mod Ns) + q * Ns.)
 template <int LOGN, int E, int P>
-__device__ __forceinline__ int pass_dest(int t, int u, int q) {
+__device__ __forceinline__ int pass_dest_base(int t, int u) {
   using S = Shape<LOGN, E>;
   constexpr int R = S::radix(P);
   constexpr int NS = S::ns(P);
   const int job = t + u * S::TPR;
-  const int k = job & (NS - 1);
-  return (job / NS) * NS * R + k + q * NS;
+  return lds_pad((job / NS) * NS * R + (job & (NS - 1)));
 }
 
 // Write the outputs of pass P to LDS (complex elements).
@@ -230,12 +278,14 @@ template <typename T, int LOGN, int E, int P>
 __device__ __forceinline__ void lds_write(const Cx<T> (&v)[E], int t, Cx<T>* lds) {
   using S = Shape<LOGN, E>;
   constexpr int R = S::radix(P);
+  constexpr int NS = S::ns(P);
   constexpr int J = E / R;
   constexpr int LR = ilog2c(R);
 #pragma unroll
   for (int u = 0; u < J; ++u) {
+    Cx<T>* b = lds + pass_dest_base<LOGN, E, P>(t, u);
 #pragma unroll
-    for (int q = 0; q < R; ++q) lds[lds_pad(pass_dest<LOGN, E, P>(t, u, q))] = v[u + J * bitrev(q, LR)];
+    for (int q = 0; q < R; ++q) b[pad_off(q * NS)] = v[u + J * bitrev(q, LR)];
   }
 }
 
@@ -243,14 +293,16 @@ template <typename T, int LOGN, int E, int P, int PART>
 __device__ __forceinline__ void lds_write_part(const Cx<T> (&v)[E], int t, T* lds) {
   using S = Shape<LOGN, E>;
   constexpr int R = S::radix(P);
+  constexpr int NS = S::ns(P);
   constexpr int J = E / R;
   constexpr int LR = ilog2c(R);
 #pragma unroll
   for (int u = 0; u < J; ++u) {
+    T* b = lds + pass_dest_base<LOGN, E, P>(t, u);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const Cx<T> val = v[u + J * bitrev(q, LR)];
-      lds[lds_pad(pass_dest<LOGN, E, P>(t, u, q))] = PART == 0 ? val.x : val.y;
+      b[pad_off(q * NS)] = PART == 0 ? val.x : val.y;
     }
   }
 }
@@ -258,16 +310,18 @@ __device__ __forceinline__ void lds_write_part(const Cx<T> (&v)[E], int t, T* ld
 template <typename T, int LOGN, int E>
 __device__ __forceinline__ void lds_read(Cx<T> (&v)[E], int t, const Cx<T>* lds) {
   using S = Shape<LOGN, E>;
+  const Cx<T>* b = lds + lds_pad(t);
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = lds[lds_pad(t + S::TPR * i)];
+  for (int i = 0; i < E; ++i) v[i] = b[pad_off(S::TPR * i)];
 }
 
 template <typename T, int LOGN, int E, int PART>
 __device__ __forceinline__ void lds_read_part(Cx<T> (&v)[E], int t, const T* lds) {
   using S = Shape<LOGN, E>;
+  const T* b = lds + lds_pad(t);
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const T val = lds[lds_pad(t + S::TPR * i)];
+    const T val = b[pad_off(S::TPR * i)];
     if constexpr (PART == 0) v[i].x = val; else v[i].y = val;
   }
 }

@@ -119,13 +119,18 @@ template <typename T, int LOGN>
 static void twiddles_of(double* out) {
   constexpr int E = pickE<T, LOGN>();
   using S = Shape<LOGN, E>;
+  const long double two_pi = 6.283185307179586476925286766559005768L;
   for (int p = 1; p < S::NP; ++p) {
     const int ns = S::ns(p), R = S::radix(p), off = S::twoff(p);
-    const long double L = (long double)ns * R;
-    for (int k = 0; k < ns; ++k) {
-      const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / L;
-      out[2 * (off + k)] = (double)cosl(ang);
-      out[2 * (off + k) + 1] = (double)sinl(ang);
+    const long long L = (long long)ns * R;
+    for (int r = 1; r < R; ++r) {
+      for (int k = 0; k < ns; ++k) {
+        const long long e = ((long long)k * r) % L;  // reduce the angle exactly before rounding
+        const long double ang = two_pi * (long double)e / (long double)L;
+        const int i = off + (r - 1) * ns + k;
+        out[2 * i] = (double)cosl(ang);
+        out[2 * i + 1] = (double)sinl(ang);
+      }
     }
   }
 }
