@@ -8,9 +8,12 @@ selection merge (FP32 mode: short-list + FP64 direct-rule recheck), the
 Blaschke update and the energy.  Inputs are resident in HBM before the timed
 region; outputs stay on the device.
 
-Workload: single signal, N = 16384 samples, M = 1000 radii uniform in
-[0, 0.999], 50 steps; G = 40 normalised Szego kernels with poles |b| <= 0.98
-and CN(0,1) weights plus CN noise at 30 dB SNR (seeded, synthetic).
+Workload (default): single signal, N = 16384 samples, M = 1000 radii uniform
+in [0, 0.999], 50 steps; G = 40 normalised Szego kernels with poles
+|b| <= 0.98 and CN(0,1) weights plus CN noise at 30 dB SNR (seeded,
+synthetic).  `--workload chirp1m` times the large decomposition instead:
+N = 2^20, M = 2000, 100 steps of the analytic part of a chirp + 3 tones +
+white noise at 20 dB, whose radius transforms run as two passes through HBM.
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 """
@@ -50,6 +53,10 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+# bytes of the two-pass intermediate per grid value (written once, read once)
+TWO_PASS_BYTES = {"fp32": 16, "fp64": 32}
+
+
 def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     from paper_1711_08604_amd import Plan
     n = int(sig.numel())
@@ -78,16 +85,29 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     flop_launch = float(m) * n * flops_per_eval(n)
     achieved = flop_launch / avg_kernel_s / 1e12
     peak = PEAK_TFLOPS[prec]
+    tname = "double" if prec == "fp64" else "float"
+    if n <= (1 << 14):
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": f"k_radius<{tname},{int(math.log2(n))}>",
+                "avg_launch_us": avg_kernel_s * 1e6, "launches": k_launches,
+                "flop_per_launch": flop_launch, "grid": [blocks, threads, lds]}
+    else:
+        # one timed unit = the column and row passes over all chunks of one AFD step
+        gbs = float(m) * n * TWO_PASS_BYTES[prec] / avg_kernel_s / 1e9
+        roof = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                "traffic": None,
+                "kernel": f"k_big_cols<{tname},{int(math.log2(n))}> + k_big_rows (all radius chunks of a step)",
+                "avg_launch_us": avg_kernel_s * 1e6, "launches": k_launches,
+                "bytes_per_launch": float(m) * n * TWO_PASS_BYTES[prec],
+                "alu_achieved_tflops": achieved, "alu_frac": achieved / peak,
+                "row_grid": [blocks, threads, lds]}
     out = {
         "value": evals / wall,
         "ms_per_step": wall / steps * 1e3,
         "p50_ms": percentile(lat, 0.5) * 1e3,
         "p99_ms": percentile(lat, 0.99) * 1e3,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": f"k_radius<{'double' if prec == 'fp64' else 'float'},{int(math.log2(n))}>",
-                     "avg_launch_us": avg_kernel_s * 1e6, "launches": k_launches,
-                     "flop_per_launch": flop_launch, "grid": [blocks, threads, lds]},
+        "roofline": roof,
         "index_last": [int(x) for x in res.index[-1].tolist()],
     }
     if prec == "fp32":
@@ -96,25 +116,35 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     return out
 
 
-def cpu_baseline(g, radii, steps_sample):
+def cpu_baseline(g, radii, steps_sample, total_steps):
     import numpy as np
 
     import oracle as O
-    t0 = time.perf_counter()
-    O.decompose(g, radii, steps_sample)
-    dt = time.perf_counter() - t0
     n = g.shape[0]
-    return {"value": len(radii) * n * steps_sample / dt, "unit": "grid evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 FFT-form oracle (numpy pocketfft, single thread), first {steps_sample} of the 50 "
-                      f"AFD steps of the same signal, {dt:.1f} s",
+    t0 = time.perf_counter()
+    if n <= (1 << 14):
+        O.decompose(g, radii, steps_sample)
+        evals = len(radii) * n * steps_sample
+        what = f"first {steps_sample} of the {total_steps} AFD steps of the same signal"
+    else:
+        # one step's grid over a subset of the radii (the full grid of one step
+        # takes minutes and tens of GB on the host)
+        sub = radii[:: max(1, len(radii) // 40)]
+        O.select(O.grid_fft(g, sub))
+        evals = len(sub) * n
+        what = f"grid values and selection of step 1 over {len(sub)} of the {len(radii)} radii"
+    dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": "grid evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 FFT-form oracle (numpy pocketfft, single thread), {what}, {dt:.1f} s",
             "seconds": dt, "numpy": np.__version__}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30, help="timed decompositions")
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["single16k", "chirp1m"], default="single16k")
+    ap.add_argument("--steps", type=int, default=None, help="timed decompositions (30; chirp1m: 3)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed decompositions (3; chirp1m: 1)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=5, help="AFD steps of the oracle sample")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
@@ -133,7 +163,18 @@ def main():
 
     import workloads as W
 
-    g, radii, afd_steps = W.config2()
+    if args.workload == "chirp1m":
+        g, radii, afd_steps = W.config5()
+        wl_text = ("large single decomposition: N=2^20 samples, M=2000 radii uniform in [0,0.999], 100 AFD "
+                   "steps; analytic part of a linear chirp + 3 Gaussian-windowed tones + white noise at 20 dB")
+        dsteps, dwarm = 3, 1
+    else:
+        g, radii, afd_steps = W.config2()
+        wl_text = ("single-signal Core-AFD: N=16384 samples, M=1000 radii uniform in [0,0.999], "
+                   "50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB")
+        dsteps, dwarm = 30, 3
+    args.steps = dsteps if args.steps is None else args.steps
+    args.warmup = dwarm if args.warmup is None else args.warmup
     n, m = g.shape[0], len(radii)
     log(f"bench: N={n} M={m} afd_steps={afd_steps} solves={args.steps} warmup={args.warmup}")
     sig = torch.from_numpy(g).to("cuda:0")
@@ -152,7 +193,7 @@ def main():
             continue
         res[prec] = run_gpu(prec, sig, radii, afd_steps, args.steps, args.warmup, torch)
         log(f"bench: {prec} {res[prec]['value']:.3e} evals/s, {res[prec]['ms_per_step']:.3f} ms/solve, "
-            f"radius kernel {res[prec]['roofline']['avg_launch_us']:.1f} us")
+            f"radius kernel(s) {res[prec]['roofline']['avg_launch_us']:.1f} us per AFD step")
     prim = res.get("fp32") or res.get("fp64")
     line = {
         "metric": METRIC,
@@ -167,9 +208,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if "fp32" in res else "f64",
         "data": "synthetic",
-        "config": {"workload": "single-signal Core-AFD: N=16384 samples, M=1000 radii uniform in [0,0.999], "
-                               "50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB",
-                   "N": n, "M": m, "afd_steps": afd_steps,
+        "config": {"workload": wl_text, "N": n, "M": m, "afd_steps": afd_steps,
                    "mode": "FP32 bulk + FP64 short-list recheck" if "fp32" in res else "FP64"},
         "p50_ms": prim["p50_ms"],
         "p99_ms": prim["p99_ms"],
@@ -182,7 +221,7 @@ def main():
         line["fp64"] = {k: res["fp64"][k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
     if not args.no_cpu:
         log(f"bench: CPU oracle baseline, {args.cpu_steps} AFD steps ...")
-        line["cpu_baseline"] = cpu_baseline(g, radii, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(g, radii, args.cpu_steps, afd_steps)
         log(f"bench: oracle {line['cpu_baseline']['value']:.3e} evals/s")
     print(json.dumps(line), flush=True)
 

@@ -65,9 +65,11 @@ typedef struct {
   int32_t first_a_zero;   /* 1: step 1 takes a_1 = 0 (the grid point (m0, 0) of the first
                              radius equal to 0) instead of the maximum; requires such a radius */
   double recheck_band;    /* FP32 mode: relative band below the FP32 maximum whose points are
-                             all re-checked in double, in [0, 1e-4] (0 -> 4e-6, about eight
-                             times the FP32 error of |.|^2 at N = 2^14); the short-list holds
-                             at most 256 points (flags bit 0 reports a cut)                   */
+                             all re-checked in double, in [0, 1e-4] (0 -> the default: 4e-6
+                             up to N = 2^14, then growing by 2^(1/3) per doubling of N to
+                             1.6e-5 at 2^20, about eight times the largest FP32 error of
+                             |.|^2 measured at those sizes); the short-list holds at most 256
+                             points (flags bit 0 reports a cut)                              */
 } afd_plan_desc;
 
 /* Per-decomposition outputs.  Caller-owned; each pointer may be host memory

@@ -43,8 +43,14 @@ enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3 }
 struct Layout {
   size_t radii, omega, tw, twf1, twf2, pw, pv, scale, g64, g32, c, xt, blocks, cand, partials, winner, epart,
       nonfinite, forced0, counters;
+  // radius transforms beyond the LDS
+  size_t wl, wh, z, rrec, bcounters;
   size_t total;
 };
+
+// Budget of the intermediate of the two-pass radius transforms: it bounds the
+// radii per chunk (32 single / 16 double precision at N = 2^20).
+constexpr size_t kBigChunkBytes = size_t(256) << 20;
 
 struct Config {
   int logn;
@@ -57,6 +63,9 @@ struct Config {
   int nblocks;
   int nch;
   int nparts;
+  bool big;     // N > 2^kMaxLdsLogN: two-pass radius transforms
+  BigGeom bg;
+  int chunk;    // radii per two-pass chunk
 };
 
 constexpr int kNumCounters = 4;  // radius, recheck, update, prepare
@@ -81,19 +90,31 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     if (r == 0.0) has_zero = true;
   }
   if (d->first_a_zero && !has_zero) return fail(AFD_E_INVALID, "first_a_zero needs a radius equal to 0");
-  if (logn > kMaxLdsLogN) return fail(AFD_E_UNSUPPORTED, "N > 2^14 is not supported by this build yet");
   if (cfg) {
     cfg->logn = logn;
     cfg->N = d->n;
     cfg->M = d->m;
     cfg->fp64 = d->precision == AFD_FP64;
-    cfg->geom = fft_geom(logn, cfg->fp64);
     cfg->fwd = fwd_plan(logn, cfg->fp64);
-    const int tpr = cfg->geom.tpr;
-    cfg->rpb = tpr >= 64 ? 1 : 64 / tpr;
-    cfg->nblocks = (d->m + cfg->rpb - 1) / cfg->rpb;
     cfg->nch = recheck_chunks(int(d->n));
     cfg->nparts = update_blocks(int(d->n));
+    cfg->big = logn > kMaxLdsLogN;
+    if (cfg->big) {
+      cfg->geom = FftGeom{0, 0, 0, false, 0};
+      cfg->bg = big_geom(logn, cfg->fp64);
+      const size_t per_radius = size_t(d->n) * (cfg->fp64 ? 16 : 8);
+      const size_t fit = kBigChunkBytes / per_radius;
+      cfg->chunk = int(fit < 1 ? 1 : fit > size_t(d->m) ? size_t(d->m) : fit);
+      cfg->rpb = 1;
+      cfg->nblocks = cfg->chunk * cfg->bg.g;
+    } else {
+      cfg->geom = fft_geom(logn, cfg->fp64);
+      cfg->bg = BigGeom{};
+      cfg->chunk = 0;
+      const int tpr = cfg->geom.tpr;
+      cfg->rpb = tpr >= 64 ? 1 : 64 / tpr;
+      cfg->nblocks = (d->m + cfg->rpb - 1) / cfg->rpb;
+    }
   }
   return AFD_OK;
 }
@@ -112,14 +133,20 @@ Layout layout_of(const Config& c) {
   L.tw = take(2 * real * size_t(c.geom.twsize + 1));
   L.twf1 = take(2 * real * size_t(c.fwd.tw1_size + 1));
   L.twf2 = take(2 * real * size_t(c.fwd.tw2_size + 1));
-  L.pw = take(real * size_t(c.M) * c.geom.tpr);
-  L.pv = take(real * size_t(c.M) * c.geom.E);
+  // LDS path: r^t [M][TPR] and r^(TPR v) [M][E]; two-pass path: r^(N2 l1) [M][N1] and r^l2 [M][N2]
+  L.pw = take(real * size_t(c.M) * (c.big ? (size_t(1) << c.bg.l1) : size_t(c.geom.tpr)));
+  L.pv = take(real * size_t(c.M) * (c.big ? (size_t(1) << c.bg.l2) : size_t(c.geom.E)));
   L.scale = take(real * size_t(c.M));
   L.g64 = take(16 * size_t(c.N));
   L.g32 = take(c.fp64 ? 0 : 8 * size_t(c.N));
   L.c = take(2 * real * size_t(c.N));
   L.xt = take(c.fwd.two_pass ? 2 * real * size_t(c.N) : 0);
   L.blocks = take((c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.nblocks));
+  L.wl = take(c.big ? 2 * real * (size_t(1) << c.bg.sw) : 0);
+  L.wh = take(c.big ? 2 * real * (size_t(1) << (c.logn - c.bg.sw)) : 0);
+  L.z = take(c.big ? 2 * real * size_t(c.chunk) * size_t(c.N) : 0);
+  L.rrec = take(c.big ? (c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.M) : 0);
+  L.bcounters = take(c.big ? 4 * (size_t(c.chunk) + 1) : 0);
   L.cand = take(sizeof(CandList));
   L.partials = take(16 * size_t(kKMax) * c.nch);
   L.winner = take(sizeof(Winner));
@@ -188,14 +215,31 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   std::vector<double> twf1(2 * size_t(c.fwd.tw1_size + 1), 0.0), twf2(2 * size_t(c.fwd.tw2_size + 1), 0.0);
   fft_twiddles(c.fwd.two_pass ? c.fwd.l1 : c.logn, c.fp64, twf1.data());
   if (c.fwd.two_pass) fft_twiddles(c.fwd.l2, c.fp64, twf2.data());
-  std::vector<double> pw(size_t(M) * tpr), pv(size_t(M) * E), sc(M);
+  // r^l = pw[m][a] * pv[m][b]: l = a + TPR b (LDS path) or l = N2 a + b (two-pass path, pw = r^(N2 a))
+  const int na = c.big ? (1 << c.bg.l1) : tpr, nb = c.big ? (1 << c.bg.l2) : E;
+  const long double sa = c.big ? (long double)nb : 1.0L, sb = c.big ? 1.0L : (long double)tpr;
+  std::vector<double> pw(size_t(M) * na), pv(size_t(M) * nb), sc(M);
   for (int m = 0; m < M; ++m) {
     const long double r = radii[m];
-    for (int t = 0; t < tpr; ++t) pw[size_t(m) * tpr + t] = t == 0 ? 1.0 : (double)powl(r, (long double)t);
-    for (int v = 0; v < E; ++v)
-      pv[size_t(m) * E + v] = v == 0 ? 1.0 : (double)powl(r, (long double)tpr * (long double)v);
+    for (int a = 0; a < na; ++a) pw[size_t(m) * na + a] = a == 0 ? 1.0 : (double)powl(r, sa * (long double)a);
+    for (int b = 0; b < nb; ++b) pv[size_t(m) * nb + b] = b == 0 ? 1.0 : (double)powl(r, sb * (long double)b);
     const long double rN = powl(r, (long double)N);
     sc[m] = (double)(sqrtl((1.0L - r) * (1.0L + r)) / ((long double)N * (1.0L - rN)));
+  }
+  // two-pass path: e^{2 pi i e/N} = wh[e >> sw] * wl[e mod 2^sw]
+  std::vector<double> wl, wh;
+  if (c.big) {
+    const int64_t nl = int64_t(1) << c.bg.sw, nh = N >> c.bg.sw;
+    wl.resize(2 * size_t(nl));
+    wh.resize(2 * size_t(nh));
+    for (int64_t e = 0; e < nl; ++e) {
+      wl[2 * e] = omega[2 * e];
+      wl[2 * e + 1] = omega[2 * e + 1];
+    }
+    for (int64_t h = 0; h < nh; ++h) {
+      wh[2 * h] = omega[2 * (h * nl)];
+      wh[2 * h + 1] = omega[2 * (h * nl) + 1];
+    }
   }
   auto up = [&](size_t off, const void* src, size_t bytes) {
     return hipMemcpy(p->arena + off, src, bytes, hipMemcpyHostToDevice);
@@ -209,6 +253,8 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     if (e == hipSuccess) e = up(p->L.pw, pw.data(), pw.size() * 8);
     if (e == hipSuccess) e = up(p->L.pv, pv.data(), pv.size() * 8);
     if (e == hipSuccess) e = up(p->L.scale, sc.data(), sc.size() * 8);
+    if (e == hipSuccess && c.big) e = up(p->L.wl, wl.data(), wl.size() * 8);
+    if (e == hipSuccess && c.big) e = up(p->L.wh, wh.data(), wh.size() * 8);
   } else {
     auto f32 = [](const std::vector<double>& v) {
       std::vector<float> o(v.size());
@@ -216,18 +262,21 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
       return o;
     };
     const std::vector<float> tw32 = f32(tw), pw32 = f32(pw), pv32 = f32(pv), sc32 = f32(sc);
-    const std::vector<float> twf1_32 = f32(twf1), twf2_32 = f32(twf2);
+    const std::vector<float> twf1_32 = f32(twf1), twf2_32 = f32(twf2), wl32 = f32(wl), wh32 = f32(wh);
     if (e == hipSuccess) e = up(p->L.tw, tw32.data(), tw32.size() * 4);
     if (e == hipSuccess) e = up(p->L.twf1, twf1_32.data(), twf1_32.size() * 4);
     if (e == hipSuccess) e = up(p->L.twf2, twf2_32.data(), twf2_32.size() * 4);
     if (e == hipSuccess) e = up(p->L.pw, pw32.data(), pw32.size() * 4);
     if (e == hipSuccess) e = up(p->L.pv, pv32.data(), pv32.size() * 4);
     if (e == hipSuccess) e = up(p->L.scale, sc32.data(), sc32.size() * 4);
+    if (e == hipSuccess && c.big) e = up(p->L.wl, wl32.data(), wl32.size() * 4);
+    if (e == hipSuccess && c.big) e = up(p->L.wh, wh32.data(), wh32.size() * 4);
   }
   const int32_t f0[2] = {p->zero_m < 0 ? 0 : p->zero_m, 0};
   if (e == hipSuccess) e = up(p->L.forced0, f0, sizeof(f0));
   if (e == hipSuccess) e = hipMemset(p->arena + p->L.nonfinite, 0, 4);
   if (e == hipSuccess) e = hipMemset(p->arena + p->L.counters, 0, 4 * kNumCounters);
+  if (e == hipSuccess && c.big) e = hipMemset(p->arena + p->L.bcounters, 0, 4 * (size_t(c.chunk) + 1));
   if (e != hipSuccess) return hip_fail(e, "uploading plan tables");
   return AFD_OK;
 }
@@ -406,6 +455,8 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   // flags and last-workgroup counters start at zero (also after an aborted call)
   HIPCHK(hipMemsetAsync(nonfinite, 0, 4, s), "clearing flag");
   HIPCHK(hipMemsetAsync(counters, 0, 4 * kNumCounters, s), "clearing counters");
+  if (c.big)
+    HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4 * (size_t(c.chunk) + 1), s), "clearing counters");
   HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N), sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
          "copying signal");
   HIPCHK(launch_prepare(g64, g32, N, epart, nonfinite, counters + 3, rec, s), "k_prepare");
@@ -424,6 +475,29 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.counter = counters + 0;
   rp.cand = cand;
   rp.winner = win;
+
+  BigParams bp{};
+  if (c.big) {
+    bp.c = cspec;
+    bp.pa = p->at<void>(p->L.pw);
+    bp.pb = p->at<void>(p->L.pv);
+    bp.scale = p->at<void>(p->L.scale);
+    bp.wl = p->at<void>(p->L.wl);
+    bp.wh = p->at<void>(p->L.wh);
+    bp.tw1 = p->at<void>(p->L.twf1);
+    bp.tw2 = p->at<void>(p->L.twf2);
+    bp.z = p->at<void>(p->L.z);
+    bp.M = c.M;
+    bp.m0 = 0;
+    bp.tau_band = p->tau_band;
+    bp.recheck_k = p->recheck_k;
+    bp.blocks = p->at<void>(p->L.blocks);
+    bp.rrec = p->at<void>(p->L.rrec);
+    bp.counter_r = p->at<unsigned int>(p->L.bcounters);
+    bp.counter_g = p->at<unsigned int>(p->L.bcounters) + c.chunk;
+    bp.cand = cand;
+    bp.winner = win;
+  }
 
   Timer tm{p, p->time_kind};
   for (int k = 0; k < steps; ++k) {
@@ -445,7 +519,14 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
              "forward DFT");
       HIPCHK(tm.end(kTimeFft), "event");
       HIPCHK(tm.begin(kTimeRadius), "event");
-      HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, s), "k_radius");
+      if (c.big) {
+        for (int m0 = 0; m0 < c.M; m0 += c.chunk) {
+          bp.m0 = m0;
+          HIPCHK(launch_big(c.logn, c.fp64, bp, c.M - m0 < c.chunk ? c.M - m0 : c.chunk, s), "k_big");
+        }
+      } else {
+        HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, s), "k_radius");
+      }
       HIPCHK(tm.end(kTimeRadius), "event");
       if (!c.fp64)
         HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1, win, s), "k_recheck");
@@ -494,7 +575,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
   p->L = layout_of(cfg);
   p->stream = reinterpret_cast<hipStream_t>(hip_stream);
   p->recheck_k = desc->recheck_k == 0 ? 8 : desc->recheck_k;
-  p->tau_band = desc->recheck_band == 0.0 ? kTauBandDefault : float(desc->recheck_band);
+  p->tau_band = desc->recheck_band == 0.0 ? default_tau_band(cfg.logn) : float(desc->recheck_band);
   p->first_a_zero = desc->first_a_zero != 0;
   for (int i = 0; i < desc->m; ++i)
     if (desc->radii[i] == 0.0) {
@@ -507,6 +588,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
     if (!attrs_done) {
       e = setup_radius_attributes();
       if (e == hipSuccess) e = setup_fwd_attributes();
+      if (e == hipSuccess) e = setup_big_attributes();
       if (e == hipSuccess) attrs_done = true;
     }
   }
@@ -592,9 +674,16 @@ afd_status afd_plan_kernel_time(afd_plan plan, double* ms, int64_t* launches) {
 
 afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threads, int32_t* lds_bytes) {
   if (!plan || !blocks || !threads || !lds_bytes) return fail(AFD_E_INVALID, "NULL argument");
-  *blocks = plan->cfg.nblocks;
-  *threads = radius_threads_of(plan->cfg.logn, plan->cfg.fp64);
-  *lds_bytes = radius_lds_bytes(plan->cfg.logn, plan->cfg.fp64, plan->cfg.rpb);
+  const Config& c = plan->cfg;
+  if (c.big) {  // the row pass, which carries the selection
+    *blocks = int64_t(c.bg.g) * c.M;
+    *threads = c.bg.thr_b;
+    *lds_bytes = int32_t(c.bg.lds_b);
+  } else {
+    *blocks = c.nblocks;
+    *threads = radius_threads_of(c.logn, c.fp64);
+    *lds_bytes = radius_lds_bytes(c.logn, c.fp64, c.rpb);
+  }
   return AFD_OK;
 }
 

@@ -6,7 +6,9 @@
 // l = k2 + N2 k1): workgroups of the first pass each take 8 columns l1, run
 // the length-N2 DFTs over l2, apply e^{-2 pi i l1 k2/N} and store the
 // intermediate as X[k2][l1]; workgroups of the second pass each take 8 rows
-// k2 and run the length-N1 DFTs over l1, writing c[k2 + N2 k1].  Both passes
+// k2 and run the length-N1 DFTs over l1, writing c[k2 + N2 k1] -- or, for
+// the radius transforms beyond the LDS, the same values in column order
+// (row k2 contiguous: the column l2 = k2 of those transforms).  Both passes
 // spread the work over many CUs instead of serialising it on one.
 #include "afd_device.h"
 #include "afd_internal.h"
@@ -81,8 +83,9 @@ __global__ __launch_bounds__((cols_threads<T, LOGN>())) void k_fwd_cols(const Cx
   }
 }
 
-// Second pass: c[k2 + N2 k1] = sum_l1 X[k2][l1] e^{-2 pi i l1 k1/N1}
-template <typename T, int LOGN>
+// Second pass: c[k2 + N2 k1] = sum_l1 X[k2][l1] e^{-2 pi i l1 k1/N1}, stored at
+// c[k2 + N2 k1] or, with COLS, at c[k2 N1 + k1].
+template <typename T, int LOGN, bool COLS>
 __global__ __launch_bounds__((rows_threads<T, LOGN>())) void k_fwd_rows(const Cx<T>* __restrict__ xt,
                                                                          const Cx<T>* __restrict__ tw1,
                                                                          Cx<T>* __restrict__ c) {
@@ -90,7 +93,10 @@ __global__ __launch_bounds__((rows_threads<T, LOGN>())) void k_fwd_rows(const Cx
   constexpr int E1 = pickE<T, P::L1>();
   using S1 = Shape<P::L1, E1>;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int ri = threadIdx.x % kColsPerBlock, t = threadIdx.x / kColsPerBlock;
+  // COLS: the threads of a row are adjacent (contiguous loads and stores);
+  // otherwise the rows are interleaved (stores of kColsPerBlock adjacent bins)
+  const int ri = COLS ? int(threadIdx.x) / S1::TPR : int(threadIdx.x) % kColsPerBlock;
+  const int t = COLS ? int(threadIdx.x) % S1::TPR : int(threadIdx.x) / kColsPerBlock;
   const int k2 = blockIdx.x * kColsPerBlock + ri;
   unsigned char* region = smem + size_t(ri) * fft_region_bytes<T, P::L1, false>();
   Cx<T> v[E1];
@@ -98,7 +104,13 @@ __global__ __launch_bounds__((rows_threads<T, LOGN>())) void k_fwd_rows(const Cx
   for (int i = 0; i < E1; ++i) v[i] = xt[size_t(k2) * P::N1 + t + S1::TPR * i];
   fft_regs<T, P::L1, E1, -1, false>(v, t, region, tw1);
 #pragma unroll
-  for (int p = 0; p < E1; ++p) c[k2 + P::N2 * out_bin<P::L1, E1>(t, p)] = v[p];
+  for (int p = 0; p < E1; ++p) {
+    const int k1 = out_bin<P::L1, E1>(t, p);
+    if constexpr (COLS)
+      c[size_t(k2) * P::N1 + k1] = v[p];
+    else
+      c[k2 + P::N2 * k1] = v[p];
+  }
 }
 
 // ---------------------------------------------------------------- host side
@@ -137,7 +149,15 @@ static void twiddles_of(double* out) {
 
 #define AFD_FWD_LOGN_CASES(X) \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
-#define AFD_FWD2_LOGN_CASES(X) X(12) X(13) X(14)
+#define AFD_FWD2_LOGN_CASES(X) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
+#define AFD_FWD_ALL_LOGN_CASES(X) AFD_FWD_LOGN_CASES(X) X(15) X(16) X(17) X(18) X(19) X(20)
+
+// the spectrum goes out in column order when the radius transforms run as
+// two passes through HBM
+template <int LOGN>
+constexpr bool fwd_cols_out() {
+  return LOGN > kMaxLdsLogN;
+}
 
 FftGeom fft_geom(int logn, bool fp64) {
   switch (logn) {
@@ -198,9 +218,9 @@ hipError_t setup_fwd_attributes() {
   if (e == hipSuccess)                                                                                    \
     e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_fwd_cols<float, L>));                             \
   if (e == hipSuccess)                                                                                    \
-    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_fwd_rows<double, L>));                             \
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_fwd_rows<double, L, fwd_cols_out<L>()>));         \
   if (e == hipSuccess)                                                                                    \
-    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_fwd_rows<float, L>));
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_fwd_rows<float, L, fwd_cols_out<L>()>));
   AFD_FWD2_LOGN_CASES(X)
 #undef X
   return e;
@@ -223,7 +243,7 @@ static hipError_t launch_fwd_t(const void* g, const void* tw1, const void* tw2, 
     hipLaunchKernelGGL((k_fwd_cols<T, LOGN>), dim3(P::N1 / kColsPerBlock), dim3(thr_c), lds_c, s,
                        reinterpret_cast<const Cx<T>*>(g), reinterpret_cast<const Cx<T>*>(tw2), omega,
                        reinterpret_cast<Cx<T>*>(xt));
-    hipLaunchKernelGGL((k_fwd_rows<T, LOGN>), dim3(P::N2 / kColsPerBlock), dim3(thr_r), lds_r, s,
+    hipLaunchKernelGGL((k_fwd_rows<T, LOGN, fwd_cols_out<LOGN>()>), dim3(P::N2 / kColsPerBlock), dim3(thr_r), lds_r, s,
                        reinterpret_cast<const Cx<T>*>(xt), reinterpret_cast<const Cx<T>*>(tw1),
                        reinterpret_cast<Cx<T>*>(c));
   }
@@ -237,7 +257,7 @@ hipError_t launch_fwd(int logn, bool fp64, const void* g, const void* tw1, const
   case L:                                                                          \
     return fp64 ? launch_fwd_t<double, L>(g, tw1, tw2, omega, xt, c, s)            \
                 : launch_fwd_t<float, L>(g, tw1, tw2, omega, xt, c, s);
-    AFD_FWD_LOGN_CASES(X)
+    AFD_FWD_ALL_LOGN_CASES(X)
 #undef X
     default:
       return hipErrorInvalidValue;

@@ -8,6 +8,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <cmath>
+
 namespace afd {
 
 constexpr int kMaxLogN = 20;       // N <= 2^20
@@ -16,7 +18,12 @@ constexpr int kListC = 64;         // per-workgroup candidate list length (FP32 
 constexpr int kListCap = 1024;     // per-workgroup LDS gather capacity before the exact fallback
 constexpr int kKMax = 256;         // longest short-list re-checked in double
 constexpr int kSelCap = 1024;      // global gather capacity of the short-list selection
-constexpr float kTauBandDefault = 4e-6f;  // default re-check band (relative to the FP32 maximum)
+// Default re-check band (relative to the FP32 maximum): 4e-6 up to 2^14
+// points, then x 2^(1/3) per doubling (1.6e-5 at 2^20), about eight times the
+// largest FP32 error of |.|^2 measured at those sizes.
+inline float default_tau_band(int logn) {
+  return logn <= 14 ? 4e-6f : float(4e-6 * std::exp2((logn - 14) / 3.0));
+}
 
 // flags (per step; bits 0-2 are reported)
 constexpr int kFlagBandTruncated = 1;
@@ -73,6 +80,46 @@ struct RadiusParams {
   CandList* cand;     // FP32 short-list (written by the last workgroup)
   Winner* winner;     // FP64 winner (written by the last workgroup)
 };
+
+// Radius transforms beyond the LDS (N > 2^kMaxLdsLogN): per radius a
+// four-step transform over N = N1 N2 through an intermediate in HBM, run
+// over chunks of radii (see afd_large.hip).
+struct BigParams {
+  const void* c;      // spectrum in column order: c_{N2 l1 + l2} at [l2][l1] (T complex)
+  const void* pa;     // [M][N1]  r_m^(N2 l1)
+  const void* pb;     // [M][N2]  r_m^l2
+  const void* scale;  // [M]      sqrt(1-r^2) / (N (1 - r^N))
+  const void* wl;     // e^{2 pi i e/N}, e < 2^sw (T complex)
+  const void* wh;     // e^{2 pi i h 2^sw/N}, h < N/2^sw (T complex)
+  const void* tw1;    // Stockham twiddles of the length-N1 transforms
+  const void* tw2;    // Stockham twiddles of the length-N2 transforms
+  void* z;            // [chunk][N1][N2] intermediate (T complex)
+  int M;
+  int m0;             // first radius of the chunk
+  float tau_band;
+  int recheck_k;
+  void* blocks;       // [chunk][G] per-workgroup records (BlockList32 or BlockBest64)
+  void* rrec;         // [M] per-radius records (same type)
+  unsigned int* counter_r;  // [chunk] workgroup arrivals per radius (zero between launches)
+  unsigned int* counter_g;  // radius arrivals over the step's chunks (zero between steps)
+  CandList* cand;
+  Winner* winner;
+};
+
+struct BigGeom {
+  int l1, l2;     // N1 = 2^l1 (column transforms), N2 = 2^l2 (row transforms)
+  int sw;         // twiddle split: e = h 2^sw + low
+  int ca, thr_a;  // columns and threads per column workgroup
+  int rb, thr_b;  // rows and threads per row workgroup
+  int g;          // row workgroups per radius
+  size_t lds_a, lds_b;
+  size_t rec_bytes;  // one per-workgroup record
+};
+BigGeom big_geom(int logn, bool fp64);
+hipError_t setup_big_attributes();
+// One chunk of `nr` radii starting at p.m0: the column pass, then the row
+// pass with the selection.
+hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s);
 
 // Step outputs written by the last workgroup of k_update / k_prepare.
 struct RecordArgs {

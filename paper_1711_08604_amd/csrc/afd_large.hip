@@ -1,0 +1,209 @@
+// Per-radius inverse DFTs beyond the LDS, N = 2^15 .. 2^20 (Sec. 3.1, eq. rcl;
+// Sec. 3.2, Steps 1-2).
+//
+// A radius' transform y_m[j] = sum_l r_m^l c_l e^{2 pi i j l/N} no longer fits
+// one workgroup, so it is split as N = N1 N2 with l = N2 l1 + l2 and
+// j = j1 + N1 j2:
+//
+//   y_m[j1 + N1 j2] = sum_l2 e^{2 pi i j2 l2/N2} Z_m[j1][l2],
+//   Z_m[j1][l2]     = r_m^l2 e^{2 pi i j1 l2/N} sum_l1 r_m^(N2 l1) c_{N2 l1 + l2} e^{2 pi i j1 l1/N1}.
+//
+// The column pass (k_big_cols) runs the length-N1 transforms of CA columns
+// l2 per workgroup, reading the spectrum in column order (the forward DFT
+// writes it that way), applies r_m^l2 e^{2 pi i j1 l2/N}, transposes through
+// LDS and stores Z_m with the columns contiguous.  The row pass (k_big_rows)
+// runs the length-N2 transforms of RB rows j1 per workgroup, scales by s_m,
+// forms |.|^2 and selects as the LDS-resident kernel does (flat index
+// m N + j1 + N1 j2).  The last row workgroup of a radius merges the radius'
+// workgroup records into one per-radius record; the last radius of the step
+// merges those into the winner (FP64) or the short-list (FP32).  Radii are
+// processed in chunks so the intermediate stays within a fixed budget.
+#include "afd_select.h"
+
+namespace afd {
+
+template <typename T, int LOGN>
+struct Big {
+  static constexpr int L1 = LOGN / 2, L2 = LOGN - L1;
+  static constexpr int N = 1 << LOGN, N1 = 1 << L1, N2 = 1 << L2;
+  static constexpr int E1 = pickE<T, L1>(), E2 = pickE<T, L2>();
+  static constexpr int TPR1 = N1 / E1, TPR2 = N2 / E2;
+  // columns per workgroup: 64-byte runs of the intermediate, >= 256 threads
+  static constexpr int CA0 = sizeof(T) == 4 ? 8 : 4;
+  static constexpr int CA = 256 / TPR1 > CA0 ? 256 / TPR1 : CA0;
+  static constexpr int THR_A = CA * TPR1;
+  static constexpr int RB = 256 / TPR2 > 1 ? 256 / TPR2 : 1;
+  static constexpr int THR_B = RB * TPR2;
+  static constexpr int G = N1 / RB;
+  static constexpr int SW = (LOGN + 1) / 2;
+  static constexpr int LDT = CA + 1;  // row pitch of the LDS transpose (complex elements)
+  static_assert(N2 % CA == 0 && N1 % RB == 0, "tiles must divide the transform");
+  static_assert(G <= THR_B, "the radius merge holds one workgroup list per thread");
+  static constexpr size_t region_a = fft_region_bytes<T, L1, false>();
+  static constexpr size_t region_b = fft_region_bytes<T, L2, false>();
+  static constexpr size_t lds_a = (size_t(CA) * region_a > size_t(N1) * LDT * sizeof(Cx<T>))
+                                      ? size_t(CA) * region_a
+                                      : size_t(N1) * LDT * sizeof(Cx<T>);
+  static constexpr size_t lds_b0 = size_t(RB) * region_b + (sizeof(T) == 4 ? kListScratchBytes : 16 * sizeof(Best));
+  static constexpr size_t lds_b = lds_b0 > sizeof(MergeScratch) ? lds_b0 : sizeof(MergeScratch);
+};
+
+template <typename T, int LOGN>
+__global__ __launch_bounds__((Big<T, LOGN>::THR_A)) void k_big_cols(BigParams p) {
+  using B = Big<T, LOGN>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ci = threadIdx.x / B::TPR1, t = threadIdx.x - ci * B::TPR1;
+  const int l2 = blockIdx.x * B::CA + ci;
+  const int ml = blockIdx.y, m = p.m0 + ml;
+
+  // weighted column x[l1] = r^(N2 l1) c_{N2 l1 + l2} (the factor r^l2 is applied after the transform)
+  const Cx<T>* __restrict__ col = reinterpret_cast<const Cx<T>*>(p.c) + size_t(l2) * B::N1;
+  const T* __restrict__ pa = reinterpret_cast<const T*>(p.pa) + size_t(m) * B::N1;
+  Cx<T> v[B::E1];
+#pragma unroll
+  for (int i = 0; i < B::E1; ++i) {
+    const int l1 = t + B::TPR1 * i;
+    const Cx<T> x = col[l1];
+    const T w = pa[l1];
+    v[i] = {x.x * w, x.y * w};
+  }
+  fft_regs<T, B::L1, B::E1, +1, false>(v, t, smem + size_t(ci) * B::region_a, reinterpret_cast<const Cx<T>*>(p.tw1));
+
+  // transpose through LDS (the transform's last exchange ended at a barrier)
+  Cx<T>* tr = reinterpret_cast<Cx<T>*>(smem);
+#pragma unroll
+  for (int q = 0; q < B::E1; ++q) tr[out_bin<B::L1, B::E1>(t, q) * B::LDT + ci] = v[q];
+  __syncthreads();
+
+  const int cj = threadIdx.x % B::CA, jr = threadIdx.x / B::CA;
+  const int l2o = blockIdx.x * B::CA + cj;
+  const T rl = reinterpret_cast<const T*>(p.pb)[size_t(m) * B::N2 + l2o];
+  const Cx<T>* __restrict__ wl = reinterpret_cast<const Cx<T>*>(p.wl);
+  const Cx<T>* __restrict__ wh = reinterpret_cast<const Cx<T>*>(p.wh);
+  Cx<T>* __restrict__ z = reinterpret_cast<Cx<T>*>(p.z) + size_t(ml) * B::N + l2o;
+  constexpr int JS = B::THR_A / B::CA;
+#pragma unroll 4
+  for (int j1 = jr; j1 < B::N1; j1 += JS) {
+    const uint32_t e = (uint32_t(j1) * uint32_t(l2o)) & uint32_t(B::N - 1);
+    Cx<T> w = cmul(wh[e >> B::SW], wl[e & ((1u << B::SW) - 1u)]);
+    w = {w.x * rl, w.y * rl};
+    z[size_t(j1) * B::N2] = cmul(tr[j1 * B::LDT + cj], w);
+  }
+}
+
+template <typename T, int LOGN, bool LIST>
+__global__ __launch_bounds__((Big<T, LOGN>::THR_B)) void k_big_rows(BigParams p) {
+  using B = Big<T, LOGN>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_last;
+  const int ri = threadIdx.x / B::TPR2, t = threadIdx.x - ri * B::TPR2;
+  const int j1 = blockIdx.x * B::RB + ri;
+  const int ml = blockIdx.y, m = p.m0 + ml;
+
+  const Cx<T>* __restrict__ row = reinterpret_cast<const Cx<T>*>(p.z) + size_t(ml) * B::N + size_t(j1) * B::N2;
+  Cx<T> v[B::E2];
+#pragma unroll
+  for (int i = 0; i < B::E2; ++i) v[i] = row[t + B::TPR2 * i];
+  fft_regs<T, B::L2, B::E2, +1, false>(v, t, smem + size_t(ri) * B::region_b, reinterpret_cast<const Cx<T>*>(p.tw2));
+
+  unsigned char* scratch = smem + size_t(B::RB) * B::region_b;
+  const T sc = reinterpret_cast<const T*>(p.scale)[m];
+  // register p of thread t holds j2 = t + TPR2 bitrev(p): flat index m N + j1 + N1 j2
+  const uint32_t fbase = uint32_t(m) * uint32_t(B::N) + uint32_t(j1);
+  const int rec = ml * B::G + int(blockIdx.x);
+  if constexpr (LIST) {
+    const FlatOrder ord{uint32_t(m) * uint32_t(B::N) + uint32_t(blockIdx.x) * uint32_t(B::RB), uint32_t(B::RB),
+                        uint32_t(B::N1), uint32_t(B::RB) * uint32_t(B::N2)};
+    select_list<B::L2>(v, true, sc, fbase, uint32_t(B::N1), t, scratch, p.tau_band, ord,
+                       reinterpret_cast<BlockList32*>(p.blocks) + rec);
+  } else {
+    select_best<B::L2, T>(v, true, sc, fbase, uint32_t(B::N1), t, reinterpret_cast<Best*>(scratch),
+                          reinterpret_cast<BlockBest64*>(p.blocks) + rec);
+  }
+
+  if (!last_arrival(p.counter_r + ml, unsigned(B::G), &s_last)) return;
+  MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
+  if constexpr (LIST) {
+    merge_list_group(reinterpret_cast<const BlockList32*>(p.blocks) + ml * B::G, B::G, p.tau_band,
+                     reinterpret_cast<BlockList32*>(p.rrec) + m, Sm);
+  } else {
+    merge_best_group(reinterpret_cast<const BlockBest64*>(p.blocks) + ml * B::G, B::G,
+                     reinterpret_cast<BlockBest64*>(p.rrec) + m, Sm);
+  }
+  if (!last_arrival(p.counter_g, unsigned(p.M), &s_last)) return;
+  if constexpr (LIST) {
+    select32_tail(reinterpret_cast<const BlockList32*>(p.rrec), p.M, p.recheck_k, p.tau_band, p.cand, Sm);
+  } else {
+    merge64_tail(reinterpret_cast<const BlockBest64*>(p.rrec), p.M, B::N, LOGN, p.winner, Sm);
+  }
+}
+
+// ---------------------------------------------------------------- host side
+#define AFD_BIG_LOGN_CASES(X) X(15) X(16) X(17) X(18) X(19) X(20)
+
+template <typename T, int LOGN>
+static BigGeom big_geom_of() {
+  using B = Big<T, LOGN>;
+  BigGeom g;
+  g.l1 = B::L1;
+  g.l2 = B::L2;
+  g.sw = B::SW;
+  g.ca = B::CA;
+  g.thr_a = B::THR_A;
+  g.rb = B::RB;
+  g.thr_b = B::THR_B;
+  g.g = B::G;
+  g.lds_a = B::lds_a;
+  g.lds_b = B::lds_b;
+  g.rec_bytes = sizeof(T) == 4 ? sizeof(BlockList32) : sizeof(BlockBest64);
+  return g;
+}
+
+BigGeom big_geom(int logn, bool fp64) {
+  switch (logn) {
+#define X(L) \
+  case L:    \
+    return fp64 ? big_geom_of<double, L>() : big_geom_of<float, L>();
+    AFD_BIG_LOGN_CASES(X)
+#undef X
+    default:
+      return BigGeom{};
+  }
+}
+
+hipError_t setup_big_attributes() {
+  hipError_t e = hipSuccess;
+#define X(L)                                                                                        \
+  if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_cols<float, L>));        \
+  if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_cols<double, L>));       \
+  if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<float, L, true>));  \
+  if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<double, L, false>));
+  AFD_BIG_LOGN_CASES(X)
+#undef X
+  return e;
+}
+
+template <typename T, int LOGN>
+static hipError_t launch_big_t(const BigParams& p, int nr, hipStream_t s) {
+  using B = Big<T, LOGN>;
+  if (nr < 1 || p.m0 < 0 || p.m0 + nr > p.M) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_big_cols<T, LOGN>), dim3(B::N2 / B::CA, nr), dim3(B::THR_A), B::lds_a, s, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_big_rows<T, LOGN, sizeof(T) == 4>), dim3(B::G, nr), dim3(B::THR_B), B::lds_b, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s) {
+  switch (logn) {
+#define X(L) \
+  case L:    \
+    return fp64 ? launch_big_t<double, L>(p, nr, s) : launch_big_t<float, L>(p, nr, s);
+    AFD_BIG_LOGN_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace afd

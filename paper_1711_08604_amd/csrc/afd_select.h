@@ -178,12 +178,13 @@ __device__ __forceinline__ float ld_agent(const float* p) {
 // Wave 0 waits for its stores to complete before thread 0 counts the
 // arrival, so the last workgroup's later loads see every record.  The counter
 // is reset for the next launch.  `flag` is an LDS int.
-__device__ __forceinline__ bool last_workgroup(unsigned int* counter, int* flag) {
+// last_arrival counts `total` arrivals instead (a group of workgroups, or
+// arrivals spread over several launches).
+__device__ __forceinline__ bool last_arrival(unsigned int* counter, unsigned int total, int* flag) {
   __syncthreads();
   if (threadIdx.x < 64) {
     __builtin_amdgcn_s_waitcnt(0);
     if (threadIdx.x == 0) {
-      const unsigned int total = gridDim.x * gridDim.y * gridDim.z;
       const unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const int last = prev == total - 1;
       if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -194,6 +195,10 @@ __device__ __forceinline__ bool last_workgroup(unsigned int* counter, int* flag)
   return *flag != 0;
 }
 
+__device__ __forceinline__ bool last_workgroup(unsigned int* counter, int* flag) {
+  return last_arrival(counter, gridDim.x * gridDim.y * gridDim.z, flag);
+}
+
 __device__ __forceinline__ void wave0_copy_keys(const uint64_t* src, uint64_t* dst, uint32_t n) {
   if (threadIdx.x < n) st_agent(dst + threadIdx.x, src[threadIdx.x]);
 }
@@ -202,13 +207,110 @@ __device__ __forceinline__ void wave0_copy_keys(const uint64_t* src, uint64_t* d
 struct MergeScratch {
   uint64_t buf[kSelCap];
   uint32_t cblk[kSelCap];
+  uint64_t sorted[kListC];
   uint64_t wb[16];
   Best bb[16];
   float wf[16];
   double wd[16];
-  uint32_t scount, sblocks, sflags;
+  uint32_t scount, sblocks, sflags, stotal;
   int last;
 };
+
+// FP64: best and runner-up over a group of workgroup records (the workgroups
+// of one radius) into one record of the same form.
+__device__ __forceinline__ void merge_best_group(const BlockBest64* __restrict__ recs, int n,
+                                                 BlockBest64* __restrict__ out, MergeScratch* S) {
+  Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const BlockBest64* o = recs + i;
+    const Best x{ld_agent(&o->p1), ld_agent(&o->p2), ld_agent(&o->vx), ld_agent(&o->vy), ld_agent(&o->f)};
+    best_merge(b, x);
+  }
+  const Best r = block_best(b, S->bb);
+  if (threadIdx.x == 0) {
+    st_agent(&out->p1, r.p1);
+    st_agent(&out->p2, r.p2);
+    st_agent(&out->vx, r.vx);
+    st_agent(&out->vy, r.vy);
+    st_agent(&out->f, r.f);
+  }
+}
+
+// FP32: the lists of a group of workgroups (the workgroups of one radius)
+// merged into one list of the same form: every listed point within tau_band
+// of the group maximum, the top kListC by key.  Each member list holds its own
+// top keys in descending order, so the top kListC of the union are exact.
+// More than kSelCap band points (a flat or nearly flat radius) are merged by
+// popping the member lists, one list per thread (n <= blockDim.x).
+__device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__ L, int n, float tau_band,
+                                                 BlockList32* __restrict__ out, MergeScratch* S) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = nwaves();
+  float pm = -1.f;
+  uint32_t fl = 0;
+  for (int b = tid; b < n; b += blockDim.x) {
+    fl |= ld_agent(&L[b].flags);
+    if (ld_agent(&L[b].count) > 0) pm = fmaxf(pm, ld_agent(&L[b].pmax));
+  }
+  if (tid == 0) {
+    S->sflags = 0;
+    S->scount = 0;
+    S->stotal = 0;
+  }
+  const float pg = block_max_f32(pm, S->wf);  // its barriers order the initialisation above
+  if (fl) atomicOr(&S->sflags, fl);
+  const float theta = pg - pg * tau_band;
+  // one wave per member list that reaches the band
+  for (int i = wave; i < n; i += nw) {
+    const BlockList32* B = L + i;
+    const uint32_t cnt = ld_agent(&B->count);
+    if (cnt == 0 || !(ld_agent(&B->pmax) >= theta)) continue;  // uniform over the wave
+    const uint64_t k = lane < int(cnt) ? ld_agent(&B->keys[lane]) : 0;
+    const bool q = lane < int(cnt) && key_p(k) >= theta;
+    wave_append(q, k, &S->scount, S->buf, uint32_t(kSelCap));
+    // a member list cut inside the band: count the points it could not hold
+    const uint64_t last = __shfl(k, int(cnt) - 1);
+    if (lane == 0 && key_p(last) >= theta) {
+      const uint32_t tot = ld_agent(&B->total);
+      if (tot > cnt) atomicAdd(&S->stotal, tot - cnt);
+    }
+  }
+  __syncthreads();
+  const uint32_t nb = S->scount;
+  uint32_t cnt_out = 0;
+  if (nb <= uint32_t(kSelCap)) {
+    top_desc(S->buf, nb, S->sorted, uint32_t(kListC));
+    cnt_out = nb < uint32_t(kListC) ? nb : uint32_t(kListC);
+  } else {
+    uint32_t hp = 0, hc = 0;
+    uint64_t hk = 0;
+    if (tid < n) {
+      hc = ld_agent(&L[tid].count);
+      hk = hc > 0 ? ld_agent(&L[tid].keys[0]) : 0;
+      if (!(key_p(hk) >= theta)) hk = 0;
+    }
+    for (; cnt_out < uint32_t(kListC); ++cnt_out) {
+      const uint64_t g = block_max_u64(hk, S->wb);
+      if (g == 0) break;
+      if (tid == 0) S->sorted[cnt_out] = g;
+      if (hk == g) {  // keys are distinct: exactly one thread owns g
+        ++hp;
+        hk = hp < hc ? ld_agent(&L[tid].keys[hp]) : 0;
+        if (!(key_p(hk) >= theta)) hk = 0;
+      }
+    }
+    if (tid == 0) atomicOr(&S->sflags, uint32_t(kFlagFallback));
+    __syncthreads();
+  }
+  wave0_copy_keys(S->sorted, out->keys, cnt_out);
+  if (tid == 0) {
+    const uint32_t tot = nb + S->stotal;  // points in the band (the cut members' extra as an upper bound)
+    st_agent(&out->pmax, pg);
+    st_agent(&out->count, cnt_out);
+    st_agent(&out->total, tot);
+    st_agent(&out->flags, S->sflags);
+  }
+}
 
 // FP64: global best of the per-block records -> winner (coefficient = the
 // grid value of the FFT form).
@@ -395,6 +497,185 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
     cand->count = r;
     cand->flags = int32_t(S->sflags | uint32_t(kFlagFallback) | uint32_t(kFlagBandTruncated));
     cand->pmax32 = pg;
+  }
+}
+
+// ---------------------------------------------------------------- workgroup selection
+// LDS scratch of select_list: 512 bytes of counters, then kListCap gathered
+// keys and kListC sorted keys.
+constexpr size_t kListScratchBytes = 512 + sizeof(uint64_t) * (kListCap + kListC);
+
+// The flat indices of a workgroup's points in increasing order: rank i is
+// first + (i mod na) + (i / na) * step (na consecutive indices, then a jump).
+// Used to list the lowest indices of a workgroup whose values all tie.
+struct FlatOrder {
+  uint32_t first, na, step, count;
+  __device__ __forceinline__ uint32_t rank(uint32_t i) const { return first + (i % na) + (i / na) * step; }
+};
+
+// FP64 workgroup selection: best point (value, flat index, grid value) and the
+// runner-up value.  Within a thread the bins are visited in increasing index
+// order, so a strict comparison keeps the lowest index among equal values.
+template <int LOGN, typename T>
+__device__ __forceinline__ void select_best(const Cx<T> (&v)[pickE<T, LOGN>()], bool active, T sc, uint32_t fbase,
+                                            uint32_t fstride, int t, Best* wb, BlockBest64* o) {
+  constexpr int E = pickE<T, LOGN>();
+  constexpr int LE = ilog2c(E);
+  double y1 = -1.0, y2 = -1.0;
+  int i1 = 0;
+  T bx = T(0), by = T(0);
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int p = bitrev(q, LE);  // register holding bin t + TPR*q
+    const double y = double(fma(v[p].x, v[p].x, v[p].y * v[p].y));
+    if (y > y1) {
+      y2 = y1;
+      y1 = y;
+      i1 = p;
+      bx = v[p].x;
+      by = v[p].y;
+    } else {
+      y2 = fmax(y2, y);
+    }
+  }
+  Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
+  if (active) {
+    const double s2 = double(sc) * double(sc);
+    b.vx = double(bx * sc);
+    b.vy = double(by * sc);
+    b.f = fbase + fstride * uint32_t(t + Shape<LOGN, E>::TPR * bitrev(i1, LE));
+    // exact |.|^2 of the scaled grid value, as compared across radii
+    b.p1 = b.vx * b.vx + b.vy * b.vy;
+    b.p2 = fmin(y2 * s2, b.p1);
+  }
+  const Best r = block_best(b, wb);
+  if (threadIdx.x == 0) {
+    st_agent(&o->p1, r.p1);
+    st_agent(&o->p2, r.p2);
+    st_agent(&o->vx, r.vx);
+    st_agent(&o->vy, r.vy);
+    st_agent(&o->f, r.f);
+  }
+}
+
+// FP32 workgroup list: the workgroup's points within tau_band of its
+// maximum, best first, at most kListC of them (exact top by key).  Points
+// are compared unscaled (|y|^2 against the threshold divided by s_m^2) and
+// keys are formed only for points that pass.
+template <int LOGN>
+__device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LOGN>()], bool active, float sc,
+                                            uint32_t fbase, uint32_t fstride, int t, unsigned char* scratch,
+                                            float tau_band, const FlatOrder& ord, BlockList32* o) {
+  constexpr int E = pickE<float, LOGN>();
+  constexpr int TPR = Shape<LOGN, E>::TPR;
+  constexpr int LE = ilog2c(E);
+  const float s2 = sc * sc;
+  float Y[E];
+  float ym = 0.f;
+#pragma unroll
+  for (int p = 0; p < E; ++p) {
+    Y[p] = fmaf(v[p].x, v[p].x, v[p].y * v[p].y);
+    ym = fmaxf(ym, Y[p]);
+  }
+  float pm = active ? ym * s2 : -1.f;
+  pm = wave_max_f32(pm);
+  float* wmax = reinterpret_cast<float*>(scratch);               // [16]
+  float* wmin = reinterpret_cast<float*>(scratch + 64);          // [16]
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(scratch + 128);    // [1]
+  uint64_t* wbest = reinterpret_cast<uint64_t*>(scratch + 256);  // [16]
+  uint64_t* keys = reinterpret_cast<uint64_t*>(scratch + 512);   // [kListCap]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = nwaves();
+  if (lane == 0) wmax[wave] = pm;
+  if (tid == 0) *cnt = 0;
+  __syncthreads();
+  float pb = wmax[0];
+  for (int w = 1; w < nw; ++w) pb = fmaxf(pb, wmax[w]);
+
+  const float theta = pb - pb * tau_band;
+  // per-thread unscaled threshold; inactive threads never pass
+  const float ty = active ? (s2 > 0.f ? theta / s2 : 3.4e38f) : 3.4e38f;
+#pragma unroll
+  for (int p = 0; p < E; ++p) {
+    const bool q = Y[p] >= ty;
+    const uint64_t mask = __ballot(q);
+    if (mask) {
+      const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(cnt, uint32_t(__popcll(mask)));
+      base = __shfl(base, leader);
+      if (q) {
+        const uint32_t pos = base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
+        if (pos < uint32_t(kListCap)) keys[pos] = key32(Y[p] * s2, fbase + fstride * uint32_t(t + TPR * bitrev(p, LE)));
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t n = *cnt;
+
+  if (n <= uint32_t(kListCap)) {
+    // the sorted top keys are staged in LDS and stored by wave 0
+    uint64_t* sorted = reinterpret_cast<uint64_t*>(scratch + 512 + sizeof(uint64_t) * kListCap);
+    top_desc(keys, n, sorted, uint32_t(kListC));
+    wave0_copy_keys(sorted, o->keys, n < uint32_t(kListC) ? n : uint32_t(kListC));
+    if (tid == 0) {
+      st_agent(&o->pmax, pb);
+      st_agent(&o->count, n < uint32_t(kListC) ? n : uint32_t(kListC));
+      st_agent(&o->total, n);
+      st_agent(&o->flags, 0u);
+    }
+    return;
+  }
+
+  // More than kListCap points in the band.  If every value is exactly equal
+  // (e.g. the r = 0 ring) the best keys are the lowest flat indices;
+  // otherwise kListC rounds of exact workgroup argmax.
+  float pn = 3.4e38f;
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < E; ++p) pn = fminf(pn, Y[p] * s2);
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) pn = fminf(pn, __shfl_xor(pn, m));
+  if (lane == 0) wmin[wave] = pn;
+  __syncthreads();
+  float pbn = wmin[0];
+  for (int w = 1; w < nw; ++w) pbn = fminf(pbn, wmin[w]);
+  if (pb == pbn) {
+    const uint32_t c = ord.count < uint32_t(kListC) ? ord.count : uint32_t(kListC);
+    if (uint32_t(tid) < c) st_agent(&o->keys[tid], key32(pb, ord.rank(uint32_t(tid))));  // wave 0 (c <= 64)
+    if (tid == 0) {
+      st_agent(&o->pmax, pb);
+      st_agent(&o->count, c);
+      st_agent(&o->total, ord.count);
+      st_agent(&o->flags, uint32_t(kFlagFallback));
+    }
+    return;
+  }
+  uint32_t taken = 0;
+  uint32_t rounds = 0;
+  for (; rounds < uint32_t(kListC); ++rounds) {
+    uint64_t tb = 0;
+#pragma unroll
+    for (int p = 0; p < E; ++p) {
+      if (!((taken >> p) & 1u) && Y[p] >= ty) {
+        const uint64_t k = key32(Y[p] * s2, fbase + fstride * uint32_t(t + TPR * bitrev(p, LE)));
+        tb = k > tb ? k : tb;
+      }
+    }
+    const uint64_t b = block_max_u64(tb, wbest);
+    if (b == 0) break;
+    if (tid == 0) st_agent(&o->keys[rounds], b);
+#pragma unroll
+    for (int p = 0; p < E; ++p) {
+      if (Y[p] >= ty && key32(Y[p] * s2, fbase + fstride * uint32_t(t + TPR * bitrev(p, LE))) == b) taken |= 1u << p;
+    }
+  }
+  if (tid == 0) {
+    st_agent(&o->pmax, pb);
+    st_agent(&o->count, rounds);
+    st_agent(&o->total, n);
+    st_agent(&o->flags, uint32_t(kFlagFallback));
   }
 }
 

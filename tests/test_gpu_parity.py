@@ -2,7 +2,7 @@
 
 Small and medium sizes: every step free-running (indices bit-exact while the
 oracle's lead exceeds 1e-6, then a validity check of the near-tie choice) and
-every step replayed with the oracle's indices.  Full BASELINE-size workloads:
+every step replayed with the oracle's indices.  Full-size workloads:
 the first steps against the oracle plus identities that hold at any size.
 """
 import numpy as np
