@@ -73,6 +73,22 @@ __device__ __forceinline__ float block_max_f32(float v, float* wf) {
   return b;
 }
 
+// SUM: block sum, else block minimum; `w` is an LDS array of 16
+template <bool SUM>
+__device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v, uint32_t* w) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const uint32_t o = __shfl_xor(v, m);
+    v = SUM ? v + o : (o < v ? o : v);
+  }
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t r = w[0];
+  for (int i = 1; i < nwaves(); ++i) r = SUM ? r + w[i] : (w[i] < r ? w[i] : r);
+  __syncthreads();
+  return r;
+}
+
 __device__ __forceinline__ double block_sum_f64(double v, double* wd) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
@@ -208,11 +224,12 @@ struct MergeScratch {
   uint64_t buf[kSelCap];
   uint32_t cblk[kSelCap];
   uint64_t sorted[kListC];
+  uint64_t hcut;
   uint64_t wb[16];
   Best bb[16];
   float wf[16];
   double wd[16];
-  uint32_t scount, sblocks, sflags, stotal;
+  uint32_t scount, sblocks, sflags, stotal, sband;
   int last;
 };
 
@@ -239,9 +256,11 @@ __device__ __forceinline__ void merge_best_group(const BlockBest64* __restrict__
 // FP32: the lists of a group of workgroups (the workgroups of one radius)
 // merged into one list of the same form: every listed point within tau_band
 // of the group maximum, the top kListC by key.  Each member list holds its own
-// top keys in descending order, so the top kListC of the union are exact.
-// More than kSelCap band points (a flat or nearly flat radius) are merged by
-// popping the member lists, one list per thread (n <= blockDim.x).
+// top keys in descending order, so the top kListC of the union are exact, and
+// none of them is below the kListC-th largest member head (those heads alone
+// are kListC keys): only keys at or above it are gathered.  More than kSelCap
+// such keys are merged by popping the member lists, one list per thread
+// (n <= blockDim.x).
 __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__ L, int n, float tau_band,
                                                  BlockList32* __restrict__ out, MergeScratch* S) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -256,18 +275,37 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
     S->sflags = 0;
     S->scount = 0;
     S->stotal = 0;
+    S->sband = 0;
+    S->hcut = 0;
   }
   const float pg = block_max_f32(pm, S->wf);  // its barriers order the initialisation above
   if (fl) atomicOr(&S->sflags, fl);
   const float theta = pg - pg * tau_band;
-  // one wave per member list that reaches the band
+  // the kListC-th largest head among the members that reach the band (0 if fewer)
+  uint64_t hd = 0;
+  if (tid < n && ld_agent(&L[tid].count) > 0) {
+    hd = ld_agent(&L[tid].keys[0]);
+    if (!(key_p(hd) >= theta)) hd = 0;
+  }
+  if (tid < n) S->buf[tid] = hd;
+  __syncthreads();
+  if (hd) {
+    uint32_t rank = 0;
+    for (int i = 0; i < n; ++i) rank += S->buf[i] > hd ? 1u : 0u;
+    if (rank == uint32_t(kListC) - 1) S->hcut = hd;  // keys are distinct: one thread at most
+  }
+  __syncthreads();
+  const uint64_t hcut = S->hcut;
+  // one wave per member list that reaches the cut
   for (int i = wave; i < n; i += nw) {
     const BlockList32* B = L + i;
     const uint32_t cnt = ld_agent(&B->count);
     if (cnt == 0 || !(ld_agent(&B->pmax) >= theta)) continue;  // uniform over the wave
     const uint64_t k = lane < int(cnt) ? ld_agent(&B->keys[lane]) : 0;
-    const bool q = lane < int(cnt) && key_p(k) >= theta;
-    wave_append(q, k, &S->scount, S->buf, uint32_t(kSelCap));
+    const bool inband = lane < int(cnt) && key_p(k) >= theta;
+    const uint64_t bm = __ballot(inband);
+    if (lane == 0 && bm) atomicAdd(&S->sband, uint32_t(__popcll(bm)));
+    wave_append(inband && k >= hcut, k, &S->scount, S->buf, uint32_t(kSelCap));
     // a member list cut inside the band: count the points it could not hold
     const uint64_t last = __shfl(k, int(cnt) - 1);
     if (lane == 0 && key_p(last) >= theta) {
@@ -304,7 +342,7 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
   }
   wave0_copy_keys(S->sorted, out->keys, cnt_out);
   if (tid == 0) {
-    const uint32_t tot = nb + S->stotal;  // points in the band (the cut members' extra as an upper bound)
+    const uint32_t tot = S->sband + S->stotal;  // points in the band (cut members' extra as an upper bound)
     st_agent(&out->pmax, pg);
     st_agent(&out->count, cnt_out);
     st_agent(&out->total, tot);
@@ -628,8 +666,11 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
   }
 
   // More than kListCap points in the band.  If every value is exactly equal
-  // (e.g. the r = 0 ring) the best keys are the lowest flat indices;
-  // otherwise kListC rounds of exact workgroup argmax.
+  // (e.g. the r = 0 ring) the best keys are the lowest flat indices.
+  // Otherwise the top kListC keys are the top keys among the points whose P
+  // reaches t, the largest P with at least kListC band points at or above it
+  // (bisection on the bits of P >= 0); only if exact ties at t still leave
+  // more than kListCap such points, kListC rounds of exact workgroup argmax.
   float pn = 3.4e38f;
   if (active) {
 #pragma unroll
@@ -652,14 +693,64 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
     }
     return;
   }
+  {
+    // Y becomes P = Y s2 for the band points and 0 elsewhere (P >= 0: the
+    // order of P is the order of its bits)
+    uint32_t pmin = 0xffffffffu;
+#pragma unroll
+    for (int p = 0; p < E; ++p) {
+      const bool in = active && Y[p] >= ty;
+      Y[p] = in ? Y[p] * s2 : 0.f;
+      if (in) pmin = min(pmin, __float_as_uint(Y[p]));
+    }
+    uint32_t* wred = reinterpret_cast<uint32_t*>(wmin);
+    __syncthreads();  // every thread has read wmin above
+    uint32_t lo = block_reduce_u32<false>(pmin, wred);
+    uint32_t hi = __float_as_uint(pb);
+    while (lo < hi) {  // uniform: lo and hi come from block reductions
+      const uint32_t mid = lo + (hi - lo + 1) / 2;
+      const float fm = __uint_as_float(mid);
+      uint32_t c = 0;
+#pragma unroll
+      for (int p = 0; p < E; ++p) c += Y[p] >= fm ? 1u : 0u;
+      if (block_reduce_u32<true>(c, wred) >= uint32_t(kListC))
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const float fl = __uint_as_float(lo);  // > 0: excludes the points outside the band
+    if (tid == 0) *cnt = 0;
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < E; ++p) {
+      const bool q = Y[p] >= fl;
+      const uint64_t k = q ? key32(Y[p], fbase + fstride * uint32_t(t + TPR * bitrev(p, LE))) : 0;
+      wave_append(q, k, cnt, keys, uint32_t(kListCap));
+    }
+    __syncthreads();
+    const uint32_t n2 = *cnt;
+    if (n2 <= uint32_t(kListCap)) {
+      uint64_t* sorted = reinterpret_cast<uint64_t*>(scratch + 512 + sizeof(uint64_t) * kListCap);
+      top_desc(keys, n2, sorted, uint32_t(kListC));
+      const uint32_t c = n2 < uint32_t(kListC) ? n2 : uint32_t(kListC);
+      wave0_copy_keys(sorted, o->keys, c);
+      if (tid == 0) {
+        st_agent(&o->pmax, pb);
+        st_agent(&o->count, c);
+        st_agent(&o->total, n);
+        st_agent(&o->flags, uint32_t(kFlagFallback));
+      }
+      return;
+    }
+  }
   uint32_t taken = 0;
   uint32_t rounds = 0;
   for (; rounds < uint32_t(kListC); ++rounds) {
     uint64_t tb = 0;
 #pragma unroll
     for (int p = 0; p < E; ++p) {
-      if (!((taken >> p) & 1u) && Y[p] >= ty) {
-        const uint64_t k = key32(Y[p] * s2, fbase + fstride * uint32_t(t + TPR * bitrev(p, LE)));
+      if (!((taken >> p) & 1u) && Y[p] > 0.f) {
+        const uint64_t k = key32(Y[p], fbase + fstride * uint32_t(t + TPR * bitrev(p, LE)));
         tb = k > tb ? k : tb;
       }
     }
@@ -668,7 +759,7 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
     if (tid == 0) st_agent(&o->keys[rounds], b);
 #pragma unroll
     for (int p = 0; p < E; ++p) {
-      if (Y[p] >= ty && key32(Y[p] * s2, fbase + fstride * uint32_t(t + TPR * bitrev(p, LE))) == b) taken |= 1u << p;
+      if (Y[p] > 0.f && key32(Y[p], fbase + fstride * uint32_t(t + TPR * bitrev(p, LE))) == b) taken |= 1u << p;
     }
   }
   if (tid == 0) {
