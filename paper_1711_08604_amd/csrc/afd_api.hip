@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -43,6 +44,10 @@ enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3 }
 struct Layout {
   size_t radii, omega, tw, twf1, twf2, pw, pv, scale, g64, g32, c, xt, blocks, cand, partials, winner, epart,
       nonfinite, forced0, counters;
+  // truncated / pruned spectrum of the LDS-resident radius transforms
+  size_t pq, lsig, order;
+  // FP32 head keys of the workgroup (or per-radius) records
+  size_t heads;
   // radius transforms beyond the LDS
   size_t wl, wh, z, rrec, bcounters;
   size_t total;
@@ -68,7 +73,7 @@ struct Config {
   int chunk;    // radii per two-pass chunk
 };
 
-constexpr int kNumCounters = 4;  // radius, recheck, update, prepare
+constexpr int kNumCounters = 5;  // radius, recheck, update, prepare; FP32 fallback flag word
 
 afd_status validate(const afd_plan_desc* d, Config* cfg) {
   if (!d) return fail(AFD_E_INVALID, "desc is NULL");
@@ -137,6 +142,10 @@ Layout layout_of(const Config& c) {
   L.pw = take(real * size_t(c.M) * (c.big ? (size_t(1) << c.bg.l1) : size_t(c.geom.tpr)));
   L.pv = take(real * size_t(c.M) * (c.big ? (size_t(1) << c.bg.l2) : size_t(c.geom.E)));
   L.scale = take(real * size_t(c.M));
+  L.pq = take(c.big ? 0 : real * size_t(c.M) * c.geom.E);
+  L.lsig = take(c.big ? 0 : 4 * size_t(c.M));
+  L.order = take(c.big ? 0 : 4 * size_t(c.M));
+  L.heads = take(c.fp64 ? 0 : 8 * size_t(c.big ? c.M : c.nblocks));
   L.g64 = take(16 * size_t(c.N));
   L.g32 = take(c.fp64 ? 0 : 8 * size_t(c.N));
   L.c = take(2 * real * size_t(c.N));
@@ -226,6 +235,22 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     const long double rN = powl(r, (long double)N);
     sc[m] = (double)(sqrtl((1.0L - r) * (1.0L + r)) / ((long double)N * (1.0L - rN)));
   }
+  // LDS path: r^((TPR/R0) v) for the pruned start, and the significant
+  // spectrum length of each radius (weights below 2^-40 single / 2^-60 double
+  // precision of the largest term, summed, are dropped)
+  std::vector<double> pq;
+  std::vector<int32_t> lsig;
+  if (!c.big) {
+    const int r0 = radius_first_radix(c.logn, c.fp64);
+    const long double step = (long double)(tpr / (r0 > 0 ? r0 : 1));
+    pq.resize(size_t(M) * E);
+    lsig.resize(M);
+    for (int m = 0; m < M; ++m) {
+      const long double r = radii[m];
+      for (int v = 0; v < E; ++v) pq[size_t(m) * E + v] = v == 0 ? 1.0 : (double)powl(r, step * (long double)v);
+      lsig[m] = significant_length(radii[m], c.fp64 ? 60 : 40, N);
+    }
+  }
   // two-pass path: e^{2 pi i e/N} = wh[e >> sw] * wl[e mod 2^sw]
   std::vector<double> wl, wh;
   if (c.big) {
@@ -255,6 +280,7 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     if (e == hipSuccess) e = up(p->L.scale, sc.data(), sc.size() * 8);
     if (e == hipSuccess && c.big) e = up(p->L.wl, wl.data(), wl.size() * 8);
     if (e == hipSuccess && c.big) e = up(p->L.wh, wh.data(), wh.size() * 8);
+    if (e == hipSuccess && !c.big) e = up(p->L.pq, pq.data(), pq.size() * 8);
   } else {
     auto f32 = [](const std::vector<double>& v) {
       std::vector<float> o(v.size());
@@ -262,7 +288,8 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
       return o;
     };
     const std::vector<float> tw32 = f32(tw), pw32 = f32(pw), pv32 = f32(pv), sc32 = f32(sc);
-    const std::vector<float> twf1_32 = f32(twf1), twf2_32 = f32(twf2), wl32 = f32(wl), wh32 = f32(wh);
+    const std::vector<float> twf1_32 = f32(twf1), twf2_32 = f32(twf2), wl32 = f32(wl), wh32 = f32(wh),
+                             pq32 = f32(pq);
     if (e == hipSuccess) e = up(p->L.tw, tw32.data(), tw32.size() * 4);
     if (e == hipSuccess) e = up(p->L.twf1, twf1_32.data(), twf1_32.size() * 4);
     if (e == hipSuccess) e = up(p->L.twf2, twf2_32.data(), twf2_32.size() * 4);
@@ -271,6 +298,15 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     if (e == hipSuccess) e = up(p->L.scale, sc32.data(), sc32.size() * 4);
     if (e == hipSuccess && c.big) e = up(p->L.wl, wl32.data(), wl32.size() * 4);
     if (e == hipSuccess && c.big) e = up(p->L.wh, wh32.data(), wh32.size() * 4);
+    if (e == hipSuccess && !c.big) e = up(p->L.pq, pq32.data(), pq32.size() * 4);
+  }
+  if (e == hipSuccess && !c.big) e = up(p->L.lsig, lsig.data(), lsig.size() * 4);
+  if (!c.big) {
+    // workgroup order: longest significant spectrum first (ties by index)
+    std::vector<int32_t> order(M);
+    for (int m = 0; m < M; ++m) order[m] = m;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return lsig[a] > lsig[b]; });
+    if (e == hipSuccess) e = up(p->L.order, order.data(), order.size() * 4);
   }
   const int32_t f0[2] = {p->zero_m < 0 ? 0 : p->zero_m, 0};
   if (e == hipSuccess) e = up(p->L.forced0, f0, sizeof(f0));
@@ -465,6 +501,9 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.c = cspec;
   rp.pw = p->at<void>(p->L.pw);
   rp.pv = p->at<void>(p->L.pv);
+  rp.pq = p->at<void>(p->L.pq);
+  rp.lsig = p->at<int>(p->L.lsig);
+  rp.order = p->at<int>(p->L.order);
   rp.scale = p->at<void>(p->L.scale);
   rp.tw = p->at<void>(p->L.tw);
   rp.M = c.M;
@@ -473,6 +512,8 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.recheck_k = p->recheck_k;
   rp.out = p->at<void>(p->L.blocks);
   rp.counter = counters + 0;
+  rp.heads = p->at<uint64_t>(p->L.heads);
+  rp.flagword = counters + 4;
   rp.cand = cand;
   rp.winner = win;
 
@@ -495,6 +536,8 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     bp.rrec = p->at<void>(p->L.rrec);
     bp.counter_r = p->at<unsigned int>(p->L.bcounters);
     bp.counter_g = p->at<unsigned int>(p->L.bcounters) + c.chunk;
+    bp.heads = p->at<uint64_t>(p->L.heads);
+    bp.flagword = counters + 4;
     bp.cand = cand;
     bp.winner = win;
   }

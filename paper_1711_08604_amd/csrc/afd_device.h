@@ -49,6 +49,9 @@ __device__ __forceinline__ Cx<T> cscale(Cx<T> a, T s) { return {a.x * s, a.y * s
 // ---------------------------------------------------------------- shape
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
 
+// LDS exchange padding: one pad element every 2^kPadShift elements
+constexpr int kPadShift = 4;
+
 // Pass structure of a length 2^LOGN transform with E values per thread: an
 // optional first pass of radix 2^(LOGN mod log2 E), then passes of radix E.
 template <int LOGN, int E>
@@ -74,7 +77,7 @@ struct Shape {
   }
   __host__ __device__ static constexpr int twsize() { return twoff(NP); }
   // LDS elements for one transform (one pad element every 16)
-  static constexpr int LDS_ELEMS = N + (N >> 4) + 1;
+  static constexpr int LDS_ELEMS = N + (N >> kPadShift) + 1;
 };
 
 __host__ __device__ constexpr int bitrev(int v, int bits) {
@@ -83,7 +86,7 @@ __host__ __device__ constexpr int bitrev(int v, int bits) {
   return r;
 }
 
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> kPadShift); }
 
 // ---------------------------------------------------------------- constant twiddles
 // cos(2 pi q / 64), q = 0..16 (correctly rounded); the rest by symmetry.
@@ -235,7 +238,7 @@ __device__ __forceinline__ void pass_job(Cx<T> (&v)[E], int t, const Cx<T>* __re
       v[U + r * J] = cmul(v[U + r * J], w);
       // double precision: keep at most four twiddles in flight so the
       // 1024-thread transforms stay inside their 128-register budget
-      if (sizeof(T) == 8 && (r % 4) == 3) __builtin_amdgcn_sched_barrier(0);
+      if ((sizeof(T) == 8 && (r % 4) == 3) || (sizeof(T) == 4 && (r % 8) == 7)) __builtin_amdgcn_sched_barrier(0);
     }
   }
   Dit<R, SIGN, U, J, T>::run(v);
@@ -254,12 +257,12 @@ __device__ __forceinline__ void pass_compute(Cx<T> (&v)[E], int t, const Cx<T>* 
   pass_jobs<T, LOGN, E, P, SIGN>(v, t, tw, std::make_integer_sequence<int, E / S::radix(P)>{});
 }
 
-// LDS addressing.  Element i lives at lds_pad(i) = i + (i >> 4).  For every
-// access pattern below the index is base + c with c a compile-time constant
-// and (base mod 16) + (c mod 16) < 16, so lds_pad(base + c) = lds_pad(base) +
-// c + (c >> 4): the padded base is computed once per job and the rest are
-// immediate offsets.
-__host__ __device__ constexpr int pad_off(int c) { return c + (c >> 4); }
+// LDS addressing.  Element i lives at lds_pad(i) = i + (i >> kPadShift).  For
+// every access pattern below the index is base + c with c a compile-time
+// constant and (base mod 2^kPadShift) + (c mod 2^kPadShift) < 2^kPadShift, so
+// lds_pad(base + c) = lds_pad(base) + pad_off(c): the padded base is computed
+// once per job and the rest are immediate offsets.
+__host__ __device__ constexpr int pad_off(int c) { return c + (c >> kPadShift); }
 
 // Padded LDS index of the first output (q = 0) of job u after pass P; output
 // q of the job sits pad_off(q * Ns) further on.  (Stockham destination
@@ -331,10 +334,14 @@ __device__ __forceinline__ void lds_read_part(Cx<T> (&v)[E], int t, const T* lds
 // complex elements, or that many reals when SPLIT, which exchanges the real
 // parts and then the imaginary parts through half the space).  Every thread
 // of the block must call this (block-wide barriers).
-template <typename T, int LOGN, int E, int SIGN, bool SPLIT, int P = 0>
+//
+// FIRST > 0 starts at pass FIRST with the registers already holding that
+// pass's inputs (no exchange before it); see the pruned start of the radius
+// transform.
+template <typename T, int LOGN, int E, int SIGN, bool SPLIT, int P = 0, int FIRST = 0>
 __device__ __forceinline__ void fft_regs(Cx<T> (&v)[E], int t, void* lds, const Cx<T>* __restrict__ tw) {
   using S = Shape<LOGN, E>;
-  if constexpr (P > 0) {
+  if constexpr (P > FIRST) {
     if constexpr (SPLIT) {
       T* l = reinterpret_cast<T*>(lds);
       lds_write_part<T, LOGN, E, P - 1, 0>(v, t, l);
@@ -354,7 +361,7 @@ __device__ __forceinline__ void fft_regs(Cx<T> (&v)[E], int t, void* lds, const 
     }
   }
   pass_compute<T, LOGN, E, P, SIGN>(v, t, tw);
-  if constexpr (P + 1 < S::NP) fft_regs<T, LOGN, E, SIGN, SPLIT, P + 1>(v, t, lds, tw);
+  if constexpr (P + 1 < S::NP) fft_regs<T, LOGN, E, SIGN, SPLIT, P + 1, FIRST>(v, t, lds, tw);
 }
 
 // Output bin held by register p after fft_regs.

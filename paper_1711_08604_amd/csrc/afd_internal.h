@@ -69,6 +69,9 @@ struct RadiusParams {
   const void* c;      // spectrum, N complex (T)
   const void* pw;     // [M][TPR]  r_m^t
   const void* pv;     // [M][E]    r_m^(TPR v)
+  const void* pq;     // [M][E]    r_m^((TPR/R0) v), R0 the radix of the first pass
+  const int* lsig;    // [M]       significant spectrum length: the terms l >= lsig[m] are dropped
+  const int* order;   // [M]       radius of workgroup b when one radius per workgroup (lsig descending)
   const void* scale;  // [M]       sqrt(1-r^2) / (N (1 - r^N))
   const void* tw;     // Stockham twiddles of the inverse transform
   int M;
@@ -76,6 +79,8 @@ struct RadiusParams {
   float tau_band;     // FP32 lists: relative band below the workgroup maximum
   int recheck_k;      // FP32: minimum short-list length
   void* out;          // BlockBest64[blocks] or BlockList32[blocks]
+  uint64_t* heads;    // FP32: [blocks] head key (best point) of each workgroup list
+  unsigned int* flagword;  // FP32: fallback flag of the step (zero between steps)
   unsigned int* counter;  // last-workgroup counter (zero between launches)
   CandList* cand;     // FP32 short-list (written by the last workgroup)
   Winner* winner;     // FP64 winner (written by the last workgroup)
@@ -100,6 +105,8 @@ struct BigParams {
   int recheck_k;
   void* blocks;       // [chunk][G] per-workgroup records (BlockList32 or BlockBest64)
   void* rrec;         // [M] per-radius records (same type)
+  uint64_t* heads;    // FP32: [M] head key of each per-radius record
+  unsigned int* flagword;  // FP32: fallback flag of the step (zero between steps)
   unsigned int* counter_r;  // [chunk] workgroup arrivals per radius (zero between launches)
   unsigned int* counter_g;  // radius arrivals over the step's chunks (zero between steps)
   CandList* cand;
@@ -159,6 +166,12 @@ struct FwdPlan {
 FwdPlan fwd_plan(int logn, bool fp64);
 
 int radius_lds_bytes(int logn, bool fp64, int rpb);
+// Radix of the first Stockham pass of the LDS-resident radius transform.
+int radius_first_radix(int logn, bool fp64);
+// Significant spectrum length of radius r: the smallest L with
+// r^L / (1 - r) <= 2^-bits (so the dropped weights sum to at most 2^-bits),
+// at least 1 and at most n.
+int significant_length(double r, int bits, int64_t n);
 int radius_threads_of(int logn, bool fp64);
 int update_blocks(int N);
 int recheck_chunks(int N);

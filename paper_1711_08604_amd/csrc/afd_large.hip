@@ -115,7 +115,7 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_B)) void k_big_rows(BigParams p)
     const FlatOrder ord{uint32_t(m) * uint32_t(B::N) + uint32_t(blockIdx.x) * uint32_t(B::RB), uint32_t(B::RB),
                         uint32_t(B::N1), uint32_t(B::RB) * uint32_t(B::N2)};
     select_list<B::L2>(v, true, sc, fbase, uint32_t(B::N1), t, scratch, p.tau_band, ord,
-                       reinterpret_cast<BlockList32*>(p.blocks) + rec);
+                       reinterpret_cast<BlockList32*>(p.blocks) + rec, nullptr, p.flagword);
   } else {
     select_best<B::L2, T>(v, true, sc, fbase, uint32_t(B::N1), t, reinterpret_cast<Best*>(scratch),
                           reinterpret_cast<BlockBest64*>(p.blocks) + rec);
@@ -125,14 +125,15 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_B)) void k_big_rows(BigParams p)
   MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
   if constexpr (LIST) {
     merge_list_group(reinterpret_cast<const BlockList32*>(p.blocks) + ml * B::G, B::G, p.tau_band,
-                     reinterpret_cast<BlockList32*>(p.rrec) + m, Sm);
+                     reinterpret_cast<BlockList32*>(p.rrec) + m, p.heads + m, Sm);
   } else {
     merge_best_group(reinterpret_cast<const BlockBest64*>(p.blocks) + ml * B::G, B::G,
                      reinterpret_cast<BlockBest64*>(p.rrec) + m, Sm);
   }
   if (!last_arrival(p.counter_g, unsigned(p.M), &s_last)) return;
   if constexpr (LIST) {
-    select32_tail(reinterpret_cast<const BlockList32*>(p.rrec), p.M, p.recheck_k, p.tau_band, p.cand, Sm);
+    select32_tail(reinterpret_cast<const BlockList32*>(p.rrec), p.heads, p.M, p.recheck_k, p.tau_band, p.flagword,
+                  p.cand, Sm);
   } else {
     merge64_tail(reinterpret_cast<const BlockBest64*>(p.rrec), p.M, B::N, LOGN, p.winner, Sm);
   }

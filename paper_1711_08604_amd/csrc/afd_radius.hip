@@ -45,7 +45,9 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
   __shared__ int s_last;
   const int tid = threadIdx.x;
   const int rl = tid / TPR, t = tid - rl * TPR;
-  const int m = blockIdx.x * prm.rpb + rl;
+  // one radius per workgroup: the radii in the order of decreasing
+  // significant spectrum length, so the longest transforms start first
+  const int m = prm.rpb == 1 ? prm.order[blockIdx.x] : int(blockIdx.x) * prm.rpb + rl;
   const bool active = m < prm.M;
   const int mm = active ? m : prm.M - 1;
   constexpr size_t region = fft_region_bytes<T, LOGN, SPLIT>();
@@ -58,27 +60,60 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
   const T* __restrict__ scale = reinterpret_cast<const T*>(prm.scale);
   const Cx<T>* __restrict__ tw = reinterpret_cast<const Cx<T>*>(prm.tw);
 
-  // weighted spectrum f(l) = r_m^l c_l, l = t + TPR i, r^l = r^t r^(TPR i)
-  const T rt = pw[size_t(mm) * TPR + t];
+  // weighted spectrum f(l) = r_m^l c_l for l < L; the weights of the later
+  // terms sum to less than 2^-40 (single) / 2^-60 (double precision) and they
+  // are dropped
+  const int L = prm.lsig[mm];
+  constexpr int R0 = S::radix(0);
   Cx<T> v[E];
+  // With L <= N/R0 the first pass (radix R0, inputs x[job + r N/R0]) only
+  // replicates x[job]: thread t's inputs of the second pass are then
+  // x[t/R0 + (TPR/R0) i], loaded directly, and the first pass and its
+  // exchange are skipped.  Uniform over the workgroup (one radius).
+  bool pruned = false;
+  if constexpr (S::NP >= 2 && R0 <= TPR) pruned = prm.rpb == 1 && L <= N / R0;
+  if (pruned) {
+    if constexpr (S::NP >= 2 && R0 <= TPR) {
+      const int a = t / R0;  // r^l = r^a r^((TPR/R0) i)
+      const T ra = pw[size_t(mm) * TPR + a];
+      const T* __restrict__ pq = reinterpret_cast<const T*>(prm.pq) + size_t(mm) * E;
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const Cx<T> x = c[t + TPR * i];
-    const T w = rt * pv[size_t(mm) * E + i];
-    v[i] = {x.x * w, x.y * w};
-    // double precision: bound the loads in flight (128-register budget)
-    if (sizeof(T) == 8 && (i % 4) == 3) __builtin_amdgcn_sched_barrier(0);
+      for (int i = 0; i < E; ++i) {
+        const int l = a + (TPR / R0) * i;
+        v[i] = {T(0), T(0)};
+        if ((TPR / R0) * i < L && l < L) {
+          const Cx<T> x = c[l];
+          const T w = ra * pq[i];
+          v[i] = {x.x * w, x.y * w};
+        }
+      }
+      fft_regs<T, LOGN, E, +1, SPLIT, 1, 1>(v, t, lds_r, tw);
+    }
+  } else {
+    const T rt = pw[size_t(mm) * TPR + t];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int l = t + TPR * i;
+      v[i] = {T(0), T(0)};
+      if (TPR * i < L && l < L) {
+        const Cx<T> x = c[l];
+        const T w = rt * pv[size_t(mm) * E + i];
+        v[i] = {x.x * w, x.y * w};
+      }
+      // double precision: bound the loads in flight (128-register budget)
+      if (sizeof(T) == 8 && (i % 4) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    fft_regs<T, LOGN, E, +1, SPLIT>(v, t, lds_r, tw);
   }
-  fft_regs<T, LOGN, E, +1, SPLIT>(v, t, lds_r, tw);
 
   const T sc = scale[mm];
   const uint32_t fbase = uint32_t(mm) * uint32_t(N);
   if constexpr (LIST) {
-    const uint32_t r0 = uint32_t(blockIdx.x) * uint32_t(prm.rpb);
+    const uint32_t r0 = prm.rpb == 1 ? uint32_t(mm) : uint32_t(blockIdx.x) * uint32_t(prm.rpb);
     const uint32_t ract = uint32_t(prm.M) - r0 < uint32_t(prm.rpb) ? uint32_t(prm.M) - r0 : uint32_t(prm.rpb);
     const FlatOrder ord{r0 * uint32_t(N), ract * uint32_t(N), 0u, ract * uint32_t(N)};
     select_list<LOGN>(v, active, sc, fbase, 1u, t, scratch, prm.tau_band, ord,
-                      reinterpret_cast<BlockList32*>(prm.out) + blockIdx.x);
+                      reinterpret_cast<BlockList32*>(prm.out) + blockIdx.x, prm.heads + blockIdx.x, prm.flagword);
   } else {
     select_best<LOGN, T>(v, active, sc, fbase, 1u, t, reinterpret_cast<Best*>(scratch),
                          reinterpret_cast<BlockBest64*>(prm.out) + blockIdx.x);
@@ -87,8 +122,8 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
   if (!last_workgroup(prm.counter, &s_last)) return;
   MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
   if constexpr (LIST) {
-    select32_tail(reinterpret_cast<const BlockList32*>(prm.out), int(gridDim.x), prm.recheck_k, prm.tau_band,
-                  prm.cand, Sm);
+    select32_tail(reinterpret_cast<const BlockList32*>(prm.out), prm.heads, int(gridDim.x), prm.recheck_k,
+                  prm.tau_band, prm.flagword, prm.cand, Sm);
   } else {
     merge64_tail(reinterpret_cast<const BlockBest64*>(prm.out), int(gridDim.x), N, LOGN, prm.winner, Sm);
   }
@@ -107,6 +142,27 @@ int radius_lds_bytes(int logn, bool fp64, int rpb) {
     default:
       return 0;
   }
+}
+
+int radius_first_radix(int logn, bool fp64) {
+  switch (logn) {
+#define X(L) \
+  case L:    \
+    return fp64 ? Shape<L, pickE<double, L>()>::radix(0) : Shape<L, pickE<float, L>()>::radix(0);
+    AFD_LDS_LOGN_CASES(X)
+#undef X
+    default:
+      return 0;
+  }
+}
+
+int significant_length(double r, int bits, int64_t n) {
+  if (!(r > 0.0)) return 1;
+  // r^L / (1 - r) <= 2^-bits  <=>  L >= (bits ln 2 + ln(1/(1 - r))) / (-ln r)
+  const long double need = ((long double)bits * logl(2.0L) - logl(1.0L - (long double)r)) / -logl((long double)r);
+  if (!(need < (long double)n)) return int(n);
+  const long double L = ceill(need);
+  return L < 1.0L ? 1 : int(L);
 }
 
 int radius_threads_of(int logn, bool fp64) {

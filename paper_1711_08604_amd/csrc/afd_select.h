@@ -262,7 +262,7 @@ __device__ __forceinline__ void merge_best_group(const BlockBest64* __restrict__
 // such keys are merged by popping the member lists, one list per thread
 // (n <= blockDim.x).
 __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__ L, int n, float tau_band,
-                                                 BlockList32* __restrict__ out, MergeScratch* S) {
+                                                 BlockList32* __restrict__ out, uint64_t* head, MergeScratch* S) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = nwaves();
   float pm = -1.f;
@@ -347,6 +347,7 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
     st_agent(&out->count, cnt_out);
     st_agent(&out->total, tot);
     st_agent(&out->flags, S->sflags);
+    if (head) st_agent(head, cnt_out > 0 ? S->sorted[0] : uint64_t(0));
   }
 }
 
@@ -379,32 +380,47 @@ __device__ __forceinline__ void merge64_tail(const BlockBest64* __restrict__ blo
 
 // FP32: short-list for the double re-check.  Every listed point within
 // tau_band of the FP32 maximum, sorted by key and cut at kKMax; if that is
-// fewer than recheck_k points, the best points of the next-best blocks
-// (maxima below the band) are appended until it is not.  A flat grid (more
+// fewer than recheck_k points, the head keys (best points) of the best blocks
+// below the band are appended until it is not.  Each block's head key is in
+// the dense array `heads` (0: no finite point), so one coalesced pass finds
+// the maximum, the band blocks and the top-up candidates.  A flat grid (more
 // band points or band blocks than the gather holds) falls back to an exact
-// pop-merge of the sorted per-block lists.
-__device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ lists, int nb, int recheck_k,
-                                              float tau_band, CandList* __restrict__ cand, MergeScratch* S) {
+// pop-merge of the sorted per-block lists.  `flagword` collects the blocks'
+// fallback flag for the step; it is read and cleared here.
+__device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ lists,
+                                              const uint64_t* __restrict__ heads, int nb, int recheck_k,
+                                              float tau_band, unsigned int* flagword, CandList* __restrict__ cand,
+                                              MergeScratch* S) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = nwaves();
-  float pm = -1.f;
-  uint32_t fl = 0;
-  for (int b = tid; b < nb; b += blockDim.x) {
-    fl |= ld_agent(&lists[b].flags);
-    if (ld_agent(&lists[b].count) > 0) pm = fmaxf(pm, ld_agent(&lists[b].pmax));
+  constexpr int HC = 8;  // head keys cached per thread
+  uint64_t hk[HC];
+  uint64_t mx = 0;
+#pragma unroll
+  for (int i = 0; i < HC; ++i) {
+    const int b = tid + i * int(blockDim.x);
+    hk[i] = b < nb ? ld_agent(heads + b) : 0;
+    mx = hk[i] > mx ? hk[i] : mx;
+  }
+  const bool spill = nb > HC * int(blockDim.x);
+  if (spill) {
+    for (int b = tid + HC * int(blockDim.x); b < nb; b += blockDim.x) {
+      const uint64_t k = ld_agent(heads + b);
+      mx = k > mx ? k : mx;
+    }
   }
   if (tid == 0) {
-    S->sflags = 0;
+    S->sflags = ld_agent(flagword) & uint32_t(kFlagFallback);
+    st_agent(flagword, 0u);
     S->scount = 0;
     S->sblocks = 0;
   }
-  const float pg = block_max_f32(pm, S->wf);  // its barriers order the initialisation above
-  if (fl) atomicOr(&S->sflags, fl & uint32_t(kFlagFallback));
+  const uint64_t gk = block_max_u64(mx, S->wb);  // its barriers order the initialisation above
+  const float pg = gk ? key_p(gk) : -1.f;
   const float theta = pg - pg * tau_band;
-  // blocks whose maximum reaches the band
-  for (int b0 = 0; b0 < nb; b0 += blockDim.x) {
-    const int b = b0 + tid;
-    const bool q = b < nb && ld_agent(&lists[b].count) > 0 && ld_agent(&lists[b].pmax) >= theta;
+  // blocks whose head reaches the band
+  auto note_band = [&](int b, uint64_t k) {
+    const bool q = b < nb && k != 0 && key_p(k) >= theta;
     const uint64_t mask = __ballot(q);
     if (mask) {
       const int leader = __ffsll(static_cast<long long>(mask)) - 1;
@@ -415,6 +431,14 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
         const uint32_t pos = base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
         if (pos < uint32_t(kSelCap)) S->cblk[pos] = uint32_t(b);
       }
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < HC; ++i) note_band(tid + i * int(blockDim.x), hk[i]);
+  if (spill) {
+    for (int b0 = HC * int(blockDim.x); b0 < nb; b0 += blockDim.x) {
+      const int b = b0 + tid;
+      note_band(b, b < nb ? ld_agent(heads + b) : 0);
     }
   }
   __syncthreads();
@@ -438,40 +462,54 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
     uint32_t keff = band < uint32_t(kKMax) ? band : uint32_t(kKMax);
     if (band > uint32_t(kKMax) && tid == 0) atomicOr(&S->sflags, uint32_t(kFlagBandTruncated));
     if (keff < uint32_t(recheck_k)) {
-      // top up with the maxima of the blocks below the band; each thread keeps
-      // the heads of its blocks in registers (re-read for more than 16 blocks)
-      constexpr int HC = 16;
-      uint64_t head[HC];
-      uint32_t popped = 0;
-#pragma unroll
-      for (int i = 0; i < HC; ++i) {
-        const int b = tid + i * int(blockDim.x);
-        head[i] = (b < nb && ld_agent(&lists[b].count) > 0 && ld_agent(&lists[b].pmax) < theta) ? ld_agent(&lists[b].keys[0]) : 0;
-      }
-      const bool spill = nb > HC * int(blockDim.x);
-      uint32_t need = uint32_t(recheck_k) - keff;
-      uint64_t last_taken = ~uint64_t(0);
-      for (uint32_t r = 0; r < need; ++r) {
-        uint64_t tb = 0;
+      const uint32_t need = uint32_t(recheck_k) - keff;  // <= 63
+      if (!spill) {
+        // each wave: the top `need` heads below the band among its lanes, by
+        // rounds of a wave maximum (no workgroup barrier) ...
 #pragma unroll
         for (int i = 0; i < HC; ++i)
-          if (!((popped >> i) & 1u) && head[i] > tb) tb = head[i];
-        if (spill) {
-          for (int b = tid + HC * int(blockDim.x); b < nb; b += blockDim.x) {
-            if (ld_agent(&lists[b].count) > 0 && ld_agent(&lists[b].pmax) < theta) {
-              const uint64_t k = ld_agent(&lists[b].keys[0]);
-              if (k < last_taken && k > tb) tb = k;
-            }
+          if (hk[i] == 0 || key_p(hk[i]) >= theta) hk[i] = 0;
+        uint64_t* wl = S->buf;  // free after top_desc: [nw][need]
+        for (uint32_t r = 0; r < need; ++r) {
+          uint64_t lm = 0;
+#pragma unroll
+          for (int i = 0; i < HC; ++i) lm = hk[i] > lm ? hk[i] : lm;
+          const uint64_t w = wave_max_u64(lm);
+          if (lane == 0) wl[uint32_t(wave) * need + r] = w;
+#pragma unroll
+          for (int i = 0; i < HC; ++i)
+            if (hk[i] == w) hk[i] = 0;  // keys are distinct: one lane owns w
+        }
+        __syncthreads();
+        // ... then the top `need` of the waves' candidates by rank
+        const uint32_t nc = uint32_t(nw) * need;
+        for (uint32_t i = tid; i < nc; i += blockDim.x) {
+          const uint64_t k = wl[i];
+          if (k) {
+            uint32_t rank = 0;
+            for (uint32_t j = 0; j < nc; ++j) rank += wl[j] > k ? 1u : 0u;
+            if (rank < need) cand->keys[keff + rank] = k;
           }
         }
-        const uint64_t g = block_max_u64(tb, S->wb);
-        if (g == 0) break;
-        if (tid == 0) cand->keys[keff] = g;
-        ++keff;
-#pragma unroll
-        for (int i = 0; i < HC; ++i)
-          if (head[i] == g) popped |= 1u << i;
-        last_taken = g;  // keys are distinct: later rounds take strictly smaller keys
+        uint32_t nz = 0;
+        for (uint32_t j = tid; j < nc; j += blockDim.x) nz += wl[j] ? 1u : 0u;
+        nz = block_reduce_u32<true>(nz, reinterpret_cast<uint32_t*>(S->wf));
+        keff += nz < need ? nz : need;
+      } else {
+        // many blocks: rounds of a workgroup maximum over all heads below the band
+        uint64_t last_taken = ~uint64_t(0);
+        for (uint32_t r = 0; r < need; ++r) {
+          uint64_t tb = 0;
+          for (int b = tid; b < nb; b += blockDim.x) {
+            const uint64_t k = ld_agent(heads + b);
+            if (k != 0 && key_p(k) < theta && k < last_taken && k > tb) tb = k;
+          }
+          const uint64_t g = block_max_u64(tb, S->wb);
+          if (g == 0) break;
+          if (tid == 0) cand->keys[keff] = g;
+          ++keff;
+          last_taken = g;
+        }
       }
     }
     __syncthreads();
@@ -483,58 +521,60 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
     return;
   }
 
-  // Exact fallback (flat grids only): pop-merge of the sorted per-block
-  // lists.  Each thread keeps the head key and position of up to HC of its
-  // lists in registers; lists beyond that are rescanned each round.
-  constexpr int HC = 16;
-  uint64_t hk[HC];
-  uint32_t hp[HC];
+  {
+    // Exact fallback (flat grids only): pop-merge of the sorted per-block
+    // lists.  Each thread keeps the head key and position of up to HC of its
+    // lists in registers; lists beyond that are rescanned each round.
+    constexpr int HC = 16;
+    uint64_t hk[HC];
+    uint32_t hp[HC];
 #pragma unroll
-  for (int i = 0; i < HC; ++i) {
-    const int b = tid + i * int(blockDim.x);
-    hp[i] = 0;
-    hk[i] = (b < nb && ld_agent(&lists[b].count) > 0) ? ld_agent(&lists[b].keys[0]) : 0;
-  }
-  const bool spill = nb > HC * int(blockDim.x);
-  const int want = recheck_k > kListC ? recheck_k : kListC;
-  uint64_t last_taken = ~uint64_t(0);
-  int r = 0;
-  for (; r < want; ++r) {
-    uint64_t tb = 0;
+    for (int i = 0; i < HC; ++i) {
+      const int b = tid + i * int(blockDim.x);
+      hp[i] = 0;
+      hk[i] = (b < nb && ld_agent(&lists[b].count) > 0) ? ld_agent(&lists[b].keys[0]) : 0;
+    }
+    const bool spill = nb > HC * int(blockDim.x);
+    const int want = recheck_k > kListC ? recheck_k : kListC;
+    uint64_t last_taken = ~uint64_t(0);
+    int r = 0;
+    for (; r < want; ++r) {
+      uint64_t tb = 0;
 #pragma unroll
-    for (int i = 0; i < HC; ++i) tb = hk[i] > tb ? hk[i] : tb;
-    if (spill) {
-      for (int b = tid + HC * int(blockDim.x); b < nb; b += blockDim.x) {
-        const uint32_t cnt = ld_agent(&lists[b].count);
-        for (uint32_t q = 0; q < cnt; ++q) {
-          const uint64_t k = ld_agent(&lists[b].keys[q]);
-          if (k < last_taken) {
-            if (k > tb) tb = k;
-            break;
+      for (int i = 0; i < HC; ++i) tb = hk[i] > tb ? hk[i] : tb;
+      if (spill) {
+        for (int b = tid + HC * int(blockDim.x); b < nb; b += blockDim.x) {
+          const uint32_t cnt = ld_agent(&lists[b].count);
+          for (uint32_t q = 0; q < cnt; ++q) {
+            const uint64_t k = ld_agent(&lists[b].keys[q]);
+            if (k < last_taken) {
+              if (k > tb) tb = k;
+              break;
+            }
           }
         }
       }
-    }
-    const uint64_t g = block_max_u64(tb, S->wb);
-    if (g == 0) break;
-    if (tid == 0) cand->keys[r] = g;
+      const uint64_t g = block_max_u64(tb, S->wb);
+      if (g == 0) break;
+      if (tid == 0) cand->keys[r] = g;
 #pragma unroll
-    for (int i = 0; i < HC; ++i) {
-      if (hk[i] == g) {
-        const int b = tid + i * int(blockDim.x);
-        const uint32_t cnt = ld_agent(&lists[b].count);
-        ++hp[i];
-        hk[i] = hp[i] < cnt ? ld_agent(&lists[b].keys[hp[i]]) : 0;
-        if (hp[i] >= cnt && ld_agent(&lists[b].total) > cnt) atomicOr(&S->sflags, uint32_t(kFlagListTruncated));
+      for (int i = 0; i < HC; ++i) {
+        if (hk[i] == g) {
+          const int b = tid + i * int(blockDim.x);
+          const uint32_t cnt = ld_agent(&lists[b].count);
+          ++hp[i];
+          hk[i] = hp[i] < cnt ? ld_agent(&lists[b].keys[hp[i]]) : 0;
+          if (hp[i] >= cnt && ld_agent(&lists[b].total) > cnt) atomicOr(&S->sflags, uint32_t(kFlagListTruncated));
+        }
       }
+      last_taken = g;
     }
-    last_taken = g;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    cand->count = r;
-    cand->flags = int32_t(S->sflags | uint32_t(kFlagFallback) | uint32_t(kFlagBandTruncated));
-    cand->pmax32 = pg;
+    __syncthreads();
+    if (tid == 0) {
+      cand->count = r;
+      cand->flags = int32_t(S->sflags | uint32_t(kFlagFallback) | uint32_t(kFlagBandTruncated));
+      cand->pmax32 = pg;
+    }
   }
 }
 
@@ -542,6 +582,19 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
 // LDS scratch of select_list: 512 bytes of counters, then kListCap gathered
 // keys and kListC sorted keys.
 constexpr size_t kListScratchBytes = 512 + sizeof(uint64_t) * (kListCap + kListC);
+
+// Header of a workgroup list (thread 0; wave 0 stores the keys): also the
+// workgroup's head key in the dense array read by the grid merge, and the
+// fallback flag of the step.
+__device__ __forceinline__ void list_header(BlockList32* o, uint64_t* head, unsigned int* flagword, float pb,
+                                            uint32_t count, uint32_t total, uint32_t flags, uint64_t first) {
+  st_agent(&o->pmax, pb);
+  st_agent(&o->count, count);
+  st_agent(&o->total, total);
+  st_agent(&o->flags, flags);
+  if (head) st_agent(head, count > 0 ? first : uint64_t(0));
+  if (flags && flagword) __hip_atomic_fetch_or(flagword, flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // The flat indices of a workgroup's points in increasing order: rank i is
 // first + (i mod na) + (i / na) * step (na consecutive indices, then a jump).
@@ -603,7 +656,8 @@ __device__ __forceinline__ void select_best(const Cx<T> (&v)[pickE<T, LOGN>()], 
 template <int LOGN>
 __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LOGN>()], bool active, float sc,
                                             uint32_t fbase, uint32_t fstride, int t, unsigned char* scratch,
-                                            float tau_band, const FlatOrder& ord, BlockList32* o) {
+                                            float tau_band, const FlatOrder& ord, BlockList32* o, uint64_t* head,
+                                            unsigned int* flagword) {
   constexpr int E = pickE<float, LOGN>();
   constexpr int TPR = Shape<LOGN, E>::TPR;
   constexpr int LE = ilog2c(E);
@@ -656,12 +710,7 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
     uint64_t* sorted = reinterpret_cast<uint64_t*>(scratch + 512 + sizeof(uint64_t) * kListCap);
     top_desc(keys, n, sorted, uint32_t(kListC));
     wave0_copy_keys(sorted, o->keys, n < uint32_t(kListC) ? n : uint32_t(kListC));
-    if (tid == 0) {
-      st_agent(&o->pmax, pb);
-      st_agent(&o->count, n < uint32_t(kListC) ? n : uint32_t(kListC));
-      st_agent(&o->total, n);
-      st_agent(&o->flags, 0u);
-    }
+    if (tid == 0) list_header(o, head, flagword, pb, n < uint32_t(kListC) ? n : uint32_t(kListC), n, 0u, sorted[0]);
     return;
   }
 
@@ -685,12 +734,7 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
   if (pb == pbn) {
     const uint32_t c = ord.count < uint32_t(kListC) ? ord.count : uint32_t(kListC);
     if (uint32_t(tid) < c) st_agent(&o->keys[tid], key32(pb, ord.rank(uint32_t(tid))));  // wave 0 (c <= 64)
-    if (tid == 0) {
-      st_agent(&o->pmax, pb);
-      st_agent(&o->count, c);
-      st_agent(&o->total, ord.count);
-      st_agent(&o->flags, uint32_t(kFlagFallback));
-    }
+    if (tid == 0) list_header(o, head, flagword, pb, c, ord.count, uint32_t(kFlagFallback), key32(pb, ord.rank(0)));
     return;
   }
   {
@@ -734,17 +778,13 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
       top_desc(keys, n2, sorted, uint32_t(kListC));
       const uint32_t c = n2 < uint32_t(kListC) ? n2 : uint32_t(kListC);
       wave0_copy_keys(sorted, o->keys, c);
-      if (tid == 0) {
-        st_agent(&o->pmax, pb);
-        st_agent(&o->count, c);
-        st_agent(&o->total, n);
-        st_agent(&o->flags, uint32_t(kFlagFallback));
-      }
+      if (tid == 0) list_header(o, head, flagword, pb, c, n, uint32_t(kFlagFallback), sorted[0]);
       return;
     }
   }
   uint32_t taken = 0;
   uint32_t rounds = 0;
+  uint64_t first = 0;
   for (; rounds < uint32_t(kListC); ++rounds) {
     uint64_t tb = 0;
 #pragma unroll
@@ -756,18 +796,14 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
     }
     const uint64_t b = block_max_u64(tb, wbest);
     if (b == 0) break;
+    if (rounds == 0) first = b;
     if (tid == 0) st_agent(&o->keys[rounds], b);
 #pragma unroll
     for (int p = 0; p < E; ++p) {
       if (Y[p] > 0.f && key32(Y[p], fbase + fstride * uint32_t(t + TPR * bitrev(p, LE))) == b) taken |= 1u << p;
     }
   }
-  if (tid == 0) {
-    st_agent(&o->pmax, pb);
-    st_agent(&o->count, rounds);
-    st_agent(&o->total, n);
-    st_agent(&o->flags, uint32_t(kFlagFallback));
-  }
+  if (tid == 0) list_header(o, head, flagword, pb, rounds, n, uint32_t(kFlagFallback), first);
 }
 
 }  // namespace afd
