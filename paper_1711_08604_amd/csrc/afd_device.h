@@ -406,23 +406,97 @@ __device__ __forceinline__ uint64_t key32(float p, uint32_t f) {
 __device__ __forceinline__ float key_p(uint64_t k) { return __uint_as_float(uint32_t(k >> 32)); }
 __device__ __forceinline__ uint32_t key_f(uint64_t k) { return ~uint32_t(k & 0xffffffffu); }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  const uint32_t lo = __shfl_xor(uint32_t(v), m);
-  const uint32_t hi = __shfl_xor(uint32_t(v >> 32), m);
-  return (uint64_t(hi) << 32) | lo;
+// ---------------------------------------------------------------- wave reductions
+// No LDS and no lane-address registers: DPP moves inside each row of 16 lanes
+// (xor 1, xor 2, half-row mirror, row mirror) leave every lane holding its
+// row's result, then the four row results are combined through readlane, so
+// every lane returns the same value.  All 64 lanes of the wave must be active.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(int(v), int(v), CTRL, 0xF, 0xF, false));
 }
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const uint64_t o = shfl_xor_u64(v, m);
-    v = o > v ? o : v;
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  return (uint64_t(dpp_u32<CTRL>(uint32_t(v >> 32))) << 32) | dpp_u32<CTRL>(uint32_t(v));
+}
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, int lane) {
+  return uint32_t(__builtin_amdgcn_readlane(int(v), lane));
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int lane) {
+  return (uint64_t(lane_u32(uint32_t(v >> 32), lane)) << 32) | lane_u32(uint32_t(v), lane);
+}
+
+// OP: a struct with static T op(T, T) on the 32/64-bit pattern of the value
+template <typename OP, typename U>
+__device__ __forceinline__ U wave_reduce_bits(U v) {
+  if constexpr (sizeof(U) == 8) {
+    v = OP::op(v, dpp_u64<kDppXor1>(v));
+    v = OP::op(v, dpp_u64<kDppXor2>(v));
+    v = OP::op(v, dpp_u64<kDppHalfMirror>(v));
+    v = OP::op(v, dpp_u64<kDppMirror>(v));
+    U r = lane_u64(v, 0);
+    r = OP::op(r, lane_u64(v, 16));
+    r = OP::op(r, lane_u64(v, 32));
+    return OP::op(r, lane_u64(v, 48));
+  } else {
+    v = OP::op(v, dpp_u32<kDppXor1>(v));
+    v = OP::op(v, dpp_u32<kDppXor2>(v));
+    v = OP::op(v, dpp_u32<kDppHalfMirror>(v));
+    v = OP::op(v, dpp_u32<kDppMirror>(v));
+    U r = lane_u32(v, 0);
+    r = OP::op(r, lane_u32(v, 16));
+    r = OP::op(r, lane_u32(v, 32));
+    return OP::op(r, lane_u32(v, 48));
   }
-  return v;
 }
+
+struct MaxU64 {
+  static __device__ __forceinline__ uint64_t op(uint64_t a, uint64_t b) { return a > b ? a : b; }
+};
+struct MaxF32 {  // on the bits of a float
+  static __device__ __forceinline__ uint32_t op(uint32_t a, uint32_t b) {
+    return __float_as_uint(fmaxf(__uint_as_float(a), __uint_as_float(b)));
+  }
+};
+struct MinF32 {
+  static __device__ __forceinline__ uint32_t op(uint32_t a, uint32_t b) {
+    return __float_as_uint(fminf(__uint_as_float(a), __uint_as_float(b)));
+  }
+};
+struct SumU32 {
+  static __device__ __forceinline__ uint32_t op(uint32_t a, uint32_t b) { return a + b; }
+};
+struct MinU32 {
+  static __device__ __forceinline__ uint32_t op(uint32_t a, uint32_t b) { return a < b ? a : b; }
+};
+struct SumF64 {  // on the bits of a double
+  static __device__ __forceinline__ uint64_t op(uint64_t a, uint64_t b) {
+    return uint64_t(__double_as_longlong(__longlong_as_double((long long)a) + __longlong_as_double((long long)b)));
+  }
+};
+struct MaxF64 {
+  static __device__ __forceinline__ uint64_t op(uint64_t a, uint64_t b) {
+    return uint64_t(__double_as_longlong(fmax(__longlong_as_double((long long)a), __longlong_as_double((long long)b))));
+  }
+};
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) { return wave_reduce_bits<MaxU64>(v); }
 __device__ __forceinline__ float wave_max_f32(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m));
-  return v;
+  return __uint_as_float(wave_reduce_bits<MaxF32>(__float_as_uint(v)));
+}
+__device__ __forceinline__ float wave_min_f32(float v) {
+  return __uint_as_float(wave_reduce_bits<MinF32>(__float_as_uint(v)));
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  return __longlong_as_double((long long)wave_reduce_bits<SumF64>(uint64_t(__double_as_longlong(v))));
+}
+__device__ __forceinline__ double wave_max_f64(double v) {
+  return __longlong_as_double((long long)wave_reduce_bits<MaxF64>(uint64_t(__double_as_longlong(v))));
 }
 
 }  // namespace afd

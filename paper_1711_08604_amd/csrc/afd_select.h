@@ -29,22 +29,39 @@ __device__ __forceinline__ void best_merge(Best& a, const Best& b) {
   }
 }
 
-__device__ __forceinline__ Best best_shfl(const Best& a, int m) {
-  Best o;
-  o.p1 = __shfl_xor(a.p1, m);
-  o.p2 = __shfl_xor(a.p2, m);
-  o.vx = __shfl_xor(a.vx, m);
-  o.vy = __shfl_xor(a.vy, m);
-  o.f = __shfl_xor(a.f, m);
-  return o;
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  return __longlong_as_double((long long)dpp_u64<CTRL>(uint64_t(__double_as_longlong(v))));
+}
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  return __longlong_as_double((long long)lane_u64(uint64_t(__double_as_longlong(v)), lane));
+}
+template <int CTRL>
+__device__ __forceinline__ Best best_dpp(const Best& a) {
+  return Best{dpp_f64<CTRL>(a.p1), dpp_f64<CTRL>(a.p2), dpp_f64<CTRL>(a.vx), dpp_f64<CTRL>(a.vy), dpp_u32<CTRL>(a.f)};
+}
+__device__ __forceinline__ Best best_lane(const Best& a, int lane) {
+  return Best{lane_f64(a.p1, lane), lane_f64(a.p2, lane), lane_f64(a.vx, lane), lane_f64(a.vy, lane),
+              lane_u32(a.f, lane)};
+}
+// best and runner-up over the wave (every lane gets the result; all lanes active)
+__device__ __forceinline__ Best wave_best(Best b) {
+  best_merge(b, best_dpp<kDppXor1>(b));
+  best_merge(b, best_dpp<kDppXor2>(b));
+  best_merge(b, best_dpp<kDppHalfMirror>(b));
+  best_merge(b, best_dpp<kDppMirror>(b));
+  Best r = best_lane(b, 0);
+  best_merge(r, best_lane(b, 16));
+  best_merge(r, best_lane(b, 32));
+  best_merge(r, best_lane(b, 48));
+  return r;
 }
 
 __device__ __forceinline__ int nwaves() { return int((blockDim.x + 63) >> 6); }
 
 // Block-wide results, returned to every thread.  `w*` are LDS arrays of 16.
 __device__ __forceinline__ Best block_best(Best b, Best* wb) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) best_merge(b, best_shfl(b, m));
+  b = wave_best(b);
   if ((threadIdx.x & 63) == 0) wb[threadIdx.x >> 6] = b;
   __syncthreads();
   Best r = wb[0];
@@ -76,11 +93,10 @@ __device__ __forceinline__ float block_max_f32(float v, float* wf) {
 // SUM: block sum, else block minimum; `w` is an LDS array of 16
 template <bool SUM>
 __device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v, uint32_t* w) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const uint32_t o = __shfl_xor(v, m);
-    v = SUM ? v + o : (o < v ? o : v);
-  }
+  if constexpr (SUM)
+    v = wave_reduce_bits<SumU32>(v);
+  else
+    v = wave_reduce_bits<MinU32>(v);
   if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = v;
   __syncthreads();
   uint32_t r = w[0];
@@ -90,8 +106,7 @@ __device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v, uint32_t* w) {
 }
 
 __device__ __forceinline__ double block_sum_f64(double v, double* wd) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  v = wave_sum_f64(v);
   if ((threadIdx.x & 63) == 0) wd[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = wd[0];
@@ -109,7 +124,7 @@ __device__ __forceinline__ void wave_append(bool q, uint64_t k, uint32_t* cnt, u
   const int leader = __ffsll(static_cast<long long>(mask)) - 1;
   uint32_t base = 0;
   if (lane == leader) base = atomicAdd(cnt, uint32_t(__popcll(mask)));
-  base = __shfl(base, leader);
+  base = lane_u32(base, leader);
   if (q) {
     const uint32_t pos = base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
     if (pos < cap) buf[pos] = k;
@@ -220,7 +235,10 @@ __device__ __forceinline__ void wave0_copy_keys(const uint64_t* src, uint64_t* d
 }
 
 // LDS layout used by the grid-level merges (placed in a kernel's dynamic LDS).
+constexpr int kHeadCap = 2048;  // head keys the FP32 grid merge holds in LDS
+
 struct MergeScratch {
+  uint64_t heads[kHeadCap];
   uint64_t buf[kSelCap];
   uint32_t cblk[kSelCap];
   uint64_t sorted[kListC];
@@ -307,7 +325,7 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
     if (lane == 0 && bm) atomicAdd(&S->sband, uint32_t(__popcll(bm)));
     wave_append(inband && k >= hcut, k, &S->scount, S->buf, uint32_t(kSelCap));
     // a member list cut inside the band: count the points it could not hold
-    const uint64_t last = __shfl(k, int(cnt) - 1);
+    const uint64_t last = lane_u64(k, __builtin_amdgcn_readfirstlane(int(cnt) - 1));
     if (lane == 0 && key_p(last) >= theta) {
       const uint32_t tot = ld_agent(&B->total);
       if (tot > cnt) atomicAdd(&S->stotal, tot - cnt);
@@ -393,21 +411,13 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
                                               MergeScratch* S) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = nwaves();
-  constexpr int HC = 8;  // head keys cached per thread
-  uint64_t hk[HC];
+  // the head keys, staged in LDS when they fit (otherwise re-read from memory)
+  const bool fits = nb <= kHeadCap;
   uint64_t mx = 0;
-#pragma unroll
-  for (int i = 0; i < HC; ++i) {
-    const int b = tid + i * int(blockDim.x);
-    hk[i] = b < nb ? ld_agent(heads + b) : 0;
-    mx = hk[i] > mx ? hk[i] : mx;
-  }
-  const bool spill = nb > HC * int(blockDim.x);
-  if (spill) {
-    for (int b = tid + HC * int(blockDim.x); b < nb; b += blockDim.x) {
-      const uint64_t k = ld_agent(heads + b);
-      mx = k > mx ? k : mx;
-    }
+  for (int b = tid; b < nb; b += blockDim.x) {
+    const uint64_t k = ld_agent(heads + b);
+    if (fits) S->heads[b] = k;
+    mx = k > mx ? k : mx;
   }
   if (tid == 0) {
     S->sflags = ld_agent(flagword) & uint32_t(kFlagFallback);
@@ -415,30 +425,25 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
     S->scount = 0;
     S->sblocks = 0;
   }
-  const uint64_t gk = block_max_u64(mx, S->wb);  // its barriers order the initialisation above
+  const uint64_t gk = block_max_u64(mx, S->wb);  // its barriers order the stores above
   const float pg = gk ? key_p(gk) : -1.f;
   const float theta = pg - pg * tau_band;
+  auto head_of = [&](int b) { return fits ? S->heads[b] : ld_agent(heads + b); };
   // blocks whose head reaches the band
-  auto note_band = [&](int b, uint64_t k) {
-    const bool q = b < nb && k != 0 && key_p(k) >= theta;
+  for (int b0 = 0; b0 < nb; b0 += blockDim.x) {
+    const int b = b0 + tid;
+    const uint64_t k = b < nb ? head_of(b) : 0;
+    const bool q = k != 0 && key_p(k) >= theta;
     const uint64_t mask = __ballot(q);
     if (mask) {
       const int leader = __ffsll(static_cast<long long>(mask)) - 1;
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(&S->sblocks, uint32_t(__popcll(mask)));
-      base = __shfl(base, leader);
+      base = lane_u32(base, leader);
       if (q) {
         const uint32_t pos = base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
         if (pos < uint32_t(kSelCap)) S->cblk[pos] = uint32_t(b);
       }
-    }
-  };
-#pragma unroll
-  for (int i = 0; i < HC; ++i) note_band(tid + i * int(blockDim.x), hk[i]);
-  if (spill) {
-    for (int b0 = HC * int(blockDim.x); b0 < nb; b0 += blockDim.x) {
-      const int b = b0 + tid;
-      note_band(b, b < nb ? ld_agent(heads + b) : 0);
     }
   }
   __syncthreads();
@@ -463,22 +468,23 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
     if (band > uint32_t(kKMax) && tid == 0) atomicOr(&S->sflags, uint32_t(kFlagBandTruncated));
     if (keff < uint32_t(recheck_k)) {
       const uint32_t need = uint32_t(recheck_k) - keff;  // <= 63
-      if (!spill) {
-        // each wave: the top `need` heads below the band among its lanes, by
-        // rounds of a wave maximum (no workgroup barrier) ...
-#pragma unroll
-        for (int i = 0; i < HC; ++i)
-          if (hk[i] == 0 || key_p(hk[i]) >= theta) hk[i] = 0;
+      if (fits) {
+        // each wave: the top `need` heads below the band among its lanes'
+        // heads (b = tid + i blockDim), by rounds of a wave maximum (no
+        // workgroup barrier) ...
         uint64_t* wl = S->buf;  // free after top_desc: [nw][need]
         for (uint32_t r = 0; r < need; ++r) {
           uint64_t lm = 0;
-#pragma unroll
-          for (int i = 0; i < HC; ++i) lm = hk[i] > lm ? hk[i] : lm;
+          for (int b = tid; b < nb; b += blockDim.x) {
+            const uint64_t k = S->heads[b];
+            if (k != 0 && key_p(k) < theta && k > lm) lm = k;
+          }
           const uint64_t w = wave_max_u64(lm);
           if (lane == 0) wl[uint32_t(wave) * need + r] = w;
-#pragma unroll
-          for (int i = 0; i < HC; ++i)
-            if (hk[i] == w) hk[i] = 0;  // keys are distinct: one lane owns w
+          if (w != 0 && lm == w) {  // keys are distinct: this lane owns w
+            for (int b = tid; b < nb; b += blockDim.x)
+              if (S->heads[b] == w) S->heads[b] = 0;
+          }
         }
         __syncthreads();
         // ... then the top `need` of the waves' candidates by rank
@@ -695,7 +701,7 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
       const int leader = __ffsll(static_cast<long long>(mask)) - 1;
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(cnt, uint32_t(__popcll(mask)));
-      base = __shfl(base, leader);
+      base = lane_u32(base, leader);
       if (q) {
         const uint32_t pos = base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
         if (pos < uint32_t(kListCap)) keys[pos] = key32(Y[p] * s2, fbase + fstride * uint32_t(t + TPR * bitrev(p, LE)));
@@ -725,8 +731,7 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
 #pragma unroll
     for (int p = 0; p < E; ++p) pn = fminf(pn, Y[p] * s2);
   }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) pn = fminf(pn, __shfl_xor(pn, m));
+  pn = wave_min_f32(pn);
   if (lane == 0) wmin[wave] = pn;
   __syncthreads();
   float pbn = wmin[0];

@@ -109,8 +109,7 @@ __device__ __forceinline__ void finalize_tail(const CandList* __restrict__ cand,
     best_merge(b, x);
   }
   const Best r = block_best(b, bb);
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) err = fmax(err, __shfl_xor(err, m));
+  err = wave_max_f64(err);
   if ((threadIdx.x & 63) == 0) wd[threadIdx.x >> 6] = err;
   __syncthreads();
   if (threadIdx.x == 0) {
