@@ -471,18 +471,32 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
       if (fits) {
         // each wave: the top `need` heads below the band among its lanes'
         // heads (b = tid + i blockDim), by rounds of a wave maximum (no
-        // workgroup barrier) ...
+        // workgroup barrier); the first two heads of a lane stay in registers
+        uint64_t h0 = 0, h1 = 0;
+        {
+          const int b0 = tid, b1 = tid + int(blockDim.x);
+          if (b0 < nb) h0 = S->heads[b0];
+          if (b1 < nb) h1 = S->heads[b1];
+          if (h0 != 0 && key_p(h0) >= theta) h0 = 0;
+          if (h1 != 0 && key_p(h1) >= theta) h1 = 0;
+        }
+        const bool more = nb > 2 * int(blockDim.x);
         uint64_t* wl = S->buf;  // free after top_desc: [nw][need]
         for (uint32_t r = 0; r < need; ++r) {
-          uint64_t lm = 0;
-          for (int b = tid; b < nb; b += blockDim.x) {
-            const uint64_t k = S->heads[b];
-            if (k != 0 && key_p(k) < theta && k > lm) lm = k;
+          uint64_t lm = h0 > h1 ? h0 : h1;
+          if (more) {
+            for (int b = tid + 2 * int(blockDim.x); b < nb; b += blockDim.x) {
+              const uint64_t k = S->heads[b];
+              if (k != 0 && key_p(k) < theta && k > lm) lm = k;
+            }
           }
           const uint64_t w = wave_max_u64(lm);
           if (lane == 0) wl[uint32_t(wave) * need + r] = w;
-          if (w != 0 && lm == w) {  // keys are distinct: this lane owns w
-            for (int b = tid; b < nb; b += blockDim.x)
+          // keys are distinct: one lane owns w
+          if (h0 == w) h0 = 0;
+          if (h1 == w) h1 = 0;
+          if (more && lm == w && w != 0) {
+            for (int b = tid + 2 * int(blockDim.x); b < nb; b += blockDim.x)
               if (S->heads[b] == w) S->heads[b] = 0;
           }
         }
