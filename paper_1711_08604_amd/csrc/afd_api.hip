@@ -382,28 +382,31 @@ afd_status ensure_forced(afd_plan_s* p, int steps) {
   return AFD_OK;
 }
 
+// Per-kernel timing: the events are handed to the launch itself, which
+// stamps the dispatch's start and end (no extra packets on the stream).
 struct Timer {
   afd_plan_s* p;
-  int kind;
   size_t next = 0;
-  hipError_t begin(int k) {
+  // events for one timed unit of kind k, or nulls when k is not timed
+  hipError_t pair(int k, hipEvent_t* a, hipEvent_t* b) {
+    *a = *b = nullptr;
     if (p->time_kind != k) return hipSuccess;
     if (next >= p->events.size() / 2) {
-      hipEvent_t a, b;
-      hipError_t e = hipEventCreate(&a);
+      hipEvent_t x, y;
+      hipError_t e = hipEventCreate(&x);
       if (e != hipSuccess) return e;
-      e = hipEventCreate(&b);
-      if (e != hipSuccess) return e;
-      p->events.push_back(a);
-      p->events.push_back(b);
+      e = hipEventCreate(&y);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(x);
+        return e;
+      }
+      p->events.push_back(x);
+      p->events.push_back(y);
     }
-    return hipEventRecord(p->events[2 * next], p->stream);
-  }
-  hipError_t end(int k) {
-    if (p->time_kind != k) return hipSuccess;
-    const hipError_t e = hipEventRecord(p->events[2 * next + 1], p->stream);
+    *a = p->events[2 * next];
+    *b = p->events[2 * next + 1];
     ++next;
-    return e;
+    return hipSuccess;
   }
   hipError_t collect() {
     for (size_t i = 0; i < next; ++i) {
@@ -542,7 +545,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     bp.winner = win;
   }
 
-  Timer tm{p, p->time_kind};
+  Timer tm{p};
   for (int k = 0; k < steps; ++k) {
     const int32_t* fsrc = nullptr;
     int fstep = k;
@@ -556,27 +559,30 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       HIPCHK(launch_force(fsrc, fstep, N, cand, s), "k_force");
       HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1, win, s), "k_recheck");
     } else {
-      HIPCHK(tm.begin(kTimeFft), "event");
+      hipEvent_t e0, e1;
+      HIPCHK(tm.pair(kTimeFft, &e0, &e1), "event");
       HIPCHK(launch_fwd(c.logn, c.fp64, c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32),
-                        p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega, p->at<void>(p->L.xt), cspec, s),
+                        p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega, p->at<void>(p->L.xt), cspec, s, e0,
+                        e1),
              "forward DFT");
-      HIPCHK(tm.end(kTimeFft), "event");
-      HIPCHK(tm.begin(kTimeRadius), "event");
+      HIPCHK(tm.pair(kTimeRadius, &e0, &e1), "event");
       if (c.big) {
         for (int m0 = 0; m0 < c.M; m0 += c.chunk) {
           bp.m0 = m0;
-          HIPCHK(launch_big(c.logn, c.fp64, bp, c.M - m0 < c.chunk ? c.M - m0 : c.chunk, s), "k_big");
+          const bool first = m0 == 0, last = m0 + c.chunk >= c.M;
+          HIPCHK(launch_big(c.logn, c.fp64, bp, c.M - m0 < c.chunk ? c.M - m0 : c.chunk, s, first ? e0 : nullptr,
+                            last ? e1 : nullptr),
+                 "k_big");
         }
       } else {
-        HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, s), "k_radius");
+        HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, s, e0, e1), "k_radius");
       }
-      HIPCHK(tm.end(kTimeRadius), "event");
       if (!c.fp64)
         HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1, win, s), "k_recheck");
     }
-    HIPCHK(tm.begin(kTimeUpdate), "event");
-    HIPCHK(launch_update(radii, omega, g64, g32, N, c.M, epart, counters + 2, rec, k, s), "k_update");
-    HIPCHK(tm.end(kTimeUpdate), "event");
+    hipEvent_t u0, u1;
+    HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
+    HIPCHK(launch_update(radii, omega, g64, g32, N, c.M, epart, counters + 2, rec, k, s, u0, u1), "k_update");
   }
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, nonfinite, 4, hipMemcpyDeviceToHost, s), "reading flag");

@@ -228,35 +228,35 @@ hipError_t setup_fwd_attributes() {
 
 template <typename T, int LOGN>
 static hipError_t launch_fwd_t(const void* g, const void* tw1, const void* tw2, const double* omega, void* xt,
-                               void* c, hipStream_t s) {
+                               void* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if constexpr (LOGN < kFwdTwoPassMin) {
     constexpr int thr = fwd_threads<T, LOGN>();
     constexpr size_t lds = fft_region_bytes<T, LOGN, pickSplit<T, LOGN>()>();
-    hipLaunchKernelGGL((k_fft_fwd<T, LOGN>), dim3(1), dim3(thr), lds, s, reinterpret_cast<const Cx<T>*>(g),
-                       reinterpret_cast<const Cx<T>*>(tw1), reinterpret_cast<Cx<T>*>(c));
+    launch_ev(k_fft_fwd<T, LOGN>, dim3(1), dim3(thr), uint32_t(lds), s, e0, e1, reinterpret_cast<const Cx<T>*>(g),
+              reinterpret_cast<const Cx<T>*>(tw1), reinterpret_cast<Cx<T>*>(c));
   } else {
     using P = Split2<LOGN>;
     constexpr int thr_c = cols_threads<T, LOGN>();
     constexpr int thr_r = rows_threads<T, LOGN>();
     constexpr size_t lds_c = kColsPerBlock * fft_region_bytes<T, P::L2, false>();
     constexpr size_t lds_r = kColsPerBlock * fft_region_bytes<T, P::L1, false>();
-    hipLaunchKernelGGL((k_fwd_cols<T, LOGN>), dim3(P::N1 / kColsPerBlock), dim3(thr_c), lds_c, s,
-                       reinterpret_cast<const Cx<T>*>(g), reinterpret_cast<const Cx<T>*>(tw2), omega,
-                       reinterpret_cast<Cx<T>*>(xt));
-    hipLaunchKernelGGL((k_fwd_rows<T, LOGN, fwd_cols_out<LOGN>()>), dim3(P::N2 / kColsPerBlock), dim3(thr_r), lds_r, s,
-                       reinterpret_cast<const Cx<T>*>(xt), reinterpret_cast<const Cx<T>*>(tw1),
-                       reinterpret_cast<Cx<T>*>(c));
+    launch_ev(k_fwd_cols<T, LOGN>, dim3(P::N1 / kColsPerBlock), dim3(thr_c), uint32_t(lds_c), s, e0, nullptr,
+              reinterpret_cast<const Cx<T>*>(g), reinterpret_cast<const Cx<T>*>(tw2), omega,
+              reinterpret_cast<Cx<T>*>(xt));
+    launch_ev(k_fwd_rows<T, LOGN, fwd_cols_out<LOGN>()>, dim3(P::N2 / kColsPerBlock), dim3(thr_r), uint32_t(lds_r), s,
+              nullptr, e1, reinterpret_cast<const Cx<T>*>(xt), reinterpret_cast<const Cx<T>*>(tw1),
+              reinterpret_cast<Cx<T>*>(c));
   }
   return hipGetLastError();
 }
 
 hipError_t launch_fwd(int logn, bool fp64, const void* g, const void* tw1, const void* tw2, const double* omega,
-                      void* xt, void* c, hipStream_t s) {
+                      void* xt, void* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (logn) {
 #define X(L)                                                                       \
   case L:                                                                          \
-    return fp64 ? launch_fwd_t<double, L>(g, tw1, tw2, omega, xt, c, s)            \
-                : launch_fwd_t<float, L>(g, tw1, tw2, omega, xt, c, s);
+    return fp64 ? launch_fwd_t<double, L>(g, tw1, tw2, omega, xt, c, s, e0, e1)    \
+                : launch_fwd_t<float, L>(g, tw1, tw2, omega, xt, c, s, e0, e1);
     AFD_FWD_ALL_LOGN_CASES(X)
 #undef X
     default:

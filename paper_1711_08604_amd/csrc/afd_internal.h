@@ -3,6 +3,7 @@
 // launchers.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <stddef.h>
@@ -126,7 +127,8 @@ BigGeom big_geom(int logn, bool fp64);
 hipError_t setup_big_attributes();
 // One chunk of `nr` radii starting at p.m0: the column pass, then the row
 // pass with the selection.
-hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s);
+hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
 
 // Step outputs written by the last workgroup of k_update / k_prepare.
 struct RecordArgs {
@@ -184,18 +186,31 @@ inline hipError_t set_max_dynamic_lds(const void* fn) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(160 * 1024 - a.sharedSizeBytes));
 }
 
+// Launch with optional timing events: a non-null e0 / e1 takes the start /
+// end timestamp of this dispatch itself (no extra packets on the stream).
+template <typename F, typename... Args>
+inline void launch_ev(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                      Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
 hipError_t setup_radius_attributes();
 hipError_t setup_fwd_attributes();
 
 hipError_t launch_fwd(int logn, bool fp64, const void* g, const void* tw1, const void* tw2, const double* omega,
-                      void* xt, void* c, hipStream_t s);
-hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, hipStream_t s);
+                      void* xt, void* c, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, hipStream_t s,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* nonfinite, unsigned int* counter,
                           const RecordArgs& R, hipStream_t s);
 hipError_t launch_force(const int32_t* forced, int step, int N, CandList* cand, hipStream_t s);
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
                           double* partials, unsigned int* counter, Winner* w, hipStream_t s);
 hipError_t launch_update(const double* radii, const double* omega, double* g64, float* g32, int N, int M,
-                         double* epart, unsigned int* counter, const RecordArgs& R, int step, hipStream_t s);
+                         double* epart, unsigned int* counter, const RecordArgs& R, int step, hipStream_t s,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 }  // namespace afd

@@ -189,18 +189,19 @@ hipError_t setup_radius_attributes() {
   return e;
 }
 
-hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, hipStream_t s) {
+hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
   switch (logn) {
 #define X(L)                                                                                 \
   case L: {                                                                                  \
     if (fp64) {                                                                              \
       constexpr int thr = radius_threads<double, L>();                                       \
       const size_t lds = radius_lds<double, L>(p.rpb);                                       \
-      hipLaunchKernelGGL((k_radius<double, L, false>), dim3(blocks), dim3(thr), lds, s, p);  \
+      launch_ev(k_radius<double, L, false>, dim3(blocks), dim3(thr), uint32_t(lds), s, e0, e1, p); \
     } else {                                                                                 \
       constexpr int thr = radius_threads<float, L>();                                        \
       const size_t lds = radius_lds<float, L>(p.rpb);                                        \
-      hipLaunchKernelGGL((k_radius<float, L, true>), dim3(blocks), dim3(thr), lds, s, p);    \
+      launch_ev(k_radius<float, L, true>, dim3(blocks), dim3(thr), uint32_t(lds), s, e0, e1, p);   \
     }                                                                                        \
     return hipGetLastError();                                                                \
   }

@@ -243,9 +243,10 @@ hipError_t launch_recheck(const CandList* cand, const double* g, const double* o
 }
 
 hipError_t launch_update(const double* radii, const double* omega, double* g64, float* g32, int N, int M,
-                         double* epart, unsigned int* counter, const RecordArgs& R, int step, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(update_blocks(N)), dim3(kUpdThreads), 0, s, radii, omega, g64, g32, N, M,
-                     epart, counter, R, step);
+                         double* epart, unsigned int* counter, const RecordArgs& R, int step, hipStream_t s,
+                         hipEvent_t e0, hipEvent_t e1) {
+  launch_ev(k_update, dim3(update_blocks(N)), dim3(kUpdThreads), 0u, s, e0, e1, radii, omega, g64, g32, N, M, epart,
+            counter, R, step);
   return hipGetLastError();
 }
 
