@@ -546,6 +546,14 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   }
 
   Timer tm{p};
+  UpdateArgs upd{};
+  upd.radii = radii;
+  upd.omega = omega;
+  upd.N = N;
+  upd.M = c.M;
+  upd.epart = epart;
+  upd.counter = counters + 2;
+  upd.R = rec;
   for (int k = 0; k < steps; ++k) {
     const int32_t* fsrc = nullptr;
     int fstep = k;
@@ -582,7 +590,8 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     }
     hipEvent_t u0, u1;
     HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
-    HIPCHK(launch_update(radii, omega, g64, g32, N, c.M, epart, counters + 2, rec, k, s, u0, u1), "k_update");
+    upd.step = k;
+    HIPCHK(launch_update(g64, g32, upd, s, u0, u1), "k_update");
   }
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, nonfinite, 4, hipMemcpyDeviceToHost, s), "reading flag");

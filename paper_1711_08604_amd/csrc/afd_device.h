@@ -410,7 +410,8 @@ __device__ __forceinline__ uint32_t key_f(uint64_t k) { return ~uint32_t(k & 0xf
 // No LDS and no lane-address registers: DPP moves inside each row of 16 lanes
 // (xor 1, xor 2, half-row mirror, row mirror) leave every lane holding its
 // row's result, then the four row results are combined through readlane, so
-// every lane returns the same value.  All 64 lanes of the wave must be active.
+// every lane returns the same value.  All 64 lanes of the wave must be active:
+// every kernel that reduces launches whole waves (a multiple of 64 threads).
 constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;

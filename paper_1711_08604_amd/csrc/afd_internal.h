@@ -146,6 +146,18 @@ struct RecordArgs {
   double* fp32err;
 };
 
+// Everything a kernel needs to apply step `step`'s remainder update (eq. (7))
+// and record the step (see afd_update.h).
+struct UpdateArgs {
+  const double* radii;
+  const double* omega;
+  int N, M;
+  double* epart;          // per-workgroup energy partial sums
+  unsigned int* counter;  // last-workgroup counter (zero between launches)
+  RecordArgs R;
+  int step;
+};
+
 // Geometry of the LDS-resident transform for 2^logn points.
 struct FftGeom {
   int E;        // values per thread
@@ -209,8 +221,7 @@ hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* no
 hipError_t launch_force(const int32_t* forced, int step, int N, CandList* cand, hipStream_t s);
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
                           double* partials, unsigned int* counter, Winner* w, hipStream_t s);
-hipError_t launch_update(const double* radii, const double* omega, double* g64, float* g32, int N, int M,
-                         double* epart, unsigned int* counter, const RecordArgs& R, int step, hipStream_t s,
-                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 
 }  // namespace afd

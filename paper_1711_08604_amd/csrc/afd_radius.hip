@@ -41,6 +41,7 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
   constexpr bool SPLIT = pickSplit<T, LOGN>();
   using S = Shape<LOGN, E>;
   constexpr int N = S::N, TPR = S::TPR;
+  static_assert(radius_threads<T, LOGN>() % 64 == 0, "the wave reductions need whole waves");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_last;
   const int tid = threadIdx.x;

@@ -59,16 +59,22 @@ __device__ __forceinline__ Best wave_best(Best b) {
 
 __device__ __forceinline__ int nwaves() { return int((blockDim.x + 63) >> 6); }
 
-// Block-wide results, returned to every thread.  `w*` are LDS arrays of 16.
+// Block-wide best and runner-up, valid in wave 0 (the callers store it from
+// thread 0): the wave results meet in LDS and wave 0 merges them.  `wb` is an
+// LDS array of 16; it must not be rewritten before the next barrier.
 __device__ __forceinline__ Best block_best(Best b, Best* wb) {
   b = wave_best(b);
   if ((threadIdx.x & 63) == 0) wb[threadIdx.x >> 6] = b;
   __syncthreads();
-  Best r = wb[0];
-  for (int w = 1; w < nwaves(); ++w) best_merge(r, wb[w]);
-  __syncthreads();
+  Best r{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
+  if (threadIdx.x < 64) {
+    if (int(threadIdx.x) < nwaves()) r = wb[threadIdx.x];
+    r = wave_best(r);
+  }
   return r;
 }
+
+// Block-wide results, returned to every thread.  `w*` are LDS arrays of 16.
 
 __device__ __forceinline__ uint64_t block_max_u64(uint64_t v, uint64_t* wb) {
   v = wave_max_u64(v);

@@ -8,7 +8,7 @@
 //   k_update    G_{k+1} = (G_k - c_k e_{a_k}) (1 - conj(a_k) z)/(z - a_k) (eq. (7))
 //               in double; the last workgroup sums E_k = (1/N) sum |G_{k+1}|^2
 //               and records the step's outputs
-#include "afd_select.h"
+#include "afd_update.h"
 
 namespace afd {
 
@@ -18,36 +18,6 @@ constexpr int kRecheckBlocksX = 16;
 
 int update_blocks(int N) { return (N + kUpdThreads * kUpdPerThread - 1) / (kUpdThreads * kUpdPerThread); }
 int recheck_chunks(int N) { return N >= 2048 ? N / 2048 : 1; }
-
-__device__ __forceinline__ void write_record(const RecordArgs& R, int step, double E) {
-  if (step < 0) {
-    R.energy[0] = E;
-    return;
-  }
-  Winner W = *R.w;
-  W.m = min(max(W.m, 0), R.M - 1);
-  W.j = W.j & (R.N - 1);
-  const double r = R.radii[W.m];
-  R.idx[2 * step] = W.m;
-  R.idx[2 * step + 1] = W.j;
-  R.a[2 * step] = r * R.omega[2 * W.j];
-  R.a[2 * step + 1] = r * R.omega[2 * W.j + 1];
-  R.coef[2 * step] = W.cx;
-  R.coef[2 * step + 1] = W.cy;
-  R.energy[step + 1] = E;
-  R.margin[step] = W.margin;
-  R.kcount[step] = W.kcount;
-  R.flags[step] = W.flags;
-  R.fp32err[step] = W.fp32err;
-}
-
-// energy of the samples from the per-workgroup partial sums, in index order
-__device__ __forceinline__ double energy_from_parts(const double* __restrict__ epart, int nparts, int N,
-                                                    double* wd) {
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += ld_agent(epart + i);
-  return block_sum_f64(acc, wd) / double(N);
-}
 
 __global__ __launch_bounds__(256) void k_prepare(double* __restrict__ g64, float* __restrict__ g32, int N,
                                                  double* __restrict__ epart, int* __restrict__ nonfinite,
@@ -167,38 +137,18 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
   finalize_tail(cand, partials, radii, N, logn, nch, w, bb, wd);
 }
 
-__global__ __launch_bounds__(256) void k_update(const double* __restrict__ radii, const double* __restrict__ omega,
-                                                double* __restrict__ g64, float* __restrict__ g32, int N, int M,
-                                                double* __restrict__ epart, unsigned int* __restrict__ counter,
-                                                RecordArgs R, int step) {
+__global__ __launch_bounds__(256) void k_update(double* __restrict__ g64, float* __restrict__ g32, UpdateArgs U) {
   __shared__ double wd[16];
   __shared__ int s_last;
-  Winner W = *R.w;
-  W.m = min(max(W.m, 0), M - 1);
-  W.j = W.j & (N - 1);
-  const double r = radii[W.m];
-  const double s = sqrt((1.0 - r) * (1.0 + r));
-  const double wjx = omega[2 * W.j], wjy = -omega[2 * W.j + 1];  // e^{-2 pi i j/N}
-  const double csx = W.cx * s, csy = W.cy * s;
+  const Blaschke B = blaschke_of(U);
+  const int N = U.N;
   double acc = 0.0;
 #pragma unroll
   for (int q = 0; q < kUpdPerThread; ++q) {
     const int n = blockIdx.x * (kUpdThreads * kUpdPerThread) + q * kUpdThreads + threadIdx.x;
     if (n < N) {
-      // with a = r e^{2 pi i j/N}, z_n = e^{2 pi i n/N}, d = n - j:
-      // G' = (G (1 - r w^d) - c s) e^{-2 pi i j/N} / (w^d - r)
-      const int d = (n - W.j) & (N - 1);
-      const double ox = omega[2 * d], oy = omega[2 * d + 1];
-      const double gx = g64[2 * n], gy = g64[2 * n + 1];
-      const double ux = fma(-r, ox, 1.0), uy = -r * oy;
-      const double nx = fma(gx, ux, -gy * uy) - csx;
-      const double ny = fma(gx, uy, gy * ux) - csy;
-      const double dx = ox - r, dy = oy;
-      const double inv = 1.0 / fma(dx, dx, dy * dy);
-      const double qx = fma(nx, dx, ny * dy) * inv;
-      const double qy = fma(ny, dx, -nx * dy) * inv;
-      const double hx = fma(qx, wjx, -qy * wjy);
-      const double hy = fma(qx, wjy, qy * wjx);
+      double hx, hy;
+      blaschke_apply(B, U.omega, N, n, g64[2 * n], g64[2 * n + 1], hx, hy);
       g64[2 * n] = hx;
       g64[2 * n + 1] = hy;
       if (g32) {
@@ -208,11 +158,7 @@ __global__ __launch_bounds__(256) void k_update(const double* __restrict__ radii
       acc += fma(hx, hx, hy * hy);
     }
   }
-  const double tot = block_sum_f64(acc, wd);
-  if (threadIdx.x == 0) st_agent(epart + blockIdx.x, tot);
-  if (!last_workgroup(counter, &s_last)) return;
-  const double E = energy_from_parts(epart, int(gridDim.x), N, wd);
-  if (threadIdx.x == 0) write_record(R, step, E);
+  update_finish(U, acc, wd, &s_last);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -242,11 +188,8 @@ hipError_t launch_recheck(const CandList* cand, const double* g, const double* o
   return hipGetLastError();
 }
 
-hipError_t launch_update(const double* radii, const double* omega, double* g64, float* g32, int N, int M,
-                         double* epart, unsigned int* counter, const RecordArgs& R, int step, hipStream_t s,
-                         hipEvent_t e0, hipEvent_t e1) {
-  launch_ev(k_update, dim3(update_blocks(N)), dim3(kUpdThreads), 0u, s, e0, e1, radii, omega, g64, g32, N, M, epart,
-            counter, R, step);
+hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_ev(k_update, dim3(update_blocks(U.N)), dim3(kUpdThreads), 0u, s, e0, e1, g64, g32, U);
   return hipGetLastError();
 }
 

@@ -1,0 +1,88 @@
+// The remainder update of Sec. 2, eq. (7), per sample, and the record of a
+// finished step: shared by the stand-alone update kernel and the forward
+// DFT's column pass, which applies the previous step's update on the fly.
+#pragma once
+
+#include "afd_select.h"
+
+namespace afd {
+
+// Per-step constants of G' = (G (1 - r w^d) - c s) e^{-2 pi i j/N} / (w^d - r),
+// a = r e^{2 pi i j/N}, z_n = e^{2 pi i n/N}, w^d = e^{2 pi i (n - j)/N},
+// s = sqrt(1 - r^2): the same rational map as eq. (7), written with the
+// sample angles relative to the selected angle.
+struct Blaschke {
+  double r, csx, csy, wjx, wjy;
+  int j;
+};
+
+__device__ __forceinline__ Blaschke blaschke_of(const UpdateArgs& U) {
+  Winner W = *U.R.w;
+  W.m = min(max(W.m, 0), U.M - 1);
+  Blaschke B;
+  B.j = W.j & (U.N - 1);
+  B.r = U.radii[W.m];
+  const double s = sqrt((1.0 - B.r) * (1.0 + B.r));
+  B.wjx = U.omega[2 * B.j];
+  B.wjy = -U.omega[2 * B.j + 1];  // e^{-2 pi i j/N}
+  B.csx = W.cx * s;
+  B.csy = W.cy * s;
+  return B;
+}
+
+__device__ __forceinline__ void blaschke_apply(const Blaschke& B, const double* __restrict__ omega, int N, int n,
+                                               double gx, double gy, double& hx, double& hy) {
+  const int d = (n - B.j) & (N - 1);
+  const double ox = omega[2 * d], oy = omega[2 * d + 1];
+  const double ux = fma(-B.r, ox, 1.0), uy = -B.r * oy;
+  const double nx = fma(gx, ux, -gy * uy) - B.csx;
+  const double ny = fma(gx, uy, gy * ux) - B.csy;
+  const double dx = ox - B.r, dy = oy;
+  const double inv = 1.0 / fma(dx, dx, dy * dy);
+  const double qx = fma(nx, dx, ny * dy) * inv;
+  const double qy = fma(ny, dx, -nx * dy) * inv;
+  hx = fma(qx, B.wjx, -qy * B.wjy);
+  hy = fma(qx, B.wjy, qy * B.wjx);
+}
+
+__device__ __forceinline__ void write_record(const RecordArgs& R, int step, double E) {
+  if (step < 0) {
+    R.energy[0] = E;
+    return;
+  }
+  Winner W = *R.w;
+  W.m = min(max(W.m, 0), R.M - 1);
+  W.j = W.j & (R.N - 1);
+  const double r = R.radii[W.m];
+  R.idx[2 * step] = W.m;
+  R.idx[2 * step + 1] = W.j;
+  R.a[2 * step] = r * R.omega[2 * W.j];
+  R.a[2 * step + 1] = r * R.omega[2 * W.j + 1];
+  R.coef[2 * step] = W.cx;
+  R.coef[2 * step + 1] = W.cy;
+  R.energy[step + 1] = E;
+  R.margin[step] = W.margin;
+  R.kcount[step] = W.kcount;
+  R.flags[step] = W.flags;
+  R.fp32err[step] = W.fp32err;
+}
+
+// energy of the samples from the per-workgroup partial sums, in index order
+__device__ __forceinline__ double energy_from_parts(const double* __restrict__ epart, int nparts, int N,
+                                                    double* wd) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += ld_agent(epart + i);
+  return block_sum_f64(acc, wd) / double(N);
+}
+
+// End of an update launch: publish this workgroup's energy partial; the last
+// workgroup sums them and records the step.  `wd`: LDS double[16], `flag`: LDS int.
+__device__ __forceinline__ void update_finish(const UpdateArgs& U, double acc, double* wd, int* flag) {
+  const double tot = block_sum_f64(acc, wd);
+  if (threadIdx.x == 0) st_agent(U.epart + blockIdx.x, tot);
+  if (!last_workgroup(U.counter, flag)) return;
+  const double E = energy_from_parts(U.epart, int(gridDim.x * gridDim.y * gridDim.z), U.N, wd);
+  if (threadIdx.x == 0) write_record(U.R, U.step, E);
+}
+
+}  // namespace afd
