@@ -144,7 +144,7 @@ Layout layout_of(const Config& c) {
   L.scale = take(real * size_t(c.M));
   L.pq = take(c.big ? 0 : real * size_t(c.M) * c.geom.E);
   L.lsig = take(c.big ? 0 : 4 * size_t(c.M));
-  L.order = take(c.big ? 0 : 4 * size_t(c.M));
+  L.order = take(c.big ? 0 : 8 * size_t(c.M));
   L.heads = take(c.fp64 ? 0 : 8 * size_t(c.big ? c.M : c.nblocks));
   L.g64 = take(16 * size_t(c.N));
   L.g32 = take(c.fp64 ? 0 : 8 * size_t(c.N));
@@ -306,7 +306,12 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     std::vector<int32_t> order(M);
     for (int m = 0; m < M; ++m) order[m] = m;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return lsig[a] > lsig[b]; });
-    if (e == hipSuccess) e = up(p->L.order, order.data(), order.size() * 4);
+    std::vector<int32_t> wi(2 * size_t(M));
+    for (int b = 0; b < M; ++b) {
+      wi[2 * size_t(b)] = order[b];
+      wi[2 * size_t(b) + 1] = lsig[order[b]];
+    }
+    if (e == hipSuccess) e = up(p->L.order, wi.data(), wi.size() * 4);
   }
   const int32_t f0[2] = {p->zero_m < 0 ? 0 : p->zero_m, 0};
   if (e == hipSuccess) e = up(p->L.forced0, f0, sizeof(f0));

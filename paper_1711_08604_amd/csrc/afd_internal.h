@@ -72,7 +72,7 @@ struct RadiusParams {
   const void* pv;     // [M][E]    r_m^(TPR v)
   const void* pq;     // [M][E]    r_m^((TPR/R0) v), R0 the radix of the first pass
   const int* lsig;    // [M]       significant spectrum length: the terms l >= lsig[m] are dropped
-  const int* order;   // [M]       radius of workgroup b when one radius per workgroup (lsig descending)
+  const int* order;   // [M][2]    (radius, lsig) of workgroup b when one radius per workgroup (lsig descending)
   const void* scale;  // [M]       sqrt(1-r^2) / (N (1 - r^N))
   const void* tw;     // Stockham twiddles of the inverse transform
   int M;

@@ -47,8 +47,17 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
   const int tid = threadIdx.x;
   const int rl = tid / TPR, t = tid - rl * TPR;
   // one radius per workgroup: the radii in the order of decreasing
-  // significant spectrum length, so the longest transforms start first
-  const int m = prm.rpb == 1 ? prm.order[blockIdx.x] : int(blockIdx.x) * prm.rpb + rl;
+  // significant spectrum length, so the longest transforms start first; the
+  // radius and its length come in one load
+  int m, L;
+  if (prm.rpb == 1) {
+    const int2 wi = reinterpret_cast<const int2*>(prm.order)[blockIdx.x];
+    m = wi.x;
+    L = wi.y;
+  } else {
+    m = int(blockIdx.x) * prm.rpb + rl;
+    L = prm.lsig[m < prm.M ? m : prm.M - 1];
+  }
   const bool active = m < prm.M;
   const int mm = active ? m : prm.M - 1;
   constexpr size_t region = fft_region_bytes<T, LOGN, SPLIT>();
@@ -64,7 +73,6 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
   // weighted spectrum f(l) = r_m^l c_l for l < L; the weights of the later
   // terms sum to less than 2^-40 (single) / 2^-60 (double precision) and they
   // are dropped
-  const int L = prm.lsig[mm];
   constexpr int R0 = S::radix(0);
   Cx<T> v[E];
   // With L <= N/R0 the first pass (radix R0, inputs x[job + r N/R0]) only
