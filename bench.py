@@ -20,6 +20,7 @@ Prints ONE JSON line on stdout (progress goes to stderr).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -51,6 +52,37 @@ def percentile(xs, q):
     k = (len(xs) - 1) * q
     lo, hi = int(math.floor(k)), int(math.ceil(k))
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+# Measured HBM traffic of the radius kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by a copy of known size), valid only for the sources it was taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_hash() -> str:
+    """sha256 over the kernel sources and the C header (names and contents, sorted by name)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1711_08604_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h")))
+    files.append(os.path.join(ROOT, "include", "afd.h"))
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode() + b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """Bytes per launch for `kernel` if measured on the current sources, else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["bytes_per_launch"])
 
 
 # bytes of the two-pass intermediate per grid value (written once, read once)
@@ -87,9 +119,10 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     peak = PEAK_TFLOPS[prec]
     tname = "double" if prec == "fp64" else "float"
     if n <= (1 << 14):
+        kname = f"k_radius<{tname},{int(math.log2(n))}>"
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": f"k_radius<{tname},{int(math.log2(n))}>",
+                "frac": achieved / peak, "traffic": measured_traffic(kname), "traffic_unit": "bytes/launch",
+                "kernel": kname,
                 "avg_launch_us": avg_kernel_s * 1e6, "launches": k_launches,
                 "flop_per_launch": flop_launch, "grid": [blocks, threads, lds]}
     else:
