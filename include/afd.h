@@ -70,10 +70,15 @@ typedef struct {
                              1.6e-5 at 2^20, about eight times the largest FP32 error of
                              |.|^2 measured at those sizes); the short-list holds at most 256
                              points (flags bit 0 reports a cut)                              */
+  int32_t batch;          /* signals per call, 1..65535 (0 -> 1): independent decompositions of
+                             signals with this N and these radii, run together (every kernel
+                             of a step covers all of them).  batch > 1 needs N <= 2^14.        */
 } afd_plan_desc;
 
 /* Per-decomposition outputs.  Caller-owned; each pointer may be host memory
-   or device memory of the plan's device (detected per pointer).  Layouts:   */
+   or device memory of the plan's device (detected per pointer).  Layouts are
+   for one signal; with batch B every array holds B of them back to back
+   (signal-major: e.g. index is [B][steps][2], energy [B][steps+1]).        */
 typedef struct {
   int32_t* index;         /* 2*steps: (m_k, j_k) per step                          [required] */
   double* a;              /* 2*steps: a_k as interleaved (re, im)                  [required] */
@@ -99,13 +104,15 @@ typedef struct {
    later call of this plan runs.  On success *out receives the plan.
    Errors: AFD_E_INVALID (null pointer, N not a power of two or < 2, M < 1,
    M*N >= 2^31, a radius outside [0,1) or non-finite, recheck_k or
-   recheck_band out of range, first_a_zero without a zero radius),
-   AFD_E_UNSUPPORTED (N > 2^20), AFD_E_NOMEM, AFD_E_HIP.  On error *out is
+   recheck_band out of range, first_a_zero without a zero radius, batch < 0
+   or batch * N * M too large), AFD_E_UNSUPPORTED (N > 2^20, or batch > 1
+   with N > 2^14), AFD_E_NOMEM, AFD_E_HIP.  On error *out is
    set to NULL and nothing is left allocated. */
 afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan* out);
 
 /* Run `steps` >= 0 steps of the maximal-selection loop on `signal` (2*N
-   doubles, interleaved complex128, host or device) and write `out`.
+   doubles, interleaved complex128, host or device; B*2*N for a plan with
+   batch B, signal b at offset 2*N*b) and write `out`.
    Synchronous: returns after the results are in `out`.  The plan's device
    state is overwritten; `signal` is only read.  Errors: AFD_E_INVALID (null
    plan/signal/out or a required out field, steps < 0), AFD_E_NONFINITE,
@@ -118,8 +125,8 @@ afd_status afd_decompose(afd_plan plan, const double* signal, int32_t steps, afd
    forced_index[2k+1] (host or device, 2*steps int32) instead of selecting;
    c_k is then the grid value at that point evaluated in double by the direct
    rule (eq. term81).  Used to compare every step with a reference trajectory
-   past near-ties.  Errors as afd_decompose, plus AFD_E_INVALID for an index
-   outside [0,M) x [0,N). */
+   past near-ties.  With batch B, forced_index is [B][steps][2].  Errors as
+   afd_decompose, plus AFD_E_INVALID for an index outside [0,M) x [0,N). */
 afd_status afd_replay(afd_plan plan, const double* signal, int32_t steps,
                       const int32_t* forced_index, afd_result* out);
 

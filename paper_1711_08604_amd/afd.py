@@ -38,6 +38,7 @@ class PlanDesc(ctypes.Structure):
         ("recheck_k", ctypes.c_int32),
         ("first_a_zero", ctypes.c_int32),
         ("recheck_band", ctypes.c_double),
+        ("batch", ctypes.c_int32),
     ]
 
 
@@ -104,7 +105,7 @@ def _check(status: int):
         raise AfdError(status, msg)
 
 
-def _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band):
+def _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch=1):
     radii = np.ascontiguousarray(np.asarray(radii, dtype=np.float64))
     d = PlanDesc()
     d.n = int(n)
@@ -114,17 +115,20 @@ def _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band):
     d.recheck_k = int(recheck_k)
     d.first_a_zero = 1 if first_a_zero else 0
     d.recheck_band = float(recheck_band)
+    d.batch = int(batch)
     return d, radii
 
 
-def workspace_bytes(n, radii, precision="fp64", recheck_k=8, first_a_zero=False, recheck_band=0.0) -> int:
+def workspace_bytes(n, radii, precision="fp64", recheck_k=8, first_a_zero=False, recheck_band=0.0,
+                    batch=1) -> int:
     lib = load_library()
-    d, keep = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band)
+    d, keep = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch)
     return int(lib.afd_workspace_bytes(ctypes.byref(d)))
 
 
 @dataclass
 class Result:
+    # shapes for one signal; a batched plan adds a leading batch dimension
     index: object      # (steps, 2) int32: (m_k, j_k)
     a: object          # (steps,) complex128
     coef: object       # (steps,) complex128
@@ -145,14 +149,16 @@ def _is_torch_cuda(x) -> bool:
 
 
 class Plan:
-    """A decomposition plan: N samples, the radius grid, the precision mode."""
+    """A decomposition plan: N samples, the radius grid, the precision mode;
+    batch > 1 decomposes that many signals of length N together."""
 
     def __init__(self, n, radii, precision="fp64", recheck_k=8, first_a_zero=False, recheck_band=0.0,
-                 stream=None):
+                 stream=None, batch=1):
         self._lib = load_library()
         self.n = int(n)
         self.precision = precision
-        d, self._radii = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band)
+        self.batch = int(batch)
+        d, self._radii = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, self.batch)
         self.m = int(self._radii.shape[0])
         self._stream = stream
         h = ctypes.c_void_p()
@@ -179,33 +185,19 @@ class Plan:
 
     # -- running
     def _outputs(self, signal, steps):
+        lead = (self.batch,) if self.batch > 1 else ()
+        shapes = {"index": ((steps, 2), "i32"), "a": ((steps,), "c128"), "coef": ((steps,), "c128"),
+                  "energy": ((steps + 1,), "f64"), "margin": ((steps,), "f64"), "remainder": ((self.n,), "c128"),
+                  "recheck_count": ((steps,), "i32"), "flags": ((steps,), "i32"), "fp32_error": ((steps,), "f64")}
         if _is_torch_cuda(signal):
             import torch
             dev = signal.device
-            out = Result(
-                index=torch.empty((steps, 2), dtype=torch.int32, device=dev),
-                a=torch.empty((steps,), dtype=torch.complex128, device=dev),
-                coef=torch.empty((steps,), dtype=torch.complex128, device=dev),
-                energy=torch.empty((steps + 1,), dtype=torch.float64, device=dev),
-                margin=torch.empty((steps,), dtype=torch.float64, device=dev),
-                remainder=torch.empty((self.n,), dtype=torch.complex128, device=dev),
-                recheck_count=torch.empty((steps,), dtype=torch.int32, device=dev),
-                flags=torch.empty((steps,), dtype=torch.int32, device=dev),
-                fp32_error=torch.empty((steps,), dtype=torch.float64, device=dev),
-            )
+            dt = {"i32": torch.int32, "f64": torch.float64, "c128": torch.complex128}
+            out = Result(**{k: torch.empty(lead + shp, dtype=dt[t], device=dev) for k, (shp, t) in shapes.items()})
             ptr = lambda t: t.data_ptr()  # noqa: E731
         else:
-            out = Result(
-                index=np.empty((steps, 2), dtype=np.int32),
-                a=np.empty(steps, dtype=np.complex128),
-                coef=np.empty(steps, dtype=np.complex128),
-                energy=np.empty(steps + 1, dtype=np.float64),
-                margin=np.empty(steps, dtype=np.float64),
-                remainder=np.empty(self.n, dtype=np.complex128),
-                recheck_count=np.empty(steps, dtype=np.int32),
-                flags=np.empty(steps, dtype=np.int32),
-                fp32_error=np.empty(steps, dtype=np.float64),
-            )
+            dt = {"i32": np.int32, "f64": np.float64, "c128": np.complex128}
+            out = Result(**{k: np.empty(lead + shp, dtype=dt[t]) for k, (shp, t) in shapes.items()})
             ptr = lambda a: a.ctypes.data  # noqa: E731
         rd = ResultDesc()
         for name in ("index", "a", "coef", "energy", "margin", "remainder", "recheck_count", "flags", "fp32_error"):
@@ -213,16 +205,20 @@ class Plan:
         return out, rd
 
     def _signal_ptr(self, signal):
+        total = self.n * self.batch
         if _is_torch_cuda(signal):
             import torch
             if signal.dtype == torch.float64:
-                assert signal.numel() == 2 * self.n and signal.is_contiguous()
+                ok = signal.numel() == 2 * total
             else:
-                assert signal.dtype == torch.complex128 and signal.numel() == self.n and signal.is_contiguous()
+                ok = signal.dtype == torch.complex128 and signal.numel() == total
+            if not (ok and signal.is_contiguous()):
+                raise ValueError(f"signal must be {self.batch} x {self.n} contiguous complex128")
             return signal.data_ptr(), signal
         arr = np.ascontiguousarray(np.asarray(signal, dtype=np.complex128))
-        if arr.shape != (self.n,):
-            raise ValueError(f"signal must have shape ({self.n},)")
+        want = (self.batch, self.n) if self.batch > 1 else (self.n,)
+        if arr.shape != want:
+            raise ValueError(f"signal must have shape {want}")
         return arr.ctypes.data, arr
 
     def decompose(self, signal, steps: int) -> Result:
@@ -237,7 +233,9 @@ class Plan:
         if _is_torch_cuda(forced):
             fptr, fkeep = forced.data_ptr(), forced
         else:
-            fkeep = np.ascontiguousarray(np.asarray(forced, dtype=np.int32).reshape(-1, 2))
+            fkeep = np.ascontiguousarray(np.asarray(forced, dtype=np.int32))
+            if fkeep.size != 2 * int(steps) * self.batch:
+                raise ValueError("forced must hold (m, j) for every step of every signal")
             fptr = fkeep.ctypes.data
         _check(self._lib.afd_replay(self._h, ctypes.c_void_p(sp), int(steps), ctypes.c_void_p(fptr),
                                     ctypes.byref(rd)))

@@ -68,6 +68,7 @@ struct Config {
   int nblocks;
   int nch;
   int nparts;
+  int batch;    // signals per call
   bool big;     // N > 2^kMaxLdsLogN: two-pass radius transforms
   BigGeom bg;
   int chunk;    // radii per two-pass chunk
@@ -95,10 +96,16 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     if (r == 0.0) has_zero = true;
   }
   if (d->first_a_zero && !has_zero) return fail(AFD_E_INVALID, "first_a_zero needs a radius equal to 0");
+  if (d->batch < 0 || d->batch > 65535) return fail(AFD_E_INVALID, "batch must be in 0..65535");
+  const int batch = d->batch == 0 ? 1 : d->batch;
+  if (batch > 1 && logn > kMaxLdsLogN) return fail(AFD_E_UNSUPPORTED, "batch > 1 needs N <= 2^14");
+  if (int64_t(batch) * d->n * d->m >= (int64_t(1) << 40) || int64_t(batch) * d->n >= (int64_t(1) << 31))
+    return fail(AFD_E_INVALID, "batch * N (* M) too large");
   if (cfg) {
     cfg->logn = logn;
     cfg->N = d->n;
     cfg->M = d->m;
+    cfg->batch = batch;
     cfg->fp64 = d->precision == AFD_FP64;
     cfg->fwd = fwd_plan(logn, cfg->fp64);
     cfg->nch = recheck_chunks(int(d->n));
@@ -145,24 +152,26 @@ Layout layout_of(const Config& c) {
   L.pq = take(c.big ? 0 : real * size_t(c.M) * c.geom.E);
   L.lsig = take(c.big ? 0 : 4 * size_t(c.M));
   L.order = take(c.big ? 0 : 8 * size_t(c.M));
-  L.heads = take(c.fp64 ? 0 : 8 * size_t(c.big ? c.M : c.nblocks));
-  L.g64 = take(16 * size_t(c.N));
-  L.g32 = take(c.fp64 ? 0 : 8 * size_t(c.N));
-  L.c = take(2 * real * size_t(c.N));
-  L.xt = take(c.fwd.two_pass ? 2 * real * size_t(c.N) : 0);
-  L.blocks = take((c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.nblocks));
+  // per-signal buffers: `batch` copies back to back
+  const size_t B = size_t(c.batch);
+  L.heads = take(c.fp64 ? 0 : 8 * size_t(c.big ? c.M : c.nblocks) * B);
+  L.g64 = take(16 * size_t(c.N) * B);
+  L.g32 = take(c.fp64 ? 0 : 8 * size_t(c.N) * B);
+  L.c = take(2 * real * size_t(c.N) * B);
+  L.xt = take(c.fwd.two_pass ? 2 * real * size_t(c.N) * B : 0);
+  L.blocks = take((c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.nblocks) * B);
   L.wl = take(c.big ? 2 * real * (size_t(1) << c.bg.sw) : 0);
   L.wh = take(c.big ? 2 * real * (size_t(1) << (c.logn - c.bg.sw)) : 0);
   L.z = take(c.big ? 2 * real * size_t(c.chunk) * size_t(c.N) : 0);
   L.rrec = take(c.big ? (c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.M) : 0);
   L.bcounters = take(c.big ? 4 * (size_t(c.chunk) + 1) : 0);
-  L.cand = take(sizeof(CandList));
-  L.partials = take(16 * size_t(kKMax) * c.nch);
-  L.winner = take(sizeof(Winner));
-  L.epart = take(8 * size_t(c.nparts));
+  L.cand = take(sizeof(CandList) * B);
+  L.partials = take(16 * size_t(kKMax) * c.nch * B);
+  L.winner = take(sizeof(Winner) * B);
+  L.epart = take(8 * size_t(c.nparts) * B);
   L.nonfinite = take(4);
   L.forced0 = take(8);
-  L.counters = take(4 * kNumCounters);
+  L.counters = take(4 * kNumCounters * B);  // [kind][signal]
   L.total = o;
   return L;
 }
@@ -316,7 +325,7 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   const int32_t f0[2] = {p->zero_m < 0 ? 0 : p->zero_m, 0};
   if (e == hipSuccess) e = up(p->L.forced0, f0, sizeof(f0));
   if (e == hipSuccess) e = hipMemset(p->arena + p->L.nonfinite, 0, 4);
-  if (e == hipSuccess) e = hipMemset(p->arena + p->L.counters, 0, 4 * kNumCounters);
+  if (e == hipSuccess) e = hipMemset(p->arena + p->L.counters, 0, 4 * kNumCounters * size_t(c.batch));
   if (e == hipSuccess && c.big) e = hipMemset(p->arena + p->L.bcounters, 0, 4 * (size_t(c.chunk) + 1));
   if (e != hipSuccess) return hip_fail(e, "uploading plan tables");
   return AFD_OK;
@@ -335,7 +344,7 @@ struct ResPtrs {
   size_t total;
 };
 
-ResPtrs res_layout(unsigned char* base, int steps) {
+ResPtrs res_layout(unsigned char* base, int steps, int batch) {
   ResPtrs r{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -343,15 +352,16 @@ ResPtrs res_layout(unsigned char* base, int steps) {
     o = align_up(o + bytes, 256);
     return base + at;
   };
-  const size_t s = size_t(steps < 1 ? 1 : steps);
-  r.idx = reinterpret_cast<int32_t*>(take(8 * s));
-  r.a = reinterpret_cast<double*>(take(16 * s));
-  r.coef = reinterpret_cast<double*>(take(16 * s));
-  r.energy = reinterpret_cast<double*>(take(8 * (s + 1)));
-  r.margin = reinterpret_cast<double*>(take(8 * s));
-  r.kcount = reinterpret_cast<int32_t*>(take(4 * s));
-  r.flags = reinterpret_cast<int32_t*>(take(4 * s));
-  r.fp32err = reinterpret_cast<double*>(take(8 * s));
+  // signal-major: signal b's arrays follow signal b-1's
+  const size_t s = size_t(steps < 1 ? 1 : steps), B = size_t(batch);
+  r.idx = reinterpret_cast<int32_t*>(take(8 * s * B));
+  r.a = reinterpret_cast<double*>(take(16 * s * B));
+  r.coef = reinterpret_cast<double*>(take(16 * s * B));
+  r.energy = reinterpret_cast<double*>(take(8 * (s + 1) * B));
+  r.margin = reinterpret_cast<double*>(take(8 * s * B));
+  r.kcount = reinterpret_cast<int32_t*>(take(4 * s * B));
+  r.flags = reinterpret_cast<int32_t*>(take(4 * s * B));
+  r.fp32err = reinterpret_cast<double*>(take(8 * s * B));
   r.total = o;
   return r;
 }
@@ -362,7 +372,7 @@ afd_status ensure_res(afd_plan_s* p, int steps) {
     (void)hipFree(p->res);
     p->res = nullptr;
   }
-  const size_t bytes = res_layout(nullptr, steps).total;
+  const size_t bytes = res_layout(nullptr, steps, p->cfg.batch).total;
   hipError_t e = hipMalloc(&p->res, bytes);
   if (e != hipSuccess) {
     p->res = nullptr;
@@ -378,7 +388,7 @@ afd_status ensure_forced(afd_plan_s* p, int steps) {
     (void)hipFree(p->forced);
     p->forced = nullptr;
   }
-  hipError_t e = hipMalloc(&p->forced, 8 * size_t(steps < 1 ? 1 : steps));
+  hipError_t e = hipMalloc(&p->forced, 8 * size_t(steps < 1 ? 1 : steps) * size_t(p->cfg.batch));
   if (e != hipSuccess) {
     p->forced = nullptr;
     return fail(AFD_E_NOMEM, std::string("forced indices: ") + hipGetErrorString(e));
@@ -440,32 +450,33 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     return fail(AFD_E_INVALID, "out.energy (and out.index, out.a, out.coef when steps > 0) are required");
   const Config& c = p->cfg;
   const int N = int(c.N);
+  const int B = c.batch;
   HIPCHK(hipSetDevice(p->device), "hipSetDevice");
 
   const bool sig_dev = is_device_pointer(signal);
   if (!sig_dev) {
-    for (int64_t i = 0; i < 2 * c.N; ++i)
+    for (int64_t i = 0; i < 2 * c.N * B; ++i)
       if (!std::isfinite(signal[i])) return fail(AFD_E_NONFINITE, "signal holds NaN or Inf");
   }
   std::vector<int32_t> forced_host;
   if (forced_user) {
-    forced_host.resize(2 * size_t(steps));
+    const size_t nf = 2 * size_t(steps) * size_t(B);
+    forced_host.resize(nf);
     if (steps > 0)
-      HIPCHK(hipMemcpy(forced_host.data(), forced_user, 8 * size_t(steps), hipMemcpyDefault), "reading forced indices");
-    for (int k = 0; k < steps; ++k) {
-      if (forced_host[2 * k] < 0 || forced_host[2 * k] >= c.M || forced_host[2 * k + 1] < 0 ||
-          forced_host[2 * k + 1] >= N)
+      HIPCHK(hipMemcpy(forced_host.data(), forced_user, 4 * nf, hipMemcpyDefault), "reading forced indices");
+    for (size_t k = 0; k < nf; k += 2) {
+      if (forced_host[k] < 0 || forced_host[k] >= c.M || forced_host[k + 1] < 0 || forced_host[k + 1] >= N)
         return fail(AFD_E_INVALID, "forced index outside [0,M) x [0,N)");
     }
     afd_status st = ensure_forced(p, steps);
     if (st != AFD_OK) return st;
     if (steps > 0)
-      HIPCHK(hipMemcpyAsync(p->forced, forced_host.data(), 8 * size_t(steps), hipMemcpyHostToDevice, p->stream),
+      HIPCHK(hipMemcpyAsync(p->forced, forced_host.data(), 4 * nf, hipMemcpyHostToDevice, p->stream),
              "uploading forced indices");
   }
   afd_status st = ensure_res(p, steps);
   if (st != AFD_OK) return st;
-  const ResPtrs R = res_layout(p->res, steps);
+  const ResPtrs R = res_layout(p->res, steps, B);
 
   hipStream_t s = p->stream;
   double* g64 = p->at<double>(p->L.g64);
@@ -487,6 +498,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rec.omega = omega;
   rec.N = N;
   rec.M = c.M;
+  rec.steps = steps;
   rec.idx = R.idx;
   rec.a = R.a;
   rec.coef = R.coef;
@@ -498,12 +510,14 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
 
   // flags and last-workgroup counters start at zero (also after an aborted call)
   HIPCHK(hipMemsetAsync(nonfinite, 0, 4, s), "clearing flag");
-  HIPCHK(hipMemsetAsync(counters, 0, 4 * kNumCounters, s), "clearing counters");
+  HIPCHK(hipMemsetAsync(counters, 0, 4 * kNumCounters * size_t(B), s), "clearing counters");
   if (c.big)
     HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4 * (size_t(c.chunk) + 1), s), "clearing counters");
-  HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N), sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
+  HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N) * B, sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        s),
          "copying signal");
-  HIPCHK(launch_prepare(g64, g32, N, epart, nonfinite, counters + 3, rec, s), "k_prepare");
+  // counters are [kind][signal]: radius, recheck, update, prepare, FP32 fallback flags
+  HIPCHK(launch_prepare(g64, g32, N, epart, nonfinite, counters + 3 * B, rec, B, s), "k_prepare");
 
   RadiusParams rp{};
   rp.c = cspec;
@@ -519,9 +533,9 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.tau_band = p->tau_band;
   rp.recheck_k = p->recheck_k;
   rp.out = p->at<void>(p->L.blocks);
-  rp.counter = counters + 0;
+  rp.counter = counters + 0 * B;
   rp.heads = p->at<uint64_t>(p->L.heads);
-  rp.flagword = counters + 4;
+  rp.flagword = counters + 4 * B;
   rp.cand = cand;
   rp.winner = win;
 
@@ -545,7 +559,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     bp.counter_r = p->at<unsigned int>(p->L.bcounters);
     bp.counter_g = p->at<unsigned int>(p->L.bcounters) + c.chunk;
     bp.heads = p->at<uint64_t>(p->L.heads);
-    bp.flagword = counters + 4;
+    bp.flagword = counters + 4 * B;
     bp.cand = cand;
     bp.winner = win;
   }
@@ -557,7 +571,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   upd.N = N;
   upd.M = c.M;
   upd.epart = epart;
-  upd.counter = counters + 2;
+  upd.counter = counters + 2 * B;
   upd.R = rec;
   for (int k = 0; k < steps; ++k) {
     const int32_t* fsrc = nullptr;
@@ -569,14 +583,14 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       fstep = 0;
     }
     if (fsrc) {
-      HIPCHK(launch_force(fsrc, fstep, N, cand, s), "k_force");
-      HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1, win, s), "k_recheck");
+      HIPCHK(launch_force(fsrc, forced_user ? 2 * steps : 0, fstep, N, cand, B, s), "k_force");
+      HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1 * B, win, B, s), "k_recheck");
     } else {
       hipEvent_t e0, e1;
       HIPCHK(tm.pair(kTimeFft, &e0, &e1), "event");
       HIPCHK(launch_fwd(c.logn, c.fp64, c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32),
-                        p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega, p->at<void>(p->L.xt), cspec, s, e0,
-                        e1),
+                        p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega, p->at<void>(p->L.xt), cspec, B, s,
+                        e0, e1),
              "forward DFT");
       HIPCHK(tm.pair(kTimeRadius, &e0, &e1), "event");
       if (c.big) {
@@ -588,15 +602,15 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
                  "k_big");
         }
       } else {
-        HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, s, e0, e1), "k_radius");
+        HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, B, s, e0, e1), "k_radius");
       }
       if (!c.fp64)
-        HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1, win, s), "k_recheck");
+        HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1 * B, win, B, s), "k_recheck");
     }
     hipEvent_t u0, u1;
     HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
     upd.step = k;
-    HIPCHK(launch_update(g64, g32, upd, s, u0, u1), "k_update");
+    HIPCHK(launch_update(g64, g32, upd, B, s, u0, u1), "k_update");
   }
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, nonfinite, 4, hipMemcpyDeviceToHost, s), "reading flag");
@@ -604,19 +618,20 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   HIPCHK(tm.collect(), "hipEventElapsedTime");
   if (bad) return fail(AFD_E_NONFINITE, "signal holds NaN or Inf");
 
-  const size_t S = size_t(steps);
+  // staged signal-major with per-signal stride `steps`: the caller's layout
+  const size_t S = size_t(steps), BB = size_t(B);
   auto cp = [&](void* dst, const void* src, size_t bytes) {
     return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s) : hipSuccess;
   };
-  HIPCHK(cp(out->index, R.idx, 8 * S), "copy index");
-  HIPCHK(cp(out->a, R.a, 16 * S), "copy a");
-  HIPCHK(cp(out->coef, R.coef, 16 * S), "copy coef");
-  HIPCHK(cp(out->energy, R.energy, 8 * (S + 1)), "copy energy");
-  if (out->margin) HIPCHK(cp(out->margin, R.margin, 8 * S), "copy margin");
-  if (out->recheck_count) HIPCHK(cp(out->recheck_count, R.kcount, 4 * S), "copy recheck_count");
-  if (out->flags) HIPCHK(cp(out->flags, R.flags, 4 * S), "copy flags");
-  if (out->fp32_error) HIPCHK(cp(out->fp32_error, R.fp32err, 8 * S), "copy fp32_error");
-  if (out->remainder) HIPCHK(cp(out->remainder, g64, 16 * size_t(N)), "copy remainder");
+  HIPCHK(cp(out->index, R.idx, 8 * S * BB), "copy index");
+  HIPCHK(cp(out->a, R.a, 16 * S * BB), "copy a");
+  HIPCHK(cp(out->coef, R.coef, 16 * S * BB), "copy coef");
+  HIPCHK(cp(out->energy, R.energy, 8 * (S + 1) * BB), "copy energy");
+  if (out->margin) HIPCHK(cp(out->margin, R.margin, 8 * S * BB), "copy margin");
+  if (out->recheck_count) HIPCHK(cp(out->recheck_count, R.kcount, 4 * S * BB), "copy recheck_count");
+  if (out->flags) HIPCHK(cp(out->flags, R.flags, 4 * S * BB), "copy flags");
+  if (out->fp32_error) HIPCHK(cp(out->fp32_error, R.fp32err, 8 * S * BB), "copy fp32_error");
+  if (out->remainder) HIPCHK(cp(out->remainder, g64, 16 * size_t(N) * BB), "copy remainder");
   HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
   g_last_error.clear();
   return AFD_OK;

@@ -31,6 +31,8 @@ __global__ __launch_bounds__((fwd_threads<T, LOGN>())) void k_fft_fwd(const Cx<T
   using S = Shape<LOGN, E>;
   extern __shared__ __align__(16) unsigned char smem[];
   const int t = threadIdx.x;
+  g += size_t(S::N) * blockIdx.y;  // signal of a batch
+  c += size_t(S::N) * blockIdx.y;
   Cx<T> v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = g[t + S::TPR * i];
@@ -69,6 +71,8 @@ __global__ __launch_bounds__((cols_threads<T, LOGN>())) void k_fwd_cols(const Cx
   extern __shared__ __align__(16) unsigned char smem[];
   const int ci = threadIdx.x % kColsPerBlock, t = threadIdx.x / kColsPerBlock;
   const int l1 = blockIdx.x * kColsPerBlock + ci;
+  x += size_t(N) * blockIdx.y;  // signal of a batch
+  xt += size_t(N) * blockIdx.y;
   unsigned char* region = smem + size_t(ci) * fft_region_bytes<T, P::L2, false>();
   Cx<T> v[E2];
 #pragma unroll
@@ -98,6 +102,8 @@ __global__ __launch_bounds__((rows_threads<T, LOGN>())) void k_fwd_rows(const Cx
   const int ri = COLS ? int(threadIdx.x) / S1::TPR : int(threadIdx.x) % kColsPerBlock;
   const int t = COLS ? int(threadIdx.x) % S1::TPR : int(threadIdx.x) / kColsPerBlock;
   const int k2 = blockIdx.x * kColsPerBlock + ri;
+  xt += (size_t(1) << LOGN) * blockIdx.y;  // signal of a batch
+  c += (size_t(1) << LOGN) * blockIdx.y;
   unsigned char* region = smem + size_t(ri) * fft_region_bytes<T, P::L1, false>();
   Cx<T> v[E1];
 #pragma unroll
@@ -228,11 +234,11 @@ hipError_t setup_fwd_attributes() {
 
 template <typename T, int LOGN>
 static hipError_t launch_fwd_t(const void* g, const void* tw1, const void* tw2, const double* omega, void* xt,
-                               void* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                               void* c, int batch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if constexpr (LOGN < kFwdTwoPassMin) {
     constexpr int thr = fwd_threads<T, LOGN>();
     constexpr size_t lds = fft_region_bytes<T, LOGN, pickSplit<T, LOGN>()>();
-    launch_ev(k_fft_fwd<T, LOGN>, dim3(1), dim3(thr), uint32_t(lds), s, e0, e1, reinterpret_cast<const Cx<T>*>(g),
+    launch_ev(k_fft_fwd<T, LOGN>, dim3(1, batch), dim3(thr), uint32_t(lds), s, e0, e1, reinterpret_cast<const Cx<T>*>(g),
               reinterpret_cast<const Cx<T>*>(tw1), reinterpret_cast<Cx<T>*>(c));
   } else {
     using P = Split2<LOGN>;
@@ -240,10 +246,11 @@ static hipError_t launch_fwd_t(const void* g, const void* tw1, const void* tw2, 
     constexpr int thr_r = rows_threads<T, LOGN>();
     constexpr size_t lds_c = kColsPerBlock * fft_region_bytes<T, P::L2, false>();
     constexpr size_t lds_r = kColsPerBlock * fft_region_bytes<T, P::L1, false>();
-    launch_ev(k_fwd_cols<T, LOGN>, dim3(P::N1 / kColsPerBlock), dim3(thr_c), uint32_t(lds_c), s, e0, nullptr,
+    launch_ev(k_fwd_cols<T, LOGN>, dim3(P::N1 / kColsPerBlock, batch), dim3(thr_c), uint32_t(lds_c), s, e0, nullptr,
               reinterpret_cast<const Cx<T>*>(g), reinterpret_cast<const Cx<T>*>(tw2), omega,
               reinterpret_cast<Cx<T>*>(xt));
-    launch_ev(k_fwd_rows<T, LOGN, fwd_cols_out<LOGN>()>, dim3(P::N2 / kColsPerBlock), dim3(thr_r), uint32_t(lds_r), s,
+    launch_ev(k_fwd_rows<T, LOGN, fwd_cols_out<LOGN>()>, dim3(P::N2 / kColsPerBlock, batch), dim3(thr_r),
+              uint32_t(lds_r), s,
               nullptr, e1, reinterpret_cast<const Cx<T>*>(xt), reinterpret_cast<const Cx<T>*>(tw1),
               reinterpret_cast<Cx<T>*>(c));
   }
@@ -251,12 +258,12 @@ static hipError_t launch_fwd_t(const void* g, const void* tw1, const void* tw2, 
 }
 
 hipError_t launch_fwd(int logn, bool fp64, const void* g, const void* tw1, const void* tw2, const double* omega,
-                      void* xt, void* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                      void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (logn) {
-#define X(L)                                                                       \
-  case L:                                                                          \
-    return fp64 ? launch_fwd_t<double, L>(g, tw1, tw2, omega, xt, c, s, e0, e1)    \
-                : launch_fwd_t<float, L>(g, tw1, tw2, omega, xt, c, s, e0, e1);
+#define X(L)                                                                              \
+  case L:                                                                                 \
+    return fp64 ? launch_fwd_t<double, L>(g, tw1, tw2, omega, xt, c, batch, s, e0, e1)    \
+                : launch_fwd_t<float, L>(g, tw1, tw2, omega, xt, c, batch, s, e0, e1);
     AFD_FWD_ALL_LOGN_CASES(X)
 #undef X
     default:

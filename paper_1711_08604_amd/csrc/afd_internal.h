@@ -136,6 +136,7 @@ struct RecordArgs {
   const double* radii;
   const double* omega;
   int N, M;
+  int steps;  // per-signal length of the step arrays (batched plans hold signals back to back)
   int32_t* idx;
   double* a;
   double* coef;
@@ -212,16 +213,20 @@ inline void launch_ev(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t
 hipError_t setup_radius_attributes();
 hipError_t setup_fwd_attributes();
 
+// Batched launches cover `batch` signals (grid dimension y, or z for the
+// re-check); each signal's buffers follow the previous signal's.
 hipError_t launch_fwd(int logn, bool fp64, const void* g, const void* tw1, const void* tw2, const double* omega,
-                      void* xt, void* c, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, hipStream_t s,
+                      void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, int batch, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* nonfinite, unsigned int* counter,
-                          const RecordArgs& R, hipStream_t s);
-hipError_t launch_force(const int32_t* forced, int step, int N, CandList* cand, hipStream_t s);
+                          const RecordArgs& R, int batch, hipStream_t s);
+// forced: per signal `fstride` int32 apart (0: the same point for every signal)
+hipError_t launch_force(const int32_t* forced, int fstride, int step, int N, CandList* cand, int batch,
+                        hipStream_t s);
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
-                          double* partials, unsigned int* counter, Winner* w, hipStream_t s);
-hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, hipStream_t s, hipEvent_t e0 = nullptr,
-                         hipEvent_t e1 = nullptr);
+                          double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s);
+hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, int batch, hipStream_t s,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 }  // namespace afd

@@ -64,7 +64,9 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
   unsigned char* lds_r = smem + size_t(rl) * region;
   unsigned char* scratch = smem + size_t(prm.rpb) * region;
 
-  const Cx<T>* __restrict__ c = reinterpret_cast<const Cx<T>*>(prm.c);
+  // signal b of a batch: its spectrum, workgroup records, counter, short-list / winner
+  const int b = blockIdx.y;
+  const Cx<T>* __restrict__ c = reinterpret_cast<const Cx<T>*>(prm.c) + size_t(N) * b;
   const T* __restrict__ pw = reinterpret_cast<const T*>(prm.pw);
   const T* __restrict__ pv = reinterpret_cast<const T*>(prm.pv);
   const T* __restrict__ scale = reinterpret_cast<const T*>(prm.scale);
@@ -121,20 +123,24 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
     const uint32_t r0 = prm.rpb == 1 ? uint32_t(mm) : uint32_t(blockIdx.x) * uint32_t(prm.rpb);
     const uint32_t ract = uint32_t(prm.M) - r0 < uint32_t(prm.rpb) ? uint32_t(prm.M) - r0 : uint32_t(prm.rpb);
     const FlatOrder ord{r0 * uint32_t(N), ract * uint32_t(N), 0u, ract * uint32_t(N)};
-    select_list<LOGN>(v, active, sc, fbase, 1u, t, scratch, prm.tau_band, ord,
-                      reinterpret_cast<BlockList32*>(prm.out) + blockIdx.x, prm.heads + blockIdx.x, prm.flagword);
+    BlockList32* lists = reinterpret_cast<BlockList32*>(prm.out) + size_t(gridDim.x) * b;
+    uint64_t* heads = prm.heads + size_t(gridDim.x) * b;
+    select_list<LOGN>(v, active, sc, fbase, 1u, t, scratch, prm.tau_band, ord, lists + blockIdx.x,
+                      heads + blockIdx.x, prm.flagword + b);
   } else {
     select_best<LOGN, T>(v, active, sc, fbase, 1u, t, reinterpret_cast<Best*>(scratch),
-                         reinterpret_cast<BlockBest64*>(prm.out) + blockIdx.x);
+                         reinterpret_cast<BlockBest64*>(prm.out) + size_t(gridDim.x) * b + blockIdx.x);
   }
 
-  if (!last_workgroup(prm.counter, &s_last)) return;
+  if (!last_arrival(prm.counter + b, gridDim.x, &s_last)) return;
   MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
   if constexpr (LIST) {
-    select32_tail(reinterpret_cast<const BlockList32*>(prm.out), prm.heads, int(gridDim.x), prm.recheck_k,
-                  prm.tau_band, prm.flagword, prm.cand, Sm);
+    select32_tail(reinterpret_cast<const BlockList32*>(prm.out) + size_t(gridDim.x) * b,
+                  prm.heads + size_t(gridDim.x) * b, int(gridDim.x), prm.recheck_k, prm.tau_band, prm.flagword + b,
+                  prm.cand + b, Sm);
   } else {
-    merge64_tail(reinterpret_cast<const BlockBest64*>(prm.out), int(gridDim.x), N, LOGN, prm.winner, Sm);
+    merge64_tail(reinterpret_cast<const BlockBest64*>(prm.out) + size_t(gridDim.x) * b, int(gridDim.x), N, LOGN,
+                 prm.winner + b, Sm);
   }
 }
 
@@ -198,19 +204,19 @@ hipError_t setup_radius_attributes() {
   return e;
 }
 
-hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, hipStream_t s, hipEvent_t e0,
-                         hipEvent_t e1) {
+hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, int batch, hipStream_t s,
+                         hipEvent_t e0, hipEvent_t e1) {
   switch (logn) {
 #define X(L)                                                                                 \
   case L: {                                                                                  \
     if (fp64) {                                                                              \
       constexpr int thr = radius_threads<double, L>();                                       \
       const size_t lds = radius_lds<double, L>(p.rpb);                                       \
-      launch_ev(k_radius<double, L, false>, dim3(blocks), dim3(thr), uint32_t(lds), s, e0, e1, p); \
+      launch_ev(k_radius<double, L, false>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, p); \
     } else {                                                                                 \
       constexpr int thr = radius_threads<float, L>();                                        \
       const size_t lds = radius_lds<float, L>(p.rpb);                                        \
-      launch_ev(k_radius<float, L, true>, dim3(blocks), dim3(thr), uint32_t(lds), s, e0, e1, p);   \
+      launch_ev(k_radius<float, L, true>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, p);   \
     }                                                                                        \
     return hipGetLastError();                                                                \
   }

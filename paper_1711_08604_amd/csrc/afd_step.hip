@@ -19,11 +19,19 @@ constexpr int kRecheckBlocksX = 16;
 int update_blocks(int N) { return (N + kUpdThreads * kUpdPerThread - 1) / (kUpdThreads * kUpdPerThread); }
 int recheck_chunks(int N) { return N >= 2048 ? N / 2048 : 1; }
 
+// Batched launches: signal b = blockIdx.y (blockIdx.z in k_recheck) works on
+// its own slices of every per-signal buffer.
 __global__ __launch_bounds__(256) void k_prepare(double* __restrict__ g64, float* __restrict__ g32, int N,
                                                  double* __restrict__ epart, int* __restrict__ nonfinite,
                                                  unsigned int* __restrict__ counter, RecordArgs R) {
   __shared__ double wd[16];
   __shared__ int s_last;
+  const int b = blockIdx.y;
+  g64 += 2 * size_t(N) * b;
+  if (g32) g32 += 2 * size_t(N) * b;
+  epart += size_t(gridDim.x) * b;
+  counter += b;
+  R = record_of(R, b);
   double acc = 0.0;
   int bad = 0;
 #pragma unroll
@@ -42,12 +50,16 @@ __global__ __launch_bounds__(256) void k_prepare(double* __restrict__ g64, float
   if (bad) atomicOr(nonfinite, 1);
   const double tot = block_sum_f64(acc, wd);
   if (threadIdx.x == 0) st_agent(epart + blockIdx.x, tot);
-  if (!last_workgroup(counter, &s_last)) return;
+  if (!last_arrival(counter, gridDim.x, &s_last)) return;
   const double E = energy_from_parts(epart, int(gridDim.x), N, wd);
   if (threadIdx.x == 0) write_record(R, -1, E);
 }
 
-__global__ void k_force(const int32_t* __restrict__ forced, int step, int N, CandList* __restrict__ cand) {
+__global__ void k_force(const int32_t* __restrict__ forced, int fstride, int step, int N,
+                        CandList* __restrict__ cand) {
+  const int b = blockIdx.x;
+  forced += size_t(fstride) * b;
+  cand += b;
   if (threadIdx.x == 0) {
     const uint32_t m = uint32_t(forced[2 * step]), j = uint32_t(forced[2 * step + 1]);
     cand->count = 1;
@@ -111,6 +123,12 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
   __shared__ int s_last;
   const int chunk = blockIdx.y;
   const int cl = N / nch;
+  const int b = blockIdx.z;
+  cand += b;
+  g += 2 * size_t(N) * b;
+  partials += 2 * size_t(kKMax) * size_t(nch) * b;
+  counter += b;
+  w += b;
   const int count = cand->count;
   for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const uint32_t f = key_f(cand->keys[i]);
@@ -133,13 +151,19 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
       st_agent(partials + 2 * (size_t(i) * nch + chunk) + 1, sy);
     }
   }
-  if (!last_workgroup(counter, &s_last)) return;
+  if (!last_arrival(counter, gridDim.x * gridDim.y, &s_last)) return;
   finalize_tail(cand, partials, radii, N, logn, nch, w, bb, wd);
 }
 
 __global__ __launch_bounds__(256) void k_update(double* __restrict__ g64, float* __restrict__ g32, UpdateArgs U) {
   __shared__ double wd[16];
   __shared__ int s_last;
+  const int b = blockIdx.y;
+  g64 += 2 * size_t(U.N) * b;
+  if (g32) g32 += 2 * size_t(U.N) * b;
+  U.epart += size_t(gridDim.x) * b;
+  U.counter += b;
+  U.R = record_of(U.R, b);
   const Blaschke B = blaschke_of(U);
   const int N = U.N;
   double acc = 0.0;
@@ -169,27 +193,29 @@ static int ilog2i(int v) {
 }
 
 hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* nonfinite, unsigned int* counter,
-                          const RecordArgs& R, hipStream_t s) {
-  hipLaunchKernelGGL(k_prepare, dim3(update_blocks(N)), dim3(kUpdThreads), 0, s, g64, g32, N, epart, nonfinite,
-                     counter, R);
+                          const RecordArgs& R, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare, dim3(update_blocks(N), batch), dim3(kUpdThreads), 0, s, g64, g32, N, epart,
+                     nonfinite, counter, R);
   return hipGetLastError();
 }
 
-hipError_t launch_force(const int32_t* forced, int step, int N, CandList* cand, hipStream_t s) {
-  hipLaunchKernelGGL(k_force, dim3(1), dim3(64), 0, s, forced, step, N, cand);
+hipError_t launch_force(const int32_t* forced, int fstride, int step, int N, CandList* cand, int batch,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_force, dim3(batch), dim3(64), 0, s, forced, fstride, step, N, cand);
   return hipGetLastError();
 }
 
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
-                          double* partials, unsigned int* counter, Winner* w, hipStream_t s) {
+                          double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s) {
   const int nch = recheck_chunks(N);
-  hipLaunchKernelGGL(k_recheck, dim3(kRecheckBlocksX, nch), dim3(256), 0, s, cand, g, omega, radii, N, ilog2i(N),
-                     nch, partials, counter, w);
+  hipLaunchKernelGGL(k_recheck, dim3(kRecheckBlocksX, nch, batch), dim3(256), 0, s, cand, g, omega, radii, N,
+                     ilog2i(N), nch, partials, counter, w);
   return hipGetLastError();
 }
 
-hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  launch_ev(k_update, dim3(update_blocks(U.N)), dim3(kUpdThreads), 0u, s, e0, e1, g64, g32, U);
+hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, int batch, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
+  launch_ev(k_update, dim3(update_blocks(U.N), batch), dim3(kUpdThreads), 0u, s, e0, e1, g64, g32, U);
   return hipGetLastError();
 }
 

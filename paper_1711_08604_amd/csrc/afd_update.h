@@ -45,6 +45,21 @@ __device__ __forceinline__ void blaschke_apply(const Blaschke& B, const double* 
   hy = fma(qx, B.wjy, qy * B.wjx);
 }
 
+// The record of signal b of a batch.
+__device__ __forceinline__ RecordArgs record_of(RecordArgs R, int b) {
+  const size_t s = size_t(R.steps) * size_t(b);
+  R.w += b;
+  R.idx += 2 * s;
+  R.a += 2 * s;
+  R.coef += 2 * s;
+  R.energy += s + size_t(b);
+  R.margin += s;
+  R.kcount += s;
+  R.flags += s;
+  R.fp32err += s;
+  return R;
+}
+
 __device__ __forceinline__ void write_record(const RecordArgs& R, int step, double E) {
   if (step < 0) {
     R.energy[0] = E;
@@ -77,11 +92,12 @@ __device__ __forceinline__ double energy_from_parts(const double* __restrict__ e
 
 // End of an update launch: publish this workgroup's energy partial; the last
 // workgroup sums them and records the step.  `wd`: LDS double[16], `flag`: LDS int.
+// (U: this signal's view, see k_update)
 __device__ __forceinline__ void update_finish(const UpdateArgs& U, double acc, double* wd, int* flag) {
   const double tot = block_sum_f64(acc, wd);
   if (threadIdx.x == 0) st_agent(U.epart + blockIdx.x, tot);
-  if (!last_workgroup(U.counter, flag)) return;
-  const double E = energy_from_parts(U.epart, int(gridDim.x * gridDim.y * gridDim.z), U.N, wd);
+  if (!last_arrival(U.counter, gridDim.x, flag)) return;
+  const double E = energy_from_parts(U.epart, int(gridDim.x), U.N, wd);
   if (threadIdx.x == 0) write_record(U.R, U.step, E);
 }
 

@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol():
     assert set(names) == set(afd.EXPORTS)
 
 
-def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=0, band=0.0):
+def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=0, band=0.0, batch=0):
     r = np.ascontiguousarray(np.asarray(radii, dtype=np.float64))
     d = afd.PlanDesc()
     d.n = n
@@ -45,6 +45,7 @@ def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=
     d.recheck_k = recheck_k
     d.first_a_zero = first_a_zero
     d.recheck_band = band
+    d.batch = batch
     return d, r
 
 
@@ -54,6 +55,7 @@ def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=
     (dict(radii=(np.nan,)), 1), (dict(radii=(np.inf,)), 1), (dict(precision=7), 1),
     (dict(recheck_k=-1), 1), (dict(recheck_k=65), 1), (dict(band=-1e-3), 1), (dict(band=0.5), 1),
     (dict(first_a_zero=1, radii=(0.1, 0.2)), 1), (dict(n=1 << 16, radii=np.zeros(1 << 15)), 1),
+    (dict(batch=-1), 1), (dict(n=1 << 15, batch=2), 5), (dict(n=1 << 14, batch=1 << 17), 1),
 ])
 def test_plan_create_rejects(kw, status):
     afd, lib = _lib()
@@ -104,6 +106,19 @@ def test_workspace_bytes_two_pass():
         assert (256 << 20) <= b < (400 << 20), (prec, b)
     d, keep = _desc(afd, n=1 << 15, radii=r[:7], precision=1)
     assert 0 < lib.afd_workspace_bytes(ctypes.byref(d)) < (16 << 20)
+
+
+def test_workspace_bytes_batch():
+    """A batch holds one copy of every per-signal buffer per signal and one copy of the tables."""
+    afd, lib = _lib()
+    r = np.linspace(0, 0.999, 512)
+    sizes = []
+    for batch in (1, 2, 512):
+        d, keep = _desc(afd, n=4096, radii=r, precision=1, batch=batch)
+        sizes.append(lib.afd_workspace_bytes(ctypes.byref(d)))
+    per_signal = sizes[1] - sizes[0]
+    assert per_signal > 16 * 4096  # at least the double remainder
+    assert sizes[2] == pytest.approx(sizes[0] + 511 * per_signal, rel=1e-3)
 
 
 def test_status_strings():

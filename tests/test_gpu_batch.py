@@ -1,0 +1,113 @@
+"""Batched plans (several signals of one N per call) against the FP64 oracle
+and against the same signals decomposed alone.
+
+Every kernel of a step covers all signals of the batch, each working on its own
+slice of the per-signal buffers, so a signal's result in the batch must equal
+its result alone bit for bit (the same kernels and reduction orders run on the
+same data), and both must match the oracle at the parity bar.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.parity_tools import TOL, compare, to_numpy
+
+torch = pytest.importorskip("torch")
+from paper_1711_08604_amd import Plan  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _signals(batch, n):
+    out = []
+    for i in range(batch):
+        rng = W.rng_for(300 + n.bit_length(), i)
+        g, _, _ = W.random_kernel_signal(rng, n, 6, 0.9)
+        out.append(W.add_noise(rng, g, 40.0))
+    return np.stack(out)
+
+
+def _one(res, b):
+    r = to_numpy(res)
+    return {k: v[b] for k, v in r.items()}
+
+
+class _Res:  # to_numpy-compatible view of one signal of a batched result
+    def __init__(self, d):
+        self.__dict__.update(d)
+
+
+FIELDS = ("index", "a", "coef", "energy", "margin", "recheck_count", "flags", "fp32_error", "remainder")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,m,batch,steps", [(64, 21, 3, 4), (1024, 33, 5, 5), (4096, 40, 4, 4), (16384, 24, 3, 3)],
+                         ids=lambda v: str(v))
+def test_batch_matches_alone_and_oracle(n, m, batch, steps, prec):
+    print(f"case N={n} M={m} batch={batch} steps={steps} {prec}", flush=True)
+    g = _signals(batch, n)
+    radii = W.uniform_radii(m, 0.999)
+    with Plan(n, radii, precision=prec, batch=batch) as pb:
+        rb = pb.decompose(_dev(g), steps)
+        refs = [O.decompose(g[b], radii, steps) for b in range(batch)]
+        forced = np.stack([r.index for r in refs]).astype(np.int32)
+        rr = pb.replay(_dev(g), steps, forced)
+    with Plan(n, radii, precision=prec) as p1:
+        alone = [to_numpy(p1.decompose(_dev(g[b]), steps)) for b in range(batch)]
+    for b in range(batch):
+        one = _one(rb, b)
+        for k in FIELDS:
+            np.testing.assert_array_equal(one[k], alone[b][k], err_msg=f"signal {b} field {k}")
+        compare(_Res(one), refs[b], TOL[prec], signal=g[b], radii=radii)
+        compare(_Res(_one(rr, b)), refs[b], TOL[prec], replay=True)
+
+
+def test_batch_first_a_zero():
+    n, m, batch, steps = 1024, 9, 3, 4
+    g = _signals(batch, n)
+    radii = np.arange(m) / 10.0
+    with Plan(n, radii, precision="fp64", batch=batch, first_a_zero=True) as pb:
+        rb = pb.decompose(_dev(g), steps)
+    for b in range(batch):
+        ref = O.decompose(g[b], radii, steps, first_a_zero=True)
+        compare(_Res(_one(rb, b)), ref, TOL["fp64"], signal=g[b], radii=radii, forced_first=True)
+
+
+def test_uniform_batch_512x4096_sampled():
+    """The uniform batch: 512 signals, N = 4096, M = 512 radii in [0, 0.999], 30
+    steps, FP32 bulk with FP64 re-check (the launch configuration of the
+    batched workload).  Sampled signals against the oracle and alone; every
+    signal: the energy bookkeeping and the FP64 path's choices where clear."""
+    g, radii, steps = W.config3_batch()
+    batch, n = g.shape
+    print(f"case batch={batch} N={n} M={radii.shape[0]} steps={steps}", flush=True)
+    with Plan(n, radii, precision="fp32", batch=batch) as pb:
+        r32 = to_numpy(pb.decompose(_dev(g), steps))
+    with Plan(n, radii, precision="fp64", batch=batch) as pb:
+        r64 = to_numpy(pb.decompose(_dev(g), steps))
+    for b in (0, 1, 257, 511):
+        ref = O.decompose(g[b], radii, steps)
+        for r, prec in ((r32, "fp32"), (r64, "fp64")):
+            compare(_Res({k: v[b] for k, v in r.items()}), ref, TOL[prec], signal=g[b], radii=radii)
+    with Plan(n, radii, precision="fp32") as p1:
+        for b in (3, 300):
+            alone = to_numpy(p1.decompose(_dev(g[b]), steps))
+            for k in FIELDS:
+                np.testing.assert_array_equal(r32[k][b], alone[k], err_msg=f"signal {b} field {k}")
+    # every signal: rho = |a|^N is below 1e-16 here except for the largest radii
+    rho = np.abs(r32["a"]) ** n
+    pred = r32["energy"][:, :-1] - np.abs(r32["coef"]) ** 2 * (1 - 2 * rho / (1 - rho))
+    assert np.all(np.abs(pred - r32["energy"][:, 1:]) <= 1e-9 * r32["energy"][:, :1])
+    assert np.all((r32["flags"] & 1) == 0)
+    clear = r64["margin"] > 1e-6
+    first_tie = np.where(clear.all(axis=1), steps, np.argmin(clear, axis=1))
+    for b in range(batch):
+        k = first_tie[b]
+        np.testing.assert_array_equal(r32["index"][b, :k], r64["index"][b, :k], err_msg=f"signal {b}")

@@ -32,6 +32,7 @@ __all__ = [
     "config1",
     "config2",
     "config3",
+    "config3_batch",
     "config5",
     "shaped_like_config2",
 ]
@@ -147,6 +148,13 @@ def config3(item: int, n: int = 4096):
     count = int(rng.integers(8, 33))
     g, _, _ = random_kernel_signal(rng, n, count, 0.95)
     return g
+
+
+def config3_batch(batch: int = 512, n: int = 4096, m: int = 512, steps: int = 30):
+    """The uniform batch: `batch` signals of config3 (item = signal index), M radii
+    uniform in [0, 0.999], 30 steps.  Returns (signals [batch][N], radii, steps)."""
+    g = np.stack([config3(i, n) for i in range(batch)])
+    return g, uniform_radii(m), steps
 
 
 def config5(item: int = 0, n: int = 1 << 20, m: int = 2000, steps: int = 100):
