@@ -16,6 +16,10 @@ N = 2^20, M = 2000, 100 steps of the analytic part of a chirp + 3 tones +
 white noise at 20 dB, whose radius transforms run as two passes through HBM.
 `--workload batch512` times the uniform batch: 512 signals of N = 4096
 (8..32 kernels, |b| <= 0.95), M = 512, 30 steps, decomposed together.
+`--workload serve` runs the served stream: requests with N log-uniform over
+2^10..2^16, M = N/8, 5..100 steps, signals as in the default workload, through
+the continuous-batching server, first all at once (throughput), then with
+Poisson arrivals at 0.7x that request rate (p50/p99 latency).
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 """
@@ -182,10 +186,85 @@ def cpu_baseline(g, radii, steps_sample, total_steps):
             "seconds": dt, "numpy": np.__version__}
 
 
+def run_serve(args, np, torch, W):
+    """The served stream through paper_1711_08604_amd.serve.Server (FP32+recheck)."""
+    from paper_1711_08604_amd.serve import Server
+    rng = np.random.default_rng(20171108)
+    reqs = []
+    for i in range(args.requests):
+        n = int(2 ** rng.integers(10, 17))
+        steps = int(rng.integers(5, 101))
+        g, radii, _ = W.shaped_like_config2(n, n // 8, steps, item=4000 + i)
+        reqs.append((g, radii, steps))
+    evals = float(sum(len(r) * g.shape[0] * s for g, r, s in reqs))
+    log(f"bench: serve {len(reqs)} requests, {evals:.3e} grid evals")
+
+    def stream(arrivals):
+        with Server(slots=8) as srv:
+            # warm the plans of every N (not timed)
+            for n in sorted({g.shape[0] for g, _, _ in reqs}):
+                g, r, s = next(q for q in reqs if q[0].shape[0] == n)
+                srv.submit(g, r, 1).result()
+            t0 = time.perf_counter()
+            futs = []
+            for (g, r, s), at in zip(reqs, arrivals):
+                delay = t0 + at - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                futs.append(srv.submit(g, r, s))
+            out = [f.result() for f in futs]
+            wall = time.perf_counter() - t0
+        lat = [o.latency for o in out]
+        return wall, lat
+
+    # the plain per-signal method: the same requests one after another on one stream
+    from paper_1711_08604_amd import Plan
+    plans = {}
+    for g, r, s in reqs:
+        if g.shape[0] not in plans:
+            plans[g.shape[0]] = Plan(g.shape[0], r, precision="fp32")
+            plans[g.shape[0]].decompose(g, 1)
+    t0 = time.perf_counter()
+    seq_lat = []
+    for g, r, s in reqs:
+        a = time.perf_counter()
+        plans[g.shape[0]].decompose(g, s)
+        seq_lat.append(time.perf_counter() - t0)  # all requests present at t0
+    wall_seq = time.perf_counter() - t0
+    for p in plans.values():
+        p.close()
+    log(f"bench: serve sequential (one stream) {evals / wall_seq:.3e} evals/s")
+
+    wall0, lat0 = stream([0.0] * len(reqs))
+    rate = len(reqs) / wall0
+    lam = 0.7 * rate
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
+    arrivals -= arrivals[0]
+    wall1, lat1 = stream(list(arrivals))
+    log(f"bench: serve saturated {evals / wall0:.3e} evals/s; Poisson at {lam:.1f} req/s: "
+        f"p50 {percentile(lat1, 0.5) * 1e3:.1f} ms p99 {percentile(lat1, 0.99) * 1e3:.1f} ms")
+    return {
+        "metric": METRIC, "value": evals / wall0, "unit": "grid evals/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": wall0 * 1e3, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"served stream: {len(reqs)} requests, N log-uniform over 2^10..2^16, M=N/8, steps "
+                               "uniform in 5..100, signals as the default workload, 8 slots, FP32+recheck",
+                   "requests": len(reqs), "grid_evals": evals},
+        "p50_ms": percentile(lat1, 0.5) * 1e3, "p99_ms": percentile(lat1, 0.99) * 1e3,
+        "serve": {"sequential_evals_per_s": evals / wall_seq, "sequential_wall_s": wall_seq,
+                  "sequential_p50_ms": percentile(seq_lat, 0.5) * 1e3,
+                  "sequential_p99_ms": percentile(seq_lat, 0.99) * 1e3,
+                  "saturated_wall_s": wall0, "saturated_p50_ms": percentile(lat0, 0.5) * 1e3,
+                  "saturated_p99_ms": percentile(lat0, 0.99) * 1e3, "poisson_rate_req_s": lam,
+                  "poisson_wall_s": wall1, "poisson_evals_per_s": evals / wall1},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single16k", "chirp1m", "batch512"], default="single16k")
+    ap.add_argument("--workload", choices=["single16k", "chirp1m", "batch512", "serve"], default="single16k")
+    ap.add_argument("--requests", type=int, default=300, help="serve: requests in the stream")
     ap.add_argument("--steps", type=int, default=None, help="timed decompositions (30; chirp1m: 3)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed decompositions (3; chirp1m: 1)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -205,6 +284,10 @@ def main():
     import torch
 
     import workloads as W
+
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args, np, torch, W)), flush=True)
+        return
 
     if args.workload == "batch512":
         g, radii, afd_steps = W.config3_batch()
