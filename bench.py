@@ -227,7 +227,6 @@ def run_serve(args, np, torch, W):
     t0 = time.perf_counter()
     seq_lat = []
     for g, r, s in reqs:
-        a = time.perf_counter()
         plans[g.shape[0]].decompose(g, s)
         seq_lat.append(time.perf_counter() - t0)  # all requests present at t0
     wall_seq = time.perf_counter() - t0
