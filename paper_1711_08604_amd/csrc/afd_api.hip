@@ -43,7 +43,7 @@ enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3 }
 // Device arena layout for one plan.
 struct Layout {
   size_t radii, omega, tw, twf1, twf2, pw, pv, scale, g64, g32, c, xt, blocks, cand, partials, winner, epart,
-      nonfinite, forced0, counters;
+      nonfinite, forced0, counters, bar, omega_t;
   // truncated / pruned spectrum of the LDS-resident radius transforms
   size_t pq, lsig, order;
   // FP32 head keys of the workgroup (or per-radius) records
@@ -71,6 +71,8 @@ struct Config {
   int batch;    // signals per call
   bool big;     // N > 2^kMaxLdsLogN: two-pass radius transforms
   BigGeom bg;
+  bool adv;     // 2^12 <= N <= 2^14: fused step tail (afd_advance.hip)
+  AdvGeom ag;
   int chunk;    // radii per two-pass chunk
 };
 
@@ -111,6 +113,14 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     cfg->nch = recheck_chunks(int(d->n));
     cfg->nparts = update_blocks(int(d->n));
     cfg->big = logn > kMaxLdsLogN;
+    cfg->adv = advance_supported(logn);
+    cfg->ag = cfg->adv ? advance_geom(logn) : AdvGeom{};
+    if (cfg->adv) {
+      cfg->fwd.tw1_size = cfg->ag.tw1_size;
+      cfg->fwd.tw2_size = cfg->ag.tw2_size;
+      cfg->nch = cfg->ag.nch;
+      cfg->nparts = cfg->ag.nb;
+    }
     if (cfg->big) {
       cfg->geom = FftGeom{0, 0, 0, false, 0};
       cfg->bg = big_geom(logn, cfg->fp64);
@@ -156,7 +166,7 @@ Layout layout_of(const Config& c) {
   const size_t B = size_t(c.batch);
   L.heads = take(c.fp64 ? 0 : 8 * size_t(c.big ? c.M : c.nblocks) * B);
   L.g64 = take(16 * size_t(c.N) * B);
-  L.g32 = take(c.fp64 ? 0 : 8 * size_t(c.N) * B);
+  L.g32 = take(c.fp64 || c.adv ? 0 : 8 * size_t(c.N) * B);
   L.c = take(2 * real * size_t(c.N) * B);
   L.xt = take(c.fwd.two_pass ? 2 * real * size_t(c.N) * B : 0);
   L.blocks = take((c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.nblocks) * B);
@@ -172,6 +182,9 @@ Layout layout_of(const Config& c) {
   L.nonfinite = take(4);
   L.forced0 = take(8);
   L.counters = take(4 * kNumCounters * B);  // [kind][signal]
+  L.bar = take(8);
+  // fused step tail in single precision: the unit roots rounded to float
+  L.omega_t = take(c.adv && !c.fp64 ? 8 * size_t(c.N) : 0);
   L.total = o;
   return L;
 }
@@ -231,8 +244,13 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   std::vector<double> tw(2 * size_t(c.geom.twsize + 1), 0.0);
   fft_twiddles(c.logn, c.fp64, tw.data());
   std::vector<double> twf1(2 * size_t(c.fwd.tw1_size + 1), 0.0), twf2(2 * size_t(c.fwd.tw2_size + 1), 0.0);
-  fft_twiddles(c.fwd.two_pass ? c.fwd.l1 : c.logn, c.fp64, twf1.data());
-  if (c.fwd.two_pass) fft_twiddles(c.fwd.l2, c.fp64, twf2.data());
+  if (c.adv) {
+    advance_twiddles(c.ag.l1, twf1.data());
+    advance_twiddles(c.ag.l2, twf2.data());
+  } else {
+    fft_twiddles(c.fwd.two_pass ? c.fwd.l1 : c.logn, c.fp64, twf1.data());
+    if (c.fwd.two_pass) fft_twiddles(c.fwd.l2, c.fp64, twf2.data());
+  }
   // r^l = pw[m][a] * pv[m][b]: l = a + TPR b (LDS path) or l = N2 a + b (two-pass path, pw = r^(N2 a))
   const int na = c.big ? (1 << c.bg.l1) : tpr, nb = c.big ? (1 << c.bg.l2) : E;
   const long double sa = c.big ? (long double)nb : 1.0L, sb = c.big ? 1.0L : (long double)tpr;
@@ -310,6 +328,11 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     if (e == hipSuccess && !c.big) e = up(p->L.pq, pq32.data(), pq32.size() * 4);
   }
   if (e == hipSuccess && !c.big) e = up(p->L.lsig, lsig.data(), lsig.size() * 4);
+  if (e == hipSuccess && c.adv && !c.fp64) {
+    std::vector<float> om(2 * size_t(N));
+    for (size_t i = 0; i < om.size(); ++i) om[i] = float(omega[i]);
+    e = up(p->L.omega_t, om.data(), om.size() * 4);
+  }
   if (!c.big) {
     // workgroup order: longest significant spectrum first (ties by index)
     std::vector<int32_t> order(M);
@@ -441,6 +464,70 @@ struct Timer {
     if (_e != hipSuccess) return hip_fail(_e, where); \
   } while (0)
 
+// Steps of a plan with the fused step tail: per step the radius kernel (or a
+// forced point), then one launch_advance that re-checks, updates and
+// transforms the new remainder for the next step.
+afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const RecordArgs& rec,
+                   const RadiusParams& rp, Timer& tm) {
+  const Config& c = p->cfg;
+  const int B = c.batch;
+  hipStream_t s = p->stream;
+  auto forced_at = [&](int k) { return forced_user != nullptr || (p->first_a_zero && k == 0); };
+  AdvanceArgs a{};
+  a.cand = p->at<CandList>(p->L.cand);
+  a.winner = p->at<Winner>(p->L.winner);
+  a.g64 = p->at<double>(p->L.g64);
+  a.radii = p->at<double>(p->L.radii);
+  a.omega = p->at<double>(p->L.omega);
+  a.omega_t = c.fp64 ? p->at<void>(p->L.omega) : p->at<void>(p->L.omega_t);
+  a.tw1 = p->at<void>(p->L.twf1);
+  a.tw2 = p->at<void>(p->L.twf2);
+  a.xt = p->at<void>(p->L.xt);
+  a.c = p->at<void>(p->L.c);
+  a.partials = p->at<double>(p->L.partials);
+  a.epart = p->at<double>(p->L.epart);
+  a.bar = p->at<unsigned long long>(p->L.bar);
+  a.bar_base = 0;
+  a.status = p->at<int>(p->L.nonfinite);
+  a.R = rec;
+  a.M = c.M;
+  auto advance = [&](hipEvent_t e0, hipEvent_t e1) -> hipError_t {
+    const hipError_t e = launch_advance(c.logn, c.fp64, a, B, s, e0, e1);
+    if (B == 1) a.bar_base += advance_arrivals(c.logn, a);
+    return e;
+  };
+  if (steps > 0 && !forced_at(0)) {
+    hipEvent_t e0, e1;
+    HIPCHK(tm.pair(kTimeFft, &e0, &e1), "event");
+    a.update = 0;
+    a.recheck = 0;
+    a.fft = 1;
+    a.step = -1;
+    HIPCHK(advance(e0, e1), "k_advance");
+  }
+  for (int k = 0; k < steps; ++k) {
+    const bool forced = forced_at(k);
+    if (forced) {
+      const int32_t* fsrc = forced_user ? p->forced : p->at<int32_t>(p->L.forced0);
+      HIPCHK(launch_force(fsrc, forced_user ? 2 * steps : 0, forced_user ? k : 0, int(c.N),
+                          p->at<CandList>(p->L.cand), B, s),
+             "k_force");
+    } else {
+      hipEvent_t e0, e1;
+      HIPCHK(tm.pair(kTimeRadius, &e0, &e1), "event");
+      HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, B, s, e0, e1), "k_radius");
+    }
+    hipEvent_t u0, u1;
+    HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
+    a.update = 1;
+    a.recheck = (!c.fp64 || forced) ? 1 : 0;
+    a.fft = (k + 1 < steps && !forced_at(k + 1)) ? 1 : 0;
+    a.step = k;
+    HIPCHK(advance(u0, u1), "k_advance");
+  }
+  return AFD_OK;
+}
+
 afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* forced_user, afd_result* out) {
   if (!p) return fail(AFD_E_INVALID, "plan is NULL");
   if (!signal) return fail(AFD_E_INVALID, "signal is NULL");
@@ -480,7 +567,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
 
   hipStream_t s = p->stream;
   double* g64 = p->at<double>(p->L.g64);
-  float* g32 = c.fp64 ? nullptr : p->at<float>(p->L.g32);
+  float* g32 = c.fp64 || c.adv ? nullptr : p->at<float>(p->L.g32);
   void* cspec = p->at<void>(p->L.c);
   const double* radii = p->at<double>(p->L.radii);
   const double* omega = p->at<double>(p->L.omega);
@@ -511,6 +598,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   // flags and last-workgroup counters start at zero (also after an aborted call)
   HIPCHK(hipMemsetAsync(nonfinite, 0, 4, s), "clearing flag");
   HIPCHK(hipMemsetAsync(counters, 0, 4 * kNumCounters * size_t(B), s), "clearing counters");
+  if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.bar, 0, 8, s), "clearing counters");
   if (c.big)
     HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4 * (size_t(c.chunk) + 1), s), "clearing counters");
   HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N) * B, sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -573,7 +661,11 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   upd.epart = epart;
   upd.counter = counters + 2 * B;
   upd.R = rec;
-  for (int k = 0; k < steps; ++k) {
+  if (c.adv) {
+    st = run_adv(p, steps, forced_user, rec, rp, tm);
+    if (st != AFD_OK) return st;
+  }
+  for (int k = 0; k < (c.adv ? 0 : steps); ++k) {
     const int32_t* fsrc = nullptr;
     int fstep = k;
     if (forced_user) {
@@ -616,6 +708,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   HIPCHK(hipMemcpyAsync(&bad, nonfinite, 4, hipMemcpyDeviceToHost, s), "reading flag");
   HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
   HIPCHK(tm.collect(), "hipEventElapsedTime");
+  if (bad & 2) return fail(AFD_E_HIP, "a grid barrier of the step tail timed out");
   if (bad) return fail(AFD_E_NONFINITE, "signal holds NaN or Inf");
 
   // staged signal-major with per-signal stride `steps`: the caller's layout

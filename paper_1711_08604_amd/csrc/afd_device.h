@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+#include <type_traits>
 #include <utility>
 
 namespace afd {
@@ -218,41 +219,88 @@ struct Dit {
   }
 };
 
+// Twiddles of every pass of a transform held in registers, for transforms
+// too short to hide a global load per pass: thread t's twiddle of pass P,
+// job U, r = 1..R-1 sits at off(P) + U (R - 1) + r - 1.
+template <typename T, int LOGN, int E>
+struct TwRegs {
+  using S = Shape<LOGN, E>;
+  static constexpr int per_pass(int p) { return (E / S::radix(p)) * (S::radix(p) - 1); }
+  static constexpr int off(int P) {
+    int o = 0;
+    for (int p = 1; p < P; ++p) o += per_pass(p);
+    return o;
+  }
+  static constexpr int kCount = off(S::NP);
+  Cx<T> w[kCount > 0 ? kCount : 1];
+};
+
+template <class X>
+struct IsTwRegs : std::false_type {};
+template <typename T, int LOGN, int E>
+struct IsTwRegs<TwRegs<T, LOGN, E>> : std::true_type {};
+
+// Fill R from the pass table (the entries pass_job would read for thread t).
+template <typename T, int LOGN, int E, int P = 1>
+__device__ __forceinline__ void tw_regs_load(TwRegs<T, LOGN, E>& R, int t, const Cx<T>* __restrict__ tw) {
+  using S = Shape<LOGN, E>;
+  if constexpr (P < S::NP) {
+    constexpr int RX = S::radix(P), NS = S::ns(P), J = E / RX;
+#pragma unroll
+    for (int u = 0; u < J; ++u) {
+      const int k = (t + u * S::TPR) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < RX; ++r)
+        R.w[TwRegs<T, LOGN, E>::off(P) + u * (RX - 1) + r - 1] = tw[S::twoff(P) + (r - 1) * NS + k];
+    }
+    tw_regs_load<T, LOGN, E, P + 1>(R, t, tw);
+  }
+}
+
 // One butterfly job u of Stockham pass P, in place on the registers: the
 // twiddles e^{+-2 pi i k r/(Ns R)} come from the pass's table (exactly
-// rounded), then the R-point DFT.
-template <typename T, int LOGN, int E, int P, int SIGN, int U>
-__device__ __forceinline__ void pass_job(Cx<T> (&v)[E], int t, const Cx<T>* __restrict__ tw) {
+// rounded; TW = const Cx<T>* reads it in memory, TW = TwRegs from
+// registers), then the R-point DFT.
+template <typename T, int LOGN, int E, int P, int SIGN, int U, class TW>
+__device__ __forceinline__ void pass_job(Cx<T> (&v)[E], int t, const TW& tw) {
   using S = Shape<LOGN, E>;
   constexpr int R = S::radix(P);
   constexpr int NS = S::ns(P);
   constexpr int J = E / R;
   if constexpr (NS > 1) {
-    const int job = t + U * S::TPR;
-    const int k = job & (NS - 1);
-    const Cx<T>* __restrict__ row = tw + S::twoff(P) + k;
+    if constexpr (!IsTwRegs<TW>::value) {
+      const int job = t + U * S::TPR;
+      const int k = job & (NS - 1);
+      const Cx<T>* __restrict__ row = tw + S::twoff(P) + k;
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-      Cx<T> w = row[(r - 1) * NS];
-      if constexpr (SIGN < 0) w.y = -w.y;
-      v[U + r * J] = cmul(v[U + r * J], w);
-      // double precision: keep at most four twiddles in flight so the
-      // 1024-thread transforms stay inside their 128-register budget
-      if ((sizeof(T) == 8 && (r % 4) == 3) || (sizeof(T) == 4 && (r % 8) == 7)) __builtin_amdgcn_sched_barrier(0);
+      for (int r = 1; r < R; ++r) {
+        Cx<T> w = row[(r - 1) * NS];
+        if constexpr (SIGN < 0) w.y = -w.y;
+        v[U + r * J] = cmul(v[U + r * J], w);
+        // double precision: keep at most four twiddles in flight so the
+        // 1024-thread transforms stay inside their 128-register budget
+        if ((sizeof(T) == 8 && (r % 4) == 3) || (sizeof(T) == 4 && (r % 8) == 7)) __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        Cx<T> w = tw.w[TW::off(P) + U * (R - 1) + r - 1];
+        if constexpr (SIGN < 0) w.y = -w.y;
+        v[U + r * J] = cmul(v[U + r * J], w);
+      }
     }
   }
   Dit<R, SIGN, U, J, T>::run(v);
 }
 
-template <typename T, int LOGN, int E, int P, int SIGN, int... U>
-__device__ __forceinline__ void pass_jobs(Cx<T> (&v)[E], int t, const Cx<T>* __restrict__ tw,
-                                          std::integer_sequence<int, U...>) {
+template <typename T, int LOGN, int E, int P, int SIGN, class TW, int... U>
+__device__ __forceinline__ void pass_jobs(Cx<T> (&v)[E], int t, const TW& tw, std::integer_sequence<int, U...>) {
   (pass_job<T, LOGN, E, P, SIGN, U>(v, t, tw), ...);
 }
 
 // One Stockham pass P on the registers v (see the file comment).
-template <typename T, int LOGN, int E, int P, int SIGN>
-__device__ __forceinline__ void pass_compute(Cx<T> (&v)[E], int t, const Cx<T>* __restrict__ tw) {
+template <typename T, int LOGN, int E, int P, int SIGN, class TW>
+__device__ __forceinline__ void pass_compute(Cx<T> (&v)[E], int t, const TW& tw) {
   using S = Shape<LOGN, E>;
   pass_jobs<T, LOGN, E, P, SIGN>(v, t, tw, std::make_integer_sequence<int, E / S::radix(P)>{});
 }
@@ -337,9 +385,9 @@ __device__ __forceinline__ void lds_read_part(Cx<T> (&v)[E], int t, const T* lds
 //
 // FIRST > 0 starts at pass FIRST with the registers already holding that
 // pass's inputs (no exchange before it); see the pruned start of the radius
-// transform.
-template <typename T, int LOGN, int E, int SIGN, bool SPLIT, int P = 0, int FIRST = 0>
-__device__ __forceinline__ void fft_regs(Cx<T> (&v)[E], int t, void* lds, const Cx<T>* __restrict__ tw) {
+// transform.  `tw`: the pass table in memory (const Cx<T>*) or a TwRegs.
+template <typename T, int LOGN, int E, int SIGN, bool SPLIT, int P = 0, int FIRST = 0, class TW>
+__device__ __forceinline__ void fft_regs(Cx<T> (&v)[E], int t, void* lds, const TW& tw) {
   using S = Shape<LOGN, E>;
   if constexpr (P > FIRST) {
     if constexpr (SPLIT) {

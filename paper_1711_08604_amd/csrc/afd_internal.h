@@ -159,6 +159,49 @@ struct UpdateArgs {
   int step;
 };
 
+// Step tail for 2^12 <= N <= 2^14 (afd_advance.hip): re-check, winner,
+// remainder update and the forward DFT of the new remainder.
+struct AdvanceArgs {
+  const CandList* cand;     // short-list (FP32 mode) or forced point
+  Winner* winner;           // written here after a re-check, else read (FP64 grid maximum)
+  double* g64;              // remainder samples, updated in place
+  const double* radii;
+  const double* omega;      // e^{2 pi i n/N}
+  const void* omega_t;      // e^{2 pi i n/N} in the transform precision (T complex)
+  const void* tw1;          // Stockham twiddles of the length-N1 row DFTs
+  const void* tw2;          // Stockham twiddles of the length-N2 column DFTs
+  void* xt;                 // [N2][N1] intermediate (T complex)
+  void* c;                  // spectrum of the new remainder (T complex)
+  double* partials;         // [kKMax][nch] (re, im) re-check partial sums
+  double* epart;            // [nb] energy partial sums
+  unsigned long long* bar;  // grid barrier counter (zero at the start of a call)
+  unsigned long long bar_base;  // arrivals of the call's earlier launches
+  int* status;              // bit 1: a grid barrier wait ran out
+  RecordArgs R;
+  int step;
+  int M;
+  int update;   // 1: apply the step's update and record it; 0: transform the samples as they are
+  int recheck;  // 1: re-check the short-list; 0: the winner is already in `winner`
+  int fft;      // 1: transform the new remainder
+  int phase;    // set by the launcher
+};
+struct AdvGeom {
+  int l1, l2;     // N1 = 2^l1 (row DFT length), N2 = 2^l2 (column DFT length)
+  int nb;         // transform workgroups (also the energy partial sums)
+  int ga;         // re-check workgroups
+  int nch;        // re-check chunks
+  int tw1_size, tw2_size;
+};
+bool advance_supported(int logn);
+AdvGeom advance_geom(int logn);
+// Stockham twiddle table of the length-2^l DFTs of the step tail (l = 6, 7).
+void advance_twiddles(int l, double* out_interleaved);
+// Grid barrier arrivals of one launch_advance with batch 1.
+unsigned long long advance_arrivals(int logn, const AdvanceArgs& a);
+// One launch with grid barriers for batch 1; one launch per phase otherwise.
+hipError_t launch_advance(int logn, bool fp64, const AdvanceArgs& a, int batch, hipStream_t s,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
 // Geometry of the LDS-resident transform for 2^logn points.
 struct FftGeom {
   int E;        // values per thread

@@ -69,50 +69,6 @@ __global__ void k_force(const int32_t* __restrict__ forced, int fstride, int ste
   }
 }
 
-// Winner among the short-list from the chunk partial sums (last workgroup).
-__device__ __forceinline__ void finalize_tail(const CandList* __restrict__ cand, const double* __restrict__ partials,
-                                              const double* __restrict__ radii, int N, int logn, int nch,
-                                              Winner* __restrict__ w, Best* bb, double* wd) {
-  const int count = cand->count;
-  const bool forced = (cand->flags & kFlagForced) != 0;
-  Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
-  double err = 0.0;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) {
-    const uint32_t f = key_f(cand->keys[i]);
-    const double r = radii[f >> logn];
-    double ax = 0.0, ay = 0.0;
-    for (int ch = 0; ch < nch; ++ch) {
-      ax += ld_agent(partials + 2 * (size_t(i) * nch + ch));
-      ay += ld_agent(partials + 2 * (size_t(i) * nch + ch) + 1);
-    }
-    const double s = sqrt((1.0 - r) * (1.0 + r)) / double(N);
-    const Best x{(ax * s) * (ax * s) + (ay * s) * (ay * s), -1.0, ax * s, ay * s, f};
-    err = fmax(err, fabs(double(key_p(cand->keys[i])) - x.p1));
-    best_merge(b, x);
-  }
-  const Best r = block_best(b, bb);
-  err = wave_max_f64(err);
-  if ((threadIdx.x & 63) == 0) wd[threadIdx.x >> 6] = err;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double e = wd[0];
-    for (int i = 1; i < nwaves(); ++i) e = fmax(e, wd[i]);
-    Winner o;
-    const bool valid = count > 0 && r.f != 0xffffffffu;
-    o.m = valid ? int32_t(r.f >> logn) : 0;
-    o.j = valid ? int32_t(r.f & uint32_t(N - 1)) : 0;
-    o.cx = valid ? r.vx : 0.0;
-    o.cy = valid ? r.vy : 0.0;
-    if (forced || count < 2 || !valid) o.margin = __builtin_nan("");
-    else o.margin = r.p1 > 0.0 ? (r.p1 - r.p2) / r.p1 : 0.0;
-    o.kcount = forced ? 1 : count;
-    o.flags = cand->flags & 7;
-    o.ax = o.ay = 0.0;
-    o.fp32err = (forced || !valid || !(r.p1 > 0.0)) ? 0.0 : e / r.p1;
-    *w = o;
-  }
-}
-
 // partial sums over a chunk of samples of G[n] / (1 - r_m e^{2 pi i (j - n)/N})
 __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ cand, const double* __restrict__ g,
                                                  const double* __restrict__ omega, const double* __restrict__ radii,
@@ -152,7 +108,14 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
     }
   }
   if (!last_arrival(counter, gridDim.x * gridDim.y, &s_last)) return;
-  finalize_tail(cand, partials, radii, N, logn, nch, w, bb, wd);
+  static_assert(kKMax <= 256, "one candidate per thread");
+  uint64_t key = 0;
+  double rk = 0.0;
+  if (int(threadIdx.x) < count) {
+    key = cand->keys[threadIdx.x];
+    rk = radii[key_f(key) >> logn];
+  }
+  winner_from_partials(count, cand->flags, key, rk, partials, N, logn, nch, w, bb, wd);
 }
 
 __global__ __launch_bounds__(256) void k_update(double* __restrict__ g64, float* __restrict__ g32, UpdateArgs U) {

@@ -1,6 +1,6 @@
-// The remainder update of Sec. 2, eq. (7), per sample, and the record of a
-// finished step: shared by the stand-alone update kernel and the forward
-// DFT's column pass, which applies the previous step's update on the fly.
+// The re-check winner, the remainder update of Sec. 2, eq. (7), per sample,
+// and the record of a finished step: shared by the stand-alone re-check and
+// update kernels and by the fused step tail (afd_advance.hip).
 #pragma once
 
 #include "afd_select.h"
@@ -16,18 +16,22 @@ struct Blaschke {
   int j;
 };
 
-__device__ __forceinline__ Blaschke blaschke_of(const UpdateArgs& U) {
-  Winner W = *U.R.w;
-  W.m = min(max(W.m, 0), U.M - 1);
+__device__ __forceinline__ Blaschke blaschke_of(Winner W, const double* __restrict__ radii,
+                                                const double* __restrict__ omega, int N, int M) {
+  W.m = min(max(W.m, 0), M - 1);
   Blaschke B;
-  B.j = W.j & (U.N - 1);
-  B.r = U.radii[W.m];
+  B.j = W.j & (N - 1);
+  B.r = radii[W.m];
   const double s = sqrt((1.0 - B.r) * (1.0 + B.r));
-  B.wjx = U.omega[2 * B.j];
-  B.wjy = -U.omega[2 * B.j + 1];  // e^{-2 pi i j/N}
+  B.wjx = omega[2 * B.j];
+  B.wjy = -omega[2 * B.j + 1];  // e^{-2 pi i j/N}
   B.csx = W.cx * s;
   B.csy = W.cy * s;
   return B;
+}
+
+__device__ __forceinline__ Blaschke blaschke_of(const UpdateArgs& U) {
+  return blaschke_of(*U.R.w, U.radii, U.omega, U.N, U.M);
 }
 
 __device__ __forceinline__ void blaschke_apply(const Blaschke& B, const double* __restrict__ omega, int N, int n,
@@ -43,6 +47,55 @@ __device__ __forceinline__ void blaschke_apply(const Blaschke& B, const double* 
   const double qy = fma(ny, dx, -nx * dy) * inv;
   hx = fma(qx, B.wjx, -qy * B.wjy);
   hy = fma(qx, B.wjy, qy * B.wjx);
+}
+
+// Winner of the short-list from the chunk partial sums of the direct rule
+// (Sec. 3.1, eq. term81): partials[i][ch] holds the (re, im) sum of
+// G[n] / (1 - r_i e^{2 pi i (j_i - n)/N}) over chunk ch of the samples for
+// candidate i; the inner product is that sum times sqrt(1 - r_i^2)/N.  One
+// candidate per thread (count <= kKMax <= blockDim.x): thread i passes its
+// key and radius (ignored for i >= count).  Largest |.|^2 wins, ties to the
+// lowest flat index.  Thread 0 writes the result to *w (any address space);
+// `bb`, `wd`: LDS Best[16], double[16].
+__device__ __forceinline__ void winner_from_partials(int count, int cflags, uint64_t key, double r,
+                                                     const double* __restrict__ partials, int N, int logn, int nch,
+                                                     Winner* w, Best* bb, double* wd) {
+  const bool forced = (cflags & kFlagForced) != 0;
+  Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
+  double err = 0.0;
+  if (int(threadIdx.x) < count) {
+    const double* pp = partials + 2 * size_t(threadIdx.x) * nch;
+    double ax = 0.0, ay = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      ax += ld_agent(pp + 2 * ch);
+      ay += ld_agent(pp + 2 * ch + 1);
+    }
+    const double s = sqrt((1.0 - r) * (1.0 + r)) / double(N);
+    const Best x{(ax * s) * (ax * s) + (ay * s) * (ay * s), -1.0, ax * s, ay * s, key_f(key)};
+    err = fabs(double(key_p(key)) - x.p1);
+    b = x;
+  }
+  const Best rb = block_best(b, bb);
+  err = wave_max_f64(err);
+  if ((threadIdx.x & 63) == 0) wd[threadIdx.x >> 6] = err;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = wd[0];
+    for (int i = 1; i < nwaves(); ++i) e = fmax(e, wd[i]);
+    Winner o;
+    const bool valid = count > 0 && rb.f != 0xffffffffu;
+    o.m = valid ? int32_t(rb.f >> logn) : 0;
+    o.j = valid ? int32_t(rb.f & uint32_t(N - 1)) : 0;
+    o.cx = valid ? rb.vx : 0.0;
+    o.cy = valid ? rb.vy : 0.0;
+    if (forced || count < 2 || !valid) o.margin = __builtin_nan("");
+    else o.margin = rb.p1 > 0.0 ? (rb.p1 - rb.p2) / rb.p1 : 0.0;
+    o.kcount = forced ? 1 : count;
+    o.flags = cflags & 7;
+    o.ax = o.ay = 0.0;
+    o.fp32err = (forced || !valid || !(rb.p1 > 0.0)) ? 0.0 : e / rb.p1;
+    *w = o;
+  }
 }
 
 // The record of signal b of a batch.
