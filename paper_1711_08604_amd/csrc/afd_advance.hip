@@ -31,6 +31,7 @@ constexpr int kAdvChunk = 64 * kAdvPts;   // samples per re-check task
 // Spin limit of a grid barrier wait (seconds): a wait that runs out reports
 // an error instead of hanging.
 constexpr unsigned int kAdvSpinLimit = 1u << 22;
+constexpr int kBarStride = 16;  // barrier counters 128 bytes apart
 
 template <int LOGN>
 struct AdvShape {
@@ -70,26 +71,40 @@ __device__ __forceinline__ Cx<float> ld_agent(const Cx<float>* p) {
 }
 __device__ __forceinline__ Cx<double> ld_agent(const Cx<double>* p) { return {ld_agent(&p->x), ld_agent(&p->y)}; }
 
-// Grid barrier on a counter that only grows during a call: every workgroup
-// arrives once per barrier, and a barrier is passed when the count reaches
-// the arrivals of every earlier barrier of the call plus its own.  Each wave
-// waits for its stores to complete before its workgroup counts the arrival,
-// so the agent-scope loads after the wait see them.
+// Grid barrier on counters that only grow during a call.  Workgroup w
+// arrives on counter w mod 8 (eight counters on separate cache lines, so
+// that arrivals do not queue on one address), and a barrier is passed when
+// every counter has reached the arrivals of the call's earlier barriers plus
+// this one's.  Each wave waits for its stores to complete before its
+// workgroup counts the arrival, so the agent-scope loads after the wait see
+// them.
 __device__ __forceinline__ void grid_arrive(unsigned long long* ctr) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(ctr + (blockIdx.x % kBarGroups) * kBarStride, 1ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void grid_wait(unsigned long long* ctr, unsigned long long target, int* status) {
-  if (threadIdx.x == 0) {
+// Lanes 0..7 of wave 0 poll one counter each against target[lane].
+__device__ __forceinline__ void grid_wait(unsigned long long* ctr, const unsigned long long (&target)[kBarGroups],
+                                          int* status) {
+  if (threadIdx.x < 64) {
+    const int g = int(threadIdx.x);
+    unsigned long long tg = 0;
+#pragma unroll
+    for (int k = 0; k < kBarGroups; ++k)
+      if (g == k) tg = target[k];
     unsigned int spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    for (;;) {
+      const unsigned long long v =
+          g < kBarGroups ? __hip_atomic_load(ctr + g * kBarStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ~0ull;
+      if (__ballot(v >= tg) == ~0ull) break;
       __builtin_amdgcn_s_sleep(2);
       ++spins;
       // after one wait of the call has run out, the others stop early
       if (spins >= kAdvSpinLimit ||
           ((spins & 1023u) == 0 && (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2))) {
-        atomicOr(status, 2);
+        if (g == 0) atomicOr(status, 2);
         break;
       }
     }
@@ -255,7 +270,9 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
   if (runA) {
     const int tasks = count * S::NCH;
     const int stride = int(gridDim.x) * WPB;
-    int task = w * WPB + wave;
+    // the re-check-only workgroups take the first tasks: the transform
+    // workgroups have their own loads in flight
+    int task = w >= S::NB ? (w - S::NB) * WPB + wave : (int(gridDim.x) - S::NB + w) * WPB + wave;
     // the key of a task is read before the count is known (keys has kKMax entries)
     uint64_t knext = cand->keys[min(task / S::NCH, kKMax - 1)];
     for (; task < tasks; task += stride) {
@@ -289,10 +306,13 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
       }
     }
   }
-  unsigned long long target = a.bar_base;
+  unsigned long long target[kBarGroups];
+#pragma unroll
+  for (int k = 0; k < kBarGroups; ++k) target[k] = a.bar_base[k];
   if (fused && recheck) {
     grid_arrive(a.bar);
-    target += gridDim.x;
+#pragma unroll
+    for (int k = 0; k < kBarGroups; ++k) target[k] += bar_group_count(int(gridDim.x), k);
     if (!runB) return;  // re-check only
     grid_wait(a.bar, target, a.status);
   }
@@ -348,7 +368,8 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
   }
   if (fused) {
     grid_arrive(a.bar);
-    target += S::NB;
+#pragma unroll
+    for (int k = 0; k < kBarGroups; ++k) target[k] += bar_group_count(S::NB, k);
     if (!a.fft && w != 0) return;
     grid_wait(a.bar, target, a.status);
   }
@@ -455,9 +476,11 @@ static hipError_t launch_advance_t(const AdvanceArgs& a0, int batch, hipStream_t
   return hipGetLastError();
 }
 
-unsigned long long advance_arrivals(int logn, const AdvanceArgs& a) {
+void advance_bar_advance(int logn, AdvanceArgs& a) {
   const AdvGeom g = advance_geom(logn);
-  return (a.update && a.recheck ? (unsigned long long)g.ga : 0ull) + (unsigned long long)g.nb;
+  const bool recheck = a.update && a.recheck;
+  for (int k = 0; k < kBarGroups; ++k)
+    a.bar_base[k] += (recheck ? bar_group_count(g.ga, k) : 0ull) + bar_group_count(g.nb, k);
 }
 
 hipError_t launch_advance(int logn, bool fp64, const AdvanceArgs& a, int batch, hipStream_t s, hipEvent_t e0,

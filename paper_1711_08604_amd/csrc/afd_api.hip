@@ -182,7 +182,7 @@ Layout layout_of(const Config& c) {
   L.nonfinite = take(4);
   L.forced0 = take(8);
   L.counters = take(4 * kNumCounters * B);  // [kind][signal]
-  L.bar = take(8);
+  L.bar = take(8 * 16 * kBarGroups);  // counters 128 bytes apart
   // fused step tail in single precision: the unit roots rounded to float
   L.omega_t = take(c.adv && !c.fp64 ? 8 * size_t(c.N) : 0);
   L.total = o;
@@ -487,13 +487,12 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
   a.partials = p->at<double>(p->L.partials);
   a.epart = p->at<double>(p->L.epart);
   a.bar = p->at<unsigned long long>(p->L.bar);
-  a.bar_base = 0;
   a.status = p->at<int>(p->L.nonfinite);
   a.R = rec;
   a.M = c.M;
   auto advance = [&](hipEvent_t e0, hipEvent_t e1) -> hipError_t {
     const hipError_t e = launch_advance(c.logn, c.fp64, a, B, s, e0, e1);
-    if (B == 1) a.bar_base += advance_arrivals(c.logn, a);
+    if (B == 1) advance_bar_advance(c.logn, a);
     return e;
   };
   if (steps > 0 && !forced_at(0)) {
@@ -598,7 +597,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   // flags and last-workgroup counters start at zero (also after an aborted call)
   HIPCHK(hipMemsetAsync(nonfinite, 0, 4, s), "clearing flag");
   HIPCHK(hipMemsetAsync(counters, 0, 4 * kNumCounters * size_t(B), s), "clearing counters");
-  if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.bar, 0, 8, s), "clearing counters");
+  if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.bar, 0, 8 * 16 * kBarGroups, s), "clearing counters");
   if (c.big)
     HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4 * (size_t(c.chunk) + 1), s), "clearing counters");
   HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N) * B, sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,

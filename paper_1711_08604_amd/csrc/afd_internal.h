@@ -159,6 +159,13 @@ struct UpdateArgs {
   int step;
 };
 
+// Grid barriers of the fused step tail count arrivals on kBarGroups
+// counters: workgroup w arrives on counter w mod kBarGroups.
+constexpr int kBarGroups = 8;
+__host__ __device__ constexpr unsigned long long bar_group_count(int nw, int g) {
+  return nw > g ? (unsigned long long)((nw - 1 - g) / kBarGroups + 1) : 0ull;
+}
+
 // Step tail for 2^12 <= N <= 2^14 (afd_advance.hip): re-check, winner,
 // remainder update and the forward DFT of the new remainder.
 struct AdvanceArgs {
@@ -174,8 +181,8 @@ struct AdvanceArgs {
   void* c;                  // spectrum of the new remainder (T complex)
   double* partials;         // [kKMax][nch] (re, im) re-check partial sums
   double* epart;            // [nb] energy partial sums
-  unsigned long long* bar;  // grid barrier counter (zero at the start of a call)
-  unsigned long long bar_base;  // arrivals of the call's earlier launches
+  unsigned long long* bar;  // grid barrier counters, kBarGroups of them (zero at the start of a call)
+  unsigned long long bar_base[kBarGroups];  // per counter: arrivals of the call's earlier launches
   int* status;              // bit 1: a grid barrier wait ran out
   RecordArgs R;
   int step;
@@ -196,8 +203,8 @@ bool advance_supported(int logn);
 AdvGeom advance_geom(int logn);
 // Stockham twiddle table of the length-2^l DFTs of the step tail (l = 6, 7).
 void advance_twiddles(int l, double* out_interleaved);
-// Grid barrier arrivals of one launch_advance with batch 1.
-unsigned long long advance_arrivals(int logn, const AdvanceArgs& a);
+// Add the grid barrier arrivals of one launch_advance with batch 1 to a.bar_base.
+void advance_bar_advance(int logn, AdvanceArgs& a);
 // One launch with grid barriers for batch 1; one launch per phase otherwise.
 hipError_t launch_advance(int logn, bool fp64, const AdvanceArgs& a, int batch, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
