@@ -455,15 +455,20 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
   __syncthreads();
   const uint32_t nbb = S->sblocks;
   const uint32_t ncb = nbb < uint32_t(kSelCap) ? nbb : uint32_t(kSelCap);
-  // one wave per band block: one coalesced load of its (at most 64) keys
+  // one wave per band block: its count, total and all kListC key slots in
+  // one round trip (slots at or beyond the count are masked)
   for (uint32_t i = wave; i < ncb; i += nw) {
     const BlockList32* L = lists + S->cblk[i];
-    const uint32_t cnt = ld_agent(&L->count);
-    const uint64_t k = lane < int(cnt) ? ld_agent(&L->keys[lane]) : 0;
+    const uint32_t cnt = uint32_t(__builtin_amdgcn_readfirstlane(int(ld_agent(&L->count))));
+    const uint32_t tot = uint32_t(__builtin_amdgcn_readfirstlane(int(ld_agent(&L->total))));
+    const uint64_t k = ld_agent(&L->keys[lane]);
     const bool q = lane < int(cnt) && key_p(k) >= theta;
     wave_append(q, k, &S->scount, S->buf, uint32_t(kSelCap));
-    if (lane == 0 && cnt > 0 && ld_agent(&L->total) > cnt && key_p(ld_agent(&L->keys[cnt - 1])) >= theta)
-      atomicOr(&S->sflags, uint32_t(kFlagListTruncated));
+    // the list was cut inside the band: its last listed key is still in it
+    if (cnt > 0 && cnt <= uint32_t(kListC) && tot > cnt) {
+      const uint64_t klast = lane_u64(k, int(cnt) - 1);
+      if (lane == 0 && key_p(klast) >= theta) atomicOr(&S->sflags, uint32_t(kFlagListTruncated));
+    }
   }
   __syncthreads();
   const uint32_t band = S->scount;
