@@ -21,6 +21,7 @@ paper's source gives them (the compiled number in brackets):
   forward DFT of the samples, per-radius inverse DFT
 * Sec. 3.2, Steps 1 and 2  all grid values, then the maximum
 * Sec. 4, eq. er [24]      relative error delta
+* Sec. 4 (case 2)          analytic (H^2) part of real boundary samples
 
 Readings adopted where the paper is silent or inconsistent (each is also
 listed with its reason in the design notes):
@@ -55,6 +56,8 @@ __all__ = [
     "decompose",
     "tm_basis",
     "partial_sum",
+    "relative_errors",
+    "analytic_part",
     "Decomposition",
 ]
 
@@ -233,3 +236,35 @@ def partial_sum(coefs, a_list, z: np.ndarray) -> np.ndarray:
     """S_n = sum_k <G_k, e_{a_k}> B_k on the samples (Sec. 2 expansion (Sn))."""
     B = tm_basis(a_list, z)
     return np.asarray(coefs) @ B
+
+
+def relative_errors(G, coefs, a_list) -> np.ndarray:
+    """delta_n = ||G - S_n||_N^2 / ||G||_N^2 for n = 1..len(a_list) (Sec. 4, eq. er),
+    with S_n the partial sum of expansion (Sn) on the N samples."""
+    G = np.asarray(G, dtype=np.complex128)
+    z = circle_points(G.shape[0])
+    B = tm_basis(a_list, z)
+    S = np.zeros_like(G)
+    out = []
+    for k in range(len(a_list)):
+        S = S + coefs[k] * B[k]
+        out.append(energy(G - S) / energy(G))
+    return np.asarray(out, dtype=np.float64)
+
+
+def analytic_part(x) -> np.ndarray:
+    """Boundary samples of the H^2 (analytic) function whose real part matches
+    real samples x, by the DFT: bin 0 and (N even) bin N/2 kept, bins
+    1..N/2-1 doubled, the negative-frequency bins N/2+1..N-1 removed.  This is
+    how the non-analytic test function of Sec. 4 (case 2) is brought into the
+    Hardy space before the decomposition."""
+    x = np.asarray(x, dtype=np.complex128)
+    n = x.shape[0]
+    h = np.zeros(n)
+    h[0] = 1.0
+    if n % 2 == 0:
+        h[1:n // 2] = 2.0
+        h[n // 2] = 1.0
+    else:
+        h[1:(n + 1) // 2] = 2.0
+    return np.fft.ifft(np.fft.fft(x) * h)

@@ -279,6 +279,44 @@ def pin_selection_rules(O):
     assert _rel(r.coef, d.coef) < 1e-15 and _rel(r.energy, d.energy) < 1e-15
 
 
+# ------------------------------------------------------------------ relative error (Sec. 4, eq. er)
+def pin_relative_errors(O):
+    """delta_n from the partial sums equals E_n/E_0 from the remainders at every
+    n (expansion (Sn) with a unimodular Blaschke factor); one kernel e_b picked
+    at b reconstructs exactly (delta_1 = 0)."""
+    g, radii, _ = W.config1()
+    g = g[::8]
+    d = O.decompose(g, radii[::5], 6)
+    dl = O.relative_errors(g, d.coef, d.a)
+    assert np.max(np.abs(dl - d.energy[1:] / d.energy[0])) < 1e-12
+    N = 64
+    z = O.circle_points(N)
+    b = 0.4 * np.exp(2j * np.pi * 5 / N)
+    gk = (1.5 - 0.5j) * O.szego(b, z)
+    assert O.relative_errors(gk, [(1.5 - 0.5j)], [b])[0] < 1e-28
+
+
+# ------------------------------------------------------------------ analytic part (Sec. 4, case 2)
+def pin_analytic_part(O):
+    """Closed forms: a positive tone cos(2 pi k n/N), 0 < k < N/2, becomes
+    e^{2 pi i k n/N}; a negative-frequency exponential vanishes; the constant
+    and the alternating (Nyquist) sequence are kept; for real samples the
+    real part of the result is the input."""
+    for N in (2, 8, 64, 1024):
+        n = np.arange(N)
+        for k in range(1, N // 2):
+            x = np.cos(2 * np.pi * k * n / N)
+            assert _rel(O.analytic_part(x), np.exp(2j * np.pi * k * n / N)) < 1e-13
+            assert np.max(np.abs(O.analytic_part(np.exp(-2j * np.pi * k * n / N)))) < 1e-13
+            if N > 64 and k > 3:
+                break
+        assert _rel(O.analytic_part(np.full(N, 2.0 + 1.0j)), np.full(N, 2.0 + 1.0j)) < 1e-14
+        alt = (-1.0) ** n
+        assert _rel(O.analytic_part(alt), alt) < 1e-13
+        x = _rng(31).standard_normal(N)
+        assert np.max(np.abs(O.analytic_part(x).real - x)) < 1e-13 * np.max(np.abs(x))
+
+
 ALL_PINS = [
     pin_bruteforce_loops,
     pin_fft_equals_direct,
@@ -292,4 +330,6 @@ ALL_PINS = [
     pin_invariances,
     pin_paper_tables,
     pin_selection_rules,
+    pin_relative_errors,
+    pin_analytic_part,
 ]

@@ -108,6 +108,37 @@ def _select_transposed(V, forced=None):
     return (f % M, f // M), 0.0
 
 
+def _analytic_szego_projection(x):
+    x = np.asarray(x, dtype=np.complex128)
+    n = x.shape[0]
+    h = np.zeros(n)
+    h[: n // 2] = 1.0
+    return np.fft.ifft(np.fft.fft(x) * h)
+
+
+def _analytic_negative_bins(x):
+    x = np.asarray(x, dtype=np.complex128)
+    n = x.shape[0]
+    h = np.zeros(n)
+    h[0] = 1.0
+    h[n // 2 + 1:] = 2.0
+    h[n // 2] = 1.0
+    return np.fft.ifft(np.fft.fft(x) * h)
+
+
+def _analytic_no_nyquist(x):
+    x = np.asarray(x, dtype=np.complex128)
+    n = x.shape[0]
+    h = np.zeros(n)
+    h[0] = 1.0
+    h[1:n // 2] = 2.0
+    return np.fft.ifft(np.fft.fft(x) * h)
+
+
+def _relative_errors_off_by_one(G, coefs, a_list):
+    return np.concatenate([[1.0], OA.relative_errors(G, coefs, a_list)[:-1]])
+
+
 def _energy_sum(G):
     return float(np.sum(np.abs(G) ** 2))
 
@@ -123,6 +154,10 @@ MUTANTS = {
     "ties to the last maximum": dict(select=_select_last_max),
     "flat index transposed": dict(select=_select_transposed),
     "energy without 1/N": dict(energy=_energy_sum),
+    "analytic part as the Szego projection": dict(analytic_part=_analytic_szego_projection),
+    "analytic part keeps the negative bins": dict(analytic_part=_analytic_negative_bins),
+    "analytic part drops the Nyquist bin": dict(analytic_part=_analytic_no_nyquist),
+    "relative errors shifted by one step": dict(relative_errors=_relative_errors_off_by_one),
 }
 
 
