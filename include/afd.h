@@ -143,6 +143,37 @@ const char* afd_status_string(afd_status status);
 /* Detail of the last error on the calling thread ("" if none). */
 const char* afd_last_error(void);
 
+/* Partial sum of a decomposition on the circle and its relative errors
+   (Sec. 2, expansion (Sn), with the Takenaka-Malmquist system of eq. (2);
+   Sec. 4, eq. er).  With n = steps, at the plan's N points
+   z_j = e^{2 pi i j/N}:
+     S_n(z) = sum_{k<n} c_k B_k(z),
+     B_k(z) = sqrt(1 - |a_k|^2)/(1 - conj(a_k) z) * prod_{l<k} (z - a_l)/(1 - conj(a_l) z),
+     delta_k = ||G - S_k||_N^2 / ||G||_N^2, k = 1..n (NaN where ||G||_N = 0).
+   a, coef: 2*steps doubles each, interleaved complex as afd_decompose writes
+   them ([B][steps][2] for a plan with batch B), host or device, copied at
+   the call.  signal: 2*N doubles (B*2*N), host or device; required for
+   delta, else nullable.  partial_sum: 2*N doubles out (B*2*N), nullable.
+   delta: steps doubles out (B*steps), nullable.  In double precision on the
+   plan's stream; synchronous.  Errors: AFD_E_INVALID (null plan, steps < 0,
+   a or coef NULL with steps > 0, delta without signal, some |a_k| >= 1),
+   AFD_E_NONFINITE (NaN or Inf in a, coef or signal), AFD_E_NOMEM, AFD_E_HIP.
+   Validation happens before any device work; on error the outputs are
+   untouched. */
+afd_status afd_reconstruct(afd_plan plan, const double* a, const double* coef, int32_t steps,
+                           const double* signal, double* partial_sum, double* delta);
+
+/* Analytic (H^2) part of N boundary samples, the front end that brings a
+   real signal into the Hardy space before the decomposition (Sec. 4,
+   case 2): g = IDFT(h . DFT(x)) with h_0 = 1, h_l = 2 for 0 < l < N/2,
+   h_{N/2} = 1, h_l = 0 for N/2 < l < N (N = 2: h = (1, 1)).  For real x,
+   Re g = x.  x, g: 2*N doubles (B*2*N), interleaved complex, host or
+   device; they may alias.  Two double-precision forward DFTs on the plan's
+   stream (IDFT(y) = conj(DFT(conj(y)))/N); synchronous.  Errors:
+   AFD_E_INVALID (NULL), AFD_E_NONFINITE (NaN or Inf in x), AFD_E_NOMEM,
+   AFD_E_HIP; on error g is untouched. */
+afd_status afd_analytic(afd_plan plan, const double* x, double* g);
+
 /* Per-kernel timing with HIP events recorded on the plan's stream around
    every launch of the kernel class `kernel` ("radius": the fused weighted
    inverse-DFT / |.|^2 / selection kernel; "fft": the forward DFT; "update":

@@ -59,7 +59,7 @@ class ResultDesc(ctypes.Structure):
 EXPORTS = [
     "afd_plan_create", "afd_decompose", "afd_replay", "afd_workspace_bytes", "afd_plan_destroy",
     "afd_status_string", "afd_last_error", "afd_plan_set_timing", "afd_plan_kernel_time",
-    "afd_plan_radius_launch",
+    "afd_plan_radius_launch", "afd_reconstruct", "afd_analytic",
 ]
 
 _lib = None
@@ -95,6 +95,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.afd_plan_kernel_time.restype = ctypes.c_int
     lib.afd_plan_radius_launch.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.afd_plan_radius_launch.restype = ctypes.c_int
+    lib.afd_reconstruct.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.afd_reconstruct.restype = ctypes.c_int
+    lib.afd_analytic.argtypes = [vp, vp, vp]
+    lib.afd_analytic.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -240,6 +244,62 @@ class Plan:
         _check(self._lib.afd_replay(self._h, ctypes.c_void_p(sp), int(steps), ctypes.c_void_p(fptr),
                                     ctypes.byref(rd)))
         return out
+
+    # -- outputs around the loop
+    def _complex_in(self, x, count, name):
+        """Pointer to `count` complex128 values (numpy or torch on the GPU) and a keep-alive."""
+        if _is_torch_cuda(x):
+            import torch
+            if not (x.is_contiguous() and ((x.dtype == torch.complex128 and x.numel() == count)
+                                           or (x.dtype == torch.float64 and x.numel() == 2 * count))):
+                raise ValueError(f"{name} must hold {count} contiguous complex128 values")
+            return x.data_ptr(), x
+        arr = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+        if arr.size != count:
+            raise ValueError(f"{name} must hold {count} complex values")
+        return arr.ctypes.data, arr
+
+    def reconstruct(self, a, coef, signal=None, partial_sum: bool = True):
+        """Partial sum S_n = sum_k c_k B_k on the N circle points and, with the
+        signal, delta_k = ||G - S_k||^2/||G||^2 for k = 1..n (afd_reconstruct).
+        `a`, `coef`: the decomposition's parameters and coefficients, shape
+        (steps,) or (batch, steps).  Returns (S or None, delta or None) as numpy
+        arrays, or torch tensors on the device when `a` is one."""
+        steps = int(np.shape(a)[-1]) if not _is_torch_cuda(a) else int(a.shape[-1])
+        count = steps * self.batch
+        ap, akeep = self._complex_in(a, count, "a")
+        cp, ckeep = self._complex_in(coef, count, "coef")
+        sp, skeep = (self._signal_ptr(signal) if signal is not None else (None, None))
+        lead = (self.batch,) if self.batch > 1 else ()
+        on_dev = _is_torch_cuda(a)
+        if on_dev:
+            import torch
+            S = torch.empty(lead + (self.n,), dtype=torch.complex128, device=a.device) if partial_sum else None
+            D = torch.empty(lead + (steps,), dtype=torch.float64, device=a.device) if signal is not None else None
+            ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        else:
+            S = np.empty(lead + (self.n,), dtype=np.complex128) if partial_sum else None
+            D = np.empty(lead + (steps,), dtype=np.float64) if signal is not None else None
+            ptr = lambda t: t.ctypes.data if t is not None else None  # noqa: E731
+        _check(self._lib.afd_reconstruct(self._h, ctypes.c_void_p(ap), ctypes.c_void_p(cp), steps,
+                                         ctypes.c_void_p(sp), ctypes.c_void_p(ptr(S)), ctypes.c_void_p(ptr(D))))
+        return S, D
+
+    def analytic(self, x):
+        """Analytic (H^2) part of the samples x: IDFT(h . DFT(x)) with the DC and
+        Nyquist bins kept, positive bins doubled and negative bins removed
+        (afd_analytic).  Same shape and location (host or device) as x."""
+        xp, keep = self._complex_in(x, self.n * self.batch, "x")
+        lead = (self.batch,) if self.batch > 1 else ()
+        if _is_torch_cuda(x):
+            import torch
+            g = torch.empty(lead + (self.n,), dtype=torch.complex128, device=x.device)
+            gp = g.data_ptr()
+        else:
+            g = np.empty(lead + (self.n,), dtype=np.complex128)
+            gp = g.ctypes.data
+        _check(self._lib.afd_analytic(self._h, ctypes.c_void_p(xp), ctypes.c_void_p(gp)))
+        return g
 
     # -- measurement
     def set_timing(self, kernel: str = "radius", enable: bool = True):

@@ -216,6 +216,9 @@ struct afd_plan_s {
   int res_steps = -1;
   int32_t* forced = nullptr;
   int forced_steps = -1;
+  // scratch of afd_reconstruct / afd_analytic, grown on demand
+  unsigned char* aux = nullptr;
+  size_t aux_bytes = 0;
   // timing
   int time_kind = kTimeNone;
   double time_ms = 0.0;
@@ -729,6 +732,135 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   return AFD_OK;
 }
 
+afd_status ensure_aux(afd_plan_s* p, size_t bytes) {
+  if (p->aux && p->aux_bytes >= bytes) return AFD_OK;
+  if (p->aux) {
+    (void)hipFree(p->aux);
+    p->aux = nullptr;
+    p->aux_bytes = 0;
+  }
+  const hipError_t e = hipMalloc(&p->aux, bytes);
+  if (e != hipSuccess) {
+    p->aux = nullptr;
+    return fail(AFD_E_NOMEM, std::string("scratch: ") + hipGetErrorString(e));
+  }
+  p->aux_bytes = bytes;
+  return AFD_OK;
+}
+
+// Copy n doubles from host or device memory into `dst` (host).
+hipError_t fetch(std::vector<double>& dst, const double* src, size_t n) {
+  dst.resize(n);
+  return n ? hipMemcpy(dst.data(), src, 8 * n, hipMemcpyDefault) : hipSuccess;
+}
+
+afd_status reconstruct(afd_plan_s* p, const double* a, const double* coef, int steps, const double* signal,
+                       double* partial_sum, double* delta) {
+  if (!p) return fail(AFD_E_INVALID, "plan is NULL");
+  if (steps < 0) return fail(AFD_E_INVALID, "steps must be >= 0");
+  if (steps > 0 && (!a || !coef)) return fail(AFD_E_INVALID, "a and coef are required when steps > 0");
+  if (delta && !signal) return fail(AFD_E_INVALID, "delta needs the signal");
+  const Config& c = p->cfg;
+  const int N = int(c.N), B = c.batch;
+  HIPCHK(hipSetDevice(p->device), "hipSetDevice");
+  const size_t nk = 2 * size_t(steps) * B;
+  std::vector<double> ah, ch, gh;
+  HIPCHK(fetch(ah, a, nk), "reading a");
+  HIPCHK(fetch(ch, coef, nk), "reading coef");
+  for (size_t i = 0; i < nk; i += 2) {
+    if (!std::isfinite(ah[i]) || !std::isfinite(ah[i + 1]) || !std::isfinite(ch[i]) || !std::isfinite(ch[i + 1]))
+      return fail(AFD_E_NONFINITE, "a or coef holds NaN or Inf");
+    if (!(ah[i] * ah[i] + ah[i + 1] * ah[i + 1] < 1.0)) return fail(AFD_E_INVALID, "|a_k| >= 1");
+  }
+  const size_t nsig = 2 * size_t(N) * B;
+  if (signal) {
+    HIPCHK(fetch(gh, signal, nsig), "reading signal");
+    for (double v : gh)
+      if (!std::isfinite(v)) return fail(AFD_E_NONFINITE, "signal holds NaN or Inf");
+  }
+  // scratch: a, coef, signal, partial sums, wave sums, delta
+  const size_t wps = (delta && steps > 0) ? size_t(steps + 1) * recon_waves(N) * B : 0;
+  const size_t o_a = 0, o_c = align_up(o_a + 8 * nk, 256), o_g = align_up(o_c + 8 * nk, 256);
+  const size_t o_s = align_up(o_g + (signal ? 8 * nsig : 0), 256);
+  const size_t o_w = align_up(o_s + (partial_sum ? 8 * nsig : 0), 256);
+  const size_t o_d = align_up(o_w + 8 * wps, 256);
+  const size_t total = align_up(o_d + 8 * size_t(steps) * B, 256) + 256;
+  afd_status st = ensure_aux(p, total);
+  if (st != AFD_OK) return st;
+  hipStream_t s = p->stream;
+  double* da = reinterpret_cast<double*>(p->aux + o_a);
+  double* dc = reinterpret_cast<double*>(p->aux + o_c);
+  double* dg = signal ? reinterpret_cast<double*>(p->aux + o_g) : nullptr;
+  double* ds = partial_sum ? reinterpret_cast<double*>(p->aux + o_s) : nullptr;
+  double* dw = wps ? reinterpret_cast<double*>(p->aux + o_w) : nullptr;
+  double* dd = reinterpret_cast<double*>(p->aux + o_d);
+  if (nk) {
+    HIPCHK(hipMemcpyAsync(da, ah.data(), 8 * nk, hipMemcpyHostToDevice, s), "uploading a");
+    HIPCHK(hipMemcpyAsync(dc, ch.data(), 8 * nk, hipMemcpyHostToDevice, s), "uploading coef");
+  }
+  if (dg) HIPCHK(hipMemcpyAsync(dg, gh.data(), 8 * nsig, hipMemcpyHostToDevice, s), "uploading signal");
+  if (ds || dw)
+    HIPCHK(launch_recon(da, dc, steps, N, p->at<double>(p->L.omega), dg, ds, dw, delta ? dd : nullptr, B, s),
+           "k_recon");
+  if (partial_sum) HIPCHK(hipMemcpyAsync(partial_sum, ds, 8 * nsig, hipMemcpyDefault, s), "copy partial sum");
+  if (delta && steps > 0)
+    HIPCHK(hipMemcpyAsync(delta, dd, 8 * size_t(steps) * B, hipMemcpyDefault, s), "copy delta");
+  HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
+  g_last_error.clear();
+  return AFD_OK;
+}
+
+afd_status analytic(afd_plan_s* p, const double* x, double* g) {
+  if (!p) return fail(AFD_E_INVALID, "plan is NULL");
+  if (!x || !g) return fail(AFD_E_INVALID, "x and g are required");
+  const Config& c = p->cfg;
+  const int N = int(c.N), B = c.batch, logn = c.logn;
+  HIPCHK(hipSetDevice(p->device), "hipSetDevice");
+  const size_t nsig = 2 * size_t(N) * B;
+  const bool x_dev = is_device_pointer(x);
+  std::vector<double> xh;
+  if (!x_dev) {
+    for (size_t i = 0; i < nsig; ++i)
+      if (!std::isfinite(x[i])) return fail(AFD_E_NONFINITE, "x holds NaN or Inf");
+  }
+  // double-precision forward DFT tables of the standard (non-fused) plan
+  const FwdPlan fp = fwd_plan(logn, true);
+  std::vector<double> tw1(2 * size_t(fp.tw1_size + 1), 0.0), tw2(2 * size_t(fp.tw2_size + 1), 0.0);
+  fft_twiddles(fp.two_pass ? fp.l1 : logn, true, tw1.data());
+  if (fp.two_pass) fft_twiddles(fp.l2, true, tw2.data());
+  const size_t o_x = 0, o_y = align_up(8 * nsig, 256), o_t = align_up(o_y + 8 * nsig, 256);
+  const size_t o_w1 = align_up(o_t + (fp.two_pass ? 8 * nsig : 0), 256);
+  const size_t o_w2 = align_up(o_w1 + 8 * tw1.size(), 256);
+  const size_t o_f = align_up(o_w2 + 8 * tw2.size(), 256);
+  afd_status st = ensure_aux(p, o_f + 256);
+  if (st != AFD_OK) return st;
+  hipStream_t s = p->stream;
+  double* X = reinterpret_cast<double*>(p->aux + o_x);
+  double* Y = reinterpret_cast<double*>(p->aux + o_y);
+  void* xt = p->aux + o_t;
+  void* w1 = p->aux + o_w1;
+  void* w2 = p->aux + o_w2;
+  int* flag = reinterpret_cast<int*>(p->aux + o_f);
+  HIPCHK(hipMemcpyAsync(w1, tw1.data(), 8 * tw1.size(), hipMemcpyHostToDevice, s), "uploading twiddles");
+  HIPCHK(hipMemcpyAsync(w2, tw2.data(), 8 * tw2.size(), hipMemcpyHostToDevice, s), "uploading twiddles");
+  HIPCHK(hipMemsetAsync(flag, 0, 4, s), "clearing flag");
+  HIPCHK(hipMemcpyAsync(Y, x, 8 * nsig, x_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s), "copying x");
+  const int cl1 = logn > kMaxLdsLogN ? fp.l1 : 0, cl2 = logn > kMaxLdsLogN ? fp.l2 : 0;
+  HIPCHK(launch_fwd(logn, true, Y, w1, w2, p->at<double>(p->L.omega), xt, X, B, s), "forward DFT");
+  HIPCHK(launch_analytic_mask(X, Y, N, cl1, cl2, flag, B, s), "k_analytic_mask");
+  HIPCHK(launch_fwd(logn, true, Y, w1, w2, p->at<double>(p->L.omega), xt, X, B, s), "forward DFT");
+  // the result goes to the caller's memory, or through Y to the host
+  const bool g_dev = is_device_pointer(g);
+  HIPCHK(launch_analytic_out(X, g_dev ? g : Y, N, cl1, cl2, flag, B, s), "k_analytic_out");
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, s), "reading flag");
+  HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (bad) return fail(AFD_E_NONFINITE, "x holds NaN or Inf");
+  if (!g_dev) HIPCHK(hipMemcpy(g, Y, 8 * nsig, hipMemcpyDeviceToHost), "copy g");
+  g_last_error.clear();
+  return AFD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -805,6 +937,7 @@ void afd_plan_destroy(afd_plan plan) {
   if (plan->arena) (void)hipFree(plan->arena);
   if (plan->res) (void)hipFree(plan->res);
   if (plan->forced) (void)hipFree(plan->forced);
+  if (plan->aux) (void)hipFree(plan->aux);
   delete plan;
 }
 
@@ -821,6 +954,13 @@ const char* afd_status_string(afd_status status) {
 }
 
 const char* afd_last_error(void) { return g_last_error.c_str(); }
+
+afd_status afd_reconstruct(afd_plan plan, const double* a, const double* coef, int32_t steps, const double* signal,
+                           double* partial_sum, double* delta) {
+  return reconstruct(plan, a, coef, steps, signal, partial_sum, delta);
+}
+
+afd_status afd_analytic(afd_plan plan, const double* x, double* g) { return analytic(plan, x, g); }
 
 afd_status afd_plan_set_timing(afd_plan plan, const char* kernel, int32_t enable) {
   if (!plan || !kernel) return fail(AFD_E_INVALID, "plan or kernel is NULL");

@@ -279,4 +279,16 @@ hipError_t launch_recheck(const CandList* cand, const double* g, const double* o
 hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, int batch, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+// Reconstruction and analytic front end (afd_recon.hip), double precision.
+int recon_waves(int N);  // wave partial sums per signal and step in `wpart`
+// S (nullable): partial sums [batch][N]; wpart/delta (nullable, together):
+// [batch][steps+1][recon_waves(N)] scratch and [batch][steps] relative errors.
+hipError_t launch_recon(const double* a, const double* c, int steps, int N, const double* omega, const double* G,
+                        double* S, double* wpart, double* delta, int batch, hipStream_t s);
+// cols_l2 > 0: the forward DFT's column-order output (bin k2 + 2^cols_l2 k1 at k2 2^cols_l1 + k1)
+hipError_t launch_analytic_mask(const double* X, double* Y, int N, int cols_l1, int cols_l2, int* flag, int batch,
+                                hipStream_t s);
+hipError_t launch_analytic_out(const double* Z, double* g, int N, int cols_l1, int cols_l2, const int* flag,
+                               int batch, hipStream_t s);
+
 }  // namespace afd

@@ -79,6 +79,8 @@ def test_null_arguments():
     lib.afd_plan_destroy(None)
     assert lib.afd_plan_set_timing(None, b"radius", 1) == 1
     assert lib.afd_workspace_bytes(None) == 0
+    assert lib.afd_reconstruct(None, None, None, 0, None, None, None) == 1
+    assert lib.afd_analytic(None, None, None) == 1
 
 
 def test_workspace_bytes_scales():
