@@ -47,11 +47,13 @@ struct AdvShape {
   static constexpr int GA = N / 256;             // re-check workgroups
   static_assert(N2 / RPB == NB, "column and row passes use the same workgroups");
   static_assert(GA >= NB && NCH >= 1, "geometry");
+  // the transforms' exchange regions, or (before them) the scratch of the merge
   template <typename T>
   static constexpr size_t lds_bytes() {
     constexpr size_t a = CPB * align16(size_t(Shape<L2, kAdvE>::LDS_ELEMS) * sizeof(Cx<T>));
     constexpr size_t b = RPB * align16(size_t(Shape<L1, kAdvE>::LDS_ELEMS) * sizeof(Cx<T>));
-    return a > b ? a : b;
+    constexpr size_t t = a > b ? a : b;
+    return t > sizeof(MergeScratch) ? t : sizeof(MergeScratch);
   }
 };
 
@@ -206,6 +208,7 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double wd[16];
   __shared__ Winner s_win;
+  __shared__ CandList s_cand;
   const int tid = int(threadIdx.x), w = int(blockIdx.x), b = int(blockIdx.y);
   const int lane = tid & 63, wave = tid >> 6;
   const bool fused = a.phase < 0;
@@ -214,7 +217,11 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
   const bool runB = w < S::NB && (fused || a.phase == 1);
   const bool runC = w < S::NB && (fused || a.phase == 2);
 
-  const CandList* __restrict__ cand = a.cand + b;
+  // the radius kernel's records are merged here (by every workgroup that
+  // needs the short-list or the winner; all reach the same result)
+  const bool merge = a.update && a.nrec > 0 && (fused || a.phase <= 1);
+  MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
+  const CandList* cand = a.cand + b;
   Winner* __restrict__ winner = a.winner + b;
   double* __restrict__ g64 = a.g64 + 2 * size_t(N) * b;
   Cx<T>* __restrict__ xt = reinterpret_cast<Cx<T>*>(a.xt) + size_t(N) * b;
@@ -246,6 +253,13 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
     }
   }
   if (runC && a.fft) tw_regs_load(twr, tr, reinterpret_cast<const Cx<T>*>(a.tw1));
+  if (merge && recheck) {
+    select32_tail<4>(reinterpret_cast<const BlockList32*>(a.recs) + size_t(a.nrec) * b, a.heads + size_t(a.nrec) * b,
+                  a.seconds + size_t(a.nrec) * b, a.nrec, a.recheck_k, a.tau_band, a.flagword + b, &s_cand, Sm,
+                  false);
+    __syncthreads();
+    cand = &s_cand;
+  }
   int count = 0, cflags = 0;
   if (recheck) {
     count = min(max(cand->count, 0), kKMax);
@@ -315,6 +329,8 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
     for (int k = 0; k < kBarGroups; ++k) target[k] += bar_group_count(int(gridDim.x), k);
     if (!runB) return;  // re-check only
     grid_wait(a.bar, target, a.status);
+    // every merge has read the step's fallback flag
+    if (merge && w == 0 && tid == 0) st_agent(a.flagword + b, 0u);
   }
   if (!runB && !runC) return;
 
@@ -332,8 +348,14 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
             if (w == 0) *winner = o;
           }
         }
+      } else if (merge) {
+        // the FP64 grid maximum from the radius kernel's records
+        merge64_tail<4>(reinterpret_cast<const BlockBest64*>(a.recs) + size_t(a.nrec) * b, a.nrec, N, LOGN, &s_win,
+                     Sm);
+        __syncthreads();
+        if (w == 0 && tid == 0) *winner = s_win;
       } else if (tid == 0) {
-        s_win = *winner;  // the radius kernel's FP64 grid maximum
+        s_win = *winner;  // written by the radius kernel
       }
       __syncthreads();
       B = blaschke_of(s_win, a.radii, a.omega, N, a.M);
@@ -377,6 +399,8 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
   // ---- C: row DFTs, record of the step
   if (runC) {
     const bool rec = a.update && w == 0;
+    // a batch's record launch: every merge of the step has read the fallback flag
+    if (!fused && rec && recheck && a.nrec > 0 && tid == 0) st_agent(a.flagword + b, 0u);
     const double ep = (rec && tid < S::NB) ? ld_agent(epart + tid) : 0.0;
     if (a.fft) {
 #pragma unroll

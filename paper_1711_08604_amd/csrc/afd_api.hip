@@ -46,8 +46,8 @@ struct Layout {
       nonfinite, forced0, counters, bar, omega_t;
   // truncated / pruned spectrum of the LDS-resident radius transforms
   size_t pq, lsig, order;
-  // FP32 head keys of the workgroup (or per-radius) records
-  size_t heads;
+  // FP32 head and second keys of the workgroup (or per-radius) records
+  size_t heads, seconds;
   // radius transforms beyond the LDS
   size_t wl, wh, z, rrec, bcounters;
   size_t total;
@@ -165,6 +165,7 @@ Layout layout_of(const Config& c) {
   // per-signal buffers: `batch` copies back to back
   const size_t B = size_t(c.batch);
   L.heads = take(c.fp64 ? 0 : 8 * size_t(c.big ? c.M : c.nblocks) * B);
+  L.seconds = take(c.fp64 || c.big ? 0 : 8 * size_t(c.nblocks) * B);
   L.g64 = take(16 * size_t(c.N) * B);
   L.g32 = take(c.fp64 || c.adv ? 0 : 8 * size_t(c.N) * B);
   L.c = take(2 * real * size_t(c.N) * B);
@@ -491,6 +492,12 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
   a.epart = p->at<double>(p->L.epart);
   a.bar = p->at<unsigned long long>(p->L.bar);
   a.status = p->at<int>(p->L.nonfinite);
+  a.recs = p->at<void>(p->L.blocks);
+  a.heads = c.fp64 ? nullptr : p->at<uint64_t>(p->L.heads);
+  a.seconds = c.fp64 ? nullptr : p->at<uint64_t>(p->L.seconds);
+  a.recheck_k = p->recheck_k;
+  a.tau_band = p->tau_band;
+  a.flagword = p->at<unsigned int>(p->L.counters) + 4 * B;
   a.R = rec;
   a.M = c.M;
   auto advance = [&](hipEvent_t e0, hipEvent_t e1) -> hipError_t {
@@ -503,6 +510,7 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
     HIPCHK(tm.pair(kTimeFft, &e0, &e1), "event");
     a.update = 0;
     a.recheck = 0;
+    a.nrec = 0;
     a.fft = 1;
     a.step = -1;
     HIPCHK(advance(e0, e1), "k_advance");
@@ -523,6 +531,7 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
     HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
     a.update = 1;
     a.recheck = (!c.fp64 || forced) ? 1 : 0;
+    a.nrec = forced ? 0 : c.nblocks;  // a forced point comes as a one-entry short-list
     a.fft = (k + 1 < steps && !forced_at(k + 1)) ? 1 : 0;
     a.step = k;
     HIPCHK(advance(u0, u1), "k_advance");
@@ -625,9 +634,11 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.out = p->at<void>(p->L.blocks);
   rp.counter = counters + 0 * B;
   rp.heads = p->at<uint64_t>(p->L.heads);
+  rp.seconds = p->at<uint64_t>(p->L.seconds);
   rp.flagword = counters + 4 * B;
   rp.cand = cand;
   rp.winner = win;
+  rp.tail = c.adv ? 0 : 1;  // with the fused step tail, the tail merges the records
 
   BigParams bp{};
   if (c.big) {

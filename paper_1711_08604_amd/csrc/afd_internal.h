@@ -81,10 +81,12 @@ struct RadiusParams {
   int recheck_k;      // FP32: minimum short-list length
   void* out;          // BlockBest64[blocks] or BlockList32[blocks]
   uint64_t* heads;    // FP32: [blocks] head key (best point) of each workgroup list
+  uint64_t* seconds;  // FP32: [blocks] second key of each workgroup list (0: none)
   unsigned int* flagword;  // FP32: fallback flag of the step (zero between steps)
   unsigned int* counter;  // last-workgroup counter (zero between launches)
   CandList* cand;     // FP32 short-list (written by the last workgroup)
   Winner* winner;     // FP64 winner (written by the last workgroup)
+  int tail;           // 1: the last workgroup merges the records; 0: the step tail merges them
 };
 
 // Radius transforms beyond the LDS (N > 2^kMaxLdsLogN): per radius a
@@ -184,6 +186,15 @@ struct AdvanceArgs {
   unsigned long long* bar;  // grid barrier counters, kBarGroups of them (zero at the start of a call)
   unsigned long long bar_base[kBarGroups];  // per counter: arrivals of the call's earlier launches
   int* status;              // bit 1: a grid barrier wait ran out
+  // the radius kernel's per-workgroup records, merged here when nrec > 0
+  // (otherwise the short-list is in cand, or the winner in winner)
+  const void* recs;         // [B][nrec] BlockList32 (FP32) or BlockBest64 (FP64)
+  const uint64_t* heads;    // FP32: [B][nrec] head keys
+  const uint64_t* seconds;  // FP32: [B][nrec] second keys
+  int nrec;
+  int recheck_k;
+  float tau_band;
+  unsigned int* flagword;   // FP32: [B] fallback flag of the step, cleared here after the merges
   RecordArgs R;
   int step;
   int M;

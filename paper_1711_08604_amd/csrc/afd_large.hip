@@ -92,7 +92,8 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_A)) void k_big_cols(BigParams p)
 }
 
 template <typename T, int LOGN, bool LIST>
-__global__ __launch_bounds__((Big<T, LOGN>::THR_B)) void k_big_rows(BigParams p) {
+__global__ __launch_bounds__((Big<T, LOGN>::THR_B)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+void k_big_rows(BigParams p) {
   using B = Big<T, LOGN>;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_last;
@@ -115,7 +116,7 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_B)) void k_big_rows(BigParams p)
     const FlatOrder ord{uint32_t(m) * uint32_t(B::N) + uint32_t(blockIdx.x) * uint32_t(B::RB), uint32_t(B::RB),
                         uint32_t(B::N1), uint32_t(B::RB) * uint32_t(B::N2)};
     select_list<B::L2>(v, true, sc, fbase, uint32_t(B::N1), t, scratch, p.tau_band, ord,
-                       reinterpret_cast<BlockList32*>(p.blocks) + rec, nullptr, p.flagword);
+                       reinterpret_cast<BlockList32*>(p.blocks) + rec, nullptr, nullptr, p.flagword);
   } else {
     select_best<B::L2, T>(v, true, sc, fbase, uint32_t(B::N1), t, reinterpret_cast<Best*>(scratch),
                           reinterpret_cast<BlockBest64*>(p.blocks) + rec);
@@ -132,8 +133,8 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_B)) void k_big_rows(BigParams p)
   }
   if (!last_arrival(p.counter_g, unsigned(p.M), &s_last)) return;
   if constexpr (LIST) {
-    select32_tail(reinterpret_cast<const BlockList32*>(p.rrec), p.heads, p.M, p.recheck_k, p.tau_band, p.flagword,
-                  p.cand, Sm);
+    select32_tail(reinterpret_cast<const BlockList32*>(p.rrec), p.heads, nullptr, p.M, p.recheck_k, p.tau_band,
+                  p.flagword, p.cand, Sm);
   } else {
     merge64_tail(reinterpret_cast<const BlockBest64*>(p.rrec), p.M, B::N, LOGN, p.winner, Sm);
   }

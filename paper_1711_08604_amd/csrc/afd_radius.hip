@@ -9,7 +9,8 @@
 // value and the runner-up value; FP32 keeps every point within the re-check
 // band of the workgroup maximum.  The grid values are never written to HBM.
 // The last workgroup to finish merges the per-workgroup records: FP64 into
-// the winner, FP32 into the short-list for the double re-check.
+// the winner, FP32 into the short-list for the double re-check (or, for
+// 2^12 <= N <= 2^14, every workgroup of the step tail merges them itself).
 #include "afd_select.h"
 
 namespace afd {
@@ -20,12 +21,12 @@ __host__ __device__ constexpr int radius_threads() {
   return Shape<LOGN, pickE<T, LOGN>()>::TPR < 64 ? 64 : Shape<LOGN, pickE<T, LOGN>()>::TPR;
 }
 
-// Waves per SIMD the register budget must allow: two workgroups per CU for
-// the 512-thread single-precision transforms (at most 128 VGPRs), no
-// constraint otherwise.
+// Waves per SIMD the register budget must allow: single precision keeps at
+// most 128 VGPRs (two 512-thread or four 256-thread workgroups per CU), no
+// constraint for double precision.
 template <typename T, int LOGN>
 __host__ __device__ constexpr int radius_min_waves() {
-  return (sizeof(T) == 4 && radius_threads<T, LOGN>() == 512) ? 4 : 1;
+  return sizeof(T) == 4 ? 4 : 1;
 }
 
 template <typename T, int LOGN>
@@ -125,19 +126,21 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
     const FlatOrder ord{r0 * uint32_t(N), ract * uint32_t(N), 0u, ract * uint32_t(N)};
     BlockList32* lists = reinterpret_cast<BlockList32*>(prm.out) + size_t(gridDim.x) * b;
     uint64_t* heads = prm.heads + size_t(gridDim.x) * b;
+    uint64_t* seconds = prm.seconds + size_t(gridDim.x) * b;
     select_list<LOGN>(v, active, sc, fbase, 1u, t, scratch, prm.tau_band, ord, lists + blockIdx.x,
-                      heads + blockIdx.x, prm.flagword + b);
+                      heads + blockIdx.x, seconds + blockIdx.x, prm.flagword + b);
   } else {
     select_best<LOGN, T>(v, active, sc, fbase, 1u, t, reinterpret_cast<Best*>(scratch),
                          reinterpret_cast<BlockBest64*>(prm.out) + size_t(gridDim.x) * b + blockIdx.x);
   }
 
+  if (!prm.tail) return;  // the step tail merges the records
   if (!last_arrival(prm.counter + b, gridDim.x, &s_last)) return;
   MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
   if constexpr (LIST) {
     select32_tail(reinterpret_cast<const BlockList32*>(prm.out) + size_t(gridDim.x) * b,
-                  prm.heads + size_t(gridDim.x) * b, int(gridDim.x), prm.recheck_k, prm.tau_band, prm.flagword + b,
-                  prm.cand + b, Sm);
+                  prm.heads + size_t(gridDim.x) * b, prm.seconds + size_t(gridDim.x) * b, int(gridDim.x),
+                  prm.recheck_k, prm.tau_band, prm.flagword + b, prm.cand + b, Sm);
   } else {
     merge64_tail(reinterpret_cast<const BlockBest64*>(prm.out) + size_t(gridDim.x) * b, int(gridDim.x), N, LOGN,
                  prm.winner + b, Sm);

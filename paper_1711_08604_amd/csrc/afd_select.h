@@ -241,10 +241,15 @@ __device__ __forceinline__ void wave0_copy_keys(const uint64_t* src, uint64_t* d
 }
 
 // LDS layout used by the grid-level merges (placed in a kernel's dynamic LDS).
-constexpr int kHeadCap = 2048;  // head keys the FP32 grid merge holds in LDS
+constexpr int kHeadCap = 2048;    // head keys the FP32 grid merge holds in LDS
+constexpr int kSecondCap = 1024;  // second keys it holds (more blocks: every band list is read)
+// Records per thread a grid merge loads in its first round trip (a template
+// parameter PRE of the merges: 2 where a 512-thread workgroup merges inside a
+// register-bound transform kernel, 4 in the 256-thread step tail).
 
 struct MergeScratch {
   uint64_t heads[kHeadCap];
+  uint64_t seconds[kSecondCap];
   uint64_t buf[kSelCap];
   uint32_t cblk[kSelCap];
   uint64_t sorted[kListC];
@@ -377,10 +382,24 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
 
 // FP64: global best of the per-block records -> winner (coefficient = the
 // grid value of the FFT form).
+template <int PRE = 2>
 __device__ __forceinline__ void merge64_tail(const BlockBest64* __restrict__ blocks, int nb, int N, int logn,
                                              Winner* __restrict__ w, MergeScratch* S) {
   Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+  {
+    // the first PRE records of each thread in one round trip
+    Best x[PRE];
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+      const int i = int(threadIdx.x) + q * int(blockDim.x);
+      const BlockBest64* o = blocks + (i < nb ? i : nb - 1);
+      x[q] = Best{ld_agent(&o->p1), ld_agent(&o->p2), ld_agent(&o->vx), ld_agent(&o->vy), ld_agent(&o->f)};
+    }
+#pragma unroll
+    for (int q = 0; q < PRE; ++q)
+      if (int(threadIdx.x) + q * int(blockDim.x) < nb) best_merge(b, x[q]);
+  }
+  for (int i = int(threadIdx.x) + PRE * int(blockDim.x); i < nb; i += blockDim.x) {
     const BlockBest64* o = blocks + i;
     const Best x{ld_agent(&o->p1), ld_agent(&o->p2), ld_agent(&o->vx), ld_agent(&o->vy), ld_agent(&o->f)};
     best_merge(b, x);
@@ -410,24 +429,53 @@ __device__ __forceinline__ void merge64_tail(const BlockBest64* __restrict__ blo
 // the maximum, the band blocks and the top-up candidates.  A flat grid (more
 // band points or band blocks than the gather holds) falls back to an exact
 // pop-merge of the sorted per-block lists.  `flagword` collects the blocks'
-// fallback flag for the step; it is read and cleared here.
+// fallback flag for the step; it is read here, and cleared unless several
+// workgroups merge the same records (then the caller clears it once all
+// have read it).  The result depends only on the records, not on the
+// workgroup size or on scheduling.
+template <int PRE = 2>
 __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ lists,
-                                              const uint64_t* __restrict__ heads, int nb, int recheck_k,
+                                              const uint64_t* __restrict__ heads,
+                                              const uint64_t* __restrict__ seconds, int nb, int recheck_k,
                                               float tau_band, unsigned int* flagword, CandList* __restrict__ cand,
-                                              MergeScratch* S) {
+                                              MergeScratch* S, bool clear_flag = true) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = nwaves();
-  // the head keys, staged in LDS when they fit (otherwise re-read from memory)
+  // the head keys, staged in LDS when they fit (otherwise re-read from
+  // memory), and in the same round trip the second keys
   const bool fits = nb <= kHeadCap;
+  const bool use2 = seconds != nullptr && nb <= kSecondCap;
   uint64_t mx = 0;
-  for (int b = tid; b < nb; b += blockDim.x) {
+  {
+    // the first PRE keys of each thread in one round trip (clamped
+    // addresses, no branches between the loads)
+    uint64_t hk[PRE], sk[PRE];
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) {
+      const int b = tid + i * int(blockDim.x);
+      const int bc = b < nb ? b : nb - 1;
+      hk[i] = ld_agent(heads + bc);
+      sk[i] = use2 ? ld_agent(seconds + bc) : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) {
+      const int b = tid + i * int(blockDim.x);
+      if (b < nb) {
+        if (use2) S->seconds[b] = sk[i];
+        if (fits) S->heads[b] = hk[i];
+        mx = hk[i] > mx ? hk[i] : mx;
+      }
+    }
+  }
+  for (int b = tid + PRE * int(blockDim.x); b < nb; b += blockDim.x) {
     const uint64_t k = ld_agent(heads + b);
+    if (use2) S->seconds[b] = ld_agent(seconds + b);
     if (fits) S->heads[b] = k;
     mx = k > mx ? k : mx;
   }
   if (tid == 0) {
     S->sflags = ld_agent(flagword) & uint32_t(kFlagFallback);
-    st_agent(flagword, 0u);
+    if (clear_flag) st_agent(flagword, 0u);
     S->scount = 0;
     S->sblocks = 0;
   }
@@ -435,11 +483,15 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
   const float pg = gk ? key_p(gk) : -1.f;
   const float theta = pg - pg * tau_band;
   auto head_of = [&](int b) { return fits ? S->heads[b] : ld_agent(heads + b); };
-  // blocks whose head reaches the band
+  // blocks whose head reaches the band: a block whose second key is below
+  // the band contributes its head alone (its list is not read)
   for (int b0 = 0; b0 < nb; b0 += blockDim.x) {
     const int b = b0 + tid;
     const uint64_t k = b < nb ? head_of(b) : 0;
-    const bool q = k != 0 && key_p(k) >= theta;
+    const bool inb = k != 0 && key_p(k) >= theta;
+    const bool alone = inb && use2 && key_p(S->seconds[b]) < theta;
+    wave_append(alone, k, &S->scount, S->buf, uint32_t(kSelCap));
+    const bool q = inb && !alone;
     const uint64_t mask = __ballot(q);
     if (mask) {
       const int leader = __ffsll(static_cast<long long>(mask)) - 1;
@@ -482,21 +534,23 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
       if (fits) {
         // each wave: the top `need` heads below the band among its lanes'
         // heads (b = tid + i blockDim), by rounds of a wave maximum (no
-        // workgroup barrier); the first two heads of a lane stay in registers
-        uint64_t h0 = 0, h1 = 0;
-        {
-          const int b0 = tid, b1 = tid + int(blockDim.x);
-          if (b0 < nb) h0 = S->heads[b0];
-          if (b1 < nb) h1 = S->heads[b1];
-          if (h0 != 0 && key_p(h0) >= theta) h0 = 0;
-          if (h1 != 0 && key_p(h1) >= theta) h1 = 0;
+        // workgroup barrier); the first HR heads of a lane stay in registers
+        constexpr int HR = 4;
+        uint64_t h[HR];
+#pragma unroll
+        for (int i = 0; i < HR; ++i) {
+          const int b = tid + i * int(blockDim.x);
+          h[i] = b < nb ? S->heads[b] : 0;
+          if (h[i] != 0 && key_p(h[i]) >= theta) h[i] = 0;
         }
-        const bool more = nb > 2 * int(blockDim.x);
+        const bool more = nb > HR * int(blockDim.x);
         uint64_t* wl = S->buf;  // free after top_desc: [nw][need]
         for (uint32_t r = 0; r < need; ++r) {
-          uint64_t lm = h0 > h1 ? h0 : h1;
+          uint64_t lm = 0;
+#pragma unroll
+          for (int i = 0; i < HR; ++i) lm = h[i] > lm ? h[i] : lm;
           if (more) {
-            for (int b = tid + 2 * int(blockDim.x); b < nb; b += blockDim.x) {
+            for (int b = tid + HR * int(blockDim.x); b < nb; b += blockDim.x) {
               const uint64_t k = S->heads[b];
               if (k != 0 && key_p(k) < theta && k > lm) lm = k;
             }
@@ -504,10 +558,11 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
           const uint64_t w = wave_max_u64(lm);
           if (lane == 0) wl[uint32_t(wave) * need + r] = w;
           // keys are distinct: one lane owns w
-          if (h0 == w) h0 = 0;
-          if (h1 == w) h1 = 0;
+#pragma unroll
+          for (int i = 0; i < HR; ++i)
+            if (h[i] == w) h[i] = 0;
           if (more && lm == w && w != 0) {
-            for (int b = tid + 2 * int(blockDim.x); b < nb; b += blockDim.x)
+            for (int b = tid + HR * int(blockDim.x); b < nb; b += blockDim.x)
               if (S->heads[b] == w) S->heads[b] = 0;
           }
         }
@@ -615,15 +670,18 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
 constexpr size_t kListScratchBytes = 512 + sizeof(uint64_t) * (kListCap + kListC);
 
 // Header of a workgroup list (thread 0; wave 0 stores the keys): also the
-// workgroup's head key in the dense array read by the grid merge, and the
-// fallback flag of the step.
-__device__ __forceinline__ void list_header(BlockList32* o, uint64_t* head, unsigned int* flagword, float pb,
-                                            uint32_t count, uint32_t total, uint32_t flags, uint64_t first) {
+// workgroup's head key and second key in the dense arrays read by the grid
+// merge (0: none; the second key may exceed the true second, never fall
+// below it), and the fallback flag of the step.
+__device__ __forceinline__ void list_header(BlockList32* o, uint64_t* head, uint64_t* second, unsigned int* flagword,
+                                            float pb, uint32_t count, uint32_t total, uint32_t flags, uint64_t first,
+                                            uint64_t next) {
   st_agent(&o->pmax, pb);
   st_agent(&o->count, count);
   st_agent(&o->total, total);
   st_agent(&o->flags, flags);
   if (head) st_agent(head, count > 0 ? first : uint64_t(0));
+  if (second) st_agent(second, count > 1 ? next : uint64_t(0));
   if (flags && flagword) __hip_atomic_fetch_or(flagword, flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -688,7 +746,7 @@ template <int LOGN>
 __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LOGN>()], bool active, float sc,
                                             uint32_t fbase, uint32_t fstride, int t, unsigned char* scratch,
                                             float tau_band, const FlatOrder& ord, BlockList32* o, uint64_t* head,
-                                            unsigned int* flagword) {
+                                            uint64_t* second, unsigned int* flagword) {
   constexpr int E = pickE<float, LOGN>();
   constexpr int TPR = Shape<LOGN, E>::TPR;
   constexpr int LE = ilog2c(E);
@@ -741,7 +799,9 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
     uint64_t* sorted = reinterpret_cast<uint64_t*>(scratch + 512 + sizeof(uint64_t) * kListCap);
     top_desc(keys, n, sorted, uint32_t(kListC));
     wave0_copy_keys(sorted, o->keys, n < uint32_t(kListC) ? n : uint32_t(kListC));
-    if (tid == 0) list_header(o, head, flagword, pb, n < uint32_t(kListC) ? n : uint32_t(kListC), n, 0u, sorted[0]);
+    if (tid == 0)
+      list_header(o, head, second, flagword, pb, n < uint32_t(kListC) ? n : uint32_t(kListC), n, 0u, sorted[0],
+                  sorted[1]);
     return;
   }
 
@@ -764,7 +824,9 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
   if (pb == pbn) {
     const uint32_t c = ord.count < uint32_t(kListC) ? ord.count : uint32_t(kListC);
     if (uint32_t(tid) < c) st_agent(&o->keys[tid], key32(pb, ord.rank(uint32_t(tid))));  // wave 0 (c <= 64)
-    if (tid == 0) list_header(o, head, flagword, pb, c, ord.count, uint32_t(kFlagFallback), key32(pb, ord.rank(0)));
+    if (tid == 0)
+      list_header(o, head, second, flagword, pb, c, ord.count, uint32_t(kFlagFallback), key32(pb, ord.rank(0)),
+                  key32(pb, ord.rank(1)));
     return;
   }
   {
@@ -808,13 +870,13 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
       top_desc(keys, n2, sorted, uint32_t(kListC));
       const uint32_t c = n2 < uint32_t(kListC) ? n2 : uint32_t(kListC);
       wave0_copy_keys(sorted, o->keys, c);
-      if (tid == 0) list_header(o, head, flagword, pb, c, n, uint32_t(kFlagFallback), sorted[0]);
+      if (tid == 0) list_header(o, head, second, flagword, pb, c, n, uint32_t(kFlagFallback), sorted[0], sorted[1]);
       return;
     }
   }
   uint32_t taken = 0;
   uint32_t rounds = 0;
-  uint64_t first = 0;
+  uint64_t first = 0, next = 0;
   for (; rounds < uint32_t(kListC); ++rounds) {
     uint64_t tb = 0;
 #pragma unroll
@@ -827,13 +889,14 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
     const uint64_t b = block_max_u64(tb, wbest);
     if (b == 0) break;
     if (rounds == 0) first = b;
+    if (rounds == 1) next = b;
     if (tid == 0) st_agent(&o->keys[rounds], b);
 #pragma unroll
     for (int p = 0; p < E; ++p) {
       if (Y[p] > 0.f && key32(Y[p], fbase + fstride * uint32_t(t + TPR * bitrev(p, LE))) == b) taken |= 1u << p;
     }
   }
-  if (tid == 0) list_header(o, head, flagword, pb, rounds, n, uint32_t(kFlagFallback), first);
+  if (tid == 0) list_header(o, head, second, flagword, pb, rounds, n, uint32_t(kFlagFallback), first, next);
 }
 
 }  // namespace afd
