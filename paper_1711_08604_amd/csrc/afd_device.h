@@ -419,15 +419,17 @@ __device__ __forceinline__ int out_bin(int t, int p) {
 }
 
 // ---------------------------------------------------------------- geometry choices
-// Values per thread: 32 for single precision at 2^14 points (fewer LDS
-// exchanges, two workgroups per CU), 16 otherwise.  From 2^12 points the
+// Values per thread: 32 at 2^14 points (fewer LDS exchanges: two instead of
+// three; single precision keeps two workgroups per CU, double precision
+// runs 512 threads in the 256-register budget of two waves per SIMD), 16
+// otherwise.  From 2^12 points the
 // exchange runs real and imaginary parts through half the LDS in turn: at
 // 2^12..2^13 that lets four 256/512-thread workgroups share a CU (measured
 // 1.4x on batches of 2^12-point signals), at 2^14 a single-precision
 // workgroup leaves room for a second one and a double-precision one fits.
 template <typename T, int LOGN>
 __host__ __device__ constexpr int pickE() {
-  return (1 << LOGN) < 16 ? (1 << LOGN) : (sizeof(T) == 4 && LOGN >= 14) ? 32 : 16;
+  return (1 << LOGN) < 16 ? (1 << LOGN) : LOGN >= 14 ? 32 : 16;
 }
 template <typename T, int LOGN>
 __host__ __device__ constexpr bool pickSplit() {

@@ -569,17 +569,33 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
         __syncthreads();
         // ... then the top `need` of the waves' candidates by rank
         const uint32_t nc = uint32_t(nw) * need;
-        for (uint32_t i = tid; i < nc; i += blockDim.x) {
-          const uint64_t k = wl[i];
-          if (k) {
-            uint32_t rank = 0;
-            for (uint32_t j = 0; j < nc; ++j) rank += wl[j] > k ? 1u : 0u;
-            if (rank < need) cand->keys[keff + rank] = k;
-          }
-        }
         uint32_t nz = 0;
-        for (uint32_t j = tid; j < nc; j += blockDim.x) nz += wl[j] ? 1u : 0u;
-        nz = block_reduce_u32<true>(nz, reinterpret_cast<uint32_t*>(S->wf));
+        if (PRE >= 4 && nc <= 64) {
+          // wave 0, one candidate per lane, ranked against the others in
+          // registers (kept out of the 128-register transform kernels)
+          if (wave == 0) {
+            const uint64_t k = uint32_t(lane) < nc ? wl[lane] : 0;
+            uint32_t rank = 0;
+            for (uint32_t j = 0; j < nc; ++j) rank += lane_u64(k, int(j)) > k ? 1u : 0u;
+            if (k && rank < need) cand->keys[keff + rank] = k;
+            // (the band count in scount was read by every thread before the rounds)
+            const uint32_t cnt = uint32_t(__popcll(__ballot(k != 0)));
+            if (lane == 0) S->scount = cnt;
+          }
+          __syncthreads();
+          nz = S->scount;
+        } else {
+          for (uint32_t i = tid; i < nc; i += blockDim.x) {
+            const uint64_t k = wl[i];
+            if (k) {
+              uint32_t rank = 0;
+              for (uint32_t j = 0; j < nc; ++j) rank += wl[j] > k ? 1u : 0u;
+              if (rank < need) cand->keys[keff + rank] = k;
+            }
+          }
+          for (uint32_t j = tid; j < nc; j += blockDim.x) nz += wl[j] ? 1u : 0u;
+          nz = block_reduce_u32<true>(nz, reinterpret_cast<uint32_t*>(S->wf));
+        }
         keff += nz < need ? nz : need;
       } else {
         // many blocks: rounds of a workgroup maximum over all heads below the band
