@@ -43,7 +43,7 @@ enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3 }
 // Device arena layout for one plan.
 struct Layout {
   size_t radii, omega, tw, twf1, twf2, pw, pv, scale, g64, g32, c, xt, blocks, cand, partials, winner, epart,
-      nonfinite, forced0, counters, bar, omega_t;
+      nonfinite, forced0, counters, bar, omega_t, rqueue;
   // truncated / pruned spectrum of the LDS-resident radius transforms
   size_t pq, lsig, order;
   // FP32 head and second keys of the workgroup (or per-radius) records
@@ -184,6 +184,7 @@ Layout layout_of(const Config& c) {
   L.forced0 = take(8);
   L.counters = take(4 * kNumCounters * B);  // [kind][signal]
   L.bar = take(8 * 16 * kBarGroups);  // counters 128 bytes apart
+  L.rqueue = take(4);                  // work queue of the radius slots
   // fused step tail in single precision: the unit roots rounded to float
   L.omega_t = take(c.adv && !c.fp64 ? 8 * size_t(c.N) : 0);
   L.total = o;
@@ -210,6 +211,7 @@ struct afd_plan_s {
   int recheck_k = 8;
   float tau_band = 1e-5f;
   bool first_a_zero = false;
+  int rslots = 0;  // radius workgroups resident at once (queued launches), 0: none
   int zero_m = -1;
   unsigned char* arena = nullptr;
   // per-call result staging on the device
@@ -472,7 +474,7 @@ struct Timer {
 // forced point), then one launch_advance that re-checks, updates and
 // transforms the new remainder for the next step.
 afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const RecordArgs& rec,
-                   const RadiusParams& rp, Timer& tm) {
+                   RadiusParams rp, Timer& tm) {
   const Config& c = p->cfg;
   const int B = c.batch;
   hipStream_t s = p->stream;
@@ -525,7 +527,11 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
     } else {
       hipEvent_t e0, e1;
       HIPCHK(tm.pair(kTimeRadius, &e0, &e1), "event");
-      HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, B, s, e0, e1), "k_radius");
+      const int grid = rp.queue ? p->rslots : c.nblocks;
+      HIPCHK(launch_radius(c.logn, c.fp64, rp, grid, B, s, e0, e1), "k_radius");
+      // the queue hands out the slots past the grid, and each workgroup's last
+      // fetch comes back past the end: nblocks - grid + grid fetches
+      if (rp.queue) rp.qbase += unsigned(c.nblocks);
     }
     hipEvent_t u0, u1;
     HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
@@ -610,6 +616,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   HIPCHK(hipMemsetAsync(nonfinite, 0, 4, s), "clearing flag");
   HIPCHK(hipMemsetAsync(counters, 0, 4 * kNumCounters * size_t(B), s), "clearing counters");
   if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.bar, 0, 8 * 16 * kBarGroups, s), "clearing counters");
+  if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.rqueue, 0, 4, s), "clearing counters");
   if (c.big)
     HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4 * (size_t(c.chunk) + 1), s), "clearing counters");
   HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N) * B, sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -639,6 +646,12 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.cand = cand;
   rp.winner = win;
   rp.tail = c.adv ? 0 : 1;  // with the fused step tail, the tail merges the records
+  rp.nrec = c.nblocks;
+  // one signal with more radius workgroups than fit at once: a work queue
+  // (double precision; see radius_queued)
+  const bool queued = c.fp64 && c.adv && B == 1 && c.rpb == 1 && p->rslots > 0 && p->rslots < c.nblocks;
+  rp.queue = queued ? p->at<unsigned int>(p->L.rqueue) : nullptr;
+  rp.qbase = 0;
 
   BigParams bp{};
   if (c.big) {
@@ -909,6 +922,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
     delete p;
     return hip_fail(e, "device setup");
   }
+  p->rslots = cfg.big ? 0 : radius_slots(cfg.logn, cfg.fp64, cfg.rpb);
   e = hipMalloc(&p->arena, p->L.total);
   if (e != hipSuccess) {
     p->arena = nullptr;
@@ -1001,7 +1015,9 @@ afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threa
     *threads = c.bg.thr_b;
     *lds_bytes = int32_t(c.bg.lds_b);
   } else {
-    *blocks = c.nblocks;
+    const bool queued =
+        c.fp64 && c.adv && c.batch == 1 && c.rpb == 1 && plan->rslots > 0 && plan->rslots < c.nblocks;
+    *blocks = queued ? plan->rslots : c.nblocks;
     *threads = radius_threads_of(c.logn, c.fp64);
     *lds_bytes = radius_lds_bytes(c.logn, c.fp64, c.rpb);
   }

@@ -87,6 +87,9 @@ struct RadiusParams {
   CandList* cand;     // FP32 short-list (written by the last workgroup)
   Winner* winner;     // FP64 winner (written by the last workgroup)
   int tail;           // 1: the last workgroup merges the records; 0: the step tail merges them
+  int nrec;           // record slots per signal (the records' stride)
+  unsigned int* queue;  // non-null (single signal, tail = 0): slots come from this work queue
+  unsigned int qbase;   // the queue's value at this launch (it only grows during a call)
 };
 
 // Radius transforms beyond the LDS (N > 2^kMaxLdsLogN): per radius a
@@ -242,6 +245,7 @@ struct FwdPlan {
 FwdPlan fwd_plan(int logn, bool fp64);
 
 int radius_lds_bytes(int logn, bool fp64, int rpb);
+int radius_slots(int logn, bool fp64, int rpb);
 // Radix of the first Stockham pass of the LDS-resident radius transform.
 int radius_first_radix(int logn, bool fp64);
 // Significant spectrum length of radius r: the smallest L with

@@ -35,28 +35,37 @@ static size_t radius_lds(int rpb) {
   return need > sizeof(MergeScratch) ? need : sizeof(MergeScratch);
 }
 
+// Double precision takes its slots from a work queue when the grid cannot
+// hold them all at once (measured: 68.0 -> 64.2 us at N = 2^14, M = 1000);
+// in single precision the loop it needs costs more than it recovers.
+template <typename T>
+__host__ __device__ constexpr bool radius_queued() {
+  return sizeof(T) == 8;
+}
+
+// Record slot `slot` of signal b: one radius (rpb = 1, the radii in the order
+// of decreasing significant spectrum length, so the longest transforms come
+// first; the radius and its length in one load) or rpb consecutive radii.
 template <typename T, int LOGN, bool LIST>
-__global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_waves_per_eu(
-    radius_min_waves<T, LOGN>()))) void k_radius(RadiusParams prm) {
+__device__ __forceinline__ void radius_slot(const RadiusParams& prm, int slot, int b, unsigned char* smem) {
   constexpr int E = pickE<T, LOGN>();
   constexpr bool SPLIT = pickSplit<T, LOGN>();
   using S = Shape<LOGN, E>;
   constexpr int N = S::N, TPR = S::TPR;
-  static_assert(radius_threads<T, LOGN>() % 64 == 0, "the wave reductions need whole waves");
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_last;
-  const int tid = threadIdx.x;
+  // in the queue loop, the thread index goes through an opaque zero so that
+  // nothing derived from it is hoisted out of the slot and kept live across
+  // the transform (which would exceed the register budget)
+  int zero = 0;
+  if constexpr (radius_queued<T>()) asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+  const int tid = int(threadIdx.x) + zero;
   const int rl = tid / TPR, t = tid - rl * TPR;
-  // one radius per workgroup: the radii in the order of decreasing
-  // significant spectrum length, so the longest transforms start first; the
-  // radius and its length come in one load
   int m, L;
   if (prm.rpb == 1) {
-    const int2 wi = reinterpret_cast<const int2*>(prm.order)[blockIdx.x];
+    const int2 wi = reinterpret_cast<const int2*>(prm.order)[slot];
     m = wi.x;
     L = wi.y;
   } else {
-    m = int(blockIdx.x) * prm.rpb + rl;
+    m = slot * prm.rpb + rl;
     L = prm.lsig[m < prm.M ? m : prm.M - 1];
   }
   const bool active = m < prm.M;
@@ -65,8 +74,7 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
   unsigned char* lds_r = smem + size_t(rl) * region;
   unsigned char* scratch = smem + size_t(prm.rpb) * region;
 
-  // signal b of a batch: its spectrum, workgroup records, counter, short-list / winner
-  const int b = blockIdx.y;
+  // signal b of a batch: its spectrum and records
   const Cx<T>* __restrict__ c = reinterpret_cast<const Cx<T>*>(prm.c) + size_t(N) * b;
   const T* __restrict__ pw = reinterpret_cast<const T*>(prm.pw);
   const T* __restrict__ pv = reinterpret_cast<const T*>(prm.pv);
@@ -121,28 +129,63 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
   const T sc = scale[mm];
   const uint32_t fbase = uint32_t(mm) * uint32_t(N);
   if constexpr (LIST) {
-    const uint32_t r0 = prm.rpb == 1 ? uint32_t(mm) : uint32_t(blockIdx.x) * uint32_t(prm.rpb);
+    const uint32_t r0 = prm.rpb == 1 ? uint32_t(mm) : uint32_t(slot) * uint32_t(prm.rpb);
     const uint32_t ract = uint32_t(prm.M) - r0 < uint32_t(prm.rpb) ? uint32_t(prm.M) - r0 : uint32_t(prm.rpb);
     const FlatOrder ord{r0 * uint32_t(N), ract * uint32_t(N), 0u, ract * uint32_t(N)};
-    BlockList32* lists = reinterpret_cast<BlockList32*>(prm.out) + size_t(gridDim.x) * b;
-    uint64_t* heads = prm.heads + size_t(gridDim.x) * b;
-    uint64_t* seconds = prm.seconds + size_t(gridDim.x) * b;
-    select_list<LOGN>(v, active, sc, fbase, 1u, t, scratch, prm.tau_band, ord, lists + blockIdx.x,
-                      heads + blockIdx.x, seconds + blockIdx.x, prm.flagword + b);
+    BlockList32* lists = reinterpret_cast<BlockList32*>(prm.out) + size_t(prm.nrec) * b;
+    uint64_t* heads = prm.heads + size_t(prm.nrec) * b;
+    uint64_t* seconds = prm.seconds + size_t(prm.nrec) * b;
+    select_list<LOGN>(v, active, sc, fbase, 1u, t, scratch, prm.tau_band, ord, lists + slot, heads + slot,
+                      seconds + slot, prm.flagword + b);
   } else {
     select_best<LOGN, T>(v, active, sc, fbase, 1u, t, reinterpret_cast<Best*>(scratch),
-                         reinterpret_cast<BlockBest64*>(prm.out) + size_t(gridDim.x) * b + blockIdx.x);
+                         reinterpret_cast<BlockBest64*>(prm.out) + size_t(prm.nrec) * b + slot);
   }
+}
 
+// With prm.queue, a single signal's record slots come from a work queue: the
+// grid holds only the workgroups that fit on the device at once, each takes
+// its own slot first and then the next free one (longest transforms first)
+// as it finishes one.  A slot's record does not depend on the workgroup that
+// computes it.  Every workgroup leaves once the queue is exhausted; none
+// waits on another.
+template <typename T, int LOGN, bool LIST>
+__global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_waves_per_eu(
+    radius_min_waves<T, LOGN>()))) void k_radius(RadiusParams prm) {
+  constexpr int N = 1 << LOGN;
+  static_assert(radius_threads<T, LOGN>() % 64 == 0, "the wave reductions need whole waves");
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_last;
+  __shared__ int s_next;
+  const int b = blockIdx.y;
+  if constexpr (radius_queued<T>()) {
+    // the first slot is the workgroup's own index; with a queue, the slots
+    // from gridDim.x on are handed out one per fetch, until a fetch comes
+    // back past the last slot
+    int slot = int(blockIdx.x);
+    while (slot < prm.nrec) {  // uniform
+      radius_slot<T, LOGN, LIST>(prm, slot, b, smem);
+      if (!prm.queue) break;
+      __syncthreads();  // every thread is done with the LDS and with s_next
+      if (threadIdx.x == 0)
+        s_next = int(gridDim.x) +
+                 int(__hip_atomic_fetch_add(prm.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - prm.qbase);
+      __syncthreads();
+      slot = __builtin_amdgcn_readfirstlane(s_next);  // uniform: a scalar register
+    }
+    if (prm.queue) return;  // the step tail merges the records
+  } else {
+    radius_slot<T, LOGN, LIST>(prm, int(blockIdx.x), b, smem);
+  }
   if (!prm.tail) return;  // the step tail merges the records
   if (!last_arrival(prm.counter + b, gridDim.x, &s_last)) return;
   MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
   if constexpr (LIST) {
-    select32_tail(reinterpret_cast<const BlockList32*>(prm.out) + size_t(gridDim.x) * b,
-                  prm.heads + size_t(gridDim.x) * b, prm.seconds + size_t(gridDim.x) * b, int(gridDim.x),
-                  prm.recheck_k, prm.tau_band, prm.flagword + b, prm.cand + b, Sm);
+    select32_tail(reinterpret_cast<const BlockList32*>(prm.out) + size_t(prm.nrec) * b,
+                  prm.heads + size_t(prm.nrec) * b, prm.seconds + size_t(prm.nrec) * b, prm.nrec, prm.recheck_k,
+                  prm.tau_band, prm.flagword + b, prm.cand + b, Sm);
   } else {
-    merge64_tail(reinterpret_cast<const BlockBest64*>(prm.out) + size_t(gridDim.x) * b, int(gridDim.x), N, LOGN,
+    merge64_tail(reinterpret_cast<const BlockBest64*>(prm.out) + size_t(prm.nrec) * b, prm.nrec, N, LOGN,
                  prm.winner + b, Sm);
   }
 }
@@ -193,6 +236,29 @@ int radius_threads_of(int logn, bool fp64) {
     default:
       return 0;
   }
+}
+
+// Workgroups of the radius kernel that fit on the device at once (its
+// occupancy times the CU count): the grid of a queued launch.
+int radius_slots(int logn, bool fp64, int rpb) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (logn) {
+#define X(L)                                                                                                   \
+  case L:                                                                                                      \
+    e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_radius<double, L, false>,                  \
+                                                            radius_threads<double, L>(), radius_lds<double, L>(rpb)) \
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_radius<float, L, true>,                    \
+                                                            radius_threads<float, L>(), radius_lds<float, L>(rpb)); \
+    break;
+    AFD_LDS_LOGN_CASES(X)
+#undef X
+    default:
+      break;
+  }
+  return e == hipSuccess ? per * cus : 0;
 }
 
 hipError_t setup_radius_attributes() {
