@@ -16,6 +16,8 @@ N = 2^20, M = 2000, 100 steps of the analytic part of a chirp + 3 tones +
 white noise at 20 dB, whose radius transforms run as two passes through HBM.
 `--workload batch512` times the uniform batch: 512 signals of N = 4096
 (8..32 kernels, |b| <= 0.95), M = 512, 30 steps, decomposed together.
+`--workload small1k` times the small latency-bound case: N = 1024, M = 100
+radii m/100, 10 steps, FP64 only, 200 solves for p50/p99.
 `--workload serve` runs the served stream: requests with N log-uniform over
 2^10..2^16, M = N/8, 5..100 steps, signals as in the default workload, through
 the continuous-batching server, first all at once (throughput), then with
@@ -95,6 +97,12 @@ def measured_traffic(kernel: str):
 TWO_PASS_BYTES = {"fp32": 16, "fp64": 32}
 
 
+# The radius kernel's duration is measured on every TIMING_EVERY-th launch of
+# the timed decompositions (7 is coprime with the step counts, so the sampled
+# steps rotate): a stamped dispatch costs a few microseconds of stream time.
+TIMING_EVERY = 7
+
+
 def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     from paper_1711_08604_amd import Plan
     batch = int(sig.shape[0]) if sig.dim() == 2 else 1
@@ -105,7 +113,7 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     for _ in range(warmup):
         plan.decompose(sig, afd_steps)
     torch.cuda.synchronize()
-    plan.set_timing("radius", True)
+    plan.set_timing("radius", TIMING_EVERY)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -262,7 +270,8 @@ def run_serve(args, np, torch, W):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single16k", "chirp1m", "batch512", "serve"], default="single16k")
+    ap.add_argument("--workload", choices=["single16k", "chirp1m", "batch512", "small1k", "serve"],
+                    default="single16k")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests in the stream")
     ap.add_argument("--steps", type=int, default=None, help="timed decompositions (30; chirp1m: 3)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed decompositions (3; chirp1m: 1)")
@@ -293,6 +302,12 @@ def main():
         wl_text = ("uniform batch: 512 signals of N=4096 samples (8..32 normalised Szego kernels, |b|<=0.95), "
                    "M=512 radii uniform in [0,0.999], 30 AFD steps each, decomposed together")
         dsteps, dwarm = 5, 1
+    elif args.workload == "small1k":
+        g, radii, afd_steps = W.config1()
+        wl_text = ("small single decomposition: N=1024 samples (5 normalised Szego kernels, |b|<=0.9), "
+                   "M=100 radii m/100, 10 AFD steps, FP64; launch-latency bound")
+        dsteps, dwarm = 200, 10
+        args.only = args.only or "fp64"
     elif args.workload == "chirp1m":
         g, radii, afd_steps = W.config5()
         wl_text = ("large single decomposition: N=2^20 samples, M=2000 radii uniform in [0,0.999], 100 AFD "

@@ -174,11 +174,15 @@ afd_status afd_reconstruct(afd_plan plan, const double* a, const double* coef, i
    AFD_E_HIP; on error g is untouched. */
 afd_status afd_analytic(afd_plan plan, const double* x, double* g);
 
-/* Per-kernel timing with HIP events recorded on the plan's stream around
-   every launch of the kernel class `kernel` ("radius": the fused weighted
-   inverse-DFT / |.|^2 / selection kernel; "fft": the forward DFT; "update":
-   the remainder update).  enable = 1 starts accumulating (and clears the
-   totals), 0 stops.  Errors: AFD_E_INVALID for an unknown class. */
+/* Per-kernel timing with HIP events that the dispatches of the kernel class
+   `kernel` stamp on the plan's stream ("radius": the fused weighted
+   inverse-DFT / |.|^2 / selection kernel, or both passes of a step at
+   N > 2^14; "fft": the forward DFT; "update": the remainder update, which
+   for 2^12 <= N <= 2^14 is the fused step tail).  enable = n >= 1 starts
+   accumulating (and clears the totals) over every n-th launch of the class
+   (1: every launch; a stamped dispatch costs a few microseconds, so a
+   benchmark samples); 0 stops.  Errors: AFD_E_INVALID for an unknown class
+   or enable < 0. */
 afd_status afd_plan_set_timing(afd_plan plan, const char* kernel, int32_t enable);
 
 /* Accumulated milliseconds and launch count of the timed kernel class since

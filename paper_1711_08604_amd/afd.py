@@ -302,8 +302,9 @@ class Plan:
         return g
 
     # -- measurement
-    def set_timing(self, kernel: str = "radius", enable: bool = True):
-        _check(self._lib.afd_plan_set_timing(self._h, kernel.encode(), 1 if enable else 0))
+    def set_timing(self, kernel: str = "radius", enable=True):
+        """Time the kernel class; enable = n >= 1 samples every n-th launch (True: every one), 0/False stops."""
+        _check(self._lib.afd_plan_set_timing(self._h, kernel.encode(), int(enable)))
 
     def kernel_time(self):
         ms = ctypes.c_double()

@@ -224,6 +224,8 @@ struct afd_plan_s {
   size_t aux_bytes = 0;
   // timing
   int time_kind = kTimeNone;
+  int time_every = 1;      // time every time_every-th unit of the class
+  int64_t time_seen = 0;   // units of the class seen since timing was enabled
   double time_ms = 0.0;
   int64_t time_launches = 0;
   std::vector<hipEvent_t> events;
@@ -435,6 +437,7 @@ struct Timer {
   hipError_t pair(int k, hipEvent_t* a, hipEvent_t* b) {
     *a = *b = nullptr;
     if (p->time_kind != k) return hipSuccess;
+    if (p->time_seen++ % p->time_every != 0) return hipSuccess;  // not sampled
     if (next >= p->events.size() / 2) {
       hipEvent_t x, y;
       hipError_t e = hipEventCreate(&x);
@@ -994,7 +997,10 @@ afd_status afd_plan_set_timing(afd_plan plan, const char* kernel, int32_t enable
   else if (std::strcmp(kernel, "fft") == 0) kind = kTimeFft;
   else if (std::strcmp(kernel, "update") == 0) kind = kTimeUpdate;
   else return fail(AFD_E_INVALID, "unknown kernel class");
+  if (enable < 0) return fail(AFD_E_INVALID, "enable must be >= 0");
   plan->time_kind = enable ? kind : kTimeNone;
+  plan->time_every = enable > 0 ? enable : 1;
+  plan->time_seen = 0;
   plan->time_ms = 0.0;
   plan->time_launches = 0;
   return AFD_OK;
