@@ -54,8 +54,9 @@ struct Layout {
 };
 
 // Budget of the intermediate of the two-pass radius transforms: it bounds the
-// radii per chunk (32 single / 16 double precision at N = 2^20).
-constexpr size_t kBigChunkBytes = size_t(256) << 20;
+// radii per chunk (128 single / 64 double precision at N = 2^20).  Each chunk
+// costs two launch boundaries per step, where the device drains and refills.
+constexpr size_t kBigChunkBytes = size_t(1) << 30;
 
 struct Config {
   int logn;

@@ -36,15 +36,20 @@ struct Big {
   static constexpr int THR_B = RB * TPR2;
   static constexpr int G = N1 / RB;
   static constexpr int SW = (LOGN + 1) / 2;
-  static constexpr int LDT = CA + 1;  // row pitch of the LDS transpose (complex elements)
+  static constexpr int LDT = CA + 1;  // row pitch of the LDS transpose (reals)
   static_assert(N2 % CA == 0 && N1 % RB == 0, "tiles must divide the transform");
   static_assert(G <= THR_B, "the radius merge holds one workgroup list per thread");
-  static constexpr size_t region_a = fft_region_bytes<T, L1, false>();
-  static constexpr size_t region_b = fft_region_bytes<T, L2, false>();
-  static constexpr size_t lds_a = (size_t(CA) * region_a > size_t(N1) * LDT * sizeof(Cx<T>))
+  // LDS per workgroup, sized for occupancy: the column transforms and the
+  // transpose move real and imaginary parts in turn through half the space;
+  // the row transforms do so in double precision, and the row selection's
+  // scratch reuses the transform regions once every row is done with them.
+  static constexpr size_t region_a = fft_region_bytes<T, L1, true>();
+  static constexpr size_t region_b = fft_region_bytes<T, L2, sizeof(T) == 8>();
+  static constexpr size_t lds_a = (size_t(CA) * region_a > size_t(N1) * LDT * sizeof(T))
                                       ? size_t(CA) * region_a
-                                      : size_t(N1) * LDT * sizeof(Cx<T>);
-  static constexpr size_t lds_b0 = size_t(RB) * region_b + (sizeof(T) == 4 ? kListScratchBytes : 16 * sizeof(Best));
+                                      : size_t(N1) * LDT * sizeof(T);
+  static constexpr size_t sel_b = sizeof(T) == 4 ? kListScratchBytes : 16 * sizeof(Best);
+  static constexpr size_t lds_b0 = size_t(RB) * region_b > sel_b ? size_t(RB) * region_b : sel_b;
   static constexpr size_t lds_b = lds_b0 > sizeof(MergeScratch) ? lds_b0 : sizeof(MergeScratch);
 };
 
@@ -67,27 +72,37 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_A)) void k_big_cols(BigParams p)
     const T w = pa[l1];
     v[i] = {x.x * w, x.y * w};
   }
-  fft_regs<T, B::L1, B::E1, +1, false>(v, t, smem + size_t(ci) * B::region_a, reinterpret_cast<const Cx<T>*>(p.tw1));
+  fft_regs<T, B::L1, B::E1, +1, true>(v, t, smem + size_t(ci) * B::region_a, reinterpret_cast<const Cx<T>*>(p.tw1));
 
-  // transpose through LDS (the transform's last exchange ended at a barrier)
-  Cx<T>* tr = reinterpret_cast<Cx<T>*>(smem);
+  // transpose through LDS, real parts then imaginary parts (the transform's
+  // last exchange ended at a barrier)
+  T* tr = reinterpret_cast<T*>(smem);
+  const int cj = threadIdx.x % B::CA, jr = threadIdx.x / B::CA;
+  constexpr int JS = B::THR_A / B::CA;
+  constexpr int NJ = B::N1 / JS;
 #pragma unroll
-  for (int q = 0; q < B::E1; ++q) tr[out_bin<B::L1, B::E1>(t, q) * B::LDT + ci] = v[q];
+  for (int q = 0; q < B::E1; ++q) tr[out_bin<B::L1, B::E1>(t, q) * B::LDT + ci] = v[q].x;
+  __syncthreads();
+  T xr[NJ];
+#pragma unroll
+  for (int k = 0; k < NJ; ++k) xr[k] = tr[(jr + JS * k) * B::LDT + cj];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < B::E1; ++q) tr[out_bin<B::L1, B::E1>(t, q) * B::LDT + ci] = v[q].y;
   __syncthreads();
 
-  const int cj = threadIdx.x % B::CA, jr = threadIdx.x / B::CA;
   const int l2o = blockIdx.x * B::CA + cj;
   const T rl = reinterpret_cast<const T*>(p.pb)[size_t(m) * B::N2 + l2o];
   const Cx<T>* __restrict__ wl = reinterpret_cast<const Cx<T>*>(p.wl);
   const Cx<T>* __restrict__ wh = reinterpret_cast<const Cx<T>*>(p.wh);
   Cx<T>* __restrict__ z = reinterpret_cast<Cx<T>*>(p.z) + size_t(ml) * B::N + l2o;
-  constexpr int JS = B::THR_A / B::CA;
-#pragma unroll 4
-  for (int j1 = jr; j1 < B::N1; j1 += JS) {
+#pragma unroll
+  for (int k = 0; k < NJ; ++k) {
+    const int j1 = jr + JS * k;
     const uint32_t e = (uint32_t(j1) * uint32_t(l2o)) & uint32_t(B::N - 1);
     Cx<T> w = cmul(wh[e >> B::SW], wl[e & ((1u << B::SW) - 1u)]);
     w = {w.x * rl, w.y * rl};
-    z[size_t(j1) * B::N2] = cmul(tr[j1 * B::LDT + cj], w);
+    z[size_t(j1) * B::N2] = cmul(Cx<T>{xr[k], tr[j1 * B::LDT + cj]}, w);
   }
 }
 
@@ -105,9 +120,10 @@ void k_big_rows(BigParams p) {
   Cx<T> v[B::E2];
 #pragma unroll
   for (int i = 0; i < B::E2; ++i) v[i] = row[t + B::TPR2 * i];
-  fft_regs<T, B::L2, B::E2, +1, false>(v, t, smem + size_t(ri) * B::region_b, reinterpret_cast<const Cx<T>*>(p.tw2));
+  fft_regs<T, B::L2, B::E2, +1, sizeof(T) == 8>(v, t, smem + size_t(ri) * B::region_b, reinterpret_cast<const Cx<T>*>(p.tw2));
 
-  unsigned char* scratch = smem + size_t(B::RB) * B::region_b;
+  __syncthreads();  // every row is done with its region: the selection reuses them
+  unsigned char* scratch = smem;
   const T sc = reinterpret_cast<const T*>(p.scale)[m];
   // register p of thread t holds j2 = t + TPR2 bitrev(p): flat index m N + j1 + N1 j2
   const uint32_t fbase = uint32_t(m) * uint32_t(B::N) + uint32_t(j1);
