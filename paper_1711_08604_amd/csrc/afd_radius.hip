@@ -43,6 +43,37 @@ __host__ __device__ constexpr bool radius_queued() {
   return sizeof(T) == 8;
 }
 
+// Inputs of Stockham pass P (P >= 2) when the spectrum has at most
+// N / ns(P) terms.  Pass p sends its job's inputs x_p[job + r N/R_p] through
+// the twiddles and an R_p-point DFT to x_{p+1}[(job / ns_p) ns_{p+1} +
+// (job mod ns_p) + q ns_p]; with only r = 0 nonzero that is a copy, so by
+// induction x_P[i] = x[i / ns(P)] and the inputs of job u of thread t are
+// x[(t + TPR u) / ns(P) + r N / (R_P ns(P))], loaded directly: passes 0..P-1
+// and their exchanges are skipped, and the skipped butterflies would only
+// have added zeros.  Every index is below N / ns(P) <= TPR, so the weight is
+// one entry r_m^l of the [M][TPR] table.
+template <typename T, int LOGN, int E, int P>
+__device__ __forceinline__ void deep_inputs(Cx<T> (&v)[E], int t, int L, const Cx<T>* __restrict__ c,
+                                            const T* __restrict__ pwm) {
+  using S = Shape<LOGN, E>;
+  constexpr int R = S::radix(P), NS = S::ns(P), J = E / R, D = S::N / (R * NS);
+  static_assert(P >= 2 && S::N / NS <= S::TPR, "the weights come from the r^t table");
+#pragma unroll
+  for (int u = 0; u < J; ++u) {
+    const int a = (t + u * S::TPR) / NS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int l = a + D * r;
+      v[u + r * J] = {T(0), T(0)};
+      if (l < L) {
+        const Cx<T> x = c[l];
+        const T w = pwm[l];
+        v[u + r * J] = {x.x * w, x.y * w};
+      }
+    }
+  }
+}
+
 // Record slot `slot` of signal b: one radius (rpb = 1, the radii in the order
 // of decreasing significant spectrum length, so the longest transforms come
 // first; the radius and its length in one load) or rpb consecutive radii.
@@ -90,9 +121,30 @@ __device__ __forceinline__ void radius_slot(const RadiusParams& prm, int slot, i
   // replicates x[job]: thread t's inputs of the second pass are then
   // x[t/R0 + (TPR/R0) i], loaded directly, and the first pass and its
   // exchange are skipped.  Uniform over the workgroup (one radius).
+  // Shorter spectra skip more passes (see deep_inputs): at most N / ns(2)
+  // terms start at pass 2, at most N / ns(3) at pass 3.
   bool pruned = false;
+  int deep = 0;
   if constexpr (S::NP >= 2 && R0 <= TPR) pruned = prm.rpb == 1 && L <= N / R0;
-  if (pruned) {
+  if constexpr (S::NP >= 3) deep = pruned && L <= N / S::ns(2) ? 2 : 0;
+  if constexpr (S::NP >= 4) deep = deep && L <= N / S::ns(3) ? 3 : deep;
+  if (deep) {
+    if constexpr (S::NP >= 3) {
+      const T* __restrict__ pwm = pw + size_t(mm) * TPR;
+      if constexpr (S::NP >= 4) {
+        if (deep == 3) {
+          deep_inputs<T, LOGN, E, 3>(v, t, L, c, pwm);
+          fft_regs<T, LOGN, E, +1, SPLIT, 3, 3>(v, t, lds_r, tw);
+        } else {
+          deep_inputs<T, LOGN, E, 2>(v, t, L, c, pwm);
+          fft_regs<T, LOGN, E, +1, SPLIT, 2, 2>(v, t, lds_r, tw);
+        }
+      } else {
+        deep_inputs<T, LOGN, E, 2>(v, t, L, c, pwm);
+        fft_regs<T, LOGN, E, +1, SPLIT, 2, 2>(v, t, lds_r, tw);
+      }
+    }
+  } else if (pruned) {
     if constexpr (S::NP >= 2 && R0 <= TPR) {
       const int a = t / R0;  // r^l = r^a r^((TPR/R0) i)
       const T ra = pw[size_t(mm) * TPR + a];
