@@ -161,7 +161,7 @@ Layout layout_of(const Config& c) {
   L.pv = take(real * size_t(c.M) * (c.big ? (size_t(1) << c.bg.l2) : size_t(c.geom.E)));
   L.scale = take(real * size_t(c.M));
   L.pq = take(c.big ? 0 : real * size_t(c.M) * c.geom.E);
-  L.lsig = take(c.big ? 0 : 4 * size_t(c.M));
+  L.lsig = take(4 * size_t(c.M));
   L.order = take(c.big ? 0 : 8 * size_t(c.M));
   // per-signal buffers: `batch` copies back to back
   const size_t B = size_t(c.batch);
@@ -275,16 +275,15 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   // spectrum length of each radius (weights below 2^-40 single / 2^-60 double
   // precision of the largest term, summed, are dropped)
   std::vector<double> pq;
-  std::vector<int32_t> lsig;
+  std::vector<int32_t> lsig(M);
+  for (int m = 0; m < M; ++m) lsig[m] = significant_length(radii[m], c.fp64 ? 60 : 40, N);
   if (!c.big) {
     const int r0 = radius_first_radix(c.logn, c.fp64);
     const long double step = (long double)(tpr / (r0 > 0 ? r0 : 1));
     pq.resize(size_t(M) * E);
-    lsig.resize(M);
     for (int m = 0; m < M; ++m) {
       const long double r = radii[m];
       for (int v = 0; v < E; ++v) pq[size_t(m) * E + v] = v == 0 ? 1.0 : (double)powl(r, step * (long double)v);
-      lsig[m] = significant_length(radii[m], c.fp64 ? 60 : 40, N);
     }
   }
   // two-pass path: e^{2 pi i e/N} = wh[e >> sw] * wl[e mod 2^sw]
@@ -336,7 +335,7 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     if (e == hipSuccess && c.big) e = up(p->L.wh, wh32.data(), wh32.size() * 4);
     if (e == hipSuccess && !c.big) e = up(p->L.pq, pq32.data(), pq32.size() * 4);
   }
-  if (e == hipSuccess && !c.big) e = up(p->L.lsig, lsig.data(), lsig.size() * 4);
+  if (e == hipSuccess) e = up(p->L.lsig, lsig.data(), lsig.size() * 4);
   if (e == hipSuccess && c.adv && !c.fp64) {
     std::vector<float> om(2 * size_t(N));
     for (size_t i = 0; i < om.size(); ++i) om[i] = float(omega[i]);
@@ -663,6 +662,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     bp.pa = p->at<void>(p->L.pw);
     bp.pb = p->at<void>(p->L.pv);
     bp.scale = p->at<void>(p->L.scale);
+    bp.lsig = p->at<int>(p->L.lsig);
     bp.wl = p->at<void>(p->L.wl);
     bp.wh = p->at<void>(p->L.wh);
     bp.tw1 = p->at<void>(p->L.twf1);

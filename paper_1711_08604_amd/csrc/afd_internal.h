@@ -100,6 +100,7 @@ struct BigParams {
   const void* pa;     // [M][N1]  r_m^(N2 l1)
   const void* pb;     // [M][N2]  r_m^l2
   const void* scale;  // [M]      sqrt(1-r^2) / (N (1 - r^N))
+  const int* lsig;    // [M]      significant spectrum length (later terms dropped)
   const void* wl;     // e^{2 pi i e/N}, e < 2^sw (T complex)
   const void* wh;     // e^{2 pi i h 2^sw/N}, h < N/2^sw (T complex)
   const void* tw1;    // Stockham twiddles of the length-N1 transforms

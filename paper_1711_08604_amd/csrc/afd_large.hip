@@ -18,6 +18,15 @@
 // workgroup records into one per-radius record; the last radius of the step
 // merges those into the winner (FP64) or the short-list (FP32).  Radii are
 // processed in chunks so the intermediate stays within a fixed budget.
+//
+// Short spectra need no intermediate.  A radius whose significant length L
+// (the terms r_m^l c_l beyond it are dropped, as in the LDS-resident kernel)
+// is at most N2 has only l1 = 0 in every column, whose transform is then the
+// constant c_{l2}, so Z_m[j1][l2] = r_m^l2 e^{2 pi i j1 l2/N} c_{l2} for
+// l2 < L and 0 beyond.  The column pass skips such a radius and the row pass
+// forms its rows from the spectrum itself, starting at a later Stockham pass
+// when L is short enough (see deep_row_inputs); at N = 2^20 that is every
+// radius below about 0.97.
 #include "afd_select.h"
 
 namespace afd {
@@ -60,6 +69,7 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_A)) void k_big_cols(BigParams p)
   const int ci = threadIdx.x / B::TPR1, t = threadIdx.x - ci * B::TPR1;
   const int l2 = blockIdx.x * B::CA + ci;
   const int ml = blockIdx.y, m = p.m0 + ml;
+  if (p.lsig[m] <= B::N2) return;  // formed by the row pass (uniform)
 
   // weighted column x[l1] = r^(N2 l1) c_{N2 l1 + l2} (the factor r^l2 is applied after the transform)
   const Cx<T>* __restrict__ col = reinterpret_cast<const Cx<T>*>(p.c) + size_t(l2) * B::N1;
@@ -106,6 +116,40 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_A)) void k_big_cols(BigParams p)
   }
 }
 
+// Inputs of Stockham pass P of the row transform for the row j1 of a short
+// radius: job u of thread t takes Z[j1][(t + TPR2 u) / ns(P) + r N2 / (R_P
+// ns(P))] (passes 0..P-1 of a spectrum with at most N2 / ns(P) terms only
+// copy their inputs; P = 0 is the plain load order), each formed as the
+// column pass would: c_{l2} e^{2 pi i j1 l2/N} r^l2, the twiddle from the
+// high/low tables.
+template <typename T, int LOGN, int P, int E>
+__device__ __forceinline__ void deep_row_inputs(Cx<T> (&v)[E], int t, int j1, int L, const BigParams& p, int m) {
+  using B = Big<T, LOGN>;
+  static_assert(E == B::E2, "row transform values per thread");
+  using S = Shape<B::L2, B::E2>;
+  constexpr int R = S::radix(P), NS = S::ns(P), J = B::E2 / R, D = B::N2 / (R * NS);
+  const Cx<T>* __restrict__ c = reinterpret_cast<const Cx<T>*>(p.c);
+  const T* __restrict__ pb = reinterpret_cast<const T*>(p.pb) + size_t(m) * B::N2;
+  const Cx<T>* __restrict__ wl = reinterpret_cast<const Cx<T>*>(p.wl);
+  const Cx<T>* __restrict__ wh = reinterpret_cast<const Cx<T>*>(p.wh);
+#pragma unroll
+  for (int u = 0; u < J; ++u) {
+    const int a = (t + u * S::TPR) / NS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int l2 = a + D * r;
+      v[u + r * J] = {T(0), T(0)};
+      if (l2 < L) {
+        const uint32_t e = (uint32_t(j1) * uint32_t(l2)) & uint32_t(B::N - 1);
+        Cx<T> w = cmul(wh[e >> B::SW], wl[e & ((1u << B::SW) - 1u)]);
+        const T rl = pb[l2];
+        w = {w.x * rl, w.y * rl};
+        v[u + r * J] = cmul(c[size_t(l2) * B::N1], w);
+      }
+    }
+  }
+}
+
 template <typename T, int LOGN, bool LIST>
 __global__ __launch_bounds__((Big<T, LOGN>::THR_B)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 void k_big_rows(BigParams p) {
@@ -116,11 +160,31 @@ void k_big_rows(BigParams p) {
   const int j1 = blockIdx.x * B::RB + ri;
   const int ml = blockIdx.y, m = p.m0 + ml;
 
-  const Cx<T>* __restrict__ row = reinterpret_cast<const Cx<T>*>(p.z) + size_t(ml) * B::N + size_t(j1) * B::N2;
+  using S2 = Shape<B::L2, B::E2>;
+  constexpr bool SPLIT = sizeof(T) == 8;
+  unsigned char* region = smem + size_t(ri) * B::region_b;
+  const Cx<T>* tw2 = reinterpret_cast<const Cx<T>*>(p.tw2);
+  const int L = p.lsig[m];
   Cx<T> v[B::E2];
+  if (L > B::N2) {
+    const Cx<T>* __restrict__ row = reinterpret_cast<const Cx<T>*>(p.z) + size_t(ml) * B::N + size_t(j1) * B::N2;
 #pragma unroll
-  for (int i = 0; i < B::E2; ++i) v[i] = row[t + B::TPR2 * i];
-  fft_regs<T, B::L2, B::E2, +1, sizeof(T) == 8>(v, t, smem + size_t(ri) * B::region_b, reinterpret_cast<const Cx<T>*>(p.tw2));
+    for (int i = 0; i < B::E2; ++i) v[i] = row[t + B::TPR2 * i];
+    fft_regs<T, B::L2, B::E2, +1, SPLIT>(v, t, region, tw2);
+  } else if (S2::NP >= 3 && L <= B::N2 / S2::ns(2)) {  // uniform: one radius per workgroup
+    if constexpr (S2::NP >= 3) {
+      deep_row_inputs<T, LOGN, 2>(v, t, j1, L, p, m);
+      fft_regs<T, B::L2, B::E2, +1, SPLIT, 2, 2>(v, t, region, tw2);
+    }
+  } else if (S2::NP >= 2 && L <= B::N2 / S2::radix(0)) {
+    if constexpr (S2::NP >= 2) {
+      deep_row_inputs<T, LOGN, 1>(v, t, j1, L, p, m);
+      fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1>(v, t, region, tw2);
+    }
+  } else {
+    deep_row_inputs<T, LOGN, 0>(v, t, j1, L, p, m);
+    fft_regs<T, B::L2, B::E2, +1, SPLIT>(v, t, region, tw2);
+  }
 
   __syncthreads();  // every row is done with its region: the selection reuses them
   unsigned char* scratch = smem;
