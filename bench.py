@@ -97,6 +97,24 @@ def measured_traffic(kernel: str):
 TWO_PASS_BYTES = {"fp32": 16, "fp64": 32}
 
 
+def two_pass_radii(radii, n: int, prec: str) -> int:
+    """Radii whose significant spectrum length exceeds N2 = 2^(K - K//2): only
+    those go through the HBM intermediate (terms r^l below 2^-40 single /
+    2^-60 double precision of the largest, summed, are dropped)."""
+    bits = 60 if prec == "fp64" else 40
+    k = int(math.log2(n))
+    n2 = 1 << (k - k // 2)
+    count = 0
+    for r in radii:
+        r = float(r)
+        if r <= 0.0:
+            continue
+        need = (bits * math.log(2.0) - math.log1p(-r)) / -math.log(r)
+        if math.ceil(need) > n2:
+            count += 1
+    return count
+
+
 # The radius kernel's duration is measured on every TIMING_EVERY-th launch of
 # the timed decompositions (7 is coprime with the step counts, so the sampled
 # steps rotate): a stamped dispatch costs a few microseconds of stream time.
@@ -141,14 +159,18 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
                 "avg_launch_us": avg_kernel_s * 1e6, "launches": k_launches,
                 "flop_per_launch": flop_launch, "grid": [blocks, threads, lds]}
     else:
-        # one timed unit = the column and row passes over all chunks of one AFD step
-        gbs = float(m) * n * TWO_PASS_BYTES[prec] / avg_kernel_s / 1e9
-        roof = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-                "traffic": None,
-                "kernel": f"k_big_cols<{tname},{int(math.log2(n))}> + k_big_rows (all radius chunks of a step)",
+        # one timed unit = the column and row passes over all chunks of one AFD
+        # step; only the radii with long spectra move through the intermediate,
+        # the rest are formed in the row pass from the spectrum (ALU-bound)
+        long_r = two_pass_radii(radii, n, prec)
+        inter = float(long_r) * n * TWO_PASS_BYTES[prec]
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": f"k_big_rows<{tname},{int(math.log2(n))}> + k_big_cols (all radius chunks of a step)",
                 "avg_launch_us": avg_kernel_s * 1e6, "launches": k_launches,
-                "bytes_per_launch": float(m) * n * TWO_PASS_BYTES[prec],
-                "alu_achieved_tflops": achieved, "alu_frac": achieved / peak,
+                "flop_per_launch": flop_launch, "two_pass_radii": long_r,
+                "intermediate_bytes_per_launch": inter,
+                "intermediate_gbs": inter / avg_kernel_s / 1e9,
                 "row_grid": [blocks, threads, lds]}
     out = {
         "value": evals / wall,

@@ -49,7 +49,7 @@ struct Layout {
   // FP32 head and second keys of the workgroup (or per-radius) records
   size_t heads, seconds;
   // radius transforms beyond the LDS
-  size_t wl, wh, z, rrec, bcounters;
+  size_t wl, wh, z, c0, rrec, bcounters;
   size_t total;
 };
 
@@ -175,6 +175,7 @@ Layout layout_of(const Config& c) {
   L.wl = take(c.big ? 2 * real * (size_t(1) << c.bg.sw) : 0);
   L.wh = take(c.big ? 2 * real * (size_t(1) << (c.logn - c.bg.sw)) : 0);
   L.z = take(c.big ? 2 * real * size_t(c.chunk) * size_t(c.N) : 0);
+  L.c0 = take(c.big ? 2 * real * (size_t(1) << c.bg.l2) * B : 0);
   L.rrec = take(c.big ? (c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.M) : 0);
   L.bcounters = take(c.big ? 4 * (size_t(c.chunk) + 1) : 0);
   L.cand = take(sizeof(CandList) * B);
@@ -659,6 +660,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   BigParams bp{};
   if (c.big) {
     bp.c = cspec;
+    bp.c0 = p->at<void>(p->L.c0);
     bp.pa = p->at<void>(p->L.pw);
     bp.pb = p->at<void>(p->L.pv);
     bp.scale = p->at<void>(p->L.scale);
@@ -712,7 +714,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       HIPCHK(tm.pair(kTimeFft, &e0, &e1), "event");
       HIPCHK(launch_fwd(c.logn, c.fp64, c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32),
                         p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega, p->at<void>(p->L.xt), cspec, B, s,
-                        e0, e1),
+                        e0, e1, c.big ? p->at<void>(p->L.c0) : nullptr),
              "forward DFT");
       HIPCHK(tm.pair(kTimeRadius, &e0, &e1), "event");
       if (c.big) {

@@ -92,7 +92,8 @@ __global__ __launch_bounds__((cols_threads<T, LOGN>())) void k_fwd_cols(const Cx
 template <typename T, int LOGN, bool COLS>
 __global__ __launch_bounds__((rows_threads<T, LOGN>())) void k_fwd_rows(const Cx<T>* __restrict__ xt,
                                                                          const Cx<T>* __restrict__ tw1,
-                                                                         Cx<T>* __restrict__ c) {
+                                                                         Cx<T>* __restrict__ c,
+                                                                         Cx<T>* __restrict__ c0) {
   using P = Split2<LOGN>;
   constexpr int E1 = pickE<T, P::L1>();
   using S1 = Shape<P::L1, E1>;
@@ -112,9 +113,11 @@ __global__ __launch_bounds__((rows_threads<T, LOGN>())) void k_fwd_rows(const Cx
 #pragma unroll
   for (int p = 0; p < E1; ++p) {
     const int k1 = out_bin<P::L1, E1>(t, p);
-    if constexpr (COLS)
+    if constexpr (COLS) {
       c[size_t(k2) * P::N1 + k1] = v[p];
-    else
+      // with c0, the bins below N2 also in natural order (c_{k2}: k1 = 0)
+      if (c0 != nullptr && k1 == 0) c0[size_t(P::N2) * blockIdx.y + k2] = v[p];
+    } else
       c[k2 + P::N2 * k1] = v[p];
   }
 }
@@ -234,7 +237,7 @@ hipError_t setup_fwd_attributes() {
 
 template <typename T, int LOGN>
 static hipError_t launch_fwd_t(const void* g, const void* tw1, const void* tw2, const double* omega, void* xt,
-                               void* c, int batch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                               void* c, void* c0, int batch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if constexpr (LOGN < kFwdTwoPassMin) {
     constexpr int thr = fwd_threads<T, LOGN>();
     constexpr size_t lds = fft_region_bytes<T, LOGN, pickSplit<T, LOGN>()>();
@@ -252,18 +255,18 @@ static hipError_t launch_fwd_t(const void* g, const void* tw1, const void* tw2, 
     launch_ev(k_fwd_rows<T, LOGN, fwd_cols_out<LOGN>()>, dim3(P::N2 / kColsPerBlock, batch), dim3(thr_r),
               uint32_t(lds_r), s,
               nullptr, e1, reinterpret_cast<const Cx<T>*>(xt), reinterpret_cast<const Cx<T>*>(tw1),
-              reinterpret_cast<Cx<T>*>(c));
+              reinterpret_cast<Cx<T>*>(c), reinterpret_cast<Cx<T>*>(c0));
   }
   return hipGetLastError();
 }
 
 hipError_t launch_fwd(int logn, bool fp64, const void* g, const void* tw1, const void* tw2, const double* omega,
-                      void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                      void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0, hipEvent_t e1, void* c0) {
   switch (logn) {
-#define X(L)                                                                              \
-  case L:                                                                                 \
-    return fp64 ? launch_fwd_t<double, L>(g, tw1, tw2, omega, xt, c, batch, s, e0, e1)    \
-                : launch_fwd_t<float, L>(g, tw1, tw2, omega, xt, c, batch, s, e0, e1);
+#define X(L)                                                                                  \
+  case L:                                                                                     \
+    return fp64 ? launch_fwd_t<double, L>(g, tw1, tw2, omega, xt, c, c0, batch, s, e0, e1)    \
+                : launch_fwd_t<float, L>(g, tw1, tw2, omega, xt, c, c0, batch, s, e0, e1);
     AFD_FWD_ALL_LOGN_CASES(X)
 #undef X
     default:

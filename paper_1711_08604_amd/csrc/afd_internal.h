@@ -97,6 +97,7 @@ struct RadiusParams {
 // over chunks of radii (see afd_large.hip).
 struct BigParams {
   const void* c;      // spectrum in column order: c_{N2 l1 + l2} at [l2][l1] (T complex)
+  const void* c0;     // [N2]     c_l for l < N2 in natural order (T complex)
   const void* pa;     // [M][N1]  r_m^(N2 l1)
   const void* pb;     // [M][N2]  r_m^l2
   const void* scale;  // [M]      sqrt(1-r^2) / (N (1 - r^N))
@@ -280,9 +281,11 @@ hipError_t setup_radius_attributes();
 hipError_t setup_fwd_attributes();
 
 // Batched launches cover `batch` signals (grid dimension y, or z for the
-// re-check); each signal's buffers follow the previous signal's.
+// re-check); each signal's buffers follow the previous signal's.  For
+// N > 2^14, c0 (nullable) also receives the bins l < N2 in natural order.
 hipError_t launch_fwd(int logn, bool fp64, const void* g, const void* tw1, const void* tw2, const double* omega,
-                      void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                      void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                      void* c0 = nullptr);
 hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks, int batch, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* nonfinite, unsigned int* counter,

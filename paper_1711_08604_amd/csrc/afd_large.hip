@@ -116,35 +116,46 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_A)) void k_big_cols(BigParams p)
   }
 }
 
+// e^{2 pi i e/N} = wh[e >> SW] wl[e mod 2^SW] (e mod N)
+template <typename T, int LOGN>
+__device__ __forceinline__ Cx<T> big_twiddle(const BigParams& p, uint32_t e) {
+  using B = Big<T, LOGN>;
+  e &= uint32_t(B::N - 1);
+  return cmul(reinterpret_cast<const Cx<T>*>(p.wh)[e >> B::SW],
+              reinterpret_cast<const Cx<T>*>(p.wl)[e & ((1u << B::SW) - 1u)]);
+}
+
 // Inputs of Stockham pass P of the row transform for the row j1 of a short
-// radius: job u of thread t takes Z[j1][(t + TPR2 u) / ns(P) + r N2 / (R_P
-// ns(P))] (passes 0..P-1 of a spectrum with at most N2 / ns(P) terms only
-// copy their inputs; P = 0 is the plain load order), each formed as the
-// column pass would: c_{l2} e^{2 pi i j1 l2/N} r^l2, the twiddle from the
-// high/low tables.
+// radius: job u of thread t takes Z[j1][l2] with l2 = (t + TPR2 u) / ns(P) +
+// r N2 / (R_P ns(P)) (passes 0..P-1 of a spectrum with at most N2 / ns(P)
+// terms only copy their inputs; P = 0 is the plain load order), Z[j1][l2] =
+// c_{l2} e^{2 pi i j1 l2/N} r^l2.  With ns(P) dividing TPR2, l2 = t / ns(P) +
+// o(u, r), so the twiddle is the thread's e^{2 pi i j1 (t / ns(P))/N} times a
+// wave-uniform e^{2 pi i j1 o/N}, and the spectrum comes from its
+// natural-order copy: every load is contiguous or uniform across the wave.
 template <typename T, int LOGN, int P, int E>
 __device__ __forceinline__ void deep_row_inputs(Cx<T> (&v)[E], int t, int j1, int L, const BigParams& p, int m) {
   using B = Big<T, LOGN>;
-  static_assert(E == B::E2, "row transform values per thread");
   using S = Shape<B::L2, B::E2>;
+  static_assert(E == B::E2, "row transform values per thread");
   constexpr int R = S::radix(P), NS = S::ns(P), J = B::E2 / R, D = B::N2 / (R * NS);
-  const Cx<T>* __restrict__ c = reinterpret_cast<const Cx<T>*>(p.c);
+  static_assert(S::TPR % NS == 0, "the lane part of l2 separates");
+  const Cx<T>* __restrict__ c0 = reinterpret_cast<const Cx<T>*>(p.c0);
   const T* __restrict__ pb = reinterpret_cast<const T*>(p.pb) + size_t(m) * B::N2;
-  const Cx<T>* __restrict__ wl = reinterpret_cast<const Cx<T>*>(p.wl);
-  const Cx<T>* __restrict__ wh = reinterpret_cast<const Cx<T>*>(p.wh);
+  const int base = t / NS;
+  const Cx<T> wa = big_twiddle<T, LOGN>(p, uint32_t(j1) * uint32_t(base));
 #pragma unroll
   for (int u = 0; u < J; ++u) {
-    const int a = (t + u * S::TPR) / NS;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int l2 = a + D * r;
+      const int o = (S::TPR / NS) * u + D * r;
+      const int l2 = base + o;
       v[u + r * J] = {T(0), T(0)};
       if (l2 < L) {
-        const uint32_t e = (uint32_t(j1) * uint32_t(l2)) & uint32_t(B::N - 1);
-        Cx<T> w = cmul(wh[e >> B::SW], wl[e & ((1u << B::SW) - 1u)]);
+        Cx<T> w = cmul(wa, big_twiddle<T, LOGN>(p, uint32_t(j1) * uint32_t(o)));
         const T rl = pb[l2];
         w = {w.x * rl, w.y * rl};
-        v[u + r * J] = cmul(c[size_t(l2) * B::N1], w);
+        v[u + r * J] = cmul(c0[l2], w);
       }
     }
   }
