@@ -386,30 +386,48 @@ __device__ __forceinline__ void lds_read_part(Cx<T> (&v)[E], int t, const T* lds
 // FIRST > 0 starts at pass FIRST with the registers already holding that
 // pass's inputs (no exchange before it); see the pruned start of the radius
 // transform.  `tw`: the pass table in memory (const Cx<T>*) or a TwRegs.
-template <typename T, int LOGN, int E, int SIGN, bool SPLIT, int P = 0, int FIRST = 0, class TW>
+//
+// WAVE: the threads of each transform lie in one wave (TPR divides 64), so
+// an exchange needs no workgroup barrier: a wave's LDS accesses complete in
+// order, and a wave-scope fence only keeps the compiler from moving them
+// across one another.  The waves of a workgroup then run their transforms
+// independently.
+template <bool WAVE>
+__device__ __forceinline__ void lds_exchange_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <typename T, int LOGN, int E, int SIGN, bool SPLIT, int P = 0, int FIRST = 0, bool WAVE = false, class TW>
 __device__ __forceinline__ void fft_regs(Cx<T> (&v)[E], int t, void* lds, const TW& tw) {
   using S = Shape<LOGN, E>;
+  static_assert(!WAVE || (64 % S::TPR == 0), "a wave-synchronised transform lies in one wave");
   if constexpr (P > FIRST) {
     if constexpr (SPLIT) {
       T* l = reinterpret_cast<T*>(lds);
       lds_write_part<T, LOGN, E, P - 1, 0>(v, t, l);
-      __syncthreads();
+      lds_exchange_sync<WAVE>();
       lds_read_part<T, LOGN, E, 0>(v, t, l);
-      __syncthreads();
+      lds_exchange_sync<WAVE>();
       lds_write_part<T, LOGN, E, P - 1, 1>(v, t, l);
-      __syncthreads();
+      lds_exchange_sync<WAVE>();
       lds_read_part<T, LOGN, E, 1>(v, t, l);
-      __syncthreads();
+      lds_exchange_sync<WAVE>();
     } else {
       Cx<T>* l = reinterpret_cast<Cx<T>*>(lds);
       lds_write<T, LOGN, E, P - 1>(v, t, l);
-      __syncthreads();
+      lds_exchange_sync<WAVE>();
       lds_read<T, LOGN, E>(v, t, l);
-      __syncthreads();
+      lds_exchange_sync<WAVE>();
     }
   }
   pass_compute<T, LOGN, E, P, SIGN>(v, t, tw);
-  if constexpr (P + 1 < S::NP) fft_regs<T, LOGN, E, SIGN, SPLIT, P + 1, FIRST>(v, t, lds, tw);
+  if constexpr (P + 1 < S::NP) fft_regs<T, LOGN, E, SIGN, SPLIT, P + 1, FIRST, WAVE>(v, t, lds, tw);
 }
 
 // Output bin held by register p after fft_regs.

@@ -82,10 +82,11 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_A)) void k_big_cols(BigParams p)
     const T w = pa[l1];
     v[i] = {x.x * w, x.y * w};
   }
-  fft_regs<T, B::L1, B::E1, +1, true>(v, t, smem + size_t(ci) * B::region_a, reinterpret_cast<const Cx<T>*>(p.tw1));
+  fft_regs<T, B::L1, B::E1, +1, true, 0, 0, true>(v, t, smem + size_t(ci) * B::region_a,
+                                                  reinterpret_cast<const Cx<T>*>(p.tw1));
+  __syncthreads();  // the transpose below overlays every column's region
 
-  // transpose through LDS, real parts then imaginary parts (the transform's
-  // last exchange ended at a barrier)
+  // transpose through LDS, real parts then imaginary parts
   T* tr = reinterpret_cast<T*>(smem);
   const int cj = threadIdx.x % B::CA, jr = threadIdx.x / B::CA;
   constexpr int JS = B::THR_A / B::CA;
@@ -181,20 +182,20 @@ void k_big_rows(BigParams p) {
     const Cx<T>* __restrict__ row = reinterpret_cast<const Cx<T>*>(p.z) + size_t(ml) * B::N + size_t(j1) * B::N2;
 #pragma unroll
     for (int i = 0; i < B::E2; ++i) v[i] = row[t + B::TPR2 * i];
-    fft_regs<T, B::L2, B::E2, +1, SPLIT>(v, t, region, tw2);
+    fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
   } else if (S2::NP >= 3 && L <= B::N2 / S2::ns(2)) {  // uniform: one radius per workgroup
     if constexpr (S2::NP >= 3) {
       deep_row_inputs<T, LOGN, 2>(v, t, j1, L, p, m);
-      fft_regs<T, B::L2, B::E2, +1, SPLIT, 2, 2>(v, t, region, tw2);
+      fft_regs<T, B::L2, B::E2, +1, SPLIT, 2, 2, true>(v, t, region, tw2);
     }
   } else if (S2::NP >= 2 && L <= B::N2 / S2::radix(0)) {
     if constexpr (S2::NP >= 2) {
       deep_row_inputs<T, LOGN, 1>(v, t, j1, L, p, m);
-      fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1>(v, t, region, tw2);
+      fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1, true>(v, t, region, tw2);
     }
   } else {
     deep_row_inputs<T, LOGN, 0>(v, t, j1, L, p, m);
-    fft_regs<T, B::L2, B::E2, +1, SPLIT>(v, t, region, tw2);
+    fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
   }
 
   __syncthreads();  // every row is done with its region: the selection reuses them

@@ -73,6 +73,24 @@ def test_two_pass_zero_radius_ties():
             compare(res, ref, TOL[prec], signal=g, radii=radii)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_short_spectra_direct_rows(prec):
+    """Every radius here has a significant spectrum shorter than N2, so no
+    radius goes through the intermediate: the row pass forms its rows from the
+    spectrum, starting at later Stockham passes for the smaller radii."""
+    n = 1 << 16
+    print(f"case short spectra N={n} {prec}", flush=True)
+    g = _signal(n, 2, rmax=0.75)
+    radii = W.uniform_radii(9, 0.8)  # longest significant length 194 (FP64) <= N2 = 256
+    ref = O.decompose(g, radii, 4)
+    with Plan(n, radii, precision=prec) as plan:
+        res = plan.decompose(_dev(g), 4)
+        torch.cuda.synchronize()
+        compare(res, ref, TOL[prec], signal=g, radii=radii)
+        rep = plan.replay(_dev(g), 4, ref.index.astype(np.int32))
+        compare(rep, ref, TOL[prec], replay=True)
+
+
 def _oracle_row(G, r):
     return O.grid_fft(G, np.array([r]))[0]
 
