@@ -177,6 +177,7 @@ void k_big_rows(BigParams p) {
   unsigned char* region = smem + size_t(ri) * B::region_b;
   const Cx<T>* tw2 = reinterpret_cast<const Cx<T>*>(p.tw2);
   const int L = p.lsig[m];
+  const T sc = reinterpret_cast<const T*>(p.scale)[m];  // loaded before the transform's barriers
   Cx<T> v[B::E2];
   if (L > B::N2) {
     const Cx<T>* __restrict__ row = reinterpret_cast<const Cx<T>*>(p.z) + size_t(ml) * B::N + size_t(j1) * B::N2;
@@ -200,7 +201,6 @@ void k_big_rows(BigParams p) {
 
   __syncthreads();  // every row is done with its region: the selection reuses them
   unsigned char* scratch = smem;
-  const T sc = reinterpret_cast<const T*>(p.scale)[m];
   // register p of thread t holds j2 = t + TPR2 bitrev(p): flat index m N + j1 + N1 j2
   const uint32_t fbase = uint32_t(m) * uint32_t(B::N) + uint32_t(j1);
   const int rec = ml * B::G + int(blockIdx.x);

@@ -91,10 +91,13 @@ __device__ __forceinline__ void radius_slot(const RadiusParams& prm, int slot, i
   const int tid = int(threadIdx.x) + zero;
   const int rl = tid / TPR, t = tid - rl * TPR;
   int m, L;
-  if (prm.rpb == 1) {
+  // (a transform of at least 64 threads always has a workgroup of its own)
+  if (S::TPR >= 64 || prm.rpb == 1) {
     const int2 wi = reinterpret_cast<const int2*>(prm.order)[slot];
-    m = wi.x;
-    L = wi.y;
+    // one radius per workgroup: uniform, so its per-radius values sit in
+    // scalar registers
+    m = __builtin_amdgcn_readfirstlane(wi.x);
+    L = __builtin_amdgcn_readfirstlane(wi.y);
   } else {
     m = slot * prm.rpb + rl;
     L = prm.lsig[m < prm.M ? m : prm.M - 1];
@@ -109,8 +112,10 @@ __device__ __forceinline__ void radius_slot(const RadiusParams& prm, int slot, i
   const Cx<T>* __restrict__ c = reinterpret_cast<const Cx<T>*>(prm.c) + size_t(N) * b;
   const T* __restrict__ pw = reinterpret_cast<const T*>(prm.pw);
   const T* __restrict__ pv = reinterpret_cast<const T*>(prm.pv);
-  const T* __restrict__ scale = reinterpret_cast<const T*>(prm.scale);
   const Cx<T>* __restrict__ tw = reinterpret_cast<const Cx<T>*>(prm.tw);
+  // the selection's scale is loaded now: after the transform's barriers its
+  // load would be one more exposed round trip
+  const T sc = reinterpret_cast<const T*>(prm.scale)[mm];
 
   // weighted spectrum f(l) = r_m^l c_l for l < L; the weights of the later
   // terms sum to less than 2^-40 (single) / 2^-60 (double precision) and they
@@ -178,7 +183,6 @@ __device__ __forceinline__ void radius_slot(const RadiusParams& prm, int slot, i
     fft_regs<T, LOGN, E, +1, SPLIT>(v, t, lds_r, tw);
   }
 
-  const T sc = scale[mm];
   const uint32_t fbase = uint32_t(mm) * uint32_t(N);
   if constexpr (LIST) {
     const uint32_t r0 = prm.rpb == 1 ? uint32_t(mm) : uint32_t(slot) * uint32_t(prm.rpb);
