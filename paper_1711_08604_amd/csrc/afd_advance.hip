@@ -1,4 +1,4 @@
-// The tail of a Core-AFD step for 2^12 <= N <= 2^14 points, after the
+// The tail of a Core-AFD step for 2^10 <= N <= 2^14 points, after the
 // radius kernel: the double-precision re-check of the short-list by the
 // direct rule (Sec. 3.1, eq. term81), the winner, the remainder update of
 // Sec. 2, eq. (7), and the forward DFT of the new remainder (Sec. 3.1,
@@ -446,7 +446,7 @@ static void stockham_twiddles(double* out) {
   }
 }
 
-bool advance_supported(int logn) { return logn >= 12 && logn <= kMaxLdsLogN; }
+bool advance_supported(int logn) { return logn >= 10 && logn <= kMaxLdsLogN; }
 
 AdvGeom advance_geom(int logn) {
   AdvGeom g{};
@@ -461,7 +461,7 @@ AdvGeom advance_geom(int logn) {
     g.tw1_size = Shape<AdvShape<L>::L1, kAdvE>::twsize(); \
     g.tw2_size = Shape<AdvShape<L>::L2, kAdvE>::twsize(); \
     break;
-    X(12) X(13) X(14)
+    X(10) X(11) X(12) X(13) X(14)
 #undef X
     default:
       break;
@@ -471,6 +471,7 @@ AdvGeom advance_geom(int logn) {
 
 void advance_twiddles(int l, double* out) {
   switch (l) {
+    case 5: stockham_twiddles<5, kAdvE>(out); break;
     case 6: stockham_twiddles<6, kAdvE>(out); break;
     case 7: stockham_twiddles<7, kAdvE>(out); break;
     default: break;
@@ -513,7 +514,7 @@ hipError_t launch_advance(int logn, bool fp64, const AdvanceArgs& a, int batch, 
 #define X(L) \
   case L:    \
     return fp64 ? launch_advance_t<double, L>(a, batch, s, e0, e1) : launch_advance_t<float, L>(a, batch, s, e0, e1);
-    X(12) X(13) X(14)
+    X(10) X(11) X(12) X(13) X(14)
 #undef X
     default:
       return hipErrorInvalidValue;

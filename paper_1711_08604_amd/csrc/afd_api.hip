@@ -72,7 +72,7 @@ struct Config {
   int batch;    // signals per call
   bool big;     // N > 2^kMaxLdsLogN: two-pass radius transforms
   BigGeom bg;
-  bool adv;     // 2^12 <= N <= 2^14: fused step tail (afd_advance.hip)
+  bool adv;     // 2^10 <= N <= 2^14: fused step tail (afd_advance.hip)
   AdvGeom ag;
   int chunk;    // radii per two-pass chunk
 };
@@ -170,7 +170,8 @@ Layout layout_of(const Config& c) {
   L.g64 = take(16 * size_t(c.N) * B);
   L.g32 = take(c.fp64 || c.adv ? 0 : 8 * size_t(c.N) * B);
   L.c = take(2 * real * size_t(c.N) * B);
-  L.xt = take(c.fwd.two_pass ? 2 * real * size_t(c.N) * B : 0);
+  // the four-step intermediate of the forward DFT, or of the fused step tail's
+  L.xt = take(c.fwd.two_pass || c.adv ? 2 * real * size_t(c.N) * B : 0);
   L.blocks = take((c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.nblocks) * B);
   L.wl = take(c.big ? 2 * real * (size_t(1) << c.bg.sw) : 0);
   L.wh = take(c.big ? 2 * real * (size_t(1) << (c.logn - c.bg.sw)) : 0);

@@ -173,7 +173,7 @@ __host__ __device__ constexpr unsigned long long bar_group_count(int nw, int g) 
   return nw > g ? (unsigned long long)((nw - 1 - g) / kBarGroups + 1) : 0ull;
 }
 
-// Step tail for 2^12 <= N <= 2^14 (afd_advance.hip): re-check, winner,
+// Step tail for 2^10 <= N <= 2^14 (afd_advance.hip): re-check, winner,
 // remainder update and the forward DFT of the new remainder.
 struct AdvanceArgs {
   const CandList* cand;     // short-list (FP32 mode) or forced point

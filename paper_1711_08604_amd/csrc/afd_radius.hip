@@ -10,7 +10,7 @@
 // band of the workgroup maximum.  The grid values are never written to HBM.
 // The last workgroup to finish merges the per-workgroup records: FP64 into
 // the winner, FP32 into the short-list for the double re-check (or, for
-// 2^12 <= N <= 2^14, every workgroup of the step tail merges them itself).
+// 2^10 <= N <= 2^14, every workgroup of the step tail merges them itself).
 #include "afd_select.h"
 
 namespace afd {
