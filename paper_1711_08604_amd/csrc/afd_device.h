@@ -277,9 +277,9 @@ __device__ __forceinline__ void pass_job(Cx<T> (&v)[E], int t, const TW& tw) {
         Cx<T> w = row[(r - 1) * NS];
         if constexpr (SIGN < 0) w.y = -w.y;
         v[U + r * J] = cmul(v[U + r * J], w);
-        // double precision: keep at most four twiddles in flight so the
-        // 1024-thread transforms stay inside their 128-register budget
-        if ((sizeof(T) == 8 && (r % 4) == 3) || (sizeof(T) == 4 && (r % 8) == 7)) __builtin_amdgcn_sched_barrier(0);
+        // bound the twiddles in flight (four in double, sixteen in single
+        // precision) so the transforms stay inside their register budgets
+        if ((sizeof(T) == 8 && (r % 4) == 3) || (sizeof(T) == 4 && (r % 16) == 15)) __builtin_amdgcn_sched_barrier(0);
       }
     } else {
 #pragma unroll
