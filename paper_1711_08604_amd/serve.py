@@ -11,9 +11,20 @@ Admitted requests run concurrently on their slots' streams, so their kernels
 overlap on the device.  Every step of every request runs in the library's HIP
 kernels; this module only schedules.
 
-The plan of a request is the same object a caller would build alone, and the
-kernels are deterministic, so a request's result does not depend on what else
-is in flight.
+Shared launches: requests of one shape (N <= 2^14, radii, precision) run as
+the members of a group on one slot.  The group advances every member by a
+segment of AFD steps per call of a batched plan (every kernel launch covers
+all members), and between segments it admits the requests of that shape
+that arrived meanwhile and retires the ones that are done.  A member's next
+segment starts from the remainder its last one returned; each AFD step
+depends on the remainder alone, so the segments concatenate to the
+decomposition of the whole request.  Batches are padded with zero signals
+to a power of two, so a group reuses a few plans.
+
+The plan of a request (or of a group) is the same object a caller would
+build, and the kernels are deterministic (a signal's result in a batch
+equals its result alone), so a request's result does not depend on what
+else is in flight.
 """
 from __future__ import annotations
 
@@ -25,7 +36,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .afd import Plan, workspace_bytes
+from .afd import Plan, Result, workspace_bytes
 
 
 @dataclass
@@ -35,6 +46,44 @@ class Request:
     steps: int
     precision: str = "fp32"
     submitted: float = field(default_factory=time.perf_counter)
+
+
+SHARE_MAX_N = 1 << 14  # batched plans cover N <= 2^14
+
+RESULT_FIELDS = ("index", "a", "coef", "energy", "margin", "remainder", "recheck_count", "flags", "fp32_error")
+
+
+@dataclass
+class _Member:
+    req: Request
+    fut: Future
+    started: float
+    g: np.ndarray               # the remainder the next segment starts from
+    left: int                   # AFD steps still to run
+    parts: list = field(default_factory=list)
+
+
+def _member_result(res, i: int, batched: bool):
+    """Signal i of a (batched) Result, copied out of the batch's arrays."""
+    return Result(**{k: np.array(getattr(res, k)[i] if batched else getattr(res, k)) for k in RESULT_FIELDS})
+
+
+def _concat(parts) -> "Result":
+    """The segments of one request as one decomposition: per-step arrays
+    concatenated; energies E_0 of the first segment, then each segment's
+    E_1.. (its own E_0 is the previous segment's last); the last remainder."""
+    out = {k: np.concatenate([getattr(p, k) for p in parts]) for k in RESULT_FIELDS
+           if k not in ("energy", "remainder")}
+    out["energy"] = np.concatenate([parts[0].energy] + [p.energy[1:] for p in parts[1:]])
+    out["remainder"] = parts[-1].remainder
+    return Result(**out)
+
+
+def _bucket(count: int) -> int:
+    b = 1
+    while b < count:
+        b *= 2
+    return b
 
 
 @dataclass
@@ -55,12 +104,23 @@ def _plan_key(req: Request):
 
 
 class Server:
-    """Admission by free slot and HBM budget; concurrent execution on per-slot streams."""
+    """Admission by free slot and HBM budget; concurrent execution on per-slot
+    streams; requests of one shape share their launches."""
 
-    def __init__(self, slots: int = 8, hbm_budget: int = 64 << 30, device: str = "cuda:0", streams=None):
-        """`streams`: one HIP stream handle per slot (default: new torch streams on `device`)."""
+    def __init__(self, slots: int = 8, hbm_budget: int = 64 << 30, device: str = "cuda:0", streams=None,
+                 share: bool = True, segment: int = 16, max_batch: int = 32):
+        """`streams`: one HIP stream handle per slot (default: new torch streams on `device`).
+        `share`: run requests of one shape (N <= 2^14) as a group with shared
+        launches, `segment` AFD steps per call, at most `max_batch` at once."""
         self.slots = int(slots)
         self.budget = int(hbm_budget)
+        self.share = bool(share)
+        self.segment = max(1, int(segment))
+        self.max_batch = _bucket(max(1, int(max_batch)))
+        self._groups = {}                    # shape key -> pending members of the group running it
+        self._group_threads = []
+        self.shared_calls = 0                # batched calls made by groups
+        self.shared_members = 0              # member-segments they covered
         self._lock = threading.Condition()
         self._queue: deque = deque()
         self._free_slots = list(range(self.slots))
@@ -108,6 +168,8 @@ class Server:
             self._closed = True
             self._lock.notify_all()
         self._dispatcher.join()
+        for th in list(self._group_threads):  # their plans are closed by their threads
+            th.join()
         for cache in self._plans:
             for plan, _ in cache.values():
                 plan.close()
@@ -136,6 +198,22 @@ class Server:
                 self._used -= b
         return self._used + need <= self.budget
 
+    def _shareable(self, req: Request) -> bool:
+        return self.share and req.signal.shape[0] <= SHARE_MAX_N and req.steps > 0
+
+    def _group_size(self, req: Request):
+        """(largest batch, HBM of every batched plan up to it) for a group of
+        this shape: the largest power of two up to max_batch whose plans (one
+        per power of two) fit the budget together; (0, 0) if none does."""
+        best, total, b = (0, 0), 0, 1
+        while b <= self.max_batch:
+            total += workspace_bytes(req.signal.shape[0], req.radii, req.precision, batch=b)
+            if total > self.budget:
+                break
+            best = (b, total)
+            b *= 2
+        return best
+
     def _dispatch(self):
         while True:
             with self._lock:
@@ -145,23 +223,111 @@ class Server:
                     return
                 req, need, fut = self._queue[0]
                 key = _plan_key(req)
-                # prefer a free slot that already holds this plan
-                slot = next((s for s in self._free_slots if key in self._plans[s]), None)
-                if slot is None and self._free_slots:
+                if self._shareable(req):
+                    if key in self._groups:  # a group of this shape is running: it takes the request
+                        self._queue.popleft()
+                        self._groups[key].append((req, fut))
+                        self._busy += 1
+                        continue
+                    if not self._free_slots:
+                        self._lock.wait()
+                        continue
+                    gmax, gneed = self._group_size(req)
+                    if gmax == 0:
+                        self._queue.popleft()
+                        fut.set_exception(ValueError(f"a request of this shape needs more than the HBM budget "
+                                                     f"{self.budget}"))
+                        continue
                     slot = self._free_slots[0]
-                if slot is None:
-                    self._lock.wait()
-                    continue
-                extra = 0 if key in self._plans[slot] else need
-                if self._used + extra > self.budget and not self._reclaim(extra, slot, key):
-                    self._lock.wait()  # wait for running requests to finish
-                    continue
-                self._queue.popleft()
-                self._free_slots.remove(slot)
-                self._used += extra
-                self.peak_used = max(self.peak_used, self._used)
-                self._busy += 1
-            threading.Thread(target=self._run, args=(slot, req, need, key, fut), daemon=True).start()
+                    if self._used + gneed > self.budget and not self._reclaim(gneed, slot, None):
+                        self._lock.wait()  # wait for running requests to finish
+                        continue
+                    self._queue.popleft()
+                    self._free_slots.remove(slot)
+                    self._used += gneed
+                    self.peak_used = max(self.peak_used, self._used)
+                    self._busy += 1
+                    self._groups[key] = deque([(req, fut)])
+                    target, args = self._run_group, (slot, key, gmax, gneed)
+                    self._group_threads = [t for t in self._group_threads if t.is_alive()]
+                else:
+                    # prefer a free slot that already holds this plan
+                    slot = next((s for s in self._free_slots if key in self._plans[s]), None)
+                    if slot is None and self._free_slots:
+                        slot = self._free_slots[0]
+                    if slot is None:
+                        self._lock.wait()
+                        continue
+                    extra = 0 if key in self._plans[slot] else need
+                    if self._used + extra > self.budget and not self._reclaim(extra, slot, key):
+                        self._lock.wait()  # wait for running requests to finish
+                        continue
+                    self._queue.popleft()
+                    self._free_slots.remove(slot)
+                    self._used += extra
+                    self.peak_used = max(self.peak_used, self._used)
+                    self._busy += 1
+                    target, args = self._run, (slot, req, need, key, fut)
+            th = threading.Thread(target=target, args=args, daemon=True)
+            if target == self._run_group:
+                with self._lock:
+                    self._group_threads.append(th)
+            th.start()
+
+    def _run_group(self, slot: int, key, gmax: int, gneed: int):
+        """Run the group of shape `key` on `slot` (at most gmax members at a
+        time) until no member is left."""
+        n, precision, _ = key
+        pending = self._groups[key]
+        radii = np.frombuffer(key[2], dtype=np.float64)
+        plans = {}
+        members = []
+        try:
+            while True:
+                with self._lock:
+                    while pending and len(members) < gmax:
+                        req, fut = pending.popleft()
+                        members.append(_Member(req, fut, time.perf_counter(), req.signal, req.steps))
+                    if not members:
+                        del self._groups[key]  # later requests of this shape start a new group
+                        return
+                nb = _bucket(len(members))
+                if nb not in plans:
+                    plans[nb] = Plan(n, radii, precision=precision, stream=self._streams[slot], batch=nb)
+                seg = min(self.segment, min(m.left for m in members))
+                sig = np.zeros((nb, n), dtype=np.complex128)
+                for i, m in enumerate(members):
+                    sig[i] = m.g
+                res = plans[nb].decompose(sig if nb > 1 else sig[0], seg)
+                self.shared_calls += 1
+                self.shared_members += len(members)
+                for i, m in enumerate(members):
+                    part = _member_result(res, i, nb > 1)
+                    m.parts.append(part)
+                    m.g = part.remainder
+                    m.left -= seg
+                done = [m for m in members if m.left == 0]
+                members = [m for m in members if m.left > 0]
+                for m in done:
+                    m.fut.set_result(Served(_concat(m.parts), m.req.submitted, m.started, time.perf_counter(), slot))
+                    with self._lock:
+                        self._busy -= 1
+                        self._lock.notify_all()
+        except Exception as e:  # the group's requests fail, the server goes on
+            with self._lock:
+                failed = members + [_Member(r, f, 0.0, r.signal, 0) for r, f in pending]
+                pending.clear()
+                self._groups.pop(key, None)
+                for m in failed:
+                    m.fut.set_exception(e)
+                    self._busy -= 1
+        finally:
+            for plan in plans.values():
+                plan.close()
+            with self._lock:
+                self._used -= gneed
+                self._free_slots.append(slot)
+                self._lock.notify_all()
 
     def _run(self, slot: int, req: Request, need: int, key, fut: Future):
         started = time.perf_counter()

@@ -1,6 +1,7 @@
 """Serving: requests of differing N and step counts admitted by free slot and
-HBM budget and run concurrently; each result must equal the same request
-decomposed alone (bit for bit) and match the FP64 oracle."""
+HBM budget and run concurrently, those of one shape in shared launches; each
+result must equal the same request decomposed alone (bit for bit) and match
+the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -36,12 +37,21 @@ def _alone(g, radii, steps, prec):
 
 
 def test_mix_equals_alone_and_oracle():
+    """Requests of one shape share launches: segments of 4 AFD steps of a
+    batched plan, members joining (also while the group runs) and leaving
+    between segments."""
     reqs = _requests(24)
-    with Server(slots=4) as srv:
-        futs = [srv.submit(*r) for r in reqs]
+    with Server(slots=4, segment=4) as srv:
+        futs = []
+        for i, r in enumerate(reqs):
+            futs.append(srv.submit(*r))
+            if i == 15:
+                futs[0].result(timeout=120)  # the rest arrive while groups run
         served = [f.result(timeout=120) for f in futs]
+        shared = (srv.shared_calls, srv.shared_members)
     slots_used = {s.slot for s in served}
     assert len(slots_used) > 1
+    assert shared[1] > shared[0], shared  # some calls covered several requests
     for i, ((g, radii, steps, prec), s) in enumerate(zip(reqs, served)):
         alone = _alone(g, radii, steps, prec)
         for k in FIELDS:
