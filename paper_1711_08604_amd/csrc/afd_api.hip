@@ -534,8 +534,9 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
       HIPCHK(tm.pair(kTimeRadius, &e0, &e1), "event");
       const int grid = rp.queue ? p->rslots : c.nblocks;
       HIPCHK(launch_radius(c.logn, c.fp64, rp, grid, B, s, e0, e1), "k_radius");
-      // the queue hands out the slots past the grid, and each workgroup's last
-      // fetch comes back past the end: nblocks - grid + grid fetches
+      // the queue hands out the slots past the grid: every processed slot
+      // takes one ticket (each workgroup's last one comes back past the end),
+      // nblocks tickets per launch
       if (rp.queue) rp.qbase += unsigned(c.nblocks);
     }
     hipEvent_t u0, u1;

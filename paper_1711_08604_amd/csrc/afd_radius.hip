@@ -78,7 +78,10 @@ __device__ __forceinline__ void deep_inputs(Cx<T> (&v)[E], int t, int L, const C
 // of decreasing significant spectrum length, so the longest transforms come
 // first; the radius and its length in one load) or rpb consecutive radii.
 template <typename T, int LOGN, bool LIST>
-__device__ __forceinline__ void radius_slot(const RadiusParams& prm, int slot, int b, unsigned char* smem) {
+// With a work queue, thread 0 claims the next slot after the transform and
+// the claim's round trip overlaps the selection; the returned ticket is
+// meaningful in thread 0 only.
+__device__ __forceinline__ unsigned int radius_slot(const RadiusParams& prm, int slot, int b, unsigned char* smem) {
   constexpr int E = pickE<T, LOGN>();
   constexpr bool SPLIT = pickSplit<T, LOGN>();
   using S = Shape<LOGN, E>;
@@ -184,6 +187,9 @@ __device__ __forceinline__ void radius_slot(const RadiusParams& prm, int slot, i
   }
 
   const uint32_t fbase = uint32_t(mm) * uint32_t(N);
+  unsigned int ticket = 0;
+  if (radius_queued<T>() && prm.queue != nullptr && threadIdx.x == 0)
+    ticket = __hip_atomic_fetch_add(prm.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if constexpr (LIST) {
     const uint32_t r0 = prm.rpb == 1 ? uint32_t(mm) : uint32_t(slot) * uint32_t(prm.rpb);
     const uint32_t ract = uint32_t(prm.M) - r0 < uint32_t(prm.rpb) ? uint32_t(prm.M) - r0 : uint32_t(prm.rpb);
@@ -197,12 +203,15 @@ __device__ __forceinline__ void radius_slot(const RadiusParams& prm, int slot, i
     select_best<LOGN, T>(v, active, sc, fbase, 1u, t, reinterpret_cast<Best*>(scratch),
                          reinterpret_cast<BlockBest64*>(prm.out) + size_t(prm.nrec) * b + slot);
   }
+  return ticket;
 }
 
 // With prm.queue, a single signal's record slots come from a work queue: the
 // grid holds only the workgroups that fit on the device at once, each takes
-// its own slot first and then the next free one (longest transforms first)
-// as it finishes one.  A slot's record does not depend on the workgroup that
+// its own slot first and then the next free one (longest transforms first),
+// claimed once the current slot's transform is done.  Every processed slot
+// claims one ticket, so a launch takes nrec tickets.  A slot's record does
+// not depend on the workgroup that
 // computes it.  Every workgroup leaves once the queue is exhausted; none
 // waits on another.
 template <typename T, int LOGN, bool LIST>
@@ -220,12 +229,10 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
     // back past the last slot
     int slot = int(blockIdx.x);
     while (slot < prm.nrec) {  // uniform
-      radius_slot<T, LOGN, LIST>(prm, slot, b, smem);
+      const unsigned int ticket = radius_slot<T, LOGN, LIST>(prm, slot, b, smem);
       if (!prm.queue) break;
       __syncthreads();  // every thread is done with the LDS and with s_next
-      if (threadIdx.x == 0)
-        s_next = int(gridDim.x) +
-                 int(__hip_atomic_fetch_add(prm.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - prm.qbase);
+      if (threadIdx.x == 0) s_next = int(gridDim.x) + int(ticket - prm.qbase);
       __syncthreads();
       slot = __builtin_amdgcn_readfirstlane(s_next);  // uniform: a scalar register
     }
