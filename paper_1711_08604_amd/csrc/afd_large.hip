@@ -169,7 +169,10 @@ void k_big_rows(BigParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_last;
   const int ri = threadIdx.x / B::TPR2, t = threadIdx.x - ri * B::TPR2;
-  const int j1 = blockIdx.x * B::RB + ri;
+  int j1 = blockIdx.x * B::RB + ri;
+  // a row of at least 64 threads spans whole waves: j1 is wave-uniform, so
+  // the row's uniform twiddles come through scalar loads
+  if constexpr (B::TPR2 % 64 == 0) j1 = __builtin_amdgcn_readfirstlane(j1);
   const int ml = blockIdx.y, m = p.m0 + ml;
 
   using S2 = Shape<B::L2, B::E2>;
