@@ -13,7 +13,8 @@ in [0, 0.999], 50 steps; G = 40 normalised Szego kernels with poles
 |b| <= 0.98 and CN(0,1) weights plus CN noise at 30 dB SNR (seeded,
 synthetic).  `--workload chirp1m` times the large decomposition instead:
 N = 2^20, M = 2000, 100 steps of the analytic part of a chirp + 3 tones +
-white noise at 20 dB, whose radius transforms run as two passes through HBM.
+white noise at 20 dB, whose radius transforms run beyond the LDS (one row pass
+for short spectra, two passes through HBM for the longest).
 `--workload batch512` times the uniform batch: 512 signals of N = 4096
 (8..32 kernels, |b| <= 0.95), M = 512, 30 steps, decomposed together.
 `--workload small1k` times the small latency-bound case: N = 1024, M = 100
