@@ -96,6 +96,16 @@ typedef struct {
   double* fp32_error;     /* steps: FP32 mode, max |P32 - P64| / P64max over the re-checked
                              points (P = |<G_k, e_a>~|^2; P64 by the double direct rule); the
                              measured error of the FP32 bulk against double.  FP64: 0 [nullable] */
+  /* Written by afd_replay only (afd_decompose leaves them untouched): what the
+     step's own selection chose on the replayed remainder G_k before the forced
+     point replaced it.                                                          */
+  int32_t* pick_index;    /* 2*steps: (m, j) of the selection's choice             [nullable] */
+  double* pick_p;         /* steps: its |<G_k, e_a>~|^2 (FP64: the FFT-form grid value the
+                             selection compared; FP32: the double re-check)        [nullable] */
+  double* pick_margin;    /* steps: the selection's margin, as `margin` in afd_decompose
+                                                                                   [nullable] */
+  int32_t* pick_flags;    /* steps: bits 0-2 as `flags`; bit 4: FP32 mode, the forced point
+                             was on the short-list that was re-checked in double   [nullable] */
 } afd_result;
 
 /* Validate `desc`, copy the radii, build the per-radius double-precision
@@ -121,12 +131,20 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
    the loop continues. */
 afd_status afd_decompose(afd_plan plan, const double* signal, int32_t steps, afd_result* out);
 
-/* As afd_decompose, but step k takes the grid point forced_index[2k],
-   forced_index[2k+1] (host or device, 2*steps int32) instead of selecting;
-   c_k is then the grid value at that point evaluated in double by the direct
-   rule (eq. term81).  Used to compare every step with a reference trajectory
-   past near-ties.  With batch B, forced_index is [B][steps][2].  Errors as
-   afd_decompose, plus AFD_E_INVALID for an index outside [0,M) x [0,N). */
+/* As afd_decompose, but step k continues from the grid point forced_index[2k],
+   forced_index[2k+1] (host or device, 2*steps int32) instead of the selected
+   one.  Every step still runs the whole path on the replayed remainder G_k:
+   the forward DFT, the per-radius inverse DFTs, |.|^2, the selection and (FP32
+   mode) the double re-check of the short-list; the choice it makes goes to
+   pick_index / pick_p / pick_margin / pick_flags.  The forced point then takes
+   its place: c_k is the FFT-form grid value there from the same radius
+   transforms (FP64 mode; so with the indices afd_decompose chose, the results
+   equal afd_decompose's bit for bit) or its double direct-rule value (eq.
+   term81; FP32 mode), and the update uses it.  `margin` is NaN.  Used to
+   compare every step of the path with a reference trajectory past near-ties.
+   first_a_zero does not apply (the forced indices cover every step).  With
+   batch B, forced_index is [B][steps][2].  Errors as afd_decompose, plus
+   AFD_E_INVALID for an index outside [0,M) x [0,N). */
 afd_status afd_replay(afd_plan plan, const double* signal, int32_t steps,
                       const int32_t* forced_index, afd_result* out);
 

@@ -54,6 +54,8 @@ __all__ = [
     "update",
     "energy",
     "decompose",
+    "select_streamed",
+    "decompose_streamed",
     "tm_basis",
     "partial_sum",
     "relative_errors",
@@ -211,6 +213,75 @@ def decompose(G, radii, steps: int, first_a_zero: bool = False, forced=None,
         (m, j), margin = select(V, f)
         a = radii[m] * np.exp(2j * np.pi * j / N)
         coef = V[m, j]
+        G = update(G, a, coef)
+        idx.append((m, j))
+        a_list.append(a)
+        c_list.append(coef)
+        e_list.append(energy(G))
+        mg.append(margin)
+    return Decomposition(idx, a_list, c_list, e_list, mg, G)
+
+
+def select_streamed(G: np.ndarray, radii: np.ndarray, chunk: int = 16, workers: int = 1):
+    """Sec. 3.2 Steps 1 and 2 without holding the whole M x N grid.
+
+    The grid values of eqs. term4/rcl are formed `chunk` radii at a time by
+    grid_fft (each radius' row is computed exactly as there), and every chunk
+    is reduced to its largest |V|^2 (first maximiser in radius-major order),
+    its second largest |V|^2 and the grid value at the maximiser.  Chunks are
+    combined in index order, so the result is select(grid_fft(G, radii))
+    bit for bit: ((m, j), margin) plus V[m, j] and P1 = |V[m, j]|^2.
+    `workers` > 1 evaluates chunks on that many threads (the FFTs release
+    the interpreter lock); the combination order does not change.
+    """
+    G = np.asarray(G, dtype=np.complex128)
+    radii = np.asarray(radii, dtype=np.float64)
+    N = G.shape[0]
+    starts = list(range(0, len(radii), chunk))
+
+    def part(m0):
+        V = grid_fft(G, radii[m0:m0 + chunk])
+        P = (V.real ** 2 + V.imag ** 2).ravel()
+        f = int(np.argmax(P))
+        p2 = np.partition(P, P.size - 2)[P.size - 2] if P.size > 1 else -1.0
+        return P[f], p2, m0 * N + f, V.ravel()[f]
+
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            parts = list(ex.map(part, starts))
+    else:
+        parts = [part(m0) for m0 in starts]
+    p1, p2, f, v = parts[0]
+    for q1, q2, g, w in parts[1:]:
+        if q1 > p1:  # strictly larger: equal values keep the lower flat index
+            p2 = max(p1, q2)
+            p1, f, v = q1, g, w
+        else:
+            p2 = max(p2, q1)
+    if len(radii) * N < 2:
+        p2 = 0.0
+    margin = float((p1 - p2) / p1) if p1 > 0 else 0.0
+    return (f // N, f % N), margin, complex(v), float(p1)
+
+
+def decompose_streamed(G, radii, steps: int, forced=None, chunk: int = 16, workers: int = 1) -> Decomposition:
+    """decompose() with the grid streamed by select_streamed: the same loop
+    (FFT form, maximal selection, coefficient, eq. (7) update, energy) for
+    grids too large to hold; results equal decompose()'s bit for bit.
+    `forced` (steps x 2) replaces the selection as in decompose()."""
+    G = np.asarray(G, dtype=np.complex128).copy()
+    radii = np.asarray(radii, dtype=np.float64)
+    N = G.shape[0]
+    idx, a_list, c_list, e_list, mg = [], [], [], [energy(G)], []
+    for k in range(steps):
+        if forced is not None:
+            m, j = int(forced[k][0]), int(forced[k][1])
+            coef = grid_fft(G, radii[m:m + 1])[0, j]
+            margin = float("nan")
+        else:
+            (m, j), margin, coef, _ = select_streamed(G, radii, chunk, workers)
+        a = radii[m] * np.exp(2j * np.pi * j / N)
         G = update(G, a, coef)
         idx.append((m, j))
         a_list.append(a)

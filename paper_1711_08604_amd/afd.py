@@ -53,6 +53,10 @@ class ResultDesc(ctypes.Structure):
         ("recheck_count", ctypes.c_void_p),
         ("flags", ctypes.c_void_p),
         ("fp32_error", ctypes.c_void_p),
+        ("pick_index", ctypes.c_void_p),
+        ("pick_p", ctypes.c_void_p),
+        ("pick_margin", ctypes.c_void_p),
+        ("pick_flags", ctypes.c_void_p),
     ]
 
 
@@ -142,6 +146,11 @@ class Result:
     recheck_count: object
     flags: object
     fp32_error: object  # (steps,) float64: FP32-vs-FP64 error of |.|^2 on the re-checked points
+    # replay only: the selection's own choice at each replayed step (None after decompose)
+    pick_index: object = None   # (steps, 2) int32
+    pick_p: object = None       # (steps,) float64: its |<G_k, e_a>~|^2
+    pick_margin: object = None  # (steps,) float64
+    pick_flags: object = None   # (steps,) int32: bit 4 = the forced point was on the FP32 short-list
 
     @property
     def delta(self):
@@ -188,11 +197,14 @@ class Plan:
         self.close()
 
     # -- running
-    def _outputs(self, signal, steps):
+    def _outputs(self, signal, steps, picks=False):
         lead = (self.batch,) if self.batch > 1 else ()
         shapes = {"index": ((steps, 2), "i32"), "a": ((steps,), "c128"), "coef": ((steps,), "c128"),
                   "energy": ((steps + 1,), "f64"), "margin": ((steps,), "f64"), "remainder": ((self.n,), "c128"),
                   "recheck_count": ((steps,), "i32"), "flags": ((steps,), "i32"), "fp32_error": ((steps,), "f64")}
+        if picks:
+            shapes.update({"pick_index": ((steps, 2), "i32"), "pick_p": ((steps,), "f64"),
+                           "pick_margin": ((steps,), "f64"), "pick_flags": ((steps,), "i32")})
         if _is_torch_cuda(signal):
             import torch
             dev = signal.device
@@ -204,7 +216,7 @@ class Plan:
             out = Result(**{k: np.empty(lead + shp, dtype=dt[t]) for k, (shp, t) in shapes.items()})
             ptr = lambda a: a.ctypes.data  # noqa: E731
         rd = ResultDesc()
-        for name in ("index", "a", "coef", "energy", "margin", "remainder", "recheck_count", "flags", "fp32_error"):
+        for name in shapes:
             setattr(rd, name, ptr(getattr(out, name)))
         return out, rd
 
@@ -232,8 +244,11 @@ class Plan:
         return out
 
     def replay(self, signal, steps: int, forced) -> Result:
+        """Decompose along the forced indices (steps x 2, or batch x steps x 2):
+        every step still runs the whole path and reports its own choice in
+        pick_index / pick_p / pick_margin / pick_flags (afd_replay)."""
         sp, keep = self._signal_ptr(signal)
-        out, rd = self._outputs(signal, int(steps))
+        out, rd = self._outputs(signal, int(steps), picks=True)
         if _is_torch_cuda(forced):
             fptr, fkeep = forced.data_ptr(), forced
         else:

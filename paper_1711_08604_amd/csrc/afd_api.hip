@@ -43,7 +43,7 @@ enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3 }
 // Device arena layout for one plan.
 struct Layout {
   size_t radii, omega, tw, twf1, twf2, pw, pv, scale, g64, g32, c, xt, blocks, cand, partials, winner, epart,
-      nonfinite, forced0, counters, bar, omega_t, rqueue;
+      nonfinite, forced0, counters, bar, omega_t, rqueue, probe;
   // truncated / pruned spectrum of the LDS-resident radius transforms
   size_t pq, lsig, order;
   // FP32 head and second keys of the workgroup (or per-radius) records
@@ -188,6 +188,7 @@ Layout layout_of(const Config& c) {
   L.counters = take(4 * kNumCounters * B);  // [kind][signal]
   L.bar = take(8 * 16 * kBarGroups);  // counters 128 bytes apart
   L.rqueue = take(4);                  // work queue of the radius slots
+  L.probe = take(16 * B);              // replay: the grid value at each signal's forced point
   // fused step tail in single precision: the unit roots rounded to float
   L.omega_t = take(c.adv && !c.fp64 ? 8 * size_t(c.N) : 0);
   L.total = o;
@@ -374,6 +375,11 @@ struct ResPtrs {
   int32_t* kcount;
   int32_t* flags;
   double* fp32err;
+  // replay: the selection's own choice per step
+  int32_t* pidx;
+  double* pp;
+  double* pmargin;
+  int32_t* pflags;
   size_t total;
 };
 
@@ -395,6 +401,10 @@ ResPtrs res_layout(unsigned char* base, int steps, int batch) {
   r.kcount = reinterpret_cast<int32_t*>(take(4 * s * B));
   r.flags = reinterpret_cast<int32_t*>(take(4 * s * B));
   r.fp32err = reinterpret_cast<double*>(take(8 * s * B));
+  r.pidx = reinterpret_cast<int32_t*>(take(8 * s * B));
+  r.pp = reinterpret_cast<double*>(take(8 * s * B));
+  r.pmargin = reinterpret_cast<double*>(take(8 * s * B));
+  r.pflags = reinterpret_cast<int32_t*>(take(4 * s * B));
   r.total = o;
   return r;
 }
@@ -475,15 +485,49 @@ struct Timer {
     if (_e != hipSuccess) return hip_fail(_e, where); \
   } while (0)
 
-// Steps of a plan with the fused step tail: per step the radius kernel (or a
-// forced point), then one launch_advance that re-checks, updates and
-// transforms the new remainder for the next step.
-afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const RecordArgs& rec,
-                   RadiusParams rp, Timer& tm) {
+// A replayed step after its selection: the records are merged (when the
+// radius kernel left them to the step tail) and, in single precision, the
+// short-list re-checked, as afd_decompose does; then k_pick records that
+// choice and puts the forced point in its place, whose coefficient is the
+// FFT-form grid value (double precision) or the direct rule in double (a
+// one-entry re-check).  The winner is then in p->L.winner.
+afd_status replay_pick(afd_plan_s* p, int k, bool merged, PickArgs pk) {
   const Config& c = p->cfg;
   const int B = c.batch;
   hipStream_t s = p->stream;
-  auto forced_at = [&](int k) { return forced_user != nullptr || (p->first_a_zero && k == 0); };
+  CandList* cand = p->at<CandList>(p->L.cand);
+  Winner* win = p->at<Winner>(p->L.winner);
+  unsigned int* counters = p->at<unsigned int>(p->L.counters);
+  const double* omega = p->at<double>(p->L.omega);
+  const double* radii = p->at<double>(p->L.radii);
+  double* g64 = p->at<double>(p->L.g64);
+  double* partials = p->at<double>(p->L.partials);
+  if (!merged)
+    HIPCHK(launch_merge(c.fp64, p->at<void>(p->L.blocks), c.fp64 ? nullptr : p->at<uint64_t>(p->L.heads),
+                        c.fp64 ? nullptr : p->at<uint64_t>(p->L.seconds), c.nblocks, int(c.N), c.logn, p->recheck_k,
+                        p->tau_band, counters + 4 * B, cand, win, B, s),
+           "k_merge");
+  if (!c.fp64)
+    HIPCHK(launch_recheck(cand, g64, omega, radii, int(c.N), partials, counters + 1 * B, win, B, s), "k_recheck");
+  pk.step = k;
+  HIPCHK(launch_pick(pk, B, s), "k_pick");
+  if (!c.fp64)
+    HIPCHK(launch_recheck(cand, g64, omega, radii, int(c.N), partials, counters + 1 * B, win, B, s), "k_recheck");
+  return AFD_OK;
+}
+
+// Steps of a plan with the fused step tail: per step the radius kernel (or a
+// forced point), then one launch_advance that re-checks, updates and
+// transforms the new remainder for the next step.  A replayed step runs the
+// radius kernel and the selection too (replay_pick), and the step tail then
+// updates with the forced point.
+afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const RecordArgs& rec,
+                   RadiusParams rp, const PickArgs& pk, Timer& tm) {
+  const Config& c = p->cfg;
+  const int B = c.batch;
+  hipStream_t s = p->stream;
+  const bool replay = forced_user != nullptr;
+  auto forced_at = [&](int k) { return !replay && p->first_a_zero && k == 0; };
   AdvanceArgs a{};
   a.cand = p->at<CandList>(p->L.cand);
   a.winner = p->at<Winner>(p->L.winner);
@@ -525,25 +569,29 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
   for (int k = 0; k < steps; ++k) {
     const bool forced = forced_at(k);
     if (forced) {
-      const int32_t* fsrc = forced_user ? p->forced : p->at<int32_t>(p->L.forced0);
-      HIPCHK(launch_force(fsrc, forced_user ? 2 * steps : 0, forced_user ? k : 0, int(c.N),
-                          p->at<CandList>(p->L.cand), B, s),
+      HIPCHK(launch_force(p->at<int32_t>(p->L.forced0), 0, 0, int(c.N), p->at<CandList>(p->L.cand), B, s),
              "k_force");
     } else {
       hipEvent_t e0, e1;
       HIPCHK(tm.pair(kTimeRadius, &e0, &e1), "event");
       const int grid = rp.queue ? p->rslots : c.nblocks;
+      if (replay && c.fp64) rp.probe = p->forced + 2 * k;
       HIPCHK(launch_radius(c.logn, c.fp64, rp, grid, B, s, e0, e1), "k_radius");
       // the queue hands out the slots past the grid: every processed slot
       // takes one ticket (each workgroup's last one comes back past the end),
       // nblocks tickets per launch
       if (rp.queue) rp.qbase += unsigned(c.nblocks);
+      if (replay) {
+        const afd_status st = replay_pick(p, k, false, pk);
+        if (st != AFD_OK) return st;
+      }
     }
     hipEvent_t u0, u1;
     HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
     a.update = 1;
-    a.recheck = (!c.fp64 || forced) ? 1 : 0;
-    a.nrec = forced ? 0 : c.nblocks;  // a forced point comes as a one-entry short-list
+    // a forced point comes as a one-entry short-list; a replayed step's winner is ready
+    a.recheck = (!replay && (!c.fp64 || forced)) ? 1 : 0;
+    a.nrec = (forced || replay) ? 0 : c.nblocks;
     a.fft = (k + 1 < steps && !forced_at(k + 1)) ? 1 : 0;
     a.step = k;
     HIPCHK(advance(u0, u1), "k_advance");
@@ -658,6 +706,9 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   const bool queued = c.fp64 && c.adv && B == 1 && c.rpb == 1 && p->rslots > 0 && p->rslots < c.nblocks;
   rp.queue = queued ? p->at<unsigned int>(p->L.rqueue) : nullptr;
   rp.qbase = 0;
+  rp.probe = nullptr;  // set per replayed step (double precision)
+  rp.probe_stride = 2 * steps;
+  rp.probe_out = p->at<double>(p->L.probe);
 
   BigParams bp{};
   if (c.big) {
@@ -684,7 +735,25 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     bp.flagword = counters + 4 * B;
     bp.cand = cand;
     bp.winner = win;
+    bp.probe = nullptr;
+    bp.probe_out = p->at<double>(p->L.probe);
   }
+  const bool replay = forced_user != nullptr;
+  PickArgs pk{};
+  pk.forced = p->forced;
+  pk.fstride = 2 * steps;
+  pk.N = N;
+  pk.logn = c.logn;
+  pk.M = c.M;
+  pk.steps = steps;
+  pk.fp64 = c.fp64 ? 1 : 0;
+  pk.cand = cand;
+  pk.winner = win;
+  pk.probe = p->at<double>(p->L.probe);
+  pk.idx = R.pidx;
+  pk.p = R.pp;
+  pk.margin = R.pmargin;
+  pk.flags = R.pflags;
 
   Timer tm{p};
   UpdateArgs upd{};
@@ -696,20 +765,12 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   upd.counter = counters + 2 * B;
   upd.R = rec;
   if (c.adv) {
-    st = run_adv(p, steps, forced_user, rec, rp, tm);
+    st = run_adv(p, steps, forced_user, rec, rp, pk, tm);
     if (st != AFD_OK) return st;
   }
   for (int k = 0; k < (c.adv ? 0 : steps); ++k) {
-    const int32_t* fsrc = nullptr;
-    int fstep = k;
-    if (forced_user) {
-      fsrc = p->forced;
-    } else if (p->first_a_zero && k == 0) {
-      fsrc = forced0;
-      fstep = 0;
-    }
-    if (fsrc) {
-      HIPCHK(launch_force(fsrc, forced_user ? 2 * steps : 0, fstep, N, cand, B, s), "k_force");
+    if (!replay && p->first_a_zero && k == 0) {
+      HIPCHK(launch_force(forced0, 0, 0, N, cand, B, s), "k_force");
       HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1 * B, win, B, s), "k_recheck");
     } else {
       hipEvent_t e0, e1;
@@ -719,6 +780,10 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
                         e0, e1, c.big ? p->at<void>(p->L.c0) : nullptr),
              "forward DFT");
       HIPCHK(tm.pair(kTimeRadius, &e0, &e1), "event");
+      if (replay && c.fp64) {
+        rp.probe = p->forced + 2 * k;
+        bp.probe = p->forced + 2 * k;
+      }
       if (c.big) {
         for (int m0 = 0; m0 < c.M; m0 += c.chunk) {
           bp.m0 = m0;
@@ -730,8 +795,13 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       } else {
         HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, B, s, e0, e1), "k_radius");
       }
-      if (!c.fp64)
+      if (replay) {
+        // the radius kernel's last workgroup merged the records
+        st = replay_pick(p, k, true, pk);
+        if (st != AFD_OK) return st;
+      } else if (!c.fp64) {
         HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1 * B, win, B, s), "k_recheck");
+      }
     }
     hipEvent_t u0, u1;
     HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
@@ -758,6 +828,12 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   if (out->recheck_count) HIPCHK(cp(out->recheck_count, R.kcount, 4 * S * BB), "copy recheck_count");
   if (out->flags) HIPCHK(cp(out->flags, R.flags, 4 * S * BB), "copy flags");
   if (out->fp32_error) HIPCHK(cp(out->fp32_error, R.fp32err, 8 * S * BB), "copy fp32_error");
+  if (replay) {
+    if (out->pick_index) HIPCHK(cp(out->pick_index, R.pidx, 8 * S * BB), "copy pick_index");
+    if (out->pick_p) HIPCHK(cp(out->pick_p, R.pp, 8 * S * BB), "copy pick_p");
+    if (out->pick_margin) HIPCHK(cp(out->pick_margin, R.pmargin, 8 * S * BB), "copy pick_margin");
+    if (out->pick_flags) HIPCHK(cp(out->pick_flags, R.pflags, 4 * S * BB), "copy pick_flags");
+  }
   if (out->remainder) HIPCHK(cp(out->remainder, g64, 16 * size_t(N) * BB), "copy remainder");
   HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
   g_last_error.clear();

@@ -90,6 +90,11 @@ struct RadiusParams {
   int nrec;           // record slots per signal (the records' stride)
   unsigned int* queue;  // non-null (single signal, tail = 0): slots come from this work queue
   unsigned int qbase;   // the queue's value at this launch (it only grows during a call)
+  // double precision, non-null: the grid point (m, j) at probe[probe_stride b] of signal b
+  // (a replayed step's forced point) has its scaled grid value stored to probe_out[2b], [2b+1]
+  const int32_t* probe;
+  int probe_stride;
+  double* probe_out;
 };
 
 // Radius transforms beyond the LDS (N > 2^kMaxLdsLogN): per radius a
@@ -119,6 +124,10 @@ struct BigParams {
   unsigned int* counter_g;  // radius arrivals over the step's chunks (zero between steps)
   CandList* cand;
   Winner* winner;
+  // double precision, non-null: the grid value at the point (m, j) = (probe[0], probe[1])
+  // is stored to probe_out[0], [1] (as in RadiusParams; one signal)
+  const int32_t* probe;
+  double* probe_out;
 };
 
 struct BigGeom {
@@ -153,6 +162,25 @@ struct RecordArgs {
   int32_t* flags;
   double* fp32err;
 };
+
+// A replayed step (afd_replay): the point the step's own selection chose is
+// recorded, then the forced point takes its place as the winner.  Arrays
+// are per signal, `steps` entries apart (index: 2 per step).
+struct PickArgs {
+  const int32_t* forced;  // [B][fstride] (m, j) per step
+  int fstride;
+  int step;
+  int N, logn, M, steps;
+  int fp64;
+  CandList* cand;         // FP32: the short-list (read), then the forced point as a one-entry list
+  Winner* winner;         // the selection's winner (read); FP64: replaced by the forced point
+  const double* probe;    // FP64: [B][2] the FFT-form grid value at the forced point
+  int32_t* idx;           // (m, j) the selection chose
+  double* p;              // its |<G_k, e_a>~|^2
+  double* margin;         // its margin
+  int32_t* flags;         // its flags; bit 4: FP32, the forced point was on the short-list
+};
+constexpr int kFlagForcedListed = 16;
 
 // Everything a kernel needs to apply step `step`'s remainder update (eq. (7))
 // and record the step (see afd_update.h).
@@ -293,6 +321,12 @@ hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* no
 // forced: per signal `fstride` int32 apart (0: the same point for every signal)
 hipError_t launch_force(const int32_t* forced, int fstride, int step, int N, CandList* cand, int batch,
                         hipStream_t s);
+// One workgroup per signal merges the radius kernel's per-workgroup records
+// (as the fused step tail does): FP64 into the winner, FP32 into the short-list.
+hipError_t launch_merge(bool fp64, const void* recs, const uint64_t* heads, const uint64_t* seconds, int nrec, int N,
+                        int logn, int recheck_k, float tau_band, unsigned int* flagword, CandList* cand, Winner* w,
+                        int batch, hipStream_t s);
+hipError_t launch_pick(const PickArgs& a, int batch, hipStream_t s);
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
                           double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s);
 hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, int batch, hipStream_t s,

@@ -213,6 +213,23 @@ void k_big_rows(BigParams p) {
     select_list<B::L2>(v, true, sc, fbase, uint32_t(B::N1), t, scratch, p.tau_band, ord,
                        reinterpret_cast<BlockList32*>(p.blocks) + rec, nullptr, nullptr, p.flagword);
   } else {
+    if (p.probe) {
+      // a replayed step: the grid value at the forced point j = j1 + N1 j2,
+      // scaled as the selection scales its best value (register q of thread
+      // t holds j2 = t + TPR2 bitrev(q))
+      const int pm = p.probe[0], pj = p.probe[1];
+      const int pj2 = pj >> B::L1;
+      if (m == pm && j1 == (pj & (B::N1 - 1)) && t == (pj2 & (B::TPR2 - 1))) {
+        const int u = pj2 / B::TPR2;
+#pragma unroll
+        for (int q = 0; q < B::E2; ++q) {
+          if (bitrev(q, ilog2c(B::E2)) == u) {
+            p.probe_out[0] = double(v[q].x * sc);
+            p.probe_out[1] = double(v[q].y * sc);
+          }
+        }
+      }
+    }
     select_best<B::L2, T>(v, true, sc, fbase, uint32_t(B::N1), t, reinterpret_cast<Best*>(scratch),
                           reinterpret_cast<BlockBest64*>(p.blocks) + rec);
   }

@@ -200,6 +200,23 @@ __device__ __forceinline__ unsigned int radius_slot(const RadiusParams& prm, int
     select_list<LOGN>(v, active, sc, fbase, 1u, t, scratch, prm.tau_band, ord, lists + slot, heads + slot,
                       seconds + slot, prm.flagword + b);
   } else {
+    if (prm.probe) {
+      // a replayed step: the grid value at the forced point, scaled exactly
+      // as the selection scales its best value (register p holds bin
+      // t + TPR bitrev(p))
+      const int32_t* pr = prm.probe + size_t(prm.probe_stride) * b;
+      const int pm = pr[0], pj = pr[1];
+      if (active && m == pm && t == (pj & (TPR - 1))) {
+        const int q = pj / TPR;
+#pragma unroll
+        for (int p = 0; p < E; ++p) {
+          if (bitrev(p, ilog2c(E)) == q) {
+            prm.probe_out[2 * b] = double(v[p].x * sc);
+            prm.probe_out[2 * b + 1] = double(v[p].y * sc);
+          }
+        }
+      }
+    }
     select_best<LOGN, T>(v, active, sc, fbase, 1u, t, reinterpret_cast<Best*>(scratch),
                          reinterpret_cast<BlockBest64*>(prm.out) + size_t(prm.nrec) * b + slot);
   }

@@ -8,6 +8,10 @@
 //   k_update    G_{k+1} = (G_k - c_k e_{a_k}) (1 - conj(a_k) z)/(z - a_k) (eq. (7))
 //               in double; the last workgroup sums E_k = (1/N) sum |G_{k+1}|^2
 //               and records the step's outputs
+//   k_merge     the radius kernel's per-workgroup records merged into the
+//               winner (FP64) or the short-list (FP32) in a launch of its own
+//   k_pick      a replayed step: the selection's own choice is recorded and
+//               the forced point takes its place
 #include "afd_update.h"
 
 namespace afd {
@@ -118,6 +122,65 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
   winner_from_partials(count, cand->flags, key, rk, partials, N, logn, nch, w, bb, wd);
 }
 
+// Same merge functions, workgroup size and record order as the fused step
+// tail, so the result is the one the tail reaches.
+__global__ __launch_bounds__(256) void k_merge(int fp64, const void* __restrict__ recs,
+                                               const uint64_t* __restrict__ heads,
+                                               const uint64_t* __restrict__ seconds, int nrec, int N, int logn,
+                                               int recheck_k, float tau_band, unsigned int* __restrict__ flagword,
+                                               CandList* __restrict__ cand, Winner* __restrict__ w) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
+  const int b = blockIdx.x;
+  if (fp64) {
+    merge64_tail<4>(reinterpret_cast<const BlockBest64*>(recs) + size_t(nrec) * b, nrec, N, logn, w + b, Sm);
+  } else {
+    select32_tail<4>(reinterpret_cast<const BlockList32*>(recs) + size_t(nrec) * b, heads + size_t(nrec) * b,
+                     seconds + size_t(nrec) * b, nrec, recheck_k, tau_band, flagword + b, cand + b, Sm, true);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_pick(PickArgs a) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int32_t* fp = a.forced + size_t(a.fstride) * b + 2 * a.step;
+  const uint32_t fm = uint32_t(fp[0]), fj = uint32_t(fp[1]);
+  const uint32_t ff = fm * uint32_t(a.N) + fj;
+  Winner* w = a.winner + b;
+  CandList* cand = a.cand + b;
+  const Winner own = *w;
+  // FP32: was the forced point among the re-checked candidates?
+  bool listed = false;
+  if (!a.fp64) {
+    const int count = min(max(cand->count, 0), kKMax);
+    for (int i = lane; i < count; i += 64) listed |= key_f(cand->keys[i]) == ff;
+  }
+  listed = __ballot(listed) != 0;
+  __syncthreads();  // every lane has read the short-list
+  if (lane != 0) return;
+  const size_t s = size_t(a.steps) * size_t(b) + size_t(a.step);
+  a.idx[2 * s] = own.m;
+  a.idx[2 * s + 1] = own.j;
+  a.p[s] = own.cx * own.cx + own.cy * own.cy;  // as the selection compared it
+  a.margin[s] = own.margin;
+  a.flags[s] = (own.flags & 7) | (listed ? kFlagForcedListed : 0);
+  if (a.fp64) {
+    Winner o = own;
+    o.m = int32_t(fm);
+    o.j = int32_t(fj);
+    o.cx = a.probe[2 * b];
+    o.cy = a.probe[2 * b + 1];
+    o.margin = __builtin_nan("");
+    o.kcount = 0;
+    o.fp32err = 0.0;
+    *w = o;
+  } else {
+    cand->count = 1;
+    cand->flags = kFlagForced | (own.flags & 7);
+    cand->pmax32 = 0.f;
+    cand->keys[0] = uint64_t(~ff);  // P = 0: the re-check supplies the value
+  }
+}
+
 __global__ __launch_bounds__(256) void k_update(double* __restrict__ g64, float* __restrict__ g32, UpdateArgs U) {
   __shared__ double wd[16];
   __shared__ int s_last;
@@ -165,6 +228,19 @@ hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* no
 hipError_t launch_force(const int32_t* forced, int fstride, int step, int N, CandList* cand, int batch,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_force, dim3(batch), dim3(64), 0, s, forced, fstride, step, N, cand);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(bool fp64, const void* recs, const uint64_t* heads, const uint64_t* seconds, int nrec, int N,
+                        int logn, int recheck_k, float tau_band, unsigned int* flagword, CandList* cand, Winner* w,
+                        int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge, dim3(batch), dim3(256), uint32_t(sizeof(MergeScratch)), s, fp64 ? 1 : 0, recs, heads,
+                     seconds, nrec, N, logn, recheck_k, tau_band, flagword, cand, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_pick(const PickArgs& a, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_pick, dim3(batch), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

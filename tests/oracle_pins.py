@@ -279,6 +279,38 @@ def pin_selection_rules(O):
     assert _rel(r.coef, d.coef) < 1e-15 and _rel(r.energy, d.energy) < 1e-15
 
 
+def pin_streamed_selection(O):
+    """The streamed grid (radius chunks, threads) selects exactly as the whole
+    grid: the same first maximiser, margin and grid value bit for bit, for any
+    chunk size, including exact ties split across chunks (a repeated radius
+    repeats its row: the first copy must win with margin 0) and the r = 0
+    ring tie; and decompose_streamed equals decompose."""
+    rng = _rng(41)
+    N = 128
+    g = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    for radii in (np.array([0.3, 0.5, 0.3, 0.5, 0.1]), np.array([0.0, 0.2, 0.0]), W.uniform_radii(13)):
+        V = O.grid_fft(g, radii)
+        (m, j), margin = O.select(V)
+        for chunk, workers in ((1, 1), (2, 3), (3, 1), (64, 1)):
+            (ms, js), mg, v, p1 = O.select_streamed(g, radii, chunk=chunk, workers=workers)
+            assert (ms, js) == (m, j) and mg == margin and v == V[m, j], (radii, chunk)
+            assert p1 == V[m, j].real ** 2 + V[m, j].imag ** 2
+    # repeated rows: the first copy wins and the tie leaves no margin
+    (m, j), margin, _, _ = O.select_streamed(g, np.array([0.3, 0.5, 0.3, 0.5]), chunk=1)
+    P = np.abs(O.grid_fft(g, np.array([0.3, 0.5]))) ** 2
+    assert m == int(np.argmax(P.max(axis=1))) and margin == 0.0
+    # a dominant mean: the r = 0 ring ties exactly; flat index 0 wins
+    (m, j), margin, _, _ = O.select_streamed(g * 0.01 + 5.0, np.array([0.0, 0.2, 0.0]), chunk=1)
+    assert (m, j) == (0, 0) and margin == 0.0
+    gc, radii, _ = W.config1()
+    a = O.decompose(gc[::2], radii[::3], 5)
+    b = O.decompose_streamed(gc[::2], radii[::3], 5, chunk=7, workers=2)
+    for k in ("index", "a", "coef", "energy", "margin", "remainder"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+    c = O.decompose_streamed(gc[::2], radii[::3], 5, forced=a.index)
+    assert np.array_equal(c.coef, a.coef) and np.array_equal(c.energy, a.energy)
+
+
 # ------------------------------------------------------------------ relative error (Sec. 4, eq. er)
 def pin_relative_errors(O):
     """delta_n from the partial sums equals E_n/E_0 from the remainders at every
@@ -330,6 +362,7 @@ ALL_PINS = [
     pin_invariances,
     pin_paper_tables,
     pin_selection_rules,
+    pin_streamed_selection,
     pin_relative_errors,
     pin_analytic_part,
 ]

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from tests.parity_tools import TOL, compare, to_numpy
+from tests.parity_tools import TOL, compare, compare_replay, to_numpy
 
 torch = pytest.importorskip("torch")
 from paper_1711_08604_amd import Plan  # noqa: E402
@@ -66,7 +66,7 @@ def test_batch_matches_alone_and_oracle(n, m, batch, steps, prec):
         for k in FIELDS:
             np.testing.assert_array_equal(one[k], alone[b][k], err_msg=f"signal {b} field {k}")
         compare(_Res(one), refs[b], TOL[prec], signal=g[b], radii=radii)
-        compare(_Res(_one(rr, b)), refs[b], TOL[prec], replay=True)
+        compare_replay(_Res(_one(rr, b)), refs[b], prec, radii=radii)
 
 
 def test_batch_first_a_zero():

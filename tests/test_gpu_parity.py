@@ -1,16 +1,18 @@
 """GPU path (libafd through its C ABI) against the FP64 oracle.
 
-Small and medium sizes: every step free-running (indices bit-exact while the
-oracle's lead exceeds 1e-6, then a validity check of the near-tie choice) and
-every step replayed with the oracle's indices.  Full-size workloads:
-the first steps against the oracle plus identities that hold at any size.
+Small and medium sizes, and the N = 16384, M = 1000 workload: every step
+free-running (indices bit-exact while the oracle's lead exceeds 1e-6, then a
+validity check of the near-tie choice) and every step replayed along the
+oracle's trajectory, with the whole path (forward DFT, radius transforms,
+selection, re-check) running on each replayed remainder and its own choice
+checked against the oracle's grid maximum.
 """
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
-from tests.parity_tools import TOL, compare, to_numpy
+from tests.parity_tools import TOL, compare, compare_replay, to_numpy
 
 torch = pytest.importorskip("torch")
 from paper_1711_08604_amd import AfdError, Plan  # noqa: E402
@@ -18,6 +20,12 @@ from paper_1711_08604_amd import AfdError, Plan  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
+
+
+def oracle_workers():
+    """Threads for the oracle's streamed grids: the host cores this process may use, at most 16."""
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def _dev(x):
@@ -48,7 +56,7 @@ def test_free_run_and_replay(n, m, steps, prec):
         torch.cuda.synchronize()
         compare(res, ref, TOL[prec], signal=g, radii=radii)
         rep = plan.replay(_dev(g), steps, ref.index.astype(np.int32))
-        compare(rep, ref, TOL[prec], replay=True)
+        compare_replay(rep, ref, prec, radii=radii)
         r = to_numpy(res)
         if prec == "fp32":
             assert np.all(r["recheck_count"] >= 1)
@@ -72,33 +80,38 @@ def test_config1_full(prec):
 _C2 = {}
 
 
-def _config2_ref(k):
-    if k not in _C2:
-        g, radii, _ = W.config2()
-        _C2[k] = (g, radii, O.decompose(g, radii, k))
-    return _C2[k]
+def _config2_oracle():
+    """The oracle's own 50-step trajectory on the N = 16384, M = 1000 workload
+    (the grid streamed by radius chunks over threads; equal to decompose())."""
+    if "ref" not in _C2:
+        g, radii, steps = W.config2()
+        ref = O.decompose_streamed(g, radii, steps, chunk=25, workers=oracle_workers())
+        _C2["ref"] = (g, radii, steps, ref)
+    return _C2["ref"]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_config2_full_size(prec):
-    """N = 16384, M = 1000 (the benchmark's launch configuration): the first
-    four steps replayed against the oracle, the free-running first choice
-    checked as a valid (near-)maximum, and all 50 free-running steps checked
-    against the aliasing-corrected energy identity."""
-    g, radii, ref = _config2_ref(4)
+def test_config2_every_step(prec):
+    """N = 16384, M = 1000, 50 steps (the benchmark's launch configuration; in
+    double precision the radius kernel takes its slots from the work queue).
+    Every step is replayed along the oracle's trajectory with the whole path
+    running: the path's own choice on each replayed remainder against the
+    oracle's grid maximum, the coefficient at the forced point against the
+    oracle's.  The free-running decomposition is compared until its first
+    near-tie, and all 50 of its steps satisfy the aliasing-corrected energy
+    identity."""
+    g, radii, steps, ref = _config2_oracle()
+    print(f"case config2 N=16384 M=1000 steps={steps} {prec}; oracle margins "
+          f"min {np.min(ref.margin):.2e} median {np.median(ref.margin):.2e}", flush=True)
     with Plan(16384, radii, precision=prec) as plan:
-        rep = plan.replay(_dev(g), 4, ref.index.astype(np.int32))
-        compare(rep, ref, TOL[prec], replay=True)
-        res = plan.decompose(_dev(g), 50)
-        compare(res, O.decompose(g, radii, 0), TOL[prec])  # E_0
+        rep = plan.replay(_dev(g), steps, ref.index.astype(np.int32))
+        report = compare_replay(rep, ref, prec, radii=radii)
+        print("replay:", report, flush=True)
+        assert report["picks_compared"] >= steps // 2
+        res = plan.decompose(_dev(g), steps)
+        upto, rr = compare(res, ref, TOL[prec], signal=g, radii=radii)
+        print("free run:", rr, flush=True)
         r = to_numpy(res)
-        # first step: the choice must be within 2e-6 of the oracle's maximum
-        V = O.grid_fft(g, radii)
-        P = np.abs(V) ** 2
-        m0, j0 = r["index"][0]
-        assert P[m0, j0] >= P.max() * (1 - 2e-6)
-        # the coefficient at the chosen point is the oracle's grid value there
-        assert abs(r["coef"][0] - V[m0, j0]) <= TOL[prec] * max(abs(V[m0, j0]), np.sqrt(ref.energy[0]))
         # energy identity E_k = E_{k-1} - |c_k|^2 (1 - 3 rho)/(1 - rho), rho = |a_k|^N
         rho = np.abs(r["a"]) ** 16384
         pred = r["energy"][:-1] - np.abs(r["coef"]) ** 2 * (1 - 3 * rho) / (1 - rho)
@@ -110,6 +123,34 @@ def test_config2_full_size(prec):
             # the re-check band (4e-6 by default) must cover twice the measured FP32 error
             print("max FP32 error of |.|^2:", float(np.max(r["fp32_error"])), flush=True)
             assert np.max(r["fp32_error"]) * 2 < 4e-6
+        else:
+            # replayed with its own choices, the decomposition comes back bit for bit
+            own = to_numpy(plan.replay(_dev(g), steps, r["index"].astype(np.int32)))
+            for k in ("index", "a", "coef", "energy", "remainder"):
+                assert np.array_equal(own[k], r[k]), k
+            assert np.array_equal(own["pick_index"], r["index"])
+            assert np.array_equal(own["pick_margin"], r["margin"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [1 << 14, 1 << 15, 1 << 20], ids=lambda v: f"N={v}")
+def test_zero_radius_ring_tie(n, prec):
+    """radii = {0, 0.2, 0.4} and a dominant mean: the r = 0 ring (every one
+    of its N values the same number) is the maximum of step 1, and the first
+    maximum of the scan, flat index 0, must be chosen: on the LDS-resident
+    radius kernel (2^14), the two-pass path (2^15) and the row pass (2^20)."""
+    g = _signal(n, 1)
+    g = 0.01 * (g - g.mean()) + 5.0
+    radii = np.array([0.0, 0.2, 0.4])
+    ref = O.decompose(g, radii, 2)
+    assert tuple(ref.index[0]) == (0, 0) and ref.margin[0] == 0.0
+    with Plan(n, radii, precision=prec) as plan:
+        res = plan.decompose(_dev(g), 2)
+        r = to_numpy(res)
+        assert tuple(r["index"][0]) == (0, 0), r["index"][0]
+        compare(res, ref, TOL[prec], signal=g, radii=radii)
+        rep = to_numpy(plan.replay(_dev(g), 2, ref.index.astype(np.int32)))
+        assert tuple(rep["pick_index"][0]) == (0, 0), rep["pick_index"][0]
 
 
 def test_paper_case1_first_a_zero():
