@@ -2,27 +2,29 @@
 """Benchmark of the FFT-based Core-AFD loop on one MI355X.
 
 One benchmark step = one complete decomposition (afd_decompose) of the
-workload below: 50 AFD steps, each a forward DFT of the remainder, the fused
-weighted inverse DFT / |.|^2 / selection over the 1000 x 16384 polar grid, the
+workload: per AFD step the forward DFT of the remainder, the weighted
+inverse DFT / |.|^2 / selection over the whole M x N polar grid, the
 selection merge (FP32 mode: short-list + FP64 direct-rule recheck), the
 Blaschke update and the energy.  Inputs are resident in HBM before the timed
 region; outputs stay on the device.
 
-Workload (default): single signal, N = 16384 samples, M = 1000 radii uniform
-in [0, 0.999], 50 steps; G = 40 normalised Szego kernels with poles
-|b| <= 0.98 and CN(0,1) weights plus CN noise at 30 dB SNR (seeded,
-synthetic).  `--workload chirp1m` times the large decomposition instead:
-N = 2^20, M = 2000, 100 steps of the analytic part of a chirp + 3 tones +
-white noise at 20 dB, whose radius transforms run beyond the LDS (one row pass
-for short spectra, two passes through HBM for the longest).
+Workload (default, `chirp1m`): the large single decomposition, N = 2^20,
+M = 2000 radii uniform in [0, 0.999], 100 AFD steps of the analytic part of a
+linear chirp + 3 Gaussian-windowed tones + white noise at 20 dB (seeded,
+synthetic); its radius transforms run beyond the LDS (one row pass for short
+spectra, two passes through HBM for the longest).  `value` is the FP64
+path; the FP32 + double re-check path is under "fp32", and the N = 16384,
+M = 1000, 50-step workload (40 Szego kernels + noise at 30 dB; LDS-resident
+transforms) under "single16k".
+`--workload single16k` times that workload alone.
 `--workload batch512` times the uniform batch: 512 signals of N = 4096
 (8..32 kernels, |b| <= 0.95), M = 512, 30 steps, decomposed together.
 `--workload small1k` times the small latency-bound case: N = 1024, M = 100
 radii m/100, 10 steps, FP64 only, 200 solves for p50/p99.
 `--workload serve` runs the served stream: requests with N log-uniform over
-2^10..2^16, M = N/8, 5..100 steps, signals as in the default workload, through
-the continuous-batching server, first all at once (throughput), then with
-Poisson arrivals at 0.7x that request rate (p50/p99 latency).
+2^10..2^16, M = N/8, 5..100 steps, signals as in the N = 16384 workload,
+through the continuous-batching server, first all at once (throughput), then
+with Poisson arrivals at 0.7x that request rate (p50/p99 latency).
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 """
@@ -42,6 +44,7 @@ if ROOT not in sys.path:
 
 METRIC = "grid evals/s (M·N·steps/s) FP32+recheck vs FP64; p50/p99 solve latency"
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector peaks (fp32 figure assumes packed math)
+HBM_PEAK_BPS = 8.0e12  # MI355X HBM3E
 
 
 def log(msg):
@@ -81,8 +84,9 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """Bytes per launch for `kernel` if measured on the current sources, else None."""
+def measured_counters(kernel: str):
+    """The counter record of `kernel` (bytes and VALU instructions per launch)
+    if it was measured on the current sources, else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -90,12 +94,18 @@ def measured_traffic(kernel: str):
         return None
     if t.get("source_sha256") != source_hash():
         return None
-    k = t.get("kernels", {}).get(kernel)
+    return t.get("kernels", {}).get(kernel)
+
+
+def measured_traffic(kernel: str):
+    """Bytes per launch for `kernel` if measured on the current sources, else None."""
+    k = measured_counters(kernel)
     return None if k is None else float(k["bytes_per_launch"])
 
 
-# bytes of the two-pass intermediate per grid value (written once, read once)
-TWO_PASS_BYTES = {"fp32": 16, "fp64": 32}
+# VALU issue capacity: each CU issues one wave64 vector instruction per clock
+# (four SIMD16 units, four clocks per wave64 instruction)
+CUS, CLOCK_HZ = 256, 2.4e9
 
 
 def two_pass_radii(radii, n: int, prec: str) -> int:
@@ -122,17 +132,37 @@ def two_pass_radii(radii, n: int, prec: str) -> int:
 TIMING_EVERY = 7
 
 
-def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
+def _kernel_name(prec, n):
+    tname = "double" if prec == "fp64" else "float"
+    k = int(math.log2(n))
+    return f"k_radius<{tname},{k}>" if n <= (1 << 14) else f"k_big_rows<{tname},{k}>"
+
+
+def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch, kernel_timing=True):
+    """Time `steps` whole decompositions after `warmup` untimed ones; the
+    dominant kernel (the radius kernel, or at N > 2^14 the row pass of the
+    radius transforms, one launch per chunk of radii) is timed live on every
+    TIMING_EVERY-th launch with events its dispatch stamps."""
     from paper_1711_08604_amd import Plan
     batch = int(sig.shape[0]) if sig.dim() == 2 else 1
     n = int(sig.numel()) // batch
     m = len(radii)
+    big = n > (1 << 14)
+    kind = "rows" if big else "radius"
     stream = torch.cuda.current_stream().cuda_stream
     plan = Plan(n, radii, precision=prec, stream=stream, batch=batch)
+    per_solve = 0
+    if kernel_timing:
+        # launches of the timed kernel per decomposition (every one stamped, untimed)
+        plan.set_timing(kind, 1)
+        plan.decompose(sig, afd_steps)
+        per_solve = plan.kernel_time()[1]
+        plan.set_timing(kind, False)
     for _ in range(warmup):
         plan.decompose(sig, afd_steps)
     torch.cuda.synchronize()
-    plan.set_timing("radius", TIMING_EVERY)
+    if kernel_timing:
+        plan.set_timing(kind, TIMING_EVERY)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -144,40 +174,45 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     wall = time.perf_counter() - t0
     k_ms, k_launches = plan.kernel_time()
     blocks, threads, lds = plan.radius_launch()
-    plan.set_timing("radius", False)
+    plan.set_timing(kind, False)
     plan.close()
     evals = float(m) * n * afd_steps * steps * batch
+    if not kernel_timing:  # (counter runs under a profiler: no stamped dispatches)
+        return {"value": evals / wall, "ms_per_step": wall / steps * 1e3, "p50_ms": percentile(lat, 0.5) * 1e3,
+                "p99_ms": percentile(lat, 0.99) * 1e3, "roofline": {"kernel": _kernel_name(prec, n), "frac": float("nan"),
+                                                                     "avg_launch_us": float("nan")}}
     avg_kernel_s = (k_ms / 1e3) / max(k_launches, 1)
-    flop_launch = float(m) * n * flops_per_eval(n) * batch
+    # algorithmic work of one launch: the step's grid values share the launches
+    # of the step (one radius-kernel launch, or one row pass per chunk of radii)
+    launches_per_step = per_solve / afd_steps
+    flop_launch = float(m) * n * flops_per_eval(n) * batch / launches_per_step
     achieved = flop_launch / avg_kernel_s / 1e12
     peak = PEAK_TFLOPS[prec]
-    tname = "double" if prec == "fp64" else "float"
-    if n <= (1 << 14):
-        kname = f"k_radius<{tname},{int(math.log2(n))}>"
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": measured_traffic(kname), "traffic_unit": "bytes/launch",
-                "kernel": kname,
-                "avg_launch_us": avg_kernel_s * 1e6, "launches": k_launches,
-                "flop_per_launch": flop_launch, "grid": [blocks, threads, lds]}
+    kname = _kernel_name(prec, n)
+    traffic = measured_traffic(kname)
+    cnt = measured_counters(kname)
+    valu = None if cnt is None or "valu_insts_per_launch" not in cnt else float(cnt["valu_insts_per_launch"])
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic, "traffic_unit": "bytes/launch", "kernel": kname,
+            "avg_launch_us": avg_kernel_s * 1e6, "launches_sampled": k_launches,
+            "launches_per_afd_step": launches_per_step, "flop_per_launch": flop_launch,
+            "hbm_gbs": None if traffic is None else traffic / avg_kernel_s / 1e9,
+            "hbm_frac": None if traffic is None else traffic / avg_kernel_s / HBM_PEAK_BPS,
+            "valu_insts_per_launch": valu,
+            "valu_busy": None if valu is None else valu / (CUS * CLOCK_HZ * avg_kernel_s)}
+    if big:
+        roof["two_pass_radii"] = two_pass_radii(radii, n, prec)
+        roof["row_grid"] = [blocks, threads, lds]
     else:
-        # one timed unit = the column and row passes over all chunks of one AFD
-        # step; only the radii with long spectra move through the intermediate,
-        # the rest are formed in the row pass from the spectrum (ALU-bound)
-        long_r = two_pass_radii(radii, n, prec)
-        inter = float(long_r) * n * TWO_PASS_BYTES[prec]
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": f"k_big_rows<{tname},{int(math.log2(n))}> + k_big_cols (all radius chunks of a step)",
-                "avg_launch_us": avg_kernel_s * 1e6, "launches": k_launches,
-                "flop_per_launch": flop_launch, "two_pass_radii": long_r,
-                "intermediate_bytes_per_launch": inter,
-                "intermediate_gbs": inter / avg_kernel_s / 1e9,
-                "row_grid": [blocks, threads, lds]}
+        roof["grid"] = [blocks, threads, lds]
+    lat_sorted = sorted(lat)
     out = {
         "value": evals / wall,
         "ms_per_step": wall / steps * 1e3,
         "p50_ms": percentile(lat, 0.5) * 1e3,
         "p99_ms": percentile(lat, 0.99) * 1e3,
+        "latency_ms": {"min": lat_sorted[0] * 1e3, "median": percentile(lat, 0.5) * 1e3,
+                       "max": lat_sorted[-1] * 1e3},
         "roofline": roof,
     }
     if prec == "fp32":
@@ -187,34 +222,56 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch):
     return out
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, radii, steps_sample, total_steps):
+    """The FP64 oracle as it stands, timed on this host on a bounded sample of
+    the same workload: an all-cores leg (the oracle's grid streamed by radius
+    chunks over one thread per usable core) and a one-worker leg."""
     import numpy as np
 
     import oracle as O
+    cores = len(os.sched_getaffinity(0))
     batched = g.ndim == 2
     if batched:
         g = g[0]  # the oracle decomposes one signal at a time
     n = g.shape[0]
+    base = {"unit": "grid evals/s", "kind": "oracle", "cpu_model": _cpu_model(), "affinity_cores": cores,
+            "numpy": np.__version__}
+    if n <= (1 << 14):
+        t0 = time.perf_counter()
+        O.decompose(g, radii, steps_sample)
+        dt1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.decompose_streamed(g, radii, steps_sample, chunk=max(1, len(radii) // (4 * cores)), workers=cores)
+        dta = time.perf_counter() - t0
+        evals = float(len(radii)) * n * steps_sample
+        what = f"first {steps_sample} of the {total_steps} AFD steps" + (" of signal 0 of the batch" if batched else "")
+        one = {"value": evals / dt1, "seconds": dt1, "sample": f"decompose(), one thread, {what}"}
+        return {**base, "value": evals / dta, "cores": cores, "seconds": dta,
+                "sample": f"decompose_streamed(), {cores} threads, {what}", "one_worker": one}
+    # N > 2^14: the whole grid of step 1 on every core, a twentieth of its radii on one
     t0 = time.perf_counter()
-    if batched:
-        O.decompose(g, radii, steps_sample)
-        evals = len(radii) * n * steps_sample
-        what = f"first {steps_sample} of the {total_steps} AFD steps of signal 0 of the batch"
-    elif n <= (1 << 14):
-        O.decompose(g, radii, steps_sample)
-        evals = len(radii) * n * steps_sample
-        what = f"first {steps_sample} of the {total_steps} AFD steps of the same signal"
-    else:
-        # one step's grid over a subset of the radii (the full grid of one step
-        # takes minutes and tens of GB on the host)
-        sub = radii[:: max(1, len(radii) // 40)]
-        O.select(O.grid_fft(g, sub))
-        evals = len(sub) * n
-        what = f"grid values and selection of step 1 over {len(sub)} of the {len(radii)} radii"
-    dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": "grid evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 FFT-form oracle (numpy pocketfft, single thread), {what}, {dt:.1f} s",
-            "seconds": dt, "numpy": np.__version__}
+    O.decompose_streamed(g, radii, 1, chunk=4, workers=cores)
+    dta = time.perf_counter() - t0
+    sub = radii[::20]
+    t0 = time.perf_counter()
+    O.decompose_streamed(g, sub, 1, chunk=4, workers=1)
+    dt1 = time.perf_counter() - t0
+    one = {"value": float(len(sub)) * n / dt1, "seconds": dt1,
+           "sample": f"grid, selection and update of AFD step 1 over {len(sub)} of the {len(radii)} radii, one thread"}
+    return {**base, "value": float(len(radii)) * n / dta, "cores": cores, "seconds": dta,
+            "sample": f"grid ({len(radii)} x {n}), selection and update of AFD step 1 of {total_steps}, "
+                      f"{cores} threads", "one_worker": one}
 
 
 def run_serve(args, np, torch, W):
@@ -290,17 +347,61 @@ def run_serve(args, np, torch, W):
     }
 
 
+WORKLOADS = {
+    "chirp1m": ("large single decomposition: N=2^20 samples, M=2000 radii uniform in [0,0.999], 100 AFD steps; "
+                "analytic part of a linear chirp (0.01->0.4 cycles/sample) + 3 Gaussian-windowed tones + white "
+                "noise at 20 dB", 5, 1),
+    "single16k": ("single-signal Core-AFD: N=16384 samples, M=1000 radii uniform in [0,0.999], 50 AFD steps; 40 "
+                  "normalised Szego kernels |b|<=0.98 + CN noise at 30 dB", 30, 3),
+    "batch512": ("uniform batch: 512 signals of N=4096 samples (8..32 normalised Szego kernels, |b|<=0.95), M=512 "
+                 "radii uniform in [0,0.999], 30 AFD steps each, decomposed together", 5, 1),
+    "small1k": ("small single decomposition: N=1024 samples (5 normalised Szego kernels, |b|<=0.9), M=100 radii "
+                "m/100, 10 AFD steps; launch-latency bound", 200, 10),
+}
+
+
+def _workload(name, W):
+    if name == "batch512":
+        return W.config3_batch()
+    if name == "small1k":
+        return W.config1()
+    if name == "chirp1m":
+        return W.config5()
+    return W.config2()
+
+
+def _time_workload(name, W, torch, steps, warmup, only=None, kernel_timing=True):
+    g, radii, afd_steps = _workload(name, W)
+    n, m = g.shape[-1], len(radii)
+    log(f"bench: {name}: N={n} M={m} afd_steps={afd_steps} solves={steps} warmup={warmup}")
+    sig = torch.from_numpy(g).to("cuda:0")
+    torch.cuda.synchronize()
+    res = {}
+    for prec in ("fp64", "fp32"):
+        if only and prec != only:
+            continue
+        res[prec] = run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch, kernel_timing)
+        log(f"bench: {name} {prec} {res[prec]['value']:.3e} evals/s, {res[prec]['ms_per_step']:.3f} ms/solve, "
+            f"{res[prec]['roofline']['kernel']} {res[prec]['roofline']['avg_launch_us']:.1f} us per launch "
+            f"({res[prec]['roofline']['frac']:.3f} of peak)")
+    del sig
+    return g, radii, afd_steps, res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["single16k", "chirp1m", "batch512", "small1k", "serve"],
-                    default="single16k")
+    ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "serve"],
+                    default="chirp1m")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests in the stream")
-    ap.add_argument("--steps", type=int, default=None, help="timed decompositions (30; chirp1m: 3)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed decompositions (3; chirp1m: 1)")
+    ap.add_argument("--steps", type=int, default=None, help="timed decompositions (chirp1m: 5)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed decompositions (chirp1m: 1)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=5, help="AFD steps of the oracle sample")
+    ap.add_argument("--no-extra", action="store_true", help="chirp1m: skip the N=16384 workload's extra key")
+    ap.add_argument("--cpu-steps", type=int, default=5, help="AFD steps of the oracle sample (N <= 2^14)")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="no event-stamped dispatches (for hardware-counter runs); no roofline figures")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size kernel for "
                          "scaling HBM byte counters)")
@@ -320,33 +421,11 @@ def main():
         print(json.dumps(run_serve(args, np, torch, W)), flush=True)
         return
 
-    if args.workload == "batch512":
-        g, radii, afd_steps = W.config3_batch()
-        wl_text = ("uniform batch: 512 signals of N=4096 samples (8..32 normalised Szego kernels, |b|<=0.95), "
-                   "M=512 radii uniform in [0,0.999], 30 AFD steps each, decomposed together")
-        dsteps, dwarm = 5, 1
-    elif args.workload == "small1k":
-        g, radii, afd_steps = W.config1()
-        wl_text = ("small single decomposition: N=1024 samples (5 normalised Szego kernels, |b|<=0.9), "
-                   "M=100 radii m/100, 10 AFD steps, FP64; launch-latency bound")
-        dsteps, dwarm = 200, 10
+    wl_text, dsteps, dwarm = WORKLOADS[args.workload]
+    if args.workload == "small1k":
         args.only = args.only or "fp64"
-    elif args.workload == "chirp1m":
-        g, radii, afd_steps = W.config5()
-        wl_text = ("large single decomposition: N=2^20 samples, M=2000 radii uniform in [0,0.999], 100 AFD "
-                   "steps; analytic part of a linear chirp + 3 Gaussian-windowed tones + white noise at 20 dB")
-        dsteps, dwarm = 3, 1
-    else:
-        g, radii, afd_steps = W.config2()
-        wl_text = ("single-signal Core-AFD: N=16384 samples, M=1000 radii uniform in [0,0.999], "
-                   "50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB")
-        dsteps, dwarm = 30, 3
     args.steps = dsteps if args.steps is None else args.steps
     args.warmup = dwarm if args.warmup is None else args.warmup
-    n, m = g.shape[-1], len(radii)
-    log(f"bench: N={n} M={m} afd_steps={afd_steps} solves={args.steps} warmup={args.warmup}")
-    sig = torch.from_numpy(g).to("cuda:0")
-    torch.cuda.synchronize()
     if args.copy_calibration_mib:
         n_el = args.copy_calibration_mib * (1 << 20) // 4
         src = torch.ones(n_el, dtype=torch.float32, device="cuda:0")
@@ -355,14 +434,13 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: copy calibration {args.copy_calibration_mib} MiB read + {args.copy_calibration_mib} MiB written")
         del src, dst
-    res = {}
-    for prec in ("fp32", "fp64"):
-        if args.only and prec != args.only:
-            continue
-        res[prec] = run_gpu(prec, sig, radii, afd_steps, args.steps, args.warmup, torch)
-        log(f"bench: {prec} {res[prec]['value']:.3e} evals/s, {res[prec]['ms_per_step']:.3f} ms/solve, "
-            f"radius kernel(s) {res[prec]['roofline']['avg_launch_us']:.1f} us per AFD step")
-    prim = res.get("fp32") or res.get("fp64")
+    kt = not args.no_kernel_timing
+    g, radii, afd_steps, res = _time_workload(args.workload, W, torch, args.steps, args.warmup, args.only, kt)
+    n, m = g.shape[-1], len(radii)
+    # the FP64 path is the primary figure (the paper computes in double); FP32 +
+    # double re-check sits under its own key
+    prim_key = "fp64" if "fp64" in res else "fp32"
+    prim = res[prim_key]
     line = {
         "metric": METRIC,
         "value": prim["value"],
@@ -374,24 +452,32 @@ def main():
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f32" if "fp32" in res else "f64",
+        "dtype": "f64" if prim_key == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": wl_text, "N": n, "M": m, "afd_steps": afd_steps,
                    "batch": int(g.shape[0]) if g.ndim == 2 else 1,
-                   "mode": "FP32 bulk + FP64 short-list recheck" if "fp32" in res else "FP64"},
+                   "mode": "FP64" if prim_key == "fp64" else "FP32 bulk + FP64 short-list recheck"},
         "p50_ms": prim["p50_ms"],
         "p99_ms": prim["p99_ms"],
+        "latency_ms": prim.get("latency_ms"),
         "roofline": prim["roofline"],
     }
-    if "fp32_error_max" in prim:
-        line["fp32_error_max"] = prim["fp32_error_max"]
-        line["recheck_count_mean"] = prim["recheck_count_mean"]
-    if "fp32" in res and "fp64" in res:
-        line["fp64"] = {k: res["fp64"][k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
+    if prim_key == "fp64" and "fp32" in res:
+        f = res["fp32"]
+        line["fp32"] = {k: f[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "latency_ms", "roofline",
+                                          "fp32_error_max", "recheck_count_mean") if k in f}
+        line["fp32"]["mode"] = "FP32 bulk + FP64 short-list recheck"
+    if args.workload == "chirp1m" and not args.no_extra:
+        # the N = 16384, M = 1000 workload: a second, VALU/LDS-bound regime
+        _, _, _, r2 = _time_workload("single16k", W, torch, max(args.steps, 10), args.warmup, args.only, kt)
+        line["single16k"] = {"workload": WORKLOADS["single16k"][0],
+                             **{p: {k: v[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
+                                for p, v in r2.items()}}
     if not args.no_cpu:
-        log(f"bench: CPU oracle baseline, {args.cpu_steps} AFD steps ...")
+        log("bench: CPU oracle baseline ...")
         line["cpu_baseline"] = cpu_baseline(g, radii, args.cpu_steps, afd_steps)
-        log(f"bench: oracle {line['cpu_baseline']['value']:.3e} evals/s")
+        log(f"bench: oracle {line['cpu_baseline']['value']:.3e} evals/s on {line['cpu_baseline']['cores']} cores, "
+            f"{line['cpu_baseline']['one_worker']['value']:.3e} on one")
     print(json.dumps(line), flush=True)
 
 

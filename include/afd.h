@@ -196,7 +196,8 @@ afd_status afd_analytic(afd_plan plan, const double* x, double* g);
    `kernel` stamp on the plan's stream ("radius": the fused weighted
    inverse-DFT / |.|^2 / selection kernel, or both passes of a step at
    N > 2^14; "fft": the forward DFT; "update": the remainder update, which
-   for 2^10 <= N <= 2^14 is the fused step tail).  enable = n >= 1 starts
+   for 2^10 <= N <= 2^14 is the fused step tail; "rows": N > 2^14, each row
+   pass launch of the radius transforms, one per chunk of radii).  enable = n >= 1 starts
    accumulating (and clears the totals) over every n-th launch of the class
    (1: every launch; a stamped dispatch costs a few microseconds, so a
    benchmark samples); 0 stops.  Errors: AFD_E_INVALID for an unknown class

@@ -38,7 +38,7 @@ int ilog2_exact(int64_t n) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3 };
+enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3, kTimeRows = 4 };
 
 // Device arena layout for one plan.
 struct Layout {
@@ -788,8 +788,10 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
         for (int m0 = 0; m0 < c.M; m0 += c.chunk) {
           bp.m0 = m0;
           const bool first = m0 == 0, last = m0 + c.chunk >= c.M;
+          hipEvent_t r0, r1;
+          HIPCHK(tm.pair(kTimeRows, &r0, &r1), "event");
           HIPCHK(launch_big(c.logn, c.fp64, bp, c.M - m0 < c.chunk ? c.M - m0 : c.chunk, s, first ? e0 : nullptr,
-                            last ? e1 : nullptr),
+                            last ? e1 : nullptr, r0, r1),
                  "k_big");
         }
       } else {
@@ -1077,6 +1079,7 @@ afd_status afd_plan_set_timing(afd_plan plan, const char* kernel, int32_t enable
   if (std::strcmp(kernel, "radius") == 0) kind = kTimeRadius;
   else if (std::strcmp(kernel, "fft") == 0) kind = kTimeFft;
   else if (std::strcmp(kernel, "update") == 0) kind = kTimeUpdate;
+  else if (std::strcmp(kernel, "rows") == 0) kind = kTimeRows;
   else return fail(AFD_E_INVALID, "unknown kernel class");
   if (enable < 0) return fail(AFD_E_INVALID, "enable must be >= 0");
   plan->time_kind = enable ? kind : kTimeNone;

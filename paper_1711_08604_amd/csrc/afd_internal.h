@@ -142,9 +142,10 @@ struct BigGeom {
 BigGeom big_geom(int logn, bool fp64);
 hipError_t setup_big_attributes();
 // One chunk of `nr` radii starting at p.m0: the column pass, then the row
-// pass with the selection.
+// pass with the selection.  e0 stamps the column pass's start, e1 the row
+// pass's end; r0 / r1 stamp the row pass alone.
 hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s, hipEvent_t e0 = nullptr,
-                      hipEvent_t e1 = nullptr);
+                      hipEvent_t e1 = nullptr, hipEvent_t r0 = nullptr, hipEvent_t r1 = nullptr);
 
 // Step outputs written by the last workgroup of k_update / k_prepare.
 struct RecordArgs {

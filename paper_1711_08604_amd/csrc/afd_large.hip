@@ -298,22 +298,24 @@ hipError_t setup_big_attributes() {
 }
 
 template <typename T, int LOGN>
-static hipError_t launch_big_t(const BigParams& p, int nr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static hipError_t launch_big_t(const BigParams& p, int nr, hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipEvent_t r0,
+                               hipEvent_t r1) {
   using B = Big<T, LOGN>;
   if (nr < 1 || p.m0 < 0 || p.m0 + nr > p.M) return hipErrorInvalidValue;
   launch_ev(k_big_cols<T, LOGN>, dim3(B::N2 / B::CA, nr), dim3(B::THR_A), uint32_t(B::lds_a), s, e0, nullptr, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  launch_ev(k_big_rows<T, LOGN, sizeof(T) == 4>, dim3(B::G, nr), dim3(B::THR_B), uint32_t(B::lds_b), s, nullptr, e1,
-            p);
+  launch_ev(k_big_rows<T, LOGN, sizeof(T) == 4>, dim3(B::G, nr), dim3(B::THR_B), uint32_t(B::lds_b), s, r0,
+            r1 ? r1 : e1, p);
   return hipGetLastError();
 }
 
-hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                      hipEvent_t r0, hipEvent_t r1) {
   switch (logn) {
 #define X(L) \
   case L:    \
-    return fp64 ? launch_big_t<double, L>(p, nr, s, e0, e1) : launch_big_t<float, L>(p, nr, s, e0, e1);
+    return fp64 ? launch_big_t<double, L>(p, nr, s, e0, e1, r0, r1) : launch_big_t<float, L>(p, nr, s, e0, e1, r0, r1);
     AFD_BIG_LOGN_CASES(X)
 #undef X
     default:

@@ -77,10 +77,12 @@ __device__ __forceinline__ void deep_inputs(Cx<T> (&v)[E], int t, int L, const C
 // Record slot `slot` of signal b: one radius (rpb = 1, the radii in the order
 // of decreasing significant spectrum length, so the longest transforms come
 // first; the radius and its length in one load) or rpb consecutive radii.
-template <typename T, int LOGN, bool LIST>
 // With a work queue, thread 0 claims the next slot after the transform and
 // the claim's round trip overlaps the selection; the returned ticket is
-// meaningful in thread 0 only.
+// meaningful in thread 0 only.  PROBE (double precision, replay): the grid
+// value at the forced point is also stored; it is a separate instantiation
+// so that the probe's code does not weigh on the decomposition's.
+template <typename T, int LOGN, bool LIST, bool PROBE>
 __device__ __forceinline__ unsigned int radius_slot(const RadiusParams& prm, int slot, int b, unsigned char* smem) {
   constexpr int E = pickE<T, LOGN>();
   constexpr bool SPLIT = pickSplit<T, LOGN>();
@@ -200,7 +202,7 @@ __device__ __forceinline__ unsigned int radius_slot(const RadiusParams& prm, int
     select_list<LOGN>(v, active, sc, fbase, 1u, t, scratch, prm.tau_band, ord, lists + slot, heads + slot,
                       seconds + slot, prm.flagword + b);
   } else {
-    if (prm.probe) {
+    if constexpr (PROBE) {
       // a replayed step: the grid value at the forced point, scaled exactly
       // as the selection scales its best value (register p holds bin
       // t + TPR bitrev(p))
@@ -231,7 +233,7 @@ __device__ __forceinline__ unsigned int radius_slot(const RadiusParams& prm, int
 // not depend on the workgroup that
 // computes it.  Every workgroup leaves once the queue is exhausted; none
 // waits on another.
-template <typename T, int LOGN, bool LIST>
+template <typename T, int LOGN, bool LIST, bool PROBE = false>
 __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_waves_per_eu(
     radius_min_waves<T, LOGN>()))) void k_radius(RadiusParams prm) {
   constexpr int N = 1 << LOGN;
@@ -246,7 +248,7 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
     // back past the last slot
     int slot = int(blockIdx.x);
     while (slot < prm.nrec) {  // uniform
-      const unsigned int ticket = radius_slot<T, LOGN, LIST>(prm, slot, b, smem);
+      const unsigned int ticket = radius_slot<T, LOGN, LIST, PROBE>(prm, slot, b, smem);
       if (!prm.queue) break;
       __syncthreads();  // every thread is done with the LDS and with s_next
       if (threadIdx.x == 0) s_next = int(gridDim.x) + int(ticket - prm.qbase);
@@ -255,7 +257,7 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
     }
     if (prm.queue) return;  // the step tail merges the records
   } else {
-    radius_slot<T, LOGN, LIST>(prm, int(blockIdx.x), b, smem);
+    radius_slot<T, LOGN, LIST, PROBE>(prm, int(blockIdx.x), b, smem);
   }
   if (!prm.tail) return;  // the step tail merges the records
   if (!last_arrival(prm.counter + b, gridDim.x, &s_last)) return;
@@ -347,6 +349,8 @@ hipError_t setup_radius_attributes() {
   if (e == hipSuccess)                                                                        \
     e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_radius<double, L, false>));                 \
   if (e == hipSuccess)                                                                        \
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_radius<double, L, false, true>));           \
+  if (e == hipSuccess)                                                                        \
     e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_radius<float, L, true>));
   AFD_LDS_LOGN_CASES(X)
 #undef X
@@ -361,7 +365,10 @@ hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks,
     if (fp64) {                                                                              \
       constexpr int thr = radius_threads<double, L>();                                       \
       const size_t lds = radius_lds<double, L>(p.rpb);                                       \
-      launch_ev(k_radius<double, L, false>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, p); \
+      if (p.probe)                                                                           \
+        launch_ev(k_radius<double, L, false, true>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, p); \
+      else                                                                                   \
+        launch_ev(k_radius<double, L, false>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, p); \
     } else {                                                                                 \
       constexpr int thr = radius_threads<float, L>();                                        \
       const size_t lds = radius_lds<float, L>(p.rpb);                                        \
