@@ -131,6 +131,24 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
    the loop continues. */
 afd_status afd_decompose(afd_plan plan, const double* signal, int32_t steps, afd_result* out);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+   tight serving loops, harnesses that forbid allocation): afd_decompose
+   without any allocation in the call.  afd_decompose stages its results in
+   device memory the plan allocates on the first call (and again when `steps`
+   grows); this entry point stages them in a static device array of 512 KiB
+   instead, one per device, held until the process ends (the plan's workspace
+   was allocated by afd_plan_create).  Limit: the staging takes about
+   (100 steps + 8) bytes per signal and must fit in 512 KiB (for one signal,
+   up to about 5200 steps); larger requests return AFD_E_INVALID before any
+   device work.  Every call on a device shares that
+   device's array and nothing in it needs to start at zero (each staged value
+   is written by the call's kernels before it is read), but calls that
+   overlap in time on one device (other threads or streams) race: serialise
+   them.  Timing (afd_plan_set_timing) is not collected by these calls.
+   Results equal afd_decompose's bit for bit.  Errors as afd_decompose, plus
+   AFD_E_INVALID for too many steps. */
+afd_status afd_decompose_noalloc(afd_plan plan, const double* signal, int32_t steps, afd_result* out);
+
 /* As afd_decompose, but step k continues from the grid point forced_index[2k],
    forced_index[2k+1] (host or device, 2*steps int32) instead of the selected
    one.  Every step still runs the whole path on the replayed remainder G_k:

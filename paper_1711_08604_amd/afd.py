@@ -61,7 +61,7 @@ class ResultDesc(ctypes.Structure):
 
 
 EXPORTS = [
-    "afd_plan_create", "afd_decompose", "afd_replay", "afd_workspace_bytes", "afd_plan_destroy",
+    "afd_plan_create", "afd_decompose", "afd_decompose_noalloc", "afd_replay", "afd_workspace_bytes", "afd_plan_destroy",
     "afd_status_string", "afd_last_error", "afd_plan_set_timing", "afd_plan_kernel_time",
     "afd_plan_radius_launch", "afd_reconstruct", "afd_analytic",
 ]
@@ -83,6 +83,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.afd_plan_create.restype = ctypes.c_int
     lib.afd_decompose.argtypes = [vp, vp, i32, ctypes.POINTER(ResultDesc)]
     lib.afd_decompose.restype = ctypes.c_int
+    lib.afd_decompose_noalloc.argtypes = [vp, vp, i32, ctypes.POINTER(ResultDesc)]
+    lib.afd_decompose_noalloc.restype = ctypes.c_int
     lib.afd_replay.argtypes = [vp, vp, i32, vp, ctypes.POINTER(ResultDesc)]
     lib.afd_replay.restype = ctypes.c_int
     lib.afd_workspace_bytes.argtypes = [ctypes.POINTER(PlanDesc)]
@@ -241,6 +243,14 @@ class Plan:
         sp, keep = self._signal_ptr(signal)
         out, rd = self._outputs(signal, int(steps))
         _check(self._lib.afd_decompose(self._h, ctypes.c_void_p(sp), int(steps), ctypes.byref(rd)))
+        return out
+
+    def decompose_noalloc(self, signal, steps: int) -> Result:
+        """decompose() through afd_decompose_noalloc: the library allocates
+        nothing in the call (results staged in its static device scratch)."""
+        sp, keep = self._signal_ptr(signal)
+        out, rd = self._outputs(signal, int(steps))
+        _check(self._lib.afd_decompose_noalloc(self._h, ctypes.c_void_p(sp), int(steps), ctypes.byref(rd)))
         return out
 
     def replay(self, signal, steps: int, forced) -> Result:

@@ -9,11 +9,20 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace afd;
+
+// Static scratch of afd_decompose_noalloc: the per-call staging of the
+// results, which afd_decompose keeps in memory the plan allocates on first
+// use.  HIP places one copy on every device the library runs on; each is
+// held until the process ends.  Host code reaches a copy only through the
+// address hipGetSymbolAddress returns for it (scratch_of).
+constexpr size_t kScratchBytes = size_t(512) << 10;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -27,6 +36,25 @@ afd_status fail(afd_status st, const std::string& msg) {
 afd_status hip_fail(hipError_t e, const char* where) {
   g_last_error = std::string(where) + ": " + hipGetErrorString(e);
   return AFD_E_HIP;
+}
+
+// Device address of `scratch` on `device`, which must be current: looked up
+// once per device and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+afd_status scratch_of(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(AFD_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch[device] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch[device];
+  return AFD_OK;
 }
 
 int ilog2_exact(int64_t n) {
@@ -444,11 +472,12 @@ afd_status ensure_forced(afd_plan_s* p, int steps) {
 // stamps the dispatch's start and end (no extra packets on the stream).
 struct Timer {
   afd_plan_s* p;
+  bool off = false;  // no timing in this call (it creates no events)
   size_t next = 0;
   // events for one timed unit of kind k, or nulls when k is not timed
   hipError_t pair(int k, hipEvent_t* a, hipEvent_t* b) {
     *a = *b = nullptr;
-    if (p->time_kind != k) return hipSuccess;
+    if (off || p->time_kind != k) return hipSuccess;
     if (p->time_seen++ % p->time_every != 0) return hipSuccess;  // not sampled
     if (next >= p->events.size() / 2) {
       hipEvent_t x, y;
@@ -599,7 +628,10 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
   return AFD_OK;
 }
 
-afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* forced_user, afd_result* out) {
+// `staging`: where the results are staged on the device (the static scratch
+// of afd_decompose_noalloc), or null for the plan's own staging.
+afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* forced_user, afd_result* out,
+               unsigned char* staging = nullptr) {
   if (!p) return fail(AFD_E_INVALID, "plan is NULL");
   if (!signal) return fail(AFD_E_INVALID, "signal is NULL");
   if (!out) return fail(AFD_E_INVALID, "out is NULL");
@@ -632,9 +664,12 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       HIPCHK(hipMemcpyAsync(p->forced, forced_host.data(), 4 * nf, hipMemcpyHostToDevice, p->stream),
              "uploading forced indices");
   }
-  afd_status st = ensure_res(p, steps);
-  if (st != AFD_OK) return st;
-  const ResPtrs R = res_layout(p->res, steps, B);
+  afd_status st = AFD_OK;
+  if (!staging) {
+    st = ensure_res(p, steps);
+    if (st != AFD_OK) return st;
+  }
+  const ResPtrs R = res_layout(staging ? staging : p->res, steps, B);
 
   hipStream_t s = p->stream;
   double* g64 = p->at<double>(p->L.g64);
@@ -756,6 +791,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   pk.flags = R.pflags;
 
   Timer tm{p};
+  tm.off = staging != nullptr;
   UpdateArgs upd{};
   upd.radii = radii;
   upd.omega = omega;
@@ -1027,6 +1063,21 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
 
 afd_status afd_decompose(afd_plan plan, const double* signal, int32_t steps, afd_result* out) {
   return run(plan, signal, steps, nullptr, out);
+}
+
+afd_status afd_decompose_noalloc(afd_plan plan, const double* signal, int32_t steps, afd_result* out) {
+  if (!plan) return fail(AFD_E_INVALID, "plan is NULL");
+  if (steps < 0) return fail(AFD_E_INVALID, "steps must be >= 0");
+  const size_t need = res_layout(nullptr, steps, plan->cfg.batch).total;
+  if (need > kScratchBytes)
+    return fail(AFD_E_INVALID, "steps * batch too large for the static scratch of afd_decompose_noalloc (" +
+                                   std::to_string(need) + " > " + std::to_string(kScratchBytes) + " bytes)");
+  hipError_t e = hipSetDevice(plan->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  unsigned char* staging = nullptr;
+  const afd_status st = scratch_of(plan->device, &staging);
+  if (st != AFD_OK) return st;
+  return run(plan, signal, steps, nullptr, out, staging);
 }
 
 afd_status afd_replay(afd_plan plan, const double* signal, int32_t steps, const int32_t* forced_index,
