@@ -72,11 +72,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def source_hash() -> str:
-    """sha256 over the kernel sources and the C header (names and contents, sorted by name)."""
+    """sha256 over the sources of the device code (names and contents, sorted
+    by name): every .hip and .h file of csrc/ except afd_api.hip, which holds
+    the host side of the library only."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1711_08604_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h")))
-    files.append(os.path.join(ROOT, "include", "afd.h"))
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
+                   if f.endswith((".hip", ".h")) and f != "afd_api.hip")
     for f in files:
         h.update(os.path.relpath(f, ROOT).encode() + b"\0")
         with open(f, "rb") as fh:
