@@ -157,7 +157,7 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
       const size_t fit = kBigChunkBytes / per_radius;
       cfg->chunk = int(fit < 1 ? 1 : fit > size_t(d->m) ? size_t(d->m) : fit);
       cfg->rpb = 1;
-      cfg->nblocks = cfg->chunk * cfg->bg.g;
+      cfg->nblocks = d->m * cfg->bg.g;  // records of every radius of a step
     } else {
       cfg->geom = fft_geom(logn, cfg->fp64);
       cfg->bg = BigGeom{};
@@ -206,7 +206,7 @@ Layout layout_of(const Config& c) {
   L.z = take(c.big ? 2 * real * size_t(c.chunk) * size_t(c.N) : 0);
   L.c0 = take(c.big ? 2 * real * (size_t(1) << c.bg.l2) * B : 0);
   L.rrec = take(c.big ? (c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.M) : 0);
-  L.bcounters = take(c.big ? 4 * (size_t(c.chunk) + 1) : 0);
+  L.bcounters = take(c.big ? 4 : 0);
   L.cand = take(sizeof(CandList) * B);
   L.partials = take(16 * size_t(kKMax) * c.nch * B);
   L.winner = take(sizeof(Winner) * B);
@@ -388,7 +388,7 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   if (e == hipSuccess) e = up(p->L.forced0, f0, sizeof(f0));
   if (e == hipSuccess) e = hipMemset(p->arena + p->L.nonfinite, 0, 4);
   if (e == hipSuccess) e = hipMemset(p->arena + p->L.counters, 0, 4 * kNumCounters * size_t(c.batch));
-  if (e == hipSuccess && c.big) e = hipMemset(p->arena + p->L.bcounters, 0, 4 * (size_t(c.chunk) + 1));
+  if (e == hipSuccess && c.big) e = hipMemset(p->arena + p->L.bcounters, 0, 4);
   if (e != hipSuccess) return hip_fail(e, "uploading plan tables");
   return AFD_OK;
 }
@@ -707,7 +707,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.bar, 0, 8 * 16 * kBarGroups, s), "clearing counters");
   if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.rqueue, 0, 4, s), "clearing counters");
   if (c.big)
-    HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4 * (size_t(c.chunk) + 1), s), "clearing counters");
+    HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4, s), "clearing counters");
   HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N) * B, sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                         s),
          "copying signal");
@@ -764,8 +764,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     bp.recheck_k = p->recheck_k;
     bp.blocks = p->at<void>(p->L.blocks);
     bp.rrec = p->at<void>(p->L.rrec);
-    bp.counter_r = p->at<unsigned int>(p->L.bcounters);
-    bp.counter_g = p->at<unsigned int>(p->L.bcounters) + c.chunk;
+    bp.counter_g = p->at<unsigned int>(p->L.bcounters);
     bp.heads = p->at<uint64_t>(p->L.heads);
     bp.flagword = counters + 4 * B;
     bp.cand = cand;
@@ -823,13 +822,14 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       if (c.big) {
         for (int m0 = 0; m0 < c.M; m0 += c.chunk) {
           bp.m0 = m0;
-          const bool first = m0 == 0, last = m0 + c.chunk >= c.M;
+          const bool first = m0 == 0;
           hipEvent_t r0, r1;
           HIPCHK(tm.pair(kTimeRows, &r0, &r1), "event");
           HIPCHK(launch_big(c.logn, c.fp64, bp, c.M - m0 < c.chunk ? c.M - m0 : c.chunk, s, first ? e0 : nullptr,
-                            last ? e1 : nullptr, r0, r1),
+                            nullptr, r0, r1),
                  "k_big");
         }
+        HIPCHK(launch_big_merge(c.logn, c.fp64, bp, s, e1), "k_big_merge");
       } else {
         HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, B, s, e0, e1), "k_radius");
       }

@@ -116,12 +116,11 @@ struct BigParams {
   int m0;             // first radius of the chunk
   float tau_band;
   int recheck_k;
-  void* blocks;       // [chunk][G] per-workgroup records (BlockList32 or BlockBest64)
+  void* blocks;       // [M][G] per-workgroup records (BlockList32 or BlockBest64)
   void* rrec;         // [M] per-radius records (same type)
   uint64_t* heads;    // FP32: [M] head key of each per-radius record
   unsigned int* flagword;  // FP32: fallback flag of the step (zero between steps)
-  unsigned int* counter_r;  // [chunk] workgroup arrivals per radius (zero between launches)
-  unsigned int* counter_g;  // radius arrivals over the step's chunks (zero between steps)
+  unsigned int* counter_g;  // radius arrivals of the step's merge (zero between steps)
   CandList* cand;
   Winner* winner;
   // double precision, non-null: the grid value at the point (m, j) = (probe[0], probe[1])
@@ -135,7 +134,7 @@ struct BigGeom {
   int sw;         // twiddle split: e = h 2^sw + low
   int ca, thr_a;  // columns and threads per column workgroup
   int rb, thr_b;  // rows and threads per row workgroup
-  int g;          // row workgroups per radius
+  int g;          // row workgroups (records) per radius
   size_t lds_a, lds_b;
   size_t rec_bytes;  // one per-workgroup record
 };
@@ -146,6 +145,9 @@ hipError_t setup_big_attributes();
 // pass's end; r0 / r1 stamp the row pass alone.
 hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr, hipEvent_t r0 = nullptr, hipEvent_t r1 = nullptr);
+// After the last chunk of a step: the radius records into the winner (FP64)
+// or the short-list (FP32); e1 stamps its end.
+hipError_t launch_big_merge(int logn, bool fp64, const BigParams& p, hipStream_t s, hipEvent_t e1 = nullptr);
 
 // Step outputs written by the last workgroup of k_update / k_prepare.
 struct RecordArgs {

@@ -12,12 +12,15 @@
 // l2 per workgroup, reading the spectrum in column order (the forward DFT
 // writes it that way), applies r_m^l2 e^{2 pi i j1 l2/N}, transposes through
 // LDS and stores Z_m with the columns contiguous.  The row pass (k_big_rows)
-// runs the length-N2 transforms of RB rows j1 per workgroup, scales by s_m,
-// forms |.|^2 and selects as the LDS-resident kernel does (flat index
-// m N + j1 + N1 j2).  The last row workgroup of a radius merges the radius'
-// workgroup records into one per-radius record; the last radius of the step
-// merges those into the winner (FP64) or the short-list (FP32).  Radii are
-// processed in chunks so the intermediate stays within a fixed budget.
+// runs the length-N2 transforms of RB x RPT rows j1 per workgroup, scales by
+// s_m, forms |.|^2 and selects as the LDS-resident kernel does (flat index
+// m N + j1 + N1 j2), one record per workgroup.  Radii are processed in
+// chunks so the intermediate stays within a fixed budget.  After the last
+// chunk of a step, k_big_merge merges each radius' workgroup records into a
+// per-radius record and those into the winner (FP64) or the short-list
+// (FP32): a launch of its own, because a last-workgroup merge inside the row
+// pass held every row workgroup through a store-and-count round trip at its
+// end (measured: 26% of the row pass at N = 2^20 in double precision).
 //
 // Short spectra need no intermediate.  A radius whose significant length L
 // (the terms r_m^l c_l beyond it are dropped, as in the LDS-resident kernel)
@@ -41,13 +44,25 @@ struct Big {
   static constexpr int CA0 = sizeof(T) == 4 ? 8 : 4;
   static constexpr int CA = 256 / TPR1 > CA0 ? 256 / TPR1 : CA0;
   static constexpr int THR_A = CA * TPR1;
-  static constexpr int RB = 256 / TPR2 > 1 ? 256 / TPR2 : 1;
+  // Row pass: RB row transforms side by side per workgroup, each over RPT
+  // rows one after another.  Single precision: 512 threads; double
+  // precision: 256 threads and, where a row transform is one wave, four rows
+  // in turn wherever a radius keeps at least 16 workgroups, so that each
+  // workgroup's fixed latencies (its first loads, the record of its best
+  // point) are paid once per 16 rows.
+  static constexpr int THR_B0 = sizeof(T) == 4 ? 512 : 256;
+  static constexpr int RB = THR_B0 / TPR2 > 1 ? THR_B0 / TPR2 : 1;
   static constexpr int THR_B = RB * TPR2;
-  static constexpr int G = N1 / RB;
+  static constexpr int RPT = (sizeof(T) == 8 && TPR2 == 64 && N1 / (RB * 4) >= 16) ? 4 : 1;
+  // waves per SIMD the row pass's register budget allows (single precision,
+  // and double precision over several rows: at most 128 VGPRs)
+  static constexpr int WPE_B = (sizeof(T) == 4 || RPT > 1) ? 4 : 1;
+  static constexpr int G = N1 / (RB * RPT);  // row workgroups (records) per radius
   static constexpr int SW = (LOGN + 1) / 2;
   static constexpr int LDT = CA + 1;  // row pitch of the LDS transpose (reals)
-  static_assert(N2 % CA == 0 && N1 % RB == 0, "tiles must divide the transform");
-  static_assert(G <= THR_B, "the radius merge holds one workgroup list per thread");
+  static_assert(N2 % CA == 0 && N1 % (RB * RPT) == 0, "tiles must divide the transform");
+  static_assert(G <= 256, "the radius merge holds one workgroup record per thread");
+  static_assert(sizeof(T) == 8 || RPT == 1, "a single-precision row workgroup lists the band of its own rows");
   // LDS per workgroup, sized for occupancy: the column transforms and the
   // transpose move real and imaginary parts in turn through half the space;
   // the row transforms do so in double precision, and the row selection's
@@ -58,8 +73,7 @@ struct Big {
                                       ? size_t(CA) * region_a
                                       : size_t(N1) * LDT * sizeof(T);
   static constexpr size_t sel_b = sizeof(T) == 4 ? kListScratchBytes : 16 * sizeof(Best);
-  static constexpr size_t lds_b0 = size_t(RB) * region_b > sel_b ? size_t(RB) * region_b : sel_b;
-  static constexpr size_t lds_b = lds_b0 > sizeof(MergeScratch) ? lds_b0 : sizeof(MergeScratch);
+  static constexpr size_t lds_b = size_t(RB) * region_b > sel_b ? size_t(RB) * region_b : sel_b;
 };
 
 template <typename T, int LOGN>
@@ -163,16 +177,11 @@ __device__ __forceinline__ void deep_row_inputs(Cx<T> (&v)[E], int t, int j1, in
 }
 
 template <typename T, int LOGN, bool LIST>
-__global__ __launch_bounds__((Big<T, LOGN>::THR_B)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+__global__ __launch_bounds__((Big<T, LOGN>::THR_B)) __attribute__((amdgpu_waves_per_eu(Big<T, LOGN>::WPE_B)))
 void k_big_rows(BigParams p) {
   using B = Big<T, LOGN>;
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_last;
-  const int ri = threadIdx.x / B::TPR2, t = threadIdx.x - ri * B::TPR2;
-  int j1 = blockIdx.x * B::RB + ri;
-  // a row of at least 64 threads spans whole waves: j1 is wave-uniform, so
-  // the row's uniform twiddles come through scalar loads
-  if constexpr (B::TPR2 % 64 == 0) j1 = __builtin_amdgcn_readfirstlane(j1);
+  const int ri = threadIdx.x / B::TPR2, t0 = threadIdx.x - ri * B::TPR2;
   const int ml = blockIdx.y, m = p.m0 + ml;
 
   using S2 = Shape<B::L2, B::E2>;
@@ -181,69 +190,94 @@ void k_big_rows(BigParams p) {
   const Cx<T>* tw2 = reinterpret_cast<const Cx<T>*>(p.tw2);
   const int L = p.lsig[m];
   const T sc = reinterpret_cast<const T*>(p.scale)[m];  // loaded before the transform's barriers
-  Cx<T> v[B::E2];
-  if (L > B::N2) {
-    const Cx<T>* __restrict__ row = reinterpret_cast<const Cx<T>*>(p.z) + size_t(ml) * B::N + size_t(j1) * B::N2;
+  const int rec = m * B::G + int(blockIdx.x);
+  Best run{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};  // double precision: this thread's best over its rows
+#pragma unroll 1
+  for (int k = 0; k < B::RPT; ++k) {
+    // the thread index goes through an opaque zero in every row, so that the
+    // transform's per-thread twiddle loads are not hoisted out of the row
+    // loop and kept live across it (which would exceed the register budget)
+    int zero = 0;
+    if constexpr (B::RPT > 1) asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+    const int t = t0 + zero;
+    int j1 = (int(blockIdx.x) * B::RB + ri) * B::RPT + k;
+    // a row of at least 64 threads spans whole waves: j1 is wave-uniform, so
+    // the row's uniform twiddles come through scalar loads
+    if constexpr (B::TPR2 % 64 == 0) j1 = __builtin_amdgcn_readfirstlane(j1);
+    Cx<T> v[B::E2];
+    if (L > B::N2) {
+      const Cx<T>* __restrict__ row = reinterpret_cast<const Cx<T>*>(p.z) + size_t(ml) * B::N + size_t(j1) * B::N2;
 #pragma unroll
-    for (int i = 0; i < B::E2; ++i) v[i] = row[t + B::TPR2 * i];
-    fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
-  } else if (S2::NP >= 3 && L <= B::N2 / S2::ns(2)) {  // uniform: one radius per workgroup
-    if constexpr (S2::NP >= 3) {
-      deep_row_inputs<T, LOGN, 2>(v, t, j1, L, p, m);
-      fft_regs<T, B::L2, B::E2, +1, SPLIT, 2, 2, true>(v, t, region, tw2);
+      for (int i = 0; i < B::E2; ++i) v[i] = row[t + B::TPR2 * i];
+      fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
+    } else if (S2::NP >= 3 && L <= B::N2 / S2::ns(2)) {  // uniform: one radius per workgroup
+      if constexpr (S2::NP >= 3) {
+        deep_row_inputs<T, LOGN, 2>(v, t, j1, L, p, m);
+        fft_regs<T, B::L2, B::E2, +1, SPLIT, 2, 2, true>(v, t, region, tw2);
+      }
+    } else if (S2::NP >= 2 && L <= B::N2 / S2::radix(0)) {
+      if constexpr (S2::NP >= 2) {
+        deep_row_inputs<T, LOGN, 1>(v, t, j1, L, p, m);
+        fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1, true>(v, t, region, tw2);
+      }
+    } else {
+      deep_row_inputs<T, LOGN, 0>(v, t, j1, L, p, m);
+      fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
     }
-  } else if (S2::NP >= 2 && L <= B::N2 / S2::radix(0)) {
-    if constexpr (S2::NP >= 2) {
-      deep_row_inputs<T, LOGN, 1>(v, t, j1, L, p, m);
-      fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1, true>(v, t, region, tw2);
-    }
-  } else {
-    deep_row_inputs<T, LOGN, 0>(v, t, j1, L, p, m);
-    fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
-  }
 
-  __syncthreads();  // every row is done with its region: the selection reuses them
-  unsigned char* scratch = smem;
-  // register p of thread t holds j2 = t + TPR2 bitrev(p): flat index m N + j1 + N1 j2
-  const uint32_t fbase = uint32_t(m) * uint32_t(B::N) + uint32_t(j1);
-  const int rec = ml * B::G + int(blockIdx.x);
-  if constexpr (LIST) {
-    const FlatOrder ord{uint32_t(m) * uint32_t(B::N) + uint32_t(blockIdx.x) * uint32_t(B::RB), uint32_t(B::RB),
-                        uint32_t(B::N1), uint32_t(B::RB) * uint32_t(B::N2)};
-    select_list<B::L2>(v, true, sc, fbase, uint32_t(B::N1), t, scratch, p.tau_band, ord,
-                       reinterpret_cast<BlockList32*>(p.blocks) + rec, nullptr, nullptr, p.flagword);
-  } else {
-    if (p.probe) {
-      // a replayed step: the grid value at the forced point j = j1 + N1 j2,
-      // scaled as the selection scales its best value (register q of thread
-      // t holds j2 = t + TPR2 bitrev(q))
-      const int pm = p.probe[0], pj = p.probe[1];
-      const int pj2 = pj >> B::L1;
-      if (m == pm && j1 == (pj & (B::N1 - 1)) && t == (pj2 & (B::TPR2 - 1))) {
-        const int u = pj2 / B::TPR2;
+    // register q of thread t holds j2 = t + TPR2 bitrev(q): flat index m N + j1 + N1 j2
+    const uint32_t fbase = uint32_t(m) * uint32_t(B::N) + uint32_t(j1);
+    if constexpr (LIST) {
+      __syncthreads();  // every row is done with its region: the selection reuses them
+      const FlatOrder ord{uint32_t(m) * uint32_t(B::N) + uint32_t(blockIdx.x) * uint32_t(B::RB), uint32_t(B::RB),
+                          uint32_t(B::N1), uint32_t(B::RB) * uint32_t(B::N2)};
+      select_list<B::L2>(v, true, sc, fbase, uint32_t(B::N1), t, smem, p.tau_band, ord,
+                         reinterpret_cast<BlockList32*>(p.blocks) + rec, nullptr, nullptr, p.flagword);
+    } else {
+      if (p.probe) {
+        // a replayed step: the grid value at the forced point j = j1 + N1 j2,
+        // scaled as the selection scales its best value
+        const int pm = p.probe[0], pj = p.probe[1];
+        const int pj2 = pj >> B::L1;
+        if (m == pm && j1 == (pj & (B::N1 - 1)) && t == (pj2 & (B::TPR2 - 1))) {
+          const int u = pj2 / B::TPR2;
 #pragma unroll
-        for (int q = 0; q < B::E2; ++q) {
-          if (bitrev(q, ilog2c(B::E2)) == u) {
-            p.probe_out[0] = double(v[q].x * sc);
-            p.probe_out[1] = double(v[q].y * sc);
+          for (int q = 0; q < B::E2; ++q) {
+            if (bitrev(q, ilog2c(B::E2)) == u) {
+              p.probe_out[0] = double(v[q].x * sc);
+              p.probe_out[1] = double(v[q].y * sc);
+            }
           }
         }
       }
+      best_merge(run, thread_best<B::L2, T>(v, sc, fbase, uint32_t(B::N1), t));
     }
-    select_best<B::L2, T>(v, true, sc, fbase, uint32_t(B::N1), t, reinterpret_cast<Best*>(scratch),
-                          reinterpret_cast<BlockBest64*>(p.blocks) + rec);
   }
+  if constexpr (!LIST) {
+    __syncthreads();  // every row is done with its region: the reduction's scratch reuses them
+    store_block_best(run, reinterpret_cast<Best*>(smem), reinterpret_cast<BlockBest64*>(p.blocks) + rec);
+  }
+}
 
-  if (!last_arrival(p.counter_r + ml, unsigned(B::G), &s_last)) return;
+// After the row passes of every chunk of a step: workgroup m merges radius
+// m's G workgroup records into its per-radius record (and, in single
+// precision, its head key), and the last workgroup to finish merges the M
+// per-radius records into the winner (FP64) or the short-list (FP32).
+template <typename T, int LOGN, bool LIST>
+__global__ __launch_bounds__(256) void k_big_merge(BigParams p) {
+  using B = Big<T, LOGN>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_last;
   MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
+  const int m = blockIdx.x;
   if constexpr (LIST) {
-    merge_list_group(reinterpret_cast<const BlockList32*>(p.blocks) + ml * B::G, B::G, p.tau_band,
+    merge_list_group(reinterpret_cast<const BlockList32*>(p.blocks) + size_t(m) * B::G, B::G, p.tau_band,
                      reinterpret_cast<BlockList32*>(p.rrec) + m, p.heads + m, Sm);
   } else {
-    merge_best_group(reinterpret_cast<const BlockBest64*>(p.blocks) + ml * B::G, B::G,
+    merge_best_group(reinterpret_cast<const BlockBest64*>(p.blocks) + size_t(m) * B::G, B::G,
                      reinterpret_cast<BlockBest64*>(p.rrec) + m, Sm);
   }
-  if (!last_arrival(p.counter_g, unsigned(p.M), &s_last)) return;
+  if (!last_arrival(p.counter_g, gridDim.x, &s_last)) return;
   if constexpr (LIST) {
     select32_tail(reinterpret_cast<const BlockList32*>(p.rrec), p.heads, nullptr, p.M, p.recheck_k, p.tau_band,
                   p.flagword, p.cand, Sm);
@@ -291,7 +325,9 @@ hipError_t setup_big_attributes() {
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_cols<float, L>));        \
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_cols<double, L>));       \
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<float, L, true>));  \
-  if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<double, L, false>));
+  if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<double, L, false>));      \
+  if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_merge<float, L, true>));      \
+  if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_merge<double, L, false>));
   AFD_BIG_LOGN_CASES(X)
 #undef X
   return e;
@@ -308,6 +344,25 @@ static hipError_t launch_big_t(const BigParams& p, int nr, hipStream_t s, hipEve
   launch_ev(k_big_rows<T, LOGN, sizeof(T) == 4>, dim3(B::G, nr), dim3(B::THR_B), uint32_t(B::lds_b), s, r0,
             r1 ? r1 : e1, p);
   return hipGetLastError();
+}
+
+template <typename T, int LOGN>
+static hipError_t launch_big_merge_t(const BigParams& p, hipStream_t s, hipEvent_t e1) {
+  launch_ev(k_big_merge<T, LOGN, sizeof(T) == 4>, dim3(p.M), dim3(256), uint32_t(sizeof(MergeScratch)), s, nullptr, e1,
+            p);
+  return hipGetLastError();
+}
+
+hipError_t launch_big_merge(int logn, bool fp64, const BigParams& p, hipStream_t s, hipEvent_t e1) {
+  switch (logn) {
+#define X(L) \
+  case L:    \
+    return fp64 ? launch_big_merge_t<double, L>(p, s, e1) : launch_big_merge_t<float, L>(p, s, e1);
+    AFD_BIG_LOGN_CASES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s, hipEvent_t e0, hipEvent_t e1,

@@ -754,6 +754,55 @@ __device__ __forceinline__ void select_best(const Cx<T> (&v)[pickE<T, LOGN>()], 
   }
 }
 
+// The per-thread part of select_best, returned instead of reduced: for a
+// thread that selects over several transforms (rows) in turn and merges
+// them (best_merge) before the workgroup reduction.  (select_best keeps its
+// own copy of the loop: written through this function it needs 13 more
+// VGPRs in the 2^14-point double-precision radius kernel.)
+template <int LOGN, typename T>
+__device__ __forceinline__ Best thread_best(const Cx<T> (&v)[pickE<T, LOGN>()], T sc, uint32_t fbase,
+                                            uint32_t fstride, int t) {
+  constexpr int E = pickE<T, LOGN>();
+  constexpr int LE = ilog2c(E);
+  double y1 = -1.0, y2 = -1.0;
+  int i1 = 0;
+  T bx = T(0), by = T(0);
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int p = bitrev(q, LE);  // register holding bin t + TPR*q
+    const double y = double(fma(v[p].x, v[p].x, v[p].y * v[p].y));
+    if (y > y1) {
+      y2 = y1;
+      y1 = y;
+      i1 = p;
+      bx = v[p].x;
+      by = v[p].y;
+    } else {
+      y2 = fmax(y2, y);
+    }
+  }
+  Best b;
+  const double s2 = double(sc) * double(sc);
+  b.vx = double(bx * sc);
+  b.vy = double(by * sc);
+  b.f = fbase + fstride * uint32_t(t + Shape<LOGN, E>::TPR * bitrev(i1, LE));
+  b.p1 = b.vx * b.vx + b.vy * b.vy;
+  b.p2 = fmin(y2 * s2, b.p1);
+  return b;
+}
+
+// Thread 0 stores the workgroup's best and runner-up of the threads' b.
+__device__ __forceinline__ void store_block_best(const Best& b, Best* wb, BlockBest64* o) {
+  const Best r = block_best(b, wb);
+  if (threadIdx.x == 0) {
+    st_agent(&o->p1, r.p1);
+    st_agent(&o->p2, r.p2);
+    st_agent(&o->vx, r.vx);
+    st_agent(&o->vy, r.vy);
+    st_agent(&o->f, r.f);
+  }
+}
+
 // FP32 workgroup list: the workgroup's points within tau_band of its
 // maximum, best first, at most kListC of them (exact top by key).  Points
 // are compared unscaled (|y|^2 against the threshold divided by s_m^2) and

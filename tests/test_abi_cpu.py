@@ -97,15 +97,17 @@ def test_workspace_bytes_scales():
 def test_workspace_bytes_two_pass():
     """N = 2^20: the radius transforms run in two passes over chunks of radii
     whose intermediate is bounded (1 GiB), so the workspace does not grow
-    with M * N."""
+    with M * N; besides it, a step keeps one selection record per row
+    workgroup of every radius (M x 128 lists of 528 bytes in single
+    precision, M x 64 bests of 40 bytes in double precision)."""
     afd, lib = _lib()
     r = np.linspace(0, 0.999, 2000)
     out = {}
     for prec in (0, 1):
         d, keep = _desc(afd, n=1 << 20, radii=r, precision=prec)
         out[prec] = lib.afd_workspace_bytes(ctypes.byref(d))
-    for prec, b in out.items():
-        assert (1 << 30) <= b < (1200 << 20), (prec, b)
+    assert (1 << 30) <= out[0] < (1200 << 20), out
+    assert (1 << 30) + 2000 * 128 * 528 <= out[1] < (1200 << 20) + 2000 * 128 * 528, out
     d, keep = _desc(afd, n=1 << 15, radii=r[:7], precision=1)
     assert 0 < lib.afd_workspace_bytes(ctypes.byref(d)) < (16 << 20)
 
