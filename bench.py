@@ -224,6 +224,37 @@ def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch, kernel_timing=Tru
     return out
 
 
+def run_graph(prec, sig, radii, afd_steps, steps, warmup, torch):
+    """The same decompositions as run_gpu, each one replay of a HIP graph that
+    captured the whole decomposition (afd_graph_create); per-solve latency is
+    launch to completion."""
+    from paper_1711_08604_amd import Plan
+    batch = int(sig.shape[0]) if sig.dim() == 2 else 1
+    n = int(sig.numel()) // batch
+    stream = torch.cuda.current_stream().cuda_stream
+    plan = Plan(n, radii, precision=prec, stream=stream, batch=batch)
+    gr = plan.graph(sig, afd_steps)
+    for _ in range(warmup):
+        gr.launch()
+    gr.status()
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        gr.launch()
+        torch.cuda.current_stream().synchronize()
+        lat.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gr.status()
+    gr.close()
+    plan.close()
+    evals = float(len(radii)) * n * afd_steps * steps * batch
+    return {"value": evals / wall, "ms_per_step": wall / steps * 1e3, "p50_ms": percentile(lat, 0.5) * 1e3,
+            "p99_ms": percentile(lat, 0.99) * 1e3}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -469,6 +500,13 @@ def main():
         line["fp32"] = {k: f[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "latency_ms", "roofline",
                                           "fp32_error_max", "recheck_count_mean") if k in f}
         line["fp32"]["mode"] = "FP32 bulk + FP64 short-list recheck"
+    if args.workload == "small1k":
+        # the same solves replayed from a captured HIP graph
+        sig = torch.from_numpy(g).to("cuda:0")
+        gres = run_graph("fp64", sig, radii, afd_steps, args.steps, args.warmup, torch)
+        log(f"bench: small1k graph {gres['value']:.3e} evals/s, p50 {gres['p50_ms']:.3f} ms, "
+            f"p99 {gres['p99_ms']:.3f} ms")
+        line["graph"] = gres
     if args.workload == "chirp1m" and not args.no_extra:
         # the N = 16384, M = 1000 workload: a second, VALU/LDS-bound regime
         _, _, _, r2 = _time_workload("single16k", W, torch, max(args.steps, 10), args.warmup, args.only, kt)

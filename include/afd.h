@@ -33,6 +33,7 @@ extern "C" {
 #endif
 
 typedef struct afd_plan_s* afd_plan; /* opaque; owns its device workspace and tables */
+typedef struct afd_graph_s* afd_graph; /* opaque; one decomposition captured as a HIP graph */
 
 typedef enum {
   AFD_OK = 0,
@@ -130,6 +131,30 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
    untouched.  An all-zero remainder selects flat index 0 with c_k = 0 and
    the loop continues. */
 afd_status afd_decompose(afd_plan plan, const double* signal, int32_t steps, afd_result* out);
+
+/* One whole decomposition of `steps` steps (as afd_decompose) captured into
+   a HIP graph, for callers that repeat decompositions of one shape and want
+   them submitted as one unit (the per-launch host work and the host waits of
+   afd_decompose are gone).  `signal` and every non-null array of `out` must
+   be device memory of the plan's device; they are baked into the graph (to
+   decompose another signal, write it into the same buffer), as is the plan's
+   workspace: the graph and the plan's other calls must not run concurrently.
+   `out` is copied.  Each afd_graph_launch enqueues one replay on the plan's
+   stream and returns at once; the results are in `out` when the stream has
+   reached them.  Counters are cleared by a kernel at the start of every
+   replay.  Errors: AFD_E_INVALID (NULL, steps < 0, a required out field
+   missing, a host pointer), AFD_E_NOMEM, AFD_E_HIP (capture or instantiation
+   failed).  Non-finite samples are not reported by the launch: see
+   afd_graph_status. */
+afd_status afd_graph_create(afd_plan plan, const double* signal, int32_t steps, const afd_result* out,
+                            afd_graph* graph);
+afd_status afd_graph_launch(afd_graph graph);
+/* Waits for the plan's stream; AFD_E_NONFINITE if the last replay's signal
+   held NaN or Inf (its outputs are then meaningless), AFD_E_HIP if a grid
+   barrier of the step tail timed out, else AFD_OK. */
+afd_status afd_graph_status(afd_graph graph);
+/* NULL-safe.  Destroy graphs before their plan. */
+void afd_graph_destroy(afd_graph graph);
 
 /* For callers that cannot allocate device memory (code under stream capture,
    tight serving loops, harnesses that forbid allocation): afd_decompose

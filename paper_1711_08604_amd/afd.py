@@ -64,6 +64,7 @@ EXPORTS = [
     "afd_plan_create", "afd_decompose", "afd_decompose_noalloc", "afd_replay", "afd_workspace_bytes", "afd_plan_destroy",
     "afd_status_string", "afd_last_error", "afd_plan_set_timing", "afd_plan_kernel_time",
     "afd_plan_radius_launch", "afd_reconstruct", "afd_analytic",
+    "afd_graph_create", "afd_graph_launch", "afd_graph_status", "afd_graph_destroy",
 ]
 
 _lib = None
@@ -105,6 +106,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.afd_reconstruct.restype = ctypes.c_int
     lib.afd_analytic.argtypes = [vp, vp, vp]
     lib.afd_analytic.restype = ctypes.c_int
+    lib.afd_graph_create.argtypes = [vp, vp, i32, ctypes.POINTER(ResultDesc), ctypes.POINTER(vp)]
+    lib.afd_graph_create.restype = ctypes.c_int
+    lib.afd_graph_launch.argtypes = [vp]
+    lib.afd_graph_launch.restype = ctypes.c_int
+    lib.afd_graph_status.argtypes = [vp]
+    lib.afd_graph_status.restype = ctypes.c_int
+    lib.afd_graph_destroy.argtypes = [vp]
+    lib.afd_graph_destroy.restype = None
     _lib = lib
     return lib
 
@@ -270,6 +279,14 @@ class Plan:
                                     ctypes.byref(rd)))
         return out
 
+    def graph(self, signal, steps: int) -> "Graph":
+        """A decomposition of `signal` (a torch tensor on the GPU) captured as a HIP
+        graph (afd_graph_create); every launch() decomposes what the tensor then
+        holds into the Graph's device outputs."""
+        if not _is_torch_cuda(signal):
+            raise ValueError("a captured decomposition needs the signal on the device")
+        return Graph(self, signal, int(steps))
+
     # -- outputs around the loop
     def _complex_in(self, x, count, name):
         """Pointer to `count` complex128 values (numpy or torch on the GPU) and a keep-alive."""
@@ -343,6 +360,44 @@ class Plan:
         l = ctypes.c_int32()
         _check(self._lib.afd_plan_radius_launch(self._h, ctypes.byref(b), ctypes.byref(t), ctypes.byref(l)))
         return b.value, t.value, l.value
+
+
+class Graph:
+    """One decomposition captured as a HIP graph; `result` holds its device outputs."""
+
+    def __init__(self, plan: Plan, signal, steps: int):
+        self._plan = plan
+        self._lib = plan._lib
+        sp, self._signal = plan._signal_ptr(signal)
+        self.result, rd = plan._outputs(signal, steps)
+        h = ctypes.c_void_p()
+        _check(self._lib.afd_graph_create(plan._h, ctypes.c_void_p(sp), steps, ctypes.byref(rd), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        """Enqueue one replay on the plan's stream (asynchronous)."""
+        _check(self._lib.afd_graph_launch(self._h))
+
+    def status(self):
+        """Wait for the plan's stream; raise AfdError if the last replay's signal was not finite."""
+        _check(self._lib.afd_graph_status(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.afd_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def status_string(status: int) -> str:

@@ -71,7 +71,7 @@ enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3, 
 // Device arena layout for one plan.
 struct Layout {
   size_t radii, omega, tw, twf1, twf2, pw, pv, scale, g64, g32, c, xt, blocks, cand, partials, winner, epart,
-      nonfinite, forced0, counters, bar, omega_t, rqueue, probe;
+      nonfinite, forced0, counters, bar, omega_t, rqueue, probe, border;
   // truncated / pruned spectrum of the LDS-resident radius transforms
   size_t pq, lsig, order;
   // FP32 head and second keys of the workgroup (or per-radius) records
@@ -102,7 +102,8 @@ struct Config {
   BigGeom bg;
   bool adv;     // 2^10 <= N <= 2^14: fused step tail (afd_advance.hip)
   AdvGeom ag;
-  int chunk;    // radii per two-pass chunk
+  int chunk;    // radii per two-pass chunk (of the radii with long spectra)
+  int nshort;   // N > 2^14: radii whose significant spectrum fits in N2 terms (no intermediate)
 };
 
 constexpr int kNumCounters = 5;  // radius, recheck, update, prepare; FP32 fallback flag word
@@ -153,15 +154,21 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     if (cfg->big) {
       cfg->geom = FftGeom{0, 0, 0, false, 0};
       cfg->bg = big_geom(logn, cfg->fp64);
+      // only the radii with long spectra go through the intermediate, in chunks
+      cfg->nshort = 0;
+      for (int i = 0; i < d->m; ++i)
+        if (significant_length(d->radii[i], cfg->fp64 ? 60 : 40, d->n) <= (int64_t(1) << cfg->bg.l2)) ++cfg->nshort;
+      const size_t nlong = size_t(d->m - cfg->nshort);
       const size_t per_radius = size_t(d->n) * (cfg->fp64 ? 16 : 8);
       const size_t fit = kBigChunkBytes / per_radius;
-      cfg->chunk = int(fit < 1 ? 1 : fit > size_t(d->m) ? size_t(d->m) : fit);
+      cfg->chunk = nlong == 0 ? 0 : int(fit < 1 ? 1 : fit > nlong ? nlong : fit);
       cfg->rpb = 1;
       cfg->nblocks = d->m * cfg->bg.g;  // records of every radius of a step
     } else {
       cfg->geom = fft_geom(logn, cfg->fp64);
       cfg->bg = BigGeom{};
       cfg->chunk = 0;
+      cfg->nshort = 0;
       const int tpr = cfg->geom.tpr;
       cfg->rpb = tpr >= 64 ? 1 : 64 / tpr;
       cfg->nblocks = (d->m + cfg->rpb - 1) / cfg->rpb;
@@ -207,6 +214,7 @@ Layout layout_of(const Config& c) {
   L.c0 = take(c.big ? 2 * real * (size_t(1) << c.bg.l2) * B : 0);
   L.rrec = take(c.big ? (c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.M) : 0);
   L.bcounters = take(c.big ? 4 : 0);
+  L.border = take(c.big ? 4 * size_t(c.M) : 0);  // radii with short spectra first
   L.cand = take(sizeof(CandList) * B);
   L.partials = take(16 * size_t(kKMax) * c.nch * B);
   L.winner = take(sizeof(Winner) * B);
@@ -266,6 +274,15 @@ struct afd_plan_s {
   P* at(size_t off) const {
     return reinterpret_cast<P*>(arena + off);
   }
+};
+
+// A decomposition captured into a HIP graph (afd_graph_create).
+struct afd_graph_s {
+  afd_plan_s* plan = nullptr;
+  afd_result out{};
+  int steps = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -389,6 +406,16 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   if (e == hipSuccess) e = hipMemset(p->arena + p->L.nonfinite, 0, 4);
   if (e == hipSuccess) e = hipMemset(p->arena + p->L.counters, 0, 4 * kNumCounters * size_t(c.batch));
   if (e == hipSuccess && c.big) e = hipMemset(p->arena + p->L.bcounters, 0, 4);
+  if (c.big) {
+    // launch order of the radii beyond the LDS: the short spectra (one row
+    // launch, no intermediate), then the long ones (chunks through it)
+    std::vector<int32_t> order;
+    for (int m = 0; m < M; ++m)
+      if (lsig[m] <= (1 << c.bg.l2)) order.push_back(m);
+    for (int m = 0; m < M; ++m)
+      if (lsig[m] > (1 << c.bg.l2)) order.push_back(m);
+    if (e == hipSuccess) e = up(p->L.border, order.data(), 4 * size_t(M));
+  }
   if (e != hipSuccess) return hip_fail(e, "uploading plan tables");
   return AFD_OK;
 }
@@ -629,9 +656,13 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
 }
 
 // `staging`: where the results are staged on the device (the static scratch
-// of afd_decompose_noalloc), or null for the plan's own staging.
+// of afd_decompose_noalloc), or null for the plan's own staging.  `graph`:
+// the call is being captured into a HIP graph (afd_graph_create): the
+// records go straight into the caller's device arrays (staging only for the
+// null ones), counters are cleared by a kernel, nothing is timed, and the
+// host neither waits nor checks the flag (afd_graph_status reads it).
 afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* forced_user, afd_result* out,
-               unsigned char* staging = nullptr) {
+               unsigned char* staging = nullptr, bool graph = false) {
   if (!p) return fail(AFD_E_INVALID, "plan is NULL");
   if (!signal) return fail(AFD_E_INVALID, "signal is NULL");
   if (!out) return fail(AFD_E_INVALID, "out is NULL");
@@ -644,6 +675,13 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   HIPCHK(hipSetDevice(p->device), "hipSetDevice");
 
   const bool sig_dev = is_device_pointer(signal);
+  if (graph) {
+    const void* dev[] = {signal, out->index, out->a, out->coef, out->energy, out->margin, out->remainder,
+                         out->recheck_count, out->flags, out->fp32_error};
+    for (const void* q : dev)
+      if (q && !is_device_pointer(q))
+        return fail(AFD_E_INVALID, "a captured decomposition needs device pointers for the signal and outputs");
+  }
   if (!sig_dev) {
     for (int64_t i = 0; i < 2 * c.N * B; ++i)
       if (!std::isfinite(signal[i])) return fail(AFD_E_NONFINITE, "signal holds NaN or Inf");
@@ -692,22 +730,37 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rec.N = N;
   rec.M = c.M;
   rec.steps = steps;
-  rec.idx = R.idx;
-  rec.a = R.a;
-  rec.coef = R.coef;
-  rec.energy = R.energy;
-  rec.margin = R.margin;
-  rec.kcount = R.kcount;
-  rec.flags = R.flags;
-  rec.fp32err = R.fp32err;
+  rec.idx = graph ? out->index : R.idx;
+  rec.a = graph ? out->a : R.a;
+  rec.coef = graph ? out->coef : R.coef;
+  rec.energy = graph ? out->energy : R.energy;
+  rec.margin = graph && out->margin ? out->margin : R.margin;
+  rec.kcount = graph && out->recheck_count ? out->recheck_count : R.kcount;
+  rec.flags = graph && out->flags ? out->flags : R.flags;
+  rec.fp32err = graph && out->fp32_error ? out->fp32_error : R.fp32err;
 
-  // flags and last-workgroup counters start at zero (also after an aborted call)
-  HIPCHK(hipMemsetAsync(nonfinite, 0, 4, s), "clearing flag");
-  HIPCHK(hipMemsetAsync(counters, 0, 4 * kNumCounters * size_t(B), s), "clearing counters");
-  if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.bar, 0, 8 * 16 * kBarGroups, s), "clearing counters");
-  if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.rqueue, 0, 4, s), "clearing counters");
-  if (c.big)
-    HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4, s), "clearing counters");
+  // flags and last-workgroup counters start at zero (also after an aborted
+  // call); in a captured graph by a kernel (no memset nodes)
+  if (graph) {
+    ZeroArgs z{};
+    auto add = [&](void* q, size_t bytes) {
+      z.p[z.n] = static_cast<unsigned int*>(q);
+      z.words[z.n] = int(bytes / 4);
+      ++z.n;
+    };
+    add(nonfinite, 4);
+    add(counters, 4 * kNumCounters * size_t(B));
+    if (c.adv) add(p->arena + p->L.bar, 8 * 16 * kBarGroups);
+    if (c.adv) add(p->arena + p->L.rqueue, 4);
+    if (c.big) add(p->arena + p->L.bcounters, 4);
+    HIPCHK(launch_zero(z, s), "k_zero");
+  } else {
+    HIPCHK(hipMemsetAsync(nonfinite, 0, 4, s), "clearing flag");
+    HIPCHK(hipMemsetAsync(counters, 0, 4 * kNumCounters * size_t(B), s), "clearing counters");
+    if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.bar, 0, 8 * 16 * kBarGroups, s), "clearing counters");
+    if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.rqueue, 0, 4, s), "clearing counters");
+    if (c.big) HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4, s), "clearing counters");
+  }
   HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N) * B, sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                         s),
          "copying signal");
@@ -771,6 +824,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     bp.winner = win;
     bp.probe = nullptr;
     bp.probe_out = p->at<double>(p->L.probe);
+    bp.border = p->at<int>(p->L.border);
   }
   const bool replay = forced_user != nullptr;
   PickArgs pk{};
@@ -790,7 +844,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   pk.flags = R.pflags;
 
   Timer tm{p};
-  tm.off = staging != nullptr;
+  tm.off = staging != nullptr || graph;
   UpdateArgs upd{};
   upd.radii = radii;
   upd.omega = omega;
@@ -820,14 +874,18 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
         bp.probe = p->forced + 2 * k;
       }
       if (c.big) {
-        for (int m0 = 0; m0 < c.M; m0 += c.chunk) {
+        // the radii with short spectra in one row launch, then the others in
+        // chunks through the intermediate (launch order in p->L.border)
+        bool first = true;
+        for (int m0 = 0; m0 < c.M;) {
+          const bool shorts = m0 < c.nshort;
+          const int nr = shorts ? c.nshort : (c.M - m0 < c.chunk ? c.M - m0 : c.chunk);
           bp.m0 = m0;
-          const bool first = m0 == 0;
           hipEvent_t r0, r1;
           HIPCHK(tm.pair(kTimeRows, &r0, &r1), "event");
-          HIPCHK(launch_big(c.logn, c.fp64, bp, c.M - m0 < c.chunk ? c.M - m0 : c.chunk, s, first ? e0 : nullptr,
-                            nullptr, r0, r1),
-                 "k_big");
+          HIPCHK(launch_big(c.logn, c.fp64, bp, nr, !shorts, s, first ? e0 : nullptr, nullptr, r0, r1), "k_big");
+          first = false;
+          m0 += nr;
         }
         HIPCHK(launch_big_merge(c.logn, c.fp64, bp, s, e1), "k_big_merge");
       } else {
@@ -845,6 +903,11 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
     upd.step = k;
     HIPCHK(launch_update(g64, g32, upd, B, s, u0, u1), "k_update");
+  }
+  if (graph) {
+    if (out->remainder)
+      HIPCHK(hipMemcpyAsync(out->remainder, g64, 16 * size_t(N) * B, hipMemcpyDeviceToDevice, s), "copy remainder");
+    return AFD_OK;
   }
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, nonfinite, 4, hipMemcpyDeviceToHost, s), "reading flag");
@@ -1063,6 +1126,83 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
 
 afd_status afd_decompose(afd_plan plan, const double* signal, int32_t steps, afd_result* out) {
   return run(plan, signal, steps, nullptr, out);
+}
+
+afd_status afd_graph_create(afd_plan plan, const double* signal, int32_t steps, const afd_result* out,
+                            afd_graph* graph) {
+  if (!graph) return fail(AFD_E_INVALID, "graph is NULL");
+  *graph = nullptr;
+  if (!plan) return fail(AFD_E_INVALID, "plan is NULL");
+  if (!out) return fail(AFD_E_INVALID, "out is NULL");
+  if (steps < 0) return fail(AFD_E_INVALID, "steps must be >= 0");
+  HIPCHK(hipSetDevice(plan->device), "hipSetDevice");
+  // the staging of the outputs the caller leaves null, allocated before the capture
+  afd_status st = ensure_res(plan, steps);
+  if (st != AFD_OK) return st;
+  afd_graph_s* g = new (std::nothrow) afd_graph_s();
+  if (!g) return fail(AFD_E_NOMEM, "host allocation failed");
+  g->plan = plan;
+  g->out = *out;
+  g->steps = steps;
+  hipStream_t cap = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "hipStreamCreateWithFlags");
+  }
+  // the plan's calls run on plan->stream: the capture swaps in its own stream
+  hipStream_t own = plan->stream;
+  plan->stream = cap;
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    afd_result o = *out;
+    st = run(plan, signal, steps, nullptr, &o, nullptr, true);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cap, &gr);
+    g->graph = gr;
+    if (st == AFD_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamEndCapture");
+    if (st == AFD_OK) {
+      e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
+    }
+  } else {
+    st = hip_fail(e, "hipStreamBeginCapture");
+  }
+  plan->stream = own;
+  (void)hipStreamDestroy(cap);
+  if (st != AFD_OK) {
+    afd_graph_destroy(g);
+    return st;
+  }
+  *graph = g;
+  g_last_error.clear();
+  return AFD_OK;
+}
+
+afd_status afd_graph_launch(afd_graph graph) {
+  if (!graph) return fail(AFD_E_INVALID, "graph is NULL");
+  HIPCHK(hipSetDevice(graph->plan->device), "hipSetDevice");
+  HIPCHK(hipGraphLaunch(graph->exec, graph->plan->stream), "hipGraphLaunch");
+  return AFD_OK;
+}
+
+afd_status afd_graph_status(afd_graph graph) {
+  if (!graph) return fail(AFD_E_INVALID, "graph is NULL");
+  afd_plan_s* p = graph->plan;
+  HIPCHK(hipSetDevice(p->device), "hipSetDevice");
+  HIPCHK(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+  int bad = 0;
+  HIPCHK(hipMemcpy(&bad, p->arena + p->L.nonfinite, 4, hipMemcpyDeviceToHost), "reading flag");
+  if (bad & 2) return fail(AFD_E_HIP, "a grid barrier of the step tail timed out");
+  if (bad) return fail(AFD_E_NONFINITE, "signal holds NaN or Inf");
+  return AFD_OK;
+}
+
+void afd_graph_destroy(afd_graph graph) {
+  if (!graph) return;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
 }
 
 afd_status afd_decompose_noalloc(afd_plan plan, const double* signal, int32_t steps, afd_result* out) {

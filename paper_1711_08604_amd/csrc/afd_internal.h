@@ -112,8 +112,9 @@ struct BigParams {
   const void* tw1;    // Stockham twiddles of the length-N1 transforms
   const void* tw2;    // Stockham twiddles of the length-N2 transforms
   void* z;            // [chunk][N1][N2] intermediate (T complex)
+  const int* border;  // [M] launch order of the radii: short spectra first, then long ones
   int M;
-  int m0;             // first radius of the chunk
+  int m0;             // position in border of the launch's first radius
   float tau_band;
   int recheck_k;
   void* blocks;       // [M][G] per-workgroup records (BlockList32 or BlockBest64)
@@ -140,11 +141,13 @@ struct BigGeom {
 };
 BigGeom big_geom(int logn, bool fp64);
 hipError_t setup_big_attributes();
-// One chunk of `nr` radii starting at p.m0: the column pass, then the row
-// pass with the selection.  e0 stamps the column pass's start, e1 the row
-// pass's end; r0 / r1 stamp the row pass alone.
-hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s, hipEvent_t e0 = nullptr,
-                      hipEvent_t e1 = nullptr, hipEvent_t r0 = nullptr, hipEvent_t r1 = nullptr);
+// The `nr` radii at launch positions p.m0.. (p.border): the column pass
+// (with `cols`; the radii with short spectra need none), then the row pass
+// with the selection.  e0 stamps the first launch's start, e1 the row pass's
+// end; r0 / r1 stamp the row pass alone.
+hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, bool cols, hipStream_t s,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, hipEvent_t r0 = nullptr,
+                      hipEvent_t r1 = nullptr);
 // After the last chunk of a step: the radius records into the winner (FP64)
 // or the short-list (FP32); e1 stamps its end.
 hipError_t launch_big_merge(int logn, bool fp64, const BigParams& p, hipStream_t s, hipEvent_t e1 = nullptr);
@@ -330,6 +333,14 @@ hipError_t launch_merge(bool fp64, const void* recs, const uint64_t* heads, cons
                         int logn, int recheck_k, float tau_band, unsigned int* flagword, CandList* cand, Winner* w,
                         int batch, hipStream_t s);
 hipError_t launch_pick(const PickArgs& a, int batch, hipStream_t s);
+// Up to 6 word ranges set to zero by one kernel (in place of memsets where a
+// call is captured into a graph).
+struct ZeroArgs {
+  unsigned int* p[6];
+  int words[6];
+  int n;
+};
+hipError_t launch_zero(const ZeroArgs& z, hipStream_t s);
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
                           double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s);
 hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, int batch, hipStream_t s,

@@ -82,7 +82,7 @@ __global__ __launch_bounds__((Big<T, LOGN>::THR_A)) void k_big_cols(BigParams p)
   extern __shared__ __align__(16) unsigned char smem[];
   const int ci = threadIdx.x / B::TPR1, t = threadIdx.x - ci * B::TPR1;
   const int l2 = blockIdx.x * B::CA + ci;
-  const int ml = blockIdx.y, m = p.m0 + ml;
+  const int ml = blockIdx.y, m = p.border[p.m0 + ml];
   if (p.lsig[m] <= B::N2) return;  // formed by the row pass (uniform)
 
   // weighted column x[l1] = r^(N2 l1) c_{N2 l1 + l2} (the factor r^l2 is applied after the transform)
@@ -182,7 +182,7 @@ void k_big_rows(BigParams p) {
   using B = Big<T, LOGN>;
   extern __shared__ __align__(16) unsigned char smem[];
   const int ri = threadIdx.x / B::TPR2, t0 = threadIdx.x - ri * B::TPR2;
-  const int ml = blockIdx.y, m = p.m0 + ml;
+  const int ml = blockIdx.y, m = p.border[p.m0 + ml];
 
   using S2 = Shape<B::L2, B::E2>;
   constexpr bool SPLIT = sizeof(T) == 8;
@@ -334,15 +334,18 @@ hipError_t setup_big_attributes() {
 }
 
 template <typename T, int LOGN>
-static hipError_t launch_big_t(const BigParams& p, int nr, hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipEvent_t r0,
-                               hipEvent_t r1) {
+static hipError_t launch_big_t(const BigParams& p, int nr, bool cols, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                               hipEvent_t r0, hipEvent_t r1) {
   using B = Big<T, LOGN>;
   if (nr < 1 || p.m0 < 0 || p.m0 + nr > p.M) return hipErrorInvalidValue;
-  launch_ev(k_big_cols<T, LOGN>, dim3(B::N2 / B::CA, nr), dim3(B::THR_A), uint32_t(B::lds_a), s, e0, nullptr, p);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  launch_ev(k_big_rows<T, LOGN, sizeof(T) == 4>, dim3(B::G, nr), dim3(B::THR_B), uint32_t(B::lds_b), s, r0,
-            r1 ? r1 : e1, p);
+  if (cols) {
+    launch_ev(k_big_cols<T, LOGN>, dim3(B::N2 / B::CA, nr), dim3(B::THR_A), uint32_t(B::lds_a), s, e0, nullptr, p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e0 = nullptr;
+  }
+  launch_ev(k_big_rows<T, LOGN, sizeof(T) == 4>, dim3(B::G, nr), dim3(B::THR_B), uint32_t(B::lds_b), s,
+            r0 ? r0 : e0, r1 ? r1 : e1, p);
   return hipGetLastError();
 }
 
@@ -365,12 +368,13 @@ hipError_t launch_big_merge(int logn, bool fp64, const BigParams& p, hipStream_t
   }
 }
 
-hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                      hipEvent_t r0, hipEvent_t r1) {
+hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, bool cols, hipStream_t s, hipEvent_t e0,
+                      hipEvent_t e1, hipEvent_t r0, hipEvent_t r1) {
   switch (logn) {
 #define X(L) \
   case L:    \
-    return fp64 ? launch_big_t<double, L>(p, nr, s, e0, e1, r0, r1) : launch_big_t<float, L>(p, nr, s, e0, e1, r0, r1);
+    return fp64 ? launch_big_t<double, L>(p, nr, cols, s, e0, e1, r0, r1)                         \
+                : launch_big_t<float, L>(p, nr, cols, s, e0, e1, r0, r1);
     AFD_BIG_LOGN_CASES(X)
 #undef X
     default:

@@ -294,11 +294,16 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
                                                  BlockList32* __restrict__ out, uint64_t* head, MergeScratch* S) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = nwaves();
-  float pm = -1.f;
-  uint32_t fl = 0;
-  for (int b = tid; b < n; b += blockDim.x) {
-    fl |= ld_agent(&L[b].flags);
-    if (ld_agent(&L[b].count) > 0) pm = fmaxf(pm, ld_agent(&L[b].pmax));
+  // every member's header and head key in one round trip (n <= blockDim.x)
+  uint32_t cm = 0, fl = 0;
+  float pmm = -1.f;
+  uint64_t hm = 0;
+  if (tid < n) {
+    const BlockList32* B = L + tid;
+    cm = ld_agent(&B->count);
+    fl = ld_agent(&B->flags);
+    pmm = ld_agent(&B->pmax);
+    hm = ld_agent(&B->keys[0]);
   }
   if (tid == 0) {
     S->sflags = 0;
@@ -307,16 +312,16 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
     S->sband = 0;
     S->hcut = 0;
   }
-  const float pg = block_max_f32(pm, S->wf);  // its barriers order the initialisation above
+  const float pg = block_max_f32(cm > 0 ? pmm : -1.f, S->wf);  // its barriers order the initialisation above
   if (fl) atomicOr(&S->sflags, fl);
   const float theta = pg - pg * tau_band;
-  // the kListC-th largest head among the members that reach the band (0 if fewer)
-  uint64_t hd = 0;
-  if (tid < n && ld_agent(&L[tid].count) > 0) {
-    hd = ld_agent(&L[tid].keys[0]);
-    if (!(key_p(hd) >= theta)) hd = 0;
+  // the kListC-th largest head among the members that reach the band (0 if
+  // fewer), and the list length of each member that reaches it (0: skipped)
+  const uint64_t hd = cm > 0 && key_p(hm) >= theta ? hm : 0;
+  if (tid < n) {
+    S->buf[tid] = hd;
+    S->cblk[tid] = cm > 0 && pmm >= theta ? cm : 0u;
   }
-  if (tid < n) S->buf[tid] = hd;
   __syncthreads();
   if (hd) {
     uint32_t rank = 0;
@@ -325,11 +330,11 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
   }
   __syncthreads();
   const uint64_t hcut = S->hcut;
-  // one wave per member list that reaches the cut
+  // one wave per member list that reaches the band
   for (int i = wave; i < n; i += nw) {
     const BlockList32* B = L + i;
-    const uint32_t cnt = ld_agent(&B->count);
-    if (cnt == 0 || !(ld_agent(&B->pmax) >= theta)) continue;  // uniform over the wave
+    const uint32_t cnt = S->cblk[i];
+    if (cnt == 0) continue;  // uniform over the wave
     const uint64_t k = lane < int(cnt) ? ld_agent(&B->keys[lane]) : 0;
     const bool inband = lane < int(cnt) && key_p(k) >= theta;
     const uint64_t bm = __ballot(inband);

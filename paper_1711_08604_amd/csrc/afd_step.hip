@@ -12,18 +12,18 @@
 //               winner (FP64) or the short-list (FP32) in a launch of its own
 //   k_pick      a replayed step: the selection's own choice is recorded and
 //               the forced point takes its place
+//   k_zero      counters cleared by a kernel in a captured decomposition
 #include "afd_update.h"
 
 namespace afd {
 
 constexpr int kUpdThreads = 256;
 constexpr int kUpdPerThread = 4;
-constexpr int kRecheckBlocksX = 16;
 
 int update_blocks(int N) { return (N + kUpdThreads * kUpdPerThread - 1) / (kUpdThreads * kUpdPerThread); }
 int recheck_chunks(int N) { return N >= 2048 ? N / 2048 : 1; }
 
-// Batched launches: signal b = blockIdx.y (blockIdx.z in k_recheck) works on
+// Batched launches: signal b = blockIdx.y works on
 // its own slices of every per-signal buffer.
 __global__ __launch_bounds__(256) void k_prepare(double* __restrict__ g64, float* __restrict__ g32, int N,
                                                  double* __restrict__ epart, int* __restrict__ nonfinite,
@@ -73,50 +73,81 @@ __global__ void k_force(const int32_t* __restrict__ forced, int fstride, int ste
   }
 }
 
-// partial sums over a chunk of samples of G[n] / (1 - r_m e^{2 pi i (j - n)/N})
+// Partial sums over a chunk of samples of G[n] / (1 - r_m e^{2 pi i (j - n)/N})
+// for every short-listed point (m, j): each workgroup holds its chunk's
+// samples and unit roots in registers and runs through the candidates, with
+// e^{2 pi i (j - n)/N} = e^{2 pi i j/N} conj(e^{2 pi i n/N}), so the samples
+// are read once per step rather than once per candidate.  The wave sums of
+// every candidate meet in LDS and are added in wave order after the loop.
+constexpr int kRecheckPerThread = 8;  // chunk of 2048 samples over 256 threads
 __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ cand, const double* __restrict__ g,
                                                  const double* __restrict__ omega, const double* __restrict__ radii,
                                                  int N, int logn, int nch, double* __restrict__ partials,
                                                  unsigned int* __restrict__ counter, Winner* __restrict__ w) {
+  __shared__ double wsum[kKMax][4][2];  // [candidate][wave] (re, im)
   __shared__ double wd[16];
   __shared__ Best bb[16];
   __shared__ int s_last;
-  const int chunk = blockIdx.y;
+  const int chunk = blockIdx.x;
   const int cl = N / nch;
-  const int b = blockIdx.z;
+  const int b = blockIdx.y;
+  const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
   cand += b;
   g += 2 * size_t(N) * b;
   partials += 2 * size_t(kKMax) * size_t(nch) * b;
   counter += b;
   w += b;
-  const int count = cand->count;
-  for (int i = blockIdx.x; i < count; i += gridDim.x) {
-    const uint32_t f = key_f(cand->keys[i]);
+  const int count = min(max(cand->count, 0), kKMax);
+  double gx[kRecheckPerThread], gy[kRecheckPerThread], ox[kRecheckPerThread], oy[kRecheckPerThread];
+#pragma unroll
+  for (int q = 0; q < kRecheckPerThread; ++q) {
+    const int i = tid + 256 * q;
+    const int n = chunk * cl + i;
+    const bool in = i < cl;
+    gx[q] = in ? g[2 * n] : 0.0;
+    gy[q] = in ? g[2 * n + 1] : 0.0;
+    ox[q] = in ? omega[2 * n] : 1.0;
+    oy[q] = in ? omega[2 * n + 1] : 0.0;
+  }
+  for (int c = 0; c < count; ++c) {
+    const uint32_t f = key_f(cand->keys[c]);
     const int m = int(f >> logn), j = int(f & uint32_t(N - 1));
     const double r = radii[m];
+    const double wjx = omega[2 * j], wjy = omega[2 * j + 1];
     double ax = 0.0, ay = 0.0;
-    for (int n = chunk * cl + threadIdx.x; n < (chunk + 1) * cl; n += blockDim.x) {
-      const int d = (j - n) & (N - 1);
-      const double ox = omega[2 * d], oy = omega[2 * d + 1];
-      const double dx = fma(-r, ox, 1.0), dy = -r * oy;
+#pragma unroll
+    for (int q = 0; q < kRecheckPerThread; ++q) {
+      // e^{2 pi i (j - n)/N}
+      const double ux = fma(wjx, ox[q], wjy * oy[q]);
+      const double uy = fma(wjy, ox[q], -wjx * oy[q]);
+      const double dx = fma(-r, ux, 1.0), dy = -r * uy;
       const double inv = 1.0 / fma(dx, dx, dy * dy);
-      const double gx = g[2 * n], gy = g[2 * n + 1];
-      ax += fma(gx, dx, gy * dy) * inv;
-      ay += fma(gy, dx, -gx * dy) * inv;
+      ax += fma(gx[q], dx, gy[q] * dy) * inv;
+      ay += fma(gy[q], dx, -gx[q] * dy) * inv;
     }
-    const double sx = block_sum_f64(ax, wd);
-    const double sy = block_sum_f64(ay, wd);
-    if (threadIdx.x == 0) {
-      st_agent(partials + 2 * (size_t(i) * nch + chunk), sx);
-      st_agent(partials + 2 * (size_t(i) * nch + chunk) + 1, sy);
+    ax = wave_sum_f64(ax);
+    ay = wave_sum_f64(ay);
+    if (lane == 0) {
+      wsum[c][wave][0] = ax;
+      wsum[c][wave][1] = ay;
     }
   }
-  if (!last_arrival(counter, gridDim.x * gridDim.y, &s_last)) return;
+  __syncthreads();
+  for (int c = tid; c < count; c += int(blockDim.x)) {
+    double sx = 0.0, sy = 0.0;
+    for (int v = 0; v < nwaves(); ++v) {
+      sx += wsum[c][v][0];
+      sy += wsum[c][v][1];
+    }
+    st_agent(partials + 2 * (size_t(c) * nch + chunk), sx);
+    st_agent(partials + 2 * (size_t(c) * nch + chunk) + 1, sy);
+  }
+  if (!last_arrival(counter, gridDim.x, &s_last)) return;
   static_assert(kKMax <= 256, "one candidate per thread");
   uint64_t key = 0;
   double rk = 0.0;
-  if (int(threadIdx.x) < count) {
-    key = cand->keys[threadIdx.x];
+  if (tid < count) {
+    key = cand->keys[tid];
     rk = radii[key_f(key) >> logn];
   }
   winner_from_partials(count, cand->flags, key, rk, partials, N, logn, nch, w, bb, wd);
@@ -181,6 +212,11 @@ __global__ __launch_bounds__(64) void k_pick(PickArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_zero(ZeroArgs z) {
+  for (int r = 0; r < z.n; ++r)
+    for (int i = int(threadIdx.x); i < z.words[r]; i += int(blockDim.x)) z.p[r][i] = 0u;
+}
+
 __global__ __launch_bounds__(256) void k_update(double* __restrict__ g64, float* __restrict__ g32, UpdateArgs U) {
   __shared__ double wd[16];
   __shared__ int s_last;
@@ -239,6 +275,11 @@ hipError_t launch_merge(bool fp64, const void* recs, const uint64_t* heads, cons
   return hipGetLastError();
 }
 
+hipError_t launch_zero(const ZeroArgs& z, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, z);
+  return hipGetLastError();
+}
+
 hipError_t launch_pick(const PickArgs& a, int batch, hipStream_t s) {
   hipLaunchKernelGGL(k_pick, dim3(batch), dim3(64), 0, s, a);
   return hipGetLastError();
@@ -247,8 +288,9 @@ hipError_t launch_pick(const PickArgs& a, int batch, hipStream_t s) {
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
                           double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s) {
   const int nch = recheck_chunks(N);
-  hipLaunchKernelGGL(k_recheck, dim3(kRecheckBlocksX, nch, batch), dim3(256), 0, s, cand, g, omega, radii, N,
-                     ilog2i(N), nch, partials, counter, w);
+  if (N / nch > 256 * kRecheckPerThread) return hipErrorInvalidValue;  // a chunk's samples fit the registers
+  hipLaunchKernelGGL(k_recheck, dim3(nch, batch), dim3(256), 0, s, cand, g, omega, radii, N, ilog2i(N), nch, partials,
+                     counter, w);
   return hipGetLastError();
 }
 

@@ -95,9 +95,10 @@ def test_workspace_bytes_scales():
 
 
 def test_workspace_bytes_two_pass():
-    """N = 2^20: the radius transforms run in two passes over chunks of radii
-    whose intermediate is bounded (1 GiB), so the workspace does not grow
-    with M * N; besides it, a step keeps one selection record per row
+    """N = 2^20: only the radii with long spectra run in two passes, over
+    chunks whose intermediate is bounded (1 GiB; 64 of the 84 such radii in
+    double precision, all 59 in single precision), so the workspace does not
+    grow with M * N; besides it, a step keeps one selection record per row
     workgroup of every radius (M x 128 lists of 528 bytes in single
     precision, M x 64 bests of 40 bytes in double precision)."""
     afd, lib = _lib()
@@ -107,7 +108,7 @@ def test_workspace_bytes_two_pass():
         d, keep = _desc(afd, n=1 << 20, radii=r, precision=prec)
         out[prec] = lib.afd_workspace_bytes(ctypes.byref(d))
     assert (1 << 30) <= out[0] < (1200 << 20), out
-    assert (1 << 30) + 2000 * 128 * 528 <= out[1] < (1200 << 20) + 2000 * 128 * 528, out
+    assert 59 * (8 << 20) + 2000 * 128 * 528 <= out[1] < 59 * (8 << 20) + 2000 * 128 * 528 + (200 << 20), out
     d, keep = _desc(afd, n=1 << 15, radii=r[:7], precision=1)
     assert 0 < lib.afd_workspace_bytes(ctypes.byref(d)) < (16 << 20)
 
