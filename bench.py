@@ -21,10 +21,12 @@ transforms) under "single16k".
 (8..32 kernels, |b| <= 0.95), M = 512, 30 steps, decomposed together.
 `--workload small1k` times the small latency-bound case: N = 1024, M = 100
 radii m/100, 10 steps, FP64 only, 200 solves for p50/p99.
-`--workload serve` runs the served stream: requests with N log-uniform over
-2^10..2^16, M = N/8, 5..100 steps, signals as in the N = 16384 workload,
-through the continuous-batching server, first all at once (throughput), then
-with Poisson arrivals at 0.7x that request rate (p50/p99 latency).
+`--workload serve` runs the served stream: 2000 requests with N log-uniform
+over 2^10..2^16, M = N/8, 5..100 steps, signals as in the N = 16384
+workload, one after another on one stream (the plain per-signal method), then
+through the continuous-batching server all at once (throughput) and with
+Poisson arrivals at 0.3, 0.5, 0.7 and 0.9 times that request rate (p50/p99
+latency).
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 """
@@ -308,7 +310,11 @@ def cpu_baseline(g, radii, steps_sample, total_steps):
 
 
 def run_serve(args, np, torch, W):
-    """The served stream through paper_1711_08604_amd.serve.Server (FP32+recheck)."""
+    """The served stream through paper_1711_08604_amd.serve.Server (FP32+recheck):
+    the plain per-signal method (the requests one after another on one
+    stream), then the server with every request present at once (saturated
+    throughput), then Poisson arrivals at 0.3, 0.5, 0.7 and 0.9 times that
+    request rate (p50/p99 latency from arrival to completion)."""
     from paper_1711_08604_amd.serve import Server
     rng = np.random.default_rng(20171108)
     reqs = []
@@ -335,8 +341,9 @@ def run_serve(args, np, torch, W):
                 futs.append(srv.submit(g, r, s))
             out = [f.result() for f in futs]
             wall = time.perf_counter() - t0
+            shared = (srv.shared_calls, srv.shared_members)
         lat = [o.latency for o in out]
-        return wall, lat
+        return wall, lat, shared
 
     # the plain per-signal method: the same requests one after another on one stream
     from paper_1711_08604_amd import Plan
@@ -353,30 +360,39 @@ def run_serve(args, np, torch, W):
     wall_seq = time.perf_counter() - t0
     for p in plans.values():
         p.close()
-    log(f"bench: serve sequential (one stream) {evals / wall_seq:.3e} evals/s")
+    log(f"bench: serve sequential (one stream) {evals / wall_seq:.3e} evals/s, {wall_seq:.1f} s")
 
-    wall0, lat0 = stream([0.0] * len(reqs))
+    wall0, lat0, shared0 = stream([0.0] * len(reqs))
     rate = len(reqs) / wall0
-    lam = 0.7 * rate
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
-    arrivals -= arrivals[0]
-    wall1, lat1 = stream(list(arrivals))
-    log(f"bench: serve saturated {evals / wall0:.3e} evals/s; Poisson at {lam:.1f} req/s: "
-        f"p50 {percentile(lat1, 0.5) * 1e3:.1f} ms p99 {percentile(lat1, 0.99) * 1e3:.1f} ms")
+    log(f"bench: serve saturated {evals / wall0:.3e} evals/s ({rate:.1f} req/s), p50 "
+        f"{percentile(lat0, 0.5) * 1e3:.0f} ms, p99 {percentile(lat0, 0.99) * 1e3:.0f} ms")
+    sweep = {}
+    for frac in (0.3, 0.5, 0.7, 0.9):
+        lam = frac * rate
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
+        arrivals -= arrivals[0]
+        wall, lat, shared = stream(list(arrivals))
+        sweep[str(frac)] = {"rate_req_s": lam, "wall_s": wall, "evals_per_s": evals / wall,
+                            "p50_ms": percentile(lat, 0.5) * 1e3, "p99_ms": percentile(lat, 0.99) * 1e3,
+                            "shared_calls": shared[0], "shared_member_segments": shared[1]}
+        log(f"bench: serve Poisson {frac}x = {lam:.1f} req/s: p50 {sweep[str(frac)]['p50_ms']:.1f} ms, "
+            f"p99 {sweep[str(frac)]['p99_ms']:.1f} ms")
+    at07 = sweep["0.7"]
     return {
         "metric": METRIC, "value": evals / wall0, "unit": "grid evals/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": wall0 * 1e3, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"served stream: {len(reqs)} requests, N log-uniform over 2^10..2^16, M=N/8, steps "
-                               "uniform in 5..100, signals as the default workload, 8 slots, FP32+recheck",
+                               "uniform in 5..100, signals as the N=16384 workload, 8 slots, FP32+recheck",
                    "requests": len(reqs), "grid_evals": evals},
-        "p50_ms": percentile(lat1, 0.5) * 1e3, "p99_ms": percentile(lat1, 0.99) * 1e3,
+        "p50_ms": at07["p50_ms"], "p99_ms": at07["p99_ms"],
         "serve": {"sequential_evals_per_s": evals / wall_seq, "sequential_wall_s": wall_seq,
                   "sequential_p50_ms": percentile(seq_lat, 0.5) * 1e3,
                   "sequential_p99_ms": percentile(seq_lat, 0.99) * 1e3,
-                  "saturated_wall_s": wall0, "saturated_p50_ms": percentile(lat0, 0.5) * 1e3,
-                  "saturated_p99_ms": percentile(lat0, 0.99) * 1e3, "poisson_rate_req_s": lam,
-                  "poisson_wall_s": wall1, "poisson_evals_per_s": evals / wall1},
+                  "saturated_wall_s": wall0, "saturated_evals_per_s": evals / wall0,
+                  "saturated_p50_ms": percentile(lat0, 0.5) * 1e3, "saturated_p99_ms": percentile(lat0, 0.99) * 1e3,
+                  "saturated_shared_calls": shared0[0], "saturated_shared_member_segments": shared0[1],
+                  "poisson": sweep},
     }
 
 
@@ -426,7 +442,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "serve"],
                     default="chirp1m")
-    ap.add_argument("--requests", type=int, default=300, help="serve: requests in the stream")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
     ap.add_argument("--steps", type=int, default=None, help="timed decompositions (chirp1m: 5)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed decompositions (chirp1m: 1)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

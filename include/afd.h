@@ -74,6 +74,12 @@ typedef struct {
   int32_t batch;          /* signals per call, 1..65535 (0 -> 1): independent decompositions of
                              signals with this N and these radii, run together (every kernel
                              of a step covers all of them).  batch > 1 needs N <= 2^14.        */
+  int32_t concurrent;     /* 1: the plan's stream runs beside other streams' kernels on the
+                             device (a server).  For one signal with 2^10 <= N <= 2^14 the step
+                             tail then runs as three launches instead of one launch whose grid
+                             barriers need every workgroup of the launch resident at once.
+                             Results are the same bit for bit.  0: the stream has the device's
+                             resources to itself while the plan runs.                          */
 } afd_plan_desc;
 
 /* Per-decomposition outputs.  Caller-owned; each pointer may be host memory

@@ -39,6 +39,7 @@ class PlanDesc(ctypes.Structure):
         ("first_a_zero", ctypes.c_int32),
         ("recheck_band", ctypes.c_double),
         ("batch", ctypes.c_int32),
+        ("concurrent", ctypes.c_int32),
     ]
 
 
@@ -124,7 +125,7 @@ def _check(status: int):
         raise AfdError(status, msg)
 
 
-def _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch=1):
+def _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch=1, concurrent=False):
     radii = np.ascontiguousarray(np.asarray(radii, dtype=np.float64))
     d = PlanDesc()
     d.n = int(n)
@@ -135,6 +136,7 @@ def _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch
     d.first_a_zero = 1 if first_a_zero else 0
     d.recheck_band = float(recheck_band)
     d.batch = int(batch)
+    d.concurrent = 1 if concurrent else 0
     return d, radii
 
 
@@ -177,12 +179,15 @@ class Plan:
     batch > 1 decomposes that many signals of length N together."""
 
     def __init__(self, n, radii, precision="fp64", recheck_k=8, first_a_zero=False, recheck_band=0.0,
-                 stream=None, batch=1):
+                 stream=None, batch=1, concurrent=False):
+        """`concurrent`: the stream runs beside other streams' work on the device
+        (no step-tail grid barriers, see afd_plan_desc.concurrent)."""
         self._lib = load_library()
         self.n = int(n)
         self.precision = precision
         self.batch = int(batch)
-        d, self._radii = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, self.batch)
+        d, self._radii = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, self.batch,
+                                    concurrent)
         self.m = int(self._radii.shape[0])
         self._stream = stream
         h = ctypes.c_void_p()

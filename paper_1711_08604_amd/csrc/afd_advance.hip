@@ -479,12 +479,13 @@ void advance_twiddles(int l, double* out) {
 }
 
 template <typename T, int LOGN>
-static hipError_t launch_advance_t(const AdvanceArgs& a0, int batch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static hipError_t launch_advance_t(const AdvanceArgs& a0, int batch, bool fused, hipStream_t s, hipEvent_t e0,
+                                   hipEvent_t e1) {
   using S = AdvShape<LOGN>;
   constexpr uint32_t lds = uint32_t(S::template lds_bytes<T>());
   AdvanceArgs a = a0;
   const bool recheck = a.update && a.recheck;
-  if (batch == 1) {
+  if (batch == 1 && fused) {
     a.phase = -1;
     launch_ev(k_advance<T, LOGN>, dim3(recheck ? S::GA : S::NB, 1), dim3(kAdvThreads), lds, s, e0, e1, a);
     return hipGetLastError();
@@ -508,12 +509,13 @@ void advance_bar_advance(int logn, AdvanceArgs& a) {
     a.bar_base[k] += (recheck ? bar_group_count(g.ga, k) : 0ull) + bar_group_count(g.nb, k);
 }
 
-hipError_t launch_advance(int logn, bool fp64, const AdvanceArgs& a, int batch, hipStream_t s, hipEvent_t e0,
-                          hipEvent_t e1) {
+hipError_t launch_advance(int logn, bool fp64, const AdvanceArgs& a, int batch, bool fused, hipStream_t s,
+                          hipEvent_t e0, hipEvent_t e1) {
   switch (logn) {
 #define X(L) \
   case L:    \
-    return fp64 ? launch_advance_t<double, L>(a, batch, s, e0, e1) : launch_advance_t<float, L>(a, batch, s, e0, e1);
+    return fp64 ? launch_advance_t<double, L>(a, batch, fused, s, e0, e1)                              \
+                : launch_advance_t<float, L>(a, batch, fused, s, e0, e1);
     X(10) X(11) X(12) X(13) X(14)
 #undef X
     default:

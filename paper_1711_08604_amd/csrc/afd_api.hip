@@ -251,6 +251,7 @@ struct afd_plan_s {
   int recheck_k = 8;
   float tau_band = 1e-5f;
   bool first_a_zero = false;
+  bool concurrent = false;  // the stream runs beside other streams' kernels: no grid barriers
   int rslots = 0;  // radius workgroups resident at once (queued launches), 0: none
   int zero_m = -1;
   unsigned char* arena = nullptr;
@@ -607,9 +608,11 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
   a.flagword = p->at<unsigned int>(p->L.counters) + 4 * B;
   a.R = rec;
   a.M = c.M;
+  // one signal on a stream that has the device to itself: one launch with grid barriers
+  const bool fused = B == 1 && !p->concurrent;
   auto advance = [&](hipEvent_t e0, hipEvent_t e1) -> hipError_t {
-    const hipError_t e = launch_advance(c.logn, c.fp64, a, B, s, e0, e1);
-    if (B == 1) advance_bar_advance(c.logn, a);
+    const hipError_t e = launch_advance(c.logn, c.fp64, a, B, fused, s, e0, e1);
+    if (fused) advance_bar_advance(c.logn, a);
     return e;
   };
   if (steps > 0 && !forced_at(0)) {
@@ -1088,6 +1091,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
   p->recheck_k = desc->recheck_k == 0 ? 8 : desc->recheck_k;
   p->tau_band = desc->recheck_band == 0.0 ? default_tau_band(cfg.logn) : float(desc->recheck_band);
   p->first_a_zero = desc->first_a_zero != 0;
+  p->concurrent = desc->concurrent != 0;
   for (int i = 0; i < desc->m; ++i)
     if (desc->radii[i] == 0.0) {
       p->zero_m = i;

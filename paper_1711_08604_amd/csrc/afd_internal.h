@@ -255,8 +255,9 @@ AdvGeom advance_geom(int logn);
 void advance_twiddles(int l, double* out_interleaved);
 // Add the grid barrier arrivals of one launch_advance with batch 1 to a.bar_base.
 void advance_bar_advance(int logn, AdvanceArgs& a);
-// One launch with grid barriers for batch 1; one launch per phase otherwise.
-hipError_t launch_advance(int logn, bool fp64, const AdvanceArgs& a, int batch, hipStream_t s,
+// One launch with grid barriers for batch 1 when `fused`; one launch per
+// phase otherwise (the barriers need every workgroup resident at once).
+hipError_t launch_advance(int logn, bool fp64, const AdvanceArgs& a, int batch, bool fused, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Geometry of the LDS-resident transform for 2^logn points.

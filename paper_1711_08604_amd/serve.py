@@ -19,7 +19,14 @@ that arrived meanwhile and retires the ones that are done.  A member's next
 segment starts from the remainder its last one returned; each AFD step
 depends on the remainder alone, so the segments concatenate to the
 decomposition of the whole request.  Batches are padded with zero signals
-to a power of two, so a group reuses a few plans.
+to a power of two, so a group reuses a few plans.  With the server's own
+device streams a member's remainder and its segments' outputs stay in device
+memory between segments (gathered into the batch's input on the device);
+only the finished request is copied to the host.
+
+Plans are created with `concurrent=True`: their streams run beside other
+slots' kernels, so no launch of theirs waits at a grid barrier for
+workgroups that other streams keep from becoming resident.
 
 The plan of a request (or of a group) is the same object a caller would
 build, and the kernels are deterministic (a signal's result in a batch
@@ -58,24 +65,39 @@ class _Member:
     req: Request
     fut: Future
     started: float
-    g: np.ndarray               # the remainder the next segment starts from
+    g: object                   # the remainder the next segment starts from (numpy, or a device tensor)
     left: int                   # AFD steps still to run
     parts: list = field(default_factory=list)
 
 
+def _is_tensor(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
 def _member_result(res, i: int, batched: bool):
-    """Signal i of a (batched) Result, copied out of the batch's arrays."""
+    """Signal i of a (batched) Result: views of the batch's arrays (device
+    tensors stay on the device; each call's outputs are fresh arrays)."""
+    if _is_tensor(res.index):
+        return Result(**{k: (getattr(res, k)[i] if batched else getattr(res, k)) for k in RESULT_FIELDS})
     return Result(**{k: np.array(getattr(res, k)[i] if batched else getattr(res, k)) for k in RESULT_FIELDS})
 
 
 def _concat(parts) -> "Result":
-    """The segments of one request as one decomposition: per-step arrays
-    concatenated; energies E_0 of the first segment, then each segment's
-    E_1.. (its own E_0 is the previous segment's last); the last remainder."""
-    out = {k: np.concatenate([getattr(p, k) for p in parts]) for k in RESULT_FIELDS
-           if k not in ("energy", "remainder")}
-    out["energy"] = np.concatenate([parts[0].energy] + [p.energy[1:] for p in parts[1:]])
+    """The segments of one request as one decomposition (numpy): per-step
+    arrays concatenated; energies E_0 of the first segment, then each
+    segment's E_1.. (its own E_0 is the previous segment's last); the last
+    remainder.  Device segments are joined on the device and copied once."""
+    on_dev = _is_tensor(parts[0].index)
+    if on_dev:
+        import torch
+        cat = torch.cat
+    else:
+        cat = np.concatenate
+    out = {k: cat([getattr(p, k) for p in parts]) for k in RESULT_FIELDS if k not in ("energy", "remainder")}
+    out["energy"] = cat([parts[0].energy] + [p.energy[1:] for p in parts[1:]])
     out["remainder"] = parts[-1].remainder
+    if on_dev:
+        out = {k: v.cpu().numpy() for k, v in out.items()}
     return Result(**out)
 
 
@@ -131,8 +153,11 @@ class Server:
             dev = torch.device(device)
             self._torch_streams = [torch.cuda.Stream(device=dev) for _ in range(self.slots)]
             self._streams = [st.cuda_stream for st in self._torch_streams]
+            self._device = dev
         else:
             self._streams = list(streams)
+            self._torch_streams = None
+            self._device = None  # caller's streams: groups keep their remainders on the host
         self._closed = False
         self._busy = 0
         self.peak_used = 0                   # largest HBM accounted at once (bytes)
@@ -293,12 +318,10 @@ class Server:
                         return
                 nb = _bucket(len(members))
                 if nb not in plans:
-                    plans[nb] = Plan(n, radii, precision=precision, stream=self._streams[slot], batch=nb)
+                    plans[nb] = Plan(n, radii, precision=precision, stream=self._streams[slot], batch=nb,
+                                     concurrent=True)
                 seg = min(self.segment, min(m.left for m in members))
-                sig = np.zeros((nb, n), dtype=np.complex128)
-                for i, m in enumerate(members):
-                    sig[i] = m.g
-                res = plans[nb].decompose(sig if nb > 1 else sig[0], seg)
+                res = self._segment(slot, plans[nb], members, nb, n, seg)
                 self.shared_calls += 1
                 self.shared_members += len(members)
                 for i, m in enumerate(members):
@@ -307,9 +330,10 @@ class Server:
                     m.g = part.remainder
                     m.left -= seg
                 done = [m for m in members if m.left == 0]
-                members = [m for m in members if m.left > 0]
                 for m in done:
-                    m.fut.set_result(Served(_concat(m.parts), m.req.submitted, m.started, time.perf_counter(), slot))
+                    out = Served(_concat(m.parts), m.req.submitted, m.started, time.perf_counter(), slot)
+                    members = [x for x in members if x is not m]
+                    m.fut.set_result(out)
                     with self._lock:
                         self._busy -= 1
                         self._lock.notify_all()
@@ -329,6 +353,25 @@ class Server:
                 self._free_slots.append(slot)
                 self._lock.notify_all()
 
+    def _segment(self, slot, plan, members, nb: int, n: int, seg: int):
+        """One call of the batched plan over the members' remainders (zero
+        padding to nb signals): on the device when the server owns its
+        streams (torch work on the slot's stream, in order with the plan's
+        kernels), else through host memory."""
+        if self._device is None:
+            sig = np.zeros((nb, n), dtype=np.complex128)
+            for i, m in enumerate(members):
+                sig[i] = m.g
+            return plan.decompose(sig if nb > 1 else sig[0], seg)
+        import torch
+        with torch.cuda.stream(self._torch_streams[slot]):
+            sig = torch.zeros((nb, n), dtype=torch.complex128, device=self._device)
+            for i, m in enumerate(members):
+                if not torch.is_tensor(m.g):
+                    m.g = torch.from_numpy(m.g).to(self._device, non_blocking=False)
+                sig[i].copy_(m.g)
+            return plan.decompose(sig if nb > 1 else sig[0], seg)
+
     def _run(self, slot: int, req: Request, need: int, key, fut: Future):
         started = time.perf_counter()
         try:
@@ -336,7 +379,8 @@ class Server:
             if key in cache:
                 plan, _ = cache.pop(key)
             else:
-                plan = Plan(req.signal.shape[0], req.radii, precision=req.precision, stream=self._streams[slot])
+                plan = Plan(req.signal.shape[0], req.radii, precision=req.precision, stream=self._streams[slot],
+                            concurrent=True)
             cache[key] = (plan, need)  # most recently used last
             res = plan.decompose(req.signal, req.steps)
             fut.set_result(Served(res, req.submitted, started, time.perf_counter(), slot))

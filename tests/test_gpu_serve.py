@@ -36,11 +36,22 @@ def _alone(g, radii, steps, prec):
         return p.decompose(g, steps)
 
 
+def _large_requests():
+    """N = 2^15 and 2^16 (M = N/8): two-pass radius transforms on slots of their own."""
+    out = []
+    for i, (k, steps, prec) in enumerate(((15, 4, "fp32"), (16, 3, "fp64"), (15, 3, "fp64"), (16, 4, "fp32"))):
+        g, radii, _ = W.shaped_like_config2(1 << k, (1 << k) // 8, steps, item=2000 + i)
+        out.append((g, radii, steps, prec))
+    return out
+
+
 def test_mix_equals_alone_and_oracle():
     """Requests of one shape share launches: segments of 4 AFD steps of a
     batched plan, members joining (also while the group runs) and leaving
-    between segments."""
+    between segments; requests of N = 2^15 and 2^16 run beside them on slots
+    of their own."""
     reqs = _requests(24)
+    reqs = reqs[:6] + _large_requests()[:2] + reqs[6:18] + _large_requests()[2:] + reqs[18:]
     with Server(slots=4, segment=4) as srv:
         futs = []
         for i, r in enumerate(reqs):
@@ -56,8 +67,9 @@ def test_mix_equals_alone_and_oracle():
         alone = _alone(g, radii, steps, prec)
         for k in FIELDS:
             np.testing.assert_array_equal(getattr(s.result, k), getattr(alone, k), err_msg=f"request {i} field {k}")
-        if i % 4 == 0:
+        if i % 4 == 0 and g.shape[0] <= 4096:
             compare(s.result, O.decompose(g, radii, steps), TOL[prec], signal=g, radii=radii)
+    assert any(g.shape[0] >= 1 << 15 for g, _, _, _ in reqs)
 
 
 def test_admission_respects_budget():

@@ -19,7 +19,7 @@ class FakePlan:
     built = 0
     lock = threading.Lock()
 
-    def __init__(self, n, radii, precision="fp32", stream=None, batch=1):
+    def __init__(self, n, radii, precision="fp32", stream=None, batch=1, concurrent=False):
         with FakePlan.lock:
             FakePlan.built += 1
         self.n = n
@@ -89,7 +89,7 @@ class HalvingPlan:
     calls = []
     lock = threading.Lock()
 
-    def __init__(self, n, radii, precision="fp32", stream=None, batch=1):
+    def __init__(self, n, radii, precision="fp32", stream=None, batch=1, concurrent=False):
         self.n, self.batch = n, batch
 
     def _one(self, x, steps):
