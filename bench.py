@@ -15,8 +15,9 @@ synthetic); its radius transforms run beyond the LDS (one row pass for short
 spectra, two passes through HBM for the longest).  `value` is the FP64
 path; the FP32 + double re-check path is under "fp32", and the N = 16384,
 M = 1000, 50-step workload (40 Szego kernels + noise at 30 dB; LDS-resident
-transforms) under "single16k".
-`--workload single16k` times that workload alone.
+transforms) under "single16k", and the same recipe at N = 3^8 = 6561 (the
+radix-3 transforms) under "tern6561".
+`--workload single16k` (or `tern6561`) times that workload alone.
 `--workload batch512` times the uniform batch: 512 signals of N = 4096
 (8..32 kernels, |b| <= 0.95), M = 512, 30 steps, decomposed together.
 `--workload small1k` times the small latency-bound case: N = 1024, M = 100
@@ -55,7 +56,8 @@ def log(msg):
 
 def flops_per_eval(n: int) -> float:
     """Algorithmic work per grid value: one inverse-DFT share (5 log2 N, the
-    standard complex radix-2 count) plus the weight multiply, |.|^2 and compare (6)."""
+    standard nominal count of a complex FFT, used for every N) plus the weight
+    multiply, |.|^2 and compare (6)."""
     return 5.0 * math.log2(n) + 6.0
 
 
@@ -138,6 +140,8 @@ TIMING_EVERY = 7
 
 def _kernel_name(prec, n):
     tname = "double" if prec == "fp64" else "float"
+    if n & (n - 1):  # N = 3^K
+        return f"k_radius3<{tname},{round(math.log(n, 3))}>"
     k = int(math.log2(n))
     return f"k_radius<{tname},{k}>" if n <= (1 << 14) else f"k_big_rows<{tname},{k}>"
 
@@ -406,6 +410,8 @@ WORKLOADS = {
                  "radii uniform in [0,0.999], 30 AFD steps each, decomposed together", 5, 1),
     "small1k": ("small single decomposition: N=1024 samples (5 normalised Szego kernels, |b|<=0.9), M=100 radii "
                 "m/100, 10 AFD steps; launch-latency bound", 200, 10),
+    "tern6561": ("single-signal Core-AFD at N=3^8=6561 samples (radix-3 transforms), M=1000 radii uniform in "
+                 "[0,0.999], 50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB", 30, 3),
 }
 
 
@@ -416,6 +422,8 @@ def _workload(name, W):
         return W.config1()
     if name == "chirp1m":
         return W.config5()
+    if name == "tern6561":
+        return W.shaped_like_config2(6561, 1000, 50)
     return W.config2()
 
 
@@ -440,13 +448,14 @@ def _time_workload(name, W, torch, steps, warmup, only=None, kernel_timing=True)
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "serve"],
+    ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "tern6561", "serve"],
                     default="chirp1m")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
     ap.add_argument("--steps", type=int, default=None, help="timed decompositions (chirp1m: 5)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed decompositions (chirp1m: 1)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="chirp1m: skip the N=16384 workload's extra key")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="chirp1m: skip the extra keys of the N=16384 and N=6561 workloads")
     ap.add_argument("--cpu-steps", type=int, default=5, help="AFD steps of the oracle sample (N <= 2^14)")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -529,6 +538,11 @@ def main():
         line["single16k"] = {"workload": WORKLOADS["single16k"][0],
                              **{p: {k: v[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
                                 for p, v in r2.items()}}
+        # N = 3^8: the radix-3 transforms
+        _, _, _, r3 = _time_workload("tern6561", W, torch, max(args.steps, 10), args.warmup, args.only, kt)
+        line["tern6561"] = {"workload": WORKLOADS["tern6561"][0],
+                            **{p: {k: v[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
+                               for p, v in r3.items()}}
     if not args.no_cpu:
         log("bench: CPU oracle baseline ...")
         line["cpu_baseline"] = cpu_baseline(g, radii, args.cpu_steps, afd_steps)

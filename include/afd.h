@@ -41,7 +41,7 @@ typedef enum {
   AFD_E_NONFINITE = 2,   /* NaN or Inf in the input samples                          */
   AFD_E_NOMEM = 3,       /* device or host allocation failed                         */
   AFD_E_HIP = 4,         /* a HIP runtime error; afd_last_error() holds its text     */
-  AFD_E_UNSUPPORTED = 5  /* valid but outside what this build supports (N > 2^20)    */
+  AFD_E_UNSUPPORTED = 5  /* valid but outside what this build supports (e.g. N > 2^20) */
 } afd_status;
 
 typedef enum {
@@ -57,7 +57,9 @@ typedef enum {
 } afd_precision;
 
 typedef struct {
-  int64_t n;              /* N = 2^K samples, 2 <= N <= 2^20                                  */
+  int64_t n;              /* N = 2^K samples, 2 <= N <= 2^20, or N = 3^K, 3 <= N <= 3^8 = 6561
+                             (radix-3 transforms; the paper's closing remark extends the fast
+                             algorithm to N = p^K)                                              */
   int32_t m;              /* M >= 1 radii; M * N must be < 2^31                                */
   const double* radii;    /* host pointer, length M, each in [0, 1); any order; copied at
                              create.  Grid index m refers to position m of this array.        */
@@ -119,11 +121,12 @@ typedef struct {
    tables and allocate the device workspace on the current HIP device.
    `hip_stream` is a hipStream_t (NULL = the default stream) on which every
    later call of this plan runs.  On success *out receives the plan.
-   Errors: AFD_E_INVALID (null pointer, N not a power of two or < 2, M < 1,
+   Errors: AFD_E_INVALID (null pointer, N neither a power of two >= 2 nor a
+   power of three >= 3, M < 1,
    M*N >= 2^31, a radius outside [0,1) or non-finite, recheck_k or
    recheck_band out of range, first_a_zero without a zero radius, batch < 0
-   or batch * N * M too large), AFD_E_UNSUPPORTED (N > 2^20, or batch > 1
-   with N > 2^14), AFD_E_NOMEM, AFD_E_HIP.  On error *out is
+   or batch * N * M too large), AFD_E_UNSUPPORTED (N > 2^20, N = 3^K with
+   K > 8, or batch > 1 with N > 2^14), AFD_E_NOMEM, AFD_E_HIP.  On error *out is
    set to NULL and nothing is left allocated. */
 afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan* out);
 
@@ -238,7 +241,8 @@ afd_status afd_reconstruct(afd_plan plan, const double* a, const double* coef, i
    device; they may alias.  Two double-precision forward DFTs on the plan's
    stream (IDFT(y) = conj(DFT(conj(y)))/N); synchronous.  Errors:
    AFD_E_INVALID (NULL), AFD_E_NONFINITE (NaN or Inf in x), AFD_E_NOMEM,
-   AFD_E_HIP; on error g is untouched. */
+   AFD_E_HIP, AFD_E_UNSUPPORTED (a plan with N = 3^K); on error g is
+   untouched. */
 afd_status afd_analytic(afd_plan plan, const double* x, double* g);
 
 /* Per-kernel timing with HIP events that the dispatches of the kernel class

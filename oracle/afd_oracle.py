@@ -29,7 +29,9 @@ listed with its reason in the design notes):
 * The circle measure is dt/2pi (so e_a has unit continuous norm and the
   discrete inner product is (1/N) * sum); the stray 1/sqrt(2pi) of eq. (2)
   and the 2pi constants of eqs. ku12/rcl are replaced by this normalisation
-  and by N = 2^K respectively.
+  and by N respectively.  Every function takes any N: the aliased series of
+  Sec. 3.1 does not use N = 2^K, which the paper's closing remark extends to
+  N = p^K (pinned at N = 3^K as well).
 * Grid order is radius-major: flat index f = m*N + j, a_{m,j} = r_m e^{2 pi i j/N}.
   Ties in the maximal selection go to the lowest flat index (the first
   maximum of a linear scan, Sec. 3.2 Step 2).

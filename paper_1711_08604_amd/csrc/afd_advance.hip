@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kAdvThreads) __attribute__((amdgpu_waves_per_eu(1, 
         }
       } else if (merge) {
         // the FP64 grid maximum from the radius kernel's records
-        merge64_tail<4>(reinterpret_cast<const BlockBest64*>(a.recs) + size_t(a.nrec) * b, a.nrec, N, LOGN, &s_win,
+        merge64_tail<4>(reinterpret_cast<const BlockBest64*>(a.recs) + size_t(a.nrec) * b, a.nrec, N, &s_win,
                      Sm);
         __syncthreads();
         if (w == 0 && tid == 0) *winner = s_win;

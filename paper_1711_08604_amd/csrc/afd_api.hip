@@ -64,6 +64,17 @@ int ilog2_exact(int64_t n) {
   return r;
 }
 
+// k if n = 3^k with k >= 1, else -1
+int ilog3_exact(int64_t n) {
+  if (n < 3) return -1;
+  int k = 0;
+  while (n % 3 == 0) {
+    n /= 3;
+    ++k;
+  }
+  return n == 1 ? k : -1;
+}
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 enum TimedKind { kTimeNone = 0, kTimeRadius = 1, kTimeFft = 2, kTimeUpdate = 3, kTimeRows = 4 };
@@ -104,6 +115,7 @@ struct Config {
   AdvGeom ag;
   int chunk;    // radii per two-pass chunk (of the radii with long spectra)
   int nshort;   // N > 2^14: radii whose significant spectrum fits in N2 terms (no intermediate)
+  int tern;     // N = 3^tern (radix-3 transforms, afd_tern.hip); 0: N = 2^logn
 };
 
 constexpr int kNumCounters = 5;  // radius, recheck, update, prepare; FP32 fallback flag word
@@ -112,8 +124,10 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
   if (!d) return fail(AFD_E_INVALID, "desc is NULL");
   if (d->n > (int64_t(1) << kMaxLogN) && ilog2_exact(d->n) > 0)
     return fail(AFD_E_UNSUPPORTED, "N > 2^20 is not supported");
-  const int logn = ilog2_exact(d->n);
-  if (logn < 1) return fail(AFD_E_INVALID, "N must be a power of two >= 2");
+  const int tern = ilog3_exact(d->n);
+  if (tern > kMaxTernK) return fail(AFD_E_UNSUPPORTED, "N = 3^K needs K <= 8");
+  const int logn = tern > 0 ? 0 : ilog2_exact(d->n);
+  if (logn < 1 && tern < 1) return fail(AFD_E_INVALID, "N must be a power of two >= 2 or a power of three >= 3");
   if (d->m < 1) return fail(AFD_E_INVALID, "M must be >= 1");
   if (!d->radii) return fail(AFD_E_INVALID, "radii is NULL");
   if (int64_t(d->m) * d->n >= (int64_t(1) << 31)) return fail(AFD_E_INVALID, "M*N must be < 2^31");
@@ -139,11 +153,12 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     cfg->M = d->m;
     cfg->batch = batch;
     cfg->fp64 = d->precision == AFD_FP64;
-    cfg->fwd = fwd_plan(logn, cfg->fp64);
+    cfg->tern = tern > 0 ? tern : 0;
+    cfg->fwd = cfg->tern ? FwdPlan{} : fwd_plan(logn, cfg->fp64);
     cfg->nch = recheck_chunks(int(d->n));
     cfg->nparts = update_blocks(int(d->n));
     cfg->big = logn > kMaxLdsLogN;
-    cfg->adv = advance_supported(logn);
+    cfg->adv = !cfg->tern && advance_supported(logn);
     cfg->ag = cfg->adv ? advance_geom(logn) : AdvGeom{};
     if (cfg->adv) {
       cfg->fwd.tw1_size = cfg->ag.tw1_size;
@@ -164,6 +179,16 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
       cfg->chunk = nlong == 0 ? 0 : int(fit < 1 ? 1 : fit > nlong ? nlong : fit);
       cfg->rpb = 1;
       cfg->nblocks = d->m * cfg->bg.g;  // records of every radius of a step
+    } else if (cfg->tern) {
+      // one radius per workgroup; the inverse and forward transforms share
+      // the twiddle table
+      const TernGeom tg = tern_geom(cfg->tern);
+      cfg->geom = FftGeom{tg.E, tg.tpr, tg.twsize, false, 0};
+      cfg->bg = BigGeom{};
+      cfg->chunk = 0;
+      cfg->nshort = 0;
+      cfg->rpb = 1;
+      cfg->nblocks = d->m;
     } else {
       cfg->geom = fft_geom(logn, cfg->fp64);
       cfg->bg = BigGeom{};
@@ -195,7 +220,7 @@ Layout layout_of(const Config& c) {
   L.pw = take(real * size_t(c.M) * (c.big ? (size_t(1) << c.bg.l1) : size_t(c.geom.tpr)));
   L.pv = take(real * size_t(c.M) * (c.big ? (size_t(1) << c.bg.l2) : size_t(c.geom.E)));
   L.scale = take(real * size_t(c.M));
-  L.pq = take(c.big ? 0 : real * size_t(c.M) * c.geom.E);
+  L.pq = take(c.big || c.tern ? 0 : real * size_t(c.M) * c.geom.E);
   L.lsig = take(4 * size_t(c.M));
   L.order = take(c.big ? 0 : 8 * size_t(c.M));
   // per-signal buffers: `batch` copies back to back
@@ -300,9 +325,14 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     omega[2 * n + 1] = (double)sinl(ang);
   }
   std::vector<double> tw(2 * size_t(c.geom.twsize + 1), 0.0);
-  fft_twiddles(c.logn, c.fp64, tw.data());
+  if (c.tern)
+    tern_twiddles(c.tern, tw.data());
+  else
+    fft_twiddles(c.logn, c.fp64, tw.data());
   std::vector<double> twf1(2 * size_t(c.fwd.tw1_size + 1), 0.0), twf2(2 * size_t(c.fwd.tw2_size + 1), 0.0);
-  if (c.adv) {
+  if (c.tern) {
+    // (the forward transform takes the inverse's table, conjugated)
+  } else if (c.adv) {
     advance_twiddles(c.ag.l1, twf1.data());
     advance_twiddles(c.ag.l2, twf2.data());
   } else {
@@ -326,7 +356,7 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   std::vector<double> pq;
   std::vector<int32_t> lsig(M);
   for (int m = 0; m < M; ++m) lsig[m] = significant_length(radii[m], c.fp64 ? 60 : 40, N);
-  if (!c.big) {
+  if (!c.big && !c.tern) {
     const int r0 = radius_first_radix(c.logn, c.fp64);
     const long double step = (long double)(tpr / (r0 > 0 ? r0 : 1));
     pq.resize(size_t(M) * E);
@@ -364,7 +394,7 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     if (e == hipSuccess) e = up(p->L.scale, sc.data(), sc.size() * 8);
     if (e == hipSuccess && c.big) e = up(p->L.wl, wl.data(), wl.size() * 8);
     if (e == hipSuccess && c.big) e = up(p->L.wh, wh.data(), wh.size() * 8);
-    if (e == hipSuccess && !c.big) e = up(p->L.pq, pq.data(), pq.size() * 8);
+    if (e == hipSuccess && !c.big && !c.tern) e = up(p->L.pq, pq.data(), pq.size() * 8);
   } else {
     auto f32 = [](const std::vector<double>& v) {
       std::vector<float> o(v.size());
@@ -382,7 +412,7 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     if (e == hipSuccess) e = up(p->L.scale, sc32.data(), sc32.size() * 4);
     if (e == hipSuccess && c.big) e = up(p->L.wl, wl32.data(), wl32.size() * 4);
     if (e == hipSuccess && c.big) e = up(p->L.wh, wh32.data(), wh32.size() * 4);
-    if (e == hipSuccess && !c.big) e = up(p->L.pq, pq32.data(), pq32.size() * 4);
+    if (e == hipSuccess && !c.big && !c.tern) e = up(p->L.pq, pq32.data(), pq32.size() * 4);
   }
   if (e == hipSuccess) e = up(p->L.lsig, lsig.data(), lsig.size() * 4);
   if (e == hipSuccess && c.adv && !c.fp64) {
@@ -561,7 +591,7 @@ afd_status replay_pick(afd_plan_s* p, int k, bool merged, PickArgs pk) {
   double* partials = p->at<double>(p->L.partials);
   if (!merged)
     HIPCHK(launch_merge(c.fp64, p->at<void>(p->L.blocks), c.fp64 ? nullptr : p->at<uint64_t>(p->L.heads),
-                        c.fp64 ? nullptr : p->at<uint64_t>(p->L.seconds), c.nblocks, int(c.N), c.logn, p->recheck_k,
+                        c.fp64 ? nullptr : p->at<uint64_t>(p->L.seconds), c.nblocks, int(c.N), p->recheck_k,
                         p->tau_band, counters + 4 * B, cand, win, B, s),
            "k_merge");
   if (!c.fp64)
@@ -867,10 +897,13 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     } else {
       hipEvent_t e0, e1;
       HIPCHK(tm.pair(kTimeFft, &e0, &e1), "event");
-      HIPCHK(launch_fwd(c.logn, c.fp64, c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32),
-                        p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega, p->at<void>(p->L.xt), cspec, B, s,
-                        e0, e1, c.big ? p->at<void>(p->L.c0) : nullptr),
-             "forward DFT");
+      const void* gin = c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32);
+      if (c.tern)
+        HIPCHK(launch_fwd3(c.tern, c.fp64, gin, p->at<void>(p->L.tw), cspec, B, s, e0, e1), "forward DFT");
+      else
+        HIPCHK(launch_fwd(c.logn, c.fp64, gin, p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega,
+                          p->at<void>(p->L.xt), cspec, B, s, e0, e1, c.big ? p->at<void>(p->L.c0) : nullptr),
+               "forward DFT");
       HIPCHK(tm.pair(kTimeRadius, &e0, &e1), "event");
       if (replay && c.fp64) {
         rp.probe = p->forced + 2 * k;
@@ -891,6 +924,8 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
           m0 += nr;
         }
         HIPCHK(launch_big_merge(c.logn, c.fp64, bp, s, e1), "k_big_merge");
+      } else if (c.tern) {
+        HIPCHK(launch_radius3(c.tern, c.fp64, rp, B, s, e0, e1), "k_radius3");
       } else {
         HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, B, s, e0, e1), "k_radius");
       }
@@ -1026,6 +1061,7 @@ afd_status analytic(afd_plan_s* p, const double* x, double* g) {
   if (!p) return fail(AFD_E_INVALID, "plan is NULL");
   if (!x || !g) return fail(AFD_E_INVALID, "x and g are required");
   const Config& c = p->cfg;
+  if (c.tern) return fail(AFD_E_UNSUPPORTED, "afd_analytic needs N = 2^K");
   const int N = int(c.N), B = c.batch, logn = c.logn;
   HIPCHK(hipSetDevice(p->device), "hipSetDevice");
   const size_t nsig = 2 * size_t(N) * B;
@@ -1104,6 +1140,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
       e = setup_radius_attributes();
       if (e == hipSuccess) e = setup_fwd_attributes();
       if (e == hipSuccess) e = setup_big_attributes();
+      if (e == hipSuccess) e = setup_tern_attributes();
       if (e == hipSuccess) attrs_done = true;
     }
   }
@@ -1299,6 +1336,11 @@ afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threa
     *blocks = int64_t(c.bg.g) * c.M;
     *threads = c.bg.thr_b;
     *lds_bytes = int32_t(c.bg.lds_b);
+  } else if (c.tern) {
+    const TernGeom tg = tern_geom(c.tern);
+    *blocks = c.nblocks;
+    *threads = tg.threads;
+    *lds_bytes = tern_lds_bytes(c.tern, c.fp64);
   } else {
     const bool queued =
         c.fp64 && c.adv && c.batch == 1 && c.rpb == 1 && plan->rslots > 0 && plan->rslots < c.nblocks;

@@ -15,6 +15,7 @@ namespace afd {
 
 constexpr int kMaxLogN = 20;       // N <= 2^20
 constexpr int kMaxLdsLogN = 14;    // single-workgroup (LDS-resident) transforms up to 2^14
+constexpr int kMaxTernK = 8;       // N = 3^K: K <= 8 (6561 points, one workgroup per transform)
 constexpr int kListC = 64;         // per-workgroup candidate list length (FP32 mode)
 constexpr int kListCap = 1024;     // per-workgroup LDS gather capacity before the exact fallback
 constexpr int kKMax = 256;         // longest short-list re-checked in double
@@ -314,6 +315,25 @@ inline void launch_ev(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t
 
 hipError_t setup_radius_attributes();
 hipError_t setup_fwd_attributes();
+hipError_t setup_tern_attributes();
+
+// N = 3^K (afd_tern.hip): transform geometry, twiddle table (2 * (twsize + 1)
+// doubles, interleaved), the forward DFT and the fused radius kernel (one
+// radius per workgroup, records merged by the last workgroup).
+struct TernGeom {
+  int k;        // N = 3^k; 0: not supported
+  int E;        // values per thread
+  int tpr;      // threads holding values (N / E)
+  int threads;  // workgroup size (tpr rounded up to whole waves)
+  int twsize;   // twiddle entries
+};
+TernGeom tern_geom(int k);
+void tern_twiddles(int k, double* tw);
+int tern_lds_bytes(int k, bool fp64);
+hipError_t launch_fwd3(int k, bool fp64, const void* g, const void* tw, void* c, int batch, hipStream_t s,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_radius3(int k, bool fp64, const RadiusParams& p, int batch, hipStream_t s, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
 
 // Batched launches cover `batch` signals (grid dimension y, or z for the
 // re-check); each signal's buffers follow the previous signal's.  For
@@ -331,7 +351,7 @@ hipError_t launch_force(const int32_t* forced, int fstride, int step, int N, Can
 // One workgroup per signal merges the radius kernel's per-workgroup records
 // (as the fused step tail does): FP64 into the winner, FP32 into the short-list.
 hipError_t launch_merge(bool fp64, const void* recs, const uint64_t* heads, const uint64_t* seconds, int nrec, int N,
-                        int logn, int recheck_k, float tau_band, unsigned int* flagword, CandList* cand, Winner* w,
+                        int recheck_k, float tau_band, unsigned int* flagword, CandList* cand, Winner* w,
                         int batch, hipStream_t s);
 hipError_t launch_pick(const PickArgs& a, int batch, hipStream_t s);
 // Up to 6 word ranges set to zero by one kernel (in place of memsets where a

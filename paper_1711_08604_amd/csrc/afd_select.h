@@ -388,7 +388,7 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
 // FP64: global best of the per-block records -> winner (coefficient = the
 // grid value of the FFT form).
 template <int PRE = 2>
-__device__ __forceinline__ void merge64_tail(const BlockBest64* __restrict__ blocks, int nb, int N, int logn,
+__device__ __forceinline__ void merge64_tail(const BlockBest64* __restrict__ blocks, int nb, int N,
                                              Winner* __restrict__ w, MergeScratch* S) {
   Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
   {
@@ -413,8 +413,8 @@ __device__ __forceinline__ void merge64_tail(const BlockBest64* __restrict__ blo
   if (threadIdx.x == 0) {
     Winner o;
     const bool valid = r.f != 0xffffffffu;  // false only if every value was NaN
-    o.m = valid ? int32_t(r.f >> logn) : 0;
-    o.j = valid ? int32_t(r.f & uint32_t(N - 1)) : 0;
+    o.m = valid ? int32_t(r.f / uint32_t(N)) : 0;
+    o.j = valid ? int32_t(r.f % uint32_t(N)) : 0;
     o.kcount = 0;
     o.flags = 0;
     o.ax = o.ay = 0.0;
@@ -714,9 +714,62 @@ struct FlatOrder {
   __device__ __forceinline__ uint32_t rank(uint32_t i) const { return first + (i % na) + (i / na) * step; }
 };
 
+// Register order of a transform's output: register p of thread t holds bin
+// t + TPR * O::bin(p), and O::reg(q) is the register holding bin t + TPR q.
+// The power-of-two transforms leave their bins in bit-reversed order.
+template <int LE>
+struct BitrevOrder {
+  static __host__ __device__ constexpr int bin(int p) { return bitrev(p, LE); }
+  static __host__ __device__ constexpr int reg(int q) { return bitrev(q, LE); }
+};
+
 // FP64 workgroup selection: best point (value, flat index, grid value) and the
 // runner-up value.  Within a thread the bins are visited in increasing index
 // order, so a strict comparison keeps the lowest index among equal values.
+// E values per thread, TPR threads per transform, output order O.
+template <typename T, int E, int TPR, class O>
+__device__ __forceinline__ void select_best_o(const Cx<T> (&v)[E], bool active, T sc, uint32_t fbase,
+                                              uint32_t fstride, int t, Best* wb, BlockBest64* o) {
+  double y1 = -1.0, y2 = -1.0;
+  int i1 = 0;
+  T bx = T(0), by = T(0);
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int p = O::reg(q);  // register holding bin t + TPR*q
+    const double y = double(fma(v[p].x, v[p].x, v[p].y * v[p].y));
+    if (y > y1) {
+      y2 = y1;
+      y1 = y;
+      i1 = p;
+      bx = v[p].x;
+      by = v[p].y;
+    } else {
+      y2 = fmax(y2, y);
+    }
+  }
+  Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
+  if (active) {
+    const double s2 = double(sc) * double(sc);
+    b.vx = double(bx * sc);
+    b.vy = double(by * sc);
+    b.f = fbase + fstride * uint32_t(t + TPR * O::bin(i1));
+    // exact |.|^2 of the scaled grid value, as compared across radii
+    b.p1 = b.vx * b.vx + b.vy * b.vy;
+    b.p2 = fmin(y2 * s2, b.p1);
+  }
+  const Best r = block_best(b, wb);
+  if (threadIdx.x == 0) {
+    st_agent(&o->p1, r.p1);
+    st_agent(&o->p2, r.p2);
+    st_agent(&o->vx, r.vx);
+    st_agent(&o->vy, r.vy);
+    st_agent(&o->f, r.f);
+  }
+}
+
+// The same for the power-of-two transforms.  (A copy of the loop rather
+// than a call of select_best_o: through the extra inlining level the 2^14-point
+// double-precision radius kernel needs 59 more VGPRs.)
 template <int LOGN, typename T>
 __device__ __forceinline__ void select_best(const Cx<T> (&v)[pickE<T, LOGN>()], bool active, T sc, uint32_t fbase,
                                             uint32_t fstride, int t, Best* wb, BlockBest64* o) {
@@ -812,14 +865,12 @@ __device__ __forceinline__ void store_block_best(const Best& b, Best* wb, BlockB
 // maximum, best first, at most kListC of them (exact top by key).  Points
 // are compared unscaled (|y|^2 against the threshold divided by s_m^2) and
 // keys are formed only for points that pass.
-template <int LOGN>
-__device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LOGN>()], bool active, float sc,
-                                            uint32_t fbase, uint32_t fstride, int t, unsigned char* scratch,
-                                            float tau_band, const FlatOrder& ord, BlockList32* o, uint64_t* head,
-                                            uint64_t* second, unsigned int* flagword) {
-  constexpr int E = pickE<float, LOGN>();
-  constexpr int TPR = Shape<LOGN, E>::TPR;
-  constexpr int LE = ilog2c(E);
+template <int E, int TPR, class O>
+__device__ __forceinline__ void select_list_o(const Cx<float> (&v)[E], bool active, float sc, uint32_t fbase,
+                                              uint32_t fstride, int t, unsigned char* scratch, float tau_band,
+                                              const FlatOrder& ord, BlockList32* o, uint64_t* head,
+                                              uint64_t* second, unsigned int* flagword) {
+  static_assert(E <= 32, "the taken mask holds one bit per register");
   const float s2 = sc * sc;
   float Y[E];
   float ym = 0.f;
@@ -857,7 +908,7 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
       base = lane_u32(base, leader);
       if (q) {
         const uint32_t pos = base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
-        if (pos < uint32_t(kListCap)) keys[pos] = key32(Y[p] * s2, fbase + fstride * uint32_t(t + TPR * bitrev(p, LE)));
+        if (pos < uint32_t(kListCap)) keys[pos] = key32(Y[p] * s2, fbase + fstride * uint32_t(t + TPR * O::bin(p)));
       }
     }
   }
@@ -930,7 +981,7 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
 #pragma unroll
     for (int p = 0; p < E; ++p) {
       const bool q = Y[p] >= fl;
-      const uint64_t k = q ? key32(Y[p], fbase + fstride * uint32_t(t + TPR * bitrev(p, LE))) : 0;
+      const uint64_t k = q ? key32(Y[p], fbase + fstride * uint32_t(t + TPR * O::bin(p))) : 0;
       wave_append(q, k, cnt, keys, uint32_t(kListCap));
     }
     __syncthreads();
@@ -952,7 +1003,7 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
 #pragma unroll
     for (int p = 0; p < E; ++p) {
       if (!((taken >> p) & 1u) && Y[p] > 0.f) {
-        const uint64_t k = key32(Y[p], fbase + fstride * uint32_t(t + TPR * bitrev(p, LE)));
+        const uint64_t k = key32(Y[p], fbase + fstride * uint32_t(t + TPR * O::bin(p)));
         tb = k > tb ? k : tb;
       }
     }
@@ -963,10 +1014,20 @@ __device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LO
     if (tid == 0) st_agent(&o->keys[rounds], b);
 #pragma unroll
     for (int p = 0; p < E; ++p) {
-      if (Y[p] > 0.f && key32(Y[p], fbase + fstride * uint32_t(t + TPR * bitrev(p, LE))) == b) taken |= 1u << p;
+      if (Y[p] > 0.f && key32(Y[p], fbase + fstride * uint32_t(t + TPR * O::bin(p))) == b) taken |= 1u << p;
     }
   }
   if (tid == 0) list_header(o, head, second, flagword, pb, rounds, n, uint32_t(kFlagFallback), first, next);
+}
+
+template <int LOGN>
+__device__ __forceinline__ void select_list(const Cx<float> (&v)[pickE<float, LOGN>()], bool active, float sc,
+                                            uint32_t fbase, uint32_t fstride, int t, unsigned char* scratch,
+                                            float tau_band, const FlatOrder& ord, BlockList32* o, uint64_t* head,
+                                            uint64_t* second, unsigned int* flagword) {
+  constexpr int E = pickE<float, LOGN>();
+  select_list_o<E, Shape<LOGN, E>::TPR, BitrevOrder<ilog2c(E)>>(v, active, sc, fbase, fstride, t, scratch, tau_band,
+                                                                ord, o, head, second, flagword);
 }
 
 }  // namespace afd

@@ -21,7 +21,7 @@ constexpr int kUpdThreads = 256;
 constexpr int kUpdPerThread = 4;
 
 int update_blocks(int N) { return (N + kUpdThreads * kUpdPerThread - 1) / (kUpdThreads * kUpdPerThread); }
-int recheck_chunks(int N) { return N >= 2048 ? N / 2048 : 1; }
+int recheck_chunks(int N) { return (N + 2047) / 2048; }
 
 // Batched launches: signal b = blockIdx.y works on
 // its own slices of every per-signal buffer.
@@ -82,14 +82,14 @@ __global__ void k_force(const int32_t* __restrict__ forced, int fstride, int ste
 constexpr int kRecheckPerThread = 8;  // chunk of 2048 samples over 256 threads
 __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ cand, const double* __restrict__ g,
                                                  const double* __restrict__ omega, const double* __restrict__ radii,
-                                                 int N, int logn, int nch, double* __restrict__ partials,
+                                                 int N, int nch, double* __restrict__ partials,
                                                  unsigned int* __restrict__ counter, Winner* __restrict__ w) {
   __shared__ double wsum[kKMax][4][2];  // [candidate][wave] (re, im)
   __shared__ double wd[16];
   __shared__ Best bb[16];
   __shared__ int s_last;
   const int chunk = blockIdx.x;
-  const int cl = N / nch;
+  const int cl = (N + nch - 1) / nch;  // samples per chunk (the last may hold fewer)
   const int b = blockIdx.y;
   const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
   cand += b;
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
   for (int q = 0; q < kRecheckPerThread; ++q) {
     const int i = tid + 256 * q;
     const int n = chunk * cl + i;
-    const bool in = i < cl;
+    const bool in = i < cl && n < N;
     gx[q] = in ? g[2 * n] : 0.0;
     gy[q] = in ? g[2 * n + 1] : 0.0;
     ox[q] = in ? omega[2 * n] : 1.0;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
   }
   for (int c = 0; c < count; ++c) {
     const uint32_t f = key_f(cand->keys[c]);
-    const int m = int(f >> logn), j = int(f & uint32_t(N - 1));
+    const int m = int(f / uint32_t(N)), j = int(f % uint32_t(N));
     const double r = radii[m];
     const double wjx = omega[2 * j], wjy = omega[2 * j + 1];
     double ax = 0.0, ay = 0.0;
@@ -148,23 +148,23 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
   double rk = 0.0;
   if (tid < count) {
     key = cand->keys[tid];
-    rk = radii[key_f(key) >> logn];
+    rk = radii[key_f(key) / uint32_t(N)];
   }
-  winner_from_partials(count, cand->flags, key, rk, partials, N, logn, nch, w, bb, wd);
+  winner_from_partials(count, cand->flags, key, rk, partials, N, nch, w, bb, wd);
 }
 
 // Same merge functions, workgroup size and record order as the fused step
 // tail, so the result is the one the tail reaches.
 __global__ __launch_bounds__(256) void k_merge(int fp64, const void* __restrict__ recs,
                                                const uint64_t* __restrict__ heads,
-                                               const uint64_t* __restrict__ seconds, int nrec, int N, int logn,
+                                               const uint64_t* __restrict__ seconds, int nrec, int N,
                                                int recheck_k, float tau_band, unsigned int* __restrict__ flagword,
                                                CandList* __restrict__ cand, Winner* __restrict__ w) {
   extern __shared__ __align__(16) unsigned char smem[];
   MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
   const int b = blockIdx.x;
   if (fp64) {
-    merge64_tail<4>(reinterpret_cast<const BlockBest64*>(recs) + size_t(nrec) * b, nrec, N, logn, w + b, Sm);
+    merge64_tail<4>(reinterpret_cast<const BlockBest64*>(recs) + size_t(nrec) * b, nrec, N, w + b, Sm);
   } else {
     select32_tail<4>(reinterpret_cast<const BlockList32*>(recs) + size_t(nrec) * b, heads + size_t(nrec) * b,
                      seconds + size_t(nrec) * b, nrec, recheck_k, tau_band, flagword + b, cand + b, Sm, true);
@@ -248,12 +248,6 @@ __global__ __launch_bounds__(256) void k_update(double* __restrict__ g64, float*
 }
 
 // ---------------------------------------------------------------- launchers
-static int ilog2i(int v) {
-  int r = 0;
-  while ((1 << r) < v) ++r;
-  return r;
-}
-
 hipError_t launch_prepare(double* g64, float* g32, int N, double* epart, int* nonfinite, unsigned int* counter,
                           const RecordArgs& R, int batch, hipStream_t s) {
   hipLaunchKernelGGL(k_prepare, dim3(update_blocks(N), batch), dim3(kUpdThreads), 0, s, g64, g32, N, epart,
@@ -268,10 +262,10 @@ hipError_t launch_force(const int32_t* forced, int fstride, int step, int N, Can
 }
 
 hipError_t launch_merge(bool fp64, const void* recs, const uint64_t* heads, const uint64_t* seconds, int nrec, int N,
-                        int logn, int recheck_k, float tau_band, unsigned int* flagword, CandList* cand, Winner* w,
+                        int recheck_k, float tau_band, unsigned int* flagword, CandList* cand, Winner* w,
                         int batch, hipStream_t s) {
   hipLaunchKernelGGL(k_merge, dim3(batch), dim3(256), uint32_t(sizeof(MergeScratch)), s, fp64 ? 1 : 0, recs, heads,
-                     seconds, nrec, N, logn, recheck_k, tau_band, flagword, cand, w);
+                     seconds, nrec, N, recheck_k, tau_band, flagword, cand, w);
   return hipGetLastError();
 }
 
@@ -288,8 +282,8 @@ hipError_t launch_pick(const PickArgs& a, int batch, hipStream_t s) {
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
                           double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s) {
   const int nch = recheck_chunks(N);
-  if (N / nch > 256 * kRecheckPerThread) return hipErrorInvalidValue;  // a chunk's samples fit the registers
-  hipLaunchKernelGGL(k_recheck, dim3(nch, batch), dim3(256), 0, s, cand, g, omega, radii, N, ilog2i(N), nch, partials,
+  if ((N + nch - 1) / nch > 256 * kRecheckPerThread) return hipErrorInvalidValue;  // a chunk fits the registers
+  hipLaunchKernelGGL(k_recheck, dim3(nch, batch), dim3(256), 0, s, cand, g, omega, radii, N, nch, partials,
                      counter, w);
   return hipGetLastError();
 }

@@ -20,7 +20,7 @@ __device__ __forceinline__ Blaschke blaschke_of(Winner W, const double* __restri
                                                 const double* __restrict__ omega, int N, int M) {
   W.m = min(max(W.m, 0), M - 1);
   Blaschke B;
-  B.j = W.j & (N - 1);
+  B.j = min(max(W.j, 0), N - 1);
   B.r = radii[W.m];
   const double s = sqrt((1.0 - B.r) * (1.0 + B.r));
   B.wjx = omega[2 * B.j];
@@ -36,7 +36,7 @@ __device__ __forceinline__ Blaschke blaschke_of(const UpdateArgs& U) {
 
 __device__ __forceinline__ void blaschke_apply(const Blaschke& B, const double* __restrict__ omega, int N, int n,
                                                double gx, double gy, double& hx, double& hy) {
-  const int d = (n - B.j) & (N - 1);
+  const int d = n >= B.j ? n - B.j : n - B.j + N;  // (n - j) mod N
   const double ox = omega[2 * d], oy = omega[2 * d + 1];
   const double ux = fma(-B.r, ox, 1.0), uy = -B.r * oy;
   const double nx = fma(gx, ux, -gy * uy) - B.csx;
@@ -58,7 +58,7 @@ __device__ __forceinline__ void blaschke_apply(const Blaschke& B, const double* 
 // lowest flat index.  Thread 0 writes the result to *w (any address space);
 // `bb`, `wd`: LDS Best[16], double[16].
 __device__ __forceinline__ void winner_from_partials(int count, int cflags, uint64_t key, double r,
-                                                     const double* __restrict__ partials, int N, int logn, int nch,
+                                                     const double* __restrict__ partials, int N, int nch,
                                                      Winner* w, Best* bb, double* wd) {
   const bool forced = (cflags & kFlagForced) != 0;
   Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
@@ -84,8 +84,8 @@ __device__ __forceinline__ void winner_from_partials(int count, int cflags, uint
     for (int i = 1; i < nwaves(); ++i) e = fmax(e, wd[i]);
     Winner o;
     const bool valid = count > 0 && rb.f != 0xffffffffu;
-    o.m = valid ? int32_t(rb.f >> logn) : 0;
-    o.j = valid ? int32_t(rb.f & uint32_t(N - 1)) : 0;
+    o.m = valid ? int32_t(rb.f / uint32_t(N)) : 0;
+    o.j = valid ? int32_t(rb.f % uint32_t(N)) : 0;
     o.cx = valid ? rb.vx : 0.0;
     o.cy = valid ? rb.vy : 0.0;
     if (forced || count < 2 || !valid) o.margin = __builtin_nan("");
@@ -120,7 +120,7 @@ __device__ __forceinline__ void write_record(const RecordArgs& R, int step, doub
   }
   Winner W = *R.w;
   W.m = min(max(W.m, 0), R.M - 1);
-  W.j = W.j & (R.N - 1);
+  W.j = min(max(W.j, 0), R.N - 1);
   const double r = R.radii[W.m];
   R.idx[2 * step] = W.m;
   R.idx[2 * step + 1] = W.j;

@@ -56,6 +56,7 @@ def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=
     (dict(recheck_k=-1), 1), (dict(recheck_k=65), 1), (dict(band=-1e-3), 1), (dict(band=0.5), 1),
     (dict(first_a_zero=1, radii=(0.1, 0.2)), 1), (dict(n=1 << 16, radii=np.zeros(1 << 15)), 1),
     (dict(batch=-1), 1), (dict(n=1 << 15, batch=2), 5), (dict(n=1 << 14, batch=1 << 17), 1),
+    (dict(n=3 ** 9), 5), (dict(n=6), 1), (dict(n=18), 1), (dict(n=3 ** 8 * 2), 1),
 ])
 def test_plan_create_rejects(kw, status):
     afd, lib = _lib()
@@ -130,3 +131,16 @@ def test_status_strings():
     afd, lib = _lib()
     for s in range(6):
         assert lib.afd_status_string(s).decode().startswith("AFD_")
+
+
+def test_workspace_bytes_three_powers():
+    """N = 3^K plans: valid for K = 1..8 (one radius per workgroup, records
+    for M radii), growing with N and M."""
+    afd, lib = _lib()
+    sizes = []
+    for k in range(1, 9):
+        d, keep = _desc(afd, n=3 ** k, radii=np.linspace(0, 0.99, 50))
+        sizes.append(lib.afd_workspace_bytes(ctypes.byref(d)))
+    assert all(b > 0 for b in sizes) and sizes == sorted(sizes), sizes
+    d, keep = _desc(afd, n=3 ** 8, radii=np.linspace(0, 0.99, 50), precision=1, batch=4)
+    assert lib.afd_workspace_bytes(ctypes.byref(d)) > sizes[-1]

@@ -1,0 +1,187 @@
+"""N = 3^K (K = 1..8, N = 3..6561): the radix-3 transforms against the FP64
+oracle, through the C ABI.  The paper's fast algorithm holds for N = p^K
+(its closing remark); the oracle's FFT and direct forms take any N.
+
+Every size free-running and replayed along the oracle's trajectory (same bar
+as the power-of-two sizes), the r = 0 ring tie, a_1 = 0, the DFT reduction of
+radii = {0}, batches equal to lone signals bit for bit, captured graphs equal
+to eager calls, reconstruction, and the errors of unsupported sizes."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.parity_tools import TOL, compare, compare_replay, to_numpy
+
+torch = pytest.importorskip("torch")
+from paper_1711_08604_amd import AfdError, Plan  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _signal(n, item, rmax=0.9, count=6):
+    rng = W.rng_for(300 + n, item)
+    g, _, _ = W.random_kernel_signal(rng, n, count, rmax)
+    return W.add_noise(rng, g, 40.0)
+
+
+SIZES = [  # (N, M, steps): every K, M ragged against nothing in particular
+    (3, 2, 2), (9, 5, 3), (27, 7, 3), (81, 13, 4), (243, 41, 5), (729, 60, 6), (2187, 50, 5), (6561, 40, 4),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,m,steps", SIZES, ids=lambda v: str(v))
+def test_free_run_and_replay(n, m, steps, prec):
+    print(f"case N={n} M={m} steps={steps} {prec}", flush=True)
+    g = _signal(n, 0)
+    radii = W.uniform_radii(m, 0.999) if n >= 81 else W.uniform_radii(m, 0.95)
+    ref = O.decompose(g, radii, steps)
+    with Plan(n, radii, precision=prec) as plan:
+        res = plan.decompose(_dev(g), steps)
+        torch.cuda.synchronize()
+        compare(res, ref, TOL[prec], signal=g, radii=radii)
+        rep = plan.replay(_dev(g), steps, ref.index.astype(np.int32))
+        compare_replay(rep, ref, prec, radii=radii)
+        r = to_numpy(res)
+        if prec == "fp32":
+            assert np.all(r["recheck_count"] >= 1)
+            assert np.all((r["flags"] & 3) == 0), r["flags"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_shaped_like_n16384_workload(prec):
+    """N = 6561, M = 1000 radii uniform in [0, 0.999], 40 normalised Szego
+    kernels + noise (the single-signal workload's recipe at the largest
+    power of three), 12 steps, every step replayed."""
+    g, radii, _ = W.shaped_like_config2(6561, 1000, 12, item=7)
+    ref = O.decompose(g, radii, 12)
+    with Plan(6561, radii, precision=prec) as plan:
+        res = plan.decompose(_dev(g), 12)
+        compare(res, ref, TOL[prec], signal=g, radii=radii)
+        rep = plan.replay(_dev(g), 12, ref.index.astype(np.int32))
+        compare_replay(rep, ref, prec, radii=radii)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [27, 729, 6561], ids=lambda v: f"N={v}")
+def test_zero_radius_ring_tie(n, prec):
+    """The r = 0 ring (all N values the same number) is the maximum of step
+    1; the first maximum of the scan, flat index 0, must be chosen."""
+    g = _signal(n, 1)
+    g = 0.01 * (g - g.mean()) + 5.0
+    radii = np.array([0.0, 0.2, 0.4])
+    ref = O.decompose(g, radii, 2)
+    assert tuple(ref.index[0]) == (0, 0) and ref.margin[0] == 0.0
+    with Plan(n, radii, precision=prec) as plan:
+        res = plan.decompose(_dev(g), 2)
+        r = to_numpy(res)
+        assert tuple(r["index"][0]) == (0, 0), r["index"][0]
+        compare(res, ref, TOL[prec], signal=g, radii=radii)
+        rep = to_numpy(plan.replay(_dev(g), 2, ref.index.astype(np.int32)))
+        assert tuple(rep["pick_index"][0]) == (0, 0), rep["pick_index"][0]
+
+
+def test_zero_radius_reduces_to_dft():
+    """radii = {0}: index 0 every step and c_k = DFT(G)[k-1] / N."""
+    n = 243
+    g = _signal(n, 2)
+    C = np.fft.fft(g)
+    for prec in ("fp64", "fp32"):
+        with Plan(n, [0.0], precision=prec) as plan:
+            r = to_numpy(plan.decompose(_dev(g), 8))
+        assert np.all(r["index"] == 0)
+        assert np.max(np.abs(r["coef"] - C[:8] / n)) < 1e-12 * np.max(np.abs(C[:8] / n))
+
+
+def test_first_a_zero():
+    n = 729
+    g = _signal(n, 3)
+    g = g - g.mean()
+    radii = np.concatenate([[0.0], W.uniform_radii(30, 0.99)[1:]])
+    ref = O.decompose(g, radii, 6, first_a_zero=True)
+    for prec in ("fp64", "fp32"):
+        with Plan(n, radii, precision=prec, first_a_zero=True) as plan:
+            res = plan.decompose(_dev(g), 6)
+            compare(res, ref, TOL[prec], signal=g, radii=radii, forced_first=True)
+            assert tuple(to_numpy(res)["index"][0]) == (0, 0)
+
+
+def test_single_kernel_recovery():
+    """G = w e_b with b on the grid: step 1 finds b and w (1 + rho)/(1 - rho)."""
+    n = 2187
+    radii = np.round(np.arange(0, 100) / 100.0, 12)
+    mb, jb, w = 50, 1234, 0.7 - 1.1j
+    b = radii[mb] * np.exp(2j * np.pi * jb / n)
+    g = w * O.szego(b, O.circle_points(n))
+    rho = abs(b) ** n
+    for prec in ("fp64", "fp32"):
+        with Plan(n, radii, precision=prec) as plan:
+            r = to_numpy(plan.decompose(_dev(g), 1))
+        assert tuple(r["index"][0]) == (mb, jb)
+        assert abs(r["coef"][0] - w * (1 + rho) / (1 - rho)) < 1e-12 * abs(w)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_matches_alone(prec):
+    n, m, batch, steps = 729, 33, 3, 4
+    sigs = np.stack([_signal(n, 10 + i) for i in range(batch)])
+    radii = W.uniform_radii(m, 0.999)
+    with Plan(n, radii, precision=prec, batch=batch) as plan:
+        rb = to_numpy(plan.decompose(_dev(sigs), steps))
+    for i in range(batch):
+        with Plan(n, radii, precision=prec) as plan:
+            ra = to_numpy(plan.decompose(_dev(sigs[i]), steps))
+        for k in ("index", "coef", "energy", "margin"):
+            np.testing.assert_array_equal(rb[k][i], ra[k], err_msg=f"signal {i} field {k}")
+    ref = O.decompose(sigs[1], radii, steps)
+    assert np.array_equal(rb["index"][1], ref.index)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replays_equal_eager(prec):
+    n, m, steps = 2187, 60, 5
+    g = _signal(n, 4)
+    radii = W.uniform_radii(m, 0.999)
+    stream = torch.cuda.current_stream().cuda_stream
+    with Plan(n, radii, precision=prec, stream=stream) as plan:
+        eager = to_numpy(plan.decompose(_dev(g), steps))
+        with plan.graph(_dev(g), steps) as gr:
+            for rep in range(3):
+                gr.launch()
+                gr.status()
+                got = to_numpy(gr.result)
+                for k in ("index", "coef", "energy", "margin", "remainder"):
+                    assert np.array_equal(got[k], eager[k], equal_nan=True), (rep, k)
+                plan.decompose(_dev(g), 1)  # eager work of the same plan between the replays
+                torch.cuda.synchronize()
+
+
+def test_reconstruct_matches_oracle():
+    n, steps = 729, 8
+    g = _signal(n, 5)
+    radii = W.uniform_radii(40, 0.999)
+    with Plan(n, radii, precision="fp64") as plan:
+        d = plan.decompose(_dev(g), steps)
+        r = to_numpy(d)
+        S, delta = plan.reconstruct(r["a"], r["coef"], signal=g)
+    z = O.circle_points(n)
+    ref = O.partial_sum(r["coef"], r["a"], z)
+    assert np.max(np.abs(np.asarray(S) - ref)) < 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(np.asarray(delta) - O.relative_errors(g, r["coef"], r["a"]))) < 1e-12
+
+
+def test_unsupported_sizes():
+    with pytest.raises(AfdError):
+        Plan(3 ** 9, [0.5])          # beyond 3^8
+    with pytest.raises(AfdError):
+        Plan(6, [0.5])               # neither 2^K nor 3^K
+    with Plan(81, [0.0, 0.5]) as plan:
+        with pytest.raises(AfdError):
+            plan.analytic(np.ones(81))   # the analytic part needs N = 2^K
