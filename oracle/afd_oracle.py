@@ -22,6 +22,7 @@ paper's source gives them (the compiled number in brackets):
 * Sec. 3.2, Steps 1 and 2  all grid values, then the maximum
 * Sec. 4, eq. er [24]      relative error delta
 * Sec. 4 (case 2)          analytic (H^2) part of real boundary samples
+* Sec. 3.2, remark after Step 2  non-uniform samples through a non-uniform DFT
 
 Readings adopted where the paper is silent or inconsistent (each is also
 listed with its reason in the design notes):
@@ -62,6 +63,14 @@ __all__ = [
     "partial_sum",
     "relative_errors",
     "analytic_part",
+    "sample_points",
+    "trapezoid_weights",
+    "grid_direct_nu",
+    "nudft",
+    "grid_series_nu",
+    "update_nu",
+    "energy_nu",
+    "decompose_nu",
     "Decomposition",
 ]
 
@@ -341,3 +350,139 @@ def analytic_part(x) -> np.ndarray:
     else:
         h[1:(n + 1) // 2] = 2.0
     return np.fft.ifft(np.fft.fft(x) * h)
+
+
+# ---------------------------------------------------------------- non-uniform samples
+# Sec. 3.2, remark after Step 2: with samples at non-uniform positions the
+# algorithm carries over once the DFT of the samples is replaced by a
+# non-uniform DFT.  Readings (listed with the others in the design notes):
+# * sample positions are given in turns t_n in [0, 1): z_n = e^{2 pi i t_n};
+# * the discrete inner product is the quadrature sum_n w_n G(z_n) conj(F(z_n))
+#   with weights w_n standing for dt/2pi (sum 1 for a consistent rule); the
+#   uniform case is w_n = 1/N at t_n = n/N;
+# * the selection grid stays the uniform polar grid a_{m,j} = r_m e^{2 pi i j/N}.
+
+
+def sample_points(turns) -> np.ndarray:
+    """z_n = e^{2 pi i t_n}, with the angle formed and the cosine and sine taken
+    in extended precision, then rounded once to double."""
+    t = np.asarray(turns, dtype=np.longdouble)
+    two_pi = np.longdouble("6.283185307179586476925286766559005768")
+    ang = two_pi * t
+    return (np.cos(ang).astype(np.float64) + 1j * np.sin(ang).astype(np.float64)).astype(np.complex128)
+
+
+def trapezoid_weights(turns) -> np.ndarray:
+    """Periodic trapezoidal weights w_n = (t_{n+1} - t_{n-1}) / 2 for strictly
+    increasing positions in [0, 1) (t_N = t_0 + 1, t_{-1} = t_{N-1} - 1); they
+    sum to 1 and equal 1/N on the uniform positions."""
+    t = np.asarray(turns, dtype=np.float64)
+    if t.size == 1:
+        return np.ones(1)
+    nxt = np.concatenate([t[1:], [t[0] + 1.0]])
+    prv = np.concatenate([[t[-1] - 1.0], t[:-1]])
+    return (nxt - prv) / 2.0
+
+
+def grid_direct_nu(G, turns, weights, radii, n: int) -> np.ndarray:
+    """Grid values by the quadrature rule on non-uniform samples:
+    V[m, j] = sqrt(1 - r_m^2) * sum_n w_n G_n / (1 - a_{m,j} conj(z_n)),
+    a_{m,j} = r_m e^{2 pi i j/n} (eq. term81 with the weights in place of
+    1/N).  Cost O(M n N_s): the plain definition."""
+    G = np.asarray(G, dtype=np.complex128)
+    w = np.asarray(weights, dtype=np.float64)
+    z = sample_points(turns)
+    grid = circle_points(n)
+    V = np.empty((len(radii), n), dtype=np.complex128)
+    for m, r in enumerate(radii):
+        den = 1.0 - np.outer(r * grid, np.conj(z))
+        V[m] = np.sqrt(1.0 - r * r) * ((den ** -1) @ (w * G))
+    return V
+
+
+def _turns_times(l, t):
+    """frac(l * t) in extended precision for integers l and doubles t: t splits
+    into a 30-bit head (l * head is exact in double) and a tail."""
+    t = np.asarray(t, dtype=np.float64)
+    head = np.round(t * 2.0 ** 30) / 2.0 ** 30
+    tail = (t - head).astype(np.longdouble)
+    prod = np.outer(np.asarray(l, dtype=np.float64), head)
+    fh = prod - np.floor(prod)
+    return fh.astype(np.longdouble) + np.outer(np.asarray(l, dtype=np.longdouble), tail)
+
+
+def nudft(u, turns, count: int) -> np.ndarray:
+    """Non-uniform DFT c_l = sum_n u_n e^{-2 pi i l t_n}, l = 0..count-1, the
+    phases in extended precision (the series coefficients of the remark's
+    non-uniform form of eq. term4)."""
+    u = np.asarray(u, dtype=np.complex128)
+    two_pi = np.longdouble("6.283185307179586476925286766559005768")
+    out = np.empty(count, dtype=np.complex128)
+    for l0 in range(0, count, 256):
+        ls = np.arange(l0, min(count, l0 + 256))
+        ph = two_pi * _turns_times(ls, turns)
+        e = np.cos(ph).astype(np.float64) - 1j * np.sin(ph).astype(np.float64)
+        out[l0:l0 + len(ls)] = e @ u
+    return out
+
+
+def grid_series_nu(G, turns, weights, radii, n: int) -> np.ndarray:
+    """Grid values from the non-uniform DFT: with c_l = sum_n w_n G_n e^{-2 pi i l t_n},
+    V[m, j] = sqrt(1 - r^2) sum_{l >= 0} r^l c_l e^{2 pi i l j/n} (the geometric
+    expansion of the kernel, eq. ku12 without the periodicity that uniform
+    samples give c_l).  The sum is cut at l < n, so this equals grid_direct_nu
+    only where r^n is negligible; the inverse DFT over j is numpy's (times n)."""
+    G = np.asarray(G, dtype=np.complex128)
+    c = nudft(np.asarray(weights, dtype=np.float64) * G, turns, n)
+    V = np.empty((len(radii), n), dtype=np.complex128)
+    for m, r in enumerate(radii):
+        V[m] = np.sqrt(1.0 - r * r) * n * np.fft.ifft(c * _radius_power(r, n))
+    return V
+
+
+def update_nu(G, z, a: complex, coef: complex) -> np.ndarray:
+    """Eq. (7) at the sample points z: (G - coef e_a(z)) (1 - conj(a) z) / (z - a)."""
+    return (G - coef * szego(a, z)) * (1.0 - np.conj(a) * z) / (z - a)
+
+
+def energy_nu(G, weights) -> float:
+    """Quadrature squared norm sum_n w_n |G_n|^2."""
+    G = np.asarray(G)
+    return float(np.sum(np.asarray(weights, dtype=np.float64) * (G.real ** 2 + G.imag ** 2)))
+
+
+def decompose_nu(G, turns, weights, radii, n: int, steps: int, first_a_zero: bool = False, forced=None,
+                 form: str = "direct") -> Decomposition:
+    """Core-AFD on non-uniform samples: the loop of decompose() with the grid
+    values of grid_direct_nu (`form` = "direct") or grid_series_nu ("series"),
+    the update at the sample points and the quadrature energy.  Indices are
+    (m, j) on the n-angle grid."""
+    G = np.asarray(G, dtype=np.complex128).copy()
+    radii = np.asarray(radii, dtype=np.float64)
+    w = np.asarray(weights, dtype=np.float64)
+    z = sample_points(turns)
+    grid = grid_direct_nu if form == "direct" else grid_series_nu
+    zero_idx = None
+    if first_a_zero:
+        hits = np.nonzero(radii == 0.0)[0]
+        if hits.size == 0:
+            raise ValueError("first_a_zero needs a radius equal to 0")
+        zero_idx = int(hits[0])
+    idx, a_list, c_list, e_list, mg = [], [], [], [energy_nu(G, w)], []
+    for k in range(steps):
+        V = grid(G, turns, w, radii, n)
+        f = None
+        if forced is not None:
+            f = tuple(forced[k])
+        elif first_a_zero and k == 0:
+            f = (zero_idx, 0)
+        (m, j), margin = select(V, f)
+        a = radii[m] * np.exp(2j * np.pi * j / n)
+        coef = V[m, j]
+        G = update_nu(G, z, a, coef)
+        idx.append((m, j))
+        a_list.append(a)
+        c_list.append(coef)
+        e_list.append(energy_nu(G, w))
+        mg.append(margin)
+    return Decomposition(idx, a_list, c_list, e_list, mg, G)

@@ -351,6 +351,131 @@ def pin_three_power_sizes(O):
     assert abs(d.energy[1] - e1) < 1e-13 * abs(w) ** 2
 
 
+# ------------------------------------------------------------------ non-uniform samples
+def _nu_loops(G, turns, weights, radii, n):
+    """The quadrature rule written out with plain Python loops (tiny inputs only)."""
+    import cmath
+    import math
+    out = []
+    for r in radii:
+        row = []
+        for j in range(n):
+            a = r * cmath.exp(2j * math.pi * j / n)
+            s = 0j
+            for t, w, g in zip(turns, weights, G):
+                s += w * complex(g) / (1 - a * cmath.exp(-2j * math.pi * t))
+            row.append(math.sqrt(1 - r * r) * s)
+        out.append(row)
+    return np.array(out)
+
+
+def _two_grids(n1, b1, n2, b2, alpha):
+    """Union of two rotated uniform grids (positions in turns, sorted) with
+    weights alpha/n1 and (1 - alpha)/n2: a quadrature exact for the
+    trigonometric polynomials up to degree min(n1, n2) - 1."""
+    t = np.concatenate([(b1 + np.arange(n1) / n1) % 1.0, (b2 + np.arange(n2) / n2) % 1.0])
+    w = np.concatenate([np.full(n1, alpha / n1), np.full(n2, (1 - alpha) / n2)])
+    order = np.argsort(t)
+    return t[order], w[order]
+
+
+def pin_nonuniform_rule(O):
+    """Non-uniform samples (Sec. 3.2, remark after Step 2).  The quadrature
+    grid values against pure-Python loops; the uniform positions t_n = n/N
+    with w_n = 1/N give the uniform grid values and decomposition; trapezoid
+    weights sum to 1 and are 1/N on uniform positions; on a union of two
+    rotated grids (n1 at beta1, n2 at beta2, weights alpha/n1, (1-alpha)/n2)
+    a polynomial of degree < min(n1, n2) has the closed form
+    sqrt(1-r^2) G(a) [alpha/(1 - (a e^{-2 pi i beta1})^n1) + (1-alpha)/(1 - (a e^{-2 pi i beta2})^n2)]."""
+    rng = _rng(51)
+    t = np.sort(rng.random(7))
+    w = rng.random(7) + 0.2
+    G = rng.standard_normal(7) + 1j * rng.standard_normal(7)
+    radii = np.array([0.0, 0.3, 0.8])
+    assert _rel(O.grid_direct_nu(G, t, w, radii, 8), _nu_loops(G, t, w, radii, 8)) < 1e-13
+    wt = O.trapezoid_weights(t)
+    assert abs(wt.sum() - 1.0) < 1e-15 and np.all(wt > 0)
+    assert abs(wt[0] - (t[1] - (t[-1] - 1.0)) / 2) < 1e-16
+    # clustered positions: the quadrature norm of e_b approaches its integral, 1
+    sc = np.arange(2000) / 2000
+    tc = sc + 0.3 * np.sin(2 * np.pi * sc) / (2 * np.pi)
+    eb = O.szego(0.5 * np.exp(0.4j), O.sample_points(tc))
+    assert abs(O.energy_nu(eb, O.trapezoid_weights(tc)) - 1.0) < 1e-4
+    N = 64
+    tu = np.arange(N) / N
+    assert np.max(np.abs(O.trapezoid_weights(tu) - 1.0 / N)) < 1e-17
+    Gu = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    radii = np.array([0.0, 0.2, 0.6, 0.9, 0.99])
+    assert _rel(O.grid_direct_nu(Gu, tu, np.full(N, 1.0 / N), radii, N), O.grid_direct(Gu, radii)) < 1e-13
+    du = O.decompose_nu(Gu, tu, np.full(N, 1.0 / N), radii, N, 4)
+    d = O.decompose(Gu, radii, 4, form="direct")
+    assert np.array_equal(du.index, d.index)
+    assert _rel(du.coef, d.coef) < 1e-12 and _rel(du.energy, d.energy) < 1e-12
+    assert _rel(du.remainder, d.remainder) < 1e-11
+    n1, b1, n2, b2, alpha = 48, 0.0031, 80, 0.0117, 0.3
+    t2, w2 = _two_grids(n1, b1, n2, b2, alpha)
+    coeffs = rng.standard_normal(30) + 1j * rng.standard_normal(30)
+    z2 = O.sample_points(t2)
+    Gp = np.polyval(coeffs[::-1], z2)
+    radii = np.array([0.0, 0.35, 0.7, 0.93])
+    V = O.grid_direct_nu(Gp, t2, w2, radii, 40)
+    for m, r in enumerate(radii):
+        a = r * O.circle_points(40)
+        ref = np.sqrt(1 - r * r) * np.polyval(coeffs[::-1], a) * (
+            alpha / (1 - (a * np.exp(-2j * np.pi * b1)) ** n1)
+            + (1 - alpha) / (1 - (a * np.exp(-2j * np.pi * b2)) ** n2))
+        assert _rel(V[m], ref) < 1e-12
+
+
+def pin_nonuniform_series(O):
+    """The non-uniform DFT and the series form: c_l of a single sample is
+    u e^{-2 pi i l t}; the series form equals the quadrature rule once r^N is
+    negligible (jittered positions, trapezoid weights); the normalised Szego
+    kernel e_b on the two-grid union has the closed form
+    sqrt((1-|a|^2)(1-|b|^2)) sum_g alpha_g (1 - (xy)^n_g) / ((1 - xy)(1 - x^n_g)(1 - y^n_g)),
+    x = conj(b) e^{2 pi i beta_g}, y = a e^{-2 pi i beta_g}; and one step on w e_b
+    (b on the grid) selects b with that coefficient and the eq. (7) update."""
+    c = O.nudft(np.array([2.0 - 1.0j]), np.array([0.1234567]), 9)
+    ref = (2.0 - 1.0j) * np.exp(-2j * np.pi * np.arange(9) * 0.1234567)
+    assert _rel(c, ref) < 1e-14
+    rng = _rng(52)
+    N = 256
+    t = np.sort((np.arange(300) + 0.45 * rng.random(300)) / 300)
+    w = O.trapezoid_weights(t)
+    G = rng.standard_normal(300) + 1j * rng.standard_normal(300)
+    radii = np.array([0.0, 0.1, 0.5, 0.8, 0.85])
+    assert _rel(O.grid_series_nu(G, t, w, radii, N), O.grid_direct_nu(G, t, w, radii, N)) < 1e-12
+    n1, b1, n2, b2, alpha = 48, 0.0031, 80, 0.0117, 0.3
+    t2, w2 = _two_grids(n1, b1, n2, b2, alpha)
+    z2 = O.sample_points(t2)
+    n = 40
+    b = 0.5 * np.exp(2j * np.pi * 13 / n)
+    wk = 0.6 + 0.8j
+    Gk = wk * O.szego(b, z2)
+    radii = np.round(np.arange(0, 20) / 20.0, 12)
+
+    def kernel_closed(a):
+        tot = 0.0
+        for ng, bg, ag in ((n1, b1, alpha), (n2, b2, 1 - alpha)):
+            x = np.conj(b) * np.exp(2j * np.pi * bg)
+            y = a * np.exp(-2j * np.pi * bg)
+            tot = tot + ag * (1 - (x * y) ** ng) / ((1 - x * y) * (1 - x ** ng) * (1 - y ** ng))
+        return np.sqrt((1 - abs(a) ** 2) * (1 - abs(b) ** 2)) * tot
+
+    V = O.grid_direct_nu(Gk, t2, w2, radii, n)
+    for m in (3, 10, 17):
+        a = radii[m] * O.circle_points(n)
+        assert _rel(V[m], wk * kernel_closed(a)) < 1e-12
+    d = O.decompose_nu(Gk, t2, w2, radii, n, 1)
+    assert tuple(d.index[0]) == (10, 13)
+    assert abs(d.coef[0] - wk * kernel_closed(b)) < 1e-13
+    e_a = np.sqrt(1 - abs(b) ** 2) / (1 - np.conj(b) * z2)
+    rem = (Gk - d.coef[0] * e_a) * (1 - np.conj(b) * z2) / (z2 - b)
+    assert _rel(d.remainder, rem) < 1e-13
+    assert abs(d.energy[1] - np.sum(w2 * np.abs(rem) ** 2)) < 1e-14
+    assert abs(d.energy[0] - np.sum(w2 * np.abs(Gk) ** 2)) < 1e-14 * d.energy[0]
+
+
 # ------------------------------------------------------------------ relative error (Sec. 4, eq. er)
 def pin_relative_errors(O):
     """delta_n from the partial sums equals E_n/E_0 from the remainders at every
@@ -399,6 +524,8 @@ ALL_PINS = [
     pin_zero_radius_is_dft,
     pin_energy_with_aliasing,
     pin_three_power_sizes,
+    pin_nonuniform_rule,
+    pin_nonuniform_series,
     pin_expansion,
     pin_invariances,
     pin_paper_tables,

@@ -47,8 +47,27 @@ def _mutant(**overrides):
             idx.append((m, j)); a_l.append(a); c_l.append(V[m, j]); e_l.append(ns.energy(G)); mg.append(margin)
         return OA.Decomposition(idx, a_l, c_l, e_l, mg, G)
 
+    def decompose_nu(G, turns, weights, radii, n, steps, first_a_zero=False, forced=None, form="direct"):
+        G = np.asarray(G, dtype=np.complex128).copy()
+        radii = np.asarray(radii, dtype=np.float64)
+        z = ns.sample_points(turns)
+        grid = ns.grid_direct_nu if form == "direct" else ns.grid_series_nu
+        idx, a_l, c_l, e_l, mg = [], [], [], [ns.energy_nu(G, weights)], []
+        zero = int(np.nonzero(radii == 0.0)[0][0]) if first_a_zero else None
+        for k in range(steps):
+            V = grid(G, turns, weights, radii, n)
+            f = tuple(forced[k]) if forced is not None else ((zero, 0) if first_a_zero and k == 0 else None)
+            (m, j), margin = ns.select(V, f)
+            a = radii[m] * np.exp(2j * np.pi * j / n)
+            G = ns.update_nu(G, z, a, V[m, j])
+            idx.append((m, j)); a_l.append(a); c_l.append(V[m, j]); e_l.append(ns.energy_nu(G, weights))
+            mg.append(margin)
+        return OA.Decomposition(idx, a_l, c_l, e_l, mg, G)
+
     if "decompose" not in overrides:
         ns.decompose = decompose
+    if "decompose_nu" not in overrides:
+        ns.decompose_nu = decompose_nu
     return ns
 
 
@@ -143,6 +162,22 @@ def _energy_sum(G):
     return float(np.sum(np.abs(G) ** 2))
 
 
+def _grid_direct_nu_unweighted(G, turns, weights, radii, n):
+    return OA.grid_direct_nu(G, turns, np.full(len(G), 1.0 / len(G)), radii, n)
+
+
+def _nudft_plus_sign(u, turns, count):
+    return np.conj(OA.nudft(np.conj(u), turns, count))
+
+
+def _update_nu_uniform_points(G, z, a, coef):
+    return OA.update_nu(G, OA.circle_points(len(G)), a, coef)
+
+
+def _energy_nu_unweighted(G, weights):
+    return OA.energy(G)
+
+
 MUTANTS = {
     "forward-sign inverse DFT": dict(grid_fft=_grid_fft_forward_sign),
     "aliasing factor 1/(1-r^N) dropped": dict(grid_fft=_grid_fft_no_alias),
@@ -158,6 +193,10 @@ MUTANTS = {
     "analytic part keeps the negative bins": dict(analytic_part=_analytic_negative_bins),
     "analytic part drops the Nyquist bin": dict(analytic_part=_analytic_no_nyquist),
     "relative errors shifted by one step": dict(relative_errors=_relative_errors_off_by_one),
+    "quadrature weights dropped": dict(grid_direct_nu=_grid_direct_nu_unweighted),
+    "non-uniform DFT with the inverse sign": dict(nudft=_nudft_plus_sign),
+    "non-uniform update at the uniform points": dict(update_nu=_update_nu_uniform_points),
+    "quadrature energy without weights": dict(energy_nu=_energy_nu_unweighted),
 }
 
 
