@@ -401,28 +401,28 @@ def grid_direct_nu(G, turns, weights, radii, n: int) -> np.ndarray:
 
 
 def _turns_times(l, t):
-    """frac(l * t) in extended precision for integers l and doubles t: t splits
-    into a 30-bit head (l * head is exact in double) and a tail."""
+    """frac(l * t) in [-1/2, 1/2] for integers l < 2^22 and doubles t: t splits
+    into a 30-bit head (l * head is exact in double, so is its fractional
+    part) and a tail (l * tail is below 2^-8 and rounds far below 1e-16)."""
     t = np.asarray(t, dtype=np.float64)
     head = np.round(t * 2.0 ** 30) / 2.0 ** 30
-    tail = (t - head).astype(np.longdouble)
-    prod = np.outer(np.asarray(l, dtype=np.float64), head)
-    fh = prod - np.floor(prod)
-    return fh.astype(np.longdouble) + np.outer(np.asarray(l, dtype=np.longdouble), tail)
+    tail = t - head
+    ld = np.asarray(l, dtype=np.float64)
+    prod = np.outer(ld, head)
+    f = (prod - np.floor(prod)) + np.outer(ld, tail)
+    return f - np.round(f)
 
 
 def nudft(u, turns, count: int) -> np.ndarray:
-    """Non-uniform DFT c_l = sum_n u_n e^{-2 pi i l t_n}, l = 0..count-1, the
-    phases in extended precision (the series coefficients of the remark's
-    non-uniform form of eq. term4)."""
+    """Non-uniform DFT c_l = sum_n u_n e^{-2 pi i l t_n}, l = 0..count-1 (the
+    series coefficients of the remark's non-uniform form of eq. term4); each
+    phase from the fractional turn of l t_n, so its error does not grow with l."""
     u = np.asarray(u, dtype=np.complex128)
-    two_pi = np.longdouble("6.283185307179586476925286766559005768")
     out = np.empty(count, dtype=np.complex128)
-    for l0 in range(0, count, 256):
-        ls = np.arange(l0, min(count, l0 + 256))
-        ph = two_pi * _turns_times(ls, turns)
-        e = np.cos(ph).astype(np.float64) - 1j * np.sin(ph).astype(np.float64)
-        out[l0:l0 + len(ls)] = e @ u
+    for l0 in range(0, count, 512):
+        ls = np.arange(l0, min(count, l0 + 512))
+        ph = 2.0 * np.pi * _turns_times(ls, turns)
+        out[l0:l0 + len(ls)] = (np.cos(ph) - 1j * np.sin(ph)) @ u
     return out
 
 
