@@ -18,6 +18,9 @@ M = 1000, 50-step workload (40 Szego kernels + noise at 30 dB; LDS-resident
 transforms) under "single16k", and the same recipe at N = 3^8 = 6561 (the
 radix-3 transforms) under "tern6561".
 `--workload single16k` (or `tern6561`) times that workload alone.
+`--workload nonuni16k` times non-uniform samples (also the "nonuni16k" key
+of the default line): 16384 jittered positions with trapezoidal weights, a
+grid of N = 16384 angles, M = 1000 radii uniform in [0, 0.996], 50 steps.
 `--workload batch512` times the uniform batch: 512 signals of N = 4096
 (8..32 kernels, |b| <= 0.95), M = 512, 30 steps, decomposed together.
 `--workload small1k` times the small latency-bound case: N = 1024, M = 100
@@ -146,19 +149,20 @@ def _kernel_name(prec, n):
     return f"k_radius<{tname},{k}>" if n <= (1 << 14) else f"k_big_rows<{tname},{k}>"
 
 
-def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch, kernel_timing=True):
+def run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch, kernel_timing=True, n_grid=None, plan_kw=None):
     """Time `steps` whole decompositions after `warmup` untimed ones; the
     dominant kernel (the radius kernel, or at N > 2^14 the row pass of the
     radius transforms, one launch per chunk of radii) is timed live on every
     TIMING_EVERY-th launch with events its dispatch stamps."""
     from paper_1711_08604_amd import Plan
     batch = int(sig.shape[0]) if sig.dim() == 2 else 1
-    n = int(sig.numel()) // batch
+    # (non-uniform samples: n_grid angles, the signal holds the samples)
+    n = n_grid or int(sig.numel()) // batch
     m = len(radii)
     big = n > (1 << 14)
     kind = "rows" if big else "radius"
     stream = torch.cuda.current_stream().cuda_stream
-    plan = Plan(n, radii, precision=prec, stream=stream, batch=batch)
+    plan = Plan(n, radii, precision=prec, stream=stream, batch=batch, **(plan_kw or {}))
     per_solve = 0
     if kernel_timing:
         # launches of the timed kernel per decomposition (every one stamped, untimed)
@@ -412,7 +416,13 @@ WORKLOADS = {
                 "m/100, 10 AFD steps; launch-latency bound", 200, 10),
     "tern6561": ("single-signal Core-AFD at N=3^8=6561 samples (radix-3 transforms), M=1000 radii uniform in "
                  "[0,0.999], 50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB", 30, 3),
+    "nonuni16k": ("non-uniform samples: 16384 jittered positions (trapezoidal weights), a grid of N=16384 angles, "
+                  "M=1000 radii uniform in [0,0.996], 50 AFD steps; 12 normalised Szego kernels |b|<=0.9 + CN noise "
+                  "at 40 dB", 10, 2),
 }
+
+# grid angles of the non-uniform workload (its signal holds the samples)
+NONUNI_GRID = 16384
 
 
 def _workload(name, W):
@@ -424,11 +434,18 @@ def _workload(name, W):
         return W.config5()
     if name == "tern6561":
         return W.shaped_like_config2(6561, 1000, 50)
+    if name == "nonuni16k":
+        g, t = W.nonuniform_kernel_signal(16384, item=0, kind="jitter")
+        return g, W.uniform_radii(1000, 0.996), 50, t
     return W.config2()
 
 
 def _time_workload(name, W, torch, steps, warmup, only=None, kernel_timing=True):
-    g, radii, afd_steps = _workload(name, W)
+    wl = _workload(name, W)
+    g, radii, afd_steps = wl[:3]
+    kw = {}
+    if len(wl) > 3:  # non-uniform positions
+        kw = {"n_grid": NONUNI_GRID, "plan_kw": {"sample_turns": wl[3]}}
     n, m = g.shape[-1], len(radii)
     log(f"bench: {name}: N={n} M={m} afd_steps={afd_steps} solves={steps} warmup={warmup}")
     sig = torch.from_numpy(g).to("cuda:0")
@@ -437,7 +454,7 @@ def _time_workload(name, W, torch, steps, warmup, only=None, kernel_timing=True)
     for prec in ("fp64", "fp32"):
         if only and prec != only:
             continue
-        res[prec] = run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch, kernel_timing)
+        res[prec] = run_gpu(prec, sig, radii, afd_steps, steps, warmup, torch, kernel_timing, **kw)
         log(f"bench: {name} {prec} {res[prec]['value']:.3e} evals/s, {res[prec]['ms_per_step']:.3f} ms/solve, "
             f"{res[prec]['roofline']['kernel']} {res[prec]['roofline']['avg_launch_us']:.1f} us per launch "
             f"({res[prec]['roofline']['frac']:.3f} of peak)")
@@ -448,7 +465,8 @@ def _time_workload(name, W, torch, steps, warmup, only=None, kernel_timing=True)
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "tern6561", "serve"],
+    ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "tern6561", "nonuni16k",
+                                           "serve"],
                     default="chirp1m")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
     ap.add_argument("--steps", type=int, default=None, help="timed decompositions (chirp1m: 5)")
@@ -543,6 +561,14 @@ def main():
         line["tern6561"] = {"workload": WORKLOADS["tern6561"][0],
                             **{p: {k: v[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
                                for p, v in r3.items()}}
+        # non-uniform samples through the non-uniform DFT
+        _, _, _, r4 = _time_workload("nonuni16k", W, torch, max(args.steps, 10), args.warmup, args.only, kt)
+        line["nonuni16k"] = {"workload": WORKLOADS["nonuni16k"][0],
+                             **{p: {k: v[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
+                                for p, v in r4.items()}}
+    if args.workload == "nonuni16k" and not args.no_cpu:
+        log("bench: no CPU oracle leg for the non-uniform workload (its oracle is the quadrature form)")
+        args.no_cpu = True
     if not args.no_cpu:
         log("bench: CPU oracle baseline ...")
         line["cpu_baseline"] = cpu_baseline(g, radii, args.cpu_steps, afd_steps)

@@ -82,6 +82,21 @@ typedef struct {
                              barriers need every workgroup of the launch resident at once.
                              Results are the same bit for bit.  0: the stream has the device's
                              resources to itself while the plan runs.                          */
+  /* Non-uniform samples (Sec. 3.2, the remark after Step 2).  NULL: the signal holds the N
+     uniform samples G(e^{2 pi i n/N}).  Otherwise the signal holds `samples` values G(z_n) at
+     z_n = e^{2 pi i t_n}, t_n = sample_turns[n] (host pointer, length `samples`, finite,
+     strictly increasing, in [0, 1); copied at create), and the inner product becomes the
+     quadrature sum_n w_n G(z_n) conj(F(z_n)) with w_n = sample_weights[n] (host pointer,
+     finite; NULL: the periodic trapezoidal weights (t_{n+1} - t_{n-1})/2).  The selection grid
+     stays a_{m,j} = r_m e^{2 pi i j/N}; the DFT of the samples becomes the non-uniform DFT
+     c_l = sum_n w_n G(z_n) e^{-2 pi i l t_n}, l < N.  Needs N = 2^K <= 2^14, batch 1,
+     1 <= samples <= 2^16 and radii whose kernel series r^l is negligible from l = N on (the
+     significant length of the uniform path's radius tables, at most N); else
+     AFD_E_UNSUPPORTED.  The remainder then has `samples` values; afd_reconstruct and
+     afd_analytic return AFD_E_UNSUPPORTED.                                                  */
+  const double* sample_turns;
+  const double* sample_weights; /* NULL: trapezoidal weights; ignored without sample_turns    */
+  int64_t samples;              /* number of non-uniform samples (0 with sample_turns NULL)   */
 } afd_plan_desc;
 
 /* Per-decomposition outputs.  Caller-owned; each pointer may be host memory

@@ -40,6 +40,9 @@ class PlanDesc(ctypes.Structure):
         ("recheck_band", ctypes.c_double),
         ("batch", ctypes.c_int32),
         ("concurrent", ctypes.c_int32),
+        ("sample_turns", ctypes.POINTER(ctypes.c_double)),
+        ("sample_weights", ctypes.POINTER(ctypes.c_double)),
+        ("samples", ctypes.c_int64),
     ]
 
 
@@ -125,9 +128,23 @@ def _check(status: int):
         raise AfdError(status, msg)
 
 
-def _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch=1, concurrent=False):
+def _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch=1, concurrent=False,
+               sample_turns=None, sample_weights=None):
+    """The plan descriptor and the host arrays it points to (kept alive by the caller)."""
     radii = np.ascontiguousarray(np.asarray(radii, dtype=np.float64))
     d = PlanDesc()
+    keep = [radii]
+    if sample_turns is not None:
+        t = np.ascontiguousarray(np.asarray(sample_turns, dtype=np.float64).reshape(-1))
+        d.sample_turns = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.samples = int(t.shape[0])
+        keep.append(t)
+        if sample_weights is not None:
+            w = np.ascontiguousarray(np.asarray(sample_weights, dtype=np.float64).reshape(-1))
+            if w.shape != t.shape:
+                raise ValueError("sample_weights must have one weight per sample")
+            d.sample_weights = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            keep.append(w)
     d.n = int(n)
     d.m = int(radii.shape[0])
     d.radii = radii.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -137,13 +154,14 @@ def _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch
     d.recheck_band = float(recheck_band)
     d.batch = int(batch)
     d.concurrent = 1 if concurrent else 0
-    return d, radii
+    return d, keep
 
 
 def workspace_bytes(n, radii, precision="fp64", recheck_k=8, first_a_zero=False, recheck_band=0.0,
-                    batch=1) -> int:
+                    batch=1, sample_turns=None, sample_weights=None) -> int:
     lib = load_library()
-    d, keep = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch)
+    d, keep = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, batch,
+                         sample_turns=sample_turns, sample_weights=sample_weights)
     return int(lib.afd_workspace_bytes(ctypes.byref(d)))
 
 
@@ -179,15 +197,20 @@ class Plan:
     batch > 1 decomposes that many signals of length N together."""
 
     def __init__(self, n, radii, precision="fp64", recheck_k=8, first_a_zero=False, recheck_band=0.0,
-                 stream=None, batch=1, concurrent=False):
+                 stream=None, batch=1, concurrent=False, sample_turns=None, sample_weights=None):
         """`concurrent`: the stream runs beside other streams' work on the device
-        (no step-tail grid barriers, see afd_plan_desc.concurrent)."""
+        (no step-tail grid barriers, see afd_plan_desc.concurrent).
+        `sample_turns` (and optionally `sample_weights`): non-uniform samples at
+        z = e^{2 pi i t}; the signal then holds one value per position and `n`
+        is the number of grid angles (afd_plan_desc.sample_turns)."""
         self._lib = load_library()
         self.n = int(n)
         self.precision = precision
         self.batch = int(batch)
-        d, self._radii = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, self.batch,
-                                    concurrent)
+        d, keep = _make_desc(n, radii, precision, recheck_k, first_a_zero, recheck_band, self.batch,
+                             concurrent, sample_turns, sample_weights)
+        self._radii = keep[0]
+        self.samples = int(d.samples) if sample_turns is not None else self.n
         self.m = int(self._radii.shape[0])
         self._stream = stream
         h = ctypes.c_void_p()
@@ -216,7 +239,8 @@ class Plan:
     def _outputs(self, signal, steps, picks=False):
         lead = (self.batch,) if self.batch > 1 else ()
         shapes = {"index": ((steps, 2), "i32"), "a": ((steps,), "c128"), "coef": ((steps,), "c128"),
-                  "energy": ((steps + 1,), "f64"), "margin": ((steps,), "f64"), "remainder": ((self.n,), "c128"),
+                  "energy": ((steps + 1,), "f64"), "margin": ((steps,), "f64"),
+                  "remainder": ((self.samples,), "c128"),
                   "recheck_count": ((steps,), "i32"), "flags": ((steps,), "i32"), "fp32_error": ((steps,), "f64")}
         if picks:
             shapes.update({"pick_index": ((steps, 2), "i32"), "pick_p": ((steps,), "f64"),
@@ -237,7 +261,7 @@ class Plan:
         return out, rd
 
     def _signal_ptr(self, signal):
-        total = self.n * self.batch
+        total = self.samples * self.batch
         if _is_torch_cuda(signal):
             import torch
             if signal.dtype == torch.float64:
@@ -245,10 +269,10 @@ class Plan:
             else:
                 ok = signal.dtype == torch.complex128 and signal.numel() == total
             if not (ok and signal.is_contiguous()):
-                raise ValueError(f"signal must be {self.batch} x {self.n} contiguous complex128")
+                raise ValueError(f"signal must be {self.batch} x {self.samples} contiguous complex128")
             return signal.data_ptr(), signal
         arr = np.ascontiguousarray(np.asarray(signal, dtype=np.complex128))
-        want = (self.batch, self.n) if self.batch > 1 else (self.n,)
+        want = (self.batch, self.samples) if self.batch > 1 else (self.samples,)
         if arr.shape != want:
             raise ValueError(f"signal must have shape {want}")
         return arr.ctypes.data, arr

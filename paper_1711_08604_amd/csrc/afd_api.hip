@@ -89,6 +89,8 @@ struct Layout {
   size_t heads, seconds;
   // radius transforms beyond the LDS
   size_t wl, wh, z, c0, rrec, bcounters;
+  // non-uniform samples: positions (turns), quadrature weights, points, DFT partial sums
+  size_t nu_t, nu_w, nu_z, nu_part;
   size_t total;
 };
 
@@ -116,6 +118,8 @@ struct Config {
   int chunk;    // radii per two-pass chunk (of the radii with long spectra)
   int nshort;   // N > 2^14: radii whose significant spectrum fits in N2 terms (no intermediate)
   int tern;     // N = 3^tern (radix-3 transforms, afd_tern.hip); 0: N = 2^logn
+  bool nu;      // non-uniform samples (afd_nonuni.hip)
+  int ns;       // samples per signal (N unless nu)
 };
 
 constexpr int kNumCounters = 5;  // radius, recheck, update, prepare; FP32 fallback flag word
@@ -144,6 +148,30 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
   if (d->first_a_zero && !has_zero) return fail(AFD_E_INVALID, "first_a_zero needs a radius equal to 0");
   if (d->batch < 0 || d->batch > 65535) return fail(AFD_E_INVALID, "batch must be in 0..65535");
   const int batch = d->batch == 0 ? 1 : d->batch;
+  const bool nu = d->sample_turns != nullptr;
+  if (nu) {
+    if (d->samples < 1) return fail(AFD_E_INVALID, "samples must be >= 1 with sample_turns");
+    if (d->samples > kMaxNuSamples) return fail(AFD_E_UNSUPPORTED, "non-uniform samples: at most 2^16");
+    double prev = -1.0;
+    for (int64_t i = 0; i < d->samples; ++i) {
+      const double t = d->sample_turns[i];
+      if (!std::isfinite(t) || t < 0.0 || t >= 1.0 || !(t > prev))
+        return fail(AFD_E_INVALID, "sample_turns must be finite, strictly increasing and in [0, 1)");
+      prev = t;
+      if (d->sample_weights && !std::isfinite(d->sample_weights[i]))
+        return fail(AFD_E_INVALID, "sample_weights must be finite");
+    }
+    if (logn < 1 || logn > kMaxLdsLogN)
+      return fail(AFD_E_UNSUPPORTED, "non-uniform samples need a grid of N = 2^K <= 2^14 angles");
+    if (batch > 1) return fail(AFD_E_UNSUPPORTED, "non-uniform samples need batch = 1");
+    const int bits = d->precision == AFD_FP64 ? 60 : 40;
+    for (int i = 0; i < d->m; ++i)
+      if (significant_length(d->radii[i], bits, int64_t(1) << 40) > d->n)
+        return fail(AFD_E_UNSUPPORTED,
+                    "non-uniform samples: a radius is too close to 1 for N (its kernel series needs more than N terms)");
+  } else if (d->samples != 0) {
+    return fail(AFD_E_INVALID, "samples needs sample_turns");
+  }
   if (batch > 1 && logn > kMaxLdsLogN) return fail(AFD_E_UNSUPPORTED, "batch > 1 needs N <= 2^14");
   if (int64_t(batch) * d->n * d->m >= (int64_t(1) << 40) || int64_t(batch) * d->n >= (int64_t(1) << 31))
     return fail(AFD_E_INVALID, "batch * N (* M) too large");
@@ -158,7 +186,14 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     cfg->nch = recheck_chunks(int(d->n));
     cfg->nparts = update_blocks(int(d->n));
     cfg->big = logn > kMaxLdsLogN;
-    cfg->adv = !cfg->tern && advance_supported(logn);
+    cfg->nu = nu;
+    cfg->ns = nu ? int(d->samples) : int(d->n);
+    if (nu) {
+      cfg->fwd = FwdPlan{};
+      cfg->nch = recheck_chunks(cfg->ns);
+      cfg->nparts = update_blocks(cfg->ns);
+    }
+    cfg->adv = !cfg->tern && !nu && advance_supported(logn);
     cfg->ag = cfg->adv ? advance_geom(logn) : AdvGeom{};
     if (cfg->adv) {
       cfg->fwd.tw1_size = cfg->ag.tw1_size;
@@ -227,8 +262,8 @@ Layout layout_of(const Config& c) {
   const size_t B = size_t(c.batch);
   L.heads = take(c.fp64 ? 0 : 8 * size_t(c.big ? c.M : c.nblocks) * B);
   L.seconds = take(c.fp64 || c.big ? 0 : 8 * size_t(c.nblocks) * B);
-  L.g64 = take(16 * size_t(c.N) * B);
-  L.g32 = take(c.fp64 || c.adv ? 0 : 8 * size_t(c.N) * B);
+  L.g64 = take(16 * size_t(c.ns) * B);
+  L.g32 = take(c.fp64 || c.adv || c.nu ? 0 : 8 * size_t(c.N) * B);
   L.c = take(2 * real * size_t(c.N) * B);
   // the four-step intermediate of the forward DFT, or of the fused step tail's
   L.xt = take(c.fwd.two_pass || c.adv ? 2 * real * size_t(c.N) * B : 0);
@@ -252,6 +287,10 @@ Layout layout_of(const Config& c) {
   L.probe = take(16 * B);              // replay: the grid value at each signal's forced point
   // fused step tail in single precision: the unit roots rounded to float
   L.omega_t = take(c.adv && !c.fp64 ? 8 * size_t(c.N) : 0);
+  L.nu_t = take(c.nu ? 8 * size_t(c.ns) : 0);
+  L.nu_w = take(c.nu ? 8 * size_t(c.ns) : 0);
+  L.nu_z = take(c.nu ? 16 * size_t(c.ns) : 0);
+  L.nu_part = take(c.nu ? 16 * size_t(nudft_chunks(c.ns)) * size_t(c.N) : 0);
   L.total = o;
   return L;
 }
@@ -313,7 +352,8 @@ struct afd_graph_s {
 
 namespace {
 
-afd_status build_tables(afd_plan_s* p, const double* radii) {
+afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
+  const double* radii = d->radii;
   const Config& c = p->cfg;
   const int64_t N = c.N;
   const int M = c.M, tpr = c.geom.tpr, E = c.geom.E;
@@ -330,8 +370,9 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
   else
     fft_twiddles(c.logn, c.fp64, tw.data());
   std::vector<double> twf1(2 * size_t(c.fwd.tw1_size + 1), 0.0), twf2(2 * size_t(c.fwd.tw2_size + 1), 0.0);
-  if (c.tern) {
-    // (the forward transform takes the inverse's table, conjugated)
+  if (c.tern || c.nu) {
+    // (N = 3^K: the forward transform takes the inverse's table, conjugated;
+    // non-uniform samples: no forward FFT)
   } else if (c.adv) {
     advance_twiddles(c.ag.l1, twf1.data());
     advance_twiddles(c.ag.l2, twf2.data());
@@ -348,7 +389,9 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
     for (int a = 0; a < na; ++a) pw[size_t(m) * na + a] = a == 0 ? 1.0 : (double)powl(r, sa * (long double)a);
     for (int b = 0; b < nb; ++b) pv[size_t(m) * nb + b] = b == 0 ? 1.0 : (double)powl(r, sb * (long double)b);
     const long double rN = powl(r, (long double)N);
-    sc[m] = (double)(sqrtl((1.0L - r) * (1.0L + r)) / ((long double)N * (1.0L - rN)));
+    // non-uniform samples: the series is not folded (its terms from l = N on are negligible)
+    sc[m] = c.nu ? (double)sqrtl((1.0L - r) * (1.0L + r))
+                 : (double)(sqrtl((1.0L - r) * (1.0L + r)) / ((long double)N * (1.0L - rN)));
   }
   // LDS path: r^((TPR/R0) v) for the pruned start, and the significant
   // spectrum length of each radius (weights below 2^-40 single / 2^-60 double
@@ -431,6 +474,30 @@ afd_status build_tables(afd_plan_s* p, const double* radii) {
       wi[2 * size_t(b) + 1] = lsig[order[b]];
     }
     if (e == hipSuccess) e = up(p->L.order, wi.data(), wi.size() * 4);
+  }
+  if (c.nu && e == hipSuccess) {
+    // positions, quadrature weights (periodic trapezoid unless given) and
+    // points z_n = e^{2 pi i t_n} in long double, rounded once
+    const int ns = c.ns;
+    std::vector<double> w(ns), z(2 * size_t(ns));
+    for (int n = 0; n < ns; ++n) {
+      const double t = d->sample_turns[n];
+      if (d->sample_weights) {
+        w[n] = d->sample_weights[n];
+      } else if (ns == 1) {
+        w[n] = 1.0;
+      } else {
+        const double nx = n + 1 < ns ? d->sample_turns[n + 1] : d->sample_turns[0] + 1.0;
+        const double pv = n > 0 ? d->sample_turns[n - 1] : d->sample_turns[ns - 1] - 1.0;
+        w[n] = (nx - pv) / 2.0;
+      }
+      const long double ang = two_pi * (long double)t;
+      z[2 * size_t(n)] = (double)cosl(ang);
+      z[2 * size_t(n) + 1] = (double)sinl(ang);
+    }
+    e = up(p->L.nu_t, d->sample_turns, 8 * size_t(ns));
+    if (e == hipSuccess) e = up(p->L.nu_w, w.data(), 8 * size_t(ns));
+    if (e == hipSuccess) e = up(p->L.nu_z, z.data(), 16 * size_t(ns));
   }
   const int32_t f0[2] = {p->zero_m < 0 ? 0 : p->zero_m, 0};
   if (e == hipSuccess) e = up(p->L.forced0, f0, sizeof(f0));
@@ -578,6 +645,13 @@ struct Timer {
 // choice and puts the forced point in its place, whose coefficient is the
 // FFT-form grid value (double precision) or the direct rule in double (a
 // one-entry re-check).  The winner is then in p->L.winner.
+// The re-check's samples: the plan's non-uniform positions and weights, or
+// the uniform points (null).
+RecheckSamples samples_of(afd_plan_s* p) {
+  if (!p->cfg.nu) return RecheckSamples{nullptr, nullptr, 0};
+  return RecheckSamples{p->at<double>(p->L.nu_z), p->at<double>(p->L.nu_w), p->cfg.ns};
+}
+
 afd_status replay_pick(afd_plan_s* p, int k, bool merged, PickArgs pk) {
   const Config& c = p->cfg;
   const int B = c.batch;
@@ -595,11 +669,13 @@ afd_status replay_pick(afd_plan_s* p, int k, bool merged, PickArgs pk) {
                         p->tau_band, counters + 4 * B, cand, win, B, s),
            "k_merge");
   if (!c.fp64)
-    HIPCHK(launch_recheck(cand, g64, omega, radii, int(c.N), partials, counters + 1 * B, win, B, s), "k_recheck");
+    HIPCHK(launch_recheck(cand, g64, omega, radii, int(c.N), partials, counters + 1 * B, win, B, s, samples_of(p)),
+           "k_recheck");
   pk.step = k;
   HIPCHK(launch_pick(pk, B, s), "k_pick");
   if (!c.fp64)
-    HIPCHK(launch_recheck(cand, g64, omega, radii, int(c.N), partials, counters + 1 * B, win, B, s), "k_recheck");
+    HIPCHK(launch_recheck(cand, g64, omega, radii, int(c.N), partials, counters + 1 * B, win, B, s, samples_of(p)),
+           "k_recheck");
   return AFD_OK;
 }
 
@@ -704,6 +780,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     return fail(AFD_E_INVALID, "out.energy (and out.index, out.a, out.coef when steps > 0) are required");
   const Config& c = p->cfg;
   const int N = int(c.N);
+  const int NS = c.ns;  // samples per signal
   const int B = c.batch;
   HIPCHK(hipSetDevice(p->device), "hipSetDevice");
 
@@ -716,7 +793,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
         return fail(AFD_E_INVALID, "a captured decomposition needs device pointers for the signal and outputs");
   }
   if (!sig_dev) {
-    for (int64_t i = 0; i < 2 * c.N * B; ++i)
+    for (int64_t i = 0; i < 2 * int64_t(NS) * B; ++i)
       if (!std::isfinite(signal[i])) return fail(AFD_E_NONFINITE, "signal holds NaN or Inf");
   }
   std::vector<int32_t> forced_host;
@@ -794,11 +871,16 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     if (c.adv) HIPCHK(hipMemsetAsync(p->arena + p->L.rqueue, 0, 4, s), "clearing counters");
     if (c.big) HIPCHK(hipMemsetAsync(p->arena + p->L.bcounters, 0, 4, s), "clearing counters");
   }
-  HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(N) * B, sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+  HIPCHK(hipMemcpyAsync(g64, signal, 16 * size_t(NS) * B, sig_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                         s),
          "copying signal");
   // counters are [kind][signal]: radius, recheck, update, prepare, FP32 fallback flags
-  HIPCHK(launch_prepare(g64, g32, N, epart, nonfinite, counters + 3 * B, rec, B, s), "k_prepare");
+  const RecheckSamples smp = samples_of(p);
+  const double* nu_w = c.nu ? p->at<double>(p->L.nu_w) : nullptr;
+  if (c.nu)
+    HIPCHK(launch_nu_prepare(g64, nu_w, NS, epart, nonfinite, counters + 3 * B, rec, s), "k_nu_prepare");
+  else
+    HIPCHK(launch_prepare(g64, g32, N, epart, nonfinite, counters + 3 * B, rec, B, s), "k_prepare");
 
   RadiusParams rp{};
   rp.c = cspec;
@@ -893,12 +975,16 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   for (int k = 0; k < (c.adv ? 0 : steps); ++k) {
     if (!replay && p->first_a_zero && k == 0) {
       HIPCHK(launch_force(forced0, 0, 0, N, cand, B, s), "k_force");
-      HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1 * B, win, B, s), "k_recheck");
+      HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1 * B, win, B, s, smp), "k_recheck");
     } else {
       hipEvent_t e0, e1;
       HIPCHK(tm.pair(kTimeFft, &e0, &e1), "event");
       const void* gin = c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32);
-      if (c.tern)
+      if (c.nu)
+        HIPCHK(launch_nudft(g64, nu_w, p->at<double>(p->L.nu_t), smp.z, NS, N, p->at<double>(p->L.nu_part), c.fp64,
+                            cspec, s, e0, e1),
+               "non-uniform DFT");
+      else if (c.tern)
         HIPCHK(launch_fwd3(c.tern, c.fp64, gin, p->at<void>(p->L.tw), cspec, B, s, e0, e1), "forward DFT");
       else
         HIPCHK(launch_fwd(c.logn, c.fp64, gin, p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega,
@@ -934,17 +1020,20 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
         st = replay_pick(p, k, true, pk);
         if (st != AFD_OK) return st;
       } else if (!c.fp64) {
-        HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1 * B, win, B, s), "k_recheck");
+        HIPCHK(launch_recheck(cand, g64, omega, radii, N, partials, counters + 1 * B, win, B, s, smp), "k_recheck");
       }
     }
     hipEvent_t u0, u1;
     HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
     upd.step = k;
-    HIPCHK(launch_update(g64, g32, upd, B, s, u0, u1), "k_update");
+    if (c.nu)
+      HIPCHK(launch_nu_update(g64, nu_w, smp.z, NS, upd, s, u0, u1), "k_nu_update");
+    else
+      HIPCHK(launch_update(g64, g32, upd, B, s, u0, u1), "k_update");
   }
   if (graph) {
     if (out->remainder)
-      HIPCHK(hipMemcpyAsync(out->remainder, g64, 16 * size_t(N) * B, hipMemcpyDeviceToDevice, s), "copy remainder");
+      HIPCHK(hipMemcpyAsync(out->remainder, g64, 16 * size_t(NS) * B, hipMemcpyDeviceToDevice, s), "copy remainder");
     return AFD_OK;
   }
   int bad = 0;
@@ -973,7 +1062,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     if (out->pick_margin) HIPCHK(cp(out->pick_margin, R.pmargin, 8 * S * BB), "copy pick_margin");
     if (out->pick_flags) HIPCHK(cp(out->pick_flags, R.pflags, 4 * S * BB), "copy pick_flags");
   }
-  if (out->remainder) HIPCHK(cp(out->remainder, g64, 16 * size_t(N) * BB), "copy remainder");
+  if (out->remainder) HIPCHK(cp(out->remainder, g64, 16 * size_t(NS) * BB), "copy remainder");
   HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
   g_last_error.clear();
   return AFD_OK;
@@ -1008,6 +1097,7 @@ afd_status reconstruct(afd_plan_s* p, const double* a, const double* coef, int s
   if (steps > 0 && (!a || !coef)) return fail(AFD_E_INVALID, "a and coef are required when steps > 0");
   if (delta && !signal) return fail(AFD_E_INVALID, "delta needs the signal");
   const Config& c = p->cfg;
+  if (c.nu) return fail(AFD_E_UNSUPPORTED, "afd_reconstruct needs uniform samples");
   const int N = int(c.N), B = c.batch;
   HIPCHK(hipSetDevice(p->device), "hipSetDevice");
   const size_t nk = 2 * size_t(steps) * B;
@@ -1061,7 +1151,7 @@ afd_status analytic(afd_plan_s* p, const double* x, double* g) {
   if (!p) return fail(AFD_E_INVALID, "plan is NULL");
   if (!x || !g) return fail(AFD_E_INVALID, "x and g are required");
   const Config& c = p->cfg;
-  if (c.tern) return fail(AFD_E_UNSUPPORTED, "afd_analytic needs N = 2^K");
+  if (c.tern || c.nu) return fail(AFD_E_UNSUPPORTED, "afd_analytic needs N = 2^K uniform samples");
   const int N = int(c.N), B = c.batch, logn = c.logn;
   HIPCHK(hipSetDevice(p->device), "hipSetDevice");
   const size_t nsig = 2 * size_t(N) * B;
@@ -1155,7 +1245,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
     delete p;
     return fail(AFD_E_NOMEM, std::string("workspace: ") + hipGetErrorString(e));
   }
-  st = build_tables(p, desc->radii);
+  st = build_tables(p, desc);
   if (st != AFD_OK) {
     afd_plan_destroy(p);
     return st;

@@ -362,10 +362,33 @@ struct ZeroArgs {
   int n;
 };
 hipError_t launch_zero(const ZeroArgs& z, hipStream_t s);
+// Samples of the re-check: uniform (z null: e^{2 pi i n/N}, n < N) or the
+// non-uniform positions z[ns] (interleaved complex) with quadrature weights w.
+struct RecheckSamples {
+  const double* z;
+  const double* w;
+  int ns;
+};
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
-                          double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s);
+                          double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s,
+                          const RecheckSamples& S = RecheckSamples{nullptr, nullptr, 0});
 hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, int batch, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
+// Non-uniform samples (afd_nonuni.hip), one signal: ns samples g (interleaved
+// complex), positions `turns`, points z = e^{2 pi i turns} (interleaved),
+// quadrature weights wt.  The non-uniform DFT writes c_l, l < N, in the
+// radius transforms' precision through `part` (nudft_chunks(ns) x N complex
+// double).
+constexpr int kMaxNuSamples = 1 << 16;
+int nudft_chunks(int ns);
+hipError_t launch_nudft(const double* g, const double* wt, const double* turns, const double* z, int ns, int N,
+                        double* part, bool fp64, void* c, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
+hipError_t launch_nu_prepare(const double* g, const double* wt, int ns, double* epart, int* nonfinite,
+                             unsigned int* counter, const RecordArgs& R, hipStream_t s);
+hipError_t launch_nu_update(double* g, const double* wt, const double* z, int ns, const UpdateArgs& U, hipStream_t s,
+                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Reconstruction and analytic front end (afd_recon.hip), double precision.
 int recon_waves(int N);  // wave partial sums per signal and step in `wpart`

@@ -79,21 +79,27 @@ __global__ void k_force(const int32_t* __restrict__ forced, int fstride, int ste
 // e^{2 pi i (j - n)/N} = e^{2 pi i j/N} conj(e^{2 pi i n/N}), so the samples
 // are read once per step rather than once per candidate.  The wave sums of
 // every candidate meet in LDS and are added in wave order after the loop.
+// Non-uniform samples (S.z non-null): the NS samples sit at S.z[n] in place of
+// e^{2 pi i n/N}, each term carries the quadrature weight S.w[n], and the sum
+// is scaled by sqrt(1 - r^2) instead of sqrt(1 - r^2)/N.
 constexpr int kRecheckPerThread = 8;  // chunk of 2048 samples over 256 threads
 __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ cand, const double* __restrict__ g,
                                                  const double* __restrict__ omega, const double* __restrict__ radii,
                                                  int N, int nch, double* __restrict__ partials,
-                                                 unsigned int* __restrict__ counter, Winner* __restrict__ w) {
+                                                 unsigned int* __restrict__ counter, Winner* __restrict__ w,
+                                                 RecheckSamples S) {
   __shared__ double wsum[kKMax][4][2];  // [candidate][wave] (re, im)
   __shared__ double wd[16];
   __shared__ Best bb[16];
   __shared__ int s_last;
   const int chunk = blockIdx.x;
-  const int cl = (N + nch - 1) / nch;  // samples per chunk (the last may hold fewer)
+  const int ns = S.z ? S.ns : N;  // samples
+  const double* __restrict__ zs = S.z ? S.z : omega;
+  const int cl = (ns + nch - 1) / nch;  // samples per chunk (the last may hold fewer)
   const int b = blockIdx.y;
   const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
   cand += b;
-  g += 2 * size_t(N) * b;
+  g += 2 * size_t(ns) * b;
   partials += 2 * size_t(kKMax) * size_t(nch) * b;
   counter += b;
   w += b;
@@ -103,11 +109,16 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
   for (int q = 0; q < kRecheckPerThread; ++q) {
     const int i = tid + 256 * q;
     const int n = chunk * cl + i;
-    const bool in = i < cl && n < N;
+    const bool in = i < cl && n < ns;
     gx[q] = in ? g[2 * n] : 0.0;
     gy[q] = in ? g[2 * n + 1] : 0.0;
-    ox[q] = in ? omega[2 * n] : 1.0;
-    oy[q] = in ? omega[2 * n + 1] : 0.0;
+    ox[q] = in ? zs[2 * n] : 1.0;
+    oy[q] = in ? zs[2 * n + 1] : 0.0;
+    if (S.w && in) {
+      const double wn = S.w[n];
+      gx[q] *= wn;
+      gy[q] *= wn;
+    }
   }
   for (int c = 0; c < count; ++c) {
     const uint32_t f = key_f(cand->keys[c]);
@@ -150,7 +161,7 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
     key = cand->keys[tid];
     rk = radii[key_f(key) / uint32_t(N)];
   }
-  winner_from_partials(count, cand->flags, key, rk, partials, N, nch, w, bb, wd);
+  winner_from_partials(count, cand->flags, key, rk, partials, N, S.z ? 1.0 : double(N), nch, w, bb, wd);
 }
 
 // Same merge functions, workgroup size and record order as the fused step
@@ -280,11 +291,13 @@ hipError_t launch_pick(const PickArgs& a, int batch, hipStream_t s) {
 }
 
 hipError_t launch_recheck(const CandList* cand, const double* g, const double* omega, const double* radii, int N,
-                          double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s) {
-  const int nch = recheck_chunks(N);
-  if ((N + nch - 1) / nch > 256 * kRecheckPerThread) return hipErrorInvalidValue;  // a chunk fits the registers
+                          double* partials, unsigned int* counter, Winner* w, int batch, hipStream_t s,
+                          const RecheckSamples& S) {
+  const int ns = S.z ? S.ns : N;
+  const int nch = recheck_chunks(ns);
+  if ((ns + nch - 1) / nch > 256 * kRecheckPerThread) return hipErrorInvalidValue;  // a chunk fits the registers
   hipLaunchKernelGGL(k_recheck, dim3(nch, batch), dim3(256), 0, s, cand, g, omega, radii, N, nch, partials,
-                     counter, w);
+                     counter, w, S);
   return hipGetLastError();
 }
 

@@ -52,14 +52,15 @@ __device__ __forceinline__ void blaschke_apply(const Blaschke& B, const double* 
 // Winner of the short-list from the chunk partial sums of the direct rule
 // (Sec. 3.1, eq. term81): partials[i][ch] holds the (re, im) sum of
 // G[n] / (1 - r_i e^{2 pi i (j_i - n)/N}) over chunk ch of the samples for
-// candidate i; the inner product is that sum times sqrt(1 - r_i^2)/N.  One
+// candidate i; the inner product is that sum times sqrt(1 - r_i^2)/div (div = N,
+// or 1 for weighted non-uniform samples).  One
 // candidate per thread (count <= kKMax <= blockDim.x): thread i passes its
 // key and radius (ignored for i >= count).  Largest |.|^2 wins, ties to the
 // lowest flat index.  Thread 0 writes the result to *w (any address space);
 // `bb`, `wd`: LDS Best[16], double[16].
 __device__ __forceinline__ void winner_from_partials(int count, int cflags, uint64_t key, double r,
-                                                     const double* __restrict__ partials, int N, int nch,
-                                                     Winner* w, Best* bb, double* wd) {
+                                                     const double* __restrict__ partials, int N, double div,
+                                                     int nch, Winner* w, Best* bb, double* wd) {
   const bool forced = (cflags & kFlagForced) != 0;
   Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
   double err = 0.0;
@@ -70,7 +71,7 @@ __device__ __forceinline__ void winner_from_partials(int count, int cflags, uint
       ax += ld_agent(pp + 2 * ch);
       ay += ld_agent(pp + 2 * ch + 1);
     }
-    const double s = sqrt((1.0 - r) * (1.0 + r)) / double(N);
+    const double s = sqrt((1.0 - r) * (1.0 + r)) / div;
     const Best x{(ax * s) * (ax * s) + (ay * s) * (ay * s), -1.0, ax * s, ay * s, key_f(key)};
     err = fabs(double(key_p(key)) - x.p1);
     b = x;

@@ -79,9 +79,11 @@ def _check_step(g, ref, k, tol, prec, report):
 
 
 def compare(gpu, ref: "O.Decomposition", tol: float, signal=None, radii=None, forced_first: bool = False,
-            prec: str | None = None):
+            prec: str | None = None, nonuniform=None):
     """Free-running GPU decomposition against the oracle's.  Return
-    (steps_compared, report dict); raise AssertionError on a violation."""
+    (steps_compared, report dict); raise AssertionError on a violation.
+    `nonuniform` = (turns, weights, n) for a decomposition of non-uniform
+    samples (the near-tie check then uses the oracle's series form)."""
     g = to_numpy(gpu)
     prec = prec or ("fp64" if tol <= TOL["fp64"] else "fp32")
     S = ref.coef.shape[0]
@@ -105,9 +107,15 @@ def compare(gpu, ref: "O.Decomposition", tol: float, signal=None, radii=None, fo
         # near-tie: the GPU's choice must be one of the (nearly) equal maxima of
         # the oracle grid, whose maximum is |c_k|^2 of the oracle's own step
         # (the trajectories agree up to here)
-        Gk = O.decompose_streamed(signal, radii, upto, forced=ref.index[:upto]).remainder if upto > 0 else signal
         m, j = (int(v) for v in g["index"][upto])
-        p = abs(O.grid_fft(Gk, np.asarray(radii)[m:m + 1])[0, j]) ** 2
+        if nonuniform is not None:
+            t, w, n = nonuniform
+            Gk = (O.decompose_nu(signal, t, w, radii, n, upto, forced=ref.index[:upto], form="series").remainder
+                  if upto > 0 else signal)
+            p = abs(O.grid_series_nu(Gk, t, w, np.asarray(radii)[m:m + 1], n)[0, j]) ** 2
+        else:
+            Gk = O.decompose_streamed(signal, radii, upto, forced=ref.index[:upto]).remainder if upto > 0 else signal
+            p = abs(O.grid_fft(Gk, np.asarray(radii)[m:m + 1])[0, j]) ** 2
         pmax = abs(ref.coef[upto]) ** 2
         assert p >= pmax * (1 - NEAR_TIE), ("near-tie choice not maximal", upto, p, pmax)
         report["near_tie_step"] = upto

@@ -144,3 +144,54 @@ def test_workspace_bytes_three_powers():
     assert all(b > 0 for b in sizes) and sizes == sorted(sizes), sizes
     d, keep = _desc(afd, n=3 ** 8, radii=np.linspace(0, 0.99, 50), precision=1, batch=4)
     assert lib.afd_workspace_bytes(ctypes.byref(d)) > sizes[-1]
+
+
+def _nu_desc(afd, n=256, radii=(0.0, 0.5), turns=None, weights=None, batch=0, precision=0):
+    d, keep = _desc(afd, n=n, radii=radii, batch=batch, precision=precision)
+    t = np.ascontiguousarray(np.arange(100) / 100 + 0.001 if turns is None else np.asarray(turns, dtype=np.float64))
+    d.sample_turns = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.samples = t.shape[0]
+    keep = [keep, t]
+    if weights is not None:
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        d.sample_weights = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        keep.append(w)
+    return d, keep
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(turns=[0.1, 0.1, 0.5]), 1),            # not strictly increasing
+    (dict(turns=[0.2, 0.1]), 1),
+    (dict(turns=[0.0, 1.0]), 1),                 # outside [0, 1)
+    (dict(turns=[-0.1, 0.5]), 1),
+    (dict(turns=[0.0, np.nan]), 1),
+    (dict(weights=[np.inf] + [0.01] * 99), 1),
+    (dict(radii=(0.0, 0.99)), 5),                # kernel series longer than N = 256 terms
+    (dict(n=243), 5),                            # the grid must be 2^K
+    (dict(n=1 << 15), 5),
+    (dict(batch=2), 5),
+    (dict(turns=np.arange(1 << 17) / (1 << 17)), 5),
+])
+def test_nonuniform_rejects(kw, status):
+    afd, lib = _lib()
+    d, keep = _nu_desc(afd, **kw)
+    h = ctypes.c_void_p(123)
+    st = lib.afd_plan_create(ctypes.byref(d), None, ctypes.byref(h))
+    assert st == status, (kw, st, lib.afd_last_error())
+    assert h.value is None
+    assert lib.afd_workspace_bytes(ctypes.byref(d)) == 0
+
+
+def test_nonuniform_workspace():
+    """A non-uniform plan sizes its samples and its non-uniform DFT partials;
+    samples without positions are rejected."""
+    afd, lib = _lib()
+    d1, k1 = _nu_desc(afd, n=1024, radii=np.linspace(0, 0.95, 20), turns=np.arange(1000) / 1000)
+    d2, k2 = _nu_desc(afd, n=1024, radii=np.linspace(0, 0.95, 20), turns=np.arange(4000) / 4000)
+    b1, b2 = lib.afd_workspace_bytes(ctypes.byref(d1)), lib.afd_workspace_bytes(ctypes.byref(d2))
+    assert 0 < b1 < b2
+    # 3000 more samples: 40 B of tables each plus 12 more chunks of 1024 complex partials
+    assert b2 - b1 >= 3000 * 40 + 12 * 1024 * 16
+    d3, k3 = _desc(afd, n=1024)
+    d3.samples = 1000
+    assert lib.afd_workspace_bytes(ctypes.byref(d3)) == 0

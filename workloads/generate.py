@@ -9,7 +9,10 @@ Recipes (all complex128 samples on z_n = e^{2 pi i n/N}, n = 0..N-1):
 * optional complex white noise CN(0, s^2) at a stated SNR, s^2 = mean|G|^2 * 10^(-SNR/10);
 * a real chirp + Gaussian-windowed tones + real white noise, reduced to its
   H^2 (analytic) part by zeroing the negative-frequency bins;
-* the two closed-form signals of the paper's Sec. 4 experiments.
+* the two closed-form signals of the paper's Sec. 4 experiments;
+* non-uniform samples: positions t_n in turns, jittered (t_n = (n + j U_n)/N_s,
+  j < 1) or clustered (t_n = s_n + c sin(2 pi s_n)/(2 pi), s_n = n/N_s, c < 1),
+  with kernel sums evaluated at z_n = e^{2 pi i t_n}.
 
 Seeds: numpy.random.SeedSequence([20171108, config, item]) with PCG64.
 """
@@ -35,6 +38,8 @@ __all__ = [
     "config3_batch",
     "config5",
     "shaped_like_config2",
+    "nonuniform_positions",
+    "nonuniform_kernel_signal",
 ]
 
 SEED_ROOT = 20171108
@@ -172,3 +177,30 @@ def config5(item: int = 0, n: int = 1 << 20, m: int = 2000, steps: int = 100):
     power = float(np.mean(x * x))
     x = x + np.sqrt(power * 10.0 ** (-2.0)) * rng.standard_normal(n)
     return analytic_part(x.astype(np.complex128)), uniform_radii(m), steps
+
+
+def nonuniform_positions(rng, ns: int, kind: str = "jitter", amount: float = 0.8) -> np.ndarray:
+    """Strictly increasing sample positions in [0, 1) (turns): "jitter" moves
+    each uniform position n/ns by amount * U[0, 1) of a spacing; "cluster"
+    warps s = n/ns to s + amount sin(2 pi s)/(2 pi) (denser near s = 1/2)."""
+    s = np.arange(ns, dtype=np.float64) / ns
+    if kind == "jitter":
+        return s + amount * rng.random(ns) / ns
+    if kind == "cluster":
+        return s + amount * np.sin(2.0 * np.pi * s) / (2.0 * np.pi)
+    raise ValueError(kind)
+
+
+def nonuniform_kernel_signal(ns: int, item: int = 0, kind: str = "jitter", count: int = 12, rmax: float = 0.9,
+                             snr_db: float = 40.0):
+    """Kernel sum (count poles area-uniform in |b| <= rmax, CN(0,1) weights) at
+    non-uniform positions, plus CN noise at snr_db.  Returns (samples, turns)."""
+    rng = rng_for(6, item)
+    t = nonuniform_positions(rng, ns, kind)
+    z = np.exp(2j * np.pi * t)
+    poles = _poles_area_uniform(rng, count, rmax)
+    weights = _cn01(rng, count)
+    g = np.zeros(ns, dtype=np.complex128)
+    for b, w in zip(poles, weights):
+        g += w * np.sqrt(1.0 - abs(b) ** 2) / (1.0 - np.conj(b) * z)
+    return add_noise(rng, g, snr_db), t
