@@ -90,7 +90,10 @@ struct Layout {
   // radius transforms beyond the LDS
   size_t wl, wh, z, c0, rrec, bcounters;
   // non-uniform samples: positions (turns), quadrature weights, points, DFT partial sums
-  size_t nu_t, nu_w, nu_z, nu_part;
+  size_t nu_t, nu_w, nu_z;
+  // and the gridding non-uniform FFT: shifted weights, cell ranges, deconvolution,
+  // grid, its transform, intermediate, twiddles and unit roots of the G-cell grid
+  size_t nu_ws, nu_rng, nu_dinv, nu_b, nu_B, nu_xt, nu_tw1, nu_tw2, nu_omega;
   size_t total;
 };
 
@@ -290,7 +293,17 @@ Layout layout_of(const Config& c) {
   L.nu_t = take(c.nu ? 8 * size_t(c.ns) : 0);
   L.nu_w = take(c.nu ? 8 * size_t(c.ns) : 0);
   L.nu_z = take(c.nu ? 16 * size_t(c.ns) : 0);
-  L.nu_part = take(c.nu ? 16 * size_t(nudft_chunks(c.ns)) * size_t(c.N) : 0);
+  const size_t G = c.nu ? size_t(1) << nu_grid_log2(c.logn) : 0;
+  const FwdPlan gp = c.nu ? fwd_plan(nu_grid_log2(c.logn), true) : FwdPlan{};
+  L.nu_ws = take(16 * size_t(c.nu ? c.ns : 0));
+  L.nu_rng = take(16 * G);
+  L.nu_dinv = take(c.nu ? 8 * size_t(c.N) : 0);
+  L.nu_b = take(16 * G);
+  L.nu_B = take(16 * G);
+  L.nu_xt = take(16 * G);
+  L.nu_tw1 = take(c.nu ? 16 * size_t(gp.tw1_size + 1) : 0);
+  L.nu_tw2 = take(c.nu ? 16 * size_t(gp.tw2_size + 1) : 0);
+  L.nu_omega = take(16 * G);
   L.total = o;
   return L;
 }
@@ -498,6 +511,38 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
     e = up(p->L.nu_t, d->sample_turns, 8 * size_t(ns));
     if (e == hipSuccess) e = up(p->L.nu_w, w.data(), 8 * size_t(ns));
     if (e == hipSuccess) e = up(p->L.nu_z, z.data(), 16 * size_t(ns));
+    // the non-uniform FFT: strengths' factor w_n e^{-2 pi i (N/2) t_n} (the
+    // fractional turn of (N/2) t_n is exact), cell ranges, deconvolution,
+    // and the forward-transform tables of the G-cell grid
+    std::vector<double> ws(2 * size_t(ns));
+    for (int n = 0; n < ns; ++n) {
+      const double h = double(N / 2) * d->sample_turns[n];  // exact: N/2 is a power of two
+      const long double ang = two_pi * (long double)(h - std::nearbyint(h));
+      ws[2 * size_t(n)] = (double)((long double)w[n] * cosl(ang));
+      ws[2 * size_t(n) + 1] = (double)(-(long double)w[n] * sinl(ang));
+    }
+    const int lg = nu_grid_log2(c.logn);
+    const int64_t G = int64_t(1) << lg;
+    std::vector<int32_t> rng(4 * size_t(G));
+    nu_cell_ranges(d->sample_turns, ns, int(G), rng.data());
+    std::vector<double> dinv(static_cast<size_t>(N));
+    nu_deconv_table(int(N), int(G), dinv.data());
+    const FwdPlan gp = fwd_plan(lg, true);
+    std::vector<double> gtw1(2 * size_t(gp.tw1_size + 1), 0.0), gtw2(2 * size_t(gp.tw2_size + 1), 0.0);
+    fft_twiddles(gp.two_pass ? gp.l1 : lg, true, gtw1.data());
+    if (gp.two_pass) fft_twiddles(gp.l2, true, gtw2.data());
+    std::vector<double> gom(2 * size_t(G));
+    for (int64_t k = 0; k < G; ++k) {
+      const long double ang = two_pi * (long double)k / (long double)G;
+      gom[2 * k] = (double)cosl(ang);
+      gom[2 * k + 1] = (double)sinl(ang);
+    }
+    if (e == hipSuccess) e = up(p->L.nu_ws, ws.data(), 8 * ws.size());
+    if (e == hipSuccess) e = up(p->L.nu_rng, rng.data(), 4 * rng.size());
+    if (e == hipSuccess) e = up(p->L.nu_dinv, dinv.data(), 8 * dinv.size());
+    if (e == hipSuccess) e = up(p->L.nu_tw1, gtw1.data(), 8 * gtw1.size());
+    if (e == hipSuccess) e = up(p->L.nu_tw2, gtw2.data(), 8 * gtw2.size());
+    if (e == hipSuccess) e = up(p->L.nu_omega, gom.data(), 8 * gom.size());
   }
   const int32_t f0[2] = {p->zero_m < 0 ? 0 : p->zero_m, 0};
   if (e == hipSuccess) e = up(p->L.forced0, f0, sizeof(f0));
@@ -645,6 +690,22 @@ struct Timer {
 // choice and puts the forced point in its place, whose coefficient is the
 // FFT-form grid value (double precision) or the direct rule in double (a
 // one-entry re-check).  The winner is then in p->L.winner.
+// The non-uniform FFT's device tables of a plan.
+NuTables nu_tables(afd_plan_s* p) {
+  NuTables t{};
+  t.turns = p->at<double>(p->L.nu_t);
+  t.ws = p->at<double>(p->L.nu_ws);
+  t.rng = p->at<int4>(p->L.nu_rng);
+  t.b = p->at<double>(p->L.nu_b);
+  t.B = p->at<double>(p->L.nu_B);
+  t.xt = p->at<void>(p->L.nu_xt);
+  t.tw1 = p->at<void>(p->L.nu_tw1);
+  t.tw2 = p->at<void>(p->L.nu_tw2);
+  t.omega = p->at<double>(p->L.nu_omega);
+  t.dinv = p->at<double>(p->L.nu_dinv);
+  return t;
+}
+
 // The re-check's samples: the plan's non-uniform positions and weights, or
 // the uniform points (null).
 RecheckSamples samples_of(afd_plan_s* p) {
@@ -981,9 +1042,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       HIPCHK(tm.pair(kTimeFft, &e0, &e1), "event");
       const void* gin = c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32);
       if (c.nu)
-        HIPCHK(launch_nudft(g64, nu_w, p->at<double>(p->L.nu_t), smp.z, NS, N, p->at<double>(p->L.nu_part), c.fp64,
-                            cspec, s, e0, e1),
-               "non-uniform DFT");
+        HIPCHK(launch_nu_fourier(g64, nu_tables(p), c.logn, c.fp64, cspec, s, e0, e1), "non-uniform DFT");
       else if (c.tern)
         HIPCHK(launch_fwd3(c.tern, c.fp64, gin, p->at<void>(p->L.tw), cspec, B, s, e0, e1), "forward DFT");
       else

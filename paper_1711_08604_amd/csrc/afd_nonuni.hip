@@ -10,108 +10,82 @@
 // 2^-60 / 2^-40 cut as the uniform path's), so the radius kernel runs
 // unchanged on c_0..c_{N-1} with the scale sqrt(1 - r^2).
 //
-//   k_nudft, k_nudft_sum  c_l, l < N: partial sums over chunks of samples,
-//                         then summed over the chunks in order
+// c_l, l < N, comes from a gridding non-uniform FFT (type 1) with the
+// "exponential of semicircle" kernel phi(x) = exp(beta (sqrt(1 - (2x/W)^2) - 1)),
+// |x| < W/2 grid cells (Barnett, Magland, af Klinteberg, SIAM J. Sci. Comput.
+// 2019): with the modes shifted to l' = l - N/2 (strengths times
+// e^{-2 pi i (N/2) t_n}), each point k of a grid of G = 4N cells gathers
+// b_k = sum_n u'_n phi(G t_n - k) (wrapped), a length-G forward FFT gives
+// B_{l'}, and c_l = B_{l'} / Phi(l'/G), Phi the kernel's Fourier transform
+// (tabled per plan).  W = 12 and beta = 2.69 W keep the error near 1e-14 of
+// max |c| (measured against the exact sum).
+//
+//   k_nu_spread           b_k from the samples within W/2 of cell k (index
+//                         ranges per cell, samples in position order)
+//   (FFT)                 the forward transforms of afd_fwd.hip, length G
+//   k_nu_deconv           c_l = B_{l'} / Phi(l'/G), in the precision of the
+//                         radius transforms
 //   k_nu_prepare          E_0 = sum_n w_n |G_n|^2 and the non-finite check
 //   k_nu_update           eq. (7) at the sample points and the quadrature
 //                         energy; the last workgroup records the step
 // All in double precision; the FP32 mode's spectrum is the double one
 // rounded once.  One signal per plan.
+#include <algorithm>
+#include <vector>
+
 #include "afd_update.h"
 
 namespace afd {
 
-constexpr int kNuThreads = 128;  // k_nudft workgroup
-constexpr int kNuL = 4;          // consecutive frequencies per thread
-constexpr int kNuChunk = 256;    // samples per workgroup (grid dimension y)
 constexpr int kNuUpdThreads = 256;
 constexpr int kNuUpdPer = 4;
 
-int nudft_chunks(int ns) { return (ns + kNuChunk - 1) / kNuChunk; }
 int nu_update_blocks(int ns) { return (ns + kNuUpdThreads * kNuUpdPer - 1) / (kNuUpdThreads * kNuUpdPer); }
 static_assert(kNuUpdThreads * kNuUpdPer == 1024, "the plan sizes the energy partials with update_blocks()");
 
-// frac(l t) for an integer l < 2^24 and a double t, to a rounding of the
-// result: l t = p + e exactly (e from the fused multiply-add), p - rint(p) is
-// exact, and adding e rounds once.
-__device__ __forceinline__ double frac_of_product(double l, double t) {
-#pragma clang fp contract(off)
-  // (no contraction: p must be the rounded product for e to be its error)
-  const double p = l * t;
-  const double e = fma(l, t, -p);
-  return (p - rint(p)) + e;
-}
+int nu_grid_log2(int logn) { return logn + 2 < 6 ? 6 : logn + 2; }  // G = 4N, at least 64 > 2W
 
-// part[chunk][l] = sum over the chunk's samples of u_n e^{-2 pi i l t_n},
-// u_n = w_n G_n.  Thread: kNuL consecutive l; e^{-2 pi i l0 t_n} from the
-// exact fractional turn and sincospi, the next ones by multiplying with
-// conj(z_n).
-__global__ __launch_bounds__(kNuThreads) void k_nudft(const double* __restrict__ g, const double* __restrict__ wt,
-                                                      const double* __restrict__ turns, const double* __restrict__ z,
-                                                      int ns, int N, double* __restrict__ part) {
-  __shared__ double su[kNuChunk][2];
-  __shared__ double sz[kNuChunk][2];
-  __shared__ double st[kNuChunk];
-  const int n0 = blockIdx.y * kNuChunk;
-  const int cnt = min(kNuChunk, ns - n0);
-  for (int i = threadIdx.x; i < cnt; i += kNuThreads) {
-    const int n = n0 + i;
-    const double w = wt[n];
-    su[i][0] = w * g[2 * n];
-    su[i][1] = w * g[2 * n + 1];
-    sz[i][0] = z[2 * n];
-    sz[i][1] = z[2 * n + 1];
-    st[i] = turns[n];
-  }
-  __syncthreads();
-  const int l0 = (blockIdx.x * kNuThreads + threadIdx.x) * kNuL;
-  if (l0 >= N) return;
-  double ax[kNuL], ay[kNuL];
+// b_k = sum of u_n phi(x), u_n = G_n ws_n (ws_n = w_n e^{-2 pi i (N/2) t_n}),
+// x = G t_n - k wrapped to [-G/2, G/2), over the samples of cell k's ranges
+// (rng[k] = {lo1, hi1, lo2, hi2}: a window that wraps around t = 0 has two).
+__global__ __launch_bounds__(256) void k_nu_spread(const double* __restrict__ g, const double* __restrict__ ws,
+                                                   const double* __restrict__ turns, const int4* __restrict__ rng,
+                                                   int G, double* __restrict__ b) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= G) return;
+  const int4 r = rng[k];
+  const double dG = double(G), half = 0.5 * dG;
+  double ax = 0.0, ay = 0.0;
 #pragma unroll
-  for (int i = 0; i < kNuL; ++i) ax[i] = ay[i] = 0.0;
-  const double dl0 = double(l0);
-  for (int i = 0; i < cnt; ++i) {
-    const double f = frac_of_product(dl0, st[i]);
-    double sn, cs;
-    sincospi(2.0 * f, &sn, &cs);
-    double ex = cs, ey = -sn;  // e^{-2 pi i l0 t}
-    const double ux = su[i][0], uy = su[i][1];
-    const double zx = sz[i][0], zy = -sz[i][1];  // conj(z_n)
-#pragma unroll
-    for (int q = 0; q < kNuL; ++q) {
-      ax[q] = fma(ux, ex, fma(-uy, ey, ax[q]));
-      ay[q] = fma(ux, ey, fma(uy, ex, ay[q]));
-      if (q + 1 < kNuL) {
-        const double nx = fma(ex, zx, -ey * zy);
-        const double ny = fma(ex, zy, ey * zx);
-        ex = nx;
-        ey = ny;
-      }
+  for (int part = 0; part < 2; ++part) {
+    const int lo = part ? r.z : r.x, hi = part ? r.w : r.y;
+    for (int n = lo; n < hi; ++n) {
+      double x = turns[n] * dG - double(k);  // exact: G is a power of two
+      if (x >= half) x -= dG;
+      if (x < -half) x += dG;
+      const double z = x * (2.0 / kEsWidth);
+      const double phi = exp(kEsBeta * (sqrt(fmax(1.0 - z * z, 0.0)) - 1.0));
+      const double gx = g[2 * n], gy = g[2 * n + 1], sx = ws[2 * n], sy = ws[2 * n + 1];
+      const double ux = fma(gx, sx, -gy * sy), uy = fma(gx, sy, gy * sx);
+      ax = fma(ux, phi, ax);
+      ay = fma(uy, phi, ay);
     }
   }
-  double* o = part + 2 * (size_t(blockIdx.y) * N + l0);
-#pragma unroll
-  for (int q = 0; q < kNuL; ++q) {
-    if (l0 + q < N) {
-      o[2 * q] = ax[q];
-      o[2 * q + 1] = ay[q];
-    }
-  }
+  b[2 * k] = ax;
+  b[2 * k + 1] = ay;
 }
 
-// c_l = sum over the chunks, in chunk order, of part[chunk][l]; written in
-// the precision of the radius transforms.
+// c_l = B_q / Phi((l - N/2)/G), q = (l - N/2) mod G; from 2^15 points the
+// forward transform leaves B in column order (bin q at (q mod N2) N1 + q / N2).
 template <typename T>
-__global__ __launch_bounds__(256) void k_nudft_sum(const double* __restrict__ part, int nchunk, int N,
-                                                   Cx<T>* __restrict__ c) {
+__global__ __launch_bounds__(256) void k_nu_deconv(const double* __restrict__ B, const double* __restrict__ dinv,
+                                                   int N, int G, int cols_l1, int cols_l2, Cx<T>* __restrict__ c) {
   const int l = blockIdx.x * 256 + threadIdx.x;
   if (l >= N) return;
-  double x = 0.0, y = 0.0;
-  for (int k = 0; k < nchunk; ++k) {
-    x += part[2 * (size_t(k) * N + l)];
-    y += part[2 * (size_t(k) * N + l) + 1];
-  }
-  c[l] = {T(x), T(y)};
+  const int q = l >= N / 2 ? l - N / 2 : l - N / 2 + G;
+  const int pos = cols_l2 ? ((q & ((1 << cols_l2) - 1)) << cols_l1) + (q >> cols_l2) : q;
+  const double d = dinv[l];
+  c[l] = {T(B[2 * pos] * d), T(B[2 * pos + 1] * d)};
 }
 
 // End of a pass over the samples: this workgroup's weighted energy partial
@@ -180,17 +154,24 @@ __global__ __launch_bounds__(kNuUpdThreads) void k_nu_update(double* __restrict_
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_nudft(const double* g, const double* wt, const double* turns, const double* z, int ns, int N,
-                        double* part, bool fp64, void* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  const int lpb = kNuThreads * kNuL;
-  const dim3 grid((N + lpb - 1) / lpb, nudft_chunks(ns));
-  launch_ev(k_nudft, grid, dim3(kNuThreads), 0u, s, e0, nullptr, g, wt, turns, z, ns, N, part);
+hipError_t launch_nu_fourier(const double* g, const NuTables& t, int logn, bool fp64, void* c, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1) {
+  const int N = 1 << logn;
+  const int lg = nu_grid_log2(logn);
+  const int G = 1 << lg;
+  launch_ev(k_nu_spread, dim3((G + 255) / 256), dim3(256), 0u, s, e0, nullptr, g, t.ws, t.turns, t.rng, G, t.b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_fwd(lg, true, t.b, t.tw1, t.tw2, t.omega, t.xt, t.B, 1, s);
+  if (e != hipSuccess) return e;
+  const FwdPlan fp = fwd_plan(lg, true);
+  const int cl1 = lg > kMaxLdsLogN ? fp.l1 : 0, cl2 = lg > kMaxLdsLogN ? fp.l2 : 0;
   if (fp64)
-    launch_ev(k_nudft_sum<double>, dim3((N + 255) / 256), dim3(256), 0u, s, nullptr, e1,
-              static_cast<const double*>(part), nudft_chunks(ns), N, static_cast<Cx<double>*>(c));
+    launch_ev(k_nu_deconv<double>, dim3((N + 255) / 256), dim3(256), 0u, s, nullptr, e1,
+              static_cast<const double*>(t.B), t.dinv, N, G, cl1, cl2, static_cast<Cx<double>*>(c));
   else
-    launch_ev(k_nudft_sum<float>, dim3((N + 255) / 256), dim3(256), 0u, s, nullptr, e1,
-              static_cast<const double*>(part), nudft_chunks(ns), N, static_cast<Cx<float>*>(c));
+    launch_ev(k_nu_deconv<float>, dim3((N + 255) / 256), dim3(256), 0u, s, nullptr, e1,
+              static_cast<const double*>(t.B), t.dinv, N, G, cl1, cl2, static_cast<Cx<float>*>(c));
   return hipGetLastError();
 }
 
@@ -205,6 +186,74 @@ hipError_t launch_nu_update(double* g, const double* wt, const double* z, int ns
                             hipEvent_t e0, hipEvent_t e1) {
   launch_ev(k_nu_update, dim3(nu_update_blocks(ns)), dim3(kNuUpdThreads), 0u, s, e0, e1, g, wt, z, ns, U);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- plan tables (host)
+// 1/Phi(l'/G), l' = l - N/2, l < N: Phi(xi) = 2 int_0^{W/2} phi(x) cos(2 pi xi x) dx
+// by Gauss-Legendre quadrature (nodes by Newton's method on P_q) in long double.
+void nu_deconv_table(int N, int G, double* dinv) {
+  constexpr int q = 100;
+  long double xs[q], ws[q];
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < q; ++i) {
+    long double z = cosl(pi * ((long double)i + 0.75L) / ((long double)q + 0.5L));
+    long double pp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = z;
+      for (int j = 2; j <= q; ++j) {
+        const long double p2 = ((2.0L * j - 1.0L) * z * p1 - (j - 1.0L) * p0) / (long double)j;
+        p0 = p1;
+        p1 = p2;
+      }
+      pp = (long double)q * (z * p1 - p0) / (z * z - 1.0L);
+      const long double dz = p1 / pp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    // node on [0, W/2]
+    xs[i] = (z + 1.0L) * (long double)kEsWidth / 4.0L;
+    ws[i] = 2.0L / ((1.0L - z * z) * pp * pp) * (long double)kEsWidth / 4.0L;
+  }
+  long double phi[q];
+  for (int i = 0; i < q; ++i) {
+    const long double zz = 2.0L * xs[i] / (long double)kEsWidth;
+    phi[i] = expl((long double)kEsBeta * (sqrtl(1.0L - zz * zz) - 1.0L)) * ws[i];
+  }
+  for (int l = 0; l < N; ++l) {
+    const long double xi = (long double)(l - N / 2) / (long double)G;
+    long double acc = 0.0L;
+    for (int i = 0; i < q; ++i) acc += phi[i] * cosl(2.0L * pi * xi * xs[i]);
+    dinv[l] = (double)(1.0L / (2.0L * acc));
+  }
+}
+
+// Per cell k of the G-cell grid: the samples with |G t_n - k| < W/2 (mod G),
+// as up to two index ranges {lo1, hi1, lo2, hi2} (positions increasing).
+void nu_cell_ranges(const double* turns, int ns, int G, int32_t* rng) {
+  std::vector<double> p(ns);
+  for (int n = 0; n < ns; ++n) p[n] = turns[n] * double(G);  // exact
+  const double h = kEsWidth / 2.0;
+  auto above = [&](double a) { return int32_t(std::upper_bound(p.begin(), p.end(), a) - p.begin()); };
+  auto below = [&](double b) { return int32_t(std::lower_bound(p.begin(), p.end(), b) - p.begin()); };
+  for (int k = 0; k < G; ++k) {
+    const double a = double(k) - h, b = double(k) + h;
+    int32_t* r = rng + 4 * size_t(k);
+    r[2] = r[3] = 0;
+    if (a < 0.0) {
+      r[0] = 0;
+      r[1] = below(b);
+      r[2] = above(a + double(G));
+      r[3] = ns;
+    } else if (b > double(G)) {
+      r[0] = above(a);
+      r[1] = ns;
+      r[2] = 0;
+      r[3] = below(b - double(G));
+    } else {
+      r[0] = above(a);
+      r[1] = below(b);
+    }
+  }
 }
 
 }  // namespace afd
