@@ -34,6 +34,7 @@ extern "C" {
 
 typedef struct afd_plan_s* afd_plan; /* opaque; owns its device workspace and tables */
 typedef struct afd_graph_s* afd_graph; /* opaque; one decomposition captured as a HIP graph */
+typedef struct afd_group_s* afd_group; /* opaque; decompositions of several plans in one graph */
 
 typedef enum {
   AFD_OK = 0,
@@ -179,6 +180,53 @@ afd_status afd_graph_launch(afd_graph graph);
 afd_status afd_graph_status(afd_graph graph);
 /* NULL-safe.  Destroy graphs before their plan. */
 void afd_graph_destroy(afd_graph graph);
+
+/* Batches of uneven N: one decomposition of each of `count` >= 1 distinct
+   plans of one device, each with its own N (2^K, 3^K or non-uniform), radii,
+   precision and batch, captured together into one HIP graph with one branch
+   per plan; the branches run concurrently on the device, and
+   afd_group_launch submits all of them with one graph launch on the stream
+   of plans[0].  signals[i], steps[i] and outs[i] are plans[i]'s, with the
+   requirements of afd_graph_create (device memory, baked in, `outs` copied).
+   Each plan's step tail takes its three-launch form (as with
+   afd_plan_desc.concurrent), so that no branch depends on having the device
+   to itself; results equal each plan's afd_decompose bit for bit.  The plans
+   must not run other calls while a launch of the group is in flight.
+   Errors: AFD_E_INVALID (NULL, count < 1, a plan twice, plans of different
+   devices, and afd_graph_create's), AFD_E_NOMEM, AFD_E_HIP. */
+afd_status afd_group_create(const afd_plan* plans, int32_t count, const double* const* signals,
+                            const int32_t* steps, const afd_result* outs, afd_group* group);
+afd_status afd_group_launch(afd_group group);
+/* Waits for the last launch; the first member (in plans order) whose signal
+   held NaN or Inf gives AFD_E_NONFINITE (that member's outputs are
+   meaningless, the others' are valid), else AFD_OK. */
+afd_status afd_group_status(afd_group group);
+/* NULL-safe.  Destroy groups before their plans. */
+void afd_group_destroy(afd_group group);
+
+/* Launch choices of a plan that leave its results unchanged bit for bit:
+   the step tail in one launch with grid barriers or in three launches
+   (2^10 <= N <= 2^14, one signal), the double-precision radius kernel's work
+   queue on or off, and the radii per two-pass chunk (N > 2^14: the
+   allocated chunk, or a half or a quarter of it).                          */
+typedef struct {
+  int32_t split_tail;    /* 1: the three-launch step tail                        */
+  int32_t no_queue;      /* 1: no work queue in the radius kernel                */
+  int32_t chunk;         /* radii per two-pass chunk (0 for N <= 2^14)           */
+  int32_t candidates;    /* combinations that apply to the plan (timed if > 1)   */
+  double ms;             /* chosen combination: ms per decomposition (0: untimed) */
+  double ms_default;     /* the default combination's ms (0: untimed)            */
+} afd_tuning;
+
+/* Autotuner: decomposes `steps` steps of `signal` (as afd_decompose takes it)
+   with every combination of the choices above that applies to the plan (one
+   warm-up and the faster of two timed runs each), keeps the fastest in the
+   plan and in a per-process table from which plans created later with the
+   same device, N, samples, M, precision and batch start.  steps = 0 times
+   nothing and reports the plan's current choices.  *out (nullable) receives
+   the choices.  Errors: those of afd_decompose; on error the plan keeps its
+   previous choices. */
+afd_status afd_plan_tune(afd_plan plan, const double* signal, int32_t steps, afd_tuning* out);
 
 /* For callers that cannot allocate device memory (code under stream capture,
    tight serving loops, harnesses that forbid allocation): afd_decompose

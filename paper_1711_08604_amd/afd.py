@@ -46,6 +46,17 @@ class PlanDesc(ctypes.Structure):
     ]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("split_tail", ctypes.c_int32),
+        ("no_queue", ctypes.c_int32),
+        ("chunk", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("ms", ctypes.c_double),
+        ("ms_default", ctypes.c_double),
+    ]
+
+
 class ResultDesc(ctypes.Structure):
     _fields_ = [
         ("index", ctypes.c_void_p),
@@ -69,6 +80,7 @@ EXPORTS = [
     "afd_status_string", "afd_last_error", "afd_plan_set_timing", "afd_plan_kernel_time",
     "afd_plan_radius_launch", "afd_reconstruct", "afd_analytic",
     "afd_graph_create", "afd_graph_launch", "afd_graph_status", "afd_graph_destroy",
+    "afd_group_create", "afd_group_launch", "afd_group_status", "afd_group_destroy", "afd_plan_tune",
 ]
 
 _lib = None
@@ -118,6 +130,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.afd_graph_status.restype = ctypes.c_int
     lib.afd_graph_destroy.argtypes = [vp]
     lib.afd_graph_destroy.restype = None
+    lib.afd_group_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                     ctypes.POINTER(ResultDesc), ctypes.POINTER(vp)]
+    lib.afd_group_create.restype = ctypes.c_int
+    lib.afd_group_launch.argtypes = [vp]
+    lib.afd_group_launch.restype = ctypes.c_int
+    lib.afd_group_status.argtypes = [vp]
+    lib.afd_group_status.restype = ctypes.c_int
+    lib.afd_group_destroy.argtypes = [vp]
+    lib.afd_group_destroy.restype = None
+    lib.afd_plan_tune.argtypes = [vp, vp, i32, ctypes.POINTER(Tuning)]
+    lib.afd_plan_tune.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -308,6 +331,15 @@ class Plan:
                                     ctypes.byref(rd)))
         return out
 
+    def tune(self, signal=None, steps: int = 0) -> dict:
+        """afd_plan_tune: time the plan's result-invariant launch choices on
+        `steps` steps of `signal` and keep the fastest (steps = 0: report the
+        current choices)."""
+        sp, keep = self._signal_ptr(signal) if signal is not None else (None, None)
+        t = Tuning()
+        _check(self._lib.afd_plan_tune(self._h, ctypes.c_void_p(sp), int(steps), ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
     def graph(self, signal, steps: int) -> "Graph":
         """A decomposition of `signal` (a torch tensor on the GPU) captured as a HIP
         graph (afd_graph_create); every launch() decomposes what the tensor then
@@ -414,6 +446,64 @@ class Graph:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.afd_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Group:
+    """Decompositions of several plans (uneven N) captured into one HIP graph
+    (afd_group_create): members = [(plan, signal on the device, steps), ...];
+    `results[i]` holds member i's device outputs after launch() + status()."""
+
+    def __init__(self, members):
+        if not members:
+            raise ValueError("a group needs at least one member")
+        self._lib = members[0][0]._lib
+        self._plans = [m[0] for m in members]
+        self._keep = []
+        self.results = []
+        count = len(members)
+        hs = (ctypes.c_void_p * count)()
+        sig = (ctypes.c_void_p * count)()
+        st = (ctypes.c_int32 * count)()
+        rds = (ResultDesc * count)()
+        for i, (plan, signal, steps) in enumerate(members):
+            if not _is_torch_cuda(signal):
+                raise ValueError("a group member's signal must be on the device")
+            sp, keep = plan._signal_ptr(signal)
+            res, rd = plan._outputs(signal, int(steps))
+            self._keep.append(keep)
+            self.results.append(res)
+            hs[i] = plan._h.value
+            sig[i] = sp
+            st[i] = int(steps)
+            rds[i] = rd
+        h = ctypes.c_void_p()
+        _check(self._lib.afd_group_create(hs, count, sig, st, rds, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        """One graph launch runs every member's decomposition (asynchronous)."""
+        _check(self._lib.afd_group_launch(self._h))
+
+    def status(self):
+        """Wait; raise AfdError for the first member whose signal was not finite."""
+        _check(self._lib.afd_group_status(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.afd_group_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -6,12 +6,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using namespace afd;
@@ -330,6 +333,12 @@ struct afd_plan_s {
   bool first_a_zero = false;
   bool concurrent = false;  // the stream runs beside other streams' kernels: no grid barriers
   int rslots = 0;  // radius workgroups resident at once (queued launches), 0: none
+  // launch choices that leave the results unchanged (afd_plan_tune): the
+  // three-launch step tail, no double-precision work queue, radii per
+  // two-pass chunk (at most cfg.chunk, whose intermediate is allocated)
+  bool split_tail = false;
+  bool no_queue = false;
+  int chunk = 0;
   int zero_m = -1;
   unsigned char* arena = nullptr;
   // per-call result staging on the device
@@ -352,6 +361,13 @@ struct afd_plan_s {
   P* at(size_t off) const {
     return reinterpret_cast<P*>(arena + off);
   }
+};
+
+// Decompositions of several plans captured into one graph (afd_group_create).
+struct afd_group_s {
+  std::vector<afd_plan_s*> plans;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 // A decomposition captured into a HIP graph (afd_graph_create).
@@ -776,7 +792,7 @@ afd_status run_adv(afd_plan_s* p, int steps, const int32_t* forced_user, const R
   a.R = rec;
   a.M = c.M;
   // one signal on a stream that has the device to itself: one launch with grid barriers
-  const bool fused = B == 1 && !p->concurrent;
+  const bool fused = B == 1 && !p->concurrent && !p->split_tail;
   auto advance = [&](hipEvent_t e0, hipEvent_t e1) -> hipError_t {
     const hipError_t e = launch_advance(c.logn, c.fp64, a, B, fused, s, e0, e1);
     if (fused) advance_bar_advance(c.logn, a);
@@ -967,7 +983,8 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.nrec = c.nblocks;
   // one signal with more radius workgroups than fit at once: a work queue
   // (double precision; see radius_queued)
-  const bool queued = c.fp64 && c.adv && B == 1 && c.rpb == 1 && p->rslots > 0 && p->rslots < c.nblocks;
+  const bool queued =
+      c.fp64 && c.adv && B == 1 && c.rpb == 1 && p->rslots > 0 && p->rslots < c.nblocks && !p->no_queue;
   rp.queue = queued ? p->at<unsigned int>(p->L.rqueue) : nullptr;
   rp.qbase = 0;
   rp.probe = nullptr;  // set per replayed step (double precision)
@@ -1060,7 +1077,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
         bool first = true;
         for (int m0 = 0; m0 < c.M;) {
           const bool shorts = m0 < c.nshort;
-          const int nr = shorts ? c.nshort : (c.M - m0 < c.chunk ? c.M - m0 : c.chunk);
+          const int nr = shorts ? c.nshort : (c.M - m0 < p->chunk ? c.M - m0 : p->chunk);
           bp.m0 = m0;
           hipEvent_t r0, r1;
           HIPCHK(tm.pair(kTimeRows, &r0, &r1), "event");
@@ -1258,6 +1275,29 @@ afd_status analytic(afd_plan_s* p, const double* x, double* g) {
   return AFD_OK;
 }
 
+// Launch choices found by afd_plan_tune, per device and plan shape; a plan
+// created later with the same shape starts from them.
+struct TuneKey {
+  int device;
+  int64_t n;
+  int ns, m, fp64, batch, tern, nu;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(device, n, ns, m, fp64, batch, tern, nu) <
+           std::tie(o.device, o.n, o.ns, o.m, o.fp64, o.batch, o.tern, o.nu);
+  }
+};
+struct TuneChoice {
+  bool split_tail, no_queue;
+  int chunk;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneChoice> g_tune;
+
+TuneKey tune_key(const afd_plan_s* p) {
+  const Config& c = p->cfg;
+  return TuneKey{p->device, c.N, c.ns, c.M, c.fp64 ? 1 : 0, c.batch, c.tern, c.nu ? 1 : 0};
+}
+
 }  // namespace
 
 extern "C" {
@@ -1297,7 +1337,18 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
     delete p;
     return hip_fail(e, "device setup");
   }
-  p->rslots = cfg.big ? 0 : radius_slots(cfg.logn, cfg.fp64, cfg.rpb);
+  p->rslots = cfg.big || cfg.tern ? 0 : radius_slots(cfg.logn, cfg.fp64, cfg.rpb);
+  p->chunk = cfg.chunk;
+  {
+    // a shape tuned earlier in this process starts from its choices
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(tune_key(p));
+    if (it != g_tune.end()) {
+      p->split_tail = it->second.split_tail;
+      p->no_queue = it->second.no_queue;
+      if (it->second.chunk > 0 && it->second.chunk <= cfg.chunk) p->chunk = it->second.chunk;
+    }
+  }
   e = hipMalloc(&p->arena, p->L.total);
   if (e != hipSuccess) {
     p->arena = nullptr;
@@ -1366,6 +1417,118 @@ afd_status afd_graph_create(afd_plan plan, const double* signal, int32_t steps, 
   }
   *graph = g;
   g_last_error.clear();
+  return AFD_OK;
+}
+
+void afd_group_destroy(afd_group group) {
+  if (!group) return;
+  if (group->exec) (void)hipGraphExecDestroy(group->exec);
+  if (group->graph) (void)hipGraphDestroy(group->graph);
+  delete group;
+}
+
+// The capture: a fork event on the group's stream, which every member's own
+// capture stream waits on (joining the capture), the member's decomposition
+// on its stream, and a join event per member that the group's stream waits
+// on before the capture ends.
+afd_status afd_group_create(const afd_plan* plans, int32_t count, const double* const* signals,
+                            const int32_t* steps, const afd_result* outs, afd_group* group) {
+  if (!group) return fail(AFD_E_INVALID, "group is NULL");
+  *group = nullptr;
+  if (!plans || !signals || !steps || !outs) return fail(AFD_E_INVALID, "NULL argument");
+  if (count < 1) return fail(AFD_E_INVALID, "count must be >= 1");
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return fail(AFD_E_INVALID, "a plan is NULL");
+    if (steps[i] < 0) return fail(AFD_E_INVALID, "steps must be >= 0");
+    if (plans[i]->device != plans[0]->device) return fail(AFD_E_INVALID, "plans of different devices");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(AFD_E_INVALID, "a plan appears twice");
+  }
+  HIPCHK(hipSetDevice(plans[0]->device), "hipSetDevice");
+  for (int i = 0; i < count; ++i) {
+    const afd_status st = ensure_res(plans[i], steps[i]);
+    if (st != AFD_OK) return st;
+  }
+  afd_group_s* g = new (std::nothrow) afd_group_s();
+  if (!g) return fail(AFD_E_NOMEM, "host allocation failed");
+  g->plans.assign(plans, plans + count);
+  std::vector<hipStream_t> cap(size_t(count) + 1, nullptr);
+  std::vector<hipEvent_t> ev(size_t(count) + 1, nullptr);
+  afd_status st = AFD_OK;
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < cap.size() && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&cap[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) st = hip_fail(e, "creating capture streams");
+  std::vector<hipStream_t> own(static_cast<size_t>(count));
+  std::vector<bool> conc(static_cast<size_t>(count));
+  for (int i = 0; i < count; ++i) {
+    own[i] = plans[i]->stream;
+    conc[i] = plans[i]->concurrent;
+  }
+  if (st == AFD_OK) {
+    e = hipStreamBeginCapture(cap[0], hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) st = hip_fail(e, "hipStreamBeginCapture");
+  }
+  if (st == AFD_OK) {
+    e = hipEventRecord(ev[0], cap[0]);
+    for (int i = 0; i < count && e == hipSuccess && st == AFD_OK; ++i) {
+      e = hipStreamWaitEvent(cap[i + 1], ev[0], 0);
+      if (e != hipSuccess) break;
+      plans[i]->stream = cap[i + 1];
+      plans[i]->concurrent = true;
+      afd_result o = outs[i];
+      st = run(plans[i], signals[i], steps[i], nullptr, &o, nullptr, true);
+      if (st == AFD_OK) e = hipEventRecord(ev[i + 1], cap[i + 1]);
+      if (st == AFD_OK && e == hipSuccess) e = hipStreamWaitEvent(cap[0], ev[i + 1], 0);
+    }
+    if (st == AFD_OK && e != hipSuccess) st = hip_fail(e, "forking the capture");
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cap[0], &gr);
+    g->graph = gr;
+    if (st == AFD_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamEndCapture");
+    if (st == AFD_OK) {
+      e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
+    }
+  }
+  for (int i = 0; i < count; ++i) {
+    plans[i]->stream = own[i];
+    plans[i]->concurrent = conc[i];
+  }
+  for (size_t i = 0; i < cap.size(); ++i) {
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (cap[i]) (void)hipStreamDestroy(cap[i]);
+  }
+  if (st != AFD_OK) {
+    afd_group_destroy(g);
+    return st;
+  }
+  *group = g;
+  g_last_error.clear();
+  return AFD_OK;
+}
+
+afd_status afd_group_launch(afd_group group) {
+  if (!group) return fail(AFD_E_INVALID, "group is NULL");
+  afd_plan_s* p0 = group->plans[0];
+  HIPCHK(hipSetDevice(p0->device), "hipSetDevice");
+  HIPCHK(hipGraphLaunch(group->exec, p0->stream), "hipGraphLaunch");
+  return AFD_OK;
+}
+
+afd_status afd_group_status(afd_group group) {
+  if (!group) return fail(AFD_E_INVALID, "group is NULL");
+  afd_plan_s* p0 = group->plans[0];
+  HIPCHK(hipSetDevice(p0->device), "hipSetDevice");
+  HIPCHK(hipStreamSynchronize(p0->stream), "hipStreamSynchronize");
+  for (afd_plan_s* p : group->plans) {
+    int bad = 0;
+    HIPCHK(hipMemcpy(&bad, p->arena + p->L.nonfinite, 4, hipMemcpyDeviceToHost), "reading flag");
+    if (bad & 2) return fail(AFD_E_HIP, "a grid barrier of the step tail timed out");
+    if (bad) return fail(AFD_E_NONFINITE, "a member's signal holds NaN or Inf");
+  }
   return AFD_OK;
 }
 
@@ -1478,6 +1641,92 @@ afd_status afd_plan_kernel_time(afd_plan plan, double* ms, int64_t* launches) {
   return AFD_OK;
 }
 
+afd_status afd_plan_tune(afd_plan plan, const double* signal, int32_t steps, afd_tuning* out) {
+  if (!plan) return fail(AFD_E_INVALID, "plan is NULL");
+  if (steps < 0) return fail(AFD_E_INVALID, "steps must be >= 0");
+  if (steps > 0 && !signal) return fail(AFD_E_INVALID, "signal is NULL");
+  const Config& c = plan->cfg;
+  // the candidates: every combination of the choices that apply to this plan
+  const bool tail_opt = c.adv && c.batch == 1;
+  const bool queue_opt =
+      c.fp64 && c.adv && c.batch == 1 && c.rpb == 1 && plan->rslots > 0 && plan->rslots < c.nblocks;
+  std::vector<int> chunks{c.chunk};
+  if (c.big && c.chunk > 1) {
+    for (int d : {2, 4})
+      if (std::max(1, c.chunk / d) != chunks.back()) chunks.push_back(std::max(1, c.chunk / d));
+  }
+  std::vector<TuneChoice> cands;
+  for (int split = 0; split <= (tail_opt ? 1 : 0); ++split)
+    for (int nq = 0; nq <= (queue_opt ? 1 : 0); ++nq)
+      for (int ch : chunks) cands.push_back(TuneChoice{split != 0, nq != 0, ch});
+  afd_tuning rep{};
+  TuneChoice best{plan->split_tail, plan->no_queue, plan->chunk};
+  if (steps > 0 && cands.size() > 1) {
+    const size_t S = size_t(steps) * size_t(c.batch);
+    std::vector<int32_t> idx(2 * S);
+    std::vector<double> a(2 * S), coef(2 * S), energy(S + size_t(c.batch));
+    afd_result r{};
+    r.index = idx.data();
+    r.a = a.data();
+    r.coef = coef.data();
+    r.energy = energy.data();
+    double best_ms = 0.0;
+    // every candidate must give the first one's results bit for bit
+    std::vector<int32_t> idx0;
+    std::vector<double> coef0, energy0;
+    for (size_t i = 0; i < cands.size(); ++i) {
+      plan->split_tail = cands[i].split_tail;
+      plan->no_queue = cands[i].no_queue;
+      plan->chunk = cands[i].chunk;
+      double ms = 0.0;
+      for (int rep_i = 0; rep_i < 3; ++rep_i) {  // one warm-up, then the faster of two
+        const auto t0 = std::chrono::steady_clock::now();
+        const afd_status st = run(plan, signal, steps, nullptr, &r);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (st != AFD_OK) {
+          plan->split_tail = best.split_tail;
+          plan->no_queue = best.no_queue;
+          plan->chunk = best.chunk;
+          return st;
+        }
+        const double t = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        if (rep_i == 1 || (rep_i == 2 && t < ms)) ms = t;
+      }
+      if (i == 0) {
+        rep.ms_default = ms;
+        idx0 = idx;
+        coef0 = coef;
+        energy0 = energy;
+      } else if (idx != idx0 || std::memcmp(coef.data(), coef0.data(), 8 * coef.size()) != 0 ||
+                 std::memcmp(energy.data(), energy0.data(), 8 * energy.size()) != 0) {
+        plan->split_tail = best.split_tail;
+        plan->no_queue = best.no_queue;
+        plan->chunk = best.chunk;
+        return fail(AFD_E_HIP, "a launch choice changed the results");
+      }
+      if (i == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = cands[i];
+      }
+    }
+    rep.ms = best_ms;
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_tune[tune_key(plan)] = best;
+    }
+  }
+  plan->split_tail = best.split_tail;
+  plan->no_queue = best.no_queue;
+  plan->chunk = best.chunk;
+  rep.split_tail = best.split_tail ? 1 : 0;
+  rep.no_queue = best.no_queue ? 1 : 0;
+  rep.chunk = c.big ? best.chunk : 0;
+  rep.candidates = int32_t(cands.size());
+  if (out) *out = rep;
+  g_last_error.clear();
+  return AFD_OK;
+}
+
 afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threads, int32_t* lds_bytes) {
   if (!plan || !blocks || !threads || !lds_bytes) return fail(AFD_E_INVALID, "NULL argument");
   const Config& c = plan->cfg;
@@ -1491,8 +1740,8 @@ afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threa
     *threads = tg.threads;
     *lds_bytes = tern_lds_bytes(c.tern, c.fp64);
   } else {
-    const bool queued =
-        c.fp64 && c.adv && c.batch == 1 && c.rpb == 1 && plan->rslots > 0 && plan->rslots < c.nblocks;
+    const bool queued = c.fp64 && c.adv && c.batch == 1 && c.rpb == 1 && plan->rslots > 0 &&
+                        plan->rslots < c.nblocks && !plan->no_queue;
     *blocks = queued ? plan->rslots : c.nblocks;
     *threads = radius_threads_of(c.logn, c.fp64);
     *lds_bytes = radius_lds_bytes(c.logn, c.fp64, c.rpb);

@@ -183,15 +183,15 @@ def test_nonuniform_rejects(kw, status):
 
 
 def test_nonuniform_workspace():
-    """A non-uniform plan sizes its samples and its non-uniform DFT partials;
-    samples without positions are rejected."""
+    """A non-uniform plan sizes its per-sample buffers; samples without
+    positions are rejected."""
     afd, lib = _lib()
     d1, k1 = _nu_desc(afd, n=1024, radii=np.linspace(0, 0.95, 20), turns=np.arange(1000) / 1000)
     d2, k2 = _nu_desc(afd, n=1024, radii=np.linspace(0, 0.95, 20), turns=np.arange(4000) / 4000)
     b1, b2 = lib.afd_workspace_bytes(ctypes.byref(d1)), lib.afd_workspace_bytes(ctypes.byref(d2))
     assert 0 < b1 < b2
-    # 3000 more samples: 40 B of tables each plus 12 more chunks of 1024 complex partials
-    assert b2 - b1 >= 3000 * 40 + 12 * 1024 * 16
+    # 3000 more samples: position, weight, point, shifted weight and the remainder sample
+    assert b2 - b1 >= 3000 * (8 + 8 + 16 + 16 + 16)
     d3, k3 = _desc(afd, n=1024)
     d3.samples = 1000
     assert lib.afd_workspace_bytes(ctypes.byref(d3)) == 0
