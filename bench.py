@@ -25,6 +25,9 @@ grid of N = 16384 angles, M = 1000 radii uniform in [0, 0.996], 50 steps.
 (8..32 kernels, |b| <= 0.95), M = 512, 30 steps, decomposed together.
 `--workload small1k` times the small latency-bound case: N = 1024, M = 100
 radii m/100, 10 steps, FP64 only, 200 solves for p50/p99.
+`--workload mixed` times a batch of uneven N (32 signals, N log-uniform over
+2^10..2^14, M = N/8, 20 steps, FP64) one plan after another and as one group
+graph (afd_group_launch).
 `--workload serve` runs the served stream: 2000 requests with N log-uniform
 over 2^10..2^16, M = N/8, 5..100 steps, signals as in the N = 16384
 workload, one after another on one stream (the plain per-signal method), then
@@ -317,6 +320,57 @@ def cpu_baseline(g, radii, steps_sample, total_steps):
                       f"{cores} threads", "one_worker": one}
 
 
+def run_mixed(args, np, torch, W):
+    """A batch of uneven N: 32 signals, N log-uniform over 2^10..2^14 (seeded),
+    M = N/8 radii uniform in [0, 0.999], 20 AFD steps each, FP64, signals as
+    in the N = 16384 workload.  Timed one plan after another on one stream
+    (afd_decompose per signal), then as one group graph (afd_group_launch:
+    a branch per plan, all concurrent)."""
+    from paper_1711_08604_amd import Group, Plan
+    rng = W.rng_for(7, 0)
+    ks = rng.integers(10, 15, size=32)
+    steps = 20
+    stream = torch.cuda.current_stream().cuda_stream
+    members, sigs = [], []
+    for i, k in enumerate(ks):
+        n = 1 << int(k)
+        g, radii, _ = W.shaped_like_config2(n, n // 8, steps, item=700 + i)
+        plan = Plan(n, radii, precision="fp64", stream=stream)
+        sig = torch.from_numpy(g).to("cuda:0")
+        members.append((plan, sig, steps))
+        sigs.append(sig)
+    evals = float(sum(p.m * p.n for p, _, _ in members)) * steps
+    reps = max(args.steps or 5, 3)
+    for p, s_, st in members:
+        p.decompose(s_, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for p, s_, st in members:
+            p.decompose(s_, st)
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t0) / reps
+    with Group(members) as grp:
+        grp.launch()
+        grp.status()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            grp.launch()
+        grp.status()
+        grouped = (time.perf_counter() - t0) / reps
+    for p, _, _ in members:
+        p.close()
+    log(f"bench: mixed one after another {seq * 1e3:.2f} ms, group {grouped * 1e3:.2f} ms per batch")
+    return {"metric": "grid evals/s of a batch of uneven N", "value": evals / grouped, "unit": "grid evals/s",
+            "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": grouped * 1e3, "higher_is_better": True,
+            "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "batch of 32 signals, N log-uniform over 2^10..2^14 (" +
+                       ",".join(str(1 << int(k)) for k in ks) + "), M = N/8 radii uniform in [0,0.999], "
+                       "20 AFD steps each, FP64; 40 normalised Szego kernels + CN noise at 30 dB"},
+            "one_after_another": {"value": evals / seq, "ms_per_batch": seq * 1e3},
+            "group_graph": {"value": evals / grouped, "ms_per_batch": grouped * 1e3}}
+
+
 def run_serve(args, np, torch, W):
     """The served stream through paper_1711_08604_amd.serve.Server (FP32+recheck):
     the plain per-signal method (the requests one after another on one
@@ -466,7 +520,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "tern6561", "nonuni16k",
-                                           "serve"],
+                                           "mixed", "serve"],
                     default="chirp1m")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
     ap.add_argument("--steps", type=int, default=None, help="timed decompositions (chirp1m: 5)")
@@ -495,6 +549,9 @@ def main():
 
     if args.workload == "serve":
         print(json.dumps(run_serve(args, np, torch, W)), flush=True)
+        return
+    if args.workload == "mixed":
+        print(json.dumps(run_mixed(args, np, torch, W)), flush=True)
         return
 
     wl_text, dsteps, dwarm = WORKLOADS[args.workload]
