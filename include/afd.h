@@ -61,7 +61,8 @@ typedef struct {
   int64_t n;              /* N = 2^K samples, 2 <= N <= 2^20, or N = 3^K, 3 <= N <= 3^8 = 6561
                              (radix-3 transforms; the paper's closing remark extends the fast
                              algorithm to N = p^K)                                              */
-  int32_t m;              /* M >= 1 radii; M * N must be < 2^31                                */
+  int32_t m;              /* M >= 1 radii; M * N must be < 2^32 - 1 (flat grid indices m N + j
+                             are unsigned 32-bit)                                              */
   const double* radii;    /* host pointer, length M, each in [0, 1); any order; copied at
                              create.  Grid index m refers to position m of this array.        */
   afd_precision precision;
@@ -139,7 +140,7 @@ typedef struct {
    later call of this plan runs.  On success *out receives the plan.
    Errors: AFD_E_INVALID (null pointer, N neither a power of two >= 2 nor a
    power of three >= 3, M < 1,
-   M*N >= 2^31, a radius outside [0,1) or non-finite, recheck_k or
+   M*N >= 2^32 - 1, a radius outside [0,1) or non-finite, recheck_k or
    recheck_band out of range, first_a_zero without a zero radius, batch < 0
    or batch * N * M too large), AFD_E_UNSUPPORTED (N > 2^20, N = 3^K with
    K > 8, or batch > 1 with N > 2^14), AFD_E_NOMEM, AFD_E_HIP.  On error *out is

@@ -140,7 +140,8 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
   if (logn < 1 && tern < 1) return fail(AFD_E_INVALID, "N must be a power of two >= 2 or a power of three >= 3");
   if (d->m < 1) return fail(AFD_E_INVALID, "M must be >= 1");
   if (!d->radii) return fail(AFD_E_INVALID, "radii is NULL");
-  if (int64_t(d->m) * d->n >= (int64_t(1) << 31)) return fail(AFD_E_INVALID, "M*N must be < 2^31");
+  // flat grid indices f = m N + j are unsigned 32-bit, 2^32 - 1 marking "no point"
+  if (int64_t(d->m) * d->n >= (int64_t(1) << 32) - 1) return fail(AFD_E_INVALID, "M*N must be < 2^32 - 1");
   if (d->precision != AFD_FP64 && d->precision != AFD_FP32_RECHECK) return fail(AFD_E_INVALID, "bad precision");
   if (d->recheck_k < 0 || d->recheck_k > kListC) return fail(AFD_E_INVALID, "recheck_k must be in 0..64");
   if (!(d->recheck_band >= 0.0) || d->recheck_band > 1e-4)

@@ -54,7 +54,7 @@ def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=
     (dict(n=1 << 21), 5), (dict(radii=()), 1), (dict(radii=(0.2, 1.0)), 1), (dict(radii=(-0.1,)), 1),
     (dict(radii=(np.nan,)), 1), (dict(radii=(np.inf,)), 1), (dict(precision=7), 1),
     (dict(recheck_k=-1), 1), (dict(recheck_k=65), 1), (dict(band=-1e-3), 1), (dict(band=0.5), 1),
-    (dict(first_a_zero=1, radii=(0.1, 0.2)), 1), (dict(n=1 << 16, radii=np.zeros(1 << 15)), 1),
+    (dict(first_a_zero=1, radii=(0.1, 0.2)), 1), (dict(n=1 << 16, radii=np.zeros(1 << 16)), 1),
     (dict(batch=-1), 1), (dict(n=1 << 15, batch=2), 5), (dict(n=1 << 14, batch=1 << 17), 1),
     (dict(n=3 ** 9), 5), (dict(n=6), 1), (dict(n=18), 1), (dict(n=3 ** 8 * 2), 1),
 ])
@@ -195,3 +195,14 @@ def test_nonuniform_workspace():
     d3, k3 = _desc(afd, n=1024)
     d3.samples = 1000
     assert lib.afd_workspace_bytes(ctypes.byref(d3)) == 0
+
+
+def test_flat_index_beyond_2p31():
+    """M*N between 2^31 and 2^32 - 2 is accepted (unsigned flat indices)."""
+    afd, lib = _lib()
+    d, keep = _desc(afd, n=1 << 20, radii=np.linspace(0.0, 0.95, 2101))
+    assert lib.afd_workspace_bytes(ctypes.byref(d)) > 0
+    d, keep = _desc(afd, n=1 << 20, radii=np.linspace(0.0, 0.95, 4095))
+    assert lib.afd_workspace_bytes(ctypes.byref(d)) > 0
+    d, keep = _desc(afd, n=1 << 20, radii=np.linspace(0.0, 0.95, 4096))
+    assert lib.afd_workspace_bytes(ctypes.byref(d)) == 0

@@ -168,3 +168,26 @@ def test_chirp_2p20_precisions_agree():
         assert tuple(a["index"][k]) == tuple(b["index"][k]), (k, a["index"][k], b["index"][k], a["margin"][k])
         den = max(abs(a["coef"][k]), np.sqrt(a["energy"][k]))
         assert abs(a["coef"][k] - b["coef"][k]) <= TOL["fp32"] * den
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_flat_index_beyond_2p31(prec):
+    """N = 2^20 and M = 2101 radii (M N = 2.2e9 > 2^31): a normalised kernel
+    w e_b with b on the grid at radius index 2100 (flat index 2100 N + j) is
+    found exactly, with the coefficient w (1 + rho)/(1 - rho) (rho = |b|^N = 0)
+    and a remainder of zero energy; replayed at that point, the selection
+    picks it too."""
+    n = 1 << 20
+    radii = np.concatenate([np.linspace(0.0, 0.9, 2100), [0.95]])
+    j = 777_777
+    b = 0.95 * np.exp(2j * np.pi * j / n)
+    w = 0.8 - 0.6j
+    g = w * O.szego(b, O.circle_points(n))
+    print(f"case flat index 2100*2^20+{j} {prec}", flush=True)
+    with Plan(n, radii, precision=prec) as plan:
+        r = to_numpy(plan.decompose(_dev(g), 1))
+        assert tuple(r["index"][0]) == (2100, j), r["index"][0]
+        assert abs(r["coef"][0] - w) < 1e-12 * abs(w)
+        assert r["energy"][1] < 1e-20 * r["energy"][0]
+        rep = to_numpy(plan.replay(_dev(g), 1, np.array([[2100, j]], dtype=np.int32)))
+        assert tuple(rep["pick_index"][0]) == (2100, j), rep["pick_index"][0]
