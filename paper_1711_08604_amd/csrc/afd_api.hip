@@ -262,7 +262,7 @@ Layout layout_of(const Config& c) {
   L.pw = take(real * size_t(c.M) * (c.big ? (size_t(1) << c.bg.l1) : size_t(c.geom.tpr)));
   L.pv = take(real * size_t(c.M) * (c.big ? (size_t(1) << c.bg.l2) : size_t(c.geom.E)));
   L.scale = take(real * size_t(c.M));
-  L.pq = take(c.big || c.tern ? 0 : real * size_t(c.M) * c.geom.E);
+  L.pq = take(c.big ? 0 : real * size_t(c.M) * c.geom.E);
   L.lsig = take(4 * size_t(c.M));
   L.order = take(c.big ? 0 : 8 * size_t(c.M));
   // per-signal buffers: `batch` copies back to back
@@ -429,8 +429,8 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
   std::vector<double> pq;
   std::vector<int32_t> lsig(M);
   for (int m = 0; m < M; ++m) lsig[m] = significant_length(radii[m], c.fp64 ? 60 : 40, N);
-  if (!c.big && !c.tern) {
-    const int r0 = radius_first_radix(c.logn, c.fp64);
+  if (!c.big) {
+    const int r0 = c.tern ? tern_first_radix(c.tern) : radius_first_radix(c.logn, c.fp64);
     const long double step = (long double)(tpr / (r0 > 0 ? r0 : 1));
     pq.resize(size_t(M) * E);
     for (int m = 0; m < M; ++m) {
@@ -467,7 +467,7 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
     if (e == hipSuccess) e = up(p->L.scale, sc.data(), sc.size() * 8);
     if (e == hipSuccess && c.big) e = up(p->L.wl, wl.data(), wl.size() * 8);
     if (e == hipSuccess && c.big) e = up(p->L.wh, wh.data(), wh.size() * 8);
-    if (e == hipSuccess && !c.big && !c.tern) e = up(p->L.pq, pq.data(), pq.size() * 8);
+    if (e == hipSuccess && !c.big) e = up(p->L.pq, pq.data(), pq.size() * 8);
   } else {
     auto f32 = [](const std::vector<double>& v) {
       std::vector<float> o(v.size());
@@ -485,7 +485,7 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
     if (e == hipSuccess) e = up(p->L.scale, sc32.data(), sc32.size() * 4);
     if (e == hipSuccess && c.big) e = up(p->L.wl, wl32.data(), wl32.size() * 4);
     if (e == hipSuccess && c.big) e = up(p->L.wh, wh32.data(), wh32.size() * 4);
-    if (e == hipSuccess && !c.big && !c.tern) e = up(p->L.pq, pq32.data(), pq32.size() * 4);
+    if (e == hipSuccess && !c.big) e = up(p->L.pq, pq32.data(), pq32.size() * 4);
   }
   if (e == hipSuccess) e = up(p->L.lsig, lsig.data(), lsig.size() * 4);
   if (e == hipSuccess && c.adv && !c.fp64) {

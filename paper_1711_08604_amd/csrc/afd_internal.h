@@ -330,6 +330,7 @@ struct TernGeom {
 TernGeom tern_geom(int k);
 void tern_twiddles(int k, double* tw);
 int tern_lds_bytes(int k, bool fp64);
+int tern_first_radix(int k);
 hipError_t launch_fwd3(int k, bool fp64, const void* g, const void* tw, void* c, int batch, hipStream_t s,
                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_radius3(int k, bool fp64, const RadiusParams& p, int batch, hipStream_t s, hipEvent_t e0 = nullptr,

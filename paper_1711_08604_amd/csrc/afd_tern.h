@@ -225,13 +225,14 @@ __device__ __forceinline__ void exchange3(Cx<T> (&v)[E], int t, bool act, void* 
 }
 
 // Full length-3^K transform on registers (every thread of the workgroup
-// calls it; threads t >= TPR only pass the barriers).
-template <typename T, int K, int E, int SIGN, bool SPLIT, int P = 0>
+// calls it; threads t >= TPR only pass the barriers).  FIRST > 0 starts at
+// pass FIRST with the registers already holding that pass's inputs.
+template <typename T, int K, int E, int SIGN, bool SPLIT, int P = 0, int FIRST = 0>
 __device__ __forceinline__ void fft3_regs(Cx<T> (&v)[E], int t, bool act, void* lds, const Cx<T>* tw) {
   using S = Shape3<K, E>;
-  if constexpr (P > 0) exchange3<T, K, E, P, SPLIT>(v, t, act, lds);
+  if constexpr (P > FIRST) exchange3<T, K, E, P, SPLIT>(v, t, act, lds);
   if (act) pass3_jobs<T, K, E, P, SIGN>(v, t, tw, std::make_integer_sequence<int, E / S::radix(P)>{});
-  if constexpr (P + 1 < S::NP) fft3_regs<T, K, E, SIGN, SPLIT, P + 1>(v, t, act, lds, tw);
+  if constexpr (P + 1 < S::NP) fft3_regs<T, K, E, SIGN, SPLIT, P + 1, FIRST>(v, t, act, lds, tw);
 }
 
 // Output order of the transforms for the selection: register p holds bin

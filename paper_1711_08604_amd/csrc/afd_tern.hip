@@ -76,19 +76,66 @@ __global__ __launch_bounds__(threads3(K)) void k_radius3(RadiusParams prm) {
   const Cx<T>* __restrict__ tw = reinterpret_cast<const Cx<T>*>(prm.tw);
   const T sc = reinterpret_cast<const T*>(prm.scale)[m];
 
+  // Short spectra skip passes (uniform over the workgroup: one radius).  A
+  // pass whose inputs x[job + r N/R] are zero for r > 0 only replicates
+  // x[job], so with at most N/ns(P) terms the inputs of pass P are
+  // x_P[i] = x[i / ns(P)]: register i of thread t holds x[a + D i] with
+  // a = t / ns(P), D = TPR / ns(P) (TPR is a multiple of ns(P)).  From pass 1:
+  // r^l = r^a (r^t table) times r^(D i) (the [M][E] table of r^((TPR/R0) i));
+  // from pass 2 (three passes): ns(2) = TPR, so register i holds x[i], with
+  // weight r^i from the r^t table (E <= TPR there).
+  constexpr int NP = S::NP;
+  int skip = 0;
+  if constexpr (NP >= 2) skip = L <= N / S::ns(1) ? 1 : 0;
+  if constexpr (NP >= 3) skip = L <= N / S::ns(2) ? 2 : skip;
   Cx<T> v[E];
-  const T rt = act ? pw[t] : T(0);
+  if (skip == 2) {
+    if constexpr (NP >= 3) {
+      static_assert(S::ns(2) == TPR && E <= TPR, "from pass 2 every thread holds x[0..E)");
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int l = t + TPR * i;
-    v[i] = {T(0), T(0)};
-    if (act && l < L) {
-      const Cx<T> x = c[l];
-      const T w = rt * pv[i];
-      v[i] = {x.x * w, x.y * w};
+      for (int i = 0; i < E; ++i) {
+        v[i] = {T(0), T(0)};
+        if (act && i < L) {
+          const Cx<T> x = c[i];
+          const T w = pw[i];
+          v[i] = {x.x * w, x.y * w};
+        }
+      }
+      fft3_regs<T, K, E, +1, tern_split<T, K>(), 2, 2>(v, t, act, smem, tw);
     }
+  } else if (skip == 1) {
+    if constexpr (NP >= 2) {
+      constexpr int R0 = S::ns(1), D = TPR / R0;
+      static_assert(TPR % R0 == 0, "TPR is a multiple of the first radix");
+      const T* __restrict__ pq = reinterpret_cast<const T*>(prm.pq) + size_t(m) * E;
+      const int a = t / R0;
+      const T ra = act ? pw[a] : T(0);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int l = a + D * i;
+        v[i] = {T(0), T(0)};
+        if (act && l < L) {
+          const Cx<T> x = c[l];
+          const T w = ra * pq[i];
+          v[i] = {x.x * w, x.y * w};
+        }
+      }
+      fft3_regs<T, K, E, +1, tern_split<T, K>(), 1, 1>(v, t, act, smem, tw);
+    }
+  } else {
+    const T rt = act ? pw[t] : T(0);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int l = t + TPR * i;
+      v[i] = {T(0), T(0)};
+      if (act && l < L) {
+        const Cx<T> x = c[l];
+        const T w = rt * pv[i];
+        v[i] = {x.x * w, x.y * w};
+      }
+    }
+    fft3_regs<T, K, E, +1, tern_split<T, K>()>(v, t, act, smem, tw);
   }
-  fft3_regs<T, K, E, +1, tern_split<T, K>()>(v, t, act, smem, tw);
 
   unsigned char* scratch = smem + tern_region<T, K>();
   const uint32_t fbase = uint32_t(m) * uint32_t(N);
@@ -229,6 +276,20 @@ hipError_t launch_radius3(int k, bool fp64, const RadiusParams& p, int batch, hi
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Radix of the first pass of the length-3^k transforms (ns(1)): the step of
+// the pruned start's r^((TPR/R0) i) table.
+int tern_first_radix(int k) {
+  switch (k) {
+#define X(K) \
+  case K:    \
+    return Shape3<K, pickE3(K)>::NP >= 2 ? Shape3<K, pickE3(K)>::ns(1) : 1;
+    AFD_TERN_CASES(X)
+#undef X
+    default:
+      return 1;
+  }
 }
 
 int tern_lds_bytes(int k, bool fp64) {
