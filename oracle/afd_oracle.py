@@ -71,6 +71,7 @@ __all__ = [
     "update_nu",
     "energy_nu",
     "decompose_nu",
+    "relative_errors_nu",
     "Decomposition",
 ]
 
@@ -486,3 +487,17 @@ def decompose_nu(G, turns, weights, radii, n: int, steps: int, first_a_zero: boo
         e_list.append(energy_nu(G, w))
         mg.append(margin)
     return Decomposition(idx, a_list, c_list, e_list, mg, G)
+
+
+def relative_errors_nu(G, turns, weights, coefs, a_list) -> np.ndarray:
+    """delta_n = ||G - S_n||^2 / ||G||^2 in the quadrature norm (Sec. 4, eq. er),
+    with S_n the partial sum of expansion (Sn) at the sample points."""
+    G = np.asarray(G, dtype=np.complex128)
+    z = sample_points(turns)
+    B = tm_basis(a_list, z)
+    S = np.zeros_like(G)
+    out = []
+    for k in range(len(a_list)):
+        S = S + coefs[k] * B[k]
+        out.append(energy_nu(G - S, weights) / energy_nu(G, weights))
+    return np.asarray(out, dtype=np.float64)

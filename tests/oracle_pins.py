@@ -476,6 +476,24 @@ def pin_nonuniform_series(O):
     assert abs(d.energy[0] - np.sum(w2 * np.abs(Gk) ** 2)) < 1e-14 * d.energy[0]
 
 
+def pin_nonuniform_relative_errors(O):
+    """At non-uniform points the Blaschke factor is still unimodular, so the
+    partial sums' errors equal the remainders' energies: delta_n = E_n / E_0
+    of decompose_nu; uniform positions give the uniform relative errors."""
+    g, t = W.nonuniform_kernel_signal(300, item=3, kind="cluster")
+    w = O.trapezoid_weights(t)
+    radii = W.uniform_radii(12, 0.8)
+    d = O.decompose_nu(g, t, w, radii, 256, 5)
+    dl = O.relative_errors_nu(g, t, w, d.coef, d.a)
+    assert np.max(np.abs(dl - d.energy[1:] / d.energy[0])) < 1e-12
+    gu, radii_u, _ = W.config1()
+    gu = gu[::8]
+    du = O.decompose(gu, radii_u[::5], 4)
+    n = gu.shape[0]
+    ref = O.relative_errors(gu, du.coef, du.a)
+    assert np.max(np.abs(O.relative_errors_nu(gu, np.arange(n) / n, np.full(n, 1.0 / n), du.coef, du.a) - ref)) < 1e-13
+
+
 # ------------------------------------------------------------------ relative error (Sec. 4, eq. er)
 def pin_relative_errors(O):
     """delta_n from the partial sums equals E_n/E_0 from the remainders at every
@@ -526,6 +544,7 @@ ALL_PINS = [
     pin_three_power_sizes,
     pin_nonuniform_rule,
     pin_nonuniform_series,
+    pin_nonuniform_relative_errors,
     pin_expansion,
     pin_invariances,
     pin_paper_tables,

@@ -178,6 +178,10 @@ def _energy_nu_unweighted(G, weights):
     return OA.energy(G)
 
 
+def _relative_errors_nu_uniform_norm(G, turns, weights, coefs, a_list):
+    return OA.relative_errors_nu(G, turns, np.full(len(G), 1.0 / len(G)), coefs, a_list)
+
+
 MUTANTS = {
     "forward-sign inverse DFT": dict(grid_fft=_grid_fft_forward_sign),
     "aliasing factor 1/(1-r^N) dropped": dict(grid_fft=_grid_fft_no_alias),
@@ -197,6 +201,7 @@ MUTANTS = {
     "non-uniform DFT with the inverse sign": dict(nudft=_nudft_plus_sign),
     "non-uniform update at the uniform points": dict(update_nu=_update_nu_uniform_points),
     "quadrature energy without weights": dict(energy_nu=_energy_nu_unweighted),
+    "non-uniform relative errors in the unweighted norm": dict(relative_errors_nu=_relative_errors_nu_uniform_norm),
 }
 
 
