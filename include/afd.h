@@ -94,8 +94,9 @@ typedef struct {
      c_l = sum_n w_n G(z_n) e^{-2 pi i l t_n}, l < N.  Needs N = 2^K <= 2^14, batch 1,
      1 <= samples <= 2^16 and radii whose kernel series r^l is negligible from l = N on (the
      significant length of the uniform path's radius tables, at most N); else
-     AFD_E_UNSUPPORTED.  The remainder then has `samples` values; afd_reconstruct and
-     afd_analytic return AFD_E_UNSUPPORTED.                                                  */
+     AFD_E_UNSUPPORTED.  The remainder then has `samples` values; afd_reconstruct gives the
+     partial sums at the sample points and the relative errors in the quadrature norm;
+     afd_analytic returns AFD_E_UNSUPPORTED.                                                 */
   const double* sample_turns;
   const double* sample_weights; /* NULL: trapezoidal weights; ignored without sample_turns    */
   int64_t samples;              /* number of non-uniform samples (0 with sample_turns NULL)   */

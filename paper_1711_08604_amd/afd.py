@@ -377,11 +377,11 @@ class Plan:
         on_dev = _is_torch_cuda(a)
         if on_dev:
             import torch
-            S = torch.empty(lead + (self.n,), dtype=torch.complex128, device=a.device) if partial_sum else None
+            S = torch.empty(lead + (self.samples,), dtype=torch.complex128, device=a.device) if partial_sum else None
             D = torch.empty(lead + (steps,), dtype=torch.float64, device=a.device) if signal is not None else None
             ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
         else:
-            S = np.empty(lead + (self.n,), dtype=np.complex128) if partial_sum else None
+            S = np.empty(lead + (self.samples,), dtype=np.complex128) if partial_sum else None
             D = np.empty(lead + (steps,), dtype=np.float64) if signal is not None else None
             ptr = lambda t: t.ctypes.data if t is not None else None  # noqa: E731
         _check(self._lib.afd_reconstruct(self._h, ctypes.c_void_p(ap), ctypes.c_void_p(cp), steps,

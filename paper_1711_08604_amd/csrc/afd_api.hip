@@ -1174,8 +1174,8 @@ afd_status reconstruct(afd_plan_s* p, const double* a, const double* coef, int s
   if (steps > 0 && (!a || !coef)) return fail(AFD_E_INVALID, "a and coef are required when steps > 0");
   if (delta && !signal) return fail(AFD_E_INVALID, "delta needs the signal");
   const Config& c = p->cfg;
-  if (c.nu) return fail(AFD_E_UNSUPPORTED, "afd_reconstruct needs uniform samples");
-  const int N = int(c.N), B = c.batch;
+  // (non-uniform samples: the partial sums at the sample points, the errors in the quadrature norm)
+  const int N = c.ns, B = c.batch;
   HIPCHK(hipSetDevice(p->device), "hipSetDevice");
   const size_t nk = 2 * size_t(steps) * B;
   std::vector<double> ah, ch, gh;
@@ -1214,7 +1214,8 @@ afd_status reconstruct(afd_plan_s* p, const double* a, const double* coef, int s
   }
   if (dg) HIPCHK(hipMemcpyAsync(dg, gh.data(), 8 * nsig, hipMemcpyHostToDevice, s), "uploading signal");
   if (ds || dw)
-    HIPCHK(launch_recon(da, dc, steps, N, p->at<double>(p->L.omega), dg, ds, dw, delta ? dd : nullptr, B, s),
+    HIPCHK(launch_recon(da, dc, steps, N, p->at<double>(c.nu ? p->L.nu_z : p->L.omega), dg, ds, dw,
+                        delta ? dd : nullptr, B, s, c.nu ? p->at<double>(p->L.nu_w) : nullptr),
            "k_recon");
   if (partial_sum) HIPCHK(hipMemcpyAsync(partial_sum, ds, 8 * nsig, hipMemcpyDefault, s), "copy partial sum");
   if (delta && steps > 0)

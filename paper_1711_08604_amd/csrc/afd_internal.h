@@ -408,10 +408,13 @@ hipError_t launch_nu_update(double* g, const double* wt, const double* z, int ns
 
 // Reconstruction and analytic front end (afd_recon.hip), double precision.
 int recon_waves(int N);  // wave partial sums per signal and step in `wpart`
-// S (nullable): partial sums [batch][N]; wpart/delta (nullable, together):
-// [batch][steps+1][recon_waves(N)] scratch and [batch][steps] relative errors.
+// N points omega (e^{2 pi i n/N}, or a non-uniform plan's sample points) with
+// quadrature weights wt (nullable: equal weights).  S (nullable): partial sums
+// [batch][N]; wpart/delta (nullable, together): [batch][steps+1][recon_waves(N)]
+// scratch and [batch][steps] relative errors.
 hipError_t launch_recon(const double* a, const double* c, int steps, int N, const double* omega, const double* G,
-                        double* S, double* wpart, double* delta, int batch, hipStream_t s);
+                        double* S, double* wpart, double* delta, int batch, hipStream_t s,
+                        const double* wt = nullptr);
 // cols_l2 > 0: the forward DFT's column-order output (bin k2 + 2^cols_l2 k1 at k2 2^cols_l1 + k1)
 hipError_t launch_analytic_mask(const double* X, double* Y, int N, int cols_l1, int cols_l2, int* flag, int batch,
                                 hipStream_t s);

@@ -14,14 +14,16 @@ namespace afd {
 
 constexpr int kRecThreads = 256;
 
-// One thread per sample z = e^{2 pi i n/N}.  With P_0 = 1 and
+// One thread per sample z = e^{2 pi i n/N} (or, for non-uniform samples, the
+// point omega[n] of N = samples points).  With P_0 = 1 and
 // d_k = 1 - conj(a_k) z: B_k = sqrt(1 - |a_k|^2) P_k / d_k, S += c_k B_k,
 // P_{k+1} = P_k (z - a_k)/d_k.  With wpart, the wave sums of |G - S_k|^2
-// (k = 0: |G|^2) go to wpart[b][k][wave] for a fixed-order total.
+// (k = 0: |G|^2), times the quadrature weight wt[n] when wt is given, go to
+// wpart[b][k][wave] for a fixed-order total.
 __global__ __launch_bounds__(kRecThreads) void k_recon(const double* __restrict__ ak, const double* __restrict__ ck,
                                                        int steps, int N, const double* __restrict__ omega,
                                                        const double* __restrict__ G, double* __restrict__ S,
-                                                       double* __restrict__ wpart) {
+                                                       double* __restrict__ wpart, const double* __restrict__ wt) {
   const int b = blockIdx.y;
   const int n = int(blockIdx.x) * kRecThreads + int(threadIdx.x);
   const bool valid = n < N;
@@ -37,8 +39,9 @@ __global__ __launch_bounds__(kRecThreads) void k_recon(const double* __restrict_
     gx = G[2 * (size_t(N) * b + n)];
     gy = G[2 * (size_t(N) * b + n) + 1];
   }
+  const double wn = (wt && valid) ? wt[n] : 1.0;
   if (wpart) {
-    const double e = wave_sum_f64(fma(gx, gx, gy * gy));
+    const double e = wave_sum_f64(wn * fma(gx, gx, gy * gy));
     if (lead) wpart[wv] = e;
   }
   double px = 1.0, py = 0.0, sx = 0.0, sy = 0.0;
@@ -58,7 +61,7 @@ __global__ __launch_bounds__(kRecThreads) void k_recon(const double* __restrict_
     px = tx;
     if (wpart) {
       const double ex = gx - sx, ey = gy - sy;
-      const double e = wave_sum_f64(valid ? fma(ex, ex, ey * ey) : 0.0);
+      const double e = wave_sum_f64(valid ? wn * fma(ex, ex, ey * ey) : 0.0);
       if (lead) wpart[size_t(k + 1) * nwt + wv] = e;
     }
   }
@@ -125,9 +128,9 @@ __global__ __launch_bounds__(kRecThreads) void k_analytic_out(const double* __re
 int recon_waves(int N) { return (N + kRecThreads - 1) / kRecThreads * (kRecThreads / 64); }
 
 hipError_t launch_recon(const double* a, const double* c, int steps, int N, const double* omega, const double* G,
-                        double* S, double* wpart, double* delta, int batch, hipStream_t s) {
+                        double* S, double* wpart, double* delta, int batch, hipStream_t s, const double* wt) {
   const int blocks = (N + kRecThreads - 1) / kRecThreads;
-  hipLaunchKernelGGL(k_recon, dim3(blocks, batch), dim3(kRecThreads), 0, s, a, c, steps, N, omega, G, S, wpart);
+  hipLaunchKernelGGL(k_recon, dim3(blocks, batch), dim3(kRecThreads), 0, s, a, c, steps, N, omega, G, S, wpart, wt);
   if (wpart && delta && steps > 0)
     hipLaunchKernelGGL(k_recon_sum, dim3(steps, batch), dim3(kRecThreads), 0, s, wpart, steps, recon_waves(N),
                        delta);

@@ -5,7 +5,7 @@ Jittered and clustered positions with trapezoidal weights (or given
 weights), every step free-running and replayed along the oracle's
 trajectory, the r = 0 ring tie, a_1 = 0, uniform positions against the
 uniform oracle, captured graphs against eager calls, and the errors of what
-a non-uniform plan does not support.  The largest radius of each grid is
+a non-uniform plan does not support; reconstruction at the sample points.  The largest radius of each grid is
 one whose kernel series is negligible from l = N on (the plan rejects
 others)."""
 import numpy as np
@@ -151,9 +151,24 @@ def test_unsupported():
     with Plan(256, [0.0, 0.5], sample_turns=t) as plan:
         with pytest.raises(AfdError):
             plan.analytic(np.ones(256))
-        with pytest.raises(AfdError):
-            plan.reconstruct(np.array([0.1 + 0j]), np.array([1.0 + 0j]))
         bad = np.ones(100, complex)
         bad[3] = np.nan
         with pytest.raises(AfdError):
             plan.decompose(bad, 2)
+
+
+def test_reconstruct_at_sample_points():
+    """Partial sums at the sample points and the relative errors in the
+    quadrature norm against the oracle; they equal E_n/E_0 of the GPU's own
+    decomposition."""
+    n, ns, steps = 1024, 1400, 8
+    g, t = W.nonuniform_kernel_signal(ns, item=11, kind="cluster")
+    w = O.trapezoid_weights(t)
+    radii = W.uniform_radii(40, 0.95)
+    with Plan(n, radii, sample_turns=t) as plan:
+        r = to_numpy(plan.decompose(_dev(g), steps))
+        S, delta = plan.reconstruct(r["a"], r["coef"], signal=g)
+    S_ref = O.partial_sum(r["coef"], r["a"], O.sample_points(t))
+    assert np.max(np.abs(S - S_ref)) < 1e-12 * np.max(np.abs(S_ref))
+    assert np.max(np.abs(delta - O.relative_errors_nu(g, t, w, r["coef"], r["a"]))) < 1e-12
+    assert np.max(np.abs(delta - r["energy"][1:] / r["energy"][0])) < 1e-11
