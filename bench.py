@@ -81,30 +81,51 @@ def percentile(xs, q):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def source_hash() -> str:
-    """sha256 over the sources of the device code (names and contents, sorted
-    by name): every .hip and .h file of csrc/ except afd_api.hip, which holds
-    the host side of the library only."""
-    h = hashlib.sha256()
+# The translation unit each measured kernel is compiled from; its counters
+# stay valid while that file and every header of csrc/ are unchanged.
+KERNEL_SOURCES = {
+    "k_big_": "afd_large.hip", "k_radius3": "afd_tern.hip", "k_fwd3": "afd_tern.hip",
+    "k_radius<": "afd_radius.hip", "k_advance": "afd_advance.hip", "k_fwd_": "afd_fwd.hip",
+    "k_fft_fwd": "afd_fwd.hip", "k_nu_": "afd_nonuni.hip", "k_recon": "afd_recon.hip",
+    "k_analytic": "afd_recon.hip",
+}
+STEP_KERNELS = ("k_update", "k_recheck", "k_prepare", "k_merge", "k_pick", "k_force", "k_zero")
+
+
+def kernel_source(kernel: str) -> str:
+    for prefix, f in KERNEL_SOURCES.items():
+        if kernel.startswith(prefix):
+            return f
+    if kernel.startswith(STEP_KERNELS):
+        return "afd_step.hip"
+    return ""
+
+
+def source_hashes() -> dict:
+    """sha256 of each device source of csrc/ (every .hip and .h file except
+    afd_api.hip, which holds the host side of the library only)."""
     csrc = os.path.join(ROOT, "paper_1711_08604_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
-                   if f.endswith((".hip", ".h")) and f != "afd_api.hip")
-    for f in files:
-        h.update(os.path.relpath(f, ROOT).encode() + b"\0")
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    out = {}
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")) and f != "afd_api.hip":
+            with open(os.path.join(csrc, f), "rb") as fh:
+                out[f] = hashlib.sha256(fh.read()).hexdigest()
+    return out
 
 
 def measured_counters(kernel: str):
     """The counter record of `kernel` (bytes and VALU instructions per launch)
-    if it was measured on the current sources, else None."""
+    if its translation unit and the headers are as they were measured, else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != source_hash():
+    then, now = t.get("sources", {}), source_hashes()
+    unit = kernel_source(kernel)
+    if not unit or then.get(unit) != now.get(unit):
+        return None
+    if any(then.get(f) != h for f, h in now.items() if f.endswith(".h")):
         return None
     return t.get("kernels", {}).get(kernel)
 
