@@ -226,6 +226,10 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
       // the twiddle table
       const TernGeom tg = tern_geom(cfg->tern);
       cfg->geom = FftGeom{tg.E, tg.tpr, tg.twsize, false, 0};
+      // the forward DFT's split (from 3^7 points): row and column tables, intermediate
+      cfg->fwd.two_pass = tern_fwd_twsize(cfg->tern, true) > 0;
+      cfg->fwd.tw1_size = tern_fwd_twsize(cfg->tern, true);
+      cfg->fwd.tw2_size = tern_fwd_twsize(cfg->tern, false);
       cfg->bg = BigGeom{};
       cfg->chunk = 0;
       cfg->nshort = 0;
@@ -400,9 +404,15 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
   else
     fft_twiddles(c.logn, c.fp64, tw.data());
   std::vector<double> twf1(2 * size_t(c.fwd.tw1_size + 1), 0.0), twf2(2 * size_t(c.fwd.tw2_size + 1), 0.0);
-  if (c.tern || c.nu) {
-    // (N = 3^K: the forward transform takes the inverse's table, conjugated;
-    // non-uniform samples: no forward FFT)
+  if (c.tern) {
+    // N = 3^K: the one-workgroup forward transform takes the inverse's table,
+    // conjugated; the split one the tables of its rows and columns
+    if (c.fwd.two_pass) {
+      tern_twiddles(c.tern / 2, twf1.data());
+      tern_twiddles(c.tern - c.tern / 2, twf2.data());
+    }
+  } else if (c.nu) {
+    // (non-uniform samples: no forward FFT)
   } else if (c.adv) {
     advance_twiddles(c.ag.l1, twf1.data());
     advance_twiddles(c.ag.l2, twf2.data());
@@ -1062,7 +1072,9 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       if (c.nu)
         HIPCHK(launch_nu_fourier(g64, nu_tables(p), c.logn, c.fp64, cspec, s, e0, e1), "non-uniform DFT");
       else if (c.tern)
-        HIPCHK(launch_fwd3(c.tern, c.fp64, gin, p->at<void>(p->L.tw), cspec, B, s, e0, e1), "forward DFT");
+        HIPCHK(launch_fwd3(c.tern, c.fp64, gin, p->at<void>(p->L.tw), p->at<void>(p->L.twf1), p->at<void>(p->L.twf2),
+                           omega, p->at<void>(p->L.xt), cspec, B, s, e0, e1),
+               "forward DFT");
       else
         HIPCHK(launch_fwd(c.logn, c.fp64, gin, p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega,
                           p->at<void>(p->L.xt), cspec, B, s, e0, e1, c.big ? p->at<void>(p->L.c0) : nullptr),

@@ -331,8 +331,13 @@ TernGeom tern_geom(int k);
 void tern_twiddles(int k, double* tw);
 int tern_lds_bytes(int k, bool fp64);
 int tern_first_radix(int k);
-hipError_t launch_fwd3(int k, bool fp64, const void* g, const void* tw, void* c, int batch, hipStream_t s,
-                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// From 3^7 points the forward DFT runs in two passes through xt (N complex,
+// the transform's precision) with the split's tables tw1 (rows) and tw2
+// (columns) and the unit roots omega; below, one workgroup with tw.
+int tern_fwd_twsize(int k, bool rows);
+hipError_t launch_fwd3(int k, bool fp64, const void* g, const void* tw, const void* tw1, const void* tw2,
+                       const double* omega, void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
 hipError_t launch_radius3(int k, bool fp64, const RadiusParams& p, int batch, hipStream_t s, hipEvent_t e0 = nullptr,
                           hipEvent_t e1 = nullptr);
 

@@ -55,6 +55,81 @@ __global__ __launch_bounds__(threads3(K)) void k_fwd3(const Cx<T>* __restrict__ 
   }
 }
 
+// From 3^7 points the forward DFT is split as N = N1 N2 (N1 = 3^(K/2)):
+// n = l1 + N1 l2, l = k2 + N2 k1.  The first pass transforms each column l1
+// over l2 and applies e^{-2 pi i l1 k2/N}, storing X[k2][l1]; the second
+// transforms each row k2 over l1 into c[k2 + N2 k1].  Both run several
+// short transforms per 64-thread workgroup on many CUs, where one
+// workgroup holding all N points would serialise the whole transform.
+constexpr int kFwd3SplitK = 7;
+template <int K>
+struct Split3 {
+  static constexpr int K1 = K / 2, K2 = K - K1;
+  static constexpr int N1 = ipow3(K1), N2 = ipow3(K2);
+};
+// transforms of 3^KK points per 64-thread workgroup
+template <int KK>
+__host__ __device__ constexpr int per_wave3() {
+  return 64 / Shape3<KK, pickE3(KK)>::TPR;
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(64) void k_fwd3_cols(const Cx<T>* __restrict__ g, const Cx<T>* __restrict__ tw2,
+                                                  const double* __restrict__ omega, Cx<T>* __restrict__ xt) {
+  using P = Split3<K>;
+  constexpr int E2 = pickE3(P::K2);
+  using S2 = Shape3<P::K2, E2>;
+  constexpr int CPB = per_wave3<P::K2>();
+  constexpr int N = ipow3(K);
+  extern __shared__ __align__(16) unsigned char smem[];
+  // adjacent threads take adjacent columns (contiguous loads)
+  const int ci = int(threadIdx.x) % CPB, t = int(threadIdx.x) / CPB;
+  const int l1 = int(blockIdx.x) * CPB + ci;
+  const bool act = t < S2::TPR && l1 < P::N1;
+  g += size_t(N) * blockIdx.y;
+  xt += size_t(N) * blockIdx.y;
+  unsigned char* region = smem + size_t(ci) * P::N2 * sizeof(Cx<T>);
+  Cx<T> v[E2];
+#pragma unroll
+  for (int i = 0; i < E2; ++i) v[i] = act ? g[l1 + P::N1 * (t + S2::TPR * i)] : Cx<T>{T(0), T(0)};
+  fft3_regs<T, P::K2, E2, -1, false>(v, t, act, region, tw2);
+  if (act) {
+#pragma unroll
+    for (int p = 0; p < E2; ++p) {
+      const int k2 = t + S2::TPR * digrev3(p, S2::LE);
+      const int e = l1 * k2;  // < N
+      const Cx<T> w{T(omega[2 * e]), T(-omega[2 * e + 1])};
+      xt[size_t(k2) * P::N1 + l1] = cmul(v[p], w);
+    }
+  }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(64) void k_fwd3_rows(const Cx<T>* __restrict__ xt, const Cx<T>* __restrict__ tw1,
+                                                  Cx<T>* __restrict__ c) {
+  using P = Split3<K>;
+  constexpr int E1 = pickE3(P::K1);
+  using S1 = Shape3<P::K1, E1>;
+  constexpr int RPB = per_wave3<P::K1>();
+  constexpr int N = ipow3(K);
+  extern __shared__ __align__(16) unsigned char smem[];
+  // the threads of a row are adjacent (contiguous loads)
+  const int ri = int(threadIdx.x) / S1::TPR, t = int(threadIdx.x) % S1::TPR;
+  const int k2 = int(blockIdx.x) * RPB + ri;
+  const bool act = ri < RPB && k2 < P::N2;
+  xt += size_t(N) * blockIdx.y;
+  c += size_t(N) * blockIdx.y;
+  unsigned char* region = smem + size_t(ri < RPB ? ri : RPB - 1) * P::N1 * sizeof(Cx<T>);
+  Cx<T> v[E1];
+#pragma unroll
+  for (int i = 0; i < E1; ++i) v[i] = act ? xt[size_t(k2) * P::N1 + t + S1::TPR * i] : Cx<T>{T(0), T(0)};
+  fft3_regs<T, P::K1, E1, -1, false>(v, t, act, region, tw1);
+  if (act) {
+#pragma unroll
+    for (int p = 0; p < E1; ++p) c[k2 + P::N2 * (t + S1::TPR * digrev3(p, S1::LE))] = v[p];
+  }
+}
+
 template <typename T, int K, bool LIST>
 __global__ __launch_bounds__(threads3(K)) void k_radius3(RadiusParams prm) {
   constexpr int E = pickE3(K);
@@ -235,8 +310,45 @@ hipError_t setup_tern_attributes() {
   return e;
 }
 
-hipError_t launch_fwd3(int k, bool fp64, const void* g, const void* tw, void* c, int batch, hipStream_t s,
-                       hipEvent_t e0, hipEvent_t e1) {
+// Forward DFT tables: the split's row (3^(K/2)) and column (3^(K - K/2))
+// twiddle entries, 0 below the split.
+int tern_fwd_twsize(int k, bool rows) {
+  if (k < kFwd3SplitK) return 0;
+  return tern_geom(rows ? k / 2 : k - k / 2).twsize;
+}
+
+hipError_t launch_fwd3(int k, bool fp64, const void* g, const void* tw, const void* tw1, const void* tw2,
+                       const double* omega, void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (k >= kFwd3SplitK) {
+    switch (k) {
+#define X(K)                                                                                                      \
+  case K: {                                                                                                       \
+    using P = Split3<K>;                                                                                          \
+    const dim3 gc((P::N1 + per_wave3<P::K2>() - 1) / per_wave3<P::K2>(), batch);                                  \
+    const dim3 gr((P::N2 + per_wave3<P::K1>() - 1) / per_wave3<P::K1>(), batch);                                  \
+    if (fp64) {                                                                                                   \
+      launch_ev(k_fwd3_cols<double, K>, gc, dim3(64), uint32_t(per_wave3<P::K2>() * P::N2 * 16), s, e0, nullptr,  \
+                static_cast<const Cx<double>*>(g), static_cast<const Cx<double>*>(tw2), omega,                   \
+                static_cast<Cx<double>*>(xt));                                                                   \
+      launch_ev(k_fwd3_rows<double, K>, gr, dim3(64), uint32_t(per_wave3<P::K1>() * P::N1 * 16), s, nullptr, e1,  \
+                static_cast<const Cx<double>*>(xt), static_cast<const Cx<double>*>(tw1),                         \
+                static_cast<Cx<double>*>(c));                                                                    \
+    } else {                                                                                                      \
+      launch_ev(k_fwd3_cols<float, K>, gc, dim3(64), uint32_t(per_wave3<P::K2>() * P::N2 * 8), s, e0, nullptr,    \
+                static_cast<const Cx<float>*>(g), static_cast<const Cx<float>*>(tw2), omega,                     \
+                static_cast<Cx<float>*>(xt));                                                                    \
+      launch_ev(k_fwd3_rows<float, K>, gr, dim3(64), uint32_t(per_wave3<P::K1>() * P::N1 * 8), s, nullptr, e1,    \
+                static_cast<const Cx<float>*>(xt), static_cast<const Cx<float>*>(tw1), static_cast<Cx<float>*>(c)); \
+    }                                                                                                             \
+    break;                                                                                                        \
+  }
+      X(7) X(8)
+#undef X
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (k) {
 #define X(K)                                                                                                     \
   case K:                                                                                                        \
