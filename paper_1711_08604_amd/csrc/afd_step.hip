@@ -81,7 +81,9 @@ __global__ void k_force(const int32_t* __restrict__ forced, int fstride, int ste
 // every candidate meet in LDS and are added in wave order after the loop.
 // Non-uniform samples (S.z non-null): the NS samples sit at S.z[n] in place of
 // e^{2 pi i n/N}, each term carries the quadrature weight S.w[n], and the sum
-// is scaled by sqrt(1 - r^2) instead of sqrt(1 - r^2)/N.
+// is scaled by sqrt(1 - r^2) instead of sqrt(1 - r^2)/N.  Workgroup z of
+// the grid's third dimension takes candidates z, z + gridDim.z, ...; their
+// radii and angles are fetched together before the sums.
 constexpr int kRecheckPerThread = 8;  // chunk of 2048 samples over 256 threads
 __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ cand, const double* __restrict__ g,
                                                  const double* __restrict__ omega, const double* __restrict__ radii,
@@ -89,6 +91,7 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
                                                  unsigned int* __restrict__ counter, Winner* __restrict__ w,
                                                  RecheckSamples S) {
   __shared__ double wsum[kKMax][4][2];  // [candidate][wave] (re, im)
+  __shared__ double cpar[kKMax][3];     // [candidate] r, e^{2 pi i j/N}
   __shared__ double wd[16];
   __shared__ Best bb[16];
   __shared__ int s_last;
@@ -104,6 +107,15 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
   counter += b;
   w += b;
   const int count = min(max(cand->count, 0), kKMax);
+  const int c0 = int(blockIdx.z), cs = int(gridDim.z);
+  // this workgroup's candidates: radius and angle, all in one round trip
+  for (int c = c0 + cs * tid; c < count; c += cs * int(blockDim.x)) {
+    const uint32_t f = key_f(cand->keys[c]);
+    const int m = int(f / uint32_t(N)), j = int(f % uint32_t(N));
+    cpar[c][0] = radii[m];
+    cpar[c][1] = omega[2 * j];
+    cpar[c][2] = omega[2 * j + 1];
+  }
   double gx[kRecheckPerThread], gy[kRecheckPerThread], ox[kRecheckPerThread], oy[kRecheckPerThread];
 #pragma unroll
   for (int q = 0; q < kRecheckPerThread; ++q) {
@@ -120,11 +132,10 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
       gy[q] *= wn;
     }
   }
-  for (int c = 0; c < count; ++c) {
-    const uint32_t f = key_f(cand->keys[c]);
-    const int m = int(f / uint32_t(N)), j = int(f % uint32_t(N));
-    const double r = radii[m];
-    const double wjx = omega[2 * j], wjy = omega[2 * j + 1];
+  __syncthreads();
+  for (int c = c0; c < count; c += cs) {
+    const double r = cpar[c][0];
+    const double wjx = cpar[c][1], wjy = cpar[c][2];
     double ax = 0.0, ay = 0.0;
 #pragma unroll
     for (int q = 0; q < kRecheckPerThread; ++q) {
@@ -144,7 +155,7 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
     }
   }
   __syncthreads();
-  for (int c = tid; c < count; c += int(blockDim.x)) {
+  for (int c = c0 + cs * tid; c < count; c += cs * int(blockDim.x)) {
     double sx = 0.0, sy = 0.0;
     for (int v = 0; v < nwaves(); ++v) {
       sx += wsum[c][v][0];
@@ -153,7 +164,7 @@ __global__ __launch_bounds__(256) void k_recheck(const CandList* __restrict__ ca
     st_agent(partials + 2 * (size_t(c) * nch + chunk), sx);
     st_agent(partials + 2 * (size_t(c) * nch + chunk) + 1, sy);
   }
-  if (!last_arrival(counter, gridDim.x, &s_last)) return;
+  if (!last_arrival(counter, gridDim.x * gridDim.z, &s_last)) return;
   static_assert(kKMax <= 256, "one candidate per thread");
   uint64_t key = 0;
   double rk = 0.0;
@@ -296,7 +307,9 @@ hipError_t launch_recheck(const CandList* cand, const double* g, const double* o
   const int ns = S.z ? S.ns : N;
   const int nch = recheck_chunks(ns);
   if ((ns + nch - 1) / nch > 256 * kRecheckPerThread) return hipErrorInvalidValue;  // a chunk fits the registers
-  hipLaunchKernelGGL(k_recheck, dim3(nch, batch), dim3(256), 0, s, cand, g, omega, radii, N, nch, partials,
+  // candidate groups: at least a few hundred workgroups for a short signal
+  const int groups = nch >= 128 ? 1 : nch >= 32 ? 2 : nch >= 8 ? 4 : 8;
+  hipLaunchKernelGGL(k_recheck, dim3(nch, batch, groups), dim3(256), 0, s, cand, g, omega, radii, N, nch, partials,
                      counter, w, S);
   return hipGetLastError();
 }
