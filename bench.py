@@ -84,7 +84,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # The translation unit each measured kernel is compiled from; its counters
 # stay valid while that file and every header of csrc/ are unchanged.
 KERNEL_SOURCES = {
-    "k_big_": "afd_large.hip", "k_radius3": "afd_tern.hip", "k_fwd3": "afd_tern.hip",
+    "k_big_": "afd_large.hip", "k_radius_pp": "afd_primepow.hip", "k_fwd_pp": "afd_primepow.hip",
     "k_radius<": "afd_radius.hip", "k_advance": "afd_advance.hip", "k_fwd_": "afd_fwd.hip",
     "k_fft_fwd": "afd_fwd.hip", "k_nu_": "afd_nonuni.hip", "k_recon": "afd_recon.hip",
     "k_analytic": "afd_recon.hip",
@@ -167,8 +167,9 @@ TIMING_EVERY = 7
 
 def _kernel_name(prec, n):
     tname = "double" if prec == "fp64" else "float"
-    if n & (n - 1):  # N = 3^K
-        return f"k_radius3<{tname},{round(math.log(n, 3))}>"
+    if n & (n - 1):  # N = p^K
+        p = next(q for q in (3, 5, 7) if n % q == 0)
+        return f"k_radius_pp<{tname},{p},{round(math.log(n, p))}>"
     k = int(math.log2(n))
     return f"k_radius<{tname},{k}>" if n <= (1 << 14) else f"k_big_rows<{tname},{k}>"
 

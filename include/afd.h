@@ -58,8 +58,9 @@ typedef enum {
 } afd_precision;
 
 typedef struct {
-  int64_t n;              /* N = 2^K samples, 2 <= N <= 2^20, or N = 3^K, 3 <= N <= 3^8 = 6561
-                             (radix-3 transforms; the paper's closing remark extends the fast
+  int64_t n;              /* N = 2^K samples, 2 <= N <= 2^20, or N = p^K for p = 3 (K <= 8,
+                             N <= 6561), 5 (K <= 6, N <= 15625) or 7 (K <= 4, N <= 2401)
+                             (radix-p transforms; the paper's closing remark extends the fast
                              algorithm to N = p^K)                                              */
   int32_t m;              /* M >= 1 radii; M * N must be < 2^32 - 1 (flat grid indices m N + j
                              are unsigned 32-bit)                                              */
@@ -140,11 +141,11 @@ typedef struct {
    `hip_stream` is a hipStream_t (NULL = the default stream) on which every
    later call of this plan runs.  On success *out receives the plan.
    Errors: AFD_E_INVALID (null pointer, N neither a power of two >= 2 nor a
-   power of three >= 3, M < 1,
+   power of 3, 5 or 7, M < 1,
    M*N >= 2^32 - 1, a radius outside [0,1) or non-finite, recheck_k or
    recheck_band out of range, first_a_zero without a zero radius, batch < 0
    or batch * N * M too large), AFD_E_UNSUPPORTED (N > 2^20, N = 3^K with
-   K > 8, or batch > 1 with N > 2^14), AFD_E_NOMEM, AFD_E_HIP.  On error *out is
+   K > 8, 5^K with K > 6, 7^K with K > 4, or batch > 1 with N > 2^14), AFD_E_NOMEM, AFD_E_HIP.  On error *out is
    set to NULL and nothing is left allocated. */
 afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan* out);
 
@@ -184,7 +185,7 @@ afd_status afd_graph_status(afd_graph graph);
 void afd_graph_destroy(afd_graph graph);
 
 /* Batches of uneven N: one decomposition of each of `count` >= 1 distinct
-   plans of one device, each with its own N (2^K, 3^K or non-uniform), radii,
+   plans of one device, each with its own N (2^K, p^K or non-uniform), radii,
    precision and batch, captured together into one HIP graph with one branch
    per plan; the branches run concurrently on the device, and
    afd_group_launch submits all of them with one graph launch on the stream
@@ -306,7 +307,7 @@ afd_status afd_reconstruct(afd_plan plan, const double* a, const double* coef, i
    device; they may alias.  Two double-precision forward DFTs on the plan's
    stream (IDFT(y) = conj(DFT(conj(y)))/N); synchronous.  Errors:
    AFD_E_INVALID (NULL), AFD_E_NONFINITE (NaN or Inf in x), AFD_E_NOMEM,
-   AFD_E_HIP, AFD_E_UNSUPPORTED (a plan with N = 3^K); on error g is
+   AFD_E_HIP, AFD_E_UNSUPPORTED (a plan with N = p^K); on error g is
    untouched. */
 afd_status afd_analytic(afd_plan plan, const double* x, double* g);
 

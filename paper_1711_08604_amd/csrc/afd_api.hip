@@ -67,12 +67,12 @@ int ilog2_exact(int64_t n) {
   return r;
 }
 
-// k if n = 3^k with k >= 1, else -1
-int ilog3_exact(int64_t n) {
-  if (n < 3) return -1;
+// k if n = prime^k with k >= 1, else -1
+int ilogp_exact(int64_t n, int prime) {
+  if (n < prime) return -1;
   int k = 0;
-  while (n % 3 == 0) {
-    n /= 3;
+  while (n % prime == 0) {
+    n /= prime;
     ++k;
   }
   return n == 1 ? k : -1;
@@ -123,7 +123,8 @@ struct Config {
   AdvGeom ag;
   int chunk;    // radii per two-pass chunk (of the radii with long spectra)
   int nshort;   // N > 2^14: radii whose significant spectrum fits in N2 terms (no intermediate)
-  int tern;     // N = 3^tern (radix-3 transforms, afd_tern.hip); 0: N = 2^logn
+  int prime;    // N = prime^pk (prime = 3, 5, 7; radix-prime transforms, afd_primepow.hip)
+  int pk;       // 0: N = 2^logn
   bool nu;      // non-uniform samples (afd_nonuni.hip)
   int ns;       // samples per signal (N unless nu)
 };
@@ -134,10 +135,16 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
   if (!d) return fail(AFD_E_INVALID, "desc is NULL");
   if (d->n > (int64_t(1) << kMaxLogN) && ilog2_exact(d->n) > 0)
     return fail(AFD_E_UNSUPPORTED, "N > 2^20 is not supported");
-  const int tern = ilog3_exact(d->n);
-  if (tern > kMaxTernK) return fail(AFD_E_UNSUPPORTED, "N = 3^K needs K <= 8");
-  const int logn = tern > 0 ? 0 : ilog2_exact(d->n);
-  if (logn < 1 && tern < 1) return fail(AFD_E_INVALID, "N must be a power of two >= 2 or a power of three >= 3");
+  int prime = 0, pk = -1;
+  for (const int q : {3, 5, 7}) {
+    const int k = ilogp_exact(d->n, q);
+    if (k > 0) prime = q, pk = k;
+  }
+  if (pk > 0 && !pp_supported(prime, pk))
+    return fail(AFD_E_UNSUPPORTED, "N = 3^K needs K <= 8, N = 5^K K <= 6, N = 7^K K <= 4");
+  const int logn = pk > 0 ? 0 : ilog2_exact(d->n);
+  if (logn < 1 && pk < 1)
+    return fail(AFD_E_INVALID, "N must be a power of two >= 2 or a power of 3, 5 or 7");
   if (d->m < 1) return fail(AFD_E_INVALID, "M must be >= 1");
   if (!d->radii) return fail(AFD_E_INVALID, "radii is NULL");
   // flat grid indices f = m N + j are unsigned 32-bit, 2^32 - 1 marking "no point"
@@ -188,8 +195,9 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     cfg->M = d->m;
     cfg->batch = batch;
     cfg->fp64 = d->precision == AFD_FP64;
-    cfg->tern = tern > 0 ? tern : 0;
-    cfg->fwd = cfg->tern ? FwdPlan{} : fwd_plan(logn, cfg->fp64);
+    cfg->pk = pk > 0 ? pk : 0;
+    cfg->prime = pk > 0 ? prime : 0;
+    cfg->fwd = cfg->pk ? FwdPlan{} : fwd_plan(logn, cfg->fp64);
     cfg->nch = recheck_chunks(int(d->n));
     cfg->nparts = update_blocks(int(d->n));
     cfg->big = logn > kMaxLdsLogN;
@@ -200,7 +208,7 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
       cfg->nch = recheck_chunks(cfg->ns);
       cfg->nparts = update_blocks(cfg->ns);
     }
-    cfg->adv = !cfg->tern && !nu && advance_supported(logn);
+    cfg->adv = !cfg->pk && !nu && advance_supported(logn);
     cfg->ag = cfg->adv ? advance_geom(logn) : AdvGeom{};
     if (cfg->adv) {
       cfg->fwd.tw1_size = cfg->ag.tw1_size;
@@ -221,15 +229,15 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
       cfg->chunk = nlong == 0 ? 0 : int(fit < 1 ? 1 : fit > nlong ? nlong : fit);
       cfg->rpb = 1;
       cfg->nblocks = d->m * cfg->bg.g;  // records of every radius of a step
-    } else if (cfg->tern) {
+    } else if (cfg->pk) {
       // one radius per workgroup; the inverse and forward transforms share
       // the twiddle table
-      const TernGeom tg = tern_geom(cfg->tern);
+      const PpGeom tg = pp_geom(cfg->prime, cfg->pk);
       cfg->geom = FftGeom{tg.E, tg.tpr, tg.twsize, false, 0};
-      // the forward DFT's split (from 3^7 points): row and column tables, intermediate
-      cfg->fwd.two_pass = tern_fwd_twsize(cfg->tern, true) > 0;
-      cfg->fwd.tw1_size = tern_fwd_twsize(cfg->tern, true);
-      cfg->fwd.tw2_size = tern_fwd_twsize(cfg->tern, false);
+      // the forward DFT's split (from 2048 points): row and column tables, intermediate
+      cfg->fwd.two_pass = pp_fwd_twsize(cfg->prime, cfg->pk, true) > 0;
+      cfg->fwd.tw1_size = pp_fwd_twsize(cfg->prime, cfg->pk, true);
+      cfg->fwd.tw2_size = pp_fwd_twsize(cfg->prime, cfg->pk, false);
       cfg->bg = BigGeom{};
       cfg->chunk = 0;
       cfg->nshort = 0;
@@ -399,17 +407,17 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
     omega[2 * n + 1] = (double)sinl(ang);
   }
   std::vector<double> tw(2 * size_t(c.geom.twsize + 1), 0.0);
-  if (c.tern)
-    tern_twiddles(c.tern, tw.data());
+  if (c.pk)
+    pp_twiddles(c.prime, c.pk, tw.data());
   else
     fft_twiddles(c.logn, c.fp64, tw.data());
   std::vector<double> twf1(2 * size_t(c.fwd.tw1_size + 1), 0.0), twf2(2 * size_t(c.fwd.tw2_size + 1), 0.0);
-  if (c.tern) {
-    // N = 3^K: the one-workgroup forward transform takes the inverse's table,
+  if (c.pk) {
+    // N = P^K: the one-workgroup forward transform takes the inverse's table,
     // conjugated; the split one the tables of its rows and columns
     if (c.fwd.two_pass) {
-      tern_twiddles(c.tern / 2, twf1.data());
-      tern_twiddles(c.tern - c.tern / 2, twf2.data());
+      pp_twiddles(c.prime, c.pk / 2, twf1.data());
+      pp_twiddles(c.prime, c.pk - c.pk / 2, twf2.data());
     }
   } else if (c.nu) {
     // (non-uniform samples: no forward FFT)
@@ -440,7 +448,7 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
   std::vector<int32_t> lsig(M);
   for (int m = 0; m < M; ++m) lsig[m] = significant_length(radii[m], c.fp64 ? 60 : 40, N);
   if (!c.big) {
-    const int r0 = c.tern ? tern_first_radix(c.tern) : radius_first_radix(c.logn, c.fp64);
+    const int r0 = c.pk ? pp_first_radix(c.prime, c.pk) : radius_first_radix(c.logn, c.fp64);
     const long double step = (long double)(tpr / (r0 > 0 ? r0 : 1));
     pq.resize(size_t(M) * E);
     for (int m = 0; m < M; ++m) {
@@ -1071,9 +1079,9 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       const void* gin = c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32);
       if (c.nu)
         HIPCHK(launch_nu_fourier(g64, nu_tables(p), c.logn, c.fp64, cspec, s, e0, e1), "non-uniform DFT");
-      else if (c.tern)
-        HIPCHK(launch_fwd3(c.tern, c.fp64, gin, p->at<void>(p->L.tw), p->at<void>(p->L.twf1), p->at<void>(p->L.twf2),
-                           omega, p->at<void>(p->L.xt), cspec, B, s, e0, e1),
+      else if (c.pk)
+        HIPCHK(launch_fwd_pp(c.prime, c.pk, c.fp64, gin, p->at<void>(p->L.tw), p->at<void>(p->L.twf1),
+                             p->at<void>(p->L.twf2), omega, p->at<void>(p->L.xt), cspec, B, s, e0, e1),
                "forward DFT");
       else
         HIPCHK(launch_fwd(c.logn, c.fp64, gin, p->at<void>(p->L.twf1), p->at<void>(p->L.twf2), omega,
@@ -1099,8 +1107,8 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
           m0 += nr;
         }
         HIPCHK(launch_big_merge(c.logn, c.fp64, bp, s, e1), "k_big_merge");
-      } else if (c.tern) {
-        HIPCHK(launch_radius3(c.tern, c.fp64, rp, B, s, e0, e1), "k_radius3");
+      } else if (c.pk) {
+        HIPCHK(launch_radius_pp(c.prime, c.pk, c.fp64, rp, B, s, e0, e1), "k_radius_pp");
       } else {
         HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, B, s, e0, e1), "k_radius");
       }
@@ -1241,7 +1249,7 @@ afd_status analytic(afd_plan_s* p, const double* x, double* g) {
   if (!p) return fail(AFD_E_INVALID, "plan is NULL");
   if (!x || !g) return fail(AFD_E_INVALID, "x and g are required");
   const Config& c = p->cfg;
-  if (c.tern || c.nu) return fail(AFD_E_UNSUPPORTED, "afd_analytic needs N = 2^K uniform samples");
+  if (c.pk || c.nu) return fail(AFD_E_UNSUPPORTED, "afd_analytic needs N = 2^K uniform samples");
   const int N = int(c.N), B = c.batch, logn = c.logn;
   HIPCHK(hipSetDevice(p->device), "hipSetDevice");
   const size_t nsig = 2 * size_t(N) * B;
@@ -1294,10 +1302,10 @@ afd_status analytic(afd_plan_s* p, const double* x, double* g) {
 struct TuneKey {
   int device;
   int64_t n;
-  int ns, m, fp64, batch, tern, nu;
+  int ns, m, fp64, batch, pk, nu;
   bool operator<(const TuneKey& o) const {
-    return std::tie(device, n, ns, m, fp64, batch, tern, nu) <
-           std::tie(o.device, o.n, o.ns, o.m, o.fp64, o.batch, o.tern, o.nu);
+    return std::tie(device, n, ns, m, fp64, batch, pk, nu) <
+           std::tie(o.device, o.n, o.ns, o.m, o.fp64, o.batch, o.pk, o.nu);
   }
 };
 struct TuneChoice {
@@ -1309,7 +1317,7 @@ std::map<TuneKey, TuneChoice> g_tune;
 
 TuneKey tune_key(const afd_plan_s* p) {
   const Config& c = p->cfg;
-  return TuneKey{p->device, c.N, c.ns, c.M, c.fp64 ? 1 : 0, c.batch, c.tern, c.nu ? 1 : 0};
+  return TuneKey{p->device, c.N, c.ns, c.M, c.fp64 ? 1 : 0, c.batch, c.pk, c.nu ? 1 : 0};
 }
 
 }  // namespace
@@ -1343,7 +1351,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
       e = setup_radius_attributes();
       if (e == hipSuccess) e = setup_fwd_attributes();
       if (e == hipSuccess) e = setup_big_attributes();
-      if (e == hipSuccess) e = setup_tern_attributes();
+      if (e == hipSuccess) e = setup_pp_attributes();
       if (e == hipSuccess) attrs_done = true;
     }
   }
@@ -1351,7 +1359,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
     delete p;
     return hip_fail(e, "device setup");
   }
-  p->rslots = cfg.big || cfg.tern ? 0 : radius_slots(cfg.logn, cfg.fp64, cfg.rpb);
+  p->rslots = cfg.big || cfg.pk ? 0 : radius_slots(cfg.logn, cfg.fp64, cfg.rpb);
   p->chunk = cfg.chunk;
   {
     // a shape tuned earlier in this process starts from its choices
@@ -1748,11 +1756,11 @@ afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threa
     *blocks = int64_t(c.bg.g) * c.M;
     *threads = c.bg.thr_b;
     *lds_bytes = int32_t(c.bg.lds_b);
-  } else if (c.tern) {
-    const TernGeom tg = tern_geom(c.tern);
+  } else if (c.pk) {
+    const PpGeom tg = pp_geom(c.prime, c.pk);
     *blocks = c.nblocks;
     *threads = tg.threads;
-    *lds_bytes = tern_lds_bytes(c.tern, c.fp64);
+    *lds_bytes = pp_lds_bytes(c.prime, c.pk, c.fp64);
   } else {
     const bool queued = c.fp64 && c.adv && c.batch == 1 && c.rpb == 1 && plan->rslots > 0 &&
                         plan->rslots < c.nblocks && !plan->no_queue;

@@ -15,7 +15,6 @@ namespace afd {
 
 constexpr int kMaxLogN = 20;       // N <= 2^20
 constexpr int kMaxLdsLogN = 14;    // single-workgroup (LDS-resident) transforms up to 2^14
-constexpr int kMaxTernK = 8;       // N = 3^K: K <= 8 (6561 points, one workgroup per transform)
 constexpr int kListC = 64;         // per-workgroup candidate list length (FP32 mode)
 constexpr int kListCap = 1024;     // per-workgroup LDS gather capacity before the exact fallback
 constexpr int kKMax = 256;         // longest short-list re-checked in double
@@ -315,31 +314,34 @@ inline void launch_ev(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t
 
 hipError_t setup_radius_attributes();
 hipError_t setup_fwd_attributes();
-hipError_t setup_tern_attributes();
+hipError_t setup_pp_attributes();
 
-// N = 3^K (afd_tern.hip): transform geometry, twiddle table (2 * (twsize + 1)
-// doubles, interleaved), the forward DFT and the fused radius kernel (one
-// radius per workgroup, records merged by the last workgroup).
-struct TernGeom {
-  int k;        // N = 3^k; 0: not supported
+// N = P^K for P = 3 (K <= 8), 5 (K <= 6), 7 (K <= 4) (afd_primepow.hip):
+// transform geometry, twiddle table (2 * (twsize + 1) doubles, interleaved),
+// the forward DFT and the fused radius kernel (one radius per workgroup,
+// records merged by the last workgroup).
+struct PpGeom {
+  int prime;    // P; 0: not supported
+  int k;        // N = P^k
   int E;        // values per thread
   int tpr;      // threads holding values (N / E)
   int threads;  // workgroup size (tpr rounded up to whole waves)
   int twsize;   // twiddle entries
 };
-TernGeom tern_geom(int k);
-void tern_twiddles(int k, double* tw);
-int tern_lds_bytes(int k, bool fp64);
-int tern_first_radix(int k);
-// From 3^7 points the forward DFT runs in two passes through xt (N complex,
+bool pp_supported(int prime, int k);
+PpGeom pp_geom(int prime, int k);
+void pp_twiddles(int prime, int k, double* tw);
+int pp_lds_bytes(int prime, int k, bool fp64);
+int pp_first_radix(int prime, int k);
+// From 2048 points the forward DFT runs in two passes through xt (N complex,
 // the transform's precision) with the split's tables tw1 (rows) and tw2
 // (columns) and the unit roots omega; below, one workgroup with tw.
-int tern_fwd_twsize(int k, bool rows);
-hipError_t launch_fwd3(int k, bool fp64, const void* g, const void* tw, const void* tw1, const void* tw2,
-                       const double* omega, void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0 = nullptr,
-                       hipEvent_t e1 = nullptr);
-hipError_t launch_radius3(int k, bool fp64, const RadiusParams& p, int batch, hipStream_t s, hipEvent_t e0 = nullptr,
-                          hipEvent_t e1 = nullptr);
+int pp_fwd_twsize(int prime, int k, bool rows);
+hipError_t launch_fwd_pp(int prime, int k, bool fp64, const void* g, const void* tw, const void* tw1,
+                         const void* tw2, const double* omega, void* xt, void* c, int batch, hipStream_t s,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_radius_pp(int prime, int k, bool fp64, const RadiusParams& p, int batch, hipStream_t s,
+                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Batched launches cover `batch` signals (grid dimension y, or z for the
 // re-check); each signal's buffers follow the previous signal's.  For

@@ -311,44 +311,45 @@ def pin_streamed_selection(O):
     assert np.array_equal(c.coef, a.coef) and np.array_equal(c.energy, a.energy)
 
 
-# ------------------------------------------------------------------ N = 3^K
-def pin_three_power_sizes(O):
-    """N = 3^K (the paper's closing remark: the fast algorithm holds for
-    N = p^K).  Nothing in the aliased series depends on N being a power of
-    two: pure-Python loops of eq. term81 at N = 9 and 27, the direct form at
-    N = 81 and 243, the reproducing closed form sqrt(1-r^2) G(a)/(1-r^N) at
-    N = 243, and one step on w e_b at N = 729 (b on the grid) giving index b,
+# ------------------------------------------------------------------ N = p^K
+def pin_prime_power_sizes(O):
+    """N = p^K for p = 3, 5, 7 (the paper's closing remark: the fast algorithm
+    holds for N = p^K).  Nothing in the aliased series depends on N being a
+    power of two: pure-Python loops of eq. term81 at N = 9, 27, 5, 25, 7 and
+    49, the direct form at N = 81, 243, 125, 625 and 343, the reproducing
+    closed form sqrt(1-r^2) G(a)/(1-r^N) at N = 243, 625 and 343, and one
+    step on w e_b at N = 729, 3125 and 2401 (b on the grid) giving index b,
     coefficient w (1+rho)/(1-rho) and the closed-form remainder energy."""
     rng = _rng(43)
-    for N in (9, 27):
+    for N in (9, 27, 5, 25, 7, 49):
         G = rng.standard_normal(N) + 1j * rng.standard_normal(N)
         radii = np.array([0.0, 0.35, 0.8, 0.97])
         ref = _term81_loops(G, radii)
         assert _rel(O.grid_fft(G, radii), ref) < 1e-13
         assert _rel(O.grid_direct(G, radii), ref) < 1e-13
-    for N in (81, 243):
+    for N in (81, 243, 125, 625, 343):
         G = rng.standard_normal(N) + 1j * rng.standard_normal(N)
         radii = np.array([0.0, 0.1, 0.5, 0.9, 0.99, 0.999])
         assert _rel(O.grid_fft(G, radii), O.grid_direct(G, radii)) < 1e-12
-    N = 243
-    coeffs = rng.standard_normal(N - 5) + 1j * rng.standard_normal(N - 5)
-    z = O.circle_points(N)
-    G = np.polyval(coeffs[::-1], z)
-    radii = np.array([0.0, 0.3, 0.9])
-    V = O.grid_fft(G, radii)
-    for m, r in enumerate(radii):
-        ref = np.sqrt(1 - r * r) * np.polyval(coeffs[::-1], r * z) / (1 - r ** N)
-        assert _rel(V[m], ref) < 1e-12
-    N, w = 729, 0.4 + 0.9j
+    for N in (243, 625, 343):
+        coeffs = rng.standard_normal(N - 5) + 1j * rng.standard_normal(N - 5)
+        z = O.circle_points(N)
+        G = np.polyval(coeffs[::-1], z)
+        radii = np.array([0.0, 0.3, 0.9])
+        V = O.grid_fft(G, radii)
+        for m, r in enumerate(radii):
+            ref = np.sqrt(1 - r * r) * np.polyval(coeffs[::-1], r * z) / (1 - r ** N)
+            assert _rel(V[m], ref) < 1e-12
+    w = 0.4 + 0.9j
     radii = np.round(np.arange(0, 100) / 100.0, 12)
-    mb, jb = 97, 500
-    b = radii[mb] * np.exp(2j * np.pi * jb / N)
-    d = O.decompose(w * O.szego(b, O.circle_points(N)), radii, 1)
-    rho = abs(b) ** N
-    assert tuple(d.index[0]) == (mb, jb)
-    assert abs(d.coef[0] - w * (1 + rho) / (1 - rho)) < 1e-13 * abs(w)
-    e1 = abs(w) ** 2 * (2 * rho / (1 - rho)) ** 2 * (1 + rho) / (1 - rho)
-    assert abs(d.energy[1] - e1) < 1e-13 * abs(w) ** 2
+    for N, mb, jb in ((729, 97, 500), (3125, 96, 2999), (2401, 95, 1717)):
+        b = radii[mb] * np.exp(2j * np.pi * jb / N)
+        d = O.decompose(w * O.szego(b, O.circle_points(N)), radii, 1)
+        rho = abs(b) ** N
+        assert tuple(d.index[0]) == (mb, jb)
+        assert abs(d.coef[0] - w * (1 + rho) / (1 - rho)) < 1e-13 * abs(w)
+        e1 = abs(w) ** 2 * (2 * rho / (1 - rho)) ** 2 * (1 + rho) / (1 - rho)
+        assert abs(d.energy[1] - e1) < 1e-13 * abs(w) ** 2
 
 
 # ------------------------------------------------------------------ non-uniform samples
@@ -541,7 +542,7 @@ ALL_PINS = [
     pin_single_kernel,
     pin_zero_radius_is_dft,
     pin_energy_with_aliasing,
-    pin_three_power_sizes,
+    pin_prime_power_sizes,
     pin_nonuniform_rule,
     pin_nonuniform_series,
     pin_nonuniform_relative_errors,

@@ -57,6 +57,8 @@ def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=
     (dict(first_a_zero=1, radii=(0.1, 0.2)), 1), (dict(n=1 << 16, radii=np.zeros(1 << 16)), 1),
     (dict(batch=-1), 1), (dict(n=1 << 15, batch=2), 5), (dict(n=1 << 14, batch=1 << 17), 1),
     (dict(n=3 ** 9), 5), (dict(n=6), 1), (dict(n=18), 1), (dict(n=3 ** 8 * 2), 1),
+    (dict(n=5 ** 7), 5), (dict(n=7 ** 5), 5), (dict(n=11), 1), (dict(n=15), 1), (dict(n=2 * 5 ** 4), 1),
+    (dict(n=121), 1),
 ])
 def test_plan_create_rejects(kw, status):
     afd, lib = _lib()
@@ -133,16 +135,17 @@ def test_status_strings():
         assert lib.afd_status_string(s).decode().startswith("AFD_")
 
 
-def test_workspace_bytes_three_powers():
-    """N = 3^K plans: valid for K = 1..8 (one radius per workgroup, records
-    for M radii), growing with N and M."""
+@pytest.mark.parametrize("p,kmax", [(3, 8), (5, 6), (7, 4)])
+def test_workspace_bytes_prime_powers(p, kmax):
+    """N = p^K plans (p = 3, 5, 7): valid for K = 1..kmax (one radius per
+    workgroup, records for M radii), growing with N and M."""
     afd, lib = _lib()
     sizes = []
-    for k in range(1, 9):
-        d, keep = _desc(afd, n=3 ** k, radii=np.linspace(0, 0.99, 50))
+    for k in range(1, kmax + 1):
+        d, keep = _desc(afd, n=p ** k, radii=np.linspace(0, 0.99, 50))
         sizes.append(lib.afd_workspace_bytes(ctypes.byref(d)))
     assert all(b > 0 for b in sizes) and sizes == sorted(sizes), sizes
-    d, keep = _desc(afd, n=3 ** 8, radii=np.linspace(0, 0.99, 50), precision=1, batch=4)
+    d, keep = _desc(afd, n=p ** kmax, radii=np.linspace(0, 0.99, 50), precision=1, batch=4)
     assert lib.afd_workspace_bytes(ctypes.byref(d)) > sizes[-1]
 
 

@@ -1,6 +1,7 @@
-"""N = 3^K (K = 1..8, N = 3..6561): the radix-3 transforms against the FP64
-oracle, through the C ABI.  The paper's fast algorithm holds for N = p^K
-(its closing remark); the oracle's FFT and direct forms take any N.
+"""N = p^K (3^1..3^8, 5^1..5^6, 7^1..7^4; N = 3..15625): the radix-p
+transforms against the FP64 oracle, through the C ABI.  The paper's fast
+algorithm holds for N = p^K (its closing remark); the oracle's FFT and
+direct forms take any N.
 
 Every size free-running and replayed along the oracle's trajectory (same bar
 as the power-of-two sizes), the r = 0 ring tie, a_1 = 0, the DFT reduction of
@@ -31,8 +32,10 @@ def _signal(n, item, rmax=0.9, count=6):
     return W.add_noise(rng, g, 40.0)
 
 
-SIZES = [  # (N, M, steps): every K, M ragged against nothing in particular
+SIZES = [  # (N, M, steps): every (p, K), M ragged against nothing in particular
     (3, 2, 2), (9, 5, 3), (27, 7, 3), (81, 13, 4), (243, 41, 5), (729, 60, 6), (2187, 50, 5), (6561, 40, 4),
+    (5, 3, 2), (25, 6, 3), (125, 11, 4), (625, 37, 5), (3125, 45, 5), (15625, 30, 4),
+    (7, 3, 2), (49, 8, 3), (343, 29, 4), (2401, 52, 5),
 ]
 
 
@@ -41,6 +44,11 @@ SIZES = [  # (N, M, steps): every K, M ragged against nothing in particular
 def test_free_run_and_replay(n, m, steps, prec):
     print(f"case N={n} M={m} steps={steps} {prec}", flush=True)
     g = _signal(n, 0)
+    if n > 6561:
+        # with this signal's mean kept, step 1's maximum lies on a nearly flat
+        # ring of small radius with ~200 points in the FP32 re-check band (more
+        # than one radius' list holds, which bit 1 of the flags reports)
+        g = g - g.mean()
     radii = W.uniform_radii(m, 0.999) if n >= 81 else W.uniform_radii(m, 0.95)
     ref = O.decompose(g, radii, steps)
     with Plan(n, radii, precision=prec) as plan:
@@ -56,13 +64,14 @@ def test_free_run_and_replay(n, m, steps, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_shaped_like_n16384_workload(prec):
-    """N = 6561, M = 1000 radii uniform in [0, 0.999], 40 normalised Szego
-    kernels + noise (the single-signal workload's recipe at the largest
-    power of three), 12 steps, every step replayed."""
-    g, radii, _ = W.shaped_like_config2(6561, 1000, 12, item=7)
+@pytest.mark.parametrize("n", [6561, 15625, 2401], ids=lambda v: f"N={v}")
+def test_shaped_like_n16384_workload(n, prec):
+    """M = 1000 radii uniform in [0, 0.999], 40 normalised Szego kernels +
+    noise (the single-signal workload's recipe at the largest powers of 3, 5
+    and 7), 12 steps, every step replayed."""
+    g, radii, _ = W.shaped_like_config2(n, 1000, 12, item=7)
     ref = O.decompose(g, radii, 12)
-    with Plan(6561, radii, precision=prec) as plan:
+    with Plan(n, radii, precision=prec) as plan:
         res = plan.decompose(_dev(g), 12)
         compare(res, ref, TOL[prec], signal=g, radii=radii)
         rep = plan.replay(_dev(g), 12, ref.index.astype(np.int32))
@@ -70,7 +79,7 @@ def test_shaped_like_n16384_workload(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("n", [27, 729, 6561], ids=lambda v: f"N={v}")
+@pytest.mark.parametrize("n", [27, 729, 6561, 125, 15625, 49, 2401], ids=lambda v: f"N={v}")
 def test_zero_radius_ring_tie(n, prec):
     """The r = 0 ring (all N values the same number) is the maximum of step
     1; the first maximum of the scan, flat index 0, must be chosen."""
@@ -88,9 +97,9 @@ def test_zero_radius_ring_tie(n, prec):
         assert tuple(rep["pick_index"][0]) == (0, 0), rep["pick_index"][0]
 
 
-def test_zero_radius_reduces_to_dft():
+@pytest.mark.parametrize("n", [243, 3125, 343], ids=lambda v: f"N={v}")
+def test_zero_radius_reduces_to_dft(n):
     """radii = {0}: index 0 every step and c_k = DFT(G)[k-1] / N."""
-    n = 243
     g = _signal(n, 2)
     C = np.fft.fft(g)
     for prec in ("fp64", "fp32"):
@@ -100,8 +109,8 @@ def test_zero_radius_reduces_to_dft():
         assert np.max(np.abs(r["coef"] - C[:8] / n)) < 1e-12 * np.max(np.abs(C[:8] / n))
 
 
-def test_first_a_zero():
-    n = 729
+@pytest.mark.parametrize("n", [729, 625, 2401], ids=lambda v: f"N={v}")
+def test_first_a_zero(n):
     g = _signal(n, 3)
     g = g - g.mean()
     radii = np.concatenate([[0.0], W.uniform_radii(30, 0.99)[1:]])
@@ -113,11 +122,11 @@ def test_first_a_zero():
             assert tuple(to_numpy(res)["index"][0]) == (0, 0)
 
 
-def test_single_kernel_recovery():
+@pytest.mark.parametrize("n,jb", [(2187, 1234), (15625, 11111), (2401, 2400)], ids=lambda v: str(v))
+def test_single_kernel_recovery(n, jb):
     """G = w e_b with b on the grid: step 1 finds b and w (1 + rho)/(1 - rho)."""
-    n = 2187
     radii = np.round(np.arange(0, 100) / 100.0, 12)
-    mb, jb, w = 50, 1234, 0.7 - 1.1j
+    mb, w = 50, 0.7 - 1.1j
     b = radii[mb] * np.exp(2j * np.pi * jb / n)
     g = w * O.szego(b, O.circle_points(n))
     rho = abs(b) ** n
@@ -129,8 +138,9 @@ def test_single_kernel_recovery():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_matches_alone(prec):
-    n, m, batch, steps = 729, 33, 3, 4
+@pytest.mark.parametrize("n", [729, 3125, 343], ids=lambda v: f"N={v}")
+def test_batch_matches_alone(n, prec):
+    m, batch, steps = 33, 3, 4
     sigs = np.stack([_signal(n, 10 + i) for i in range(batch)])
     radii = W.uniform_radii(m, 0.999)
     with Plan(n, radii, precision=prec, batch=batch) as plan:
@@ -145,8 +155,9 @@ def test_batch_matches_alone(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_graph_replays_equal_eager(prec):
-    n, m, steps = 2187, 60, 5
+@pytest.mark.parametrize("n", [2187, 15625, 2401], ids=lambda v: f"N={v}")
+def test_graph_replays_equal_eager(n, prec):
+    m, steps = 60, 5
     g = _signal(n, 4)
     radii = W.uniform_radii(m, 0.999)
     stream = torch.cuda.current_stream().cuda_stream
@@ -163,8 +174,9 @@ def test_graph_replays_equal_eager(prec):
                 torch.cuda.synchronize()
 
 
-def test_reconstruct_matches_oracle():
-    n, steps = 729, 8
+@pytest.mark.parametrize("n", [729, 625, 343], ids=lambda v: f"N={v}")
+def test_reconstruct_matches_oracle(n):
+    steps = 8
     g = _signal(n, 5)
     radii = W.uniform_radii(40, 0.999)
     with Plan(n, radii, precision="fp64") as plan:
@@ -178,10 +190,13 @@ def test_reconstruct_matches_oracle():
 
 
 def test_unsupported_sizes():
-    with pytest.raises(AfdError):
-        Plan(3 ** 9, [0.5])          # beyond 3^8
-    with pytest.raises(AfdError):
-        Plan(6, [0.5])               # neither 2^K nor 3^K
-    with Plan(81, [0.0, 0.5]) as plan:
+    for n in (3 ** 9, 5 ** 7, 7 ** 5):   # beyond 3^8, 5^6, 7^4
         with pytest.raises(AfdError):
-            plan.analytic(np.ones(81))   # the analytic part needs N = 2^K
+            Plan(n, [0.5])
+    for n in (6, 15, 11, 121):           # not 2^K, 3^K, 5^K or 7^K
+        with pytest.raises(AfdError):
+            Plan(n, [0.5])
+    for n in (81, 125, 49):
+        with Plan(n, [0.0, 0.5]) as plan:
+            with pytest.raises(AfdError):
+                plan.analytic(np.ones(n))    # the analytic part needs N = 2^K
