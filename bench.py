@@ -16,8 +16,9 @@ spectra, two passes through HBM for the longest).  `value` is the FP64
 path; the FP32 + double re-check path is under "fp32", and the N = 16384,
 M = 1000, 50-step workload (40 Szego kernels + noise at 30 dB; LDS-resident
 transforms) under "single16k", and the same recipe at N = 3^8 = 6561 (the
-radix-3 transforms) under "tern6561".
-`--workload single16k` (or `tern6561`) times that workload alone.
+radix-3 transforms) under "tern6561" and at N = 5^6 = 15625 (the radix-5
+transforms) under "pow5_15625".
+`--workload single16k` (or `tern6561`, `pow5_15625`) times that workload alone.
 `--workload nonuni16k` times non-uniform samples (also the "nonuni16k" key
 of the default line): 16384 jittered positions with trapezoidal weights, a
 grid of N = 16384 angles, M = 1000 radii uniform in [0, 0.996], 50 steps.
@@ -492,6 +493,8 @@ WORKLOADS = {
                 "m/100, 10 AFD steps; launch-latency bound", 200, 10),
     "tern6561": ("single-signal Core-AFD at N=3^8=6561 samples (radix-3 transforms), M=1000 radii uniform in "
                  "[0,0.999], 50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB", 30, 3),
+    "pow5_15625": ("single-signal Core-AFD at N=5^6=15625 samples (radix-5 transforms), M=1000 radii uniform in "
+                   "[0,0.999], 50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB", 30, 3),
     "nonuni16k": ("non-uniform samples: 16384 jittered positions (trapezoidal weights), a grid of N=16384 angles, "
                   "M=1000 radii uniform in [0,0.996], 50 AFD steps; 12 normalised Szego kernels |b|<=0.9 + CN noise "
                   "at 40 dB", 10, 2),
@@ -510,6 +513,8 @@ def _workload(name, W):
         return W.config5()
     if name == "tern6561":
         return W.shaped_like_config2(6561, 1000, 50)
+    if name == "pow5_15625":
+        return W.shaped_like_config2(15625, 1000, 50)
     if name == "nonuni16k":
         g, t = W.nonuniform_kernel_signal(16384, item=0, kind="jitter")
         return g, W.uniform_radii(1000, 0.996), 50, t
@@ -541,15 +546,15 @@ def _time_workload(name, W, torch, steps, warmup, only=None, kernel_timing=True)
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "tern6561", "nonuni16k",
-                                           "mixed", "serve"],
+    ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "tern6561", "pow5_15625",
+                                           "nonuni16k", "mixed", "serve"],
                     default="chirp1m")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
     ap.add_argument("--steps", type=int, default=None, help="timed decompositions (chirp1m: 5)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed decompositions (chirp1m: 1)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
-                    help="chirp1m: skip the extra keys of the N=16384 and N=6561 workloads")
+                    help="chirp1m: skip the extra keys of the N=16384, 6561, 15625 and non-uniform workloads")
     ap.add_argument("--cpu-steps", type=int, default=5, help="AFD steps of the oracle sample (N <= 2^14)")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -640,6 +645,11 @@ def main():
         line["tern6561"] = {"workload": WORKLOADS["tern6561"][0],
                             **{p: {k: v[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
                                for p, v in r3.items()}}
+        # N = 5^6: the radix-5 transforms
+        _, _, _, r5 = _time_workload("pow5_15625", W, torch, max(args.steps, 10), args.warmup, args.only, kt)
+        line["pow5_15625"] = {"workload": WORKLOADS["pow5_15625"][0],
+                              **{p: {k: v[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "roofline")}
+                                 for p, v in r5.items()}}
         # non-uniform samples through the non-uniform DFT
         _, _, _, r4 = _time_workload("nonuni16k", W, torch, max(args.steps, 10), args.warmup, args.only, kt)
         line["nonuni16k"] = {"workload": WORKLOADS["nonuni16k"][0],

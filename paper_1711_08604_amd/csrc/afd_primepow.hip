@@ -19,11 +19,16 @@
 
 namespace afd {
 
-// The transforms exchange complex values through LDS, or, beyond 32 KiB,
-// real and imaginary parts in turn.
+// The transforms exchange complex values through LDS.  Double precision
+// beyond 32 KiB exchanges real and imaginary parts in turn, which keeps two
+// or three of the 3^8-point workgroups on a CU (non-split: 1.5x slower) and
+// lets 5^6 points fit at all; single precision (at most 125 KB) always
+// exchanges whole complex values, half the barriers and LDS instructions of
+// the split form (measured 1.16x at 3^8 and 1.24x at 5^6, where its
+// registers already hold one workgroup per CU).
 template <typename T, int P, int K>
 __host__ __device__ constexpr bool pp_split() {
-  return size_t(ipow(P, K)) * 2 * sizeof(T) > 32768;
+  return sizeof(T) == 8 && size_t(ipow(P, K)) * 2 * sizeof(T) > 32768;
 }
 template <typename T, int P, int K>
 __host__ __device__ constexpr size_t pp_region() {
