@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libafd.so")
 
-SOURCES = ["afd_fwd.hip", "afd_radius.hip", "afd_large.hip", "afd_primepow.hip", "afd_step.hip", "afd_advance.hip",
+SOURCES = ["afd_fwd.hip", "afd_radius.hip", "afd_large.hip", "afd_primepow.hip", "afd_mixed.hip", "afd_step.hip", "afd_advance.hip",
            "afd_nonuni.hip", "afd_recon.hip", "afd_api.hip"]
 
 HIPCC_FLAGS = [

@@ -90,6 +90,8 @@ struct Layout {
   size_t pq, lsig, order;
   // FP32 head and second keys of the workgroup (or per-radius) records
   size_t heads, seconds;
+  // mixed-radix pass table (radix, ns, twiddle offset per pass)
+  size_t mixp;
   // radius transforms beyond the LDS
   size_t wl, wh, z, c0, rrec, bcounters;
   // non-uniform samples: positions (turns), quadrature weights, points, DFT partial sums
@@ -125,6 +127,8 @@ struct Config {
   int nshort;   // N > 2^14: radii whose significant spectrum fits in N2 terms (no intermediate)
   int prime;    // N = prime^pk (prime = 3, 5, 7; radix-prime transforms, afd_primepow.hip)
   int pk;       // 0: N = 2^logn
+  bool mixed;   // N = 2^a 3^b 5^c 7^d with several primes (mixed-radix transforms, afd_mixed.hip)
+  MixedGeom mg;
   bool nu;      // non-uniform samples (afd_nonuni.hip)
   int ns;       // samples per signal (N unless nu)
 };
@@ -143,8 +147,17 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
   if (pk > 0 && !pp_supported(prime, pk))
     return fail(AFD_E_UNSUPPORTED, "N = 3^K needs K <= 8, N = 5^K K <= 6, N = 7^K K <= 4");
   const int logn = pk > 0 ? 0 : ilog2_exact(d->n);
-  if (logn < 1 && pk < 1)
-    return fail(AFD_E_INVALID, "N must be a power of two >= 2 or a power of 3, 5 or 7");
+  const MixedGeom mg = logn < 1 && pk < 1 ? mixed_geom(d->n) : MixedGeom{};
+  if (logn < 1 && pk < 1 && mg.E == 0) {
+    int64_t v = d->n;
+    for (const int q : {2, 3, 5, 7})
+      while (v > 1 && v % q == 0) v /= q;
+    if (d->n >= 2 && v == 1)
+      return fail(AFD_E_UNSUPPORTED,
+                  "mixed-radix N needs N <= 16384, the product of its distinct primes <= 30 and N/E threads "
+                  "within the workgroup");
+    return fail(AFD_E_INVALID, "N must be a power of two >= 2 or a product of powers of 2, 3, 5 and 7");
+  }
   if (d->m < 1) return fail(AFD_E_INVALID, "M must be >= 1");
   if (!d->radii) return fail(AFD_E_INVALID, "radii is NULL");
   // flat grid indices f = m N + j are unsigned 32-bit, 2^32 - 1 marking "no point"
@@ -197,7 +210,9 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     cfg->fp64 = d->precision == AFD_FP64;
     cfg->pk = pk > 0 ? pk : 0;
     cfg->prime = pk > 0 ? prime : 0;
-    cfg->fwd = cfg->pk ? FwdPlan{} : fwd_plan(logn, cfg->fp64);
+    cfg->mixed = mg.E > 0;
+    cfg->mg = mg;
+    cfg->fwd = cfg->pk || cfg->mixed ? FwdPlan{} : fwd_plan(logn, cfg->fp64);
     cfg->nch = recheck_chunks(int(d->n));
     cfg->nparts = update_blocks(int(d->n));
     cfg->big = logn > kMaxLdsLogN;
@@ -208,7 +223,7 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
       cfg->nch = recheck_chunks(cfg->ns);
       cfg->nparts = update_blocks(cfg->ns);
     }
-    cfg->adv = !cfg->pk && !nu && advance_supported(logn);
+    cfg->adv = !cfg->pk && !cfg->mixed && !nu && advance_supported(logn);
     cfg->ag = cfg->adv ? advance_geom(logn) : AdvGeom{};
     if (cfg->adv) {
       cfg->fwd.tw1_size = cfg->ag.tw1_size;
@@ -243,6 +258,15 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
       cfg->nshort = 0;
       cfg->rpb = 1;
       cfg->nblocks = d->m;
+    } else if (cfg->mixed) {
+      // one radius per workgroup; the one-workgroup forward transform takes
+      // the inverse's table, conjugated
+      cfg->geom = FftGeom{mg.E, mg.tpr, mg.twsize, false, 0};
+      cfg->bg = BigGeom{};
+      cfg->chunk = 0;
+      cfg->nshort = 0;
+      cfg->rpb = 1;
+      cfg->nblocks = d->m;
     } else {
       cfg->geom = fft_geom(logn, cfg->fp64);
       cfg->bg = BigGeom{};
@@ -266,6 +290,7 @@ Layout layout_of(const Config& c) {
     return at;
   };
   L.radii = take(8 * size_t(c.M));
+  L.mixp = take(c.mixed ? sizeof(int) * 3 * kMaxMixedPasses : 0);
   L.omega = take(16 * size_t(c.N));
   L.tw = take(2 * real * size_t(c.geom.twsize + 1));
   L.twf1 = take(2 * real * size_t(c.fwd.tw1_size + 1));
@@ -409,6 +434,8 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
   std::vector<double> tw(2 * size_t(c.geom.twsize + 1), 0.0);
   if (c.pk)
     pp_twiddles(c.prime, c.pk, tw.data());
+  else if (c.mixed)
+    mixed_twiddles(c.mg, tw.data());
   else
     fft_twiddles(c.logn, c.fp64, tw.data());
   std::vector<double> twf1(2 * size_t(c.fwd.tw1_size + 1), 0.0), twf2(2 * size_t(c.fwd.tw2_size + 1), 0.0);
@@ -419,8 +446,8 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
       pp_twiddles(c.prime, c.pk / 2, twf1.data());
       pp_twiddles(c.prime, c.pk - c.pk / 2, twf2.data());
     }
-  } else if (c.nu) {
-    // (non-uniform samples: no forward FFT)
+  } else if (c.nu || c.mixed) {
+    // (non-uniform samples: no forward FFT; mixed radix: the inverse's table)
   } else if (c.adv) {
     advance_twiddles(c.ag.l1, twf1.data());
     advance_twiddles(c.ag.l2, twf2.data());
@@ -448,7 +475,9 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
   std::vector<int32_t> lsig(M);
   for (int m = 0; m < M; ++m) lsig[m] = significant_length(radii[m], c.fp64 ? 60 : 40, N);
   if (!c.big) {
-    const int r0 = c.pk ? pp_first_radix(c.prime, c.pk) : radius_first_radix(c.logn, c.fp64);
+    const int r0 = c.pk      ? pp_first_radix(c.prime, c.pk)
+                   : c.mixed ? (c.mg.np >= 2 ? c.mg.ns[1] : 1)
+                             : radius_first_radix(c.logn, c.fp64);
     const long double step = (long double)(tpr / (r0 > 0 ? r0 : 1));
     pq.resize(size_t(M) * E);
     for (int m = 0; m < M; ++m) {
@@ -476,6 +505,11 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
   };
   hipError_t e = up(p->L.radii, radii, 8 * size_t(M));
   if (e == hipSuccess) e = up(p->L.omega, omega.data(), omega.size() * 8);
+  if (e == hipSuccess && c.mixed) {
+    int table[3 * kMaxMixedPasses] = {};
+    mixed_pass_table(c.mg, table);
+    e = up(p->L.mixp, table, sizeof(table));
+  }
   if (c.fp64) {
     if (e == hipSuccess) e = up(p->L.tw, tw.data(), tw.size() * 8);
     if (e == hipSuccess) e = up(p->L.twf1, twf1.data(), twf1.size() * 8);
@@ -1079,6 +1113,9 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       const void* gin = c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32);
       if (c.nu)
         HIPCHK(launch_nu_fourier(g64, nu_tables(p), c.logn, c.fp64, cspec, s, e0, e1), "non-uniform DFT");
+      else if (c.mixed)
+        HIPCHK(launch_fwd_mixed(c.mg, p->at<int>(p->L.mixp), c.fp64, gin, p->at<void>(p->L.tw), cspec, B, s, e0, e1),
+               "forward DFT");
       else if (c.pk)
         HIPCHK(launch_fwd_pp(c.prime, c.pk, c.fp64, gin, p->at<void>(p->L.tw), p->at<void>(p->L.twf1),
                              p->at<void>(p->L.twf2), omega, p->at<void>(p->L.xt), cspec, B, s, e0, e1),
@@ -1109,6 +1146,8 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
         HIPCHK(launch_big_merge(c.logn, c.fp64, bp, s, e1), "k_big_merge");
       } else if (c.pk) {
         HIPCHK(launch_radius_pp(c.prime, c.pk, c.fp64, rp, B, s, e0, e1), "k_radius_pp");
+      } else if (c.mixed) {
+        HIPCHK(launch_radius_mixed(c.mg, p->at<int>(p->L.mixp), c.fp64, rp, B, s, e0, e1), "k_radius_mixed");
       } else {
         HIPCHK(launch_radius(c.logn, c.fp64, rp, c.nblocks, B, s, e0, e1), "k_radius");
       }
@@ -1249,7 +1288,7 @@ afd_status analytic(afd_plan_s* p, const double* x, double* g) {
   if (!p) return fail(AFD_E_INVALID, "plan is NULL");
   if (!x || !g) return fail(AFD_E_INVALID, "x and g are required");
   const Config& c = p->cfg;
-  if (c.pk || c.nu) return fail(AFD_E_UNSUPPORTED, "afd_analytic needs N = 2^K uniform samples");
+  if (c.pk || c.mixed || c.nu) return fail(AFD_E_UNSUPPORTED, "afd_analytic needs N = 2^K uniform samples");
   const int N = int(c.N), B = c.batch, logn = c.logn;
   HIPCHK(hipSetDevice(p->device), "hipSetDevice");
   const size_t nsig = 2 * size_t(N) * B;
@@ -1352,6 +1391,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
       if (e == hipSuccess) e = setup_fwd_attributes();
       if (e == hipSuccess) e = setup_big_attributes();
       if (e == hipSuccess) e = setup_pp_attributes();
+      if (e == hipSuccess) e = setup_mixed_attributes();
       if (e == hipSuccess) attrs_done = true;
     }
   }
@@ -1359,7 +1399,7 @@ afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan
     delete p;
     return hip_fail(e, "device setup");
   }
-  p->rslots = cfg.big || cfg.pk ? 0 : radius_slots(cfg.logn, cfg.fp64, cfg.rpb);
+  p->rslots = cfg.big || cfg.pk || cfg.mixed ? 0 : radius_slots(cfg.logn, cfg.fp64, cfg.rpb);
   p->chunk = cfg.chunk;
   {
     // a shape tuned earlier in this process starts from its choices
@@ -1761,6 +1801,10 @@ afd_status afd_plan_radius_launch(afd_plan plan, int64_t* blocks, int32_t* threa
     *blocks = c.nblocks;
     *threads = tg.threads;
     *lds_bytes = pp_lds_bytes(c.prime, c.pk, c.fp64);
+  } else if (c.mixed) {
+    *blocks = c.nblocks;
+    *threads = c.mg.threads;
+    *lds_bytes = mixed_lds_bytes(c.mg, c.fp64);
   } else {
     const bool queued = c.fp64 && c.adv && c.batch == 1 && c.rpb == 1 && plan->rslots > 0 &&
                         plan->rslots < c.nblocks && !plan->no_queue;

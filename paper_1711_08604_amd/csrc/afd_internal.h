@@ -343,6 +343,38 @@ hipError_t launch_fwd_pp(int prime, int k, bool fp64, const void* g, const void*
 hipError_t launch_radius_pp(int prime, int k, bool fp64, const RadiusParams& p, int batch, hipStream_t s,
                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+// Mixed-radix N (afd_mixed.hip): N = 2^a 3^b 5^c 7^d <= kMaxMixedN with at
+// least two distinct primes, E values per thread (a multiple of each prime
+// of N, E <= 30), TPR = N/E threads, run-time pass radices (the last is E).
+constexpr int kMaxMixedPasses = 12;
+constexpr int kMaxMixedN = 16384;
+struct MixedGeom {
+  int E;        // values per thread; 0: N is not taken by the mixed-radix path
+  int tpr;      // threads holding values (N / E)
+  int threads;  // workgroup size (tpr rounded up to whole waves)
+  int np;       // passes
+  int twsize;   // twiddle entries
+  int radix[kMaxMixedPasses];  // pass radices, each dividing E
+  int ns[kMaxMixedPasses];     // product of the earlier radices
+  int twoff[kMaxMixedPasses];  // twiddle-table offset of each pass (from pass 1)
+};
+// kernel arguments: the pass table lives in device memory (3 ints per pass:
+// radix, ns, twiddle offset), so no kernel indexes its arguments at run time
+struct MixedArgs {
+  const int* passes;
+  int np, tpr, threads, E;
+};
+MixedGeom mixed_geom(int64_t n);
+void mixed_twiddles(const MixedGeom& g, double* tw);
+void mixed_pass_table(const MixedGeom& g, int* out);
+hipError_t setup_mixed_attributes();
+int mixed_lds_bytes(const MixedGeom& g, bool fp64);
+// one workgroup per signal: c = DFT(sig) with the inverse's table, conjugated
+hipError_t launch_fwd_mixed(const MixedGeom& g, const int* passes, bool fp64, const void* sig, const void* tw,
+                            void* c, int batch, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_radius_mixed(const MixedGeom& g, const int* passes, bool fp64, const RadiusParams& p, int batch,
+                               hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
 // Batched launches cover `batch` signals (grid dimension y, or z for the
 // re-check); each signal's buffers follow the previous signal's.  For
 // N > 2^14, c0 (nullable) also receives the bins l < N2 in natural order.

@@ -726,10 +726,12 @@ struct BitrevOrder {
 // FP64 workgroup selection: best point (value, flat index, grid value) and the
 // runner-up value.  Within a thread the bins are visited in increasing index
 // order, so a strict comparison keeps the lowest index among equal values.
-// E values per thread, TPR threads per transform, output order O.
+// E values per thread, TPR threads per transform (0: the run-time count
+// tpr_rt), output order O.
 template <typename T, int E, int TPR, class O>
 __device__ __forceinline__ void select_best_o(const Cx<T> (&v)[E], bool active, T sc, uint32_t fbase,
-                                              uint32_t fstride, int t, Best* wb, BlockBest64* o) {
+                                              uint32_t fstride, int t, Best* wb, BlockBest64* o, int tpr_rt = TPR) {
+  const int tpr = TPR > 0 ? TPR : tpr_rt;
   double y1 = -1.0, y2 = -1.0;
   int i1 = 0;
   T bx = T(0), by = T(0);
@@ -752,7 +754,7 @@ __device__ __forceinline__ void select_best_o(const Cx<T> (&v)[E], bool active, 
     const double s2 = double(sc) * double(sc);
     b.vx = double(bx * sc);
     b.vy = double(by * sc);
-    b.f = fbase + fstride * uint32_t(t + TPR * O::bin(i1));
+    b.f = fbase + fstride * uint32_t(t + tpr * O::bin(i1));
     // exact |.|^2 of the scaled grid value, as compared across radii
     b.p1 = b.vx * b.vx + b.vy * b.vy;
     b.p2 = fmin(y2 * s2, b.p1);
@@ -869,8 +871,9 @@ template <int E, int TPR, class O>
 __device__ __forceinline__ void select_list_o(const Cx<float> (&v)[E], bool active, float sc, uint32_t fbase,
                                               uint32_t fstride, int t, unsigned char* scratch, float tau_band,
                                               const FlatOrder& ord, BlockList32* o, uint64_t* head,
-                                              uint64_t* second, unsigned int* flagword) {
+                                              uint64_t* second, unsigned int* flagword, int tpr_rt = TPR) {
   static_assert(E <= 32, "the taken mask holds one bit per register");
+  const int tpr = TPR > 0 ? TPR : tpr_rt;
   const float s2 = sc * sc;
   float Y[E];
   float ym = 0.f;
@@ -908,7 +911,7 @@ __device__ __forceinline__ void select_list_o(const Cx<float> (&v)[E], bool acti
       base = lane_u32(base, leader);
       if (q) {
         const uint32_t pos = base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
-        if (pos < uint32_t(kListCap)) keys[pos] = key32(Y[p] * s2, fbase + fstride * uint32_t(t + TPR * O::bin(p)));
+        if (pos < uint32_t(kListCap)) keys[pos] = key32(Y[p] * s2, fbase + fstride * uint32_t(t + tpr * O::bin(p)));
       }
     }
   }
@@ -981,7 +984,7 @@ __device__ __forceinline__ void select_list_o(const Cx<float> (&v)[E], bool acti
 #pragma unroll
     for (int p = 0; p < E; ++p) {
       const bool q = Y[p] >= fl;
-      const uint64_t k = q ? key32(Y[p], fbase + fstride * uint32_t(t + TPR * O::bin(p))) : 0;
+      const uint64_t k = q ? key32(Y[p], fbase + fstride * uint32_t(t + tpr * O::bin(p))) : 0;
       wave_append(q, k, cnt, keys, uint32_t(kListCap));
     }
     __syncthreads();
@@ -1003,7 +1006,7 @@ __device__ __forceinline__ void select_list_o(const Cx<float> (&v)[E], bool acti
 #pragma unroll
     for (int p = 0; p < E; ++p) {
       if (!((taken >> p) & 1u) && Y[p] > 0.f) {
-        const uint64_t k = key32(Y[p], fbase + fstride * uint32_t(t + TPR * O::bin(p)));
+        const uint64_t k = key32(Y[p], fbase + fstride * uint32_t(t + tpr * O::bin(p)));
         tb = k > tb ? k : tb;
       }
     }
@@ -1014,7 +1017,7 @@ __device__ __forceinline__ void select_list_o(const Cx<float> (&v)[E], bool acti
     if (tid == 0) st_agent(&o->keys[rounds], b);
 #pragma unroll
     for (int p = 0; p < E; ++p) {
-      if (Y[p] > 0.f && key32(Y[p], fbase + fstride * uint32_t(t + TPR * O::bin(p))) == b) taken |= 1u << p;
+      if (Y[p] > 0.f && key32(Y[p], fbase + fstride * uint32_t(t + tpr * O::bin(p))) == b) taken |= 1u << p;
     }
   }
   if (tid == 0) list_header(o, head, second, flagword, pb, rounds, n, uint32_t(kFlagFallback), first, next);

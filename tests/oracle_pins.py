@@ -352,6 +352,46 @@ def pin_prime_power_sizes(O):
         assert abs(d.energy[1] - e1) < 1e-13 * abs(w) ** 2
 
 
+# ------------------------------------------------------------------ mixed radix
+def pin_mixed_radix_sizes(O):
+    """N with several prime factors (2, 3, 5, 7): the aliased series holds
+    for any N.  Pure-Python loops of eq. term81 at N = 6, 10, 12, 15 and 21,
+    the direct form at N = 60, 100, 210 and 360, the reproducing closed form
+    at N = 360 and 1000, and one step on w e_b at N = 1000 and 1536 (b on the
+    grid) giving index b, coefficient w (1+rho)/(1-rho) and the closed-form
+    remainder energy."""
+    rng = _rng(44)
+    for N in (6, 10, 12, 15, 21):
+        G = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        radii = np.array([0.0, 0.35, 0.8, 0.97])
+        ref = _term81_loops(G, radii)
+        assert _rel(O.grid_fft(G, radii), ref) < 1e-13
+        assert _rel(O.grid_direct(G, radii), ref) < 1e-13
+    for N in (60, 100, 210, 360):
+        G = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        radii = np.array([0.0, 0.1, 0.5, 0.9, 0.99, 0.999])
+        assert _rel(O.grid_fft(G, radii), O.grid_direct(G, radii)) < 1e-12
+    for N in (360, 1000):
+        coeffs = rng.standard_normal(N - 7) + 1j * rng.standard_normal(N - 7)
+        z = O.circle_points(N)
+        G = np.polyval(coeffs[::-1], z)
+        radii = np.array([0.0, 0.3, 0.9])
+        V = O.grid_fft(G, radii)
+        for m, r in enumerate(radii):
+            ref = np.sqrt(1 - r * r) * np.polyval(coeffs[::-1], r * z) / (1 - r ** N)
+            assert _rel(V[m], ref) < 1e-12
+    w = -0.3 + 1.2j
+    radii = np.round(np.arange(0, 100) / 100.0, 12)
+    for N, mb, jb in ((1000, 93, 777), (1536, 97, 1111)):
+        b = radii[mb] * np.exp(2j * np.pi * jb / N)
+        d = O.decompose(w * O.szego(b, O.circle_points(N)), radii, 1)
+        rho = abs(b) ** N
+        assert tuple(d.index[0]) == (mb, jb)
+        assert abs(d.coef[0] - w * (1 + rho) / (1 - rho)) < 1e-13 * abs(w)
+        e1 = abs(w) ** 2 * (2 * rho / (1 - rho)) ** 2 * (1 + rho) / (1 - rho)
+        assert abs(d.energy[1] - e1) < 1e-13 * abs(w) ** 2
+
+
 # ------------------------------------------------------------------ non-uniform samples
 def _nu_loops(G, turns, weights, radii, n):
     """The quadrature rule written out with plain Python loops (tiny inputs only)."""
@@ -543,6 +583,7 @@ ALL_PINS = [
     pin_zero_radius_is_dft,
     pin_energy_with_aliasing,
     pin_prime_power_sizes,
+    pin_mixed_radix_sizes,
     pin_nonuniform_rule,
     pin_nonuniform_series,
     pin_nonuniform_relative_errors,

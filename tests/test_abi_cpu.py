@@ -50,15 +50,15 @@ def _desc(afd, n=1024, radii=(0.0, 0.5), precision=0, recheck_k=8, first_a_zero=
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(n=1000), 1), (dict(n=1), 1), (dict(n=0), 1), (dict(n=-4), 1),
+    (dict(n=1001), 1), (dict(n=1), 1), (dict(n=0), 1), (dict(n=-4), 1),
     (dict(n=1 << 21), 5), (dict(radii=()), 1), (dict(radii=(0.2, 1.0)), 1), (dict(radii=(-0.1,)), 1),
     (dict(radii=(np.nan,)), 1), (dict(radii=(np.inf,)), 1), (dict(precision=7), 1),
     (dict(recheck_k=-1), 1), (dict(recheck_k=65), 1), (dict(band=-1e-3), 1), (dict(band=0.5), 1),
     (dict(first_a_zero=1, radii=(0.1, 0.2)), 1), (dict(n=1 << 16, radii=np.zeros(1 << 16)), 1),
     (dict(batch=-1), 1), (dict(n=1 << 15, batch=2), 5), (dict(n=1 << 14, batch=1 << 17), 1),
-    (dict(n=3 ** 9), 5), (dict(n=6), 1), (dict(n=18), 1), (dict(n=3 ** 8 * 2), 1),
-    (dict(n=5 ** 7), 5), (dict(n=7 ** 5), 5), (dict(n=11), 1), (dict(n=15), 1), (dict(n=2 * 5 ** 4), 1),
-    (dict(n=121), 1),
+    (dict(n=3 ** 9), 5), (dict(n=22), 1), (dict(n=26), 1), (dict(n=3 ** 8 * 2), 5),
+    (dict(n=5 ** 7), 5), (dict(n=7 ** 5), 5), (dict(n=11), 1), (dict(n=35), 5), (dict(n=42), 5),
+    (dict(n=121), 1), (dict(n=3 << 14), 5), (dict(n=17 * 3), 1),
 ])
 def test_plan_create_rejects(kw, status):
     afd, lib = _lib()
@@ -147,6 +147,20 @@ def test_workspace_bytes_prime_powers(p, kmax):
     assert all(b > 0 for b in sizes) and sizes == sorted(sizes), sizes
     d, keep = _desc(afd, n=p ** kmax, radii=np.linspace(0, 0.99, 50), precision=1, batch=4)
     assert lib.afd_workspace_bytes(ctypes.byref(d)) > sizes[-1]
+
+
+@pytest.mark.parametrize("n", [6, 10, 12, 15, 18, 100, 1000, 1536, 6000, 10125, 12288, 14336, 15360])
+def test_workspace_bytes_mixed_radix(n):
+    """Mixed-radix N (several of the primes 2, 3, 5, 7): valid up to 16384,
+    one radius per workgroup, growing with M and with the batch."""
+    afd, lib = _lib()
+    d, keep = _desc(afd, n=n, radii=np.linspace(0, 0.99, 50))
+    a = lib.afd_workspace_bytes(ctypes.byref(d))
+    d, keep = _desc(afd, n=n, radii=np.linspace(0, 0.99, 80))
+    b = lib.afd_workspace_bytes(ctypes.byref(d))
+    d, keep = _desc(afd, n=n, radii=np.linspace(0, 0.99, 50), precision=1, batch=3)
+    c = lib.afd_workspace_bytes(ctypes.byref(d))
+    assert 0 < a < b and a < c, (a, b, c)
 
 
 def _nu_desc(afd, n=256, radii=(0.0, 0.5), turns=None, weights=None, batch=0, precision=0):

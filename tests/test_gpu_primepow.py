@@ -193,7 +193,7 @@ def test_unsupported_sizes():
     for n in (3 ** 9, 5 ** 7, 7 ** 5):   # beyond 3^8, 5^6, 7^4
         with pytest.raises(AfdError):
             Plan(n, [0.5])
-    for n in (6, 15, 11, 121):           # not 2^K, 3^K, 5^K or 7^K
+    for n in (11, 22, 121, 13 * 27):     # a prime beyond 7
         with pytest.raises(AfdError):
             Plan(n, [0.5])
     for n in (81, 125, 49):
