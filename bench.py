@@ -18,7 +18,9 @@ M = 1000, 50-step workload (40 Szego kernels + noise at 30 dB; LDS-resident
 transforms) under "single16k", and the same recipe at N = 3^8 = 6561 (the
 radix-3 transforms) under "tern6561" and at N = 5^6 = 15625 (the radix-5
 transforms) under "pow5_15625".
-`--workload single16k` (or `tern6561`, `pow5_15625`) times that workload alone.
+`--workload single16k` (or `tern6561`, `pow5_15625`) times that workload alone;
+`--workload mixed12288` the same recipe at N = 12288 = 3 * 2^12 (mixed-radix
+transforms).
 `--workload nonuni16k` times non-uniform samples (also the "nonuni16k" key
 of the default line): 16384 jittered positions with trapezoidal weights, a
 grid of N = 16384 angles, M = 1000 radii uniform in [0, 0.996], 50 steps.
@@ -86,6 +88,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # stay valid while that file and every header of csrc/ are unchanged.
 KERNEL_SOURCES = {
     "k_big_": "afd_large.hip", "k_radius_pp": "afd_primepow.hip", "k_fwd_pp": "afd_primepow.hip",
+    "k_radius_mixed": "afd_mixed.hip", "k_fwd_mixed": "afd_mixed.hip",
     "k_radius<": "afd_radius.hip", "k_advance": "afd_advance.hip", "k_fwd_": "afd_fwd.hip",
     "k_fft_fwd": "afd_fwd.hip", "k_nu_": "afd_nonuni.hip", "k_recon": "afd_recon.hip",
     "k_analytic": "afd_recon.hip",
@@ -168,9 +171,12 @@ TIMING_EVERY = 7
 
 def _kernel_name(prec, n):
     tname = "double" if prec == "fp64" else "float"
-    if n & (n - 1):  # N = p^K
+    if n & (n - 1):
         p = next(q for q in (3, 5, 7) if n % q == 0)
-        return f"k_radius_pp<{tname},{p},{round(math.log(n, p))}>"
+        k = round(math.log(n, p))
+        if p ** k == n:  # N = p^K
+            return f"k_radius_pp<{tname},{p},{k}>"
+        return f"k_radius_mixed<{tname}>"  # mixed radix
     k = int(math.log2(n))
     return f"k_radius<{tname},{k}>" if n <= (1 << 14) else f"k_big_rows<{tname},{k}>"
 
@@ -495,6 +501,8 @@ WORKLOADS = {
                  "[0,0.999], 50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB", 30, 3),
     "pow5_15625": ("single-signal Core-AFD at N=5^6=15625 samples (radix-5 transforms), M=1000 radii uniform in "
                    "[0,0.999], 50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB", 30, 3),
+    "mixed12288": ("single-signal Core-AFD at N=12288=3*2^12 samples (mixed-radix transforms), M=1000 radii uniform "
+                   "in [0,0.999], 50 AFD steps; 40 normalised Szego kernels |b|<=0.98 + CN noise at 30 dB", 30, 3),
     "nonuni16k": ("non-uniform samples: 16384 jittered positions (trapezoidal weights), a grid of N=16384 angles, "
                   "M=1000 radii uniform in [0,0.996], 50 AFD steps; 12 normalised Szego kernels |b|<=0.9 + CN noise "
                   "at 40 dB", 10, 2),
@@ -515,6 +523,8 @@ def _workload(name, W):
         return W.shaped_like_config2(6561, 1000, 50)
     if name == "pow5_15625":
         return W.shaped_like_config2(15625, 1000, 50)
+    if name == "mixed12288":
+        return W.shaped_like_config2(12288, 1000, 50)
     if name == "nonuni16k":
         g, t = W.nonuniform_kernel_signal(16384, item=0, kind="jitter")
         return g, W.uniform_radii(1000, 0.996), 50, t
@@ -547,7 +557,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=["chirp1m", "single16k", "batch512", "small1k", "tern6561", "pow5_15625",
-                                           "nonuni16k", "mixed", "serve"],
+                                           "mixed12288", "nonuni16k", "mixed", "serve"],
                     default="chirp1m")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests in the stream")
     ap.add_argument("--steps", type=int, default=None, help="timed decompositions (chirp1m: 5)")

@@ -61,7 +61,11 @@ typedef struct {
   int64_t n;              /* N = 2^K samples, 2 <= N <= 2^20, or N = p^K for p = 3 (K <= 8,
                              N <= 6561), 5 (K <= 6, N <= 15625) or 7 (K <= 4, N <= 2401)
                              (radix-p transforms; the paper's closing remark extends the fast
-                             algorithm to N = p^K)                                              */
+                             algorithm to N = p^K), or a mixed radix N = 2^a 3^b 5^c 7^d <= 16384
+                             with several of these primes, their product at most 30 (2*3, 2*5,
+                             2*7, 3*5, 3*7, 2*3*5), and N/E <= 1024 threads (512 from E = 18),
+                             E the values per thread (a multiple of that product, E <= 30);
+                             e.g. 1000, 1536, 6000, 12288, 15360                                */
   int32_t m;              /* M >= 1 radii; M * N must be < 2^32 - 1 (flat grid indices m N + j
                              are unsigned 32-bit)                                              */
   const double* radii;    /* host pointer, length M, each in [0, 1); any order; copied at
@@ -140,12 +144,13 @@ typedef struct {
    tables and allocate the device workspace on the current HIP device.
    `hip_stream` is a hipStream_t (NULL = the default stream) on which every
    later call of this plan runs.  On success *out receives the plan.
-   Errors: AFD_E_INVALID (null pointer, N neither a power of two >= 2 nor a
-   power of 3, 5 or 7, M < 1,
+   Errors: AFD_E_INVALID (null pointer, N < 2 or with a prime factor above 7,
+   M < 1,
    M*N >= 2^32 - 1, a radius outside [0,1) or non-finite, recheck_k or
    recheck_band out of range, first_a_zero without a zero radius, batch < 0
    or batch * N * M too large), AFD_E_UNSUPPORTED (N > 2^20, N = 3^K with
-   K > 8, 5^K with K > 6, 7^K with K > 4, or batch > 1 with N > 2^14), AFD_E_NOMEM, AFD_E_HIP.  On error *out is
+   K > 8, 5^K with K > 6, 7^K with K > 4, a mixed-radix N outside the
+   sizes above, or batch > 1 with N > 2^14), AFD_E_NOMEM, AFD_E_HIP.  On error *out is
    set to NULL and nothing is left allocated. */
 afd_status afd_plan_create(const afd_plan_desc* desc, void* hip_stream, afd_plan* out);
 
@@ -185,7 +190,7 @@ afd_status afd_graph_status(afd_graph graph);
 void afd_graph_destroy(afd_graph graph);
 
 /* Batches of uneven N: one decomposition of each of `count` >= 1 distinct
-   plans of one device, each with its own N (2^K, p^K or non-uniform), radii,
+   plans of one device, each with its own N (2^K, p^K, mixed radix or non-uniform), radii,
    precision and batch, captured together into one HIP graph with one branch
    per plan; the branches run concurrently on the device, and
    afd_group_launch submits all of them with one graph launch on the stream
@@ -307,7 +312,7 @@ afd_status afd_reconstruct(afd_plan plan, const double* a, const double* coef, i
    device; they may alias.  Two double-precision forward DFTs on the plan's
    stream (IDFT(y) = conj(DFT(conj(y)))/N); synchronous.  Errors:
    AFD_E_INVALID (NULL), AFD_E_NONFINITE (NaN or Inf in x), AFD_E_NOMEM,
-   AFD_E_HIP, AFD_E_UNSUPPORTED (a plan with N = p^K); on error g is
+   AFD_E_HIP, AFD_E_UNSUPPORTED (a plan whose N is not 2^K); on error g is
    untouched. */
 afd_status afd_analytic(afd_plan plan, const double* x, double* g);
 
