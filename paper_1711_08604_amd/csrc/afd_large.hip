@@ -279,10 +279,10 @@ __global__ __launch_bounds__(256) void k_big_merge(BigParams p) {
   }
   if (!last_arrival(p.counter_g, gridDim.x, &s_last)) return;
   if constexpr (LIST) {
-    select32_tail(reinterpret_cast<const BlockList32*>(p.rrec), p.heads, nullptr, p.M, p.recheck_k, p.tau_band,
+    select32_tail<2, 8>(reinterpret_cast<const BlockList32*>(p.rrec), p.heads, nullptr, p.M, p.recheck_k, p.tau_band,
                   p.flagword, p.cand, Sm);
   } else {
-    merge64_tail(reinterpret_cast<const BlockBest64*>(p.rrec), p.M, B::N, p.winner, Sm);
+    merge64_tail<2, 8>(reinterpret_cast<const BlockBest64*>(p.rrec), p.M, B::N, p.winner, Sm);
   }
 }
 

@@ -427,11 +427,11 @@ __global__ __launch_bounds__(mixed_max_threads(E)) void k_radius_mixed(RadiusPar
   if (!last_arrival(prm.counter + b, gridDim.x, &s_last)) return;
   MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
   if constexpr (LIST) {
-    select32_tail(reinterpret_cast<const BlockList32*>(prm.out) + size_t(prm.nrec) * b,
+    select32_tail<2, 8>(reinterpret_cast<const BlockList32*>(prm.out) + size_t(prm.nrec) * b,
                   prm.heads + size_t(prm.nrec) * b, prm.seconds + size_t(prm.nrec) * b, prm.nrec, prm.recheck_k,
                   prm.tau_band, prm.flagword + b, prm.cand + b, Sm);
   } else {
-    merge64_tail(reinterpret_cast<const BlockBest64*>(prm.out) + size_t(prm.nrec) * b, prm.nrec, N, prm.winner + b,
+    merge64_tail<2, 8>(reinterpret_cast<const BlockBest64*>(prm.out) + size_t(prm.nrec) * b, prm.nrec, N, prm.winner + b,
                  Sm);
   }
 }

@@ -386,8 +386,11 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
 }
 
 // FP64: global best of the per-block records -> winner (coefficient = the
-// grid value of the FFT form).
-template <int PRE = 2>
+// grid value of the FFT form).  Each thread loads its first PRE records in
+// one round trip, then BATCH records per round trip (workgroups with few
+// threads and many records: the loop's loads would otherwise wait one by
+// one).
+template <int PRE = 2, int BATCH = 1>
 __device__ __forceinline__ void merge64_tail(const BlockBest64* __restrict__ blocks, int nb, int N,
                                              Winner* __restrict__ w, MergeScratch* S) {
   Best b{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};
@@ -404,10 +407,25 @@ __device__ __forceinline__ void merge64_tail(const BlockBest64* __restrict__ blo
     for (int q = 0; q < PRE; ++q)
       if (int(threadIdx.x) + q * int(blockDim.x) < nb) best_merge(b, x[q]);
   }
-  for (int i = int(threadIdx.x) + PRE * int(blockDim.x); i < nb; i += blockDim.x) {
-    const BlockBest64* o = blocks + i;
-    const Best x{ld_agent(&o->p1), ld_agent(&o->p2), ld_agent(&o->vx), ld_agent(&o->vy), ld_agent(&o->f)};
-    best_merge(b, x);
+  if constexpr (BATCH == 1) {
+    for (int i = int(threadIdx.x) + PRE * int(blockDim.x); i < nb; i += blockDim.x) {
+      const BlockBest64* o = blocks + i;
+      const Best x{ld_agent(&o->p1), ld_agent(&o->p2), ld_agent(&o->vx), ld_agent(&o->vy), ld_agent(&o->f)};
+      best_merge(b, x);
+    }
+  } else {
+    for (int i0 = int(threadIdx.x) + PRE * int(blockDim.x); i0 < nb; i0 += BATCH * int(blockDim.x)) {
+      Best x[BATCH];
+#pragma unroll
+      for (int q = 0; q < BATCH; ++q) {
+        const int i = i0 + q * int(blockDim.x);
+        const BlockBest64* o = blocks + (i < nb ? i : nb - 1);
+        x[q] = Best{ld_agent(&o->p1), ld_agent(&o->p2), ld_agent(&o->vx), ld_agent(&o->vy), ld_agent(&o->f)};
+      }
+#pragma unroll
+      for (int q = 0; q < BATCH; ++q)
+        if (i0 + q * int(blockDim.x) < nb) best_merge(b, x[q]);
+    }
   }
   const Best r = block_best(b, S->bb);
   if (threadIdx.x == 0) {
@@ -437,8 +455,9 @@ __device__ __forceinline__ void merge64_tail(const BlockBest64* __restrict__ blo
 // fallback flag for the step; it is read here, and cleared unless several
 // workgroups merge the same records (then the caller clears it once all
 // have read it).  The result depends only on the records, not on the
-// workgroup size or on scheduling.
-template <int PRE = 2>
+// workgroup size or on scheduling.  BATCH: head keys per thread, and band
+// lists per wave, fetched per round trip after the first.
+template <int PRE = 2, int BATCH = 1>
 __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ lists,
                                               const uint64_t* __restrict__ heads,
                                               const uint64_t* __restrict__ seconds, int nb, int recheck_k,
@@ -472,11 +491,33 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
       }
     }
   }
-  for (int b = tid + PRE * int(blockDim.x); b < nb; b += blockDim.x) {
-    const uint64_t k = ld_agent(heads + b);
-    if (use2) S->seconds[b] = ld_agent(seconds + b);
-    if (fits) S->heads[b] = k;
-    mx = k > mx ? k : mx;
+  if constexpr (BATCH == 1) {
+    for (int b = tid + PRE * int(blockDim.x); b < nb; b += blockDim.x) {
+      const uint64_t k = ld_agent(heads + b);
+      if (use2) S->seconds[b] = ld_agent(seconds + b);
+      if (fits) S->heads[b] = k;
+      mx = k > mx ? k : mx;
+    }
+  } else {
+    for (int b0 = tid + PRE * int(blockDim.x); b0 < nb; b0 += BATCH * int(blockDim.x)) {
+      uint64_t hk[BATCH], sk[BATCH];
+#pragma unroll
+      for (int i = 0; i < BATCH; ++i) {
+        const int b = b0 + i * int(blockDim.x);
+        const int bc = b < nb ? b : nb - 1;
+        hk[i] = ld_agent(heads + bc);
+        sk[i] = use2 ? ld_agent(seconds + bc) : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < BATCH; ++i) {
+        const int b = b0 + i * int(blockDim.x);
+        if (b < nb) {
+          if (use2) S->seconds[b] = sk[i];
+          if (fits) S->heads[b] = hk[i];
+          mx = hk[i] > mx ? hk[i] : mx;
+        }
+      }
+    }
   }
   if (tid == 0) {
     S->sflags = ld_agent(flagword) & uint32_t(kFlagFallback);
@@ -513,18 +554,39 @@ __device__ __forceinline__ void select32_tail(const BlockList32* __restrict__ li
   const uint32_t nbb = S->sblocks;
   const uint32_t ncb = nbb < uint32_t(kSelCap) ? nbb : uint32_t(kSelCap);
   // one wave per band block: its count, total and all kListC key slots in
-  // one round trip (slots at or beyond the count are masked)
-  for (uint32_t i = wave; i < ncb; i += nw) {
-    const BlockList32* L = lists + S->cblk[i];
-    const uint32_t cnt = uint32_t(__builtin_amdgcn_readfirstlane(int(ld_agent(&L->count))));
-    const uint32_t tot = uint32_t(__builtin_amdgcn_readfirstlane(int(ld_agent(&L->total))));
-    const uint64_t k = ld_agent(&L->keys[lane]);
+  // one round trip (slots at or beyond the count are masked); BATCH blocks
+  // per wave and round trip
+  auto band_list = [&](uint32_t cnt, uint32_t tot, uint64_t k) {
     const bool q = lane < int(cnt) && key_p(k) >= theta;
     wave_append(q, k, &S->scount, S->buf, uint32_t(kSelCap));
     // the list was cut inside the band: its last listed key is still in it
     if (cnt > 0 && cnt <= uint32_t(kListC) && tot > cnt) {
       const uint64_t klast = lane_u64(k, int(cnt) - 1);
       if (lane == 0 && key_p(klast) >= theta) atomicOr(&S->sflags, uint32_t(kFlagListTruncated));
+    }
+  };
+  if constexpr (BATCH == 1) {
+    for (uint32_t i = wave; i < ncb; i += nw) {
+      const BlockList32* L = lists + S->cblk[i];
+      const uint32_t cnt = uint32_t(__builtin_amdgcn_readfirstlane(int(ld_agent(&L->count))));
+      const uint32_t tot = uint32_t(__builtin_amdgcn_readfirstlane(int(ld_agent(&L->total))));
+      band_list(cnt, tot, ld_agent(&L->keys[lane]));
+    }
+  } else {
+    for (uint32_t i0 = wave; i0 < ncb; i0 += uint32_t(nw) * BATCH) {
+      uint32_t cnt[BATCH], tot[BATCH];
+      uint64_t k[BATCH];
+#pragma unroll
+      for (int q = 0; q < BATCH; ++q) {
+        const uint32_t i = i0 + uint32_t(q * nw);
+        const BlockList32* L = lists + S->cblk[i < ncb ? i : i0];
+        cnt[q] = uint32_t(__builtin_amdgcn_readfirstlane(int(ld_agent(&L->count))));
+        tot[q] = uint32_t(__builtin_amdgcn_readfirstlane(int(ld_agent(&L->total))));
+        k[q] = ld_agent(&L->keys[lane]);
+      }
+#pragma unroll
+      for (int q = 0; q < BATCH; ++q)
+        if (i0 + uint32_t(q * nw) < ncb) band_list(cnt[q], tot[q], k[q]);
     }
   }
   __syncthreads();
