@@ -93,7 +93,7 @@ struct Layout {
   // mixed-radix pass table (radix, ns, twiddle offset per pass)
   size_t mixp;
   // radius transforms beyond the LDS
-  size_t wl, wh, z, c0, rrec, bcounters;
+  size_t wl, wh, z, c0, rrec, bcounters, twm;
   // non-uniform samples: positions (turns), quadrature weights, points, DFT partial sums
   size_t nu_t, nu_w, nu_z;
   // and the gridding non-uniform FFT: shifted weights, cell ranges, deconvolution,
@@ -125,6 +125,8 @@ struct Config {
   AdvGeom ag;
   int chunk;    // radii per two-pass chunk (of the radii with long spectra)
   int nshort;   // N > 2^14: radii whose significant spectrum fits in N2 terms (no intermediate)
+  int nmed;     // N > 2^14: radii with N2 < L <= N2 2^kBigMedShift (the shifted split's row pass)
+  int twm_size; // N > 2^14: twiddle entries of the length-(N2 2^kBigMedShift) transforms
   int prime;    // N = prime^pk (prime = 3, 5, 7; radix-prime transforms, afd_primepow.hip)
   int pk;       // 0: N = 2^logn
   bool mixed;   // N = 2^a 3^b 5^c 7^d with several primes (mixed-radix transforms, afd_mixed.hip)
@@ -234,16 +236,22 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     if (cfg->big) {
       cfg->geom = FftGeom{0, 0, 0, false, 0};
       cfg->bg = big_geom(logn, cfg->fp64);
-      // only the radii with long spectra go through the intermediate, in chunks
+      // only the radii with long spectra go through the intermediate, in
+      // chunks; those of medium length run in the shifted split's row pass
       cfg->nshort = 0;
-      for (int i = 0; i < d->m; ++i)
-        if (significant_length(d->radii[i], cfg->fp64 ? 60 : 40, d->n) <= (int64_t(1) << cfg->bg.l2)) ++cfg->nshort;
-      const size_t nlong = size_t(d->m - cfg->nshort);
+      cfg->nmed = 0;
+      for (int i = 0; i < d->m; ++i) {
+        const int64_t L = significant_length(d->radii[i], cfg->fp64 ? 60 : 40, d->n);
+        if (L <= (int64_t(1) << cfg->bg.l2)) ++cfg->nshort;
+        else if (L <= (int64_t(1) << (cfg->bg.l2 + kBigMedShift))) ++cfg->nmed;
+      }
+      cfg->twm_size = fft_geom(cfg->bg.l2 + kBigMedShift, cfg->fp64).twsize;
+      const size_t nlong = size_t(d->m - cfg->nshort - cfg->nmed);
       const size_t per_radius = size_t(d->n) * (cfg->fp64 ? 16 : 8);
       const size_t fit = kBigChunkBytes / per_radius;
       cfg->chunk = nlong == 0 ? 0 : int(fit < 1 ? 1 : fit > nlong ? nlong : fit);
       cfg->rpb = 1;
-      cfg->nblocks = d->m * cfg->bg.g;  // records of every radius of a step
+      cfg->nblocks = d->m * cfg->bg.gstride;  // record slots of every radius of a step
     } else if (cfg->pk) {
       // one radius per workgroup; the inverse and forward transforms share
       // the twiddle table
@@ -315,7 +323,8 @@ Layout layout_of(const Config& c) {
   L.wl = take(c.big ? 2 * real * (size_t(1) << c.bg.sw) : 0);
   L.wh = take(c.big ? 2 * real * (size_t(1) << (c.logn - c.bg.sw)) : 0);
   L.z = take(c.big ? 2 * real * size_t(c.chunk) * size_t(c.N) : 0);
-  L.c0 = take(c.big ? 2 * real * (size_t(1) << c.bg.l2) * B : 0);
+  L.c0 = take(c.big ? 2 * real * (size_t(1) << (c.bg.l2 + kBigMedShift)) * B : 0);
+  L.twm = take(c.big ? 2 * real * size_t(c.twm_size + 1) : 0);
   L.rrec = take(c.big ? (c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.M) : 0);
   L.bcounters = take(c.big ? 4 : 0);
   L.border = take(c.big ? 4 * size_t(c.M) : 0);  // radii with short spectra first
@@ -620,13 +629,25 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
   if (e == hipSuccess && c.big) e = hipMemset(p->arena + p->L.bcounters, 0, 4);
   if (c.big) {
     // launch order of the radii beyond the LDS: the short spectra (one row
-    // launch, no intermediate), then the long ones (chunks through it)
+    // launch, no intermediate), the medium ones (one row launch of the
+    // shifted split), then the long ones (chunks through the intermediate)
     std::vector<int32_t> order;
+    const int n2 = 1 << c.bg.l2, n2m = n2 << kBigMedShift;
     for (int m = 0; m < M; ++m)
-      if (lsig[m] <= (1 << c.bg.l2)) order.push_back(m);
+      if (lsig[m] <= n2) order.push_back(m);
     for (int m = 0; m < M; ++m)
-      if (lsig[m] > (1 << c.bg.l2)) order.push_back(m);
+      if (lsig[m] > n2 && lsig[m] <= n2m) order.push_back(m);
+    for (int m = 0; m < M; ++m)
+      if (lsig[m] > n2m) order.push_back(m);
     if (e == hipSuccess) e = up(p->L.border, order.data(), 4 * size_t(M));
+    std::vector<double> twm(2 * size_t(c.twm_size + 1), 0.0);
+    fft_twiddles(c.bg.l2 + kBigMedShift, c.fp64, twm.data());
+    if (c.fp64) {
+      if (e == hipSuccess) e = up(p->L.twm, twm.data(), twm.size() * 8);
+    } else {
+      std::vector<float> twm32(twm.begin(), twm.end());
+      if (e == hipSuccess) e = up(p->L.twm, twm32.data(), twm32.size() * 4);
+    }
   }
   if (e != hipSuccess) return hip_fail(e, "uploading plan tables");
   return AFD_OK;
@@ -1056,6 +1077,9 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     bp.wh = p->at<void>(p->L.wh);
     bp.tw1 = p->at<void>(p->L.twf1);
     bp.tw2 = p->at<void>(p->L.twf2);
+    bp.tw2m = p->at<void>(p->L.twm);
+    bp.gstride = c.bg.gstride;
+    bp.med = 1;
     bp.z = p->at<void>(p->L.z);
     bp.M = c.M;
     bp.m0 = 0;
@@ -1135,11 +1159,13 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
         bool first = true;
         for (int m0 = 0; m0 < c.M;) {
           const bool shorts = m0 < c.nshort;
-          const int nr = shorts ? c.nshort : (c.M - m0 < p->chunk ? c.M - m0 : p->chunk);
+          const bool meds = !shorts && m0 < c.nshort + c.nmed;
+          const int nr = shorts ? c.nshort : meds ? c.nmed : (c.M - m0 < p->chunk ? c.M - m0 : p->chunk);
           bp.m0 = m0;
           hipEvent_t r0, r1;
           HIPCHK(tm.pair(kTimeRows, &r0, &r1), "event");
-          HIPCHK(launch_big(c.logn, c.fp64, bp, nr, !shorts, s, first ? e0 : nullptr, nullptr, r0, r1), "k_big");
+          HIPCHK(launch_big(c.logn, c.fp64, bp, nr, !shorts && !meds, meds, s, first ? e0 : nullptr, nullptr, r0, r1),
+                 "k_big");
           first = false;
           m0 += nr;
         }

@@ -34,9 +34,11 @@
 
 namespace afd {
 
-template <typename T, int LOGN>
+// DL > 0: the split N1 = 2^(LOGN/2 - DL), N2 = 2^(LOGN - LOGN/2 + DL) of the
+// row-only pass for radii of medium spectrum length (see k_big_rows).
+template <typename T, int LOGN, int DL = 0>
 struct Big {
-  static constexpr int L1 = LOGN / 2, L2 = LOGN - L1;
+  static constexpr int L1 = LOGN / 2 - DL, L2 = LOGN - L1;
   static constexpr int N = 1 << LOGN, N1 = 1 << L1, N2 = 1 << L2;
   static constexpr int E1 = pickE<T, L1>(), E2 = pickE<T, L2>();
   static constexpr int TPR1 = N1 / E1, TPR2 = N2 / E2;
@@ -148,15 +150,18 @@ __device__ __forceinline__ Cx<T> big_twiddle(const BigParams& p, uint32_t e) {
 // o(u, r), so the twiddle is the thread's e^{2 pi i j1 (t / ns(P))/N} times a
 // wave-uniform e^{2 pi i j1 o/N}, and the spectrum comes from its
 // natural-order copy: every load is contiguous or uniform across the wave.
-template <typename T, int LOGN, int P, int E>
+template <typename T, int LOGN, int P, int E, int DL = 0>
 __device__ __forceinline__ void deep_row_inputs(Cx<T> (&v)[E], int t, int j1, int L, const BigParams& p, int m) {
-  using B = Big<T, LOGN>;
+  using B = Big<T, LOGN, DL>;
+  using B0 = Big<T, LOGN>;
   using S = Shape<B::L2, B::E2>;
   static_assert(E == B::E2, "row transform values per thread");
   constexpr int R = S::radix(P), NS = S::ns(P), J = B::E2 / R, D = B::N2 / (R * NS);
   static_assert(S::TPR % NS == 0, "the lane part of l2 separates");
   const Cx<T>* __restrict__ c0 = reinterpret_cast<const Cx<T>*>(p.c0);
-  const T* __restrict__ pb = reinterpret_cast<const T*>(p.pb) + size_t(m) * B::N2;
+  // r^l2 from the tables of the base split: r^(l2 mod N2) r^(N2 (l2 / N2))
+  const T* __restrict__ pb = reinterpret_cast<const T*>(p.pb) + size_t(m) * B0::N2;
+  const T* __restrict__ pa = reinterpret_cast<const T*>(p.pa) + size_t(m) * B0::N1;
   const int base = t / NS;
   const Cx<T> wa = big_twiddle<T, LOGN>(p, uint32_t(j1) * uint32_t(base));
 #pragma unroll
@@ -168,7 +173,11 @@ __device__ __forceinline__ void deep_row_inputs(Cx<T> (&v)[E], int t, int j1, in
       v[u + r * J] = {T(0), T(0)};
       if (l2 < L) {
         Cx<T> w = cmul(wa, big_twiddle<T, LOGN>(p, uint32_t(j1) * uint32_t(o)));
-        const T rl = pb[l2];
+        T rl;
+        if constexpr (DL == 0)
+          rl = pb[l2];
+        else
+          rl = pb[l2 & (B0::N2 - 1)] * pa[l2 >> B0::L2];
         w = {w.x * rl, w.y * rl};
         v[u + r * J] = cmul(c0[l2], w);
       }
@@ -176,10 +185,14 @@ __device__ __forceinline__ void deep_row_inputs(Cx<T> (&v)[E], int t, int j1, in
   }
 }
 
-template <typename T, int LOGN, bool LIST>
-__global__ __launch_bounds__((Big<T, LOGN>::THR_B)) __attribute__((amdgpu_waves_per_eu(Big<T, LOGN>::WPE_B)))
-void k_big_rows(BigParams p) {
-  using B = Big<T, LOGN>;
+// DL > 0: the row-only pass of the radii of medium spectrum length
+// (N2 < L <= N2 2^DL of the base split): with the split shifted by DL their
+// spectrum fits the longer rows, which are formed from the spectrum itself
+// as the short radii's are, and no column pass or intermediate is needed.
+template <typename T, int LOGN, bool LIST, int DL = 0>
+__global__ __launch_bounds__((Big<T, LOGN, DL>::THR_B))
+__attribute__((amdgpu_waves_per_eu(Big<T, LOGN, DL>::WPE_B))) void k_big_rows(BigParams p) {
+  using B = Big<T, LOGN, DL>;
   extern __shared__ __align__(16) unsigned char smem[];
   const int ri = threadIdx.x / B::TPR2, t0 = threadIdx.x - ri * B::TPR2;
   const int ml = blockIdx.y, m = p.border[p.m0 + ml];
@@ -187,10 +200,10 @@ void k_big_rows(BigParams p) {
   using S2 = Shape<B::L2, B::E2>;
   constexpr bool SPLIT = sizeof(T) == 8;
   unsigned char* region = smem + size_t(ri) * B::region_b;
-  const Cx<T>* tw2 = reinterpret_cast<const Cx<T>*>(p.tw2);
+  const Cx<T>* tw2 = reinterpret_cast<const Cx<T>*>(DL == 0 ? p.tw2 : p.tw2m);
   const int L = p.lsig[m];
   const T sc = reinterpret_cast<const T*>(p.scale)[m];  // loaded before the transform's barriers
-  const int rec = m * B::G + int(blockIdx.x);
+  const int rec = m * p.gstride + int(blockIdx.x);
   Best run{-1.0, -1.0, 0.0, 0.0, 0xffffffffu};  // double precision: this thread's best over its rows
 #pragma unroll 1
   for (int k = 0; k < B::RPT; ++k) {
@@ -205,24 +218,39 @@ void k_big_rows(BigParams p) {
     // the row's uniform twiddles come through scalar loads
     if constexpr (B::TPR2 % 64 == 0) j1 = __builtin_amdgcn_readfirstlane(j1);
     Cx<T> v[B::E2];
-    if (L > B::N2) {
-      const Cx<T>* __restrict__ row = reinterpret_cast<const Cx<T>*>(p.z) + size_t(ml) * B::N + size_t(j1) * B::N2;
+    if constexpr (DL == 0) {
+      if (L > B::N2) {
+        const Cx<T>* __restrict__ row = reinterpret_cast<const Cx<T>*>(p.z) + size_t(ml) * B::N + size_t(j1) * B::N2;
 #pragma unroll
-      for (int i = 0; i < B::E2; ++i) v[i] = row[t + B::TPR2 * i];
-      fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
-    } else if (S2::NP >= 3 && L <= B::N2 / S2::ns(2)) {  // uniform: one radius per workgroup
-      if constexpr (S2::NP >= 3) {
-        deep_row_inputs<T, LOGN, 2>(v, t, j1, L, p, m);
-        fft_regs<T, B::L2, B::E2, +1, SPLIT, 2, 2, true>(v, t, region, tw2);
-      }
-    } else if (S2::NP >= 2 && L <= B::N2 / S2::radix(0)) {
-      if constexpr (S2::NP >= 2) {
-        deep_row_inputs<T, LOGN, 1>(v, t, j1, L, p, m);
-        fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1, true>(v, t, region, tw2);
+        for (int i = 0; i < B::E2; ++i) v[i] = row[t + B::TPR2 * i];
+        fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
+      } else if (S2::NP >= 3 && L <= B::N2 / S2::ns(2)) {  // uniform: one radius per workgroup
+        if constexpr (S2::NP >= 3) {
+          deep_row_inputs<T, LOGN, 2>(v, t, j1, L, p, m);
+          fft_regs<T, B::L2, B::E2, +1, SPLIT, 2, 2, true>(v, t, region, tw2);
+        }
+      } else if (S2::NP >= 2 && L <= B::N2 / S2::radix(0)) {
+        if constexpr (S2::NP >= 2) {
+          deep_row_inputs<T, LOGN, 1>(v, t, j1, L, p, m);
+          fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1, true>(v, t, region, tw2);
+        }
+      } else {
+        deep_row_inputs<T, LOGN, 0>(v, t, j1, L, p, m);
+        fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
       }
     } else {
-      deep_row_inputs<T, LOGN, 0>(v, t, j1, L, p, m);
-      fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, true>(v, t, region, tw2);
+      // L <= N2 (the launch holds medium radii only); rows longer than a
+      // wave synchronise the workgroup
+      constexpr bool WAVE = 64 % B::TPR2 == 0;
+      if (S2::NP >= 2 && L <= B::N2 / S2::radix(0)) {
+        if constexpr (S2::NP >= 2) {
+          deep_row_inputs<T, LOGN, 1, B::E2, DL>(v, t, j1, L, p, m);
+          fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1, WAVE>(v, t, region, tw2);
+        }
+      } else {
+        deep_row_inputs<T, LOGN, 0, B::E2, DL>(v, t, j1, L, p, m);
+        fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, WAVE>(v, t, region, tw2);
+      }
     }
 
     // register q of thread t holds j2 = t + TPR2 bitrev(q): flat index m N + j1 + N1 j2
@@ -270,11 +298,14 @@ __global__ __launch_bounds__(256) void k_big_merge(BigParams p) {
   __shared__ int s_last;
   MergeScratch* Sm = reinterpret_cast<MergeScratch*>(smem);
   const int m = blockIdx.x;
+  // a radius of medium spectrum length ran in the shifted split's row pass
+  const int L = p.lsig[m];
+  const int g = (p.med && L > B::N2 && L <= (B::N2 << kBigMedShift)) ? Big<T, LOGN, kBigMedShift>::G : B::G;
   if constexpr (LIST) {
-    merge_list_group(reinterpret_cast<const BlockList32*>(p.blocks) + size_t(m) * B::G, B::G, p.tau_band,
+    merge_list_group(reinterpret_cast<const BlockList32*>(p.blocks) + size_t(m) * p.gstride, g, p.tau_band,
                      reinterpret_cast<BlockList32*>(p.rrec) + m, p.heads + m, Sm);
   } else {
-    merge_best_group(reinterpret_cast<const BlockBest64*>(p.blocks) + size_t(m) * B::G, B::G,
+    merge_best_group(reinterpret_cast<const BlockBest64*>(p.blocks) + size_t(m) * p.gstride, g,
                      reinterpret_cast<BlockBest64*>(p.rrec) + m, Sm);
   }
   if (!last_arrival(p.counter_g, gridDim.x, &s_last)) return;
@@ -301,6 +332,11 @@ static BigGeom big_geom_of() {
   g.rb = B::RB;
   g.thr_b = B::THR_B;
   g.g = B::G;
+  using BM = Big<T, LOGN, kBigMedShift>;
+  g.g_med = BM::G;
+  g.thr_b_med = BM::THR_B;
+  g.lds_b_med = BM::lds_b;
+  g.gstride = BM::G > B::G ? BM::G : B::G;
   g.lds_a = B::lds_a;
   g.lds_b = B::lds_b;
   g.rec_bytes = sizeof(T) == 4 ? sizeof(BlockList32) : sizeof(BlockBest64);
@@ -326,6 +362,10 @@ hipError_t setup_big_attributes() {
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_cols<double, L>));       \
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<float, L, true>));  \
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<double, L, false>));      \
+  if (e == hipSuccess)                                                                                      \
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<float, L, true, kBigMedShift>));       \
+  if (e == hipSuccess)                                                                                      \
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<double, L, false, kBigMedShift>));     \
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_merge<float, L, true>));      \
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_merge<double, L, false>));
   AFD_BIG_LOGN_CASES(X)
@@ -334,10 +374,16 @@ hipError_t setup_big_attributes() {
 }
 
 template <typename T, int LOGN>
-static hipError_t launch_big_t(const BigParams& p, int nr, bool cols, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                               hipEvent_t r0, hipEvent_t r1) {
+static hipError_t launch_big_t(const BigParams& p, int nr, bool cols, bool med, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1, hipEvent_t r0, hipEvent_t r1) {
   using B = Big<T, LOGN>;
-  if (nr < 1 || p.m0 < 0 || p.m0 + nr > p.M) return hipErrorInvalidValue;
+  if (nr < 1 || p.m0 < 0 || p.m0 + nr > p.M || (cols && med)) return hipErrorInvalidValue;
+  if (med) {
+    using BM = Big<T, LOGN, kBigMedShift>;
+    launch_ev(k_big_rows<T, LOGN, sizeof(T) == 4, kBigMedShift>, dim3(BM::G, nr), dim3(BM::THR_B),
+              uint32_t(BM::lds_b), s, r0 ? r0 : e0, r1 ? r1 : e1, p);
+    return hipGetLastError();
+  }
   if (cols) {
     launch_ev(k_big_cols<T, LOGN>, dim3(B::N2 / B::CA, nr), dim3(B::THR_A), uint32_t(B::lds_a), s, e0, nullptr, p);
     const hipError_t e = hipGetLastError();
@@ -368,13 +414,13 @@ hipError_t launch_big_merge(int logn, bool fp64, const BigParams& p, hipStream_t
   }
 }
 
-hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, bool cols, hipStream_t s, hipEvent_t e0,
-                      hipEvent_t e1, hipEvent_t r0, hipEvent_t r1) {
+hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, bool cols, bool med, hipStream_t s,
+                      hipEvent_t e0, hipEvent_t e1, hipEvent_t r0, hipEvent_t r1) {
   switch (logn) {
 #define X(L) \
   case L:    \
-    return fp64 ? launch_big_t<double, L>(p, nr, cols, s, e0, e1, r0, r1)                         \
-                : launch_big_t<float, L>(p, nr, cols, s, e0, e1, r0, r1);
+    return fp64 ? launch_big_t<double, L>(p, nr, cols, med, s, e0, e1, r0, r1)                    \
+                : launch_big_t<float, L>(p, nr, cols, med, s, e0, e1, r0, r1);
     AFD_BIG_LOGN_CASES(X)
 #undef X
     default:
