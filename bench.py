@@ -146,13 +146,13 @@ CUS, CLOCK_HZ = 256, 2.4e9
 
 
 def two_pass_radii(radii, n: int, prec: str) -> int:
-    """Radii whose significant spectrum length exceeds 4 N2, N2 = 2^(K - K//2):
+    """Radii whose significant spectrum length exceeds 16 N2, N2 = 2^(K - K//2):
     only those go through the HBM intermediate (terms r^l below 2^-40 single /
     2^-60 double precision of the largest, summed, are dropped; lengths up to
-    4 N2 run in a row pass of the split shifted by a factor 4)."""
+    16 N2 run in row passes of the split shifted by a factor 4 or 16)."""
     bits = 60 if prec == "fp64" else 40
     k = int(math.log2(n))
-    n2 = 4 << (k - k // 2)
+    n2 = 16 << (k - k // 2)
     count = 0
     for r in radii:
         r = float(r)

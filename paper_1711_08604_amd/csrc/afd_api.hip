@@ -93,7 +93,7 @@ struct Layout {
   // mixed-radix pass table (radix, ns, twiddle offset per pass)
   size_t mixp;
   // radius transforms beyond the LDS
-  size_t wl, wh, z, c0, rrec, bcounters, twm;
+  size_t wl, wh, z, c0, rrec, bcounters, twm, twm2;
   // non-uniform samples: positions (turns), quadrature weights, points, DFT partial sums
   size_t nu_t, nu_w, nu_z;
   // and the gridding non-uniform FFT: shifted weights, cell ranges, deconvolution,
@@ -125,8 +125,8 @@ struct Config {
   AdvGeom ag;
   int chunk;    // radii per two-pass chunk (of the radii with long spectra)
   int nshort;   // N > 2^14: radii whose significant spectrum fits in N2 terms (no intermediate)
-  int nmed;     // N > 2^14: radii with N2 < L <= N2 2^kBigMedShift (the shifted split's row pass)
-  int twm_size; // N > 2^14: twiddle entries of the length-(N2 2^kBigMedShift) transforms
+  int nmed[2];  // N > 2^14: radii with N2 < L <= 4 N2, 4 N2 < L <= 16 N2 (the shifted splits' row passes)
+  int twm_size[2];  // N > 2^14: twiddle entries of the length-4 N2 and -16 N2 transforms
   int prime;    // N = prime^pk (prime = 3, 5, 7; radix-prime transforms, afd_primepow.hip)
   int pk;       // 0: N = 2^logn
   bool mixed;   // N = 2^a 3^b 5^c 7^d with several primes (mixed-radix transforms, afd_mixed.hip)
@@ -239,14 +239,16 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
       // only the radii with long spectra go through the intermediate, in
       // chunks; those of medium length run in the shifted split's row pass
       cfg->nshort = 0;
-      cfg->nmed = 0;
+      cfg->nmed[0] = cfg->nmed[1] = 0;
       for (int i = 0; i < d->m; ++i) {
         const int64_t L = significant_length(d->radii[i], cfg->fp64 ? 60 : 40, d->n);
         if (L <= (int64_t(1) << cfg->bg.l2)) ++cfg->nshort;
-        else if (L <= (int64_t(1) << (cfg->bg.l2 + kBigMedShift))) ++cfg->nmed;
+        else if (L <= (int64_t(1) << (cfg->bg.l2 + kBigMedShift))) ++cfg->nmed[0];
+        else if (L <= (int64_t(1) << (cfg->bg.l2 + kBigMedShift2))) ++cfg->nmed[1];
       }
-      cfg->twm_size = fft_geom(cfg->bg.l2 + kBigMedShift, cfg->fp64).twsize;
-      const size_t nlong = size_t(d->m - cfg->nshort - cfg->nmed);
+      cfg->twm_size[0] = fft_geom(cfg->bg.l2 + kBigMedShift, cfg->fp64).twsize;
+      cfg->twm_size[1] = fft_geom(cfg->bg.l2 + kBigMedShift2, cfg->fp64).twsize;
+      const size_t nlong = size_t(d->m - cfg->nshort - cfg->nmed[0] - cfg->nmed[1]);
       const size_t per_radius = size_t(d->n) * (cfg->fp64 ? 16 : 8);
       const size_t fit = kBigChunkBytes / per_radius;
       cfg->chunk = nlong == 0 ? 0 : int(fit < 1 ? 1 : fit > nlong ? nlong : fit);
@@ -323,8 +325,9 @@ Layout layout_of(const Config& c) {
   L.wl = take(c.big ? 2 * real * (size_t(1) << c.bg.sw) : 0);
   L.wh = take(c.big ? 2 * real * (size_t(1) << (c.logn - c.bg.sw)) : 0);
   L.z = take(c.big ? 2 * real * size_t(c.chunk) * size_t(c.N) : 0);
-  L.c0 = take(c.big ? 2 * real * (size_t(1) << (c.bg.l2 + kBigMedShift)) * B : 0);
-  L.twm = take(c.big ? 2 * real * size_t(c.twm_size + 1) : 0);
+  L.c0 = take(c.big ? 2 * real * (size_t(1) << (c.bg.l2 + kBigMedShift2)) * B : 0);
+  L.twm = take(c.big ? 2 * real * size_t(c.twm_size[0] + 1) : 0);
+  L.twm2 = take(c.big ? 2 * real * size_t(c.twm_size[1] + 1) : 0);
   L.rrec = take(c.big ? (c.fp64 ? sizeof(BlockBest64) : sizeof(BlockList32)) * size_t(c.M) : 0);
   L.bcounters = take(c.big ? 4 : 0);
   L.border = take(c.big ? 4 * size_t(c.M) : 0);  // radii with short spectra first
@@ -632,21 +635,26 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
     // launch, no intermediate), the medium ones (one row launch of the
     // shifted split), then the long ones (chunks through the intermediate)
     std::vector<int32_t> order;
-    const int n2 = 1 << c.bg.l2, n2m = n2 << kBigMedShift;
+    const int n2 = 1 << c.bg.l2, n2m = n2 << kBigMedShift, n2m2 = n2 << kBigMedShift2;
     for (int m = 0; m < M; ++m)
       if (lsig[m] <= n2) order.push_back(m);
     for (int m = 0; m < M; ++m)
       if (lsig[m] > n2 && lsig[m] <= n2m) order.push_back(m);
     for (int m = 0; m < M; ++m)
-      if (lsig[m] > n2m) order.push_back(m);
+      if (lsig[m] > n2m && lsig[m] <= n2m2) order.push_back(m);
+    for (int m = 0; m < M; ++m)
+      if (lsig[m] > n2m2) order.push_back(m);
     if (e == hipSuccess) e = up(p->L.border, order.data(), 4 * size_t(M));
-    std::vector<double> twm(2 * size_t(c.twm_size + 1), 0.0);
-    fft_twiddles(c.bg.l2 + kBigMedShift, c.fp64, twm.data());
-    if (c.fp64) {
-      if (e == hipSuccess) e = up(p->L.twm, twm.data(), twm.size() * 8);
-    } else {
-      std::vector<float> twm32(twm.begin(), twm.end());
-      if (e == hipSuccess) e = up(p->L.twm, twm32.data(), twm32.size() * 4);
+    for (int k = 0; k < 2; ++k) {
+      std::vector<double> twm(2 * size_t(c.twm_size[k] + 1), 0.0);
+      fft_twiddles(c.bg.l2 + (k == 0 ? kBigMedShift : kBigMedShift2), c.fp64, twm.data());
+      const size_t at = k == 0 ? p->L.twm : p->L.twm2;
+      if (c.fp64) {
+        if (e == hipSuccess) e = up(at, twm.data(), twm.size() * 8);
+      } else {
+        std::vector<float> twm32(twm.begin(), twm.end());
+        if (e == hipSuccess) e = up(at, twm32.data(), twm32.size() * 4);
+      }
     }
   }
   if (e != hipSuccess) return hip_fail(e, "uploading plan tables");
@@ -1077,7 +1085,8 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     bp.wh = p->at<void>(p->L.wh);
     bp.tw1 = p->at<void>(p->L.twf1);
     bp.tw2 = p->at<void>(p->L.twf2);
-    bp.tw2m = p->at<void>(p->L.twm);
+    bp.tw2m[0] = p->at<void>(p->L.twm);
+    bp.tw2m[1] = p->at<void>(p->L.twm2);
     bp.gstride = c.bg.gstride;
     bp.med = 1;
     bp.z = p->at<void>(p->L.z);
@@ -1158,14 +1167,16 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
         // chunks through the intermediate (launch order in p->L.border)
         bool first = true;
         for (int m0 = 0; m0 < c.M;) {
-          const bool shorts = m0 < c.nshort;
-          const bool meds = !shorts && m0 < c.nshort + c.nmed;
-          const int nr = shorts ? c.nshort : meds ? c.nmed : (c.M - m0 < p->chunk ? c.M - m0 : p->chunk);
+          // launch positions: short radii, the two medium classes, then chunks of long ones
+          const int b1 = c.nshort, b2 = b1 + c.nmed[0], b3 = b2 + c.nmed[1];
+          const int med = m0 < b1 ? 0 : m0 < b2 ? 1 : m0 < b3 ? 2 : 0;
+          const bool longs = m0 >= b3;
+          const int nr = m0 < b1 ? b1 - m0 : m0 < b2 ? b2 - m0 : m0 < b3 ? b3 - m0
+                                                                       : (c.M - m0 < p->chunk ? c.M - m0 : p->chunk);
           bp.m0 = m0;
           hipEvent_t r0, r1;
           HIPCHK(tm.pair(kTimeRows, &r0, &r1), "event");
-          HIPCHK(launch_big(c.logn, c.fp64, bp, nr, !shorts && !meds, meds, s, first ? e0 : nullptr, nullptr, r0, r1),
-                 "k_big");
+          HIPCHK(launch_big(c.logn, c.fp64, bp, nr, longs, med, s, first ? e0 : nullptr, nullptr, r0, r1), "k_big");
           first = false;
           m0 += nr;
         }

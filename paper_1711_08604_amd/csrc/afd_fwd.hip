@@ -115,10 +115,10 @@ __global__ __launch_bounds__((rows_threads<T, LOGN>())) void k_fwd_rows(const Cx
     const int k1 = out_bin<P::L1, E1>(t, p);
     if constexpr (COLS) {
       c[size_t(k2) * P::N1 + k1] = v[p];
-      // with c0, the bins below N2 2^kBigMedShift also in natural order
-      // (c_{k2 + N2 k1}: k1 < 2^kBigMedShift)
-      if (c0 != nullptr && k1 < (1 << kBigMedShift))
-        c0[(size_t(P::N2) << kBigMedShift) * blockIdx.y + size_t(k1) * P::N2 + k2] = v[p];
+      // with c0, the bins below N2 2^kBigMedShift2 also in natural order
+      // (c_{k2 + N2 k1}: k1 < 2^kBigMedShift2)
+      if (c0 != nullptr && k1 < (1 << kBigMedShift2))
+        c0[(size_t(P::N2) << kBigMedShift2) * blockIdx.y + size_t(k1) * P::N2 + k2] = v[p];
     } else
       c[k2 + P::N2 * k1] = v[p];
   }

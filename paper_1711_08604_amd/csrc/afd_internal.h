@@ -102,7 +102,7 @@ struct RadiusParams {
 // over chunks of radii (see afd_large.hip).
 struct BigParams {
   const void* c;      // spectrum in column order: c_{N2 l1 + l2} at [l2][l1] (T complex)
-  const void* c0;     // [N2 2^kBigMedShift] c_l for l < N2 2^kBigMedShift in natural order (T complex)
+  const void* c0;     // [N2 2^kBigMedShift2] c_l for l < N2 2^kBigMedShift2 in natural order (T complex)
   const void* pa;     // [M][N1]  r_m^(N2 l1)
   const void* pb;     // [M][N2]  r_m^l2
   const void* scale;  // [M]      sqrt(1-r^2) / (N (1 - r^N))
@@ -111,7 +111,7 @@ struct BigParams {
   const void* wh;     // e^{2 pi i h 2^sw/N}, h < N/2^sw (T complex)
   const void* tw1;    // Stockham twiddles of the length-N1 transforms
   const void* tw2;    // Stockham twiddles of the length-N2 transforms
-  const void* tw2m;   // Stockham twiddles of the length-(N2 2^kBigMedShift) transforms
+  const void* tw2m[2];  // Stockham twiddles of the length-(N2 2^kBigMedShift), (N2 2^kBigMedShift2) transforms
   void* z;            // [chunk][N1][N2] intermediate (T complex)
   const int* border;  // [M] launch order of the radii: short spectra first, then long ones
   int M;
@@ -120,7 +120,7 @@ struct BigParams {
   int recheck_k;
   void* blocks;       // [M][gstride] per-workgroup records (BlockList32 or BlockBest64)
   int gstride;        // record slots per radius (the larger record count of the two row passes)
-  int med;            // 1: radii with N2 < L <= N2 2^kBigMedShift ran in the shifted split's row pass
+  int med;            // 1: radii with N2 < L <= N2 2^kBigMedShift2 ran in the shifted splits' row passes
   void* rrec;         // [M] per-radius records (same type)
   uint64_t* heads;    // FP32: [M] head key of each per-radius record
   unsigned int* flagword;  // FP32: fallback flag of the step (zero between steps)
@@ -133,14 +133,16 @@ struct BigParams {
   double* probe_out;
 };
 
-// Radii of medium spectrum length (N2 < L <= N2 2^kBigMedShift) run in a
-// row-only pass over the split N1 / 2^kBigMedShift x N2 2^kBigMedShift.
+// Radii of medium spectrum length run in a row-only pass over a shifted
+// split: N2 < L <= 4 N2 over N1/4 x 4 N2 (kBigMedShift), 4 N2 < L <= 16 N2
+// over N1/16 x 16 N2 (kBigMedShift2).
 constexpr int kBigMedShift = 2;
+constexpr int kBigMedShift2 = 4;
 struct BigGeom {
   int l1, l2;     // N1 = 2^l1 (column transforms), N2 = 2^l2 (row transforms)
-  int g_med, thr_b_med;  // the medium radii's row pass: records per radius, threads
-  size_t lds_b_med;
-  int gstride;    // record slots per radius: max(g, g_med)
+  int g_med[2], thr_b_med[2];  // the medium radii's row passes: records per radius, threads
+  size_t lds_b_med[2];
+  int gstride;    // record slots per radius: the largest record count of the three row passes
   int sw;         // twiddle split: e = h 2^sw + low
   int ca, thr_a;  // columns and threads per column workgroup
   int rb, thr_b;  // rows and threads per row workgroup
@@ -154,8 +156,9 @@ hipError_t setup_big_attributes();
 // (with `cols`; the radii with short spectra need none), then the row pass
 // with the selection.  e0 stamps the first launch's start, e1 the row pass's
 // end; r0 / r1 stamp the row pass alone.
-// med: the row pass of the shifted split (radii of medium spectrum length; no column pass).
-hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, bool cols, bool med, hipStream_t s,
+// med (1, 2): the row pass of the split shifted by kBigMedShift, kBigMedShift2 (radii of
+// medium spectrum length; no column pass).
+hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, bool cols, int med, hipStream_t s,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, hipEvent_t r0 = nullptr,
                       hipEvent_t r1 = nullptr);
 // After the last chunk of a step: the radius records into the winner (FP64)
@@ -387,7 +390,7 @@ hipError_t launch_radius_mixed(const MixedGeom& g, const int* passes, bool fp64,
 
 // Batched launches cover `batch` signals (grid dimension y, or z for the
 // re-check); each signal's buffers follow the previous signal's.  For
-// N > 2^14, c0 (nullable) also receives the bins l < N2 2^kBigMedShift in natural order.
+// N > 2^14, c0 (nullable) also receives the bins l < N2 2^kBigMedShift2 in natural order.
 hipError_t launch_fwd(int logn, bool fp64, const void* g, const void* tw1, const void* tw2, const double* omega,
                       void* xt, void* c, int batch, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
                       void* c0 = nullptr);

@@ -58,7 +58,9 @@ struct Big {
   static constexpr int RPT = (sizeof(T) == 8 && TPR2 == 64 && N1 / (RB * 4) >= 16) ? 4 : 1;
   // waves per SIMD the row pass's register budget allows (single precision,
   // and double precision over several rows: at most 128 VGPRs)
-  static constexpr int WPE_B = (sizeof(T) == 4 || RPT > 1) ? 4 : 1;
+  // (the 16 N2-point rows of the largest shift hold one 512-thread workgroup
+  // per CU: two waves per SIMD)
+  static constexpr int WPE_B = (sizeof(T) == 4 || RPT > 1) ? (DL >= 4 ? 2 : 4) : 1;
   static constexpr int G = N1 / (RB * RPT);  // row workgroups (records) per radius
   static constexpr int SW = (LOGN + 1) / 2;
   static constexpr int LDT = CA + 1;  // row pitch of the LDS transpose (reals)
@@ -186,7 +188,7 @@ __device__ __forceinline__ void deep_row_inputs(Cx<T> (&v)[E], int t, int j1, in
 }
 
 // DL > 0: the row-only pass of the radii of medium spectrum length
-// (N2 < L <= N2 2^DL of the base split): with the split shifted by DL their
+// (L <= N2 2^DL of the base split): with the split shifted by DL their
 // spectrum fits the longer rows, which are formed from the spectrum itself
 // as the short radii's are, and no column pass or intermediate is needed.
 template <typename T, int LOGN, bool LIST, int DL = 0>
@@ -200,7 +202,7 @@ __attribute__((amdgpu_waves_per_eu(Big<T, LOGN, DL>::WPE_B))) void k_big_rows(Bi
   using S2 = Shape<B::L2, B::E2>;
   constexpr bool SPLIT = sizeof(T) == 8;
   unsigned char* region = smem + size_t(ri) * B::region_b;
-  const Cx<T>* tw2 = reinterpret_cast<const Cx<T>*>(DL == 0 ? p.tw2 : p.tw2m);
+  const Cx<T>* tw2 = reinterpret_cast<const Cx<T>*>(DL == 0 ? p.tw2 : p.tw2m[DL == kBigMedShift ? 0 : 1]);
   const int L = p.lsig[m];
   const T sc = reinterpret_cast<const T*>(p.scale)[m];  // loaded before the transform's barriers
   const int rec = m * p.gstride + int(blockIdx.x);
@@ -300,7 +302,10 @@ __global__ __launch_bounds__(256) void k_big_merge(BigParams p) {
   const int m = blockIdx.x;
   // a radius of medium spectrum length ran in the shifted split's row pass
   const int L = p.lsig[m];
-  const int g = (p.med && L > B::N2 && L <= (B::N2 << kBigMedShift)) ? Big<T, LOGN, kBigMedShift>::G : B::G;
+  const int g = !p.med || L <= B::N2               ? B::G
+                : L <= (B::N2 << kBigMedShift)  ? Big<T, LOGN, kBigMedShift>::G
+                : L <= (B::N2 << kBigMedShift2) ? Big<T, LOGN, kBigMedShift2>::G
+                                                : B::G;
   if constexpr (LIST) {
     merge_list_group(reinterpret_cast<const BlockList32*>(p.blocks) + size_t(m) * p.gstride, g, p.tau_band,
                      reinterpret_cast<BlockList32*>(p.rrec) + m, p.heads + m, Sm);
@@ -333,10 +338,16 @@ static BigGeom big_geom_of() {
   g.thr_b = B::THR_B;
   g.g = B::G;
   using BM = Big<T, LOGN, kBigMedShift>;
-  g.g_med = BM::G;
-  g.thr_b_med = BM::THR_B;
-  g.lds_b_med = BM::lds_b;
-  g.gstride = BM::G > B::G ? BM::G : B::G;
+  using BM2 = Big<T, LOGN, kBigMedShift2>;
+  g.g_med[0] = BM::G;
+  g.thr_b_med[0] = BM::THR_B;
+  g.lds_b_med[0] = BM::lds_b;
+  g.g_med[1] = BM2::G;
+  g.thr_b_med[1] = BM2::THR_B;
+  g.lds_b_med[1] = BM2::lds_b;
+  g.gstride = B::G;
+  if (BM::G > g.gstride) g.gstride = BM::G;
+  if (BM2::G > g.gstride) g.gstride = BM2::G;
   g.lds_a = B::lds_a;
   g.lds_b = B::lds_b;
   g.rec_bytes = sizeof(T) == 4 ? sizeof(BlockList32) : sizeof(BlockBest64);
@@ -366,6 +377,10 @@ hipError_t setup_big_attributes() {
     e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<float, L, true, kBigMedShift>));       \
   if (e == hipSuccess)                                                                                      \
     e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<double, L, false, kBigMedShift>));     \
+  if (e == hipSuccess)                                                                                      \
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<float, L, true, kBigMedShift2>));      \
+  if (e == hipSuccess)                                                                                      \
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_rows<double, L, false, kBigMedShift2>));    \
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_merge<float, L, true>));      \
   if (e == hipSuccess) e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_big_merge<double, L, false>));
   AFD_BIG_LOGN_CASES(X)
@@ -374,13 +389,19 @@ hipError_t setup_big_attributes() {
 }
 
 template <typename T, int LOGN>
-static hipError_t launch_big_t(const BigParams& p, int nr, bool cols, bool med, hipStream_t s, hipEvent_t e0,
+static hipError_t launch_big_t(const BigParams& p, int nr, bool cols, int med, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1, hipEvent_t r0, hipEvent_t r1) {
   using B = Big<T, LOGN>;
-  if (nr < 1 || p.m0 < 0 || p.m0 + nr > p.M || (cols && med)) return hipErrorInvalidValue;
-  if (med) {
+  if (nr < 1 || p.m0 < 0 || p.m0 + nr > p.M || (cols && med) || med < 0 || med > 2) return hipErrorInvalidValue;
+  if (med == 1) {
     using BM = Big<T, LOGN, kBigMedShift>;
     launch_ev(k_big_rows<T, LOGN, sizeof(T) == 4, kBigMedShift>, dim3(BM::G, nr), dim3(BM::THR_B),
+              uint32_t(BM::lds_b), s, r0 ? r0 : e0, r1 ? r1 : e1, p);
+    return hipGetLastError();
+  }
+  if (med == 2) {
+    using BM = Big<T, LOGN, kBigMedShift2>;
+    launch_ev(k_big_rows<T, LOGN, sizeof(T) == 4, kBigMedShift2>, dim3(BM::G, nr), dim3(BM::THR_B),
               uint32_t(BM::lds_b), s, r0 ? r0 : e0, r1 ? r1 : e1, p);
     return hipGetLastError();
   }
@@ -414,7 +435,7 @@ hipError_t launch_big_merge(int logn, bool fp64, const BigParams& p, hipStream_t
   }
 }
 
-hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, bool cols, bool med, hipStream_t s,
+hipError_t launch_big(int logn, bool fp64, const BigParams& p, int nr, bool cols, int med, hipStream_t s,
                       hipEvent_t e0, hipEvent_t e1, hipEvent_t r0, hipEvent_t r1) {
   switch (logn) {
 #define X(L) \
