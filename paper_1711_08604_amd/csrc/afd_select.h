@@ -330,21 +330,33 @@ __device__ __forceinline__ void merge_list_group(const BlockList32* __restrict__
   }
   __syncthreads();
   const uint64_t hcut = S->hcut;
-  // one wave per member list that reaches the band
-  for (int i = wave; i < n; i += nw) {
-    const BlockList32* B = L + i;
-    const uint32_t cnt = S->cblk[i];
-    if (cnt == 0) continue;  // uniform over the wave
-    const uint64_t k = lane < int(cnt) ? ld_agent(&B->keys[lane]) : 0;
-    const bool inband = lane < int(cnt) && key_p(k) >= theta;
-    const uint64_t bm = __ballot(inband);
-    if (lane == 0 && bm) atomicAdd(&S->sband, uint32_t(__popcll(bm)));
-    wave_append(inband && k >= hcut, k, &S->scount, S->buf, uint32_t(kSelCap));
-    // a member list cut inside the band: count the points it could not hold
-    const uint64_t last = lane_u64(k, __builtin_amdgcn_readfirstlane(int(cnt) - 1));
-    if (lane == 0 && key_p(last) >= theta) {
-      const uint32_t tot = ld_agent(&B->total);
-      if (tot > cnt) atomicAdd(&S->stotal, tot - cnt);
+  // one wave per member list that reaches the band, the keys (and totals)
+  // of kGroupBatch consecutive lists per round trip: where most members reach
+  // the band (a flat radius) one list per round trip held every wave for n/nw
+  // dependent loads
+  constexpr int kGroupBatch = 8;
+  for (int i0 = wave * kGroupBatch; i0 < n; i0 += nw * kGroupBatch) {
+    uint64_t k[kGroupBatch];
+    uint32_t tot[kGroupBatch];
+#pragma unroll
+    for (int q = 0; q < kGroupBatch; ++q) {
+      const int i = i0 + q;
+      const uint32_t cnt = i < n ? S->cblk[i] : 0u;
+      k[q] = cnt > 0 && lane < int(cnt) ? ld_agent(&L[i].keys[lane]) : 0;
+      tot[q] = cnt > 0 && lane == 0 ? ld_agent(&L[i].total) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kGroupBatch; ++q) {
+      const int i = i0 + q;
+      const uint32_t cnt = i < n ? S->cblk[i] : 0u;
+      if (cnt == 0) continue;  // uniform over the wave
+      const bool inband = lane < int(cnt) && key_p(k[q]) >= theta;
+      const uint64_t bm = __ballot(inband);
+      if (lane == 0 && bm) atomicAdd(&S->sband, uint32_t(__popcll(bm)));
+      wave_append(inband && k[q] >= hcut, k[q], &S->scount, S->buf, uint32_t(kSelCap));
+      // a member list cut inside the band: count the points it could not hold
+      const uint64_t last = lane_u64(k[q], __builtin_amdgcn_readfirstlane(int(cnt) - 1));
+      if (lane == 0 && key_p(last) >= theta && tot[q] > cnt) atomicAdd(&S->stotal, tot[q] - cnt);
     }
   }
   __syncthreads();
