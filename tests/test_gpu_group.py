@@ -25,12 +25,14 @@ def _dev(x):
 
 
 def _members(stream):
-    """Plans of N = 256, 1024 (FP32), 4096, 729 (= 3^6), 16384 (FP32), 2^15, a
-    batch of 3 x 2048, and non-uniform samples on a 1024-angle grid."""
+    """Plans of N = 256, 1024 (FP32), 4096, 729 (= 3^6), 16384 (FP32), 2^15,
+    1000 and 12288 (mixed radix; FP32), 3125 (= 5^5, FP32), a batch of
+    3 x 2048, and non-uniform samples on a 1024-angle grid."""
     out = []
     for k, (n, m, steps, prec) in enumerate(((256, 41, 6, "fp64"), (1024, 100, 8, "fp32"), (4096, 64, 5, "fp64"),
                                               (729, 60, 6, "fp32"), (16384, 200, 4, "fp32"),
-                                              (1 << 15, 40, 3, "fp64"))):
+                                              (1 << 15, 40, 3, "fp64"), (1000, 60, 5, "fp64"),
+                                              (12288, 40, 3, "fp32"), (3125, 50, 4, "fp32"))):
         g, radii, _ = W.shaped_like_config2(n, m, steps, item=500 + k)
         out.append((Plan(n, radii, precision=prec, stream=stream), g, steps, radii))
     sigs = np.stack([W.shaped_like_config2(2048, 33, 4, item=520 + i)[0] for i in range(3)])

@@ -26,6 +26,7 @@ def _dev(x):
     (4096, 300, "fp32", 2),      # the tail only
     (1 << 16, 300, "fp64", 3),   # radii per two-pass chunk: allocated, half, quarter
     (729, 60, "fp64", 1),        # nothing to choose
+    (1000, 60, "fp32", 1),       # nor for a mixed radix
 ], ids=str)
 def test_tune_keeps_results(n, m, prec, cands):
     g, radii, _ = W.shaped_like_config2(n, m, 6, item=600)
