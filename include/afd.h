@@ -96,7 +96,8 @@ typedef struct {
      quadrature sum_n w_n G(z_n) conj(F(z_n)) with w_n = sample_weights[n] (host pointer,
      finite; NULL: the periodic trapezoidal weights (t_{n+1} - t_{n-1})/2).  The selection grid
      stays a_{m,j} = r_m e^{2 pi i j/N}; the DFT of the samples becomes the non-uniform DFT
-     c_l = sum_n w_n G(z_n) e^{-2 pi i l t_n}, l < N.  Needs N = 2^K <= 2^14, batch 1,
+     c_l = sum_n w_n G(z_n) e^{-2 pi i l t_n}, l < N.  A batch shares the positions and
+     weights (each signal holds `samples` values).  Needs N = 2^K <= 2^14,
      1 <= samples <= 2^16 and radii whose kernel series r^l is negligible from l = N on (the
      significant length of the uniform path's radius tables, at most N); else
      AFD_E_UNSUPPORTED.  The remainder then has `samples` values; afd_reconstruct gives the

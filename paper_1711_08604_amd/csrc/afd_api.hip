@@ -192,7 +192,6 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     }
     if (logn < 1 || logn > kMaxLdsLogN)
       return fail(AFD_E_UNSUPPORTED, "non-uniform samples need a grid of N = 2^K <= 2^14 angles");
-    if (batch > 1) return fail(AFD_E_UNSUPPORTED, "non-uniform samples need batch = 1");
     const int bits = d->precision == AFD_FP64 ? 60 : 40;
     for (int i = 0; i < d->m; ++i)
       if (significant_length(d->radii[i], bits, int64_t(1) << 40) > d->n)
@@ -351,9 +350,9 @@ Layout layout_of(const Config& c) {
   L.nu_ws = take(16 * size_t(c.nu ? c.ns : 0));
   L.nu_rng = take(16 * G);
   L.nu_dinv = take(c.nu ? 8 * size_t(c.N) : 0);
-  L.nu_b = take(16 * G);
-  L.nu_B = take(16 * G);
-  L.nu_xt = take(16 * G);
+  L.nu_b = take(16 * G * B);
+  L.nu_B = take(16 * G * B);
+  L.nu_xt = take(16 * G * B);
   L.nu_tw1 = take(c.nu ? 16 * size_t(gp.tw1_size + 1) : 0);
   L.nu_tw2 = take(c.nu ? 16 * size_t(gp.tw2_size + 1) : 0);
   L.nu_omega = take(16 * G);
@@ -1037,7 +1036,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   const RecheckSamples smp = samples_of(p);
   const double* nu_w = c.nu ? p->at<double>(p->L.nu_w) : nullptr;
   if (c.nu)
-    HIPCHK(launch_nu_prepare(g64, nu_w, NS, epart, nonfinite, counters + 3 * B, rec, s), "k_nu_prepare");
+    HIPCHK(launch_nu_prepare(g64, nu_w, NS, epart, nonfinite, counters + 3 * B, rec, B, s), "k_nu_prepare");
   else
     HIPCHK(launch_prepare(g64, g32, N, epart, nonfinite, counters + 3 * B, rec, B, s), "k_prepare");
 
@@ -1145,7 +1144,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
       HIPCHK(tm.pair(kTimeFft, &e0, &e1), "event");
       const void* gin = c.fp64 ? static_cast<const void*>(g64) : static_cast<const void*>(g32);
       if (c.nu)
-        HIPCHK(launch_nu_fourier(g64, nu_tables(p), c.logn, c.fp64, cspec, s, e0, e1), "non-uniform DFT");
+        HIPCHK(launch_nu_fourier(g64, nu_tables(p), c.logn, c.fp64, cspec, NS, B, s, e0, e1), "non-uniform DFT");
       else if (c.mixed)
         HIPCHK(launch_fwd_mixed(c.mg, p->at<int>(p->L.mixp), c.fp64, gin, p->at<void>(p->L.tw), cspec, B, s, e0, e1),
                "forward DFT");
@@ -1200,7 +1199,7 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
     HIPCHK(tm.pair(kTimeUpdate, &u0, &u1), "event");
     upd.step = k;
     if (c.nu)
-      HIPCHK(launch_nu_update(g64, nu_w, smp.z, NS, upd, s, u0, u1), "k_nu_update");
+      HIPCHK(launch_nu_update(g64, nu_w, smp.z, NS, upd, B, s, u0, u1), "k_nu_update");
     else
       HIPCHK(launch_update(g64, g32, upd, B, s, u0, u1), "k_update");
   }

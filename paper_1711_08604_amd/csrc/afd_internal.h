@@ -428,10 +428,11 @@ hipError_t launch_recheck(const CandList* cand, const double* g, const double* o
 hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, int batch, hipStream_t s,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
-// Non-uniform samples (afd_nonuni.hip), one signal: ns samples g (interleaved
-// complex), positions `turns`, points z = e^{2 pi i turns} (interleaved),
-// quadrature weights wt.  launch_nu_fourier writes c_l, l < N = 2^logn, in
-// the radius transforms' precision by a gridding non-uniform FFT on a grid of
+// Non-uniform samples (afd_nonuni.hip): per signal of a batch, ns samples g
+// (interleaved complex, signals back to back), at positions `turns`, points
+// z = e^{2 pi i turns} (interleaved), quadrature weights wt, shared by the
+// batch.  launch_nu_fourier writes c_l, l < N = 2^logn, per signal in the
+// radius transforms' precision by a gridding non-uniform FFT on a grid of
 // G = 2^nu_grid_log2(logn) cells (kernel width kEsWidth cells).
 constexpr int kMaxNuSamples = 1 << 16;
 constexpr double kEsWidth = 12.0;
@@ -441,9 +442,9 @@ struct NuTables {
   const double* turns;  // [ns]
   const double* ws;     // [ns] complex: w_n e^{-2 pi i (N/2) t_n}
   const int4* rng;      // [G] sample index ranges of each cell
-  double* b;            // [G] complex: the gridded strengths
-  double* B;            // [G] complex: their forward DFT
-  void* xt;             // [G] complex: four-step intermediate
+  double* b;            // [batch][G] complex: the gridded strengths
+  double* B;            // [batch][G] complex: their forward DFT
+  void* xt;             // [batch][G] complex: four-step intermediate
   const void* tw1;      // forward-DFT twiddles of length G (fwd_plan(log2 G, true))
   const void* tw2;
   const double* omega;  // [G] complex e^{2 pi i k/G}
@@ -451,12 +452,12 @@ struct NuTables {
 };
 void nu_deconv_table(int N, int G, double* dinv);
 void nu_cell_ranges(const double* turns, int ns, int G, int32_t* rng);
-hipError_t launch_nu_fourier(const double* g, const NuTables& t, int logn, bool fp64, void* c, hipStream_t s,
-                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_nu_fourier(const double* g, const NuTables& t, int logn, bool fp64, void* c, int ns, int batch,
+                             hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_nu_prepare(const double* g, const double* wt, int ns, double* epart, int* nonfinite,
-                             unsigned int* counter, const RecordArgs& R, hipStream_t s);
-hipError_t launch_nu_update(double* g, const double* wt, const double* z, int ns, const UpdateArgs& U, hipStream_t s,
-                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                             unsigned int* counter, const RecordArgs& R, int batch, hipStream_t s);
+hipError_t launch_nu_update(double* g, const double* wt, const double* z, int ns, const UpdateArgs& U, int batch,
+                            hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Reconstruction and analytic front end (afd_recon.hip), double precision.
 int recon_waves(int N);  // wave partial sums per signal and step in `wpart`

@@ -29,7 +29,8 @@
 //   k_nu_update           eq. (7) at the sample points and the quadrature
 //                         energy; the last workgroup records the step
 // All in double precision; the FP32 mode's spectrum is the double one
-// rounded once.  One signal per plan.
+// rounded once.  A batch (grid dimension y) shares the positions, weights and
+// tables; each signal has its own samples, grid, spectrum and records.
 #include <algorithm>
 #include <vector>
 
@@ -50,9 +51,11 @@ int nu_grid_log2(int logn) { return logn + 2 < 6 ? 6 : logn + 2; }  // G = 4N, a
 // (rng[k] = {lo1, hi1, lo2, hi2}: a window that wraps around t = 0 has two).
 __global__ __launch_bounds__(256) void k_nu_spread(const double* __restrict__ g, const double* __restrict__ ws,
                                                    const double* __restrict__ turns, const int4* __restrict__ rng,
-                                                   int G, double* __restrict__ b) {
+                                                   int G, int ns, double* __restrict__ b) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= G) return;
+  g += 2 * size_t(ns) * blockIdx.y;
+  b += 2 * size_t(G) * blockIdx.y;
   const int4 r = rng[k];
   const double dG = double(G), half = 0.5 * dG;
   double ax = 0.0, ay = 0.0;
@@ -82,6 +85,8 @@ __global__ __launch_bounds__(256) void k_nu_deconv(const double* __restrict__ B,
                                                    int N, int G, int cols_l1, int cols_l2, Cx<T>* __restrict__ c) {
   const int l = blockIdx.x * 256 + threadIdx.x;
   if (l >= N) return;
+  B += 2 * size_t(G) * blockIdx.y;
+  c += size_t(N) * blockIdx.y;
   const int q = l >= N / 2 ? l - N / 2 : l - N / 2 + G;
   const int pos = cols_l2 ? ((q & ((1 << cols_l2) - 1)) << cols_l1) + (q >> cols_l2) : q;
   const double d = dinv[l];
@@ -105,6 +110,11 @@ __global__ __launch_bounds__(kNuUpdThreads) void k_nu_prepare(const double* __re
                                                               unsigned int* __restrict__ counter, RecordArgs R) {
   __shared__ double wd[16];
   __shared__ int s_last;
+  const int b = blockIdx.y;
+  g += 2 * size_t(ns) * b;
+  epart += size_t(gridDim.x) * b;
+  counter += b;
+  R = record_of(R, b);
   double acc = 0.0;
   int bad = 0;
 #pragma unroll
@@ -127,6 +137,11 @@ __global__ __launch_bounds__(kNuUpdThreads) void k_nu_update(double* __restrict_
                                                              const double* __restrict__ z, int ns, UpdateArgs U) {
   __shared__ double wd[16];
   __shared__ int s_last;
+  const int b = blockIdx.y;
+  g += 2 * size_t(ns) * b;
+  U.epart += size_t(gridDim.x) * b;
+  U.counter += b;
+  U.R = record_of(U.R, b);
   const Blaschke B = blaschke_of(U);
   double acc = 0.0;
 #pragma unroll
@@ -154,37 +169,38 @@ __global__ __launch_bounds__(kNuUpdThreads) void k_nu_update(double* __restrict_
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_nu_fourier(const double* g, const NuTables& t, int logn, bool fp64, void* c, hipStream_t s,
-                             hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_nu_fourier(const double* g, const NuTables& t, int logn, bool fp64, void* c, int ns, int batch,
+                             hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int N = 1 << logn;
   const int lg = nu_grid_log2(logn);
   const int G = 1 << lg;
-  launch_ev(k_nu_spread, dim3((G + 255) / 256), dim3(256), 0u, s, e0, nullptr, g, t.ws, t.turns, t.rng, G, t.b);
+  launch_ev(k_nu_spread, dim3((G + 255) / 256, batch), dim3(256), 0u, s, e0, nullptr, g, t.ws, t.turns, t.rng, G, ns,
+            t.b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_fwd(lg, true, t.b, t.tw1, t.tw2, t.omega, t.xt, t.B, 1, s);
+  e = launch_fwd(lg, true, t.b, t.tw1, t.tw2, t.omega, t.xt, t.B, batch, s);
   if (e != hipSuccess) return e;
   const FwdPlan fp = fwd_plan(lg, true);
   const int cl1 = lg > kMaxLdsLogN ? fp.l1 : 0, cl2 = lg > kMaxLdsLogN ? fp.l2 : 0;
   if (fp64)
-    launch_ev(k_nu_deconv<double>, dim3((N + 255) / 256), dim3(256), 0u, s, nullptr, e1,
+    launch_ev(k_nu_deconv<double>, dim3((N + 255) / 256, batch), dim3(256), 0u, s, nullptr, e1,
               static_cast<const double*>(t.B), t.dinv, N, G, cl1, cl2, static_cast<Cx<double>*>(c));
   else
-    launch_ev(k_nu_deconv<float>, dim3((N + 255) / 256), dim3(256), 0u, s, nullptr, e1,
+    launch_ev(k_nu_deconv<float>, dim3((N + 255) / 256, batch), dim3(256), 0u, s, nullptr, e1,
               static_cast<const double*>(t.B), t.dinv, N, G, cl1, cl2, static_cast<Cx<float>*>(c));
   return hipGetLastError();
 }
 
 hipError_t launch_nu_prepare(const double* g, const double* wt, int ns, double* epart, int* nonfinite,
-                             unsigned int* counter, const RecordArgs& R, hipStream_t s) {
-  hipLaunchKernelGGL(k_nu_prepare, dim3(nu_update_blocks(ns)), dim3(kNuUpdThreads), 0, s, g, wt, ns, epart,
+                             unsigned int* counter, const RecordArgs& R, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_nu_prepare, dim3(nu_update_blocks(ns), batch), dim3(kNuUpdThreads), 0, s, g, wt, ns, epart,
                      nonfinite, counter, R);
   return hipGetLastError();
 }
 
-hipError_t launch_nu_update(double* g, const double* wt, const double* z, int ns, const UpdateArgs& U, hipStream_t s,
-                            hipEvent_t e0, hipEvent_t e1) {
-  launch_ev(k_nu_update, dim3(nu_update_blocks(ns)), dim3(kNuUpdThreads), 0u, s, e0, e1, g, wt, z, ns, U);
+hipError_t launch_nu_update(double* g, const double* wt, const double* z, int ns, const UpdateArgs& U, int batch,
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_ev(k_nu_update, dim3(nu_update_blocks(ns), batch), dim3(kNuUpdThreads), 0u, s, e0, e1, g, wt, z, ns, U);
   return hipGetLastError();
 }
 

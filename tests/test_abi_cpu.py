@@ -190,7 +190,6 @@ def _nu_desc(afd, n=256, radii=(0.0, 0.5), turns=None, weights=None, batch=0, pr
     (dict(radii=(0.0, 0.99)), 5),                # kernel series longer than N = 256 terms
     (dict(n=243), 5),                            # the grid must be 2^K
     (dict(n=1 << 15), 5),
-    (dict(batch=2), 5),
     (dict(turns=np.arange(1 << 17) / (1 << 17)), 5),
 ])
 def test_nonuniform_rejects(kw, status):
@@ -213,6 +212,11 @@ def test_nonuniform_workspace():
     assert 0 < b1 < b2
     # 3000 more samples: position, weight, point, shifted weight and the remainder sample
     assert b2 - b1 >= 3000 * (8 + 8 + 16 + 16 + 16)
+    # a batch of 3 holds three remainders and three gridding buffers (G = 4096 cells of
+    # 16 bytes, three of them per signal)
+    d3, k3 = _nu_desc(afd, n=1024, radii=np.linspace(0, 0.95, 20), turns=np.arange(1000) / 1000, batch=3)
+    b3 = lib.afd_workspace_bytes(ctypes.byref(d3))
+    assert b3 - b1 >= 2 * (1000 * 16 + 3 * 4096 * 16)
     d3, k3 = _desc(afd, n=1024)
     d3.samples = 1000
     assert lib.afd_workspace_bytes(ctypes.byref(d3)) == 0

@@ -140,14 +140,40 @@ def test_graph_replays_equal_eager(prec):
                 torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_matches_alone(prec):
+    """A batch of three signals on one set of positions: each equals its own
+    decomposition bit for bit, and one is checked against the oracle."""
+    n, ns, m, steps, batch = 1024, 1300, 40, 5, 3
+    made = [W.nonuniform_kernel_signal(ns, item=40 + i, kind="cluster") for i in range(batch)]
+    t = made[0][1]
+    assert all(np.array_equal(ti, t) for _, ti in made)  # clustered positions do not depend on the item
+    sigs = np.stack([g for g, _ in made])
+    radii = W.uniform_radii(m, 0.95)
+    with Plan(n, radii, precision=prec, sample_turns=t, batch=batch) as plan:
+        rb = to_numpy(plan.decompose(_dev(sigs), steps))
+        S, delta = plan.reconstruct(rb["a"], rb["coef"], signal=sigs)
+    w = O.trapezoid_weights(t)
+    for i in range(batch):
+        # partial sums at the sample points and relative errors, per signal
+        S_ref = O.partial_sum(rb["coef"][i], rb["a"][i], O.sample_points(t))
+        assert np.max(np.abs(S[i] - S_ref)) < 1e-12 * np.max(np.abs(S_ref))
+        assert np.max(np.abs(delta[i] - O.relative_errors_nu(sigs[i], t, w, rb["coef"][i], rb["a"][i]))) < 1e-12
+    for i in range(batch):
+        with Plan(n, radii, precision=prec, sample_turns=t) as plan:
+            ra = to_numpy(plan.decompose(_dev(sigs[i]), steps))
+        for k in ("index", "coef", "energy", "margin", "remainder"):
+            np.testing.assert_array_equal(rb[k][i], ra[k], err_msg=f"signal {i} field {k}")
+    ref = O.decompose_nu(sigs[1], t, w, radii, n, steps)
+    assert np.array_equal(rb["index"][1], ref.index)
+
+
 def test_unsupported():
     t = np.arange(100) / 100 + 0.001
     with pytest.raises(AfdError):
         Plan(256, [0.0, 0.99], sample_turns=t)       # r = 0.99 needs more than 256 terms
     with pytest.raises(AfdError):
         Plan(243, [0.0, 0.5], sample_turns=t)        # the grid must be 2^K
-    with pytest.raises(AfdError):
-        Plan(256, [0.0, 0.5], sample_turns=t, batch=2)
     with Plan(256, [0.0, 0.5], sample_turns=t) as plan:
         with pytest.raises(AfdError):
             plan.analytic(np.ones(256))
