@@ -298,11 +298,31 @@ __device__ __forceinline__ void pass_jobs(Cx<T> (&v)[E], int t, const TW& tw, st
   (pass_job<T, LOGN, E, P, SIGN, U>(v, t, tw), ...);
 }
 
+// A twiddle table in memory whose address the compiler may not derive from
+// before the pass that reads it: the table pointer passes through an empty
+// asm at the start of every pass, so the per-thread addresses of a pass's
+// twiddles are formed there and not hoisted to the start of the kernel (in
+// the longest transforms they were, and were spilled).
+template <typename T>
+struct TwLate {
+  const Cx<T>* p;
+};
+template <class TW>
+struct IsTwLate : std::false_type {};
+template <typename T>
+struct IsTwLate<TwLate<T>> : std::true_type {};
+
 // One Stockham pass P on the registers v (see the file comment).
 template <typename T, int LOGN, int E, int P, int SIGN, class TW>
 __device__ __forceinline__ void pass_compute(Cx<T> (&v)[E], int t, const TW& tw) {
   using S = Shape<LOGN, E>;
-  pass_jobs<T, LOGN, E, P, SIGN>(v, t, tw, std::make_integer_sequence<int, E / S::radix(P)>{});
+  if constexpr (IsTwLate<TW>::value) {
+    const Cx<T>* p = tw.p;
+    asm volatile("" : "+s"(p));
+    pass_jobs<T, LOGN, E, P, SIGN>(v, t, p, std::make_integer_sequence<int, E / S::radix(P)>{});
+  } else {
+    pass_jobs<T, LOGN, E, P, SIGN>(v, t, tw, std::make_integer_sequence<int, E / S::radix(P)>{});
+  }
 }
 
 // LDS addressing.  Element i lives at lds_pad(i) = i + (i >> kPadShift).  For

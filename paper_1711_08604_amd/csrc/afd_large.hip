@@ -244,14 +244,15 @@ __attribute__((amdgpu_waves_per_eu(Big<T, LOGN, DL>::WPE_B))) void k_big_rows(Bi
       // L <= N2 (the launch holds medium radii only); rows longer than a
       // wave synchronise the workgroup
       constexpr bool WAVE = 64 % B::TPR2 == 0;
+      const TwLate<T> twl{tw2};
       if (S2::NP >= 2 && L <= B::N2 / S2::radix(0)) {
         if constexpr (S2::NP >= 2) {
           deep_row_inputs<T, LOGN, 1, B::E2, DL>(v, t, j1, L, p, m);
-          fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1, WAVE>(v, t, region, tw2);
+          fft_regs<T, B::L2, B::E2, +1, SPLIT, 1, 1, WAVE>(v, t, region, twl);
         }
       } else {
         deep_row_inputs<T, LOGN, 0, B::E2, DL>(v, t, j1, L, p, m);
-        fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, WAVE>(v, t, region, tw2);
+        fft_regs<T, B::L2, B::E2, +1, SPLIT, 0, 0, WAVE>(v, t, region, twl);
       }
     }
 
