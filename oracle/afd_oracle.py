@@ -427,17 +427,26 @@ def nudft(u, turns, count: int) -> np.ndarray:
     return out
 
 
-def grid_series_nu(G, turns, weights, radii, n: int) -> np.ndarray:
+def grid_series_nu(G, turns, weights, radii, n: int, terms: int = None) -> np.ndarray:
     """Grid values from the non-uniform DFT: with c_l = sum_n w_n G_n e^{-2 pi i l t_n},
     V[m, j] = sqrt(1 - r^2) sum_{l >= 0} r^l c_l e^{2 pi i l j/n} (the geometric
     expansion of the kernel, eq. ku12 without the periodicity that uniform
-    samples give c_l).  The sum is cut at l < n, so this equals grid_direct_nu
-    only where r^n is negligible; the inverse DFT over j is numpy's (times n)."""
+    samples give c_l).  The sum is cut at l < `terms` (default n), so this
+    equals grid_direct_nu only where r^terms is negligible.  Since
+    e^{2 pi i l j/n} depends on l mod n only, the terms l = l' + k n are
+    summed into x[l'] = sum_k r^(l' + k n) c_(l' + k n), and the inverse DFT
+    over j is numpy's (times n)."""
+    terms = n if terms is None else int(terms)
     G = np.asarray(G, dtype=np.complex128)
-    c = nudft(np.asarray(weights, dtype=np.float64) * G, turns, n)
+    c = nudft(np.asarray(weights, dtype=np.float64) * G, turns, terms)
     V = np.empty((len(radii), n), dtype=np.complex128)
     for m, r in enumerate(radii):
-        V[m] = np.sqrt(1.0 - r * r) * n * np.fft.ifft(c * _radius_power(r, n))
+        y = c * _radius_power(r, terms)
+        x = np.zeros(n, dtype=np.complex128)
+        for k0 in range(0, terms, n):
+            part = y[k0:k0 + n]
+            x[:len(part)] += part
+        V[m] = np.sqrt(1.0 - r * r) * n * np.fft.ifft(x)
     return V
 
 
@@ -453,16 +462,20 @@ def energy_nu(G, weights) -> float:
 
 
 def decompose_nu(G, turns, weights, radii, n: int, steps: int, first_a_zero: bool = False, forced=None,
-                 form: str = "direct") -> Decomposition:
+                 form: str = "direct", terms: int = None) -> Decomposition:
     """Core-AFD on non-uniform samples: the loop of decompose() with the grid
-    values of grid_direct_nu (`form` = "direct") or grid_series_nu ("series"),
-    the update at the sample points and the quadrature energy.  Indices are
-    (m, j) on the n-angle grid."""
+    values of grid_direct_nu (`form` = "direct") or grid_series_nu ("series",
+    cut at `terms`, default n), the update at the sample points and the
+    quadrature energy.  Indices are (m, j) on the n-angle grid."""
     G = np.asarray(G, dtype=np.complex128).copy()
     radii = np.asarray(radii, dtype=np.float64)
     w = np.asarray(weights, dtype=np.float64)
     z = sample_points(turns)
-    grid = grid_direct_nu if form == "direct" else grid_series_nu
+    if form == "direct":
+        grid = grid_direct_nu
+    else:
+        def grid(G_, t_, w_, r_, n_):
+            return grid_series_nu(G_, t_, w_, r_, n_, terms)
     zero_idx = None
     if first_a_zero:
         hits = np.nonzero(radii == 0.0)[0]

@@ -471,7 +471,9 @@ def pin_nonuniform_rule(O):
 def pin_nonuniform_series(O):
     """The non-uniform DFT and the series form: c_l of a single sample is
     u e^{-2 pi i l t}; the series form equals the quadrature rule once r^N is
-    negligible (jittered positions, trapezoid weights); the normalised Szego
+    negligible (jittered positions, trapezoid weights), and for radii near 1
+    once its cut (terms) makes r^terms negligible, while the cut at N misses
+    their tail; the normalised Szego
     kernel e_b on the two-grid union has the closed form
     sqrt((1-|a|^2)(1-|b|^2)) sum_g alpha_g (1 - (xy)^n_g) / ((1 - xy)(1 - x^n_g)(1 - y^n_g)),
     x = conj(b) e^{2 pi i beta_g}, y = a e^{-2 pi i beta_g}; and one step on w e_b
@@ -486,6 +488,12 @@ def pin_nonuniform_series(O):
     G = rng.standard_normal(300) + 1j * rng.standard_normal(300)
     radii = np.array([0.0, 0.1, 0.5, 0.8, 0.85])
     assert _rel(O.grid_series_nu(G, t, w, radii, N), O.grid_direct_nu(G, t, w, radii, N)) < 1e-12
+    # radii near 1: the series cut at N terms misses the tail that the
+    # quadrature rule holds; cut at 32 N (0.99^8192 ~ 1e-36) it does not
+    near = np.array([0.5, 0.95, 0.99])
+    direct = O.grid_direct_nu(G, t, w, near, N)
+    assert _rel(O.grid_series_nu(G, t, w, near, N), direct) > 1e-3
+    assert _rel(O.grid_series_nu(G, t, w, near, N, terms=32 * N), direct) < 1e-12
     n1, b1, n2, b2, alpha = 48, 0.0031, 80, 0.0117, 0.3
     t2, w2 = _two_grids(n1, b1, n2, b2, alpha)
     z2 = O.sample_points(t2)
