@@ -98,9 +98,11 @@ typedef struct {
      stays a_{m,j} = r_m e^{2 pi i j/N}; the DFT of the samples becomes the non-uniform DFT
      c_l = sum_n w_n G(z_n) e^{-2 pi i l t_n}, l < N.  A batch shares the positions and
      weights (each signal holds `samples` values).  Needs N = 2^K <= 2^14,
-     1 <= samples <= 2^16 and radii whose kernel series r^l is negligible from l = N on (the
-     significant length of the uniform path's radius tables, at most N); else
-     AFD_E_UNSUPPORTED.  The remainder then has `samples` values; afd_reconstruct gives the
+     1 <= samples <= 2^16 and radii whose kernel series r^l is negligible from l = 2^18 on (the
+     significant length of the uniform path's radius tables); else AFD_E_UNSUPPORTED.  The
+     non-uniform DFT computes the K N modes (K a power of two) the longest series needs, and a
+     radius whose series outlasts N terms is transformed from its folded spectrum
+     sum_k r^(kN) c_(l+kN).  The remainder then has `samples` values; afd_reconstruct gives the
      partial sums at the sample points and the relative errors in the quadrature norm;
      afd_analytic returns AFD_E_UNSUPPORTED.                                                 */
   const double* sample_turns;

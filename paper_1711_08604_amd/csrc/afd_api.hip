@@ -99,6 +99,8 @@ struct Layout {
   // and the gridding non-uniform FFT: shifted weights, cell ranges, deconvolution,
   // grid, its transform, intermediate, twiddles and unit roots of the G-cell grid
   size_t nu_ws, nu_rng, nu_dinv, nu_b, nu_B, nu_xt, nu_tw1, nu_tw2, nu_omega;
+  // and radii whose series outlasts N terms: modes l >= N, folded spectra, r^N, slots
+  size_t nu_ctail, nu_cfold, nu_rho, nu_fslot;
   size_t total;
 };
 
@@ -133,6 +135,8 @@ struct Config {
   MixedGeom mg;
   bool nu;      // non-uniform samples (afd_nonuni.hip)
   int ns;       // samples per signal (N unless nu)
+  int nu_lognm; // non-uniform samples: 2^nu_lognm modes of the non-uniform DFT (N, or K N)
+  int nfold;    // non-uniform samples: radii whose series outlasts N terms (folded spectra)
 };
 
 constexpr int kNumCounters = 5;  // radius, recheck, update, prepare; FP32 fallback flag word
@@ -192,11 +196,25 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     }
     if (logn < 1 || logn > kMaxLdsLogN)
       return fail(AFD_E_UNSUPPORTED, "non-uniform samples need a grid of N = 2^K <= 2^14 angles");
+    // the modes of the non-uniform DFT: N, or the power of two K N >= the
+    // longest significant series (radii beyond N terms get folded spectra)
     const int bits = d->precision == AFD_FP64 ? 60 : 40;
-    for (int i = 0; i < d->m; ++i)
-      if (significant_length(d->radii[i], bits, int64_t(1) << 40) > d->n)
-        return fail(AFD_E_UNSUPPORTED,
-                    "non-uniform samples: a radius is too close to 1 for N (its kernel series needs more than N terms)");
+    int64_t lmax = d->n;
+    int nfold = 0;
+    for (int i = 0; i < d->m; ++i) {
+      const int64_t L = significant_length(d->radii[i], bits, int64_t(1) << 30);
+      lmax = L > lmax ? L : lmax;
+      if (L > d->n) ++nfold;
+    }
+    int lognm = logn;
+    while ((int64_t(1) << lognm) < lmax && lognm <= kMaxNuLogModes) ++lognm;
+    if (lognm > kMaxNuLogModes)
+      return fail(AFD_E_UNSUPPORTED,
+                  "non-uniform samples: a radius is too close to 1 (its kernel series needs more than 2^18 terms)");
+    if (cfg) {
+      cfg->nu_lognm = lognm;
+      cfg->nfold = nfold;
+    }
   } else if (d->samples != 0) {
     return fail(AFD_E_INVALID, "samples needs sample_turns");
   }
@@ -219,6 +237,7 @@ afd_status validate(const afd_plan_desc* d, Config* cfg) {
     cfg->big = logn > kMaxLdsLogN;
     cfg->nu = nu;
     cfg->ns = nu ? int(d->samples) : int(d->n);
+    if (!nu) cfg->nu_lognm = cfg->nfold = 0;  // (set with the checks of the samples otherwise)
     if (nu) {
       cfg->fwd = FwdPlan{};
       cfg->nch = recheck_chunks(cfg->ns);
@@ -345,11 +364,16 @@ Layout layout_of(const Config& c) {
   L.nu_t = take(c.nu ? 8 * size_t(c.ns) : 0);
   L.nu_w = take(c.nu ? 8 * size_t(c.ns) : 0);
   L.nu_z = take(c.nu ? 16 * size_t(c.ns) : 0);
-  const size_t G = c.nu ? size_t(1) << nu_grid_log2(c.logn) : 0;
-  const FwdPlan gp = c.nu ? fwd_plan(nu_grid_log2(c.logn), true) : FwdPlan{};
+  const size_t G = c.nu ? size_t(1) << nu_grid_log2(c.nu_lognm) : 0;
+  const size_t NM = c.nu ? size_t(1) << c.nu_lognm : 0;
+  const FwdPlan gp = c.nu ? fwd_plan(nu_grid_log2(c.nu_lognm), true) : FwdPlan{};
   L.nu_ws = take(16 * size_t(c.nu ? c.ns : 0));
   L.nu_rng = take(16 * G);
-  L.nu_dinv = take(c.nu ? 8 * size_t(c.N) : 0);
+  L.nu_dinv = take(8 * NM);
+  L.nu_ctail = take(c.nu ? 2 * real * (NM - size_t(c.N)) * B : 0);
+  L.nu_cfold = take(c.nu ? 2 * real * size_t(c.nfold) * size_t(c.N) * B : 0);
+  L.nu_rho = take(c.nu ? 8 * size_t(c.nfold) : 0);
+  L.nu_fslot = take(c.nu && c.nfold > 0 ? 4 * size_t(c.M) : 0);
   L.nu_b = take(16 * G * B);
   L.nu_B = take(16 * G * B);
   L.nu_xt = take(16 * G * B);
@@ -591,22 +615,35 @@ afd_status build_tables(afd_plan_s* p, const afd_plan_desc* d) {
     e = up(p->L.nu_t, d->sample_turns, 8 * size_t(ns));
     if (e == hipSuccess) e = up(p->L.nu_w, w.data(), 8 * size_t(ns));
     if (e == hipSuccess) e = up(p->L.nu_z, z.data(), 16 * size_t(ns));
-    // the non-uniform FFT: strengths' factor w_n e^{-2 pi i (N/2) t_n} (the
-    // fractional turn of (N/2) t_n is exact), cell ranges, deconvolution,
-    // and the forward-transform tables of the G-cell grid
+    // the non-uniform FFT of NM modes: strengths' factor w_n e^{-2 pi i (NM/2) t_n}
+    // (the fractional turn of (NM/2) t_n is exact), cell ranges,
+    // deconvolution, and the forward-transform tables of the G-cell grid
+    const int64_t NM = int64_t(1) << c.nu_lognm;
     std::vector<double> ws(2 * size_t(ns));
     for (int n = 0; n < ns; ++n) {
-      const double h = double(N / 2) * d->sample_turns[n];  // exact: N/2 is a power of two
+      const double h = double(NM / 2) * d->sample_turns[n];  // exact: NM/2 is a power of two
       const long double ang = two_pi * (long double)(h - std::nearbyint(h));
       ws[2 * size_t(n)] = (double)((long double)w[n] * cosl(ang));
       ws[2 * size_t(n) + 1] = (double)(-(long double)w[n] * sinl(ang));
     }
-    const int lg = nu_grid_log2(c.logn);
+    const int lg = nu_grid_log2(c.nu_lognm);
     const int64_t G = int64_t(1) << lg;
     std::vector<int32_t> rng(4 * size_t(G));
     nu_cell_ranges(d->sample_turns, ns, int(G), rng.data());
-    std::vector<double> dinv(static_cast<size_t>(N));
-    nu_deconv_table(int(N), int(G), dinv.data());
+    std::vector<double> dinv(static_cast<size_t>(NM));
+    nu_deconv_table(int(NM), int(G), dinv.data());
+    // radii whose series outlasts N terms: their slots and r^N
+    if (c.nfold > 0) {
+      std::vector<int32_t> fslot(M, -1);
+      std::vector<double> rho;
+      for (int m = 0; m < M; ++m)
+        if (significant_length(radii[m], c.fp64 ? 60 : 40, int64_t(1) << 30) > N) {
+          fslot[m] = int32_t(rho.size());
+          rho.push_back((double)powl((long double)radii[m], (long double)N));
+        }
+      if (e == hipSuccess) e = up(p->L.nu_fslot, fslot.data(), 4 * fslot.size());
+      if (e == hipSuccess) e = up(p->L.nu_rho, rho.data(), 8 * rho.size());
+    }
     const FwdPlan gp = fwd_plan(lg, true);
     std::vector<double> gtw1(2 * size_t(gp.tw1_size + 1), 0.0), gtw2(2 * size_t(gp.tw2_size + 1), 0.0);
     fft_twiddles(gp.two_pass ? gp.l1 : lg, true, gtw1.data());
@@ -799,6 +836,11 @@ NuTables nu_tables(afd_plan_s* p) {
   t.tw1 = p->at<void>(p->L.nu_tw1);
   t.tw2 = p->at<void>(p->L.nu_tw2);
   t.omega = p->at<double>(p->L.nu_omega);
+  t.lognm = p->cfg.nu_lognm;
+  t.ctail = p->at<void>(p->L.nu_ctail);
+  t.nfold = p->cfg.nfold;
+  t.rho = p->at<double>(p->L.nu_rho);
+  t.cfold = p->at<void>(p->L.nu_cfold);
   t.dinv = p->at<double>(p->L.nu_dinv);
   return t;
 }
@@ -1071,6 +1113,10 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
   rp.probe = nullptr;  // set per replayed step (double precision)
   rp.probe_stride = 2 * steps;
   rp.probe_out = p->at<double>(p->L.probe);
+  // non-uniform samples: radii whose series outlasts N terms read folded spectra
+  rp.cfold = c.nu && c.nfold > 0 ? p->at<void>(p->L.nu_cfold) : nullptr;
+  rp.fslot = c.nu && c.nfold > 0 ? p->at<int>(p->L.nu_fslot) : nullptr;
+  rp.nfold = c.nu ? c.nfold : 0;
 
   BigParams bp{};
   if (c.big) {

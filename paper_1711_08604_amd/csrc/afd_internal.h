@@ -95,6 +95,12 @@ struct RadiusParams {
   const int32_t* probe;
   int probe_stride;
   double* probe_out;
+  // non-uniform samples with radii whose series outlasts N terms: radius m
+  // with fslot[m] >= 0 reads its own folded spectrum cfold[b][fslot[m]][N]
+  // (the FOLD instantiations of the radius kernel only)
+  const void* cfold;
+  const int* fslot;
+  int nfold;
 };
 
 // Radius transforms beyond the LDS (N > 2^kMaxLdsLogN): per radius a
@@ -432,9 +438,12 @@ hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, int batch
 // (interleaved complex, signals back to back), at positions `turns`, points
 // z = e^{2 pi i turns} (interleaved), quadrature weights wt, shared by the
 // batch.  launch_nu_fourier writes c_l, l < N = 2^logn, per signal in the
-// radius transforms' precision by a gridding non-uniform FFT on a grid of
-// G = 2^nu_grid_log2(logn) cells (kernel width kEsWidth cells).
+// radius transforms' precision (and the folded spectra of the radii that
+// need more than N terms) by a gridding non-uniform FFT of NM = 2^t.lognm
+// modes on a grid of G = 2^nu_grid_log2(t.lognm) cells (kernel width
+// kEsWidth cells).
 constexpr int kMaxNuSamples = 1 << 16;
+constexpr int kMaxNuLogModes = 18;  // NM <= 2^18 modes (grids of up to 2^20 cells)
 constexpr double kEsWidth = 12.0;
 constexpr double kEsBeta = 2.69 * 12.0;
 int nu_grid_log2(int logn);
@@ -448,7 +457,12 @@ struct NuTables {
   const void* tw1;      // forward-DFT twiddles of length G (fwd_plan(log2 G, true))
   const void* tw2;
   const double* omega;  // [G] complex e^{2 pi i k/G}
-  const double* dinv;   // [N] 1/Phi((l - N/2)/G)
+  const double* dinv;   // [NM] 1/Phi((l - NM/2)/G)
+  int lognm;            // NM = 2^lognm modes: N, or K N when radii need K N terms (G = 4 NM)
+  void* ctail;          // [batch][NM - N] modes l >= N (the radius transforms' precision)
+  int nfold;            // radii whose series outlasts N terms
+  const double* rho;    // [nfold] r^N of each
+  void* cfold;          // [batch][nfold][N] their folded spectra
 };
 void nu_deconv_table(int N, int G, double* dinv);
 void nu_cell_ranges(const double* turns, int ns, int G, int32_t* rng);

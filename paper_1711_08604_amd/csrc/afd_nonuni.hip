@@ -6,15 +6,17 @@
 //   sqrt(1 - r^2) sum_{l >= 0} r^l c_l e^{2 pi i l j/N}        (eq. ku12),
 // the geometric expansion of the Szego kernel; unlike the uniform case c_l
 // is not N-periodic, so the series is not folded into 1/(1 - r^N).  A plan
-// accepts only radii whose terms beyond l = N - 1 are negligible (the same
-// 2^-60 / 2^-40 cut as the uniform path's), so the radius kernel runs
-// unchanged on c_0..c_{N-1} with the scale sqrt(1 - r^2).
+// computes the modes l < K N (K a power of two) that the largest radius
+// needs (the same 2^-60 / 2^-40 cut as the uniform path's radius tables);
+// the radius kernel runs on c_0..c_{N-1} with the scale sqrt(1 - r^2), and a
+// radius whose terms outlast N reads its own folded spectrum
+// cf[l] = sum_k (r^N)^k c_(l + kN) (k_nu_fold).
 //
-// c_l, l < N, comes from a gridding non-uniform FFT (type 1) with the
+// c_l, l < K N, comes from a gridding non-uniform FFT (type 1) with the
 // "exponential of semicircle" kernel phi(x) = exp(beta (sqrt(1 - (2x/W)^2) - 1)),
 // |x| < W/2 grid cells (Barnett, Magland, af Klinteberg, SIAM J. Sci. Comput.
-// 2019): with the modes shifted to l' = l - N/2 (strengths times
-// e^{-2 pi i (N/2) t_n}), each point k of a grid of G = 4N cells gathers
+// 2019): with the modes shifted to l' = l - KN/2 (strengths times
+// e^{-2 pi i (KN/2) t_n}), each point k of a grid of G = 4KN cells gathers
 // b_k = sum_n u'_n phi(G t_n - k) (wrapped), a length-G forward FFT gives
 // B_{l'}, and c_l = B_{l'} / Phi(l'/G), Phi the kernel's Fourier transform
 // (tabled per plan).  W = 12 and beta = 2.69 W keep the error near 1e-14 of
@@ -25,6 +27,8 @@
 //   (FFT)                 the forward transforms of afd_fwd.hip, length G
 //   k_nu_deconv           c_l = B_{l'} / Phi(l'/G), in the precision of the
 //                         radius transforms
+//   k_nu_fold             the folded spectra of the radii that need more
+//                         than N terms
 //   k_nu_prepare          E_0 = sum_n w_n |G_n|^2 and the non-finite check
 //   k_nu_update           eq. (7) at the sample points and the quadrature
 //                         energy; the last workgroup records the step
@@ -78,19 +82,50 @@ __global__ __launch_bounds__(256) void k_nu_spread(const double* __restrict__ g,
   b[2 * k + 1] = ay;
 }
 
-// c_l = B_q / Phi((l - N/2)/G), q = (l - N/2) mod G; from 2^15 points the
-// forward transform leaves B in column order (bin q at (q mod N2) N1 + q / N2).
+// c_l = B_q / Phi((l - NM/2)/G), q = (l - NM/2) mod G, for the NM modes
+// l < NM (NM = N, or K N when radii need K N terms): l < N into c, the
+// rest into ctail[l - N].  From 2^15 points the forward transform leaves B
+// in column order (bin q at (q mod N2) N1 + q / N2).
 template <typename T>
 __global__ __launch_bounds__(256) void k_nu_deconv(const double* __restrict__ B, const double* __restrict__ dinv,
-                                                   int N, int G, int cols_l1, int cols_l2, Cx<T>* __restrict__ c) {
+                                                   int N, int NM, int G, int cols_l1, int cols_l2,
+                                                   Cx<T>* __restrict__ c, Cx<T>* __restrict__ ctail) {
   const int l = blockIdx.x * 256 + threadIdx.x;
-  if (l >= N) return;
+  if (l >= NM) return;
   B += 2 * size_t(G) * blockIdx.y;
-  c += size_t(N) * blockIdx.y;
-  const int q = l >= N / 2 ? l - N / 2 : l - N / 2 + G;
+  const int q = l >= NM / 2 ? l - NM / 2 : l - NM / 2 + G;
   const int pos = cols_l2 ? ((q & ((1 << cols_l2) - 1)) << cols_l1) + (q >> cols_l2) : q;
   const double d = dinv[l];
-  c[l] = {T(B[2 * pos] * d), T(B[2 * pos + 1] * d)};
+  const Cx<T> v{T(B[2 * pos] * d), T(B[2 * pos + 1] * d)};
+  if (l < N)
+    c[size_t(N) * blockIdx.y + l] = v;
+  else
+    ctail[size_t(NM - N) * blockIdx.y + (l - N)] = v;
+}
+
+// Folded spectra of the radii whose series outlasts N terms (Sec. 3.1,
+// eq. ku12 with e^{2 pi i l j/N} depending on l mod N only): with
+// rho = r^N, cf[l] = sum_k rho^k c_(l + kN), k < K, so that r^l cf[l] holds
+// every term r^(l + kN) c_(l + kN) of the series (the radius kernel applies
+// r^l).  Summed in double precision in the order of k.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nu_fold(const Cx<T>* __restrict__ c, const Cx<T>* __restrict__ ctail,
+                                                 const double* __restrict__ rho, int N, int K, int nfold,
+                                                 Cx<T>* __restrict__ cfold) {
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  if (l >= N) return;
+  const int f = blockIdx.y, b = blockIdx.z;
+  c += size_t(N) * b;
+  ctail += size_t(N) * (K - 1) * b;
+  const double p = rho[f];
+  double ax = double(c[l].x), ay = double(c[l].y), pk = 1.0;
+  for (int k = 1; k < K; ++k) {
+    pk *= p;
+    const Cx<T> x = ctail[size_t(k - 1) * N + l];
+    ax = fma(pk, double(x.x), ax);
+    ay = fma(pk, double(x.y), ay);
+  }
+  cfold[(size_t(b) * nfold + f) * N + l] = {T(ax), T(ay)};
 }
 
 // End of a pass over the samples: this workgroup's weighted energy partial
@@ -172,7 +207,9 @@ __global__ __launch_bounds__(kNuUpdThreads) void k_nu_update(double* __restrict_
 hipError_t launch_nu_fourier(const double* g, const NuTables& t, int logn, bool fp64, void* c, int ns, int batch,
                              hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int N = 1 << logn;
-  const int lg = nu_grid_log2(logn);
+  const int NM = 1 << t.lognm;  // modes: N, or K N for the folded radii
+  const int K = NM / N;
+  const int lg = nu_grid_log2(t.lognm);
   const int G = 1 << lg;
   launch_ev(k_nu_spread, dim3((G + 255) / 256, batch), dim3(256), 0u, s, e0, nullptr, g, t.ws, t.turns, t.rng, G, ns,
             t.b);
@@ -182,12 +219,26 @@ hipError_t launch_nu_fourier(const double* g, const NuTables& t, int logn, bool 
   if (e != hipSuccess) return e;
   const FwdPlan fp = fwd_plan(lg, true);
   const int cl1 = lg > kMaxLdsLogN ? fp.l1 : 0, cl2 = lg > kMaxLdsLogN ? fp.l2 : 0;
+  hipEvent_t ed = t.nfold > 0 ? nullptr : e1;
   if (fp64)
-    launch_ev(k_nu_deconv<double>, dim3((N + 255) / 256, batch), dim3(256), 0u, s, nullptr, e1,
-              static_cast<const double*>(t.B), t.dinv, N, G, cl1, cl2, static_cast<Cx<double>*>(c));
+    launch_ev(k_nu_deconv<double>, dim3((NM + 255) / 256, batch), dim3(256), 0u, s, nullptr, ed,
+              static_cast<const double*>(t.B), t.dinv, N, NM, G, cl1, cl2, static_cast<Cx<double>*>(c),
+              static_cast<Cx<double>*>(t.ctail));
   else
-    launch_ev(k_nu_deconv<float>, dim3((N + 255) / 256, batch), dim3(256), 0u, s, nullptr, e1,
-              static_cast<const double*>(t.B), t.dinv, N, G, cl1, cl2, static_cast<Cx<float>*>(c));
+    launch_ev(k_nu_deconv<float>, dim3((NM + 255) / 256, batch), dim3(256), 0u, s, nullptr, ed,
+              static_cast<const double*>(t.B), t.dinv, N, NM, G, cl1, cl2, static_cast<Cx<float>*>(c),
+              static_cast<Cx<float>*>(t.ctail));
+  if (t.nfold > 0) {
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid((N + 255) / 256, t.nfold, batch);
+    if (fp64)
+      launch_ev(k_nu_fold<double>, grid, dim3(256), 0u, s, nullptr, e1, static_cast<const Cx<double>*>(c),
+                static_cast<const Cx<double>*>(t.ctail), t.rho, N, K, t.nfold, static_cast<Cx<double>*>(t.cfold));
+    else
+      launch_ev(k_nu_fold<float>, grid, dim3(256), 0u, s, nullptr, e1, static_cast<const Cx<float>*>(c),
+                static_cast<const Cx<float>*>(t.ctail), t.rho, N, K, t.nfold, static_cast<Cx<float>*>(t.cfold));
+  }
   return hipGetLastError();
 }
 

@@ -82,7 +82,7 @@ __device__ __forceinline__ void deep_inputs(Cx<T> (&v)[E], int t, int L, const C
 // meaningful in thread 0 only.  PROBE (double precision, replay): the grid
 // value at the forced point is also stored; it is a separate instantiation
 // so that the probe's code does not weigh on the decomposition's.
-template <typename T, int LOGN, bool LIST, bool PROBE>
+template <typename T, int LOGN, bool LIST, bool PROBE, bool FOLD>
 __device__ __forceinline__ unsigned int radius_slot(const RadiusParams& prm, int slot, int b, unsigned char* smem) {
   constexpr int E = pickE<T, LOGN>();
   constexpr bool SPLIT = pickSplit<T, LOGN>();
@@ -115,6 +115,13 @@ __device__ __forceinline__ unsigned int radius_slot(const RadiusParams& prm, int
 
   // signal b of a batch: its spectrum and records
   const Cx<T>* __restrict__ c = reinterpret_cast<const Cx<T>*>(prm.c) + size_t(N) * b;
+  if constexpr (FOLD) {
+    // a radius whose series outlasts N terms has its own folded spectrum
+    // (one radius per workgroup: a uniform choice, in scalar registers)
+    int fs = prm.fslot[mm];
+    if (S::TPR >= 64 || prm.rpb == 1) fs = __builtin_amdgcn_readfirstlane(fs);
+    if (fs >= 0) c = reinterpret_cast<const Cx<T>*>(prm.cfold) + (size_t(b) * size_t(prm.nfold) + size_t(fs)) * N;
+  }
   const T* __restrict__ pw = reinterpret_cast<const T*>(prm.pw);
   const T* __restrict__ pv = reinterpret_cast<const T*>(prm.pv);
   const Cx<T>* __restrict__ tw = reinterpret_cast<const Cx<T>*>(prm.tw);
@@ -233,7 +240,7 @@ __device__ __forceinline__ unsigned int radius_slot(const RadiusParams& prm, int
 // not depend on the workgroup that
 // computes it.  Every workgroup leaves once the queue is exhausted; none
 // waits on another.
-template <typename T, int LOGN, bool LIST, bool PROBE = false>
+template <typename T, int LOGN, bool LIST, bool PROBE = false, bool FOLD = false>
 __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_waves_per_eu(
     radius_min_waves<T, LOGN>()))) void k_radius(RadiusParams prm) {
   constexpr int N = 1 << LOGN;
@@ -248,7 +255,7 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
     // back past the last slot
     int slot = int(blockIdx.x);
     while (slot < prm.nrec) {  // uniform
-      const unsigned int ticket = radius_slot<T, LOGN, LIST, PROBE>(prm, slot, b, smem);
+      const unsigned int ticket = radius_slot<T, LOGN, LIST, PROBE, FOLD>(prm, slot, b, smem);
       if (!prm.queue) break;
       __syncthreads();  // every thread is done with the LDS and with s_next
       if (threadIdx.x == 0) s_next = int(gridDim.x) + int(ticket - prm.qbase);
@@ -257,7 +264,7 @@ __global__ __launch_bounds__((radius_threads<T, LOGN>())) __attribute__((amdgpu_
     }
     if (prm.queue) return;  // the step tail merges the records
   } else {
-    radius_slot<T, LOGN, LIST, PROBE>(prm, int(blockIdx.x), b, smem);
+    radius_slot<T, LOGN, LIST, PROBE, FOLD>(prm, int(blockIdx.x), b, smem);
   }
   if (!prm.tail) return;  // the step tail merges the records
   if (!last_arrival(prm.counter + b, gridDim.x, &s_last)) return;
@@ -351,7 +358,13 @@ hipError_t setup_radius_attributes() {
   if (e == hipSuccess)                                                                        \
     e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_radius<double, L, false, true>));           \
   if (e == hipSuccess)                                                                        \
-    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_radius<float, L, true>));
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_radius<float, L, true>));          \
+  if (e == hipSuccess)                                                                        \
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_radius<double, L, false, false, true>)); \
+  if (e == hipSuccess)                                                                        \
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_radius<double, L, false, true, true>)); \
+  if (e == hipSuccess)                                                                        \
+    e = set_max_dynamic_lds(reinterpret_cast<const void*>(k_radius<float, L, true, false, true>));
   AFD_LDS_LOGN_CASES(X)
 #undef X
   return e;
@@ -365,14 +378,24 @@ hipError_t launch_radius(int logn, bool fp64, const RadiusParams& p, int blocks,
     if (fp64) {                                                                              \
       constexpr int thr = radius_threads<double, L>();                                       \
       const size_t lds = radius_lds<double, L>(p.rpb);                                       \
-      if (p.probe)                                                                           \
+      if (p.fslot && p.probe)                                                                \
+        launch_ev(k_radius<double, L, false, true, true>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, \
+                  p);                                                                        \
+      else if (p.fslot)                                                                      \
+        launch_ev(k_radius<double, L, false, false, true>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, \
+                  e1, p);                                                                    \
+      else if (p.probe)                                                                      \
         launch_ev(k_radius<double, L, false, true>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, p); \
       else                                                                                   \
         launch_ev(k_radius<double, L, false>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, p); \
     } else {                                                                                 \
       constexpr int thr = radius_threads<float, L>();                                        \
       const size_t lds = radius_lds<float, L>(p.rpb);                                        \
-      launch_ev(k_radius<float, L, true>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, p);   \
+      if (p.fslot)                                                                           \
+        launch_ev(k_radius<float, L, true, false, true>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, \
+                  p);                                                                        \
+      else                                                                                   \
+        launch_ev(k_radius<float, L, true>, dim3(blocks, batch), dim3(thr), uint32_t(lds), s, e0, e1, p); \
     }                                                                                        \
     return hipGetLastError();                                                                \
   }

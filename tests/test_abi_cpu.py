@@ -187,7 +187,7 @@ def _nu_desc(afd, n=256, radii=(0.0, 0.5), turns=None, weights=None, batch=0, pr
     (dict(turns=[-0.1, 0.5]), 1),
     (dict(turns=[0.0, np.nan]), 1),
     (dict(weights=[np.inf] + [0.01] * 99), 1),
-    (dict(radii=(0.0, 0.99)), 5),                # kernel series longer than N = 256 terms
+    (dict(radii=(0.0, 0.99999)), 5),             # kernel series longer than 2^18 terms
     (dict(n=243), 5),                            # the grid must be 2^K
     (dict(n=1 << 15), 5),
     (dict(turns=np.arange(1 << 17) / (1 << 17)), 5),

@@ -141,6 +141,35 @@ def test_graph_replays_equal_eager(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,ns,m,steps,rmax", [(1024, 1200, 40, 5, 0.999), (256, 300, 25, 4, 0.995)],
+                         ids=lambda v: str(v))
+def test_radii_near_one(n, ns, m, steps, rmax, prec):
+    """Radii whose kernel series outlasts N terms (up to 0.999 on a 1024-angle
+    grid: about 41600 terms): the non-uniform DFT computes K N modes and those
+    radii read folded spectra; against the quadrature rule itself, every step
+    free-running and replayed."""
+    print(f"case nonuniform near one N={n} samples={ns} M={m} rmax={rmax} {prec}", flush=True)
+    g, t = W.nonuniform_kernel_signal(ns, item=70, kind="cluster", rmax=0.95)
+    w = O.trapezoid_weights(t)
+    radii = W.uniform_radii(m, rmax)
+    assert n * ns * m <= 2e8  # the oracle's quadrature rule itself (not the series cut at N)
+    ref = _oracle(g, t, w, radii, n, steps, key=("near", n, ns, m, steps, rmax))
+    with Plan(n, radii, precision=prec, sample_turns=t) as plan:
+        res = plan.decompose(_dev(g), steps)
+        compare(res, ref, TOL[prec], signal=g, radii=radii, nonuniform=(t, w, n))
+        rep = plan.replay(_dev(g), steps, ref.index.astype(np.int32))
+        compare_replay(rep, ref, prec, radii=radii)
+        alone = to_numpy(res)
+    # a batch of two on the same (clustered) positions: the first equals its lone decomposition
+    g1, t1 = W.nonuniform_kernel_signal(ns, item=71, kind="cluster", rmax=0.95)
+    assert np.array_equal(t1, t)
+    with Plan(n, radii, precision=prec, sample_turns=t, batch=2) as plan:
+        rb = to_numpy(plan.decompose(_dev(np.stack([g, g1])), steps))
+    for k in ("index", "coef", "energy", "remainder"):
+        assert np.array_equal(rb[k][0], alone[k], equal_nan=True), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_matches_alone(prec):
     """A batch of three signals on one set of positions: each equals its own
     decomposition bit for bit, and one is checked against the oracle."""
@@ -171,7 +200,7 @@ def test_batch_matches_alone(prec):
 def test_unsupported():
     t = np.arange(100) / 100 + 0.001
     with pytest.raises(AfdError):
-        Plan(256, [0.0, 0.99], sample_turns=t)       # r = 0.99 needs more than 256 terms
+        Plan(256, [0.0, 0.99999], sample_turns=t)    # r = 0.99999 needs more than 2^18 terms
     with pytest.raises(AfdError):
         Plan(243, [0.0, 0.5], sample_turns=t)        # the grid must be 2^K
     with Plan(256, [0.0, 0.5], sample_turns=t) as plan:

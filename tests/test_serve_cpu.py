@@ -88,6 +88,7 @@ class HalvingPlan:
     (exact in binary), energies of the remainders.  Batched like the library."""
     calls = []
     lock = threading.Lock()
+    gate = threading.Event()  # calls wait for it: requests join groups while a segment runs
 
     def __init__(self, n, radii, precision="fp32", stream=None, batch=1, concurrent=False):
         self.n, self.batch = n, batch
@@ -107,6 +108,7 @@ class HalvingPlan:
                     recheck_count=np.ones(steps, np.int32), flags=np.zeros(steps, np.int32), fp32_error=f * 0)
 
     def decompose(self, signal, steps):
+        assert HalvingPlan.gate.wait(30)
         with HalvingPlan.lock:
             HalvingPlan.calls.append((self.batch, steps))
         sig = np.asarray(signal).reshape(self.batch, self.n)
@@ -123,6 +125,7 @@ def test_shared_launches_equal_alone(monkeypatch):
     monkeypatch.setattr(S, "Plan", HalvingPlan)
     monkeypatch.setattr(S, "workspace_bytes", lambda n, radii, precision="fp32", batch=1: 1000 * batch)
     HalvingPlan.calls = []
+    HalvingPlan.gate.clear()
     rng = np.random.default_rng(3)
     reqs = []
     for i in range(30):
@@ -133,8 +136,9 @@ def test_shared_launches_equal_alone(monkeypatch):
     futs = []
     for i, r in enumerate(reqs):
         futs.append(srv.submit(*r))
-        if i % 5 == 4:
-            time.sleep(0.01)  # later requests join groups already running
+        if i == 5:
+            time.sleep(0.01)  # the first groups have started and hold their first segment
+    HalvingPlan.gate.set()  # later requests joined groups already running
     served = [f.result(timeout=30) for f in futs]
     srv.close()
     calls = list(HalvingPlan.calls)
