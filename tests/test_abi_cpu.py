@@ -222,6 +222,35 @@ def test_nonuniform_workspace():
     assert lib.afd_workspace_bytes(ctypes.byref(d3)) == 0
 
 
+def test_nonuniform_fold_workspace():
+    """Radii whose kernel series outlasts N terms are accepted: the plan holds
+    the K N modes the longest series needs (K a power of two) and one folded
+    spectrum per such radius; series beyond 2^18 terms are rejected."""
+    afd, lib = _lib()
+    turns = np.arange(1000) / 1000
+    # FP64: the series of r is cut where r^L / (1 - r) <= 2^-60
+    need = lambda r: (60 * np.log(2) - np.log1p(-r)) / -np.log(r)
+    d1, k1 = _nu_desc(afd, n=1024, radii=(0.0, 0.5, 0.6), turns=turns)     # every series within N
+    d2, k2 = _nu_desc(afd, n=1024, radii=(0.0, 0.5, 0.99), turns=turns)    # 4596 terms: 8 N modes, one fold
+    d3, k3 = _nu_desc(afd, n=1024, radii=(0.0, 0.99, 0.995), turns=turns)  # 9354 terms: 16 N modes, two folds
+    assert 4096 < need(0.99) < 8192 < need(0.995) < 16384
+    b1, b2, b3 = (lib.afd_workspace_bytes(ctypes.byref(d)) for d in (d1, d2, d3))
+    assert 0 < b1 < b2 < b3
+    assert b2 - b1 >= 16 * (8192 - 1024) + 16 * 1024
+    assert b3 - b2 >= 16 * (16384 - 8192) + 16 * 1024
+    # 2^18 modes at most: a series of about 250000 terms is accepted, 5.4e6 is not
+    lo, hi = 0.99, 1.0 - 1e-9
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if need(mid) < 250000 else (lo, mid)
+    r_ok = lo
+    assert 249000 < need(r_ok) <= 250000 and need(0.99999) > 2 ** 18
+    d4, k4 = _nu_desc(afd, n=1024, radii=(0.0, r_ok), turns=turns)
+    assert lib.afd_workspace_bytes(ctypes.byref(d4)) > b3
+    d5, k5 = _nu_desc(afd, n=1024, radii=(0.0, 0.99999), turns=turns)
+    assert lib.afd_workspace_bytes(ctypes.byref(d5)) == 0
+
+
 def test_flat_index_beyond_2p31():
     """M*N between 2^31 and 2^32 - 2 is accepted (unsigned flat indices)."""
     afd, lib = _lib()
