@@ -48,14 +48,20 @@ struct Big {
   static constexpr int THR_A = CA * TPR1;
   // Row pass: RB row transforms side by side per workgroup, each over RPT
   // rows one after another.  Single precision: 512 threads; double
-  // precision: 256 threads and, where a row transform is one wave, four rows
-  // in turn wherever a radius keeps at least 16 workgroups, so that each
-  // workgroup's fixed latencies (its first loads, the record of its best
-  // point) are paid once per 16 rows.
+  // precision: 256 threads and, where a row transform is one wave, 16, 8 or
+  // 4 rows in turn, the most that leave a radius at least 16 workgroups, so
+  // that each workgroup's fixed latencies (its first loads, the record of
+  // its best point) are paid once per 64 rows at N = 2^20 (measured on the
+  // whole decomposition there: 16 rows per workgroup 3% slower, 32 rows
+  // 0.8% slower).
   static constexpr int THR_B0 = sizeof(T) == 4 ? 512 : 256;
   static constexpr int RB = THR_B0 / TPR2 > 1 ? THR_B0 / TPR2 : 1;
   static constexpr int THR_B = RB * TPR2;
-  static constexpr int RPT = (sizeof(T) == 8 && TPR2 == 64 && N1 / (RB * 4) >= 16) ? 4 : 1;
+  static constexpr int RPT = (sizeof(T) != 8 || TPR2 != 64) ? 1
+                             : N1 / (RB * 16) >= 16        ? 16
+                             : N1 / (RB * 8) >= 16         ? 8
+                             : N1 / (RB * 4) >= 16         ? 4
+                                                           : 1;
   // waves per SIMD the row pass's register budget allows (single precision,
   // and double precision over several rows: at most 128 VGPRs)
   // (the 16 N2-point rows of the largest shift hold one 512-thread workgroup

@@ -33,8 +33,9 @@ def _signal(n, item, rmax=0.9, count=6):
     return W.add_noise(rng, g, 40.0)
 
 
-# (N, M, steps): M = 40 at 2^20 spans two chunks of radii in FP32 and three in FP64
-MEDIUM = [(1 << 15, 13, 4), (1 << 16, 9, 3), (1 << 17, 6, 3), (1 << 20, 40, 2)]
+# (N, M, steps): M = 40 at 2^20 spans two chunks of radii in FP32 and three in FP64;
+# the FP64 row pass runs 8 rows per transform wave at 2^19 and 16 at 2^20
+MEDIUM = [(1 << 15, 13, 4), (1 << 16, 9, 3), (1 << 17, 6, 3), (1 << 19, 12, 2), (1 << 20, 40, 2)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
