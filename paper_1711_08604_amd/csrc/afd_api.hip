@@ -1216,8 +1216,9 @@ afd_status run(afd_plan_s* p, const double* signal, int steps, const int32_t* fo
           const int b1 = c.nshort, b2 = b1 + c.nmed[0], b3 = b2 + c.nmed[1];
           const int med = m0 < b1 ? 0 : m0 < b2 ? 1 : m0 < b3 ? 2 : 0;
           const bool longs = m0 >= b3;
-          const int nr = m0 < b1 ? b1 - m0 : m0 < b2 ? b2 - m0 : m0 < b3 ? b3 - m0
-                                                                       : (c.M - m0 < p->chunk ? c.M - m0 : p->chunk);
+          int nr = m0 < b1 ? b1 - m0 : m0 < b2 ? b2 - m0 : m0 < b3 ? b3 - m0
+                                                                 : (c.M - m0 < p->chunk ? c.M - m0 : p->chunk);
+          if (nr > kMaxGridY) nr = kMaxGridY;  // radii run along grid y
           bp.m0 = m0;
           hipEvent_t r0, r1;
           HIPCHK(tm.pair(kTimeRows, &r0, &r1), "event");

@@ -444,6 +444,9 @@ hipError_t launch_update(double* g64, float* g32, const UpdateArgs& U, int batch
 // kEsWidth cells).
 constexpr int kMaxNuSamples = 1 << 16;
 constexpr int kMaxNuLogModes = 18;  // NM <= 2^18 modes (grids of up to 2^20 cells)
+// Largest grid dimension y or z of one launch: launches whose radii or
+// folded spectra run along y take at most this many per launch.
+constexpr int kMaxGridY = 65535;
 constexpr double kEsWidth = 12.0;
 constexpr double kEsBeta = 2.69 * 12.0;
 int nu_grid_log2(int logn);

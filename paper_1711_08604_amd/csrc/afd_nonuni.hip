@@ -114,18 +114,22 @@ __global__ __launch_bounds__(256) void k_nu_fold(const Cx<T>* __restrict__ c, co
                                                  Cx<T>* __restrict__ cfold) {
   const int l = blockIdx.x * 256 + threadIdx.x;
   if (l >= N) return;
-  const int f = blockIdx.y, b = blockIdx.z;
+  const int b = blockIdx.z;
   c += size_t(N) * b;
   ctail += size_t(N) * (K - 1) * b;
-  const double p = rho[f];
-  double ax = double(c[l].x), ay = double(c[l].y), pk = 1.0;
-  for (int k = 1; k < K; ++k) {
-    pk *= p;
-    const Cx<T> x = ctail[size_t(k - 1) * N + l];
-    ax = fma(pk, double(x.x), ax);
-    ay = fma(pk, double(x.y), ay);
+  // folded spectra f = blockIdx.y, blockIdx.y + gridDim.y, ... (grid y
+  // holds at most kMaxGridY)
+  for (int f = blockIdx.y; f < nfold; f += gridDim.y) {
+    const double p = rho[f];
+    double ax = double(c[l].x), ay = double(c[l].y), pk = 1.0;
+    for (int k = 1; k < K; ++k) {
+      pk *= p;
+      const Cx<T> x = ctail[size_t(k - 1) * N + l];
+      ax = fma(pk, double(x.x), ax);
+      ay = fma(pk, double(x.y), ay);
+    }
+    cfold[(size_t(b) * nfold + f) * N + l] = {T(ax), T(ay)};
   }
-  cfold[(size_t(b) * nfold + f) * N + l] = {T(ax), T(ay)};
 }
 
 // End of a pass over the samples: this workgroup's weighted energy partial
@@ -231,7 +235,7 @@ hipError_t launch_nu_fourier(const double* g, const NuTables& t, int logn, bool 
   if (t.nfold > 0) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid((N + 255) / 256, t.nfold, batch);
+    const dim3 grid((N + 255) / 256, t.nfold < kMaxGridY ? t.nfold : kMaxGridY, batch);
     if (fp64)
       launch_ev(k_nu_fold<double>, grid, dim3(256), 0u, s, nullptr, e1, static_cast<const Cx<double>*>(c),
                 static_cast<const Cx<double>*>(t.ctail), t.rho, N, K, t.nfold, static_cast<Cx<double>*>(t.cfold));

@@ -192,3 +192,24 @@ def test_flat_index_beyond_2p31(prec):
         assert r["energy"][1] < 1e-20 * r["energy"][0]
         rep = to_numpy(plan.replay(_dev(g), 1, np.array([[2100, j]], dtype=np.int32)))
         assert tuple(rep["pick_index"][0]) == (2100, j), rep["pick_index"][0]
+
+
+def test_more_radii_than_one_launch_holds():
+    """N = 2^15 with 8 radii repeated 11000 times (M = 88000, of which 66000
+    have short spectra: more than the 65535 radii one row launch takes): every
+    copy of a radius gives the same grid values, so the first maximum in flat
+    order lies on the first copy, and the decomposition equals the one over
+    the 8 radii bit for bit.  Double precision only: in FP32 mode the copies of
+    one point would fill the short-list."""
+    n, reps, steps = 1 << 15, 11000, 3
+    base = np.array([0.0, 0.2, 0.4, 0.6, 0.7, 0.8, 0.95, 0.999])  # 6 short, 1 medium, 1 long
+    radii = np.tile(base, reps)
+    g = _signal(n, 5)
+    print(f"case N={n} M={radii.shape[0]} (8 radii x {reps}) fp64", flush=True)
+    with Plan(n, base, precision="fp64") as plan:
+        ref = to_numpy(plan.decompose(_dev(g), steps))
+    with Plan(n, radii, precision="fp64") as plan:
+        res = to_numpy(plan.decompose(_dev(g), steps))
+    assert np.array_equal(res["index"], ref["index"]), (res["index"], ref["index"])
+    for k in ("coef", "a", "energy", "remainder"):
+        assert np.array_equal(res[k], ref[k]), k
