@@ -103,7 +103,7 @@ def test_workspace_bytes_two_pass():
     4 such radii in double precision, all 3 in single precision; the 63 + 17
     / 45 + 11 of medium length run in the shifted splits' row passes), so the
     workspace does not grow with M * N; besides it, a step keeps the
-    selection records of every radius (M x 128 lists of 528 bytes in single
+    selection records of every radius (M x 256 lists of 528 bytes in single
     precision, M x 256 bests of 40 bytes in double precision: the largest
     record count of the row passes)."""
     afd, lib = _lib()
@@ -113,7 +113,7 @@ def test_workspace_bytes_two_pass():
         d, keep = _desc(afd, n=1 << 20, radii=r, precision=prec)
         out[prec] = lib.afd_workspace_bytes(ctypes.byref(d))
     base64 = 4 * (16 << 20) + 2000 * 256 * 40
-    base32 = 3 * (8 << 20) + 2000 * 128 * 528
+    base32 = 3 * (8 << 20) + 2000 * 256 * 528
     assert base64 <= out[0] < base64 + (200 << 20), out
     assert base32 <= out[1] < base32 + (200 << 20), out
     d, keep = _desc(afd, n=1 << 15, radii=r[:7], precision=1)
