@@ -46,18 +46,18 @@ struct Big {
   static constexpr int CA0 = sizeof(T) == 4 ? 8 : 4;
   static constexpr int CA = 256 / TPR1 > CA0 ? 256 / TPR1 : CA0;
   static constexpr int THR_A = CA * TPR1;
-  // Row pass: RB row transforms side by side per workgroup, each over RPT
-  // rows one after another.  Single precision: 256 threads (512 in the
-  // shifted splits' passes; in the base split 512 threads made the N = 2^20
-  // decomposition 7% slower and 1024 threads 31%, because a workgroup's
-  // band list grows with its rows); double
-  // precision: 256 threads and, where a row transform is one wave, 16, 8 or
-  // 4 rows in turn, the most that leave a radius at least 16 workgroups, so
-  // that each workgroup's fixed latencies (its first loads, the record of
-  // its best point) are paid once per 64 rows at N = 2^20 (measured on the
-  // whole decomposition there: 16 rows per workgroup 3% slower, 32 rows
-  // 0.8% slower).
-  static constexpr int THR_B0 = sizeof(T) == 4 && DL > 0 ? 512 : 256;
+  // Row pass: RB row transforms side by side per workgroup of 256 threads
+  // (a longer row takes a workgroup of its own), each over RPT rows one
+  // after another.  Measured on the whole N = 2^20 decomposition: in single
+  // precision 512-thread workgroups were 7% slower in the base split (0.5%
+  // in the split shifted by 4) and 1024 threads 31%, because a workgroup's
+  // band list grows with its rows; in double precision 128 threads were
+  // 0.4% slower and 512 threads 3%.  Double precision, where a row transform
+  // is one wave, takes 16, 8 or 4 rows in turn, the most that leave a radius
+  // at least 16 workgroups, so that each workgroup's fixed latencies (its
+  // first loads, the record of its best point) are paid once per 64 rows at
+  // N = 2^20 (16 rows per workgroup: 3% slower; 32 rows: 0.8% slower).
+  static constexpr int THR_B0 = 256;
   static constexpr int RB = THR_B0 / TPR2 > 1 ? THR_B0 / TPR2 : 1;
   static constexpr int THR_B = RB * TPR2;
   static constexpr int RPT = (sizeof(T) != 8 || TPR2 != 64) ? 1
