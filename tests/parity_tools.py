@@ -16,6 +16,11 @@ Bar (per step k, oracle values unhatted, GPU values hatted):
   discrete energy by orders of magnitude);  |a^_k - a_k| <= 1e-13;
 * FP64 mode: the margin (P1 - P2)/P1 within 1e-10 of the oracle's.
 tol = 1e-12 for the FP64 path and 1e-5 for the FP32 + FP64-recheck path.
+Both paths update the remainder in double, with rounding errors of about
+1e-16 of the signal's norm; once the oracle's remainder norm falls below
+RESIDUAL_FLOOR / tol of the signal's (the decomposition has converged to
+that accuracy, Sec. 2), its digits are below that rounding and the steps
+from there on are not compared.
 
 Replay (compare_replay) forces the oracle's own trajectory, so every step is
 compared, and checks the path's own selection on each replayed remainder:
@@ -34,6 +39,7 @@ MARGIN_MIN = 1e-6
 NEAR_TIE = 1e-11
 PICK_MARGIN = 1e-10
 REL_FLOOR = 1e-2
+RESIDUAL_FLOOR = 1e-16
 FLAG_FORCED_LISTED = 16
 
 FIELDS = ("index", "a", "coef", "energy", "margin", "remainder", "recheck_count", "flags", "fp32_error",
@@ -58,6 +64,17 @@ def _ring_tie(ref, k, radii) -> bool:
         return False
     m, j = (int(v) for v in ref.index[k])
     return j == 0 and float(radii[m]) == 0.0
+
+
+def converged_step(ref, tol, steps=None) -> int:
+    """The first step whose remainder (energy E_k entering it) is below the
+    rounding level of the update: sqrt(E_k) <= RESIDUAL_FLOOR / tol * sqrt(E_0)."""
+    S = ref.coef.shape[0] if steps is None else steps
+    cut = (RESIDUAL_FLOOR / tol) ** 2 * ref.energy[0]
+    for k in range(S):
+        if ref.energy[k] <= cut:
+            return k
+    return S
 
 
 def _check_step(g, ref, k, tol, prec, report):
@@ -89,13 +106,16 @@ def compare(gpu, ref: "O.Decomposition", tol: float, signal=None, radii=None, fo
     S = ref.coef.shape[0]
     E0 = ref.energy[0]
     assert abs(g["energy"][0] - E0) <= tol * E0 + 1e-300, ("E0", g["energy"][0], E0)
-    upto = S
-    for k in range(S):
+    conv = converged_step(ref, tol)
+    upto = conv
+    for k in range(conv):
         decided = (forced_first and k == 0) or (ref.margin[k] > MARGIN_MIN) or _ring_tie(ref, k, radii)
         if not decided:
             upto = k
             break
     report = {"worst_coef": 0.0, "worst_coef_rel": 0.0, "worst_energy": 0.0, "worst_margin": 0.0}
+    if conv < S:
+        report["converged_step"] = conv
     for k in range(upto):
         assert tuple(g["index"][k]) == tuple(ref.index[k]), (k, g["index"][k], ref.index[k], ref.margin[k])
         _check_step(g, ref, k, tol, prec, report)
@@ -103,7 +123,7 @@ def compare(gpu, ref: "O.Decomposition", tol: float, signal=None, radii=None, fo
             dm = abs(g["margin"][k] - ref.margin[k])
             assert dm <= 1e-10, (k, "margin", g["margin"][k], ref.margin[k])
             report["worst_margin"] = max(report["worst_margin"], dm)
-    if upto < S and signal is not None and radii is not None:
+    if upto < conv and signal is not None and radii is not None:
         # near-tie: the GPU's choice must be one of the (nearly) equal maxima of
         # the oracle grid, whose maximum is |c_k|^2 of the oracle's own step
         # (the trajectories agree up to here)
@@ -136,7 +156,10 @@ def compare_replay(gpu, ref: "O.Decomposition", prec: str, radii=None, steps=Non
     assert abs(g["energy"][0] - E0) <= tol * E0 + 1e-300, ("E0", g["energy"][0], E0)
     report = {"worst_coef": 0.0, "worst_coef_rel": 0.0, "worst_energy": 0.0, "worst_pick_p": 0.0,
               "picks_compared": 0, "steps": S}
-    for k in range(S):
+    conv = converged_step(ref, tol, S)
+    if conv < S:
+        report["converged_step"] = conv
+    for k in range(conv):
         assert tuple(g["index"][k]) == tuple(ref.index[k]), (k, g["index"][k], ref.index[k])
         _check_step(g, ref, k, tol, prec, report)
         # the path's own selection on the oracle's remainder G_k
