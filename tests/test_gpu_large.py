@@ -213,3 +213,23 @@ def test_more_radii_than_one_launch_holds():
     assert np.array_equal(res["index"], ref["index"]), (res["index"], ref["index"])
     for k in ("coef", "a", "energy", "remainder"):
         assert np.array_equal(res[k], ref[k]), k
+
+
+def test_flat_ring_fp32_cut_lists():
+    """A single ring of radius 0.0158 at N = 2^16: thousands of points lie
+    within 1e-5 of its maximum, more than a radius' list holds, so FP32 mode
+    flags the cut (bit 1) and its choice is a maximum within the FP32
+    accuracy; FP64 mode picks the oracle's points exactly while they lead."""
+    n = 1 << 16
+    radii = np.array([0.0158])
+    g = _signal(n, 7)
+    ref = O.decompose(g, radii, 3)
+    print(f"case flat ring N={n} r=0.0158 margins {ref.margin}", flush=True)
+    for prec in ("fp64", "fp32"):
+        with Plan(n, radii, precision=prec) as plan:
+            res = plan.decompose(_dev(g), 3)
+            compare(res, ref, TOL[prec], signal=g, radii=radii)
+            rep = plan.replay(_dev(g), 3, ref.index.astype(np.int32))
+            compare_replay(rep, ref, prec, radii=radii)
+            if prec == "fp32":
+                assert np.all(to_numpy(rep)["pick_flags"] & 2), to_numpy(rep)["pick_flags"]
