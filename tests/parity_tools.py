@@ -111,7 +111,7 @@ def compare(gpu, ref: "O.Decomposition", tol: float, signal=None, radii=None, fo
     """Free-running GPU decomposition against the oracle's.  Return
     (steps_compared, report dict); raise AssertionError on a violation.
     `nonuniform` = (turns, weights, n) for a decomposition of non-uniform
-    samples (the near-tie check then uses the oracle's series form)."""
+    samples (the near-tie check then evaluates the quadrature rule)."""
     g = to_numpy(gpu)
     prec = prec or ("fp64" if tol <= TOL["fp64"] else "fp32")
     S = ref.coef.shape[0]
@@ -144,7 +144,8 @@ def compare(gpu, ref: "O.Decomposition", tol: float, signal=None, radii=None, fo
             t, w, n = nonuniform
             Gk = (O.decompose_nu(signal, t, w, radii, n, upto, forced=ref.index[:upto], form="series").remainder
                   if upto > 0 else signal)
-            p = abs(O.grid_series_nu(Gk, t, w, np.asarray(radii)[m:m + 1], n)[0, j]) ** 2
+            # the quadrature rule itself (the series cut at n terms misses radii near 1)
+            p = abs(O.grid_direct_nu(Gk, t, w, np.asarray(radii)[m:m + 1], n)[0, j]) ** 2
         else:
             Gk = O.decompose_streamed(signal, radii, upto, forced=ref.index[:upto]).remainder if upto > 0 else signal
             p = abs(O.grid_fft(Gk, np.asarray(radii)[m:m + 1])[0, j]) ** 2
